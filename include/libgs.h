@@ -1,0 +1,229 @@
+/*
+ * libgs — differentiable 3D Gaussian splatting for AMD Instinct MI355X (gfx950).
+ *
+ * The hot path of LVI-GS's mapping back-end (Section III-B and III-E of the paper):
+ *   project  : 3D Gaussians (mean, log-scale, rotation, opacity logit, SH colour) to 2D conics
+ *              per view, Sigma = R S S^T R^T (eq. Sigma), mu_I = [Q|T] mu_W and
+ *              Sigma_I = J Q Sigma Q^T J^T (eq. muI);
+ *   bin      : tile lists ordered by depth, by an own stable LSD radix sort of
+ *              (global tile << 32 | depth bits) keys;
+ *   render   : front-to-back compositing of colour, depth and visibility per pixel
+ *              (eqs. Cp, Dp, Vp with the alpha of eq. alpha);
+ *   backward : the L1 colour + lambda_d L1 depth loss (eqs. L, Lc with the SSIM weight 0, Ld)
+ *              and its gradient to every Gaussian parameter;
+ *   adam     : one bias-corrected Adam step (the paper optimises rotation, scaling, opacity
+ *              and SH by minimising L, Section III-E; it names no optimiser).
+ *
+ * Conventions (readings of what the paper leaves open):
+ *   camera   : world -> camera t = R mu + T, x right, y down, z forward; pixel (u, v) has its centre
+ *              at (u + 0.5, v + 0.5); depth of a Gaussian = camera z of its centre;
+ *   culling  : t_z < near_z; pixel mean outside the image widened by (guard - 1)/2 of its size per
+ *              side; opacity < alpha_min; det(Sigma_I) <= 0; empty pixel rectangle;
+ *   EWA      : exact pinhole Jacobian at t, lowpass px^2 added to the diagonal of Sigma_I;
+ *   alpha    : alpha = min(alpha_max, o exp(power)); skipped if alpha < alpha_min; a pixel stops before
+ *              the first record whose T (1 - alpha) < t_min;
+ *   extent   : pixel rectangle from the opacity-aware radius sqrt((2 ln(255 o) + 1) Sigma_I,diag);
+ *   colour   : max(0, sum_k f_k Y_k(dir) + 0.5) with real orthonormal SH up to degree 3, dir the unit
+ *              vector from the camera centre to the mean.
+ *
+ * Memory and ownership: every pointer is a device pointer unless marked (host).  The caller owns all
+ * memory.  The library never allocates or frees device memory and keeps no device state; the
+ * per-iteration intermediates live in a caller-provided "frame" block that gs_frame_init carves.
+ * Every call is asynchronous on `stream` (a hipStream_t) and can be captured in a HIP graph, except the
+ * two calls documented as synchronising.  Calls on different streams need disjoint frames.
+ *
+ * Errors: invalid arguments are detected on the host before anything is enqueued and return
+ * GS_ERR_ARG (text from gs_last_error()).  A failed HIP launch returns GS_ERR_HIP.  Conditions found
+ * on the device (instance capacity exceeded, non-finite parameters) set bits in frame->counters[1]
+ * without synchronising; the caller reads them after the stream completes.
+ */
+#ifndef LIBGS_H
+#define LIBGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GS_VERSION 1
+#define GS_MAX_VIEWS 64
+
+typedef enum {
+  GS_OK = 0,
+  GS_ERR_ARG = -1,
+  GS_ERR_HIP = -2,
+  GS_ERR_WORKSPACE = -3,
+  GS_ERR_UNSUPPORTED = -4
+} gs_status;
+
+/* bits of frame->counters[1] */
+#define GS_FLAG_INSTANCE_OVERFLOW 1 /* more tile instances than the frame's capacity; outputs undefined */
+#define GS_FLAG_NONFINITE 2         /* some parameter was NaN/Inf; that Gaussian was culled */
+
+/* One view.  128 bytes, the same layout on host and device. */
+typedef struct gs_camera {
+  float R[9];          /* world -> camera rotation, row-major ([Q_iw] of eq. muI) */
+  float T[3];          /* translation ([T_iw] of eq. muI): t = R mu + T */
+  float fx, fy, cx, cy;
+  float campos[3];     /* camera centre in world coordinates (-R^T T), for SH view directions */
+  float loss_weight;   /* w_v: weight of this view (keyframe x pyramid level) in the loss */
+  int32_t width, height;
+  /* filled by gs_plan_cameras: */
+  int32_t tiles_x, tiles_y;
+  int32_t tile_offset;  /* first global tile id of this view */
+  int32_t pixel_offset; /* first pixel of this view in the concatenated image planes */
+  float guard_lo_x, guard_hi_x, guard_lo_y, guard_hi_y; /* guard band, pixels */
+  int32_t reserved[2];
+} gs_camera;
+
+typedef struct gs_opts {
+  int32_t tile_w, tile_h; /* 16x16 (default), 8x8, 16x8, 32x8 or 32x16 */
+  float near_z;           /* 0.2 */
+  float guard;            /* 1.3 */
+  float lowpass;          /* 0.3 px^2 */
+  float alpha_min;        /* 1/255 */
+  float alpha_max;        /* 0.99 */
+  float t_min;            /* 1e-4 */
+  float bg[3];            /* background colour, 0 */
+  int32_t reserved[3];
+} gs_opts;
+
+/* Gaussian parameters, or gradients / Adam moments in the same layout.  Row-major float32:
+ * means [n,3], log_scales [n,3], quats [n,4] (w,x,y,z, any norm > 0), opacity [n] (logits),
+ * sh [n,K,3] with K = (sh_degree+1)^2 ordered by l then m = -l..l. */
+typedef struct gs_params {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacity;
+  float* sh;
+  int64_t n;
+  int32_t sh_degree;
+  int32_t reserved;
+} gs_params;
+
+/* Per-iteration intermediates of one batch of views, carved from one caller-owned device block.
+ * Records are dense over r = v * n + g (view-major); only visible ones are written. */
+typedef struct gs_frame {
+  int64_t n;            /* Gaussians */
+  int32_t n_views;
+  int32_t n_tiles;      /* global tiles over all views */
+  int64_t n_pixels;     /* pixels over all views */
+  int64_t max_view_pixels; /* pixels of the largest view */
+  int64_t capacity;     /* tile-instance capacity (<= 2^31 - 1) */
+  int32_t key_bits;     /* 32 depth bits + tile bits */
+  int32_t sort_passes;  /* 8-bit LSD passes */
+  int32_t tile_w, tile_h;
+  const gs_camera* cams;  /* device copy of the planned cameras (caller-owned) */
+  void* block;
+  size_t bytes;
+  /* carved device arrays (library layout; read-only for callers except where noted) */
+  float* rec;           /* [n_views*n][12]: {mu_x, mu_y, z, o}, {conic a, b, c, red}, {green, blue, -, -} */
+  int16_t* rect;        /* [n_views*n][4]: tile rectangle tx0, tx1, ty0, ty1 (valid when visible) */
+  float* rgrad;         /* [n_views*n][12]: dL/d{mu_x, mu_y, a, b, c, o, red, green, blue, z} */
+  uint64_t* vis_mask;   /* [n]: bit v set if Gaussian g is visible in view v */
+  int32_t* n_inst;      /* [n]: tile instances of Gaussian g over all views */
+  int32_t* inst_off;    /* [n]: exclusive scan of n_inst */
+  uint64_t* keys[2];    /* [capacity] ping-pong sort buffers */
+  int32_t* vals[2];     /* [capacity] record ids */
+  int32_t* tile_range;  /* [n_tiles][2]: [begin, end) of each tile's instances in the sorted list */
+  int32_t* counters;    /* [128]: [0] instance count, [1] flags, [2..2+n_views) valid depth pixels per view */
+  float* loss;          /* [1]: loss value written by gs_render_bwd in loss mode */
+  int32_t* scratch;     /* sort histograms and scan partials */
+  size_t scratch_ints;
+} gs_frame;
+
+typedef struct gs_images {
+  float* rgb;   /* sum_v [3][H_v][W_v] planar, view v at 3 * pixel_offset_v */
+  float* depth; /* sum_v [H_v][W_v], view v at pixel_offset_v */
+  float* vis;   /* sum_v [H_v][W_v] */
+} gs_images;
+
+/* Upstream of the backward: either targets (loss mode) or image gradients (autograd mode). */
+typedef struct gs_loss {
+  const float* g_rgb;     /* autograd mode: dL/d rgb image (layout of gs_images.rgb); NULL = 0 */
+  const float* g_depth;   /* autograd mode: dL/d depth image; NULL = 0 */
+  const float* g_vis;     /* autograd mode: dL/d visibility image; NULL = 0 */
+  const float* tgt_rgb;   /* loss mode when non-NULL: target images, layout of gs_images.rgb */
+  const float* tgt_depth; /* loss mode: LiDAR depth, layout of gs_images.depth, 0 = no measurement */
+  float lambda_d;         /* loss mode: depth weight (0.1) */
+  int32_t reserved;
+} gs_loss;
+
+typedef struct gs_adam {
+  float lr[6];          /* means, log_scales, quats, opacity, sh degree 0, sh degree >= 1 */
+  float beta1, beta2, eps;
+  int32_t reserved;
+  int64_t* step;        /* device counter, incremented by each call before it is used */
+  float* bias;          /* device scratch of 2 floats */
+} gs_adam;
+
+/* ------------------------------------------------------------------ host-side set-up */
+void gs_default_opts(gs_opts* opts);
+
+/* Fill tiles_x/y, tile_offset, pixel_offset and the guard band of cams[0..n_views) (host, in/out).
+ * GS_ERR_ARG for n_views outside [1, 64], non-positive sizes, fx/fy <= 0, unsupported tiles. */
+int gs_plan_cameras(gs_camera* cams, int32_t n_views, const gs_opts* opts);
+
+/* Bytes of the frame block for n Gaussians, the planned cameras (host) and an instance capacity. */
+size_t gs_frame_bytes(int64_t n, const gs_camera* cams, int32_t n_views, const gs_opts* opts,
+                      int64_t capacity);
+
+/* Carve `block` (device, >= gs_frame_bytes, 256-byte aligned) into *frame (host struct).
+ * cams_host are the planned cameras, cams_dev a device copy of them that must stay valid. */
+int gs_frame_init(gs_frame* frame, void* block, size_t bytes, int64_t n, const gs_camera* cams_host,
+                  const gs_camera* cams_dev, int32_t n_views, const gs_opts* opts, int64_t capacity);
+
+/* ------------------------------------------------------------------ the five hot-path calls */
+/* Projection of every Gaussian into every view of the frame (Section III-B, eqs. Sigma and muI):
+ * writes records, tile rectangles, visibility masks and per-Gaussian instance counts; zeroes the
+ * per-record gradients of visible records when zero_grads != 0.  Reads each Gaussian once. */
+int gs_project(const gs_params* params, const gs_frame* frame, const gs_opts* opts, int32_t zero_grads,
+               void* stream);
+
+/* Tile binning: exclusive scan of instance counts, emission of (global tile << 32 | depth bits, record)
+ * pairs, stable LSD radix sort, per-tile ranges.  The order within a tile is ascending depth, ties by
+ * record index.  sync_count != 0 synchronises the stream after the scan to size the work exactly and
+ * returns the instance count in *n_instances (host, nullable); otherwise the work is sized by the
+ * capacity and the count stays on the device (graph-capturable). */
+int gs_bin_tiles(const gs_frame* frame, const gs_opts* opts, int32_t sync_count, int64_t* n_instances,
+                 void* stream);
+
+/* Forward compositing of colour, depth and visibility for every view (eqs. Cp, Dp, Vp, alpha). */
+int gs_render_fwd(const gs_frame* frame, const gs_opts* opts, const gs_images* out, void* stream);
+
+/* Backward: per-pixel upstream gradients (autograd mode) or the L1 colour + lambda_d L1 depth loss
+ * against targets (loss mode: L = sum_v w_v [ mean_3P |C - I| + lambda_d mean_valid |D - D_lidar| ],
+ * eqs. L, Lc, Ld), through the compositing to every record, then through the projection to the
+ * parameters.  Gradients are ACCUMULATED into grads (+=; the caller zeroes them).  fwd holds the
+ * forward images of this frame; NULL recomputes them per tile inside the kernel (no image is stored).
+ * In loss mode the loss value is written to frame->loss. */
+int gs_render_bwd(const gs_params* params, const gs_frame* frame, const gs_opts* opts, const gs_images* fwd,
+                  const gs_loss* loss, const gs_params* grads, void* stream);
+
+/* One Adam step over all parameters (m, v as moments; bias-corrected, eps added to the corrected
+ * root), with per-group learning rates.  Dense: Gaussians with zero gradient still move. */
+int gs_adam_step(const gs_params* params, const gs_params* grads, const gs_params* m, const gs_params* v,
+                 const gs_adam* adam, void* stream);
+
+/* ------------------------------------------------------------------ utilities */
+/* Synchronises the stream and returns the instance count and flags of the frame (host outputs). */
+int gs_read_counters(const gs_frame* frame, int64_t* n_instances, int32_t* flags, void* stream);
+
+/* Stable ascending LSD radix sort of n (key, value) pairs on the low `key_bits` bits of the keys.
+ * keys/vals are sorted in place through the buffers keys_tmp/vals_tmp; scratch must hold
+ * gs_sort_scratch_ints(n) int32s.  The binning step uses the same sort. */
+size_t gs_sort_scratch_ints(int64_t n);
+int gs_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys_tmp, int32_t* vals_tmp, int64_t n,
+                  int32_t key_bits, int32_t* scratch, void* stream);
+
+const char* gs_status_string(int status);
+const char* gs_last_error(void);
+int gs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBGS_H */

@@ -386,7 +386,7 @@ struct Contrib { int64_t rec; R alpha, G, T; bool clamped; };
 
 template <class R>
 PixelOut<R> composite_pixel(const Splat<R>* recs, const int64_t* order, int64_t n, R px, R py, const Opts& op,
-                            std::vector<Contrib<R>>* trace) {
+                            std::vector<Contrib<R>>* trace, std::vector<int64_t>* near_recs = nullptr) {
   PixelOut<R> out;
   out.C[0] = out.C[1] = out.C[2] = 0;
   out.D = 0;
@@ -404,11 +404,15 @@ PixelOut<R> composite_pixel(const Splat<R>* recs, const int64_t* order, int64_t 
     R oG = s.o * G;
     bool clamped = oG > amax;
     R alpha = clamped ? amax : oG;
-    if (std::fabs((double)oG - op.alpha_max) <= 1e-5 * op.alpha_max) out.near = true;
-    if (std::fabs((double)alpha - op.alpha_min) <= 1e-5 * op.alpha_min) out.near = true;
+    bool nr = std::fabs((double)oG - op.alpha_max) <= 1e-5 * op.alpha_max ||
+              std::fabs((double)alpha - op.alpha_min) <= 1e-5 * op.alpha_min;
+    if (!(alpha < amin)) nr = nr || std::fabs((double)(T * ((R)1 - alpha)) - op.t_min) <= 1e-5 * op.t_min;
+    if (nr) {
+      out.near = true;
+      if (near_recs) near_recs->push_back(order[i]);
+    }
     if (alpha < amin) continue;
     R Tn = T * ((R)1 - alpha);
-    if (std::fabs((double)Tn - op.t_min) <= 1e-5 * op.t_min) out.near = true;
     if (Tn < tmin) break;
     R w = alpha * T;
     for (int ch = 0; ch < 3; ++ch) out.C[ch] += w * s.rgb[ch];
@@ -489,9 +493,10 @@ std::vector<int64_t> brute_order(const Scene<R>& sc, int v) {
 // Render every pixel of every view.  mode 0 = brute force (the definition), 1 = tiled lists.
 template <class R>
 void render_all(const Scene<R>& sc, int mode, std::vector<PixelOut<R>>& out,
-                std::vector<std::vector<Contrib<R>>>* traces) {
+                std::vector<std::vector<Contrib<R>>>* traces, std::vector<std::vector<int64_t>>* nears = nullptr) {
   out.resize(sc.total_px);
   if (traces) traces->assign(sc.total_px, {});
+  if (nears) nears->assign(sc.total_px, {});
   for (int v = 0; v < sc.V; ++v) {
     const Cam<R>& cam = sc.cams[v];
     std::vector<int64_t> brute;
@@ -512,7 +517,7 @@ void render_all(const Scene<R>& sc, int mode, std::vector<PixelOut<R>>& out,
           n = sc.bins.range_hi[t] - sc.bins.range_lo[t];
         }
         out[pix] = composite_pixel<R>(sc.splats.data(), ord, n, (R)x + (R)0.5, (R)y + (R)0.5, sc.op,
-                                      traces ? &(*traces)[pix] : nullptr);
+                                      traces ? &(*traces)[pix] : nullptr, nears ? &(*nears)[pix] : nullptr);
       }
   }
 }
@@ -754,7 +759,8 @@ double backward_impl(const double* means, const double* log_scales, const double
   build_scene<R>(sc, means, log_scales, quats, opac, sh, N, deg, cams, V, opts);
   std::vector<PixelOut<R>> img;
   std::vector<std::vector<Contrib<R>>> traces;
-  render_all<R>(sc, 1, img, &traces);
+  std::vector<std::vector<int64_t>> nears;
+  render_all<R>(sc, 1, img, &traces, &nears);
   std::vector<double> g;
   std::vector<char> near_sign(sc.total_px, 0);
   double L = 0;
@@ -777,8 +783,9 @@ double backward_impl(const double* means, const double* log_scales, const double
   std::vector<R> grec;
   composite_backward<R>(sc, img, traces, g, grec);
   project_backward_all<R>(sc, sh, grec, gmean, gscale, gquat, gopac, gsh);
-  // Excusal: a Gaussian that reaches a pixel whose discrete decisions are within 1e-5 of a threshold,
-  // or that has a colour or cull decision near its threshold.
+  // Excusal: at a pixel with a decision within 1e-5 of its threshold (a skip, clamp or stop, or the sign of
+  // its loss), the records with that decision and every contributor of the pixel; plus Gaussians with a
+  // cull or colour-clamp decision near its threshold.
   int64_t nn = 0;
   if (excused_gauss) {
     std::memset(excused_gauss, 0, (size_t)N);
@@ -786,14 +793,8 @@ double backward_impl(const double* means, const double* log_scales, const double
       bool nr = img[pix].near || near_sign[pix];
       if (!nr) continue;
       ++nn;
-      // every record evaluated at this pixel may be affected; mark those in its tile list
-      int v = 0;
-      while (v + 1 < V && sc.cams[v + 1].pixel_offset <= pix) ++v;
-      const Cam<R>& cam = sc.cams[v];
-      int64_t i = pix - cam.pixel_offset;
-      int y = (int)(i / cam.W), x = (int)(i % cam.W);
-      int t = cam.tile_offset + (y / sc.op.tile_h) * cam.tiles_x + (x / sc.op.tile_w);
-      for (int64_t k = sc.bins.range_lo[t]; k < sc.bins.range_hi[t]; ++k) excused_gauss[sc.bins.vals[k] % N] = 1;
+      for (const auto& c : traces[pix]) excused_gauss[c.rec % N] = 1;
+      for (int64_t r : nears[pix]) excused_gauss[r % N] = 1;
     }
     for (int64_t r = 0; r < (int64_t)V * N; ++r) {
       const Proj<R>& p = sc.proj[r];

@@ -1,0 +1,287 @@
+"""ctypes binding of libgs.so: the C-ABI calls under the same names, plus argument marshalling.
+
+Every step of the splatting path runs in the HIP library; this module only turns torch tensors and
+camera descriptions into the C structures and raises on a non-zero status.  There is no fallback:
+if libgs.so is missing or fails to load, `load()` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgs.so")
+
+c_f = ctypes.c_float
+c_i32 = ctypes.c_int32
+c_i64 = ctypes.c_int64
+c_vp = ctypes.c_void_p
+P = ctypes.POINTER
+
+
+class gs_camera(ctypes.Structure):
+    _fields_ = [("R", c_f * 9), ("T", c_f * 3), ("fx", c_f), ("fy", c_f), ("cx", c_f), ("cy", c_f),
+                ("campos", c_f * 3), ("loss_weight", c_f), ("width", c_i32), ("height", c_i32),
+                ("tiles_x", c_i32), ("tiles_y", c_i32), ("tile_offset", c_i32), ("pixel_offset", c_i32),
+                ("guard_lo_x", c_f), ("guard_hi_x", c_f), ("guard_lo_y", c_f), ("guard_hi_y", c_f),
+                ("reserved", c_i32 * 2)]
+
+
+class gs_opts(ctypes.Structure):
+    _fields_ = [("tile_w", c_i32), ("tile_h", c_i32), ("near_z", c_f), ("guard", c_f), ("lowpass", c_f),
+                ("alpha_min", c_f), ("alpha_max", c_f), ("t_min", c_f), ("bg", c_f * 3), ("reserved", c_i32 * 3)]
+
+
+class gs_params(ctypes.Structure):
+    _fields_ = [("means", c_vp), ("log_scales", c_vp), ("quats", c_vp), ("opacity", c_vp), ("sh", c_vp),
+                ("n", c_i64), ("sh_degree", c_i32), ("reserved", c_i32)]
+
+
+class gs_frame(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("n_views", c_i32), ("n_tiles", c_i32), ("n_pixels", c_i64),
+                ("max_view_pixels", c_i64), ("capacity", c_i64), ("key_bits", c_i32), ("sort_passes", c_i32),
+                ("tile_w", c_i32), ("tile_h", c_i32), ("cams", c_vp), ("block", c_vp), ("bytes", ctypes.c_size_t),
+                ("rec", c_vp), ("rect", c_vp), ("rgrad", c_vp), ("vis_mask", c_vp), ("n_inst", c_vp),
+                ("inst_off", c_vp), ("keys", c_vp * 2), ("vals", c_vp * 2), ("tile_range", c_vp),
+                ("counters", c_vp), ("loss", c_vp), ("scratch", c_vp), ("scratch_ints", ctypes.c_size_t)]
+
+
+class gs_images(ctypes.Structure):
+    _fields_ = [("rgb", c_vp), ("depth", c_vp), ("vis", c_vp)]
+
+
+class gs_loss(ctypes.Structure):
+    _fields_ = [("g_rgb", c_vp), ("g_depth", c_vp), ("g_vis", c_vp), ("tgt_rgb", c_vp), ("tgt_depth", c_vp),
+                ("lambda_d", c_f), ("reserved", c_i32)]
+
+
+class gs_adam(ctypes.Structure):
+    _fields_ = [("lr", c_f * 6), ("beta1", c_f), ("beta2", c_f), ("eps", c_f), ("reserved", c_i32),
+                ("step", c_vp), ("bias", c_vp)]
+
+
+assert ctypes.sizeof(gs_camera) == 128
+
+GS_FLAG_INSTANCE_OVERFLOW = 1
+GS_FLAG_NONFINITE = 2
+
+EXPORTED = ["gs_default_opts", "gs_plan_cameras", "gs_frame_bytes", "gs_frame_init", "gs_project", "gs_bin_tiles",
+            "gs_render_fwd", "gs_render_bwd", "gs_adam_step", "gs_read_counters", "gs_sort_scratch_ints",
+            "gs_sort_pairs", "gs_status_string", "gs_last_error", "gs_version"]
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libgs.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run paper_2411_02703_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.gs_default_opts.argtypes = [P(gs_opts)]
+    lib.gs_default_opts.restype = None
+    lib.gs_plan_cameras.argtypes = [P(gs_camera), c_i32, P(gs_opts)]
+    lib.gs_frame_bytes.argtypes = [c_i64, P(gs_camera), c_i32, P(gs_opts), c_i64]
+    lib.gs_frame_bytes.restype = ctypes.c_size_t
+    lib.gs_frame_init.argtypes = [P(gs_frame), c_vp, ctypes.c_size_t, c_i64, P(gs_camera), c_vp, c_i32, P(gs_opts),
+                                  c_i64]
+    lib.gs_project.argtypes = [P(gs_params), P(gs_frame), P(gs_opts), c_i32, c_vp]
+    lib.gs_bin_tiles.argtypes = [P(gs_frame), P(gs_opts), c_i32, P(c_i64), c_vp]
+    lib.gs_render_fwd.argtypes = [P(gs_frame), P(gs_opts), P(gs_images), c_vp]
+    lib.gs_render_bwd.argtypes = [P(gs_params), P(gs_frame), P(gs_opts), P(gs_images), P(gs_loss), P(gs_params),
+                                  c_vp]
+    lib.gs_adam_step.argtypes = [P(gs_params), P(gs_params), P(gs_params), P(gs_params), P(gs_adam), c_vp]
+    lib.gs_read_counters.argtypes = [P(gs_frame), P(c_i64), P(c_i32), c_vp]
+    lib.gs_sort_scratch_ints.argtypes = [c_i64]
+    lib.gs_sort_scratch_ints.restype = ctypes.c_size_t
+    lib.gs_sort_pairs.argtypes = [c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, c_vp, c_vp]
+    lib.gs_status_string.argtypes = [ctypes.c_int]
+    lib.gs_status_string.restype = ctypes.c_char_p
+    lib.gs_last_error.argtypes = []
+    lib.gs_last_error.restype = ctypes.c_char_p
+    lib.gs_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        lib = load()
+        raise RuntimeError(f"{what}: {lib.gs_status_string(rc).decode()} ({lib.gs_last_error().decode()})")
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("image arguments must be contiguous float32 CUDA tensors")
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+# --------------------------------------------------------------------------- structures
+def default_opts(**over) -> gs_opts:
+    o = gs_opts()
+    load().gs_default_opts(ctypes.byref(o))
+    for k, v in over.items():
+        if k == "bg":
+            for i in range(3):
+                o.bg[i] = v[i]
+        else:
+            setattr(o, k, v)
+    return o
+
+
+def make_cameras(cams: Sequence) -> ctypes.Array:
+    """gs_camera array from scenes.Camera-like objects (R, T, fx, fy, cx, cy, width, height, weight)."""
+    arr = (gs_camera * len(cams))()
+    for i, c in enumerate(cams):
+        R = np.asarray(c.R, np.float64)
+        T = np.asarray(c.T, np.float64)
+        pos = -R.T @ T
+        a = arr[i]
+        for k in range(9):
+            a.R[k] = float(R.reshape(-1)[k])
+        for k in range(3):
+            a.T[k] = float(T[k])
+            a.campos[k] = float(pos[k])
+        a.fx, a.fy, a.cx, a.cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+        a.width, a.height = int(c.width), int(c.height)
+        a.loss_weight = float(c.weight)
+    return arr
+
+
+def params_struct(p: Dict[str, torch.Tensor], sh_degree: int) -> gs_params:
+    for k in ("means", "log_scales", "quats", "opacity", "sh"):
+        t = p[k]
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError(f"{k} must be a contiguous float32 CUDA tensor")
+    return gs_params(p["means"].data_ptr(), p["log_scales"].data_ptr(), p["quats"].data_ptr(),
+                     p["opacity"].data_ptr(), p["sh"].data_ptr(), int(p["means"].shape[0]), int(sh_degree), 0)
+
+
+class Frame:
+    """A frame block (device memory owned by torch) carved by gs_frame_init, with its cameras."""
+
+    def __init__(self, n: int, cams: Sequence, opts: Optional[gs_opts] = None, capacity: Optional[int] = None,
+                 device: str = "cuda"):
+        lib = load()
+        self.opts = opts if opts is not None else default_opts()
+        self.cams_host = make_cameras(cams)
+        self.n_views = len(cams)
+        _check(lib.gs_plan_cameras(self.cams_host, self.n_views, ctypes.byref(self.opts)), "gs_plan_cameras")
+        raw = bytes(self.cams_host)
+        self.cams_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+        self.n = int(n)
+        self.n_pixels = sum(c.width * c.height for c in self.cams_host)
+        self.capacity = int(capacity) if capacity else max(1 << 16, 4 * self.n)
+        nbytes = lib.gs_frame_bytes(self.n, self.cams_host, self.n_views, ctypes.byref(self.opts), self.capacity)
+        if nbytes == 0:
+            _check(-1, "gs_frame_bytes")
+        self.block = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.block.data_ptr()
+        aligned = (base + 255) & ~255
+        self.f = gs_frame()
+        _check(lib.gs_frame_init(ctypes.byref(self.f), aligned, nbytes, self.n, self.cams_host,
+                                 self.cams_dev.data_ptr(), self.n_views, ctypes.byref(self.opts), self.capacity),
+               "gs_frame_init")
+        self.pixel_offsets = [c.pixel_offset for c in self.cams_host]
+
+    @property
+    def sorted_index(self) -> int:
+        return self.f.sort_passes & 1
+
+    def empty_images(self, device="cuda"):
+        P = self.n_pixels
+        return (torch.empty(3 * P, device=device), torch.empty(P, device=device), torch.empty(P, device=device))
+
+    def view_slices(self, v: int):
+        c = self.cams_host[v]
+        P = c.width * c.height
+        return c.pixel_offset, P, c.height, c.width
+
+
+# --------------------------------------------------------------------------- the C-ABI calls
+def gs_project(params: gs_params, frame: Frame, zero_grads: bool = True, stream=None) -> None:
+    _check(load().gs_project(ctypes.byref(params), ctypes.byref(frame.f), ctypes.byref(frame.opts),
+                             int(zero_grads), _stream(stream)), "gs_project")
+
+
+def gs_bin_tiles(frame: Frame, sync_count: bool = True, stream=None) -> Optional[int]:
+    n = c_i64(-1)
+    _check(load().gs_bin_tiles(ctypes.byref(frame.f), ctypes.byref(frame.opts), int(sync_count), ctypes.byref(n),
+                               _stream(stream)), "gs_bin_tiles")
+    return int(n.value) if sync_count else None
+
+
+def gs_render_fwd(frame: Frame, rgb: torch.Tensor, depth: torch.Tensor, vis: torch.Tensor, stream=None) -> None:
+    im = gs_images(rgb.data_ptr(), depth.data_ptr(), vis.data_ptr())
+    _check(load().gs_render_fwd(ctypes.byref(frame.f), ctypes.byref(frame.opts), ctypes.byref(im), _stream(stream)),
+           "gs_render_fwd")
+
+
+def gs_render_bwd(params: gs_params, frame: Frame, fwd: Optional[Sequence[torch.Tensor]], grads: gs_params,
+                  g_rgb=None, g_depth=None, g_vis=None, tgt_rgb=None, tgt_depth=None, lambda_d: float = 0.1,
+                  stream=None) -> None:
+    im = None
+    if fwd is not None:
+        im = gs_images(fwd[0].data_ptr(), fwd[1].data_ptr(), fwd[2].data_ptr())
+    l = gs_loss(_ptr(g_rgb), _ptr(g_depth), _ptr(g_vis), _ptr(tgt_rgb), _ptr(tgt_depth), float(lambda_d), 0)
+    _check(load().gs_render_bwd(ctypes.byref(params), ctypes.byref(frame.f), ctypes.byref(frame.opts),
+                                ctypes.byref(im) if im is not None else None, ctypes.byref(l), ctypes.byref(grads),
+                                _stream(stream)), "gs_render_bwd")
+
+
+def gs_adam_step(params: gs_params, grads: gs_params, m: gs_params, v: gs_params, adam: gs_adam,
+                 stream=None) -> None:
+    _check(load().gs_adam_step(ctypes.byref(params), ctypes.byref(grads), ctypes.byref(m), ctypes.byref(v),
+                               ctypes.byref(adam), _stream(stream)), "gs_adam_step")
+
+
+def gs_read_counters(frame: Frame, stream=None):
+    n = c_i64(0)
+    fl = c_i32(0)
+    _check(load().gs_read_counters(ctypes.byref(frame.f), ctypes.byref(n), ctypes.byref(fl), _stream(stream)),
+           "gs_read_counters")
+    return int(n.value), int(fl.value)
+
+
+def gs_sort_pairs(keys: torch.Tensor, vals: torch.Tensor, key_bits: int, stream=None) -> None:
+    """Sort int64 (used as uint64) keys with int32 values in place."""
+    n = keys.numel()
+    kt = torch.empty_like(keys)
+    vt = torch.empty_like(vals)
+    scratch = torch.empty(int(load().gs_sort_scratch_ints(n)) + 64, dtype=torch.int32, device=keys.device)
+    _check(load().gs_sort_pairs(keys.data_ptr(), vals.data_ptr(), kt.data_ptr(), vt.data_ptr(), n, int(key_bits),
+                                scratch.data_ptr(), _stream(stream)), "gs_sort_pairs")
+
+
+# --------------------------------------------------------------------------- frame views (torch, zero-copy)
+def frame_tensor(frame: Frame, field: str, count: int, dtype: torch.dtype) -> torch.Tensor:
+    """A torch view of a carved frame array (for tests and diagnostics)."""
+    if field in ("keys", "vals"):
+        raise ValueError("use sorted_keys / sorted_vals")
+    addr = getattr(frame.f, field)
+    off = addr - frame.block.data_ptr()
+    nbytes = count * torch.tensor([], dtype=dtype).element_size()
+    return frame.block[off:off + nbytes].view(dtype)
+
+
+def sorted_pairs(frame: Frame, count: int):
+    i = frame.sorted_index
+    koff = frame.f.keys[i] - frame.block.data_ptr()
+    voff = frame.f.vals[i] - frame.block.data_ptr()
+    k = frame.block[koff:koff + 8 * count].view(torch.int64)
+    v = frame.block[voff:voff + 4 * count].view(torch.int32)
+    return k, v

@@ -1,0 +1,91 @@
+// One Adam step over all Gaussian parameters (bias-corrected moments, eps added to the corrected root),
+// with one learning rate per parameter group.  The paper optimises rotation, scaling, opacity and SH
+// colour by minimising its loss (LVI-GS Section III-E) without naming the optimiser.
+// HBM-bound: per element it reads p, g, m, v and writes p, m, v.
+#include "common.h"
+
+namespace {
+
+// step <- step + 1; bias = {1 - beta1^step, sqrt(1 - beta2^step)} (computed in double).
+__global__ void k_adam_prep(int64_t* __restrict__ step, float* __restrict__ bias, float b1, float b2) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t t = step[0] + 1;
+  step[0] = t;
+  bias[0] = (float)(1.0 - pow((double)b1, (double)t));
+  bias[1] = (float)sqrt(1.0 - pow((double)b2, (double)t));
+}
+
+// period > 0: element i of the group uses lr0 when (i % period) < 3 (the degree-0 SH coefficients of a
+// Gaussian's colour), lr1 otherwise.
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                             float* __restrict__ m, float* __restrict__ v, int64_t n, float lr0,
+                                             float lr1, int period, float b1, float b2, float eps,
+                                             const float* __restrict__ bias) {
+  const float bc1 = bias[0], bc2s = bias[1];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
+  for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i0 < n; i0 += stride) {
+    if (i0 + 4 <= n) {
+      const float4 gg = *reinterpret_cast<const float4*>(g + i0);
+      float4 mm = *reinterpret_cast<const float4*>(m + i0);
+      float4 vv = *reinterpret_cast<const float4*>(v + i0);
+      float4 pp = *reinterpret_cast<const float4*>(p + i0);
+      float* pm = &mm.x;
+      float* pv = &vv.x;
+      float* pq = &pp.x;
+      const float* pg = &gg.x;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float gk = pg[k];
+        pm[k] = b1 * pm[k] + (1.f - b1) * gk;
+        pv[k] = b2 * pv[k] + (1.f - b2) * gk * gk;
+        const float lr = (period > 0 && ((i0 + k) % period) >= 3) ? lr1 : lr0;
+        pq[k] -= (lr / bc1) * pm[k] / (sqrtf(pv[k]) / bc2s + eps);
+      }
+      *reinterpret_cast<float4*>(m + i0) = mm;
+      *reinterpret_cast<float4*>(v + i0) = vv;
+      *reinterpret_cast<float4*>(p + i0) = pp;
+    } else {
+      for (int64_t i = i0; i < n; ++i) {
+        const float gk = g[i];
+        const float mk = b1 * m[i] + (1.f - b1) * gk;
+        const float vk = b2 * v[i] + (1.f - b2) * gk * gk;
+        m[i] = mk;
+        v[i] = vk;
+        const float lr = (period > 0 && (i % period) >= 3) ? lr1 : lr0;
+        p[i] -= (lr / bc1) * mk / (sqrtf(vk) / bc2s + eps);
+      }
+    }
+  }
+}
+
+hipError_t group(float* p, const float* g, float* m, float* v, int64_t n, float lr0, float lr1, int period,
+                 const gs_adam& a, hipStream_t st) {
+  const int threads = 256;
+  int64_t blocks = (n + 4 * threads - 1) / (4 * threads);
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  k_adam<<<(unsigned)blocks, threads, 0, st>>>(p, g, m, v, n, lr0, lr1, period, a.beta1, a.beta2, a.eps, a.bias);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+namespace gs_launch {
+
+hipError_t adam(const gs_params& p, const gs_params& g, const gs_params& m, const gs_params& v, const gs_adam& a,
+                hipStream_t st) {
+  k_adam_prep<<<1, 64, 0, st>>>(a.step, a.bias, a.beta1, a.beta2);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = p.n;
+  const int K = (p.sh_degree + 1) * (p.sh_degree + 1);
+  if ((e = group(p.means, g.means, m.means, v.means, 3 * n, a.lr[0], a.lr[0], 0, a, st)) != hipSuccess) return e;
+  if ((e = group(p.log_scales, g.log_scales, m.log_scales, v.log_scales, 3 * n, a.lr[1], a.lr[1], 0, a, st)) !=
+      hipSuccess)
+    return e;
+  if ((e = group(p.quats, g.quats, m.quats, v.quats, 4 * n, a.lr[2], a.lr[2], 0, a, st)) != hipSuccess) return e;
+  if ((e = group(p.opacity, g.opacity, m.opacity, v.opacity, n, a.lr[3], a.lr[3], 0, a, st)) != hipSuccess) return e;
+  return group(p.sh, g.sh, m.sh, v.sh, (int64_t)3 * K * n, a.lr[4], a.lr[5], 3 * K, a, st);
+}
+
+}  // namespace gs_launch

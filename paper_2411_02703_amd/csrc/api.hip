@@ -1,0 +1,360 @@
+// C ABI of libgs: argument checks, the frame layout and the launch sequences of the hot-path calls.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "common.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(GS_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define GS_HIP(call, where)                       \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+bool tiles_supported(int tw, int th) {
+  return (tw == 16 && th == 16) || (tw == 16 && th == 8) || (tw == 8 && th == 8) || (tw == 32 && th == 8) ||
+         (tw == 32 && th == 16);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t rec, rect, rgrad, mask, ninst, instoff, k0, k1, v0, v1, range, counters, loss, scratch, total;
+  size_t scratch_ints;
+  int key_bits, passes;
+};
+
+int opts_check(const gs_opts* o) {
+  if (!o) return fail(GS_ERR_ARG, "opts is NULL");
+  if (!tiles_supported(o->tile_w, o->tile_h))
+    return fail(GS_ERR_ARG, "unsupported tile %dx%d (16x16, 16x8, 8x8, 32x8, 32x16)", o->tile_w, o->tile_h);
+  if (!(o->near_z > 0.f) || !(o->guard >= 1.f) || !(o->lowpass >= 0.f) || !(o->alpha_min > 0.f) ||
+      !(o->alpha_max > o->alpha_min) || !(o->alpha_max < 1.f) || !(o->t_min > 0.f))
+    return fail(GS_ERR_ARG, "invalid option values");
+  return GS_OK;
+}
+
+int views_info(const gs_camera* cams, int32_t V, const gs_opts* o, int* n_tiles, int64_t* n_pixels,
+               int64_t* max_view = nullptr) {
+  if (!cams) return fail(GS_ERR_ARG, "cameras are NULL");
+  if (V < 1 || V > GS_MAX_VIEWS) return fail(GS_ERR_ARG, "n_views %d outside [1, %d]", V, GS_MAX_VIEWS);
+  int64_t tiles = 0, px = 0;
+  for (int v = 0; v < V; ++v) {
+    const gs_camera& c = cams[v];
+    if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
+      return fail(GS_ERR_ARG, "view %d: size %dx%d", v, c.width, c.height);
+    tiles += (int64_t)((c.width + o->tile_w - 1) / o->tile_w) * ((c.height + o->tile_h - 1) / o->tile_h);
+    px += (int64_t)c.width * c.height;
+    if (max_view && (int64_t)c.width * c.height > *max_view) *max_view = (int64_t)c.width * c.height;
+  }
+  if (tiles >= (int64_t(1) << 30)) return fail(GS_ERR_ARG, "too many tiles");
+  if (3 * px >= (int64_t(1) << 31)) return fail(GS_ERR_ARG, "too many pixels");
+  *n_tiles = (int)tiles;
+  *n_pixels = px;
+  return GS_OK;
+}
+
+Layout make_layout(int64_t n, int V, int n_tiles, int64_t cap) {
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o = align256(o + bytes);
+    return r;
+  };
+  const size_t R = (size_t)V * (size_t)n;
+  L.rec = take(R * 48);
+  L.rect = take(R * 8);
+  L.rgrad = take(R * 48);
+  L.mask = take((size_t)n * 8);
+  L.ninst = take((size_t)n * 4);
+  L.instoff = take((size_t)n * 4);
+  L.k0 = take((size_t)cap * 8);
+  L.k1 = take((size_t)cap * 8);
+  L.v0 = take((size_t)cap * 4);
+  L.v1 = take((size_t)cap * 4);
+  L.range = take((size_t)n_tiles * 8);
+  L.counters = take(128 * 4);
+  L.loss = take(64 * 4);
+  const size_t s1 = gs_launch::scan_scratch_ints(n), s2 = gs_launch::sort_scratch_ints(cap);
+  L.scratch_ints = s1 > s2 ? s1 : s2;
+  L.scratch = take(L.scratch_ints * 4);
+  L.total = o;
+  int tb = 1;
+  while ((int64_t(1) << tb) < n_tiles) ++tb;
+  L.key_bits = 32 + tb;
+  L.passes = (L.key_bits + 7) / 8;
+  return L;
+}
+
+int params_check(const gs_params* p, const char* what) {
+  if (!p) return fail(GS_ERR_ARG, "%s is NULL", what);
+  if (!p->means || !p->log_scales || !p->quats || !p->opacity || !p->sh)
+    return fail(GS_ERR_ARG, "%s has a NULL array", what);
+  if (p->n < 1) return fail(GS_ERR_ARG, "%s: n = %lld", what, (long long)p->n);
+  if (p->sh_degree < 0 || p->sh_degree > 3) return fail(GS_ERR_ARG, "%s: sh_degree %d", what, p->sh_degree);
+  return GS_OK;
+}
+
+int frame_check(const gs_frame* f) {
+  if (!f || !f->block || !f->cams) return fail(GS_ERR_ARG, "frame not initialised");
+  return GS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gs_default_opts(gs_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tile_w = 16;
+  o->tile_h = 16;
+  o->near_z = 0.2f;
+  o->guard = 1.3f;
+  o->lowpass = 0.3f;
+  o->alpha_min = 1.0f / 255.0f;
+  o->alpha_max = 0.99f;
+  o->t_min = 1e-4f;
+}
+
+int gs_plan_cameras(gs_camera* cams, int32_t V, const gs_opts* o) {
+  int rc = opts_check(o);
+  if (rc) return rc;
+  int nt;
+  int64_t np;
+  if ((rc = views_info(cams, V, o, &nt, &np))) return rc;
+  int toff = 0, poff = 0;
+  for (int v = 0; v < V; ++v) {
+    gs_camera& c = cams[v];
+    if (!(c.fx > 0.f) || !(c.fy > 0.f) || !std::isfinite(c.cx) || !std::isfinite(c.cy))
+      return fail(GS_ERR_ARG, "view %d: invalid intrinsics", v);
+    for (int i = 0; i < 9; ++i)
+      if (!std::isfinite(c.R[i])) return fail(GS_ERR_ARG, "view %d: non-finite rotation", v);
+    c.tiles_x = (c.width + o->tile_w - 1) / o->tile_w;
+    c.tiles_y = (c.height + o->tile_h - 1) / o->tile_h;
+    c.tile_offset = toff;
+    c.pixel_offset = poff;
+    toff += c.tiles_x * c.tiles_y;
+    poff += c.width * c.height;
+    // guard band: the image widened by (guard - 1)/2 of its size on each side
+    const float gm = (o->guard - 1.0f) * 0.5f;
+    const float mxw = gm * (float)c.width;
+    const float myw = gm * (float)c.height;
+    c.guard_lo_x = -mxw;
+    c.guard_hi_x = (float)c.width + mxw;
+    c.guard_lo_y = -myw;
+    c.guard_hi_y = (float)c.height + myw;
+  }
+  return GS_OK;
+}
+
+size_t gs_frame_bytes(int64_t n, const gs_camera* cams, int32_t V, const gs_opts* o, int64_t capacity) {
+  if (opts_check(o)) return 0;
+  int nt;
+  int64_t np;
+  if (views_info(cams, V, o, &nt, &np)) return 0;
+  if (n < 1 || capacity < 1 || capacity > INT32_MAX) return 0;
+  return make_layout(n, V, nt, capacity).total;
+}
+
+int gs_frame_init(gs_frame* f, void* block, size_t bytes, int64_t n, const gs_camera* cams_host,
+                  const gs_camera* cams_dev, int32_t V, const gs_opts* o, int64_t capacity) {
+  if (!f) return fail(GS_ERR_ARG, "frame is NULL");
+  int rc = opts_check(o);
+  if (rc) return rc;
+  int nt;
+  int64_t np, mv = 0;
+  if ((rc = views_info(cams_host, V, o, &nt, &np, &mv))) return rc;
+  if (!cams_dev) return fail(GS_ERR_ARG, "device cameras are NULL");
+  if (n < 1) return fail(GS_ERR_ARG, "n = %lld", (long long)n);
+  if ((int64_t)V * n > INT32_MAX) return fail(GS_ERR_ARG, "n_views * n exceeds 2^31 - 1 records");
+  if (capacity < 1 || capacity > INT32_MAX) return fail(GS_ERR_ARG, "capacity %lld", (long long)capacity);
+  for (int v = 0; v < V; ++v)
+    if (cams_host[v].tiles_x != (cams_host[v].width + o->tile_w - 1) / o->tile_w)
+      return fail(GS_ERR_ARG, "view %d is not planned for these options (call gs_plan_cameras)", v);
+  if (!block) return fail(GS_ERR_ARG, "block is NULL");
+  if (((uintptr_t)block & 255) != 0) return fail(GS_ERR_ARG, "block is not 256-byte aligned");
+  const Layout L = make_layout(n, V, nt, capacity);
+  if (bytes < L.total) return fail(GS_ERR_WORKSPACE, "frame block of %zu bytes, %zu needed", bytes, L.total);
+  char* b = static_cast<char*>(block);
+  std::memset(f, 0, sizeof(*f));
+  f->n = n;
+  f->n_views = V;
+  f->n_tiles = nt;
+  f->n_pixels = np;
+  f->max_view_pixels = mv;
+  f->capacity = capacity;
+  f->key_bits = L.key_bits;
+  f->sort_passes = L.passes;
+  f->tile_w = o->tile_w;
+  f->tile_h = o->tile_h;
+  f->cams = cams_dev;
+  f->block = block;
+  f->bytes = bytes;
+  f->rec = reinterpret_cast<float*>(b + L.rec);
+  f->rect = reinterpret_cast<int16_t*>(b + L.rect);
+  f->rgrad = reinterpret_cast<float*>(b + L.rgrad);
+  f->vis_mask = reinterpret_cast<uint64_t*>(b + L.mask);
+  f->n_inst = reinterpret_cast<int32_t*>(b + L.ninst);
+  f->inst_off = reinterpret_cast<int32_t*>(b + L.instoff);
+  f->keys[0] = reinterpret_cast<uint64_t*>(b + L.k0);
+  f->keys[1] = reinterpret_cast<uint64_t*>(b + L.k1);
+  f->vals[0] = reinterpret_cast<int32_t*>(b + L.v0);
+  f->vals[1] = reinterpret_cast<int32_t*>(b + L.v1);
+  f->tile_range = reinterpret_cast<int32_t*>(b + L.range);
+  f->counters = reinterpret_cast<int32_t*>(b + L.counters);
+  f->loss = reinterpret_cast<float*>(b + L.loss);
+  f->scratch = reinterpret_cast<int32_t*>(b + L.scratch);
+  f->scratch_ints = L.scratch_ints;
+  return GS_OK;
+}
+
+int gs_project(const gs_params* p, const gs_frame* f, const gs_opts* o, int32_t zero_grads, void* stream) {
+  int rc;
+  if ((rc = params_check(p, "params")) || (rc = frame_check(f)) || (rc = opts_check(o))) return rc;
+  if (p->n != f->n) return fail(GS_ERR_ARG, "params n %lld != frame n %lld", (long long)p->n, (long long)f->n);
+  if (o->tile_w != f->tile_w || o->tile_h != f->tile_h) return fail(GS_ERR_ARG, "tile size differs from the frame");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  GS_HIP(gs_launch::fill_i32(f->counters, 0, 2, st), "gs_project: clear counters");
+  GS_HIP(gs_launch::project(*p, *f, *o, zero_grads, st), "gs_project");
+  return GS_OK;
+}
+
+int gs_bin_tiles(const gs_frame* f, const gs_opts* o, int32_t sync_count, int64_t* n_instances, void* stream) {
+  int rc;
+  if ((rc = frame_check(f)) || (rc = opts_check(o))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  GS_HIP(gs_launch::scan_exclusive(f->n_inst, f->inst_off, f->n, f->scratch, st), "gs_bin_tiles: scan");
+  GS_HIP(gs_launch::instance_total(*f, st), "gs_bin_tiles: total");
+  int64_t n_sized = f->capacity;
+  const int32_t* count_dev = f->counters;
+  if (sync_count) {
+    int32_t c = 0;
+    GS_HIP(hipMemcpyAsync(&c, f->counters, sizeof(int32_t), hipMemcpyDeviceToHost, st), "gs_bin_tiles: count");
+    GS_HIP(hipStreamSynchronize(st), "gs_bin_tiles: sync");
+    if (n_instances) *n_instances = c;
+    n_sized = c < f->capacity ? c : f->capacity;
+    count_dev = nullptr;
+  }
+  GS_HIP(gs_launch::emit(*f, n_sized, st), "gs_bin_tiles: emit");
+  GS_HIP(gs_launch::sort_pairs(f->keys[0], f->vals[0], f->keys[1], f->vals[1], n_sized, count_dev, f->capacity,
+                               f->key_bits, f->scratch, st),
+         "gs_bin_tiles: sort");
+  GS_HIP(gs_launch::ranges(*f, f->keys[f->sort_passes & 1], n_sized, count_dev, st), "gs_bin_tiles: ranges");
+  return GS_OK;
+}
+
+int gs_render_fwd(const gs_frame* f, const gs_opts* o, const gs_images* out, void* stream) {
+  int rc;
+  if ((rc = frame_check(f)) || (rc = opts_check(o))) return rc;
+  if (!out || !out->rgb || !out->depth || !out->vis) return fail(GS_ERR_ARG, "output images are NULL");
+  if (o->tile_w != f->tile_w || o->tile_h != f->tile_h) return fail(GS_ERR_ARG, "tile size differs from the frame");
+  GS_HIP(gs_launch::render_fwd(*f, *o, *out, static_cast<hipStream_t>(stream)), "gs_render_fwd");
+  return GS_OK;
+}
+
+int gs_render_bwd(const gs_params* p, const gs_frame* f, const gs_opts* o, const gs_images* fwd, const gs_loss* l,
+                  const gs_params* grads, void* stream) {
+  int rc;
+  if ((rc = params_check(p, "params")) || (rc = params_check(grads, "grads")) || (rc = frame_check(f)) ||
+      (rc = opts_check(o)))
+    return rc;
+  if (!l) return fail(GS_ERR_ARG, "loss is NULL");
+  if (p->n != f->n || grads->n != f->n || grads->sh_degree != p->sh_degree)
+    return fail(GS_ERR_ARG, "params / grads / frame sizes differ");
+  if (fwd && (!fwd->rgb || !fwd->depth || !fwd->vis)) return fail(GS_ERR_ARG, "forward images incomplete");
+  if (l->tgt_rgb && !l->tgt_depth) return fail(GS_ERR_ARG, "loss mode needs tgt_depth");
+  if (o->tile_w != f->tile_w || o->tile_h != f->tile_h) return fail(GS_ERR_ARG, "tile size differs from the frame");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (l->tgt_rgb) {
+    GS_HIP(gs_launch::fill_f32(f->loss, 0.f, 1, st), "gs_render_bwd: clear loss");
+    GS_HIP(gs_launch::count_valid(*f, l->tgt_depth, f->max_view_pixels, st), "gs_render_bwd: valid depth");
+  }
+  GS_HIP(gs_launch::render_bwd(*f, *o, fwd, *l, st), "gs_render_bwd: composite");
+  GS_HIP(gs_launch::project_bwd(*p, *f, *o, *grads, st), "gs_render_bwd: projection");
+  return GS_OK;
+}
+
+int gs_adam_step(const gs_params* p, const gs_params* g, const gs_params* m, const gs_params* v, const gs_adam* a,
+                 void* stream) {
+  int rc;
+  if ((rc = params_check(p, "params")) || (rc = params_check(g, "grads")) || (rc = params_check(m, "m")) ||
+      (rc = params_check(v, "v")))
+    return rc;
+  if (g->n != p->n || m->n != p->n || v->n != p->n || g->sh_degree != p->sh_degree ||
+      m->sh_degree != p->sh_degree || v->sh_degree != p->sh_degree)
+    return fail(GS_ERR_ARG, "params / grads / moments sizes differ");
+  if (!a || !a->step || !a->bias) return fail(GS_ERR_ARG, "adam state is NULL");
+  if (!(a->beta1 >= 0.f && a->beta1 < 1.f) || !(a->beta2 >= 0.f && a->beta2 < 1.f) || !(a->eps >= 0.f))
+    return fail(GS_ERR_ARG, "invalid Adam hyper-parameters");
+  GS_HIP(gs_launch::adam(*p, *g, *m, *v, *a, static_cast<hipStream_t>(stream)), "gs_adam_step");
+  return GS_OK;
+}
+
+int gs_read_counters(const gs_frame* f, int64_t* n_instances, int32_t* flags, void* stream) {
+  int rc;
+  if ((rc = frame_check(f))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int32_t c[2] = {0, 0};
+  GS_HIP(hipMemcpyAsync(c, f->counters, sizeof(c), hipMemcpyDeviceToHost, st), "gs_read_counters");
+  GS_HIP(hipStreamSynchronize(st), "gs_read_counters: sync");
+  if (n_instances) *n_instances = c[0];
+  if (flags) *flags = c[1];
+  return GS_OK;
+}
+
+size_t gs_sort_scratch_ints(int64_t n) { return gs_launch::sort_scratch_ints(n); }
+
+int gs_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys_tmp, int32_t* vals_tmp, int64_t n, int32_t key_bits,
+                  int32_t* scratch, void* stream) {
+  if (!keys || !vals || !keys_tmp || !vals_tmp || !scratch) return fail(GS_ERR_ARG, "NULL buffer");
+  if (n < 0 || n > INT32_MAX) return fail(GS_ERR_ARG, "n = %lld", (long long)n);
+  if (key_bits < 1 || key_bits > 64) return fail(GS_ERR_ARG, "key_bits = %d", key_bits);
+  if (n == 0) return GS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int passes = (key_bits + 7) / 8;
+  GS_HIP(gs_launch::sort_pairs(keys, vals, keys_tmp, vals_tmp, n, nullptr, n, key_bits, scratch, st), "gs_sort_pairs");
+  if (passes & 1) {
+    GS_HIP(hipMemcpyAsync(keys, keys_tmp, (size_t)n * 8, hipMemcpyDeviceToDevice, st), "gs_sort_pairs: copy keys");
+    GS_HIP(hipMemcpyAsync(vals, vals_tmp, (size_t)n * 4, hipMemcpyDeviceToDevice, st), "gs_sort_pairs: copy vals");
+  }
+  return GS_OK;
+}
+
+const char* gs_status_string(int s) {
+  switch (s) {
+    case GS_OK: return "ok";
+    case GS_ERR_ARG: return "invalid argument";
+    case GS_ERR_HIP: return "HIP error";
+    case GS_ERR_WORKSPACE: return "workspace too small";
+    case GS_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* gs_last_error(void) { return g_err.c_str(); }
+
+int gs_version(void) { return GS_VERSION; }
+
+}  // extern "C"

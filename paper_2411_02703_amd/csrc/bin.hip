@@ -1,0 +1,321 @@
+// Tile binning: exclusive scan of per-Gaussian instance counts, emission of (tile, depth) keys,
+// stable LSD radix sort (8-bit digits), per-tile ranges.  Integer work, bit-exact by construction:
+// within a tile the order is ascending depth bits, ties by record index (emission order).
+#include "common.h"
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;  // 4096
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per block
+constexpr int kWaveItems = kSortTile / 4;              // 1024 keys per wave
+
+// Exclusive scan of 256 values, one per thread; returns the exclusive prefix, *total = sum.
+__device__ __forceinline__ int block_scan_256(int x, int* sh_wave, int* total) {
+  const int lane = __lane_id(), wave = threadIdx.x >> 6;
+  int incl = x;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(incl, d);
+    if (lane >= d) incl += y;
+  }
+  if (lane == 63) sh_wave[wave] = incl;
+  __syncthreads();
+  int base = 0;
+  for (int w = 0; w < wave; ++w) base += sh_wave[w];
+  *total = sh_wave[0] + sh_wave[1] + sh_wave[2] + sh_wave[3];
+  __syncthreads();
+  return base + incl - x;
+}
+
+// Each block scans kScanTile consecutive items (exclusive) and writes its total.
+__global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int32_t* __restrict__ in, int32_t* __restrict__ out,
+                                                          int64_t n, int32_t* __restrict__ sums) {
+  __shared__ int sh_wave[4];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int acc = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t idx = base + i;
+    v[i] = idx < n ? in[idx] : 0;
+    acc += v[i];
+  }
+  int total;
+  int run = block_scan_256(acc, sh_wave, &total);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t idx = base + i;
+    if (idx < n) out[idx] = run;
+    run += v[i];
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t* __restrict__ out, int64_t n,
+                                                         const int32_t* __restrict__ sums) {
+  const int add = sums[blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  for (int i = threadIdx.x; i < kScanTile; i += kScanThreads) {
+    const int64_t idx = base + i;
+    if (idx < n) out[idx] += add;
+  }
+}
+
+__global__ void k_fill_i32(int32_t* __restrict__ p, int32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_f32(float* __restrict__ p, float v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// counters[0] = total instances; overflow flag if above capacity.
+__global__ void k_instance_total(const int32_t* __restrict__ n_inst, const int32_t* __restrict__ off, int64_t n,
+                                 int64_t capacity, int32_t* __restrict__ counters) {
+  const int64_t total = (int64_t)off[n - 1] + (int64_t)n_inst[n - 1];
+  counters[0] = (int32_t)total;
+  if (total > capacity) atomicOr(counters + 1, GS_FLAG_INSTANCE_OVERFLOW);
+}
+
+__global__ __launch_bounds__(256) void k_emit(const uint64_t* __restrict__ vis_mask, const int32_t* __restrict__ off,
+                                             const short4* __restrict__ rect, const float4* __restrict__ rec,
+                                             const gs_camera* __restrict__ cams, int64_t n, int64_t capacity,
+                                             uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  uint64_t mask = vis_mask[g];
+  int64_t o = off[g];
+  while (mask) {
+    const int v = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    const int64_t r = (int64_t)v * n + g;
+    const short4 rc = rect[r];
+    const uint32_t zb = __float_as_uint(rec[3 * r].z);
+    const int toff = cams[v].tile_offset, tx_n = cams[v].tiles_x;
+    for (int ty = rc.z; ty <= rc.w; ++ty)
+      for (int tx = rc.x; tx <= rc.y; ++tx) {
+        if (o < capacity) {
+          keys[o] = ((uint64_t)(uint32_t)(toff + ty * tx_n + tx) << 32) | (uint64_t)zb;
+          vals[o] = (int32_t)r;
+        }
+        ++o;
+      }
+  }
+}
+
+__device__ __forceinline__ int64_t sort_count(const int32_t* count_dev, int64_t n_sized, int64_t cap) {
+  if (count_dev == nullptr) return n_sized;
+  const int64_t c = count_dev[0];
+  return c < cap ? c : cap;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t* __restrict__ keys,
+                                                           const int32_t* __restrict__ count_dev, int64_t n_sized,
+                                                           int64_t cap, int shift, int32_t* __restrict__ hist,
+                                                           int nblocks) {
+  __shared__ int h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t n = sort_count(count_dev, n_sized, cap);
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int i = 0; i < kSortItems; ++i) {
+    const int64_t idx = base + i * kSortThreads + threadIdx.x;
+    if (idx < n) atomicAdd(&h[(int)((keys[idx] >> shift) & 255u)], 1);
+  }
+  __syncthreads();
+  hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter of one 8-bit digit.  Each wave ranks its 1024 keys (16 rounds of 64) with ballot-based
+// digit matching, the block orders them in LDS (digit-major, stable), then writes runs to their global
+// offsets from the scanned digit-major histogram.
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* __restrict__ kin,
+                                                              const int32_t* __restrict__ vin,
+                                                              uint64_t* __restrict__ kout, int32_t* __restrict__ vout,
+                                                              const int32_t* __restrict__ count_dev, int64_t n_sized,
+                                                              int64_t cap, int shift,
+                                                              const int32_t* __restrict__ hist_scan, int nblocks) {
+  __shared__ uint64_t sk[kSortTile];
+  __shared__ int32_t sv[kSortTile];
+  __shared__ int32_t wcnt[4][256];
+  __shared__ int32_t dstart[256];
+  __shared__ int32_t gofs[256];
+  __shared__ int sh_wave[4];
+  const int64_t n = sort_count(count_dev, n_sized, cap);
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  if (base >= n) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id();
+  for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
+  __syncthreads();
+  uint64_t key[kSortItems];
+  int32_t val[kSortItems];
+  int pos[kSortItems];
+  const uint64_t lt = gsk::lanemask_lt();
+#pragma unroll
+  for (int k = 0; k < kSortItems; ++k) {
+    const int64_t idx = base + (int64_t)wave * kWaveItems + k * 64 + lane;
+    const bool valid = idx < n;
+    key[k] = valid ? kin[idx] : 0ull;
+    val[k] = valid ? vin[idx] : 0;
+    const int d = (int)((key[k] >> shift) & 255u);
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const int rank = __popcll(peers & lt);
+    int before = 0;
+    if (valid) before = wcnt[wave][d];
+    pos[k] = before + rank;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && rank == 0) wcnt[wave][d] = before + __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  {
+    const int c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
+    int total;
+    const int ds = block_scan_256(c0 + c1 + c2 + c3, sh_wave, &total);
+    dstart[tid] = ds;
+    wcnt[0][tid] = ds;
+    wcnt[1][tid] = ds + c0;
+    wcnt[2][tid] = ds + c0 + c1;
+    wcnt[3][tid] = ds + c0 + c1 + c2;
+    gofs[tid] = hist_scan[tid * nblocks + blockIdx.x];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSortItems; ++k) {
+    const int64_t idx = base + (int64_t)wave * kWaveItems + k * 64 + lane;
+    if (idx < n) {
+      const int d = (int)((key[k] >> shift) & 255u);
+      const int p = wcnt[wave][d] + pos[k];
+      sk[p] = key[k];
+      sv[p] = val[k];
+    }
+  }
+  __syncthreads();
+  const int64_t rem = n - base;
+  const int nvalid = rem < kSortTile ? (int)rem : kSortTile;
+  for (int p = tid; p < nvalid; p += kSortThreads) {
+    const uint64_t kk = sk[p];
+    const int d = (int)((kk >> shift) & 255u);
+    const int64_t o = (int64_t)gofs[d] + (p - dstart[d]);
+    kout[o] = kk;
+    vout[o] = sv[p];
+  }
+}
+
+__global__ void k_ranges(const uint64_t* __restrict__ keys, const int32_t* __restrict__ count_dev, int64_t n_sized,
+                         int64_t cap, int2* __restrict__ range) {
+  const int64_t n = sort_count(count_dev, n_sized, cap);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t t = (uint32_t)(keys[i] >> 32);
+  if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) range[t].x = (int)i;
+  if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != t) range[t].y = (int)(i + 1);
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t align64(int64_t a) { return (a + 63) & ~int64_t(63); }
+
+}  // namespace
+
+namespace gs_launch {
+
+size_t scan_scratch_ints(int64_t n) {
+  size_t total = 0;
+  while (n > 1) {
+    n = cdiv(n, kScanTile);
+    total += (size_t)align64(n);
+  }
+  return total + 64;
+}
+
+hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = cdiv(n, kScanTile);
+  int32_t* sums = scratch;
+  k_scan_tile<<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, n, sums);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (nb > 1) {
+    e = scan_exclusive(sums, sums, nb, scratch + align64(nb), st);
+    if (e != hipSuccess) return e;
+    k_scan_add<<<(unsigned)nb, kScanThreads, 0, st>>>(out, n, sums);
+    return hipGetLastError();
+  }
+  return hipSuccess;
+}
+
+hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_fill_i32<<<(unsigned)cdiv(n, 256), 256, 0, st>>>(p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  k_fill_f32<<<(unsigned)cdiv(n, 256), 256, 0, st>>>(p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t instance_total(const gs_frame& f, hipStream_t st) {
+  k_instance_total<<<1, 1, 0, st>>>(f.n_inst, f.inst_off, f.n, f.capacity, f.counters);
+  return hipGetLastError();
+}
+
+hipError_t emit(const gs_frame& f, int64_t /*n_sized*/, hipStream_t st) {
+  k_emit<<<(unsigned)cdiv(f.n, 256), 256, 0, st>>>(f.vis_mask, f.inst_off, reinterpret_cast<const short4*>(f.rect),
+                                                   reinterpret_cast<const float4*>(f.rec), f.cams, f.n, f.capacity,
+                                                   f.keys[0], f.vals[0]);
+  return hipGetLastError();
+}
+
+size_t sort_scratch_ints(int64_t n) {
+  const int64_t nb = cdiv(n > 0 ? n : 1, kSortTile);
+  return (size_t)align64(256 * nb) + scan_scratch_ints(256 * nb);
+}
+
+hipError_t sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int64_t n_sized, const int32_t* count_dev,
+                      int64_t cap, int key_bits, int32_t* scratch, hipStream_t st) {
+  if (n_sized <= 0) return hipSuccess;
+  const int64_t nb = cdiv(n_sized, kSortTile);
+  int32_t* hist = scratch;
+  int32_t* scan_scr = scratch + align64(256 * nb);
+  const int passes = (key_bits + 7) / 8;
+  uint64_t* kb[2] = {k0, k1};
+  int32_t* vb[2] = {v0, v1};
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    const int src = p & 1, dst = src ^ 1;
+    k_sort_hist<<<(unsigned)nb, kSortThreads, 0, st>>>(kb[src], count_dev, n_sized, cap, shift, hist, (int)nb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_exclusive(hist, hist, 256 * nb, scan_scr, st);
+    if (e != hipSuccess) return e;
+    k_sort_scatter<<<(unsigned)nb, kSortThreads, 0, st>>>(kb[src], vb[src], kb[dst], vb[dst], count_dev, n_sized,
+                                                          cap, shift, hist, (int)nb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t ranges(const gs_frame& f, const uint64_t* keys, int64_t n_sized, const int32_t* count_dev,
+                  hipStream_t st) {
+  hipError_t e = fill_i32(f.tile_range, 0, 2 * (int64_t)f.n_tiles, st);
+  if (e != hipSuccess || n_sized <= 0) return e;
+  k_ranges<<<(unsigned)cdiv(n_sized, 256), 256, 0, st>>>(keys, count_dev, n_sized, f.capacity,
+                                                         reinterpret_cast<int2*>(f.tile_range));
+  return hipGetLastError();
+}
+
+}  // namespace gs_launch

@@ -1,0 +1,110 @@
+// Internal device helpers of libgs (HIP, gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/libgs.h"
+
+namespace gsk {
+
+constexpr int kWave = 64;
+
+// Options as the kernels see them (passed by value).
+struct DevOpts {
+  float near_z, lowpass, alpha_min, alpha_max, t_min;
+  float bg[3];
+  int tile_w, tile_h;
+};
+
+inline DevOpts dev_opts(const gs_opts& o) {
+  DevOpts d;
+  d.near_z = o.near_z;
+  d.lowpass = o.lowpass;
+  d.alpha_min = o.alpha_min;
+  d.alpha_max = o.alpha_max;
+  d.t_min = o.t_min;
+  d.bg[0] = o.bg[0];
+  d.bg[1] = o.bg[1];
+  d.bg[2] = o.bg[2];
+  d.tile_w = o.tile_w;
+  d.tile_h = o.tile_h;
+  return d;
+}
+
+// ------------------------------------------------------------------ wave primitives
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int l = __lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// DPP move of a float with control CTRL; lanes without a valid source (or in a masked row) read 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
+}
+
+// Sum over the 64 lanes of a wave; the total lands in lane 63.  Six DPP adds:
+// pairs, quads, half rows, rows (mirrors), then row broadcasts 15 and 31 across rows.
+__device__ __forceinline__ float wave_sum_last(float x) {
+  x += dpp_f<0xB1>(x);        // quad_perm [1,0,3,2]
+  x += dpp_f<0x4E>(x);        // quad_perm [2,3,0,1]
+  x += dpp_f<0x141>(x);       // row_half_mirror
+  x += dpp_f<0x140>(x);       // row_mirror
+  x += dpp_f<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_f<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+__device__ __forceinline__ float read_lane(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+// Hardware float atomic add without return (global_atomic_add_f32).
+__device__ __forceinline__ void atomic_add_f32(float* p, float v) { unsafeAtomicAdd(p, v); }
+
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous range of work items
+// so neighbouring tiles (which share Gaussians) meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+  const int per = (nblocks + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+// View of a global tile: largest v with tile_offset <= tile (uniform scalar loop, n_views <= 64).
+__device__ __forceinline__ int view_of_tile(const gs_camera* __restrict__ cams, int n_views, int tile) {
+  int v = 0;
+  for (int i = 1; i < n_views; ++i)
+    if (cams[i].tile_offset <= tile) v = i;
+  return v;
+}
+
+__device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
+
+}  // namespace gsk
+
+// ------------------------------------------------------------------ host launchers (one per file)
+namespace gs_launch {
+hipError_t project(const gs_params& p, const gs_frame& f, const gs_opts& o, int zero_grads, hipStream_t s);
+hipError_t project_bwd(const gs_params& p, const gs_frame& f, const gs_opts& o, const gs_params& g,
+                       hipStream_t s);
+size_t scan_scratch_ints(int64_t n);
+hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t s);
+hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t s);
+hipError_t instance_total(const gs_frame& f, hipStream_t s);
+hipError_t emit(const gs_frame& f, int64_t n_sized, hipStream_t s);
+size_t sort_scratch_ints(int64_t n);
+hipError_t sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int64_t n_sized,
+                      const int32_t* count_dev, int64_t cap, int key_bits, int32_t* scratch, hipStream_t s);
+hipError_t ranges(const gs_frame& f, const uint64_t* keys, int64_t n_sized, const int32_t* count_dev, hipStream_t s);
+hipError_t render_fwd(const gs_frame& f, const gs_opts& o, const gs_images& out, hipStream_t s);
+hipError_t count_valid(const gs_frame& f, const float* tgt_depth, int64_t max_pixels, hipStream_t s);
+hipError_t render_bwd(const gs_frame& f, const gs_opts& o, const gs_images* fwd, const gs_loss& l,
+                      hipStream_t s);
+hipError_t adam(const gs_params& p, const gs_params& g, const gs_params& m, const gs_params& v,
+                const gs_adam& a, hipStream_t s);
+}  // namespace gs_launch

@@ -1,0 +1,454 @@
+// Projection of 3D Gaussians to per-view 2D conics and its backward (LVI-GS Section III-B:
+// covariance factorisation eq. Sigma, EWA projection eq. muI; colour from real spherical harmonics,
+// Section III-E).  One thread per Gaussian; it reads the Gaussian once and loops over all views.
+#include "common.h"
+
+namespace {
+
+using gsk::DevOpts;
+
+// Real orthonormal spherical harmonics up to degree 3 (Cartesian form on the unit sphere),
+// ordered by l then m = -l..l.
+constexpr float kC0 = 0.28209479177387814f;
+constexpr float kC1 = 0.4886025119029199f;
+constexpr float kC2a = 1.0925484305920792f;   // xy, yz, xz
+constexpr float kC2b = 0.31539156525252005f;  // 3z^2 - 1
+constexpr float kC2c = 0.5462742152960396f;   // x^2 - y^2
+constexpr float kC3a = 0.5900435899266435f;   // y(3x^2 - y^2), x(x^2 - 3y^2)
+constexpr float kC3b = 2.890611442640554f;    // xyz
+constexpr float kC3c = 0.4570457994644658f;   // y(5z^2 - 1), x(5z^2 - 1)
+constexpr float kC3d = 0.3731763325901154f;   // z(5z^2 - 3)
+constexpr float kC3e = 1.445305721320277f;    // z(x^2 - y^2)
+
+template <int DEG>
+__device__ __forceinline__ void sh_basis(float x, float y, float z, float* Y) {
+  Y[0] = kC0;
+  if (DEG >= 1) {
+    Y[1] = kC1 * y;
+    Y[2] = kC1 * z;
+    Y[3] = kC1 * x;
+  }
+  if (DEG >= 2) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = kC2a * (x * y);
+    Y[5] = kC2a * (y * z);
+    Y[6] = kC2b * (3.f * zz - 1.f);
+    Y[7] = kC2a * (x * z);
+    Y[8] = kC2c * (xx - yy);
+    if (DEG >= 3) {
+      Y[9] = kC3a * y * (3.f * xx - yy);
+      Y[10] = kC3b * (x * y) * z;
+      Y[11] = kC3c * y * (5.f * zz - 1.f);
+      Y[12] = kC3d * z * (5.f * zz - 3.f);
+      Y[13] = kC3c * x * (5.f * zz - 1.f);
+      Y[14] = kC3e * z * (xx - yy);
+      Y[15] = kC3a * x * (xx - 3.f * yy);
+    }
+  }
+}
+
+// sum_k w_k grad Y_k at (x, y, z) for the forms above (the radial part is removed by the caller).
+template <int DEG>
+__device__ __forceinline__ void sh_dir_grad(float x, float y, float z, const float* w, float& gx, float& gy,
+                                            float& gz) {
+  gx = gy = gz = 0.f;
+  if (DEG >= 1) {
+    gy += kC1 * w[1];
+    gz += kC1 * w[2];
+    gx += kC1 * w[3];
+  }
+  if (DEG >= 2) {
+    gx += kC2a * y * w[4];
+    gy += kC2a * x * w[4];
+    gy += kC2a * z * w[5];
+    gz += kC2a * y * w[5];
+    gz += 6.f * kC2b * z * w[6];
+    gx += kC2a * z * w[7];
+    gz += kC2a * x * w[7];
+    gx += 2.f * kC2c * x * w[8];
+    gy -= 2.f * kC2c * y * w[8];
+    if (DEG >= 3) {
+      const float xx = x * x, yy = y * y, zz = z * z;
+      gx += 6.f * kC3a * x * y * w[9];
+      gy += 3.f * kC3a * (xx - yy) * w[9];
+      gx += kC3b * y * z * w[10];
+      gy += kC3b * x * z * w[10];
+      gz += kC3b * x * y * w[10];
+      gy += kC3c * (5.f * zz - 1.f) * w[11];
+      gz += 10.f * kC3c * y * z * w[11];
+      gz += kC3d * (15.f * zz - 3.f) * w[12];
+      gx += kC3c * (5.f * zz - 1.f) * w[13];
+      gz += 10.f * kC3c * x * z * w[13];
+      gx += 2.f * kC3e * x * z * w[14];
+      gy -= 2.f * kC3e * y * z * w[14];
+      gz += kC3e * (xx - yy) * w[14];
+      gx += 3.f * kC3a * (xx - yy) * w[15];
+      gy -= 6.f * kC3a * x * y * w[15];
+    }
+  }
+}
+
+// Camera transform with a fixed operation order (reproducible bit for bit):
+// t_r = fma(R_r2, mu_z, fma(R_r1, mu_y, fma(R_r0, mu_x, T_r))).
+__device__ __forceinline__ void camera_point(const gs_camera& c, float m0, float m1, float m2, float& tx, float& ty,
+                                             float& tz) {
+  tx = __builtin_fmaf(c.R[2], m2, __builtin_fmaf(c.R[1], m1, __builtin_fmaf(c.R[0], m0, c.T[0])));
+  ty = __builtin_fmaf(c.R[5], m2, __builtin_fmaf(c.R[4], m1, __builtin_fmaf(c.R[3], m0, c.T[1])));
+  tz = __builtin_fmaf(c.R[8], m2, __builtin_fmaf(c.R[7], m1, __builtin_fmaf(c.R[6], m0, c.T[2])));
+}
+
+// View-independent part of one Gaussian.
+struct Shape {
+  float S[3];
+  float q[4], qnorm;
+  float Rq[9];
+  float M[9];
+  float Sig[6];  // s00 s01 s02 s11 s12 s22
+  float o;
+};
+
+__device__ __forceinline__ void shape_of(const float* ls, const float* qq, float ol, Shape& s) {
+  for (int i = 0; i < 3; ++i) s.S[i] = expf(ls[i]);
+  s.qnorm = sqrtf(qq[0] * qq[0] + qq[1] * qq[1] + qq[2] * qq[2] + qq[3] * qq[3]);
+  const float iq = 1.f / s.qnorm;
+  for (int i = 0; i < 4; ++i) s.q[i] = qq[i] * iq;
+  const float w = s.q[0], x = s.q[1], y = s.q[2], z = s.q[3];
+  s.Rq[0] = 1.f - 2.f * (y * y + z * z);
+  s.Rq[1] = 2.f * (x * y - w * z);
+  s.Rq[2] = 2.f * (x * z + w * y);
+  s.Rq[3] = 2.f * (x * y + w * z);
+  s.Rq[4] = 1.f - 2.f * (x * x + z * z);
+  s.Rq[5] = 2.f * (y * z - w * x);
+  s.Rq[6] = 2.f * (x * z - w * y);
+  s.Rq[7] = 2.f * (y * z + w * x);
+  s.Rq[8] = 1.f - 2.f * (x * x + y * y);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) s.M[i * 3 + j] = s.Rq[i * 3 + j] * s.S[j];
+  // Sigma = M M^T
+  auto row_dot = [&](int i, int j) {
+    return s.M[i * 3] * s.M[j * 3] + s.M[i * 3 + 1] * s.M[j * 3 + 1] + s.M[i * 3 + 2] * s.M[j * 3 + 2];
+  };
+  s.Sig[0] = row_dot(0, 0);
+  s.Sig[1] = row_dot(0, 1);
+  s.Sig[2] = row_dot(0, 2);
+  s.Sig[3] = row_dot(1, 1);
+  s.Sig[4] = row_dot(1, 2);
+  s.Sig[5] = row_dot(2, 2);
+  s.o = 1.f / (1.f + expf(-ol));
+}
+
+// EWA: rows u, w of T2 = J W and the 2x2 covariance A, B, C (with the low-pass on the diagonal).
+struct Ewa {
+  float u[3], w[3], su[3], sw[3];
+  float A, B, C, det;
+  float inv_tz;
+};
+
+__device__ __forceinline__ void ewa(const gs_camera& c, const float* Sig, float tx, float ty, float tz, float lowpass,
+                                    Ewa& e) {
+  e.inv_tz = 1.f / tz;
+  const float j00 = c.fx * e.inv_tz, j11 = c.fy * e.inv_tz;
+  const float j02 = -c.fx * tx * e.inv_tz * e.inv_tz;
+  const float j12 = -c.fy * ty * e.inv_tz * e.inv_tz;
+  for (int k = 0; k < 3; ++k) {
+    e.u[k] = j00 * c.R[k] + j02 * c.R[6 + k];
+    e.w[k] = j11 * c.R[3 + k] + j12 * c.R[6 + k];
+  }
+  const float s00 = Sig[0], s01 = Sig[1], s02 = Sig[2], s11 = Sig[3], s12 = Sig[4], s22 = Sig[5];
+  e.su[0] = s00 * e.u[0] + s01 * e.u[1] + s02 * e.u[2];
+  e.su[1] = s01 * e.u[0] + s11 * e.u[1] + s12 * e.u[2];
+  e.su[2] = s02 * e.u[0] + s12 * e.u[1] + s22 * e.u[2];
+  e.sw[0] = s00 * e.w[0] + s01 * e.w[1] + s02 * e.w[2];
+  e.sw[1] = s01 * e.w[0] + s11 * e.w[1] + s12 * e.w[2];
+  e.sw[2] = s02 * e.w[0] + s12 * e.w[1] + s22 * e.w[2];
+  e.A = e.u[0] * e.su[0] + e.u[1] * e.su[1] + e.u[2] * e.su[2] + lowpass;
+  e.B = e.u[0] * e.sw[0] + e.u[1] * e.sw[1] + e.u[2] * e.sw[2];
+  e.C = e.w[0] * e.sw[0] + e.w[1] * e.sw[1] + e.w[2] * e.sw[2] + lowpass;
+  e.det = e.A * e.C - e.B * e.B;
+}
+
+template <int DEG>
+__device__ __forceinline__ void colour(const float* f, float dx, float dy, float dz, float* Y, float* pre) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  sh_basis<DEG>(dx, dy, dz, Y);
+  for (int ch = 0; ch < 3; ++ch) {
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) s += f[k * 3 + ch] * Y[k];
+    pre[ch] = s + 0.5f;
+  }
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project(const float* __restrict__ means, const float* __restrict__ log_scales,
+                                                 const float* __restrict__ quats, const float* __restrict__ opac,
+                                                 const float* __restrict__ sh, int64_t n,
+                                                 const gs_camera* __restrict__ cams, int V, DevOpts op,
+                                                 int zero_grads, float4* __restrict__ rec, short4* __restrict__ rect,
+                                                 float4* __restrict__ rgrad, uint64_t* __restrict__ vis_mask,
+                                                 int32_t* __restrict__ n_inst, int32_t* __restrict__ flags) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  float mu[3], ls[3], qq[4], f[K * 3];
+  bool finite = true;
+  for (int i = 0; i < 3; ++i) {
+    mu[i] = means[g * 3 + i];
+    ls[i] = log_scales[g * 3 + i];
+    finite &= isfinite(mu[i]) && isfinite(ls[i]);
+  }
+  for (int i = 0; i < 4; ++i) {
+    qq[i] = quats[g * 4 + i];
+    finite &= isfinite(qq[i]);
+  }
+  const float ol = opac[g];
+  finite &= isfinite(ol);
+#pragma unroll
+  for (int i = 0; i < K * 3; ++i) {
+    f[i] = sh[g * (K * 3) + i];
+    finite &= isfinite(f[i]);
+  }
+  uint64_t mask = 0;
+  int cnt = 0;
+  if (!finite) {
+    atomicOr(flags, GS_FLAG_NONFINITE);
+  } else {
+    Shape s;
+    shape_of(ls, qq, ol, s);
+    if (s.qnorm > 0.f && s.o >= op.alpha_min) {
+      // opacity-aware radius factor: outside sqrt(kp * Sigma_I,diag) alpha < exp(-1/2) / 255
+      const float kp = 2.f * logf(255.f * s.o) + 1.f;
+      for (int v = 0; v < V; ++v) {
+        const gs_camera& c = cams[v];
+        float tx, ty, tz;
+        camera_point(c, mu[0], mu[1], mu[2], tx, ty, tz);
+        if (!(tz >= op.near_z)) continue;
+        const float un = tx / tz, vn = ty / tz;
+        const float mx = __builtin_fmaf(c.fx, un, c.cx);
+        const float my = __builtin_fmaf(c.fy, vn, c.cy);
+        if (!(mx >= c.guard_lo_x && mx <= c.guard_hi_x && my >= c.guard_lo_y && my <= c.guard_hi_y)) continue;
+        Ewa e;
+        ewa(c, s.Sig, tx, ty, tz, op.lowpass, e);
+        if (!(e.det > 0.f) || !isfinite(e.det)) continue;
+        const float ext_x = sqrtf(kp * e.A), ext_y = sqrtf(kp * e.C);
+        float lo_x = ceilf(mx - ext_x - 0.5f), hi_x = floorf(mx + ext_x - 0.5f);
+        float lo_y = ceilf(my - ext_y - 0.5f), hi_y = floorf(my + ext_y - 0.5f);
+        lo_x = fminf(fmaxf(lo_x, 0.f), (float)c.width);
+        hi_x = fminf(fmaxf(hi_x, -1.f), (float)(c.width - 1));
+        lo_y = fminf(fmaxf(lo_y, 0.f), (float)c.height);
+        hi_y = fminf(fmaxf(hi_y, -1.f), (float)(c.height - 1));
+        const int px0 = (int)lo_x, px1 = (int)hi_x, py0 = (int)lo_y, py1 = (int)hi_y;
+        if (px0 > px1 || py0 > py1) continue;
+        const int tx0 = px0 / op.tile_w, tx1 = px1 / op.tile_w, ty0 = py0 / op.tile_h, ty1 = py1 / op.tile_h;
+        const float det_inv = 1.f / e.det;
+        // colour at the direction from the camera centre
+        const float d0 = mu[0] - c.campos[0], d1 = mu[1] - c.campos[1], d2 = mu[2] - c.campos[2];
+        const float idist = 1.f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+        float Y[K], pre[3];
+        colour<DEG>(f, d0 * idist, d1 * idist, d2 * idist, Y, pre);
+        const int64_t r = (int64_t)v * n + g;
+        rec[3 * r + 0] = make_float4(mx, my, tz, s.o);
+        rec[3 * r + 1] = make_float4(e.C * det_inv, -e.B * det_inv, e.A * det_inv, fmaxf(pre[0], 0.f));
+        rec[3 * r + 2] = make_float4(fmaxf(pre[1], 0.f), fmaxf(pre[2], 0.f), 0.f, 0.f);
+        rect[r] = make_short4((short)tx0, (short)tx1, (short)ty0, (short)ty1);
+        if (zero_grads) {
+          const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+          rgrad[3 * r + 0] = z4;
+          rgrad[3 * r + 1] = z4;
+          rgrad[3 * r + 2] = z4;
+        }
+        mask |= 1ull << v;
+        cnt += (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+      }
+    }
+  }
+  vis_mask[g] = mask;
+  n_inst[g] = cnt;
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ means,
+                                                     const float* __restrict__ log_scales,
+                                                     const float* __restrict__ quats, const float* __restrict__ opac,
+                                                     const float* __restrict__ sh, int64_t n,
+                                                     const gs_camera* __restrict__ cams, DevOpts op,
+                                                     const float4* __restrict__ rgrad,
+                                                     const uint64_t* __restrict__ vis_mask, float* __restrict__ g_means,
+                                                     float* __restrict__ g_scales, float* __restrict__ g_quats,
+                                                     float* __restrict__ g_opac, float* __restrict__ g_sh) {
+  constexpr int K = (DEG + 1) * (DEG + 1);
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  uint64_t mask = vis_mask[g];
+  if (mask == 0) return;
+  float mu[3], ls[3], qq[4], f[K * 3];
+  for (int i = 0; i < 3; ++i) {
+    mu[i] = means[g * 3 + i];
+    ls[i] = log_scales[g * 3 + i];
+  }
+  for (int i = 0; i < 4; ++i) qq[i] = quats[g * 4 + i];
+#pragma unroll
+  for (int i = 0; i < K * 3; ++i) f[i] = sh[g * (K * 3) + i];
+  Shape s;
+  shape_of(ls, qq, opac[g], s);
+
+  float gmu[3] = {0.f, 0.f, 0.f};
+  float gs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // symmetric dL/dSigma: 00 01 02 11 12 22
+  float go = 0.f;
+  float gf[K * 3];
+#pragma unroll
+  for (int i = 0; i < K * 3; ++i) gf[i] = 0.f;
+
+  while (mask) {
+    const int v = __builtin_ctzll(mask);
+    mask &= mask - 1;
+    const gs_camera& c = cams[v];
+    const int64_t r = (int64_t)v * n + g;
+    const float4 q0 = rgrad[3 * r + 0], q1 = rgrad[3 * r + 1], q2 = rgrad[3 * r + 2];
+    const float dmx = q0.x, dmy = q0.y, da = q0.z, db = q0.w;
+    const float dc = q1.x, d_o = q1.y, dr = q1.z, dg = q1.w;
+    const float dbl = q2.x, dz = q2.y;
+    float tx, ty, tz;
+    camera_point(c, mu[0], mu[1], mu[2], tx, ty, tz);
+    Ewa e;
+    ewa(c, s.Sig, tx, ty, tz, op.lowpass, e);
+    const float idet = 1.f / e.det;
+    const float a = e.C * idet, b = -e.B * idet, cc = e.A * idet;
+    // conic (a, b, c) = inverse of [[A, B], [B, C]]
+    const float GA = -(a * a * da + a * b * db + b * b * dc);
+    const float GC = -(b * b * da + b * cc * db + cc * cc * dc);
+    const float GB = -(2.f * a * b * da + (a * cc + b * b) * db + 2.f * b * cc * dc);
+    // A = u.Sigma.u, B = u.Sigma.w, C = w.Sigma.w
+    const float* u = e.u;
+    const float* w = e.w;
+    gs[0] += GA * u[0] * u[0] + GB * u[0] * w[0] + GC * w[0] * w[0];
+    gs[1] += GA * u[0] * u[1] + 0.5f * GB * (u[0] * w[1] + w[0] * u[1]) + GC * w[0] * w[1];
+    gs[2] += GA * u[0] * u[2] + 0.5f * GB * (u[0] * w[2] + w[0] * u[2]) + GC * w[0] * w[2];
+    gs[3] += GA * u[1] * u[1] + GB * u[1] * w[1] + GC * w[1] * w[1];
+    gs[4] += GA * u[1] * u[2] + 0.5f * GB * (u[1] * w[2] + w[1] * u[2]) + GC * w[1] * w[2];
+    gs[5] += GA * u[2] * u[2] + GB * u[2] * w[2] + GC * w[2] * w[2];
+    float Gu[3], Gw[3];
+    for (int k = 0; k < 3; ++k) {
+      Gu[k] = 2.f * GA * e.su[k] + GB * e.sw[k];
+      Gw[k] = 2.f * GC * e.sw[k] + GB * e.su[k];
+    }
+    // u = J00 W_0 + J02 W_2, w = J11 W_1 + J12 W_2 (W_i rows of the camera rotation)
+    const float GJ00 = Gu[0] * c.R[0] + Gu[1] * c.R[1] + Gu[2] * c.R[2];
+    const float GJ02 = Gu[0] * c.R[6] + Gu[1] * c.R[7] + Gu[2] * c.R[8];
+    const float GJ11 = Gw[0] * c.R[3] + Gw[1] * c.R[4] + Gw[2] * c.R[5];
+    const float GJ12 = Gw[0] * c.R[6] + Gw[1] * c.R[7] + Gw[2] * c.R[8];
+    const float it = e.inv_tz, it2 = it * it, it3 = it2 * it;
+    const float gtx = -c.fx * it2 * GJ02 + dmx * c.fx * it;
+    const float gty = -c.fy * it2 * GJ12 + dmy * c.fy * it;
+    const float gtz = -c.fx * it2 * GJ00 + 2.f * c.fx * tx * it3 * GJ02 - c.fy * it2 * GJ11 +
+                      2.f * c.fy * ty * it3 * GJ12 - dmx * c.fx * tx * it2 - dmy * c.fy * ty * it2 + dz;
+    for (int j = 0; j < 3; ++j) gmu[j] += c.R[j] * gtx + c.R[3 + j] * gty + c.R[6 + j] * gtz;
+    go += d_o;
+    // colour
+    const float d0 = mu[0] - c.campos[0], d1 = mu[1] - c.campos[1], d2 = mu[2] - c.campos[2];
+    const float idist = 1.f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+    const float x = d0 * idist, y = d1 * idist, z = d2 * idist;
+    float Y[K], pre[3];
+    colour<DEG>(f, x, y, z, Y, pre);
+    const float grgb[3] = {pre[0] >= 0.f ? dr : 0.f, pre[1] >= 0.f ? dg : 0.f, pre[2] >= 0.f ? dbl : 0.f};
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      for (int ch = 0; ch < 3; ++ch) gf[k * 3 + ch] += grgb[ch] * Y[k];
+    if (DEG > 0) {
+      float wk[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) wk[k] = grgb[0] * f[k * 3] + grgb[1] * f[k * 3 + 1] + grgb[2] * f[k * 3 + 2];
+      float gx, gy, gz;
+      sh_dir_grad<DEG>(x, y, z, wk, gx, gy, gz);
+      const float dot = gx * x + gy * y + gz * z;
+      gmu[0] += (gx - x * dot) * idist;
+      gmu[1] += (gy - y * dot) * idist;
+      gmu[2] += (gz - z * dot) * idist;
+    }
+  }
+  // Sigma = M M^T: dL/dM = 2 Gs M ; M = Rq diag(S)
+  const float Gs[9] = {gs[0], gs[1], gs[2], gs[1], gs[3], gs[4], gs[2], gs[4], gs[5]};
+  float GM[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      GM[i * 3 + j] = 2.f * (Gs[i * 3] * s.M[j] + Gs[i * 3 + 1] * s.M[3 + j] + Gs[i * 3 + 2] * s.M[6 + j]);
+  float gls[3], GR[9];
+  for (int j = 0; j < 3; ++j) {
+    const float dS = s.Rq[j] * GM[j] + s.Rq[3 + j] * GM[3 + j] + s.Rq[6 + j] * GM[6 + j];
+    gls[j] = dS * s.S[j];
+    for (int i = 0; i < 3; ++i) GR[i * 3 + j] = GM[i * 3 + j] * s.S[j];
+  }
+  const float qw = s.q[0], qx = s.q[1], qy = s.q[2], qz = s.q[3];
+  float gq[4];
+  gq[0] = 2.f * (-qz * GR[1] + qy * GR[2] + qz * GR[3] - qx * GR[5] - qy * GR[6] + qx * GR[7]);
+  gq[1] = 2.f * (qy * GR[1] + qz * GR[2] + qy * GR[3] - 2.f * qx * GR[4] - qw * GR[5] + qz * GR[6] + qw * GR[7] -
+                 2.f * qx * GR[8]);
+  gq[2] = 2.f * (-2.f * qy * GR[0] + qx * GR[1] + qw * GR[2] + qx * GR[3] + qz * GR[5] - qw * GR[6] + qz * GR[7] -
+                 2.f * qy * GR[8]);
+  gq[3] = 2.f * (-2.f * qz * GR[0] - qw * GR[1] + qx * GR[2] + qw * GR[3] - 2.f * qz * GR[4] + qy * GR[5] +
+                 qx * GR[6] + qy * GR[7]);
+  const float dq = gq[0] * qw + gq[1] * qx + gq[2] * qy + gq[3] * qz;
+  const float iq = 1.f / s.qnorm;
+  for (int i = 0; i < 3; ++i) {
+    g_means[g * 3 + i] += gmu[i];
+    g_scales[g * 3 + i] += gls[i];
+  }
+  for (int i = 0; i < 4; ++i) g_quats[g * 4 + i] += (gq[i] - s.q[i] * dq) * iq;
+  g_opac[g] += go * s.o * (1.f - s.o);
+#pragma unroll
+  for (int i = 0; i < K * 3; ++i) g_sh[g * (K * 3) + i] += gf[i];
+}
+
+}  // namespace
+
+namespace gs_launch {
+
+hipError_t project(const gs_params& p, const gs_frame& f, const gs_opts& o, int zero_grads, hipStream_t st) {
+  const int threads = 256;
+  const int blocks = (int)((p.n + threads - 1) / threads);
+  const DevOpts op = gsk::dev_opts(o);
+  auto* rec = reinterpret_cast<float4*>(f.rec);
+  auto* rect = reinterpret_cast<short4*>(f.rect);
+  auto* rg = reinterpret_cast<float4*>(f.rgrad);
+  int32_t* flags = f.counters + 1;
+  switch (p.sh_degree) {
+    case 0:
+      k_project<0><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams,
+                                               f.n_views, op, zero_grads, rec, rect, rg, f.vis_mask, f.n_inst, flags);
+      break;
+    case 1:
+      k_project<1><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams,
+                                               f.n_views, op, zero_grads, rec, rect, rg, f.vis_mask, f.n_inst, flags);
+      break;
+    case 2:
+      k_project<2><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams,
+                                               f.n_views, op, zero_grads, rec, rect, rg, f.vis_mask, f.n_inst, flags);
+      break;
+    default:
+      k_project<3><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams,
+                                               f.n_views, op, zero_grads, rec, rect, rg, f.vis_mask, f.n_inst, flags);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t project_bwd(const gs_params& p, const gs_frame& f, const gs_opts& o, const gs_params& gr, hipStream_t st) {
+  const int threads = 256;
+  const int blocks = (int)((p.n + threads - 1) / threads);
+  const DevOpts op = gsk::dev_opts(o);
+  const auto* rg = reinterpret_cast<const float4*>(f.rgrad);
+#define GS_PB(D)                                                                                              \
+  k_project_bwd<D><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams, op, \
+                                               rg, f.vis_mask, gr.means, gr.log_scales, gr.quats, gr.opacity,    \
+                                               gr.sh)
+  switch (p.sh_degree) {
+    case 0: GS_PB(0); break;
+    case 1: GS_PB(1); break;
+    case 2: GS_PB(2); break;
+    default: GS_PB(3); break;
+  }
+#undef GS_PB
+  return hipGetLastError();
+}
+
+}  // namespace gs_launch

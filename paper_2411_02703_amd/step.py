@@ -1,0 +1,202 @@
+"""One optimisation iteration of LVI-GS mapping over a set of views (keyframes x pyramid levels).
+
+Section III-D renders every pyramid level of a keyframe and compares it with the down-sampled targets;
+Section III-E sums an L1 colour and an L1 LiDAR-depth loss and optimises the Gaussians.  An iteration
+here is: every view forward and backward with that loss, then one Adam step over all parameters.
+
+PlainStep  : the per-view launch sequence (project, bin with a host-synchronised instance count, render,
+             backward with the loss against the view's targets), then Adam.
+BatchedStep: all views in one frame - one projection launch that reads every Gaussian once, one binning
+             over global (view, tile) keys sized by a capacity (no host synchronisation), one fused
+             forward + loss + backward compositing launch over every tile of every view, the projection
+             backward and Adam - captured once as a HIP graph and replayed.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+PARAM_KEYS = ("means", "log_scales", "quats", "opacity", "sh")
+
+# Learning rates per group (means, log-scales, rotations, opacity, SH degree 0, SH degree >= 1).  The
+# paper does not state them; these follow common 3DGS practice.
+DEFAULT_LR = (1.6e-4, 5e-3, 1e-3, 2.5e-2, 2.5e-3, 1.25e-4)
+
+
+class GaussianModel:
+    """Gaussian parameters on the device plus their gradients and Adam moments."""
+
+    def __init__(self, params: Dict[str, np.ndarray], sh_degree: int, device: str = "cuda",
+                 lr: Sequence[float] = DEFAULT_LR, betas=(0.9, 0.999), eps: float = 1e-15):
+        self.sh_degree = int(sh_degree)
+        self.p = {k: torch.as_tensor(np.ascontiguousarray(params[k]), dtype=torch.float32).to(device)
+                  for k in PARAM_KEYS}
+        self.g = {k: torch.zeros_like(v) for k, v in self.p.items()}
+        self.m = {k: torch.zeros_like(v) for k, v in self.p.items()}
+        self.v = {k: torch.zeros_like(v) for k, v in self.p.items()}
+        self.step_count = torch.zeros(1, dtype=torch.int64, device=device)
+        self.bias = torch.zeros(2, dtype=torch.float32, device=device)
+        self.ps = B.params_struct(self.p, self.sh_degree)
+        self.gs = B.params_struct(self.g, self.sh_degree)
+        self.ms = B.params_struct(self.m, self.sh_degree)
+        self.vs = B.params_struct(self.v, self.sh_degree)
+        self.adam = B.gs_adam()
+        for i in range(6):
+            self.adam.lr[i] = float(lr[i])
+        self.adam.beta1, self.adam.beta2, self.adam.eps = float(betas[0]), float(betas[1]), float(eps)
+        self.adam.step = self.step_count.data_ptr()
+        self.adam.bias = self.bias.data_ptr()
+
+    @property
+    def n(self) -> int:
+        return int(self.p["means"].shape[0])
+
+    def zero_grad(self) -> None:
+        for t in self.g.values():
+            t.zero_()
+
+    def adam_step(self, stream=None) -> None:
+        B.gs_adam_step(self.ps, self.gs, self.ms, self.vs, self.adam, stream)
+
+    def state(self) -> Dict[str, torch.Tensor]:
+        out = {}
+        for k in PARAM_KEYS:
+            out[k] = self.p[k].detach().cpu()
+            out["m_" + k] = self.m[k].detach().cpu()
+            out["v_" + k] = self.v[k].detach().cpu()
+        out["step"] = self.step_count.detach().cpu()
+        return out
+
+    def load_state(self, st: Dict[str, torch.Tensor]) -> None:
+        for k in PARAM_KEYS:
+            self.p[k].copy_(st[k])
+            self.m[k].copy_(st["m_" + k])
+            self.v[k].copy_(st["v_" + k])
+        self.step_count.copy_(st["step"])
+
+
+def _targets_for(cams, tgt_rgb: np.ndarray, tgt_depth: np.ndarray, device: str):
+    """Per-view target tensors cut from the concatenated arrays."""
+    out, off = [], 0
+    for c in cams:
+        P = c.width * c.height
+        out.append((torch.as_tensor(tgt_rgb[3 * off:3 * off + 3 * P]).to(device).contiguous(),
+                    torch.as_tensor(tgt_depth[off:off + P]).to(device).contiguous()))
+        off += P
+    return out
+
+
+class PlainStep:
+    """The per-view launch sequence of the library calls (one frame per view)."""
+
+    def __init__(self, model: GaussianModel, cams: Sequence, tgt_rgb: np.ndarray, tgt_depth: np.ndarray,
+                 lambda_d: float = 0.1, opts: Optional[B.gs_opts] = None, device: str = "cuda"):
+        self.model = model
+        self.cams = list(cams)
+        self.opts = opts if opts is not None else B.default_opts()
+        self.lambda_d = float(lambda_d)
+        self.frames = [B.Frame(model.n, [c], self.opts, None, device) for c in self.cams]
+        self.images = [f.empty_images(device) for f in self.frames]
+        self.targets = _targets_for(self.cams, tgt_rgb, tgt_depth, device)
+        self.device = device
+
+    def run(self) -> None:
+        m = self.model
+        m.zero_grad()
+        for v, fr in enumerate(self.frames):
+            while True:
+                B.gs_project(m.ps, fr, zero_grads=True)
+                n = B.gs_bin_tiles(fr, sync_count=True)
+                if n <= fr.capacity:
+                    break
+                fr = self.frames[v] = B.Frame(m.n, [self.cams[v]], self.opts, int(n * 1.25) + 1024, self.device)
+                self.images[v] = fr.empty_images(self.device)
+            rgb, depth, vis = self.images[v]
+            B.gs_render_fwd(fr, rgb, depth, vis)
+            tr, td = self.targets[v]
+            B.gs_render_bwd(m.ps, fr, (rgb, depth, vis), m.gs, tgt_rgb=tr, tgt_depth=td, lambda_d=self.lambda_d)
+        m.adam_step()
+
+    def loss(self) -> float:
+        """Sum of the per-view loss values of the last run (synchronises)."""
+        tot = 0.0
+        for fr in self.frames:
+            t = B.frame_tensor(fr, "loss", 1, torch.float32)
+            tot += float(t.item())
+        return tot
+
+
+class BatchedStep:
+    """All views in one frame, fused forward + loss + backward, captured as a HIP graph."""
+
+    def __init__(self, model: GaussianModel, cams: Sequence, tgt_rgb: np.ndarray, tgt_depth: np.ndarray,
+                 lambda_d: float = 0.1, opts: Optional[B.gs_opts] = None, device: str = "cuda",
+                 capacity: Optional[int] = None, headroom: float = 1.25):
+        self.model = model
+        self.cams = list(cams)
+        self.opts = opts if opts is not None else B.default_opts()
+        self.lambda_d = float(lambda_d)
+        self.device = device
+        self.headroom = headroom
+        self.tgt_rgb = torch.as_tensor(tgt_rgb).to(device).contiguous()
+        self.tgt_depth = torch.as_tensor(tgt_depth).to(device).contiguous()
+        if capacity is None:
+            capacity = self._measure_capacity()
+        self.frame = B.Frame(model.n, self.cams, self.opts, capacity, device)
+        self.graph: Optional[torch.cuda.CUDAGraph] = None
+
+    def _measure_capacity(self) -> int:
+        probe = B.Frame(self.model.n, self.cams, self.opts, max(1 << 20, 8 * self.model.n), self.device)
+        B.gs_project(self.model.ps, probe, zero_grads=False)
+        n = B.gs_bin_tiles(probe, sync_count=True)
+        del probe
+        return int(n * self.headroom) + 4096
+
+    def _body(self, stream=None) -> None:
+        m = self.model
+        for t in m.g.values():
+            t.zero_()
+        B.gs_project(m.ps, self.frame, zero_grads=True, stream=stream)
+        B.gs_bin_tiles(self.frame, sync_count=False, stream=stream)
+        B.gs_render_bwd(m.ps, self.frame, None, m.gs, tgt_rgb=self.tgt_rgb, tgt_depth=self.tgt_depth,
+                        lambda_d=self.lambda_d, stream=stream)
+        m.adam_step(stream)
+
+    def run_eager(self) -> None:
+        self._body()
+
+    def capture(self) -> None:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self._body(s)  # warm-up on the side stream (not captured)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self._body()
+        self.graph = g
+
+    def run(self) -> None:
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()
+
+    def flags(self) -> int:
+        _, fl = B.gs_read_counters(self.frame)
+        return fl
+
+    def overflowed(self) -> bool:
+        return bool(self.flags() & B.GS_FLAG_INSTANCE_OVERFLOW)
+
+    def loss(self) -> float:
+        return float(B.frame_tensor(self.frame, "loss", 1, torch.float32).item())
+
+    def n_instances(self) -> int:
+        n, _ = B.gs_read_counters(self.frame)
+        return n

@@ -1,0 +1,125 @@
+"""The C-ABI library loads, exports every declared symbol, and its host-only logic behaves (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2411_02703_amd import binding as B
+from paper_2411_02703_amd import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "libgs.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2411_02703_amd import build
+
+        build.build()
+    return B.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gs_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_hot_path_calls():
+    names = declared_functions()
+    for n in ("gs_project", "gs_bin_tiles", "gs_render_fwd", "gs_render_bwd", "gs_adam_step"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert sorted(B.EXPORTED) == declared_functions()
+
+
+def test_struct_layouts(lib):
+    assert ctypes.sizeof(B.gs_camera) == 128
+    assert ctypes.sizeof(B.gs_opts) == 56
+    assert ctypes.sizeof(B.gs_params) == 56
+    assert lib.gs_version() == 1
+
+
+def test_default_opts_and_status_strings(lib):
+    o = B.default_opts()
+    assert (o.tile_w, o.tile_h) == (16, 16)
+    assert o.near_z == np.float32(0.2) and o.guard == np.float32(1.3) and o.lowpass == np.float32(0.3)
+    assert o.alpha_min == np.float32(1 / 255) and o.alpha_max == np.float32(0.99) and o.t_min == np.float32(1e-4)
+    assert lib.gs_status_string(-1) == b"invalid argument"
+
+
+def test_plan_cameras_offsets_and_guard(lib):
+    sc = scenes.random_scene(1, 10, 40, 30, views=3)
+    arr = B.make_cameras(sc.cams)
+    o = B.default_opts()
+    assert lib.gs_plan_cameras(arr, 3, ctypes.byref(o)) == 0
+    toff = poff = 0
+    for c, cam in zip(arr, sc.cams):
+        assert c.tiles_x == -(-cam.width // 16) and c.tiles_y == -(-cam.height // 16)
+        assert c.tile_offset == toff and c.pixel_offset == poff
+        toff += c.tiles_x * c.tiles_y
+        poff += cam.width * cam.height
+        gm = (np.float32(1.3) - np.float32(1)) * np.float32(0.5)
+        assert c.guard_lo_x == -(gm * np.float32(cam.width))
+        assert c.guard_hi_x == np.float32(cam.width) + gm * np.float32(cam.width)
+    bad = B.make_cameras(sc.cams)
+    bad[1].fx = 0.0
+    assert lib.gs_plan_cameras(bad, 3, ctypes.byref(o)) == -1
+    assert b"intrinsics" in lib.gs_last_error()
+    o2 = B.default_opts(tile_w=12)
+    assert lib.gs_plan_cameras(arr, 3, ctypes.byref(o2)) == -1
+
+
+def test_frame_layout_on_host(lib):
+    sc = scenes.random_scene(2, 10, 50, 40, views=2)
+    arr = B.make_cameras(sc.cams)
+    o = B.default_opts()
+    lib.gs_plan_cameras(arr, 2, ctypes.byref(o))
+    n, cap = 1000, 5000
+    nbytes = lib.gs_frame_bytes(n, arr, 2, ctypes.byref(o), cap)
+    assert nbytes >= 2 * n * (48 + 8 + 48) + 2 * cap * 12
+    f = B.gs_frame()
+    base = 1 << 20  # carving is pure host arithmetic: any 256-aligned address works
+    assert lib.gs_frame_init(ctypes.byref(f), base, nbytes, n, arr, base, 2, ctypes.byref(o), cap) == 0
+    ptrs = sorted([f.rec, f.rect, f.rgrad, f.vis_mask, f.n_inst, f.inst_off, f.keys[0], f.keys[1], f.vals[0],
+                   f.vals[1], f.tile_range, f.counters, f.loss, f.scratch])
+    assert all(p % 256 == 0 for p in ptrs) and ptrs[0] == base and ptrs[-1] < base + nbytes
+    total_tiles = sum(c.tiles_x * c.tiles_y for c in arr)
+    assert f.n_tiles == total_tiles and f.key_bits == 32 + max(1, int(np.ceil(np.log2(total_tiles))))
+    assert f.sort_passes == -(-f.key_bits // 8)
+    assert lib.gs_frame_init(ctypes.byref(f), base, nbytes - 1, n, arr, base, 2, ctypes.byref(o), cap) == -3
+    assert lib.gs_frame_init(ctypes.byref(f), base + 8, nbytes, n, arr, base, 2, ctypes.byref(o), cap) == -1
+
+
+def test_argument_errors_return_before_any_launch(lib):
+    o = B.default_opts()
+    f = B.gs_frame()
+    p = B.gs_params()
+    assert lib.gs_project(ctypes.byref(p), ctypes.byref(f), ctypes.byref(o), 1, None) == -1
+    assert lib.gs_bin_tiles(ctypes.byref(f), ctypes.byref(o), 1, None, None) == -1
+    assert lib.gs_render_fwd(ctypes.byref(f), ctypes.byref(o), None, None) == -1
+    assert lib.gs_adam_step(ctypes.byref(p), ctypes.byref(p), ctypes.byref(p), ctypes.byref(p), None, None) == -1
+    assert lib.gs_sort_pairs(None, None, None, None, 10, 40, None, None) == -1
+    p.means = p.log_scales = p.quats = p.opacity = p.sh = 4096
+    p.n = 10
+    p.sh_degree = 4
+    assert lib.gs_project(ctypes.byref(p), ctypes.byref(f), ctypes.byref(o), 1, None) == -1
+    assert b"sh_degree" in lib.gs_last_error()
+
+
+def test_oracle_defaults_match_library_defaults(lib):
+    import oracle
+
+    o = B.default_opts()
+    d = oracle.DEFAULT_OPTS
+    for k in ("near", "guard", "lowpass", "alpha_min", "alpha_max", "t_min"):
+        lib_v = getattr(o, "near_z" if k == "near" else k)
+        assert np.float32(d[k]) == np.float32(lib_v), k
+    assert (d["tile_w"], d["tile_h"]) == (o.tile_w, o.tile_h)

@@ -1,0 +1,372 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Bars: integer work (sort, binning, tile ranges) bit-exact; the camera-space depth and pixel mean
+bit-exact (both follow the FP32 fma specification); FP32 forward images within 1e-5 relative (+1e-7
+absolute) of the FP32 oracle; gradients within 1e-3 of the FP64 oracle relative to |ref| plus the
+RMS of the parameter group.  Decisions that FP rounding may flip (a pair within 1e-5 of the 1/255 skip,
+the 0.99 clamp or the 1e-4 stop, a loss sign at |C - I| < 1e-5, a cull or colour clamp near its threshold)
+are excused where the oracle flags them, counted, and bounded.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2411_02703_amd import binding as B
+from paper_2411_02703_amd import scenes
+from paper_2411_02703_amd.step import BatchedStep, GaussianModel, PlainStep
+
+pytestmark = pytest.mark.gpu
+
+FWD_RTOL, FWD_ATOL = 1e-5, 1e-7
+GRAD_TOL = 1e-3
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def run_gpu(sc, tile=(16, 16), g_images=None, targets=True, fused=False, capacity=None, zero=True):
+    """Project, bin, render and (optionally) backpropagate one scene; returns numpy results."""
+    torch.cuda.synchronize()
+    model = GaussianModel(sc.params(), sc.sh_degree)
+    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1])
+    fr = B.Frame(model.n, sc.cams, opts, capacity)
+    B.gs_project(model.ps, fr, zero_grads=zero)
+    n_inst = B.gs_bin_tiles(fr, sync_count=True)
+    if n_inst > fr.capacity:
+        fr = B.Frame(model.n, sc.cams, opts, n_inst + 1024)
+        B.gs_project(model.ps, fr, zero_grads=zero)
+        n_inst = B.gs_bin_tiles(fr, sync_count=True)
+    assert n_inst <= fr.capacity
+    rgb, depth, vis = fr.empty_images()
+    B.gs_render_fwd(fr, rgb, depth, vis)
+    out = dict(n_inst=n_inst, frame=fr, model=model, rgb=rgb.cpu().numpy(), depth=depth.cpu().numpy(),
+               vis=vis.cpu().numpy())
+    if g_images is not None or targets:
+        if g_images is not None:
+            gr, gd, gv = (torch.as_tensor(a).cuda() for a in g_images)
+            B.gs_render_bwd(model.ps, fr, (rgb, depth, vis), model.gs, g_rgb=gr, g_depth=gd, g_vis=gv)
+        else:
+            tr = torch.as_tensor(sc.tgt_rgb).cuda()
+            td = torch.as_tensor(sc.tgt_depth).cuda()
+            B.gs_render_bwd(model.ps, fr, None if fused else (rgb, depth, vis), model.gs, tgt_rgb=tr, tgt_depth=td)
+            out["loss"] = float(B.frame_tensor(fr, "loss", 1, torch.float32).item())
+        out["grads"] = {k: v.cpu().numpy() for k, v in model.g.items()}
+    torch.cuda.synchronize()
+    return out
+
+
+def gpu_records(fr, n, V):
+    R = V * n
+    rec = B.frame_tensor(fr, "rec", R * 12, torch.float32).view(R, 12).cpu().numpy()
+    rect = B.frame_tensor(fr, "rect", R * 4, torch.int16).view(R, 4).cpu().numpy().astype(np.int32)
+    mask = B.frame_tensor(fr, "vis_mask", n, torch.int64).cpu().numpy().view(np.uint64)
+    vis = np.zeros(R, bool)
+    for v in range(V):
+        vis[v * n:(v + 1) * n] = ((mask >> np.uint64(v)) & np.uint64(1)) == 1
+    return rec, rect, vis
+
+
+def check_images(gpu, ref, near, what=""):
+    ok = np.ones_like(near, bool) if near is None else ~near.astype(bool)
+    P = ok.size
+    for key, rep in (("rgb", 3), ("depth", 1), ("vis", 1)):
+        g, r = gpu[key], ref[key]
+        err = np.abs(g - r)
+        tol = FWD_RTOL * np.abs(r) + FWD_ATOL
+        bad = err > tol
+        if rep == 3:
+            # planar per view: excuse a pixel in every channel
+            bad_px = np.zeros(P, bool)
+            off = 0
+            for c in gpu["cams"]:
+                Pv = c.width * c.height
+                b = bad[3 * off:3 * off + 3 * Pv].reshape(3, Pv).any(axis=0)
+                bad_px[off:off + Pv] |= b
+                off += Pv
+            bad = bad_px
+        bad &= ok
+        assert not bad.any(), f"{what} {key}: {bad.sum()} pixels off, max err {err.max():.3e}"
+
+
+def check_grads(gpu, ref, excused, what=""):
+    n_exc = int(excused.sum())
+    assert n_exc <= max(5, 1e-2 * excused.size), (what, n_exc)
+    for k in ref:
+        r = np.asarray(ref[k]).reshape(excused.size, -1)
+        g = np.asarray(gpu[k], np.float64).reshape(excused.size, -1)
+        keep = ~excused
+        rms = math.sqrt(float((r[keep] ** 2).mean())) if keep.any() else 0.0
+        err = np.abs(g[keep] - r[keep])
+        tol = GRAD_TOL * (np.abs(r[keep]) + rms)
+        bad = err > tol
+        assert not bad.any(), (f"{what} {k}: {bad.sum()} / {bad.size} off; worst err {err.max():.3e}, "
+                               f"rms {rms:.3e}")
+
+
+# ----------------------------------------------------------------------------- sort (bit-exact)
+@pytest.mark.parametrize("n,bits", [(1, 40), (4095, 38), (4096, 40), (4097, 45), (100_003, 48), (1_300_001, 49)])
+def test_radix_sort_matches_stable_argsort(gpu_lib, n, bits):
+    rng = np.random.default_rng(n)
+    # few distinct high parts and many ties, like (tile, depth) keys
+    hi = rng.integers(0, max(1, 1 << (bits - 32)), n, dtype=np.uint64)
+    lo = rng.integers(0, 1 << 12, n, dtype=np.uint64) << np.uint64(18)
+    keys = (hi << np.uint64(32)) | lo
+    vals = np.arange(n, dtype=np.int32)
+    kt = torch.as_tensor(keys.view(np.int64)).cuda()
+    vt = torch.as_tensor(vals).cuda()
+    log("sort", n, bits)
+    B.gs_sort_pairs(kt, vt, bits)
+    torch.cuda.synchronize()
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(kt.cpu().numpy().view(np.uint64), keys[order])
+    assert np.array_equal(vt.cpu().numpy(), vals[order])
+
+
+# ----------------------------------------------------------------------------- projection
+@pytest.mark.parametrize("deg", [0, 1, 2, 3])
+def test_projection_matches_oracle(gpu_lib, deg):
+    sc = scenes.random_scene(100 + deg, 3000, 96, 72, sh_degree=deg, views=3, log_scale_mu=-2.5)
+    log("projection deg", deg)
+    out = run_gpu(sc, targets=False)
+    V, n = len(sc.cams), sc.n
+    rec, rect, vis = gpu_records(out["frame"], n, V)
+    ref = oracle.project(32, sc.params(), deg, sc.cams)
+    rvis = ref["visible"].astype(bool)
+    marginal = (ref["near_margin"] <= 1e-5) | (ref["rect_margin"] <= 1e-3)
+    assert np.array_equal(vis[~marginal], rvis[~marginal])
+    both = vis & rvis
+    assert both.sum() > 1000
+    # bit-exact pixel mean and depth (FP32 fma specification)
+    assert np.array_equal(rec[both, 0], ref["mean2d"][both, 0].astype(np.float32))
+    assert np.array_equal(rec[both, 1], ref["mean2d"][both, 1].astype(np.float32))
+    assert np.array_equal(rec[both, 2].view(np.uint32), ref["zbits"][both])
+    np.testing.assert_allclose(rec[both, 3], ref["opacity"][both], rtol=1e-6)
+    con = ref["conic"][both]
+    scale = np.sqrt(np.abs(con[:, 0] * con[:, 2]))[:, None]
+    assert np.all(np.abs(rec[both][:, 4:7] - con) <= 1e-5 * (np.abs(con) + scale))
+    rgb = np.stack([rec[both, 7], rec[both, 8], rec[both, 9]], 1)
+    np.testing.assert_allclose(rgb, ref["rgb"][both], rtol=1e-5, atol=1e-6)
+    ok = both & ~marginal
+    tr = ref["tilerect"][ok]
+    assert np.array_equal(rect[ok], tr[:, [0, 1, 2, 3]])
+
+
+# ----------------------------------------------------------------------------- binning
+def test_binning_matches_oracle(gpu_lib):
+    sc = scenes.random_scene(200, 4000, 130, 90, sh_degree=1, views=3, log_scale_mu=-2.0)
+    log("binning")
+    out = run_gpu(sc, targets=False)
+    fr, V, n = out["frame"], len(sc.cams), sc.n
+    I = out["n_inst"]
+    keys, vals = B.sorted_pairs(fr, I)
+    keys = keys.cpu().numpy().view(np.uint64)
+    vals = vals.cpu().numpy()
+    rng_ = B.frame_tensor(fr, "tile_range", 2 * fr.f.n_tiles, torch.int32).view(-1, 2).cpu().numpy()
+    ref = oracle.project(32, sc.params(), 1, sc.cams)
+    rk, rv, lo, hi = oracle.bin_records(ref["tilerect"], ref["zbits"], ref["visible"], n, sc.cams)
+    marginal = set(np.nonzero((ref["rect_margin"] <= 1e-3) | (ref["near_margin"] <= 1e-5))[0].tolist())
+    log("instances gpu", I, "oracle", len(rk))
+    n_diff = 0
+    for t in range(fr.f.n_tiles):
+        g_list = vals[rng_[t, 0]:rng_[t, 1]]
+        r_list = rv[lo[t]:hi[t]]
+        if not np.array_equal(g_list, r_list):
+            gk = [x for x in g_list if x not in marginal]
+            rk_ = [x for x in r_list if x not in marginal]
+            assert gk == rk_, f"tile {t}"
+            n_diff += 1
+        if rng_[t, 1] > rng_[t, 0]:
+            assert np.all((keys[rng_[t, 0]:rng_[t, 1]] >> np.uint64(32)) == t)
+    log("tiles differing only in marginal records:", n_diff, "marginal records:", len(marginal))
+    if not marginal:
+        assert np.array_equal(vals, rv) and np.array_equal(keys, rk)
+
+
+# ----------------------------------------------------------------------------- forward
+@pytest.mark.parametrize("deg,views,W,H", [(0, 1, 128, 96), (3, 3, 100, 77), (2, 2, 33, 17)])
+def test_forward_matches_oracle(gpu_lib, deg, views, W, H):
+    sc = scenes.random_scene(300 + deg, 2500, W, H, sh_degree=deg, views=views, log_scale_mu=-2.4)
+    log("forward", deg, views, W, H)
+    out = run_gpu(sc, targets=False)
+    out["cams"] = sc.cams
+    ref = oracle.forward(32, sc.params(), deg, sc.cams)
+    log("near-threshold pixels:", int(ref["near"].sum()))
+    check_images(out, ref, ref["near"], "fwd")
+
+
+def test_forward_config1_matches_oracle(gpu_lib):
+    sc = scenes.config(1)
+    out = run_gpu(sc, targets=False)
+    out["cams"] = sc.cams
+    ref = oracle.forward(32, sc.params(), 0, sc.cams)
+    check_images(out, ref, ref["near"], "cfg1")
+
+
+def test_forward_is_tile_size_invariant_and_deterministic(gpu_lib):
+    sc = scenes.random_scene(400, 3000, 150, 100, sh_degree=1, views=2, log_scale_mu=-2.2)
+    base = run_gpu(sc, targets=False)
+    again = run_gpu(sc, targets=False)
+    for k in ("rgb", "depth", "vis"):
+        assert np.array_equal(base[k], again[k]), k
+    for tile in [(8, 8), (16, 8), (32, 8), (32, 16)]:
+        log("tile", tile)
+        o = run_gpu(sc, tile=tile, targets=False)
+        for k in ("rgb", "depth", "vis"):
+            assert np.array_equal(base[k], o[k]), (tile, k)
+
+
+# ----------------------------------------------------------------------------- backward
+@pytest.mark.parametrize("deg", [0, 1, 3])
+def test_backward_upstream_gradients_match_fp64_oracle(gpu_lib, deg):
+    sc = scenes.random_scene(500 + deg, 1500, 80, 60, sh_degree=deg, views=2, log_scale_mu=-2.3)
+    P = sc.total_pixels
+    rng = np.random.default_rng(deg)
+    g = (rng.standard_normal(3 * P).astype(np.float32), rng.standard_normal(P).astype(np.float32),
+         rng.standard_normal(P).astype(np.float32))
+    log("backward g-mode deg", deg)
+    out = run_gpu(sc, g_images=g, targets=False)
+    L, ref, exc, nn, _ = oracle.backward(64, sc.params(), deg, sc.cams, g_rgb=g[0], g_depth=g[1], g_vis=g[2])
+    log("excused Gaussians:", int(exc.sum()), "near pixels:", nn)
+    check_grads(out["grads"], ref, exc, f"g-mode deg {deg}")
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_backward_loss_mode_matches_fp64_oracle(gpu_lib, fused):
+    sc = scenes.random_scene(600, 1500, 90, 70, sh_degree=2, views=3, log_scale_mu=-2.3, depth_fraction=0.3)
+    log("backward loss mode fused", fused)
+    out = run_gpu(sc, targets=True, fused=fused)
+    L, ref, exc, nn, _ = oracle.backward(64, sc.params(), 2, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
+    np.testing.assert_allclose(out["loss"], L, rtol=1e-5)
+    check_grads(out["grads"], ref, exc, f"loss mode fused={fused}")
+
+
+def test_backward_config1(gpu_lib):
+    sc = scenes.config(1)
+    out = run_gpu(sc, targets=True, fused=True)
+    L, ref, exc, nn, _ = oracle.backward(64, sc.params(), 0, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
+    np.testing.assert_allclose(out["loss"], L, rtol=1e-5)
+    check_grads(out["grads"], ref, exc, "cfg1")
+
+
+# ----------------------------------------------------------------------------- Adam
+def test_adam_matches_oracle(gpu_lib):
+    sc = scenes.random_scene(700, 1000, 64, 48, sh_degree=3)
+    model = GaussianModel(sc.params(), 3)
+    rng = np.random.default_rng(7)
+    ref = {k: (v.astype(np.float64).copy(), np.zeros(v.size), np.zeros(v.size)) for k, v in sc.params().items()}
+    lrs = dict(means=model.adam.lr[0], log_scales=model.adam.lr[1], quats=model.adam.lr[2], opacity=model.adam.lr[3])
+    for step in (1, 2, 3):
+        for k, t in model.g.items():
+            gk = rng.standard_normal(t.shape).astype(np.float32)
+            gk.reshape(-1)[::5] = 0.0
+            t.copy_(torch.as_tensor(gk))
+            p, m, v = ref[k]
+            if k == "sh":
+                p2, m2, v2 = p.reshape(-1).copy(), m.copy(), v.copy()
+                K3 = 48
+                idx = np.arange(p2.size)
+                dc = (idx % K3) < 3
+                for mask, lr in ((dc, model.adam.lr[4]), (~dc, model.adam.lr[5])):
+                    pp, mm, vv = oracle.adam(p2[mask], gk.reshape(-1)[mask], m[mask], v[mask], lr, eps=1e-15,
+                                             step=step)
+                    p2[mask], m2[mask], v2[mask] = pp, mm, vv
+                ref[k] = (p2.reshape(p.shape), m2, v2)
+            else:
+                pp, mm, vv = oracle.adam(p.reshape(-1), gk.reshape(-1), m, v, lrs[k], eps=1e-15, step=step)
+                ref[k] = (pp.reshape(p.shape), mm, vv)
+        model.adam_step()
+        torch.cuda.synchronize()
+        for k in model.p:
+            got = model.p[k].cpu().numpy().astype(np.float64)
+            np.testing.assert_allclose(got, ref[k][0], rtol=2e-6, atol=1e-6, err_msg=f"{k} step {step}")
+    assert int(model.step_count.item()) == 3
+
+
+# ----------------------------------------------------------------------------- batched step
+def test_batched_graph_step_matches_plain_step(gpu_lib):
+    sc = scenes.random_scene(800, 3000, 120, 90, sh_degree=1, views=4, log_scale_mu=-2.3, depth_fraction=0.2)
+    log("batched vs plain")
+    ma = GaussianModel(sc.params(), 1)
+    mb = GaussianModel(sc.params(), 1)
+    plain = PlainStep(ma, sc.cams, sc.tgt_rgb, sc.tgt_depth)
+    plain.run()
+    bat = BatchedStep(mb, sc.cams, sc.tgt_rgb, sc.tgt_depth)
+    bat.run_eager()
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(bat.loss(), plain.loss(), rtol=1e-5)
+    for k in ma.g:
+        a, b = ma.g[k].cpu().numpy(), mb.g[k].cpu().numpy()
+        rms = np.sqrt((a.astype(np.float64) ** 2).mean()) + 1e-30
+        assert np.all(np.abs(a - b) <= 1e-5 * (np.abs(a) + rms)), k
+    for k in ma.p:
+        np.testing.assert_allclose(mb.p[k].cpu().numpy(), ma.p[k].cpu().numpy(), rtol=1e-5, atol=1e-7)
+
+
+def test_graph_replays_match_eager(gpu_lib):
+    sc = scenes.random_scene(900, 2000, 96, 80, sh_degree=2, views=3, log_scale_mu=-2.3, depth_fraction=0.2)
+    me = GaussianModel(sc.params(), 2)
+    mg = GaussianModel(sc.params(), 2)
+    eager = BatchedStep(me, sc.cams, sc.tgt_rgb, sc.tgt_depth)
+    graph = BatchedStep(mg, sc.cams, sc.tgt_rgb, sc.tgt_depth)
+    graph.capture()  # capture warms up with one eager step
+    eager.run_eager()
+    for it in range(4):
+        eager.run_eager()
+        graph.run()
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(graph.loss(), eager.loss(), rtol=1e-5)
+        for k in me.p:
+            np.testing.assert_allclose(mg.p[k].cpu().numpy(), me.p[k].cpu().numpy(), rtol=1e-5, atol=1e-6,
+                                       err_msg=f"replay {it} {k}")
+        _ = torch.ones(10, device="cuda").sum().item()  # eager work between replays
+    assert not graph.overflowed()
+
+
+# ----------------------------------------------------------------------------- edge cases
+def test_everything_culled(gpu_lib):
+    sc = scenes.random_scene(1000, 200, 40, 30)
+    sc.means[:, 2] = -5.0  # behind the camera
+    out = run_gpu(sc, targets=True)
+    assert out["n_inst"] == 0
+    assert np.all(out["rgb"] == 0) and np.all(out["depth"] == 0) and np.all(out["vis"] == 0)
+    for g in out["grads"].values():
+        assert np.all(g == 0)
+
+
+def test_single_gaussian_and_one_pixel_views(gpu_lib):
+    sc = scenes.random_scene(1100, 1, 1, 1)
+    sc.means[0] = [0.0, 0.0, 3.0]
+    sc.log_scales[0] = math.log(0.2)
+    sc.opacity[0] = 3.0
+    out = run_gpu(sc, targets=True)
+    out["cams"] = sc.cams
+    ref = oracle.forward(32, sc.params(), 0, sc.cams)
+    check_images(out, ref, ref["near"], "1px")
+    assert out["vis"][0] > 0.5
+
+
+def test_nonfinite_parameters_are_flagged_and_culled(gpu_lib):
+    sc = scenes.random_scene(1200, 500, 64, 48, log_scale_mu=-2.3)
+    sc.means[7, 0] = np.nan
+    out = run_gpu(sc, targets=False)
+    n, flags = B.gs_read_counters(out["frame"])
+    assert flags & B.GS_FLAG_NONFINITE
+    assert np.isfinite(out["rgb"]).all()
+
+
+def test_capacity_overflow_is_flagged_without_fault(gpu_lib):
+    sc = scenes.random_scene(1300, 2000, 96, 64, log_scale_mu=-2.0, depth_fraction=0.3)
+    model = GaussianModel(sc.params(), 0)
+    step = BatchedStep(model, sc.cams, sc.tgt_rgb, sc.tgt_depth, capacity=100)
+    step.run_eager()
+    torch.cuda.synchronize()
+    assert step.overflowed()
+    n = step.n_instances()
+    assert n > 100
+    ok = BatchedStep(GaussianModel(sc.params(), 0), sc.cams, sc.tgt_rgb, sc.tgt_depth)
+    ok.run_eager()
+    assert not ok.overflowed()

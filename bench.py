@@ -1,0 +1,199 @@
+"""Benchmark: forward + backward + Adam iterations per second of the splatting hot path on one MI355X.
+
+Workload (default): 1M Gaussians (SH degree 3) initialised from a synthetic LiDAR scan, 8 keyframes of
+mixed resolution (640x512 .. 1280x1024) each rendered as a 3-level image pyramid = 24 views, L1 colour +
+0.1 L1 LiDAR-depth loss.  One step = every view forward and backward, then Adam over all parameters.
+`value` is the batched step (one HIP-graph replay); the plain per-view launch sequence is timed beside it,
+as is the 1M-Gaussian single-keyframe 1280x1024 pyramid.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd splat iters/sec at 1M Gaussians, 1280×1024; batched vs plain"
+
+# Algorithmic VALU lane-operations per (pixel, record) pair of the compositing, counted from the per-pair
+# definition with a multiply-add as one operation and exp / reciprocal (quarter-rate) as four.
+OPS_EVAL = 19          # alpha of one pair: offsets, conic quadratic form, exp, opacity, clamp, skip test
+OPS_CONTRIB_FWD = 9    # transmittance update, stop test, colour / depth / visibility accumulation
+OPS_CONTRIB_BWD = 37   # weight, upstream dot product, dL/dalpha, 10 per-record partial derivatives
+# MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz, one VALU lane-operation per lane per cycle.
+ALU_PEAK = 256 * 4 * 16 * 2.4e9
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed(fn, steps, stream):
+    import torch
+
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    end.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def measure(sc, steps, warmup, plain_steps, do_plain, tile=None):
+    import torch
+
+    from paper_2411_02703_amd import autotune
+    from paper_2411_02703_amd import binding as B
+    from paper_2411_02703_amd.step import BatchedStep, GaussianModel, PlainStep
+
+    stream = torch.cuda.current_stream()
+    if tile is None:
+        tile, _ = autotune.tune_batched(
+            lambda o: BatchedStep(GaussianModel(sc.params(), sc.sh_degree), sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=o),
+            sc.n, sc.cams, sc.sh_degree, log=log)
+    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], waves_per_tile=tile[2])
+    log(f"  configuration: {tile[0]}x{tile[1]} tiles, {tile[2]} waves per tile")
+    model = GaussianModel(sc.params(), sc.sh_degree)
+    t0 = time.time()
+    bat = BatchedStep(model, sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=opts)
+    bat.capture()
+    log(f"  batched: capacity {bat.frame.capacity}, capture {time.time() - t0:.1f}s")
+    for _ in range(warmup):
+        bat.run()
+    ms = timed(bat.run, steps, stream)
+    if bat.overflowed():
+        raise RuntimeError("instance capacity overflow during timing")
+    res = dict(ms=ms, n_instances=bat.n_instances(), loss=bat.loss(), frame=bat.frame, model=model, step=bat,
+               tile=tile)
+    log(f"  batched: {ms:.3f} ms/step ({1000 / ms:.2f} it/s), {res['n_instances']} instances")
+    if do_plain:
+        pm = GaussianModel(sc.params(), sc.sh_degree)
+        plain = PlainStep(pm, sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=opts)
+        plain.run()
+        pms = timed(plain.run, plain_steps, stream)
+        res["plain_ms"] = pms
+        log(f"  plain:   {pms:.3f} ms/step ({1000 / pms:.2f} it/s)")
+    return res
+
+
+def dominant_kernel(res, steps):
+    """Average duration of the fused forward + loss + backward compositing launch, timed with HIP events on
+    its stream, and its algorithmic work from the pair counts."""
+    import torch
+
+    from paper_2411_02703_amd import binding as B
+
+    fr = res["frame"]
+    st = res["step"]
+    ev, co = B.gs_count_pairs(fr)
+    ms = timed(lambda: B.gs_composite_bwd(fr, None, tgt_rgb=st.tgt_rgb, tgt_depth=st.tgt_depth), steps,
+               torch.cuda.current_stream())
+    ops = ev * 2 * OPS_EVAL + co * (OPS_CONTRIB_FWD + OPS_CONTRIB_BWD)
+    achieved = ops / (ms * 1e-3)
+    return dict(ms=ms, evaluated=ev, contributing=co, ops=ops, achieved=achieved)
+
+
+def cpu_baseline(sc, kf_views):
+    import numpy as np
+
+    import oracle
+
+    cams = [sc.cams[i] for i in kf_views]
+    offs = np.cumsum([0] + [c.width * c.height for c in sc.cams])
+    rgb = np.concatenate([sc.tgt_rgb[3 * offs[i]:3 * offs[i + 1]] for i in kf_views])
+    dep = np.concatenate([sc.tgt_depth[offs[i]:offs[i + 1]] for i in kf_views])
+    p_sample = sum(c.width * c.height for c in cams)
+    t0 = time.time()
+    oracle.backward(32, sc.params(), sc.sh_degree, cams, tgt_rgb=rgb, tgt_depth=dep)
+    dt = time.time() - t0
+    scale = sc.total_pixels / p_sample
+    return dict(value=1.0 / (dt * scale), unit="iters/s", cores=oracle.num_threads(), kind="oracle",
+                sample=(f"FP32 oracle forward + loss + backward of views {list(kf_views)} "
+                        f"({'+'.join(f'{c.width}x{c.height}' for c in cams)}) against all {sc.n} Gaussians: "
+                        f"{dt:.2f} s, scaled x{scale:.2f} by pixel count to the full step"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=5)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cfg3", action="store_true")
+    ap.add_argument("--n", type=int, default=None, help="override the Gaussian count (smaller trial runs)")
+    ap.add_argument("--tile", type=str, default=None, help="tile_w,tile_h,waves (skips the autotuner)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md on sharding by view).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2411_02703_amd import binding as B
+    from paper_2411_02703_amd import scenes
+
+    B.load()
+    log(f"device: {torch.cuda.get_device_name(0)}; host threads {os.cpu_count()}")
+    t0 = time.time()
+    sc4 = scenes.config(4, n=args.n)
+    log(f"cfg4 scene: {sc4.n} Gaussians, {len(sc4.cams)} views, {sc4.total_pixels} px ({time.time() - t0:.1f}s)")
+    tile = tuple(int(x) for x in args.tile.split(",")) if args.tile else None
+    r4 = measure(sc4, args.steps, args.warmup, args.plain_steps, not args.no_plain, tile)
+    dk = dominant_kernel(r4, args.steps)
+    log(f"  fused compositing kernel: {dk['ms']:.3f} ms, {dk['evaluated']} evaluated / {dk['contributing']} "
+        f"contributing pairs, {dk['achieved'] / 1e12:.2f} T lane-ops/s")
+    out = {
+        "metric": METRIC,
+        "value": round(1000.0 / r4["ms"], 3),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r4["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": ("batched step: 1M Gaussians (SH degree 3) from a synthetic LiDAR scan, 8 keyframes "
+                                "640x512..1280x1024 x 3-level pyramid = 24 views, L1 RGB + 0.1 L1 depth, Adam; "
+                                "one HIP-graph replay per step"),
+                   "gaussians": sc4.n, "views": len(sc4.cams), "pixels": sc4.total_pixels,
+                   "instances": r4["n_instances"], "tile": list(r4["tile"][:2]), "waves_per_tile": r4["tile"][2]},
+    }
+    if "plain_ms" in r4:
+        out["plain"] = {"value": round(1000.0 / r4["plain_ms"], 3), "ms_per_step": round(r4["plain_ms"], 4),
+                        "steps": args.plain_steps}
+        out["batched_over_plain"] = round(r4["plain_ms"] / r4["ms"], 3)
+    out["roofline"] = {"bound": "alu", "achieved": round(dk["achieved"] / 1e12, 3), "peak": round(ALU_PEAK / 1e12, 3),
+                       "unit": "T lane-op/s", "frac": round(dk["achieved"] / ALU_PEAK, 4), "traffic": None,
+                       "kernel": (f"k_render_bwd<{r4['tile'][0]},{r4['tile'][1]},{r4['tile'][2]} waves,fused loss> "
+                                  "(forward sweep + loss + backward sweep)"),
+                       "kernel_ms": round(dk["ms"], 4), "pairs_evaluated": dk["evaluated"],
+                       "pairs_contributing": dk["contributing"]}
+    if not args.no_cfg3:
+        sc3 = scenes.config(3, n=args.n)
+        log(f"cfg3 scene: {len(sc3.cams)} views, {sc3.total_pixels} px")
+        r3 = measure(sc3, args.steps, args.warmup, args.plain_steps, not args.no_plain, tile)
+        out["single_keyframe_1280x1024_pyramid"] = {"batched": round(1000.0 / r3["ms"], 3)}
+        if "plain_ms" in r3:
+            out["single_keyframe_1280x1024_pyramid"]["plain"] = round(1000.0 / r3["plain_ms"], 3)
+    if not args.no_cpu:
+        big = max(range(0, len(sc4.cams), 3), key=lambda i: sc4.cams[i].width)
+        out["cpu_baseline"] = cpu_baseline(sc4, [big, big + 1, big + 2])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

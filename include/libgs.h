@@ -87,7 +87,9 @@ typedef struct gs_opts {
   float alpha_max;        /* 0.99 */
   float t_min;            /* 1e-4 */
   float bg[3];            /* background colour, 0 */
-  int32_t reserved[3];
+  int32_t waves_per_tile; /* wave64s per tile workgroup, each owning a sub-tile: 1, 2 or 4 (0 = 4 where the
+                             tile shape allows it, else 2, else 1); results are identical for every choice */
+  int32_t reserved[2];
 } gs_opts;
 
 /* Gaussian parameters, or gradients / Adam moments in the same layout.  Row-major float32:
@@ -120,7 +122,8 @@ typedef struct gs_frame {
   void* block;
   size_t bytes;
   /* carved device arrays (library layout; read-only for callers except where noted) */
-  float* rec;           /* [n_views*n][12]: {mu_x, mu_y, z, o}, {conic a, b, c, red}, {green, blue, -, -} */
+  float* rec;           /* [n_views*n][12]: {mu_x, mu_y, z, o}, {conic a, b, c, red},
+                           {green, blue, px0 | px1 << 16, py0 | py1 << 16} (pixel rectangle as int16 pairs) */
   int16_t* rect;        /* [n_views*n][4]: tile rectangle tx0, tx1, ty0, ty1 (valid when visible) */
   float* rgrad;         /* [n_views*n][12]: dL/d{mu_x, mu_y, a, b, c, o, red, green, blue, z} */
   uint64_t* vis_mask;   /* [n]: bit v set if Gaussian g is visible in view v */
@@ -203,12 +206,29 @@ int gs_render_fwd(const gs_frame* frame, const gs_opts* opts, const gs_images* o
 int gs_render_bwd(const gs_params* params, const gs_frame* frame, const gs_opts* opts, const gs_images* fwd,
                   const gs_loss* loss, const gs_params* grads, void* stream);
 
+/* The two halves of gs_render_bwd, for callers that schedule them separately.
+ * gs_composite_bwd: compositing backward only (the same eqs.), accumulating dL/d{mean_I, conic, opacity,
+ * colour, depth} of every record into frame->rgrad (zeroed by gs_project with zero_grads != 0); in loss
+ * mode it also writes frame->loss.
+ * gs_project_bwd: projection backward only (eqs. Sigma and muI): frame->rgrad -> grads (+=), one thread
+ * per Gaussian summing its views, no atomics on parameters. */
+int gs_composite_bwd(const gs_frame* frame, const gs_opts* opts, const gs_images* fwd, const gs_loss* loss,
+                     void* stream);
+int gs_project_bwd(const gs_params* params, const gs_frame* frame, const gs_opts* opts, const gs_params* grads,
+                   void* stream);
+
 /* One Adam step over all parameters (m, v as moments; bias-corrected, eps added to the corrected
  * root), with per-group learning rates.  Dense: Gaussians with zero gradient still move. */
 int gs_adam_step(const gs_params* params, const gs_params* grads, const gs_params* m, const gs_params* v,
                  const gs_adam* adam, void* stream);
 
 /* ------------------------------------------------------------------ utilities */
+/* Work counts of the frame's forward compositing at its tile shape, ADDED to counts[0..1] (device, uint64):
+ * [0] pairs evaluated (each record of a pixel's tile list up to the record that stops the pixel),
+ * [1] pairs contributing (alpha >= alpha_min, before the stop).  Diagnostic: these counts define the
+ * algorithmic work of the compositing kernels. */
+int gs_count_pairs(const gs_frame* frame, const gs_opts* opts, uint64_t* counts, void* stream);
+
 /* Synchronises the stream and returns the instance count and flags of the frame (host outputs). */
 int gs_read_counters(const gs_frame* frame, int64_t* n_instances, int32_t* flags, void* stream);
 

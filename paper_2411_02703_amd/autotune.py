@@ -1,0 +1,85 @@
+"""Pick the tile shape and waves per tile of the batched step by measured replay time.
+
+Every candidate computes the same forward bit for bit (the per-pair arithmetic is fixed and records are
+culled only where they provably do not contribute) and the same gradients up to the order of the float
+atomic additions, so the choice changes speed only.  Results are cached in a JSON file keyed by the GPU
+architecture, the resolution class, the Gaussian-count band and the SH degree.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import binding as B
+
+CANDIDATES: List[Tuple[int, int, int]] = [(16, 16, 4), (16, 16, 2), (16, 16, 1), (32, 16, 4), (32, 8, 4),
+                                          (16, 8, 2), (8, 8, 1)]
+
+_CACHE = os.environ.get("GS_AUTOTUNE_CACHE",
+                        os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), ".scene_cache",
+                                     "autotune.json"))
+
+
+def cache_key(n: int, cams: Sequence, sh_degree: int) -> str:
+    arch = torch.cuda.get_device_properties(0).gcnArchName if torch.cuda.is_available() else "cpu"
+    px = sum(c.width * c.height for c in cams)
+    return f"{arch}|views{len(cams)}|px2^{round(math.log2(max(px, 1)))}|n2^{round(math.log2(max(n, 1)))}|deg{sh_degree}"
+
+
+def _load() -> Dict[str, list]:
+    try:
+        with open(_CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(d: Dict[str, list]) -> None:
+    try:
+        os.makedirs(os.path.dirname(_CACHE), exist_ok=True)
+        with open(_CACHE + ".tmp", "w") as f:
+            json.dump(d, f, indent=1)
+        os.replace(_CACHE + ".tmp", _CACHE)
+    except OSError:
+        pass
+
+
+def tune_batched(make_step, n: int, cams: Sequence, sh_degree: int, replays: int = 3,
+                 candidates: Sequence[Tuple[int, int, int]] = CANDIDATES, use_cache: bool = True, log=None):
+    """make_step(opts) -> a BatchedStep.  Returns (best (tile_w, tile_h, waves), {candidate: ms})."""
+    key = cache_key(n, cams, sh_degree)
+    cache = _load() if use_cache else {}
+    if key in cache:
+        tw, th, nw = cache[key][0]
+        return (tw, th, nw), {}
+    times = {}
+    for tw, th, nw in candidates:
+        opts = B.default_opts(tile_w=tw, tile_h=th, waves_per_tile=nw)
+        step = make_step(opts)
+        step.capture()
+        step.run()
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(replays):
+            step.run()
+        e.record()
+        e.synchronize()
+        ms = s.elapsed_time(e) / replays
+        if step.overflowed():
+            ms = float("inf")
+        times[(tw, th, nw)] = ms
+        if log:
+            log(f"  autotune {tw}x{th} waves {nw}: {ms:.3f} ms")
+        del step
+        torch.cuda.empty_cache()
+    best = min(times, key=times.get)
+    if use_cache:
+        cache[key] = [list(best), {f"{a}x{b}x{c}": v for (a, b, c), v in times.items()}]
+        _store(cache)
+    return best, times

@@ -34,7 +34,8 @@ class gs_camera(ctypes.Structure):
 
 class gs_opts(ctypes.Structure):
     _fields_ = [("tile_w", c_i32), ("tile_h", c_i32), ("near_z", c_f), ("guard", c_f), ("lowpass", c_f),
-                ("alpha_min", c_f), ("alpha_max", c_f), ("t_min", c_f), ("bg", c_f * 3), ("reserved", c_i32 * 3)]
+                ("alpha_min", c_f), ("alpha_max", c_f), ("t_min", c_f), ("bg", c_f * 3), ("waves_per_tile", c_i32),
+                ("reserved", c_i32 * 2)]
 
 
 class gs_params(ctypes.Structure):
@@ -71,8 +72,9 @@ GS_FLAG_INSTANCE_OVERFLOW = 1
 GS_FLAG_NONFINITE = 2
 
 EXPORTED = ["gs_default_opts", "gs_plan_cameras", "gs_frame_bytes", "gs_frame_init", "gs_project", "gs_bin_tiles",
-            "gs_render_fwd", "gs_render_bwd", "gs_adam_step", "gs_read_counters", "gs_sort_scratch_ints",
-            "gs_sort_pairs", "gs_status_string", "gs_last_error", "gs_version"]
+            "gs_render_fwd", "gs_render_bwd", "gs_composite_bwd", "gs_project_bwd", "gs_adam_step",
+            "gs_count_pairs", "gs_read_counters", "gs_sort_scratch_ints", "gs_sort_pairs", "gs_status_string",
+            "gs_last_error", "gs_version"]
 
 _lib: Optional[ctypes.CDLL] = None
 
@@ -97,7 +99,10 @@ def load() -> ctypes.CDLL:
     lib.gs_render_fwd.argtypes = [P(gs_frame), P(gs_opts), P(gs_images), c_vp]
     lib.gs_render_bwd.argtypes = [P(gs_params), P(gs_frame), P(gs_opts), P(gs_images), P(gs_loss), P(gs_params),
                                   c_vp]
+    lib.gs_composite_bwd.argtypes = [P(gs_frame), P(gs_opts), P(gs_images), P(gs_loss), c_vp]
+    lib.gs_project_bwd.argtypes = [P(gs_params), P(gs_frame), P(gs_opts), P(gs_params), c_vp]
     lib.gs_adam_step.argtypes = [P(gs_params), P(gs_params), P(gs_params), P(gs_params), P(gs_adam), c_vp]
+    lib.gs_count_pairs.argtypes = [P(gs_frame), P(gs_opts), c_vp, c_vp]
     lib.gs_read_counters.argtypes = [P(gs_frame), P(c_i64), P(c_i32), c_vp]
     lib.gs_sort_scratch_ints.argtypes = [c_i64]
     lib.gs_sort_scratch_ints.restype = ctypes.c_size_t
@@ -241,6 +246,35 @@ def gs_render_bwd(params: gs_params, frame: Frame, fwd: Optional[Sequence[torch.
     _check(load().gs_render_bwd(ctypes.byref(params), ctypes.byref(frame.f), ctypes.byref(frame.opts),
                                 ctypes.byref(im) if im is not None else None, ctypes.byref(l), ctypes.byref(grads),
                                 _stream(stream)), "gs_render_bwd")
+
+
+def _loss_struct(g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth, lambda_d) -> gs_loss:
+    return gs_loss(_ptr(g_rgb), _ptr(g_depth), _ptr(g_vis), _ptr(tgt_rgb), _ptr(tgt_depth), float(lambda_d), 0)
+
+
+def gs_composite_bwd(frame: Frame, fwd: Optional[Sequence[torch.Tensor]], g_rgb=None, g_depth=None, g_vis=None,
+                     tgt_rgb=None, tgt_depth=None, lambda_d: float = 0.1, stream=None) -> None:
+    im = None
+    if fwd is not None:
+        im = gs_images(fwd[0].data_ptr(), fwd[1].data_ptr(), fwd[2].data_ptr())
+    l = _loss_struct(g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth, lambda_d)
+    _check(load().gs_composite_bwd(ctypes.byref(frame.f), ctypes.byref(frame.opts),
+                                   ctypes.byref(im) if im is not None else None, ctypes.byref(l), _stream(stream)),
+           "gs_composite_bwd")
+
+
+def gs_project_bwd(params: gs_params, frame: Frame, grads: gs_params, stream=None) -> None:
+    _check(load().gs_project_bwd(ctypes.byref(params), ctypes.byref(frame.f), ctypes.byref(frame.opts),
+                                 ctypes.byref(grads), _stream(stream)), "gs_project_bwd")
+
+
+def gs_count_pairs(frame: Frame, stream=None):
+    """(evaluated, contributing) pairs of the frame's forward compositing (synchronises)."""
+    c = torch.zeros(2, dtype=torch.int64, device="cuda")
+    _check(load().gs_count_pairs(ctypes.byref(frame.f), ctypes.byref(frame.opts), c.data_ptr(), _stream(stream)),
+           "gs_count_pairs")
+    ev, co = c.cpu().tolist()
+    return int(ev), int(co)
 
 
 def gs_adam_step(params: gs_params, grads: gs_params, m: gs_params, v: gs_params, adam: gs_adam,

@@ -48,6 +48,10 @@ int opts_check(const gs_opts* o) {
   if (!o) return fail(GS_ERR_ARG, "opts is NULL");
   if (!tiles_supported(o->tile_w, o->tile_h))
     return fail(GS_ERR_ARG, "unsupported tile %dx%d (16x16, 16x8, 8x8, 32x8, 32x16)", o->tile_w, o->tile_h);
+  const int nw = o->waves_per_tile;
+  const bool nw_ok = nw == 0 || nw == 1 || (nw == 2 && !(o->tile_w == 8 && o->tile_h == 8)) ||
+                     (nw == 4 && (o->tile_w == 32 || (o->tile_w == 16 && o->tile_h == 16)));
+  if (!nw_ok) return fail(GS_ERR_ARG, "waves_per_tile %d unsupported for %dx%d tiles", nw, o->tile_w, o->tile_h);
   if (!(o->near_z > 0.f) || !(o->guard >= 1.f) || !(o->lowpass >= 0.f) || !(o->alpha_min > 0.f) ||
       !(o->alpha_max > o->alpha_min) || !(o->alpha_max < 1.f) || !(o->t_min > 0.f))
     return fail(GS_ERR_ARG, "invalid option values");
@@ -274,25 +278,51 @@ int gs_render_fwd(const gs_frame* f, const gs_opts* o, const gs_images* out, voi
   return GS_OK;
 }
 
-int gs_render_bwd(const gs_params* p, const gs_frame* f, const gs_opts* o, const gs_images* fwd, const gs_loss* l,
-                  const gs_params* grads, void* stream) {
+int gs_composite_bwd(const gs_frame* f, const gs_opts* o, const gs_images* fwd, const gs_loss* l, void* stream) {
   int rc;
-  if ((rc = params_check(p, "params")) || (rc = params_check(grads, "grads")) || (rc = frame_check(f)) ||
-      (rc = opts_check(o)))
-    return rc;
+  if ((rc = frame_check(f)) || (rc = opts_check(o))) return rc;
   if (!l) return fail(GS_ERR_ARG, "loss is NULL");
-  if (p->n != f->n || grads->n != f->n || grads->sh_degree != p->sh_degree)
-    return fail(GS_ERR_ARG, "params / grads / frame sizes differ");
   if (fwd && (!fwd->rgb || !fwd->depth || !fwd->vis)) return fail(GS_ERR_ARG, "forward images incomplete");
   if (l->tgt_rgb && !l->tgt_depth) return fail(GS_ERR_ARG, "loss mode needs tgt_depth");
   if (o->tile_w != f->tile_w || o->tile_h != f->tile_h) return fail(GS_ERR_ARG, "tile size differs from the frame");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (l->tgt_rgb) {
-    GS_HIP(gs_launch::fill_f32(f->loss, 0.f, 1, st), "gs_render_bwd: clear loss");
-    GS_HIP(gs_launch::count_valid(*f, l->tgt_depth, f->max_view_pixels, st), "gs_render_bwd: valid depth");
+    GS_HIP(gs_launch::fill_f32(f->loss, 0.f, 1, st), "gs_composite_bwd: clear loss");
+    GS_HIP(gs_launch::count_valid(*f, l->tgt_depth, f->max_view_pixels, st), "gs_composite_bwd: valid depth");
   }
-  GS_HIP(gs_launch::render_bwd(*f, *o, fwd, *l, st), "gs_render_bwd: composite");
-  GS_HIP(gs_launch::project_bwd(*p, *f, *o, *grads, st), "gs_render_bwd: projection");
+  GS_HIP(gs_launch::render_bwd(*f, *o, fwd, *l, st), "gs_composite_bwd");
+  return GS_OK;
+}
+
+int gs_project_bwd(const gs_params* p, const gs_frame* f, const gs_opts* o, const gs_params* grads, void* stream) {
+  int rc;
+  if ((rc = params_check(p, "params")) || (rc = params_check(grads, "grads")) || (rc = frame_check(f)) ||
+      (rc = opts_check(o)))
+    return rc;
+  if (p->n != f->n || grads->n != f->n || grads->sh_degree != p->sh_degree)
+    return fail(GS_ERR_ARG, "params / grads / frame sizes differ");
+  GS_HIP(gs_launch::project_bwd(*p, *f, *o, *grads, static_cast<hipStream_t>(stream)), "gs_project_bwd");
+  return GS_OK;
+}
+
+int gs_render_bwd(const gs_params* p, const gs_frame* f, const gs_opts* o, const gs_images* fwd, const gs_loss* l,
+                  const gs_params* grads, void* stream) {
+  int rc;
+  if ((rc = params_check(p, "params")) || (rc = params_check(grads, "grads")) || (rc = frame_check(f))) return rc;
+  if (p->n != f->n || grads->n != f->n || grads->sh_degree != p->sh_degree)
+    return fail(GS_ERR_ARG, "params / grads / frame sizes differ");
+  if ((rc = gs_composite_bwd(f, o, fwd, l, stream))) return rc;
+  return gs_project_bwd(p, f, o, grads, stream);
+}
+
+int gs_count_pairs(const gs_frame* f, const gs_opts* o, uint64_t* counts, void* stream) {
+  int rc;
+  if ((rc = frame_check(f)) || (rc = opts_check(o))) return rc;
+  if (!counts) return fail(GS_ERR_ARG, "counts is NULL");
+  if (o->tile_w != f->tile_w || o->tile_h != f->tile_h) return fail(GS_ERR_ARG, "tile size differs from the frame");
+  GS_HIP(gs_launch::count_pairs(*f, *o, reinterpret_cast<unsigned long long*>(counts),
+                                static_cast<hipStream_t>(stream)),
+         "gs_count_pairs");
   return GS_OK;
 }
 

@@ -249,7 +249,10 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ means
         const int64_t r = (int64_t)v * n + g;
         rec[3 * r + 0] = make_float4(mx, my, tz, s.o);
         rec[3 * r + 1] = make_float4(e.C * det_inv, -e.B * det_inv, e.A * det_inv, fmaxf(pre[0], 0.f));
-        rec[3 * r + 2] = make_float4(fmaxf(pre[1], 0.f), fmaxf(pre[2], 0.f), 0.f, 0.f);
+        // the pixel rectangle rides in the record's last two words (int16 pairs) for sub-tile culling
+        rec[3 * r + 2] = make_float4(fmaxf(pre[1], 0.f), fmaxf(pre[2], 0.f),
+                                     __int_as_float((px0 & 0xffff) | (px1 << 16)),
+                                     __int_as_float((py0 & 0xffff) | (py1 << 16)));
         rect[r] = make_short4((short)tx0, (short)tx1, (short)ty0, (short)ty1);
         if (zero_grads) {
           const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);

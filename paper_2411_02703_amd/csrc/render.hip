@@ -1,39 +1,59 @@
 // Per-tile front-to-back compositing of colour, depth and visibility (LVI-GS Section III-B,
 // eqs. Cp, Dp, Vp with the alpha of eq. alpha) and its backward.
 //
-// One wave64 per tile; each lane owns PPT pixels of the tile (a column of rows spaced 64/TW apart), so a
-// record staged in LDS is read once per lane and used PPT times.  Records of a tile's depth-sorted list
-// are staged 64 at a time (one per lane, coalesced by record id) into LDS and broadcast to all lanes.
+// One workgroup of NW wave64s per tile.  The tile is split into NW sub-tiles (quadrants or halves), one per
+// wave; each lane owns PPT pixels of its wave's sub-tile (a column of rows spaced 64/SW apart).  The tile's
+// depth-sorted list is staged 64*NW records at a time into LDS (one record per thread, gathered by record
+// id).  Each record carries its exact pixel rectangle, so every wave compacts the staged batch down to the
+// records whose rectangle meets its sub-tile and loops over those only.  A record is skipped only where its
+// rectangle misses the pixel, where alpha < exp(-1/2)/255 holds, so the result is the same bit for bit as
+// walking the whole list.  This matters for coarse pyramid levels, where a tile holds tens of thousands of
+// sub-pixel Gaussians of which each pixel sees a few percent.
 //
 // The backward walks the list in the same front-to-back order as the forward.  With the forward's final
 // values C, D, V of a pixel and its upstream gradient g, the gradient of alpha_i is
 //   dL/dalpha_i = T_i q_i - (S - P_i) / (1 - alpha_i),   q_i = g . (c_i, d_i, 1),
 //   S = g . (C, D, V),  P_i = sum_{j <= i} alpha_j T_j q_j,
-// i.e. what lies behind record i is S - P_i.  No per-pixel state has to be stored between the forward
-// and the backward (the fused variant recomputes C, D, V with a first sweep in the same kernel), and the
-// skip / stop decisions are re-evaluated with the forward's arithmetic.  Per-record gradients of a wave
-// are summed with DPP before one atomic add per value.
+// i.e. what lies behind record i is S - P_i.  No per-pixel state is stored between the forward and the
+// backward (the fused variant recomputes C, D, V with a first sweep in the same kernel), and the skip / stop
+// decisions are re-evaluated with the forward's arithmetic.  Per-record gradients of a wave are summed with
+// DPP before one atomic add per value.
 #include "common.h"
 
 namespace {
 
 using gsk::DevOpts;
 
-template <int TW, int TH>
+template <int TW, int TH, int NW>
 struct Geo {
-  static_assert(TW == 8 || TW == 16 || TW == 32, "tile width");
-  static constexpr int RPP = 64 / TW;  // rows of the tile covered by the 64 lanes at once
-  static constexpr int PPT = TH / RPP; // pixels per lane
-  static_assert(PPT >= 1 && PPT * RPP == TH, "tile height");
+  static constexpr int SX = NW == 4 ? 2 : 1;  // sub-tiles across
+  static constexpr int SY = NW / SX;          // sub-tiles down
+  static constexpr int SW = TW / SX;          // sub-tile width
+  static constexpr int SH = TH / SY;          // sub-tile height
+  static constexpr int RPP = 64 / SW;         // rows covered by the 64 lanes at once
+  static constexpr int PPT = SH / RPP;        // pixels per lane
+  static constexpr int BATCH = 64 * NW;       // records staged per round
+  static_assert(SW == 8 || SW == 16 || SW == 32, "sub-tile width");
+  static_assert(PPT >= 1 && PPT * RPP == SH, "sub-tile height");
+};
+
+template <int BATCH, int NW>
+struct Stage {
+  float4 A[BATCH], B[BATCH], C[BATCH];
+  int32_t r[BATCH];
+  uint8_t mask[BATCH];
+  uint16_t list[NW][BATCH];
 };
 
 struct TileCtx {
-  int view, W, H, px, py0;
+  int view, W, H, tx0, ty0;  // view and tile origin (pixels)
+  int px, py0;               // this lane's column and first row
+  int wave, lane;
   int64_t pix_off;
   float weight;
 };
 
-template <int TW, int TH>
+template <class G>
 __device__ __forceinline__ bool tile_setup(const gs_camera* __restrict__ cams, int V, int n_tiles, TileCtx& t,
                                            int& tile) {
   tile = gsk::xcd_remap(blockIdx.x, gridDim.x);
@@ -42,22 +62,31 @@ __device__ __forceinline__ bool tile_setup(const gs_camera* __restrict__ cams, i
   const gs_camera& c = cams[t.view];
   const int lt = tile - c.tile_offset;
   const int tyi = lt / c.tiles_x, txi = lt - tyi * c.tiles_x;
-  const int lane = threadIdx.x;
+  t.wave = threadIdx.x >> 6;
+  t.lane = threadIdx.x & 63;
   t.W = c.width;
   t.H = c.height;
-  t.px = txi * TW + (lane % TW);
-  t.py0 = tyi * TH + lane / TW;
+  t.tx0 = txi * (G::SW * G::SX);
+  t.ty0 = tyi * (G::SH * G::SY);
+  t.px = t.tx0 + (t.wave % G::SX) * G::SW + (t.lane % G::SW);
+  t.py0 = t.ty0 + (t.wave / G::SX) * G::SH + t.lane / G::SW;
   t.pix_off = c.pixel_offset;
   t.weight = c.loss_weight;
   return true;
 }
 
-// One record at one pixel: returns false if skipped (power > 0 or alpha < alpha_min).
+// One record at one pixel: returns false if skipped (power > 0 or alpha < alpha_min).  The operation
+// sequence is fixed (contraction off, explicit fma) so that every kernel and every tile shape computes the
+// same bits for the same (record, pixel) pair, whatever the compiler shares between a lane's pixels.
 __device__ __forceinline__ bool eval_pair(const float4& A, const float4& B, float fx, float fy, const DevOpts& op,
                                           float& alpha, float& G, bool& clamped, float& dx, float& dy) {
+#pragma clang fp contract(off)
   dx = A.x - fx;
   dy = A.y - fy;
-  const float power = -0.5f * (B.x * dx * dx + B.z * dy * dy) - B.y * dx * dy;
+  const float adx2 = (B.x * dx) * dx;
+  const float quad = __builtin_fmaf(B.z * dy, dy, adx2);  // a dx^2 + c dy^2
+  const float bxy = (B.y * dx) * dy;
+  const float power = __builtin_fmaf(-0.5f, quad, -bxy);  // -(a dx^2 + c dy^2)/2 - b dx dy
   if (power > 0.f) return false;
   G = __expf(power);
   const float oG = A.w * G;
@@ -66,28 +95,58 @@ __device__ __forceinline__ bool eval_pair(const float4& A, const float4& B, floa
   return alpha >= op.alpha_min;
 }
 
-struct Stage {
-  float4 A[64], B[64], C[64];
-  int32_t r[64];
-};
-
-__device__ __forceinline__ void stage_batch(Stage& s, const float4* __restrict__ rec, const int32_t* __restrict__ vals,
-                                            int b0, int nb) {
-  const int lane = threadIdx.x;
-  if (lane < nb) {
-    const int r = vals[b0 + lane];
-    s.A[lane] = rec[3 * (int64_t)r];
-    s.B[lane] = rec[3 * (int64_t)r + 1];
-    s.C[lane] = rec[3 * (int64_t)r + 2];
-    s.r[lane] = r;
-  }
+__device__ __forceinline__ void unpack_rect(const float4& C, int& x0, int& x1, int& y0, int& y1) {
+  const int a = __float_as_int(C.z), b = __float_as_int(C.w);
+  x0 = a & 0xffff;
+  x1 = (int)((unsigned)a >> 16);
+  y0 = b & 0xffff;
+  y1 = (int)((unsigned)b >> 16);
 }
 
-// Forward sweep of one tile (shared by the forward kernel and the fused backward's first phase).
-template <int PPT, int RPP>
-__device__ __forceinline__ void forward_sweep(Stage& s, const float4* __restrict__ rec, const int32_t* __restrict__ vals,
+// Stage records [b0, b0 + nb) of the tile list, then build each wave's list of the staged records whose
+// pixel rectangle meets its sub-tile.  Returns the length of this wave's list.  Ends with a barrier.
+template <class G, class S>
+__device__ __forceinline__ int stage_and_compact(S& s, const float4* __restrict__ rec, const int32_t* __restrict__ vals,
+                                                 int b0, int nb, const TileCtx& t) {
+  const int tid = threadIdx.x;
+  uint32_t m = 0;
+  if (tid < nb) {
+    const int r = vals[b0 + tid];
+    const float4 A = rec[3 * (int64_t)r], B = rec[3 * (int64_t)r + 1], C = rec[3 * (int64_t)r + 2];
+    s.A[tid] = A;
+    s.B[tid] = B;
+    s.C[tid] = C;
+    s.r[tid] = r;
+    int x0, x1, y0, y1;
+    unpack_rect(C, x0, x1, y0, y1);
+#pragma unroll
+    for (int w = 0; w < G::SX * G::SY; ++w) {
+      const int sx0 = t.tx0 + (w % G::SX) * G::SW, sy0 = t.ty0 + (w / G::SX) * G::SH;
+      if (x0 <= sx0 + G::SW - 1 && x1 >= sx0 && y0 <= sy0 + G::SH - 1 && y1 >= sy0) m |= 1u << w;
+    }
+  }
+  s.mask[tid] = (uint8_t)m;
+  __syncthreads();
+  int cnt = 0;
+  const uint64_t lt = gsk::lanemask_lt();
+#pragma unroll
+  for (int c = 0; c < G::BATCH / 64; ++c) {
+    const int j = c * 64 + t.lane;
+    const bool bit = (s.mask[j] >> t.wave) & 1;
+    const uint64_t bal = __ballot(bit);
+    if (bit) s.list[t.wave][cnt + __popcll(bal & lt)] = (uint16_t)j;
+    cnt += __popcll(bal);
+  }
+  __syncthreads();
+  return cnt;
+}
+
+// Forward sweep of one tile for this lane's pixels (shared by the forward kernel and the fused backward).
+template <class G, class S>
+__device__ __forceinline__ void forward_sweep(S& s, const float4* __restrict__ rec, const int32_t* __restrict__ vals,
                                               int2 rg, const TileCtx& t, const DevOpts& op, float* T, float* Cr,
                                               float* Cg, float* Cb, float* D, float* Vs) {
+  constexpr int PPT = G::PPT, RPP = G::RPP;
   bool live[PPT];
   float fy[PPT];
   const float fx = (float)t.px + 0.5f;
@@ -99,62 +158,65 @@ __device__ __forceinline__ void forward_sweep(Stage& s, const float4* __restrict
     T[k] = 1.f;
     Cr[k] = Cg[k] = Cb[k] = D[k] = Vs[k] = 0.f;
   }
-  for (int b0 = rg.x; b0 < rg.y; b0 += 64) {
+  for (int b0 = rg.x; b0 < rg.y; b0 += G::BATCH) {
     bool any = false;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) any |= live[k];
-    if (__ballot(any) == 0) break;
-    const int nb = min(64, rg.y - b0);
-    __syncthreads();
-    stage_batch(s, rec, vals, b0, nb);
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
+    if (!__syncthreads_or(any)) break;
+    const int nb = min(G::BATCH, rg.y - b0);
+    const int cnt = stage_and_compact<G>(s, rec, vals, b0, nb, t);
+    if (__ballot(any) == 0) continue;
+    for (int i = 0; i < cnt; ++i) {
+      const int j = s.list[t.wave][i];
       const float4 A = s.A[j], B = s.B[j], C = s.C[j];
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
+#pragma clang fp contract(off)
         if (!live[k]) continue;
-        float alpha, G, dx, dy;
+        float alpha, Gv, dx, dy;
         bool cl;
-        if (!eval_pair(A, B, fx, fy[k], op, alpha, G, cl, dx, dy)) continue;
+        if (!eval_pair(A, B, fx, fy[k], op, alpha, Gv, cl, dx, dy)) continue;
         const float Tn = T[k] * (1.f - alpha);
         if (Tn < op.t_min) {
           live[k] = false;
           continue;
         }
         const float w = alpha * T[k];
-        Cr[k] += w * B.w;
-        Cg[k] += w * C.x;
-        Cb[k] += w * C.y;
-        D[k] += w * A.z;
-        Vs[k] += w;
+        Cr[k] = __builtin_fmaf(w, B.w, Cr[k]);
+        Cg[k] = __builtin_fmaf(w, C.x, Cg[k]);
+        Cb[k] = __builtin_fmaf(w, C.y, Cb[k]);
+        D[k] = __builtin_fmaf(w, A.z, D[k]);
+        Vs[k] = Vs[k] + w;
         T[k] = Tn;
       }
     }
   }
 }
 
-template <int TW, int TH>
-__global__ __launch_bounds__(64) void k_render_fwd(const float4* __restrict__ rec, const int32_t* __restrict__ vals,
-                                                   const int2* __restrict__ range, const gs_camera* __restrict__ cams,
-                                                   int V, int n_tiles, DevOpts op, float* __restrict__ out_rgb,
-                                                   float* __restrict__ out_depth, float* __restrict__ out_vis) {
-  using Gm = Geo<TW, TH>;
-  constexpr int PPT = Gm::PPT, RPP = Gm::RPP;
-  __shared__ Stage s;
+template <int TW, int TH, int NW>
+__global__ __launch_bounds__(64 * NW) void k_render_fwd(const float4* __restrict__ rec,
+                                                        const int32_t* __restrict__ vals,
+                                                        const int2* __restrict__ range,
+                                                        const gs_camera* __restrict__ cams, int V, int n_tiles,
+                                                        DevOpts op, float* __restrict__ out_rgb,
+                                                        float* __restrict__ out_depth, float* __restrict__ out_vis) {
+  using G = Geo<TW, TH, NW>;
+  constexpr int PPT = G::PPT, RPP = G::RPP;
+  __shared__ Stage<G::BATCH, NW> s;
   TileCtx t;
   int tile;
-  if (!tile_setup<TW, TH>(cams, V, n_tiles, t, tile)) return;
+  if (!tile_setup<G>(cams, V, n_tiles, t, tile)) return;
   float T[PPT], Cr[PPT], Cg[PPT], Cb[PPT], D[PPT], Vs[PPT];
-  forward_sweep<PPT, RPP>(s, rec, vals, range[tile], t, op, T, Cr, Cg, Cb, D, Vs);
+  forward_sweep<G>(s, rec, vals, range[tile], t, op, T, Cr, Cg, Cb, D, Vs);
   const int64_t P = (int64_t)t.W * t.H;
 #pragma unroll
   for (int k = 0; k < PPT; ++k) {
     const int py = t.py0 + k * RPP;
     if (t.px < t.W && py < t.H) {
       const int64_t i = (int64_t)py * t.W + t.px;
-      out_rgb[3 * t.pix_off + i] = Cr[k] + T[k] * op.bg[0];
-      out_rgb[3 * t.pix_off + P + i] = Cg[k] + T[k] * op.bg[1];
-      out_rgb[3 * t.pix_off + 2 * P + i] = Cb[k] + T[k] * op.bg[2];
+      out_rgb[3 * t.pix_off + i] = __builtin_fmaf(T[k], op.bg[0], Cr[k]);
+      out_rgb[3 * t.pix_off + P + i] = __builtin_fmaf(T[k], op.bg[1], Cg[k]);
+      out_rgb[3 * t.pix_off + 2 * P + i] = __builtin_fmaf(T[k], op.bg[2], Cb[k]);
       out_depth[t.pix_off + i] = D[k];
       out_vis[t.pix_off + i] = Vs[k];
     }
@@ -176,16 +238,18 @@ struct BwdArgs {
   float* loss;
 };
 
-template <int TW, int TH, bool HAVE_FWD, bool LOSS>
-__global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ rec, const int32_t* __restrict__ vals,
-                                                   const int2* __restrict__ range, const gs_camera* __restrict__ cams,
-                                                   int V, int n_tiles, DevOpts op, BwdArgs a) {
-  using Gm = Geo<TW, TH>;
-  constexpr int PPT = Gm::PPT, RPP = Gm::RPP;
-  __shared__ Stage s;
+template <int TW, int TH, int NW, bool HAVE_FWD, bool LOSS>
+__global__ __launch_bounds__(64 * NW) void k_render_bwd(const float4* __restrict__ rec,
+                                                        const int32_t* __restrict__ vals,
+                                                        const int2* __restrict__ range,
+                                                        const gs_camera* __restrict__ cams, int V, int n_tiles,
+                                                        DevOpts op, BwdArgs a) {
+  using G = Geo<TW, TH, NW>;
+  constexpr int PPT = G::PPT, RPP = G::RPP;
+  __shared__ Stage<G::BATCH, NW> s;
   TileCtx t;
   int tile;
-  if (!tile_setup<TW, TH>(cams, V, n_tiles, t, tile)) return;
+  if (!tile_setup<G>(cams, V, n_tiles, t, tile)) return;
   const int2 rg = range[tile];
   const int64_t P = (int64_t)t.W * t.H;
   // final values of each pixel
@@ -206,12 +270,12 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
     }
   } else {
     float T[PPT];
-    forward_sweep<PPT, RPP>(s, rec, vals, rg, t, op, T, Cf, Gf, Bf, Df, Vf);
+    forward_sweep<G>(s, rec, vals, rg, t, op, T, Cf, Gf, Bf, Df, Vf);
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-      Cf[k] += T[k] * op.bg[0];
-      Gf[k] += T[k] * op.bg[1];
-      Bf[k] += T[k] * op.bg[2];
+      Cf[k] = __builtin_fmaf(T[k], op.bg[0], Cf[k]);
+      Gf[k] = __builtin_fmaf(T[k], op.bg[1], Gf[k]);
+      Bf[k] = __builtin_fmaf(T[k], op.bg[2], Bf[k]);
     }
   }
   // upstream gradient of each pixel
@@ -257,7 +321,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
   }
   if (LOSS) {
     const float ls = gsk::wave_sum_last(loss_acc);
-    if (threadIdx.x == 63) gsk::atomic_add_f32(a.loss, ls);
+    if (t.lane == 63) gsk::atomic_add_f32(a.loss, ls);
   }
   // second sweep, front to back
   bool live[PPT];
@@ -271,42 +335,42 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
     T[k] = 1.f;
     Pp[k] = 0.f;
   }
-  for (int b0 = rg.x; b0 < rg.y; b0 += 64) {
+  for (int b0 = rg.x; b0 < rg.y; b0 += G::BATCH) {
     bool any = false;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) any |= live[k];
-    if (__ballot(any) == 0) break;
-    const int nb = min(64, rg.y - b0);
-    __syncthreads();
-    stage_batch(s, rec, vals, b0, nb);
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
+    if (!__syncthreads_or(any)) break;
+    const int nb = min(G::BATCH, rg.y - b0);
+    const int cnt = stage_and_compact<G>(s, rec, vals, b0, nb, t);
+    if (__ballot(any) == 0) continue;
+    for (int i = 0; i < cnt; ++i) {
+      const int j = s.list[t.wave][i];
       const float4 A = s.A[j], B = s.B[j], C = s.C[j];
       float acc[10];
 #pragma unroll
-      for (int i = 0; i < 10; ++i) acc[i] = 0.f;
+      for (int q = 0; q < 10; ++q) acc[q] = 0.f;
       bool hit = false;
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         if (!live[k]) continue;
-        float alpha, G, dx, dy;
+        float alpha, Gv, dx, dy;
         bool cl;
-        if (!eval_pair(A, B, fx, fy[k], op, alpha, G, cl, dx, dy)) continue;
+        if (!eval_pair(A, B, fx, fy[k], op, alpha, Gv, cl, dx, dy)) continue;
         const float Tn = T[k] * (1.f - alpha);
         if (Tn < op.t_min) {
           live[k] = false;
           continue;
         }
         const float w = alpha * T[k];
-        const float q = gr[k] * B.w + gg[k] * C.x + gb[k] * C.y + gd[k] * A.z + gv[k];
-        Pp[k] += w * q;
-        const float dalpha = T[k] * q - (S[k] - Pp[k]) * __builtin_amdgcn_rcpf(1.f - alpha);
+        const float qv = gr[k] * B.w + gg[k] * C.x + gb[k] * C.y + gd[k] * A.z + gv[k];
+        Pp[k] += w * qv;
+        const float dalpha = T[k] * qv - (S[k] - Pp[k]) * __builtin_amdgcn_rcpf(1.f - alpha);
         acc[6] += w * gr[k];
         acc[7] += w * gg[k];
         acc[8] += w * gb[k];
         acc[9] += w * gd[k];
         if (!cl) {
-          acc[5] += dalpha * G;
+          acc[5] += dalpha * Gv;
           const float dq = dalpha * alpha;
           acc[2] += -0.5f * dx * dx * dq;
           acc[3] += -dx * dy * dq;
@@ -320,52 +384,134 @@ __global__ __launch_bounds__(64) void k_render_bwd(const float4* __restrict__ re
       if (__ballot(hit) != 0) {
         float* dst = a.rgrad + 12 * (int64_t)s.r[j];
 #pragma unroll
-        for (int i = 0; i < 10; ++i) {
-          const float sum = gsk::wave_sum_last(acc[i]);
-          if (threadIdx.x == 63) gsk::atomic_add_f32(dst + i, sum);
+        for (int q = 0; q < 10; ++q) {
+          const float sum = gsk::wave_sum_last(acc[q]);
+          if (t.lane == 63) gsk::atomic_add_f32(dst + q, sum);
         }
       }
     }
   }
 }
 
-__global__ void k_count_valid(const float* __restrict__ tgt_depth, const gs_camera* __restrict__ cams,
-                              int32_t* __restrict__ n_valid) {
+// Work counts of the forward: pairs evaluated (pixel inside the record's pixel rectangle, up to the
+// pixel's stop) and pairs contributing.  Independent of the tile shape; diagnostic.
+template <int TW, int TH, int NW>
+__global__ __launch_bounds__(64 * NW) void k_count_pairs(const float4* __restrict__ rec,
+                                                         const int32_t* __restrict__ vals,
+                                                         const int2* __restrict__ range,
+                                                         const gs_camera* __restrict__ cams, int V, int n_tiles,
+                                                         DevOpts op, unsigned long long* __restrict__ counts) {
+  using G = Geo<TW, TH, NW>;
+  constexpr int PPT = G::PPT, RPP = G::RPP;
+  __shared__ Stage<G::BATCH, NW> s;
+  TileCtx t;
+  int tile;
+  if (!tile_setup<G>(cams, V, n_tiles, t, tile)) return;
+  const int2 rg = range[tile];
+  bool live[PPT];
+  float fy[PPT], T[PPT];
+  const float fx = (float)t.px + 0.5f;
+  unsigned long long ev = 0, co = 0;
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int py = t.py0 + k * RPP;
+    live[k] = t.px < t.W && py < t.H;
+    fy[k] = (float)py + 0.5f;
+    T[k] = 1.f;
+  }
+  for (int b0 = rg.x; b0 < rg.y; b0 += G::BATCH) {
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) any |= live[k];
+    if (!__syncthreads_or(any)) break;
+    const int nb = min(G::BATCH, rg.y - b0);
+    const int cnt = stage_and_compact<G>(s, rec, vals, b0, nb, t);
+    for (int i = 0; i < cnt; ++i) {
+      const int j = s.list[t.wave][i];
+      const float4 A = s.A[j], B = s.B[j], C = s.C[j];
+      int x0, x1, y0, y1;
+      unpack_rect(C, x0, x1, y0, y1);
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        if (!live[k]) continue;
+        const int py = t.py0 + k * RPP;
+        if (t.px < x0 || t.px > x1 || py < y0 || py > y1) continue;
+        ++ev;
+        float alpha, Gv, dx, dy;
+        bool cl;
+        if (!eval_pair(A, B, fx, fy[k], op, alpha, Gv, cl, dx, dy)) continue;
+        const float Tn = T[k] * (1.f - alpha);
+        if (Tn < op.t_min) {
+          live[k] = false;
+          continue;
+        }
+        ++co;
+        T[k] = Tn;
+      }
+    }
+  }
+  atomicAdd(counts, ev);
+  atomicAdd(counts + 1, co);
+}
+
+// Valid LiDAR-depth pixels per view: grid-stride per view, one atomic per block.
+__global__ __launch_bounds__(256) void k_count_valid(const float* __restrict__ tgt_depth,
+                                                     const gs_camera* __restrict__ cams,
+                                                     int32_t* __restrict__ n_valid) {
+  __shared__ int sh;
+  if (threadIdx.x == 0) sh = 0;
+  __syncthreads();
   const int v = blockIdx.y;
   const gs_camera& c = cams[v];
   const int64_t P = (int64_t)c.width * c.height;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool ok = i < P && tgt_depth[c.pixel_offset + i] > 0.f;
-  const uint64_t b = __ballot(ok);
-  if (__lane_id() == 0 && b) atomicAdd(n_valid + v, (int)__popcll(b));
+  int cnt = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x)
+    cnt += tgt_depth[c.pixel_offset + i] > 0.f;
+  atomicAdd(&sh, cnt);
+  __syncthreads();
+  if (threadIdx.x == 0 && sh) atomicAdd(n_valid + v, sh);
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int NW>
 hipError_t launch_fwd(const gs_frame& f, const DevOpts& op, const gs_images& out, hipStream_t st) {
   const int nb = ((f.n_tiles + 7) / 8) * 8;
   const int sorted = f.sort_passes & 1;
-  k_render_fwd<TW, TH><<<nb, 64, 0, st>>>(reinterpret_cast<const float4*>(f.rec), f.vals[sorted],
-                                          reinterpret_cast<const int2*>(f.tile_range), f.cams, f.n_views, f.n_tiles,
-                                          op, out.rgb, out.depth, out.vis);
+  k_render_fwd<TW, TH, NW><<<nb, 64 * NW, 0, st>>>(reinterpret_cast<const float4*>(f.rec), f.vals[sorted],
+                                                   reinterpret_cast<const int2*>(f.tile_range), f.cams, f.n_views,
+                                                   f.n_tiles, op, out.rgb, out.depth, out.vis);
   return hipGetLastError();
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int NW>
 hipError_t launch_bwd(const gs_frame& f, const DevOpts& op, bool have_fwd, bool loss, const BwdArgs& a,
                       hipStream_t st) {
   const int nb = ((f.n_tiles + 7) / 8) * 8;
   const int sorted = f.sort_passes & 1;
   const auto* rec = reinterpret_cast<const float4*>(f.rec);
   const auto* rng = reinterpret_cast<const int2*>(f.tile_range);
+  const int bs = 64 * NW;
   if (have_fwd && loss)
-    k_render_bwd<TW, TH, true, true><<<nb, 64, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, f.n_tiles, op, a);
+    k_render_bwd<TW, TH, NW, true, true><<<nb, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, f.n_tiles,
+                                                            op, a);
   else if (have_fwd)
-    k_render_bwd<TW, TH, true, false><<<nb, 64, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, f.n_tiles, op, a);
+    k_render_bwd<TW, TH, NW, true, false><<<nb, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views,
+                                                             f.n_tiles, op, a);
   else if (loss)
-    k_render_bwd<TW, TH, false, true><<<nb, 64, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, f.n_tiles, op, a);
+    k_render_bwd<TW, TH, NW, false, true><<<nb, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views,
+                                                             f.n_tiles, op, a);
   else
-    k_render_bwd<TW, TH, false, false><<<nb, 64, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, f.n_tiles, op,
-                                                          a);
+    k_render_bwd<TW, TH, NW, false, false><<<nb, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views,
+                                                              f.n_tiles, op, a);
+  return hipGetLastError();
+}
+
+template <int TW, int TH, int NW>
+hipError_t launch_count(const gs_frame& f, const DevOpts& op, unsigned long long* counts, hipStream_t st) {
+  const int nb = ((f.n_tiles + 7) / 8) * 8;
+  const int sorted = f.sort_passes & 1;
+  k_count_pairs<TW, TH, NW><<<nb, 64 * NW, 0, st>>>(reinterpret_cast<const float4*>(f.rec), f.vals[sorted],
+                                                    reinterpret_cast<const int2*>(f.tile_range), f.cams, f.n_views,
+                                                    f.n_tiles, op, counts);
   return hipGetLastError();
 }
 
@@ -373,14 +519,31 @@ hipError_t launch_bwd(const gs_frame& f, const DevOpts& op, bool have_fwd, bool 
 
 namespace gs_launch {
 
-#define GS_TILE_DISPATCH(FN, ...)                                          \
-  do {                                                                     \
-    if (o.tile_w == 16 && o.tile_h == 16) return FN<16, 16>(__VA_ARGS__);  \
-    if (o.tile_w == 16 && o.tile_h == 8) return FN<16, 8>(__VA_ARGS__);    \
-    if (o.tile_w == 8 && o.tile_h == 8) return FN<8, 8>(__VA_ARGS__);      \
-    if (o.tile_w == 32 && o.tile_h == 8) return FN<32, 8>(__VA_ARGS__);    \
-    if (o.tile_w == 32 && o.tile_h == 16) return FN<32, 16>(__VA_ARGS__);  \
-    return hipErrorInvalidValue;                                           \
+// Tile shape and waves per tile (o.waves_per_tile; 0 picks 4 where the shape allows it).
+#define GS_TILE_DISPATCH(FN, ...)                                 \
+  do {                                                            \
+    const int nw = o.waves_per_tile;                              \
+    if (o.tile_w == 16 && o.tile_h == 16) {                       \
+      if (nw == 1) return FN<16, 16, 1>(__VA_ARGS__);             \
+      if (nw == 2) return FN<16, 16, 2>(__VA_ARGS__);             \
+      return FN<16, 16, 4>(__VA_ARGS__);                          \
+    }                                                             \
+    if (o.tile_w == 16 && o.tile_h == 8) {                        \
+      if (nw == 1) return FN<16, 8, 1>(__VA_ARGS__);              \
+      return FN<16, 8, 2>(__VA_ARGS__);                           \
+    }                                                             \
+    if (o.tile_w == 8 && o.tile_h == 8) return FN<8, 8, 1>(__VA_ARGS__); \
+    if (o.tile_w == 32 && o.tile_h == 8) {                        \
+      if (nw == 1) return FN<32, 8, 1>(__VA_ARGS__);              \
+      if (nw == 2) return FN<32, 8, 2>(__VA_ARGS__);              \
+      return FN<32, 8, 4>(__VA_ARGS__);                           \
+    }                                                             \
+    if (o.tile_w == 32 && o.tile_h == 16) {                       \
+      if (nw == 1) return FN<32, 16, 1>(__VA_ARGS__);             \
+      if (nw == 2) return FN<32, 16, 2>(__VA_ARGS__);             \
+      return FN<32, 16, 4>(__VA_ARGS__);                          \
+    }                                                             \
+    return hipErrorInvalidValue;                                  \
   } while (0)
 
 hipError_t render_fwd(const gs_frame& f, const gs_opts& o, const gs_images& out, hipStream_t st) {
@@ -388,10 +551,17 @@ hipError_t render_fwd(const gs_frame& f, const gs_opts& o, const gs_images& out,
   GS_TILE_DISPATCH(launch_fwd, f, op, out, st);
 }
 
+hipError_t count_pairs(const gs_frame& f, const gs_opts& o, unsigned long long* counts, hipStream_t st) {
+  const DevOpts op = gsk::dev_opts(o);
+  GS_TILE_DISPATCH(launch_count, f, op, counts, st);
+}
+
 hipError_t count_valid(const gs_frame& f, const float* tgt_depth, int64_t max_pixels, hipStream_t st) {
   hipError_t e = fill_i32(f.counters + 2, 0, f.n_views, st);
   if (e != hipSuccess) return e;
-  dim3 grid((unsigned)((max_pixels + 255) / 256), (unsigned)f.n_views);
+  int64_t bx = (max_pixels + 256 * 32 - 1) / (256 * 32);
+  if (bx < 1) bx = 1;
+  dim3 grid((unsigned)bx, (unsigned)f.n_views);
   k_count_valid<<<grid, 256, 0, st>>>(tgt_depth, f.cams, f.counters + 2);
   return hipGetLastError();
 }

@@ -28,11 +28,11 @@ def log(*a):
     print(*a, flush=True)
 
 
-def run_gpu(sc, tile=(16, 16), g_images=None, targets=True, fused=False, capacity=None, zero=True):
+def run_gpu(sc, tile=(16, 16), g_images=None, targets=True, fused=False, capacity=None, zero=True, nw=0):
     """Project, bin, render and (optionally) backpropagate one scene; returns numpy results."""
     torch.cuda.synchronize()
     model = GaussianModel(sc.params(), sc.sh_degree)
-    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1])
+    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], waves_per_tile=nw)
     fr = B.Frame(model.n, sc.cams, opts, capacity)
     B.gs_project(model.ps, fr, zero_grads=zero)
     n_inst = B.gs_bin_tiles(fr, sync_count=True)
@@ -92,9 +92,12 @@ def check_images(gpu, ref, near, what=""):
         assert not bad.any(), f"{what} {key}: {bad.sum()} pixels off, max err {err.max():.3e}"
 
 
-def check_grads(gpu, ref, excused, what=""):
+def check_grads(gpu, ref, excused, what="", near_pixels=0, n_pixels=1):
+    """Gradient bar; Gaussians touching a near-threshold pixel are excused (those pixels <= 1e-3 of all)."""
     n_exc = int(excused.sum())
-    assert n_exc <= max(5, 1e-2 * excused.size), (what, n_exc)
+    log(f"{what}: excused Gaussians {n_exc} / {excused.size}, near-threshold pixels {near_pixels} / {n_pixels}")
+    assert near_pixels <= max(2, 1e-3 * n_pixels), (what, near_pixels)
+    assert n_exc <= 0.05 * excused.size, (what, n_exc)
     for k in ref:
         r = np.asarray(ref[k]).reshape(excused.size, -1)
         g = np.asarray(gpu[k], np.float64).reshape(excused.size, -1)
@@ -212,11 +215,13 @@ def test_forward_is_tile_size_invariant_and_deterministic(gpu_lib):
     again = run_gpu(sc, targets=False)
     for k in ("rgb", "depth", "vis"):
         assert np.array_equal(base[k], again[k]), k
-    for tile in [(8, 8), (16, 8), (32, 8), (32, 16)]:
-        log("tile", tile)
-        o = run_gpu(sc, tile=tile, targets=False)
+    for tile, nw in [((16, 16), 1), ((16, 16), 2), ((8, 8), 1), ((16, 8), 1), ((16, 8), 2), ((32, 8), 1),
+                     ((32, 8), 2), ((32, 8), 4), ((32, 16), 1), ((32, 16), 2), ((32, 16), 4)]:
+        log("tile", tile, "waves", nw)
+        o = run_gpu(sc, tile=tile, targets=False, nw=nw)
         for k in ("rgb", "depth", "vis"):
-            assert np.array_equal(base[k], o[k]), (tile, k)
+            d = np.abs(base[k] - o[k])
+            assert np.array_equal(base[k], o[k]), (tile, nw, k, int((d > 0).sum()), float(d.max()))
 
 
 # ----------------------------------------------------------------------------- backward
@@ -230,8 +235,7 @@ def test_backward_upstream_gradients_match_fp64_oracle(gpu_lib, deg):
     log("backward g-mode deg", deg)
     out = run_gpu(sc, g_images=g, targets=False)
     L, ref, exc, nn, _ = oracle.backward(64, sc.params(), deg, sc.cams, g_rgb=g[0], g_depth=g[1], g_vis=g[2])
-    log("excused Gaussians:", int(exc.sum()), "near pixels:", nn)
-    check_grads(out["grads"], ref, exc, f"g-mode deg {deg}")
+    check_grads(out["grads"], ref, exc, f"g-mode deg {deg}", nn, P)
 
 
 @pytest.mark.parametrize("fused", [False, True])
@@ -241,7 +245,7 @@ def test_backward_loss_mode_matches_fp64_oracle(gpu_lib, fused):
     out = run_gpu(sc, targets=True, fused=fused)
     L, ref, exc, nn, _ = oracle.backward(64, sc.params(), 2, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
     np.testing.assert_allclose(out["loss"], L, rtol=1e-5)
-    check_grads(out["grads"], ref, exc, f"loss mode fused={fused}")
+    check_grads(out["grads"], ref, exc, f"loss mode fused={fused}", nn, sc.total_pixels)
 
 
 def test_backward_config1(gpu_lib):
@@ -249,7 +253,7 @@ def test_backward_config1(gpu_lib):
     out = run_gpu(sc, targets=True, fused=True)
     L, ref, exc, nn, _ = oracle.backward(64, sc.params(), 0, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
     np.testing.assert_allclose(out["loss"], L, rtol=1e-5)
-    check_grads(out["grads"], ref, exc, "cfg1")
+    check_grads(out["grads"], ref, exc, "cfg1", nn, sc.total_pixels)
 
 
 # ----------------------------------------------------------------------------- Adam
@@ -370,3 +374,25 @@ def test_capacity_overflow_is_flagged_without_fault(gpu_lib):
     ok = BatchedStep(GaussianModel(sc.params(), 0), sc.cams, sc.tgt_rgb, sc.tgt_depth)
     ok.run_eager()
     assert not ok.overflowed()
+
+
+def test_pair_counts_match_oracle(gpu_lib):
+    sc = scenes.random_scene(1400, 2500, 110, 80, sh_degree=0, views=2, log_scale_mu=-2.3)
+    out = run_gpu(sc, targets=False)
+    ev, co = B.gs_count_pairs(out["frame"])
+    ref = oracle.forward(32, sc.params(), 0, sc.cams)
+    assert co == int(ref["n_contrib"].sum())
+    assert ev >= co
+
+
+@pytest.mark.parametrize("nw", [1, 2, 4])
+def test_backward_identical_across_waves_per_tile(gpu_lib, nw):
+    """Gradients agree (to atomic summation order) whatever the number of waves per tile."""
+    sc = scenes.random_scene(1500, 2000, 100, 70, sh_degree=1, views=2, log_scale_mu=-2.3, depth_fraction=0.3)
+    ref = run_gpu(sc, targets=True, fused=True, nw=1)
+    out = run_gpu(sc, targets=True, fused=True, nw=nw)
+    np.testing.assert_allclose(out["loss"], ref["loss"], rtol=1e-6)
+    for k in ref["grads"]:
+        a, b = ref["grads"][k], out["grads"][k]
+        rms = np.sqrt((a.astype(np.float64) ** 2).mean()) + 1e-30
+        assert np.all(np.abs(a - b) <= 1e-5 * (np.abs(a) + rms)), k

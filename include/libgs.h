@@ -132,7 +132,9 @@ typedef struct gs_frame {
   uint64_t* keys[2];    /* [capacity] ping-pong sort buffers */
   int32_t* vals[2];     /* [capacity] record ids */
   int32_t* tile_range;  /* [n_tiles][2]: [begin, end) of each tile's instances in the sorted list */
-  int32_t* counters;    /* [128]: [0] instance count, [1] flags, [2..2+n_views) valid depth pixels per view */
+  int32_t* tile_order;  /* [n_tiles]: tiles by descending list length (the compositing schedule) */
+  int32_t* counters;    /* [256]: [0] instance count, [1] flags, [2..2+n_views) valid depth pixels per view,
+                           [128..192) tile-length bucket counts and offsets */
   float* loss;          /* [1]: loss value written by gs_render_bwd in loss mode */
   int32_t* scratch;     /* sort histograms and scan partials */
   size_t scratch_ints;

@@ -49,7 +49,7 @@ class gs_frame(ctypes.Structure):
                 ("tile_w", c_i32), ("tile_h", c_i32), ("cams", c_vp), ("block", c_vp), ("bytes", ctypes.c_size_t),
                 ("rec", c_vp), ("rect", c_vp), ("rgrad", c_vp), ("vis_mask", c_vp), ("n_inst", c_vp),
                 ("inst_off", c_vp), ("keys", c_vp * 2), ("vals", c_vp * 2), ("tile_range", c_vp),
-                ("counters", c_vp), ("loss", c_vp), ("scratch", c_vp), ("scratch_ints", ctypes.c_size_t)]
+                ("tile_order", c_vp), ("counters", c_vp), ("loss", c_vp), ("scratch", c_vp), ("scratch_ints", ctypes.c_size_t)]
 
 
 class gs_images(ctypes.Structure):

@@ -39,7 +39,7 @@ bool tiles_supported(int tw, int th) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t rec, rect, rgrad, mask, ninst, instoff, k0, k1, v0, v1, range, counters, loss, scratch, total;
+  size_t rec, rect, rgrad, mask, ninst, instoff, k0, k1, v0, v1, range, order, counters, loss, scratch, total;
   size_t scratch_ints;
   int key_bits, passes;
 };
@@ -98,7 +98,8 @@ Layout make_layout(int64_t n, int V, int n_tiles, int64_t cap) {
   L.v0 = take((size_t)cap * 4);
   L.v1 = take((size_t)cap * 4);
   L.range = take((size_t)n_tiles * 8);
-  L.counters = take(128 * 4);
+  L.order = take((size_t)n_tiles * 4);
+  L.counters = take(256 * 4);
   L.loss = take(64 * 4);
   const size_t s1 = gs_launch::scan_scratch_ints(n), s2 = gs_launch::sort_scratch_ints(cap);
   L.scratch_ints = s1 > s2 ? s1 : s2;
@@ -227,6 +228,7 @@ int gs_frame_init(gs_frame* f, void* block, size_t bytes, int64_t n, const gs_ca
   f->vals[0] = reinterpret_cast<int32_t*>(b + L.v0);
   f->vals[1] = reinterpret_cast<int32_t*>(b + L.v1);
   f->tile_range = reinterpret_cast<int32_t*>(b + L.range);
+  f->tile_order = reinterpret_cast<int32_t*>(b + L.order);
   f->counters = reinterpret_cast<int32_t*>(b + L.counters);
   f->loss = reinterpret_cast<float*>(b + L.loss);
   f->scratch = reinterpret_cast<int32_t*>(b + L.scratch);
@@ -266,6 +268,7 @@ int gs_bin_tiles(const gs_frame* f, const gs_opts* o, int32_t sync_count, int64_
                                f->key_bits, f->scratch, st),
          "gs_bin_tiles: sort");
   GS_HIP(gs_launch::ranges(*f, f->keys[f->sort_passes & 1], n_sized, count_dev, st), "gs_bin_tiles: ranges");
+  GS_HIP(gs_launch::tile_schedule(*f, st), "gs_bin_tiles: schedule");
   return GS_OK;
 }
 

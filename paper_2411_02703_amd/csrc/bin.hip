@@ -223,6 +223,50 @@ __global__ void k_ranges(const uint64_t* __restrict__ keys, const int32_t* __res
   if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != t) range[t].y = (int)(i + 1);
 }
 
+// Compositing schedule: tiles in descending order of their list length, bucketed by floor(log2(len + 1))
+// (32 buckets, longest first; the order inside a bucket does not matter).
+__device__ __forceinline__ int len_bucket(const int2* range, int t) {
+  const int len = range[t].y - range[t].x;
+  return __clz(len + 1);  // 31 - floor(log2(len + 1)): longer lists get smaller bucket ids
+}
+
+__global__ __launch_bounds__(256) void k_sched_hist(const int2* __restrict__ range, int n_tiles,
+                                                    int32_t* __restrict__ bucket_cnt) {
+  __shared__ int h[32];
+  if (threadIdx.x < 32) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n_tiles) atomicAdd(&h[len_bucket(range, t)], 1);
+  __syncthreads();
+  if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(bucket_cnt + threadIdx.x, h[threadIdx.x]);
+}
+
+__global__ void k_sched_scan(const int32_t* __restrict__ bucket_cnt, int32_t* __restrict__ bucket_off) {
+  if (threadIdx.x != 0) return;
+  int run = 0;
+  for (int b = 0; b < 32; ++b) {
+    bucket_off[b] = run;
+    run += bucket_cnt[b];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sched_scatter(const int2* __restrict__ range, int n_tiles,
+                                                       int32_t* __restrict__ bucket_off, int32_t* __restrict__ order) {
+  __shared__ int h[32], base[32];
+  if (threadIdx.x < 32) h[threadIdx.x] = 0;
+  __syncthreads();
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int b = 0, rank = 0;
+  if (t < n_tiles) {
+    b = len_bucket(range, t);
+    rank = atomicAdd(&h[b], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < 32 && h[threadIdx.x]) base[threadIdx.x] = atomicAdd(bucket_off + threadIdx.x, h[threadIdx.x]);
+  __syncthreads();
+  if (t < n_tiles) order[base[b] + rank] = t;
+}
+
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t align64(int64_t a) { return (a + 63) & ~int64_t(63); }
 
@@ -307,6 +351,21 @@ hipError_t sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int6
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t tile_schedule(const gs_frame& f, hipStream_t st) {
+  int32_t* cnt = f.counters + 128;
+  int32_t* off = f.counters + 160;
+  hipError_t e = fill_i32(cnt, 0, 32, st);
+  if (e != hipSuccess) return e;
+  const auto* rng = reinterpret_cast<const int2*>(f.tile_range);
+  const unsigned nb = (unsigned)cdiv(f.n_tiles, 256);
+  k_sched_hist<<<nb, 256, 0, st>>>(rng, f.n_tiles, cnt);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_sched_scan<<<1, 64, 0, st>>>(cnt, off);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_sched_scatter<<<nb, 256, 0, st>>>(rng, f.n_tiles, off, f.tile_order);
+  return hipGetLastError();
 }
 
 hipError_t ranges(const gs_frame& f, const uint64_t* keys, int64_t n_sized, const int32_t* count_dev,

@@ -101,6 +101,7 @@ size_t sort_scratch_ints(int64_t n);
 hipError_t sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int64_t n_sized,
                       const int32_t* count_dev, int64_t cap, int key_bits, int32_t* scratch, hipStream_t s);
 hipError_t ranges(const gs_frame& f, const uint64_t* keys, int64_t n_sized, const int32_t* count_dev, hipStream_t s);
+hipError_t tile_schedule(const gs_frame& f, hipStream_t s);
 hipError_t render_fwd(const gs_frame& f, const gs_opts& o, const gs_images& out, hipStream_t s);
 hipError_t count_pairs(const gs_frame& f, const gs_opts& o, unsigned long long* counts, hipStream_t s);
 hipError_t count_valid(const gs_frame& f, const float* tgt_depth, int64_t max_pixels, hipStream_t s);

@@ -17,7 +17,7 @@
 // i.e. what lies behind record i is S - P_i.  No per-pixel state is stored between the forward and the
 // backward (the fused variant recomputes C, D, V with a first sweep in the same kernel), and the skip / stop
 // decisions are re-evaluated with the forward's arithmetic.  Per-record gradients of a wave are summed with
-// DPP before one atomic add per value.
+// DPP before one atomic add per value, unless at most four lanes contributed (then each adds its own).
 #include "common.h"
 
 namespace {
@@ -53,11 +53,13 @@ struct TileCtx {
   float weight;
 };
 
+// Workgroup b composites tile order[b]: tiles in descending order of list length, so the longest start first
+// and are dealt round-robin over the XCDs.
 template <class G>
-__device__ __forceinline__ bool tile_setup(const gs_camera* __restrict__ cams, int V, int n_tiles, TileCtx& t,
-                                           int& tile) {
-  tile = gsk::xcd_remap(blockIdx.x, gridDim.x);
-  if (tile >= n_tiles) return false;
+__device__ __forceinline__ bool tile_setup(const gs_camera* __restrict__ cams, int V, int n_tiles,
+                                           const int32_t* __restrict__ order, TileCtx& t, int& tile) {
+  if ((int)blockIdx.x >= n_tiles) return false;
+  tile = order[blockIdx.x];
   t.view = gsk::view_of_tile(cams, V, tile);
   const gs_camera& c = cams[t.view];
   const int lt = tile - c.tile_offset;
@@ -197,7 +199,7 @@ template <int TW, int TH, int NW>
 __global__ __launch_bounds__(64 * NW) void k_render_fwd(const float4* __restrict__ rec,
                                                         const int32_t* __restrict__ vals,
                                                         const int2* __restrict__ range,
-                                                        const gs_camera* __restrict__ cams, int V, int n_tiles,
+                                                        const gs_camera* __restrict__ cams, int V, int n_tiles, const int32_t* __restrict__ order,
                                                         DevOpts op, float* __restrict__ out_rgb,
                                                         float* __restrict__ out_depth, float* __restrict__ out_vis) {
   using G = Geo<TW, TH, NW>;
@@ -205,7 +207,7 @@ __global__ __launch_bounds__(64 * NW) void k_render_fwd(const float4* __restrict
   __shared__ Stage<G::BATCH, NW> s;
   TileCtx t;
   int tile;
-  if (!tile_setup<G>(cams, V, n_tiles, t, tile)) return;
+  if (!tile_setup<G>(cams, V, n_tiles, order, t, tile)) return;
   float T[PPT], Cr[PPT], Cg[PPT], Cb[PPT], D[PPT], Vs[PPT];
   forward_sweep<G>(s, rec, vals, range[tile], t, op, T, Cr, Cg, Cb, D, Vs);
   const int64_t P = (int64_t)t.W * t.H;
@@ -242,14 +244,14 @@ template <int TW, int TH, int NW, bool HAVE_FWD, bool LOSS>
 __global__ __launch_bounds__(64 * NW) void k_render_bwd(const float4* __restrict__ rec,
                                                         const int32_t* __restrict__ vals,
                                                         const int2* __restrict__ range,
-                                                        const gs_camera* __restrict__ cams, int V, int n_tiles,
+                                                        const gs_camera* __restrict__ cams, int V, int n_tiles, const int32_t* __restrict__ order,
                                                         DevOpts op, BwdArgs a) {
   using G = Geo<TW, TH, NW>;
   constexpr int PPT = G::PPT, RPP = G::RPP;
   __shared__ Stage<G::BATCH, NW> s;
   TileCtx t;
   int tile;
-  if (!tile_setup<G>(cams, V, n_tiles, t, tile)) return;
+  if (!tile_setup<G>(cams, V, n_tiles, order, t, tile)) return;
   const int2 rg = range[tile];
   const int64_t P = (int64_t)t.W * t.H;
   // final values of each pixel
@@ -381,12 +383,21 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const float4* __restrict
         T[k] = Tn;
         hit = true;
       }
-      if (__ballot(hit) != 0) {
+      const uint64_t hits = __ballot(hit);
+      if (hits != 0) {
         float* dst = a.rgrad + 12 * (int64_t)s.r[j];
+        if (__popcll(hits) <= 4) {
+          // few contributing lanes: each adds its own partials (no wave reduction)
+          if (hit) {
 #pragma unroll
-        for (int q = 0; q < 10; ++q) {
-          const float sum = gsk::wave_sum_last(acc[q]);
-          if (t.lane == 63) gsk::atomic_add_f32(dst + q, sum);
+            for (int q = 0; q < 10; ++q) gsk::atomic_add_f32(dst + q, acc[q]);
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 10; ++q) {
+            const float sum = gsk::wave_sum_last(acc[q]);
+            if (t.lane == 63) gsk::atomic_add_f32(dst + q, sum);
+          }
         }
       }
     }
@@ -399,14 +410,14 @@ template <int TW, int TH, int NW>
 __global__ __launch_bounds__(64 * NW) void k_count_pairs(const float4* __restrict__ rec,
                                                          const int32_t* __restrict__ vals,
                                                          const int2* __restrict__ range,
-                                                         const gs_camera* __restrict__ cams, int V, int n_tiles,
+                                                         const gs_camera* __restrict__ cams, int V, int n_tiles, const int32_t* __restrict__ order,
                                                          DevOpts op, unsigned long long* __restrict__ counts) {
   using G = Geo<TW, TH, NW>;
   constexpr int PPT = G::PPT, RPP = G::RPP;
   __shared__ Stage<G::BATCH, NW> s;
   TileCtx t;
   int tile;
-  if (!tile_setup<G>(cams, V, n_tiles, t, tile)) return;
+  if (!tile_setup<G>(cams, V, n_tiles, order, t, tile)) return;
   const int2 rg = range[tile];
   bool live[PPT];
   float fy[PPT], T[PPT];
@@ -474,44 +485,41 @@ __global__ __launch_bounds__(256) void k_count_valid(const float* __restrict__ t
 
 template <int TW, int TH, int NW>
 hipError_t launch_fwd(const gs_frame& f, const DevOpts& op, const gs_images& out, hipStream_t st) {
-  const int nb = ((f.n_tiles + 7) / 8) * 8;
   const int sorted = f.sort_passes & 1;
-  k_render_fwd<TW, TH, NW><<<nb, 64 * NW, 0, st>>>(reinterpret_cast<const float4*>(f.rec), f.vals[sorted],
-                                                   reinterpret_cast<const int2*>(f.tile_range), f.cams, f.n_views,
-                                                   f.n_tiles, op, out.rgb, out.depth, out.vis);
+  k_render_fwd<TW, TH, NW><<<f.n_tiles, 64 * NW, 0, st>>>(
+      reinterpret_cast<const float4*>(f.rec), f.vals[sorted], reinterpret_cast<const int2*>(f.tile_range), f.cams,
+      f.n_views, f.n_tiles, f.tile_order, op, out.rgb, out.depth, out.vis);
   return hipGetLastError();
 }
 
 template <int TW, int TH, int NW>
 hipError_t launch_bwd(const gs_frame& f, const DevOpts& op, bool have_fwd, bool loss, const BwdArgs& a,
                       hipStream_t st) {
-  const int nb = ((f.n_tiles + 7) / 8) * 8;
   const int sorted = f.sort_passes & 1;
   const auto* rec = reinterpret_cast<const float4*>(f.rec);
   const auto* rng = reinterpret_cast<const int2*>(f.tile_range);
-  const int bs = 64 * NW;
+  const int nb = f.n_tiles, bs = 64 * NW;
+  const int32_t* vals = f.vals[sorted];
   if (have_fwd && loss)
-    k_render_bwd<TW, TH, NW, true, true><<<nb, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, f.n_tiles,
-                                                            op, a);
+    k_render_bwd<TW, TH, NW, true, true><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb, f.tile_order, op, a);
   else if (have_fwd)
-    k_render_bwd<TW, TH, NW, true, false><<<nb, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views,
-                                                             f.n_tiles, op, a);
+    k_render_bwd<TW, TH, NW, true, false><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb, f.tile_order, op,
+                                                             a);
   else if (loss)
-    k_render_bwd<TW, TH, NW, false, true><<<nb, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views,
-                                                             f.n_tiles, op, a);
+    k_render_bwd<TW, TH, NW, false, true><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb, f.tile_order, op,
+                                                             a);
   else
-    k_render_bwd<TW, TH, NW, false, false><<<nb, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views,
-                                                              f.n_tiles, op, a);
+    k_render_bwd<TW, TH, NW, false, false><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb, f.tile_order,
+                                                              op, a);
   return hipGetLastError();
 }
 
 template <int TW, int TH, int NW>
 hipError_t launch_count(const gs_frame& f, const DevOpts& op, unsigned long long* counts, hipStream_t st) {
-  const int nb = ((f.n_tiles + 7) / 8) * 8;
   const int sorted = f.sort_passes & 1;
-  k_count_pairs<TW, TH, NW><<<nb, 64 * NW, 0, st>>>(reinterpret_cast<const float4*>(f.rec), f.vals[sorted],
-                                                    reinterpret_cast<const int2*>(f.tile_range), f.cams, f.n_views,
-                                                    f.n_tiles, op, counts);
+  k_count_pairs<TW, TH, NW><<<f.n_tiles, 64 * NW, 0, st>>>(
+      reinterpret_cast<const float4*>(f.rec), f.vals[sorted], reinterpret_cast<const int2*>(f.tile_range), f.cams,
+      f.n_views, f.n_tiles, f.tile_order, op, counts);
   return hipGetLastError();
 }
 

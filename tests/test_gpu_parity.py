@@ -396,3 +396,16 @@ def test_backward_identical_across_waves_per_tile(gpu_lib, nw):
         a, b = ref["grads"][k], out["grads"][k]
         rms = np.sqrt((a.astype(np.float64) ** 2).mean()) + 1e-30
         assert np.all(np.abs(a - b) <= 1e-5 * (np.abs(a) + rms)), k
+
+
+def test_tile_schedule_is_a_longest_first_permutation(gpu_lib):
+    sc = scenes.random_scene(1600, 3000, 150, 110, sh_degree=0, views=3, log_scale_mu=-2.2)
+    out = run_gpu(sc, targets=False)
+    fr = out["frame"]
+    nt = fr.f.n_tiles
+    order = B.frame_tensor(fr, "tile_order", nt, torch.int32).cpu().numpy()
+    rng_ = B.frame_tensor(fr, "tile_range", 2 * nt, torch.int32).view(-1, 2).cpu().numpy()
+    assert np.array_equal(np.sort(order), np.arange(nt))
+    lens = (rng_[:, 1] - rng_[:, 0])[order]
+    buckets = np.floor(np.log2(lens + 1.0))
+    assert np.all(np.diff(buckets) <= 0)

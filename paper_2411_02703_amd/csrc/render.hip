@@ -43,7 +43,25 @@ struct Stage {
   int32_t r[BATCH];
   uint8_t mask[BATCH];
   uint16_t list[NW][BATCH];
+  int4 wbox[NW][BATCH];  // per wave, in list order: pixel box as (x0, x1 - x0, y0, y1 - y0)
+  int cover[NW];         // pixels of the wave's sub-tile covered by the boxes of its list, summed
 };
+
+// Per-pixel "stream" walk, used for a wave's batch when the boxes of its records cover under a quarter of its
+// (record, pixel) pairs - the coarse pyramid levels, where a tile holds tens of thousands of sub-pixel
+// Gaussians.  Each lane tests the boxes of the next 64 records of its wave's list against its own pixel and
+// walks only the records that cover it, in list order.  It meets exactly the records that can contribute, in
+// the same order, so the result is the same bit for bit as the dense walk; it only skips work.
+__device__ __forceinline__ uint64_t cover_mask(const int4* __restrict__ boxes, int nc, int px, int py) {
+  uint64_t m = 0;
+#pragma unroll 8
+  for (int k = 0; k < nc; ++k) {
+    const int4 b = boxes[k];
+    const bool c = (unsigned)(px - b.x) <= (unsigned)b.y && (unsigned)(py - b.z) <= (unsigned)b.w;
+    m |= (uint64_t)c << k;
+  }
+  return m;
+}
 
 struct TileCtx {
   int view, W, H, tx0, ty0;  // view and tile origin (pixels)
@@ -109,9 +127,11 @@ __device__ __forceinline__ void unpack_rect(const float4& C, int& x0, int& x1, i
 // pixel rectangle meets its sub-tile.  Returns the length of this wave's list.  Ends with a barrier.
 template <class G, class S>
 __device__ __forceinline__ int stage_and_compact(S& s, const float4* __restrict__ rec, const int32_t* __restrict__ vals,
-                                                 int b0, int nb, const TileCtx& t) {
+                                                 int b0, int nb, const TileCtx& t, int& cover) {
   const int tid = threadIdx.x;
   uint32_t m = 0;
+  int4 box = make_int4(0, 0, 0, 0);
+  if (tid < G::SX * G::SY) s.cover[tid] = 0;
   if (tid < nb) {
     const int r = vals[b0 + tid];
     const float4 A = rec[3 * (int64_t)r], B = rec[3 * (int64_t)r + 1], C = rec[3 * (int64_t)r + 2];
@@ -121,6 +141,7 @@ __device__ __forceinline__ int stage_and_compact(S& s, const float4* __restrict_
     s.r[tid] = r;
     int x0, x1, y0, y1;
     unpack_rect(C, x0, x1, y0, y1);
+    box = make_int4(x0, x1 - x0, y0, y1 - y0);
 #pragma unroll
     for (int w = 0; w < G::SX * G::SY; ++w) {
       const int sx0 = t.tx0 + (w % G::SX) * G::SW, sy0 = t.ty0 + (w / G::SX) * G::SH;
@@ -129,6 +150,16 @@ __device__ __forceinline__ int stage_and_compact(S& s, const float4* __restrict_
   }
   s.mask[tid] = (uint8_t)m;
   __syncthreads();
+  if (m) {
+#pragma unroll
+    for (int w = 0; w < G::SX * G::SY; ++w) {
+      if (!((m >> w) & 1)) continue;
+      const int sx0 = t.tx0 + (w % G::SX) * G::SW, sy0 = t.ty0 + (w / G::SX) * G::SH;
+      const int ox = min(box.x + box.y, sx0 + G::SW - 1) - max(box.x, sx0) + 1;
+      const int oy = min(box.z + box.w, sy0 + G::SH - 1) - max(box.z, sy0) + 1;
+      atomicAdd(&s.cover[w], ox * oy);
+    }
+  }
   int cnt = 0;
   const uint64_t lt = gsk::lanemask_lt();
 #pragma unroll
@@ -136,11 +167,25 @@ __device__ __forceinline__ int stage_and_compact(S& s, const float4* __restrict_
     const int j = c * 64 + t.lane;
     const bool bit = (s.mask[j] >> t.wave) & 1;
     const uint64_t bal = __ballot(bit);
-    if (bit) s.list[t.wave][cnt + __popcll(bal & lt)] = (uint16_t)j;
+    if (bit) {
+      const int p = cnt + __popcll(bal & lt);
+      s.list[t.wave][p] = (uint16_t)j;
+      const float4 C = s.C[j];
+      int x0, x1, y0, y1;
+      unpack_rect(C, x0, x1, y0, y1);
+      s.wbox[t.wave][p] = make_int4(x0, x1 - x0, y0, y1 - y0);
+    }
     cnt += __popcll(bal);
   }
   __syncthreads();
+  cover = s.cover[t.wave];
   return cnt;
+}
+
+// Stream walk only where one lane holds one pixel and the wave's records cover under a quarter of its pairs.
+template <class G>
+__device__ __forceinline__ bool use_stream(int cnt, int cover) {
+  return G::PPT == 1 && cnt >= 64 && 4 * cover < G::SW * G::SH * cnt;
 }
 
 // Forward sweep of one tile for this lane's pixels (shared by the forward kernel and the fused backward).
@@ -160,36 +205,55 @@ __device__ __forceinline__ void forward_sweep(S& s, const float4* __restrict__ r
     T[k] = 1.f;
     Cr[k] = Cg[k] = Cb[k] = D[k] = Vs[k] = 0.f;
   }
+  // one (record, pixel) step of the front-to-back walk
+  auto step = [&](const float4& A, const float4& B, const float4& C, int k) {
+#pragma clang fp contract(off)
+    float alpha, Gv, dx, dy;
+    bool cl;
+    if (!eval_pair(A, B, fx, fy[k], op, alpha, Gv, cl, dx, dy)) return;
+    const float Tn = T[k] * (1.f - alpha);
+    if (Tn < op.t_min) {
+      live[k] = false;
+      return;
+    }
+    const float w = alpha * T[k];
+    Cr[k] = __builtin_fmaf(w, B.w, Cr[k]);
+    Cg[k] = __builtin_fmaf(w, C.x, Cg[k]);
+    Cb[k] = __builtin_fmaf(w, C.y, Cb[k]);
+    D[k] = __builtin_fmaf(w, A.z, D[k]);
+    Vs[k] = Vs[k] + w;
+    T[k] = Tn;
+  };
   for (int b0 = rg.x; b0 < rg.y; b0 += G::BATCH) {
     bool any = false;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) any |= live[k];
     if (!__syncthreads_or(any)) break;
     const int nb = min(G::BATCH, rg.y - b0);
-    const int cnt = stage_and_compact<G>(s, rec, vals, b0, nb, t);
+    int cover;
+    const int cnt = stage_and_compact<G>(s, rec, vals, b0, nb, t, cover);
     if (__ballot(any) == 0) continue;
-    for (int i = 0; i < cnt; ++i) {
-      const int j = s.list[t.wave][i];
-      const float4 A = s.A[j], B = s.B[j], C = s.C[j];
-#pragma unroll
-      for (int k = 0; k < PPT; ++k) {
-#pragma clang fp contract(off)
-        if (!live[k]) continue;
-        float alpha, Gv, dx, dy;
-        bool cl;
-        if (!eval_pair(A, B, fx, fy[k], op, alpha, Gv, cl, dx, dy)) continue;
-        const float Tn = T[k] * (1.f - alpha);
-        if (Tn < op.t_min) {
-          live[k] = false;
-          continue;
+    if (use_stream<G>(cnt, cover)) {
+      const int py = t.py0;
+      for (int c0 = 0; c0 < cnt; c0 += 64) {
+        uint64_t m = live[0] ? cover_mask(&s.wbox[t.wave][c0], min(64, cnt - c0), t.px, py) : 0ull;
+        while (__ballot(m != 0)) {
+          if (m) {
+            const int k = __builtin_ctzll(m);
+            m &= m - 1;
+            const int j = s.list[t.wave][c0 + k];
+            step(s.A[j], s.B[j], s.C[j], 0);
+            if (!live[0]) m = 0;
+          }
         }
-        const float w = alpha * T[k];
-        Cr[k] = __builtin_fmaf(w, B.w, Cr[k]);
-        Cg[k] = __builtin_fmaf(w, C.x, Cg[k]);
-        Cb[k] = __builtin_fmaf(w, C.y, Cb[k]);
-        D[k] = __builtin_fmaf(w, A.z, D[k]);
-        Vs[k] = Vs[k] + w;
-        T[k] = Tn;
+      }
+    } else {
+      for (int i = 0; i < cnt; ++i) {
+        const int j = s.list[t.wave][i];
+        const float4 A = s.A[j], B = s.B[j], C = s.C[j];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+          if (live[k]) step(A, B, C, k);
       }
     }
   }
@@ -337,68 +401,116 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const float4* __restrict
     T[k] = 1.f;
     Pp[k] = 0.f;
   }
+  // per-record gradient partials of the stream walk, summed in LDS and flushed once per batch
+  __shared__ float gacc[G::BATCH][10];
+  __shared__ int gtouch[G::BATCH];
+  for (int i = threadIdx.x; i < G::BATCH; i += 64 * NW) {
+    gtouch[i] = 0;
+#pragma unroll
+    for (int q = 0; q < 10; ++q) gacc[i][q] = 0.f;
+  }
+  // one (record, pixel) step of the front-to-back walk: returns true if the pair contributed, with its
+  // 10 partial derivatives in acc (added, not overwritten)
+  auto step = [&](const float4& A, const float4& B, const float4& C, int k, float* acc) -> bool {
+    float alpha, Gv, dx, dy;
+    bool cl;
+    if (!eval_pair(A, B, fx, fy[k], op, alpha, Gv, cl, dx, dy)) return false;
+    const float Tn = T[k] * (1.f - alpha);
+    if (Tn < op.t_min) {
+      live[k] = false;
+      return false;
+    }
+    const float w = alpha * T[k];
+    const float qv = gr[k] * B.w + gg[k] * C.x + gb[k] * C.y + gd[k] * A.z + gv[k];
+    Pp[k] += w * qv;
+    const float dalpha = T[k] * qv - (S[k] - Pp[k]) * __builtin_amdgcn_rcpf(1.f - alpha);
+    acc[6] += w * gr[k];
+    acc[7] += w * gg[k];
+    acc[8] += w * gb[k];
+    acc[9] += w * gd[k];
+    if (!cl) {
+      acc[5] += dalpha * Gv;
+      const float dq = dalpha * alpha;
+      acc[2] += -0.5f * dx * dx * dq;
+      acc[3] += -dx * dy * dq;
+      acc[4] += -0.5f * dy * dy * dq;
+      acc[0] += -(B.x * dx + B.y * dy) * dq;
+      acc[1] += -(B.z * dy + B.y * dx) * dq;
+    }
+    T[k] = Tn;
+    return true;
+  };
   for (int b0 = rg.x; b0 < rg.y; b0 += G::BATCH) {
     bool any = false;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) any |= live[k];
     if (!__syncthreads_or(any)) break;
     const int nb = min(G::BATCH, rg.y - b0);
-    const int cnt = stage_and_compact<G>(s, rec, vals, b0, nb, t);
-    if (__ballot(any) == 0) continue;
-    for (int i = 0; i < cnt; ++i) {
-      const int j = s.list[t.wave][i];
-      const float4 A = s.A[j], B = s.B[j], C = s.C[j];
-      float acc[10];
+    int cover;
+    const int cnt = stage_and_compact<G>(s, rec, vals, b0, nb, t, cover);
+    if (__ballot(any) != 0) {
+      if (use_stream<G>(cnt, cover)) {
+        for (int c0 = 0; c0 < cnt; c0 += 64) {
+          uint64_t m = live[0] ? cover_mask(&s.wbox[t.wave][c0], min(64, cnt - c0), t.px, t.py0) : 0ull;
+          while (__ballot(m != 0)) {
+            if (m) {
+              const int kk = __builtin_ctzll(m);
+              m &= m - 1;
+              const int j = s.list[t.wave][c0 + kk];
+              float acc[10];
 #pragma unroll
-      for (int q = 0; q < 10; ++q) acc[q] = 0.f;
-      bool hit = false;
+              for (int q = 0; q < 10; ++q) acc[q] = 0.f;
+              if (step(s.A[j], s.B[j], s.C[j], 0, acc)) {
 #pragma unroll
-      for (int k = 0; k < PPT; ++k) {
-        if (!live[k]) continue;
-        float alpha, Gv, dx, dy;
-        bool cl;
-        if (!eval_pair(A, B, fx, fy[k], op, alpha, Gv, cl, dx, dy)) continue;
-        const float Tn = T[k] * (1.f - alpha);
-        if (Tn < op.t_min) {
-          live[k] = false;
-          continue;
+                for (int q = 0; q < 10; ++q) atomicAdd(&gacc[j][q], acc[q]);
+                gtouch[j] = 1;
+              }
+              if (!live[0]) m = 0;
+            }
+          }
         }
-        const float w = alpha * T[k];
-        const float qv = gr[k] * B.w + gg[k] * C.x + gb[k] * C.y + gd[k] * A.z + gv[k];
-        Pp[k] += w * qv;
-        const float dalpha = T[k] * qv - (S[k] - Pp[k]) * __builtin_amdgcn_rcpf(1.f - alpha);
-        acc[6] += w * gr[k];
-        acc[7] += w * gg[k];
-        acc[8] += w * gb[k];
-        acc[9] += w * gd[k];
-        if (!cl) {
-          acc[5] += dalpha * Gv;
-          const float dq = dalpha * alpha;
-          acc[2] += -0.5f * dx * dx * dq;
-          acc[3] += -dx * dy * dq;
-          acc[4] += -0.5f * dy * dy * dq;
-          acc[0] += -(B.x * dx + B.y * dy) * dq;
-          acc[1] += -(B.z * dy + B.y * dx) * dq;
+      } else {
+        for (int i = 0; i < cnt; ++i) {
+          const int j = s.list[t.wave][i];
+          const float4 A = s.A[j], B = s.B[j], C = s.C[j];
+          float acc[10];
+#pragma unroll
+          for (int q = 0; q < 10; ++q) acc[q] = 0.f;
+          bool hit = false;
+#pragma unroll
+          for (int k = 0; k < PPT; ++k)
+            if (live[k]) hit |= step(A, B, C, k, acc);
+          const uint64_t hits = __ballot(hit);
+          if (hits != 0) {
+            float* dst = a.rgrad + 12 * (int64_t)s.r[j];
+            if (__popcll(hits) <= 4) {
+              // few contributing lanes: each adds its own partials (no wave reduction)
+              if (hit) {
+#pragma unroll
+                for (int q = 0; q < 10; ++q) gsk::atomic_add_f32(dst + q, acc[q]);
+              }
+            } else {
+#pragma unroll
+              for (int q = 0; q < 10; ++q) {
+                const float sum = gsk::wave_sum_last(acc[q]);
+                if (t.lane == 63) gsk::atomic_add_f32(dst + q, sum);
+              }
+            }
+          }
         }
-        T[k] = Tn;
-        hit = true;
       }
-      const uint64_t hits = __ballot(hit);
-      if (hits != 0) {
-        float* dst = a.rgrad + 12 * (int64_t)s.r[j];
-        if (__popcll(hits) <= 4) {
-          // few contributing lanes: each adds its own partials (no wave reduction)
-          if (hit) {
+    }
+    // flush the LDS partials of this batch (records touched by a stream walk)
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += 64 * NW) {
+      if (gtouch[i]) {
+        float* dst = a.rgrad + 12 * (int64_t)s.r[i];
 #pragma unroll
-            for (int q = 0; q < 10; ++q) gsk::atomic_add_f32(dst + q, acc[q]);
-          }
-        } else {
-#pragma unroll
-          for (int q = 0; q < 10; ++q) {
-            const float sum = gsk::wave_sum_last(acc[q]);
-            if (t.lane == 63) gsk::atomic_add_f32(dst + q, sum);
-          }
+        for (int q = 0; q < 10; ++q) {
+          gsk::atomic_add_f32(dst + q, gacc[i][q]);
+          gacc[i][q] = 0.f;
         }
+        gtouch[i] = 0;
       }
     }
   }
@@ -436,7 +548,8 @@ __global__ __launch_bounds__(64 * NW) void k_count_pairs(const float4* __restric
     for (int k = 0; k < PPT; ++k) any |= live[k];
     if (!__syncthreads_or(any)) break;
     const int nb = min(G::BATCH, rg.y - b0);
-    const int cnt = stage_and_compact<G>(s, rec, vals, b0, nb, t);
+    int cover;
+    const int cnt = stage_and_compact<G>(s, rec, vals, b0, nb, t, cover);
     for (int i = 0; i < cnt; ++i) {
       const int j = s.list[t.wave][i];
       const float4 A = s.A[j], B = s.B[j], C = s.C[j];

@@ -409,3 +409,37 @@ def test_tile_schedule_is_a_longest_first_permutation(gpu_lib):
     lens = (rng_[:, 1] - rng_[:, 0])[order]
     buckets = np.floor(np.log2(lens + 1.0))
     assert np.all(np.diff(buckets) <= 0)
+
+
+def _subpixel_scene(seed, n=20000, W=64, H=48, views=1, deg=0):
+    # many sub-pixel Gaussians per tile: the case the per-pixel stream walk is for
+    return scenes.random_scene(seed, n, W, H, sh_degree=deg, views=views, log_scale_mu=-5.0, log_scale_sigma=0.3,
+                               opacity_sigma=0.5, depth_fraction=0.5)
+
+
+def test_stream_walk_matches_dense_walk_and_oracle(gpu_lib):
+    sc = _subpixel_scene(1700, views=2)
+    dense = run_gpu(sc, tile=(16, 16), nw=1, targets=False)  # four pixels per lane: always the dense walk
+    for tile, nw in [((16, 16), 4), ((8, 8), 1), ((32, 8), 4), ((16, 8), 2)]:
+        o = run_gpu(sc, tile=tile, nw=nw, targets=False)
+        for k in ("rgb", "depth", "vis"):
+            assert np.array_equal(dense[k], o[k]), (tile, nw, k)
+    dense["cams"] = sc.cams
+    ref = oracle.forward(32, sc.params(), 0, sc.cams)
+    check_images(dense, ref, ref["near"], "sub-pixel fwd")
+    ev, co = B.gs_count_pairs(dense["frame"])
+    log("sub-pixel scene: instances", dense["n_inst"], "evaluated", ev, "contributing", co)
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_stream_walk_backward_matches_fp64_oracle(gpu_lib, fused):
+    sc = _subpixel_scene(1800, n=12000, views=2, deg=1)
+    out = run_gpu(sc, targets=True, fused=fused, tile=(16, 16), nw=4)
+    L, ref, exc, nn, _ = oracle.backward(64, sc.params(), 1, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
+    np.testing.assert_allclose(out["loss"], L, rtol=1e-5)
+    check_grads(out["grads"], ref, exc, f"sub-pixel fused={fused}", nn, sc.total_pixels)
+    dense = run_gpu(sc, targets=True, fused=fused, tile=(16, 16), nw=1)
+    for k in dense["grads"]:
+        a, b = dense["grads"][k], out["grads"][k]
+        rms = np.sqrt((a.astype(np.float64) ** 2).mean()) + 1e-30
+        assert np.all(np.abs(a - b) <= 1e-5 * (np.abs(a) + rms)), k

@@ -59,8 +59,10 @@ def measure(sc, steps, warmup, plain_steps, do_plain, tile=None):
         tile, _ = autotune.tune_batched(
             lambda o: BatchedStep(GaussianModel(sc.params(), sc.sh_degree), sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=o),
             sc.n, sc.cams, sc.sh_degree, log=log)
-    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], waves_per_tile=tile[2])
-    log(f"  configuration: {tile[0]}x{tile[1]} tiles, {tile[2]} waves per tile")
+    if len(tile) < 4:
+        tile = (*tile, 0.0)
+    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], waves_per_tile=tile[2], stream_cover=tile[3])
+    log(f"  configuration: {tile[0]}x{tile[1]} tiles, {tile[2]} waves per tile, stream cover {tile[3]}")
     model = GaussianModel(sc.params(), sc.sh_degree)
     t0 = time.time()
     bat = BatchedStep(model, sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=opts)
@@ -131,7 +133,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-cfg3", action="store_true")
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count (smaller trial runs)")
-    ap.add_argument("--tile", type=str, default=None, help="tile_w,tile_h,waves (skips the autotuner)")
+    ap.add_argument("--tile", type=str, default=None,
+                    help="tile_w,tile_h,waves[,stream_cover] (skips the autotuner)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md on sharding by view).",
@@ -148,7 +151,10 @@ def main():
     t0 = time.time()
     sc4 = scenes.config(4, n=args.n)
     log(f"cfg4 scene: {sc4.n} Gaussians, {len(sc4.cams)} views, {sc4.total_pixels} px ({time.time() - t0:.1f}s)")
-    tile = tuple(int(x) for x in args.tile.split(",")) if args.tile else None
+    tile = None
+    if args.tile:
+        parts = args.tile.split(",")
+        tile = tuple(int(x) for x in parts[:3]) + tuple(float(x) for x in parts[3:])
     r4 = measure(sc4, args.steps, args.warmup, args.plain_steps, not args.no_plain, tile)
     dk = dominant_kernel(r4, args.steps)
     log(f"  fused compositing kernel: {dk['ms']:.3f} ms, {dk['evaluated']} evaluated / {dk['contributing']} "
@@ -170,7 +176,8 @@ def main():
                                 "640x512..1280x1024 x 3-level pyramid = 24 views, L1 RGB + 0.1 L1 depth, Adam; "
                                 "one HIP-graph replay per step"),
                    "gaussians": sc4.n, "views": len(sc4.cams), "pixels": sc4.total_pixels,
-                   "instances": r4["n_instances"], "tile": list(r4["tile"][:2]), "waves_per_tile": r4["tile"][2]},
+                   "instances": r4["n_instances"], "tile": list(r4["tile"][:2]), "waves_per_tile": r4["tile"][2],
+                   "stream_cover": r4["tile"][3]},
     }
     if "plain_ms" in r4:
         out["plain"] = {"value": round(1000.0 / r4["plain_ms"], 3), "ms_per_step": round(r4["plain_ms"], 4),

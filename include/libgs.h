@@ -89,7 +89,10 @@ typedef struct gs_opts {
   float bg[3];            /* background colour, 0 */
   int32_t waves_per_tile; /* wave64s per tile workgroup, each owning a sub-tile: 1, 2 or 4 (0 = 4 where the
                              tile shape allows it, else 2, else 1); results are identical for every choice */
-  int32_t reserved[2];
+  float stream_cover;     /* a wave walks its staged records per pixel (only those whose box covers the pixel)
+                             when their boxes cover less than this fraction of its (record, pixel) pairs and it
+                             holds one pixel per lane; 0 = default 0.25, < 0 = never; results are identical */
+  int32_t reserved[1];
 } gs_opts;
 
 /* Gaussian parameters, or gradients / Adam moments in the same layout.  Row-major float32:

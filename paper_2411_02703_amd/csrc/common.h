@@ -15,6 +15,7 @@ struct DevOpts {
   float near_z, lowpass, alpha_min, alpha_max, t_min;
   float bg[3];
   int tile_w, tile_h;
+  float stream_cover;
 };
 
 inline DevOpts dev_opts(const gs_opts& o) {
@@ -29,6 +30,7 @@ inline DevOpts dev_opts(const gs_opts& o) {
   d.bg[2] = o.bg[2];
   d.tile_w = o.tile_w;
   d.tile_h = o.tile_h;
+  d.stream_cover = o.stream_cover == 0.f ? 0.25f : o.stream_cover;
   return d;
 }
 

@@ -182,10 +182,11 @@ __device__ __forceinline__ int stage_and_compact(S& s, const float4* __restrict_
   return cnt;
 }
 
-// Stream walk only where one lane holds one pixel and the wave's records cover under a quarter of its pairs.
+// Stream walk only where one lane holds one pixel and the wave's records cover under a fraction (default a
+// quarter) of its pairs.
 template <class G>
-__device__ __forceinline__ bool use_stream(int cnt, int cover) {
-  return G::PPT == 1 && cnt >= 64 && 4 * cover < G::SW * G::SH * cnt;
+__device__ __forceinline__ bool use_stream(int cnt, int cover, const DevOpts& op) {
+  return G::PPT == 1 && cnt >= 64 && (float)cover < op.stream_cover * (float)(G::SW * G::SH * cnt);
 }
 
 // Forward sweep of one tile for this lane's pixels (shared by the forward kernel and the fused backward).
@@ -233,24 +234,36 @@ __device__ __forceinline__ void forward_sweep(S& s, const float4* __restrict__ r
     int cover;
     const int cnt = stage_and_compact<G>(s, rec, vals, b0, nb, t, cover);
     if (__ballot(any) == 0) continue;
-    if (use_stream<G>(cnt, cover)) {
+    if (use_stream<G>(cnt, cover, op)) {
       const int py = t.py0;
       for (int c0 = 0; c0 < cnt; c0 += 64) {
         uint64_t m = live[0] ? cover_mask(&s.wbox[t.wave][c0], min(64, cnt - c0), t.px, py) : 0ull;
+        // the next covered record is fetched while the current one is composited
+        int jn = s.list[t.wave][c0 + (m ? __builtin_ctzll(m) : 0)];
+        float4 An = s.A[jn], Bn = s.B[jn], Cn = s.C[jn];
         while (__ballot(m != 0)) {
           if (m) {
-            const int k = __builtin_ctzll(m);
+            const float4 A = An, B = Bn, C = Cn;
             m &= m - 1;
-            const int j = s.list[t.wave][c0 + k];
-            step(s.A[j], s.B[j], s.C[j], 0);
+            jn = s.list[t.wave][c0 + (m ? __builtin_ctzll(m) : 0)];
+            An = s.A[jn];
+            Bn = s.B[jn];
+            Cn = s.C[jn];
+            step(A, B, C, 0);
             if (!live[0]) m = 0;
           }
         }
       }
     } else {
+      // records i + 1 (data) and i + 2 (index) are fetched while record i is composited
+      float4 An = s.A[s.list[t.wave][0]], Bn = s.B[s.list[t.wave][0]], Cn = s.C[s.list[t.wave][0]];
+      int jn2 = s.list[t.wave][cnt > 1 ? 1 : 0];
       for (int i = 0; i < cnt; ++i) {
-        const int j = s.list[t.wave][i];
-        const float4 A = s.A[j], B = s.B[j], C = s.C[j];
+        const float4 A = An, B = Bn, C = Cn;
+        An = s.A[jn2];
+        Bn = s.B[jn2];
+        Cn = s.C[jn2];
+        jn2 = s.list[t.wave][i + 2 < cnt ? i + 2 : 0];
 #pragma unroll
         for (int k = 0; k < PPT; ++k)
           if (live[k]) step(A, B, C, k);
@@ -449,18 +462,24 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const float4* __restrict
     int cover;
     const int cnt = stage_and_compact<G>(s, rec, vals, b0, nb, t, cover);
     if (__ballot(any) != 0) {
-      if (use_stream<G>(cnt, cover)) {
+      if (use_stream<G>(cnt, cover, op)) {
         for (int c0 = 0; c0 < cnt; c0 += 64) {
           uint64_t m = live[0] ? cover_mask(&s.wbox[t.wave][c0], min(64, cnt - c0), t.px, t.py0) : 0ull;
+          int jn = s.list[t.wave][c0 + (m ? __builtin_ctzll(m) : 0)];
+          float4 An = s.A[jn], Bn = s.B[jn], Cn = s.C[jn];
           while (__ballot(m != 0)) {
             if (m) {
-              const int kk = __builtin_ctzll(m);
+              const float4 A = An, B = Bn, C = Cn;
+              const int j = jn;
               m &= m - 1;
-              const int j = s.list[t.wave][c0 + kk];
+              jn = s.list[t.wave][c0 + (m ? __builtin_ctzll(m) : 0)];
+              An = s.A[jn];
+              Bn = s.B[jn];
+              Cn = s.C[jn];
               float acc[10];
 #pragma unroll
               for (int q = 0; q < 10; ++q) acc[q] = 0.f;
-              if (step(s.A[j], s.B[j], s.C[j], 0, acc)) {
+              if (step(A, B, C, 0, acc)) {
 #pragma unroll
                 for (int q = 0; q < 10; ++q) atomicAdd(&gacc[j][q], acc[q]);
                 gtouch[j] = 1;
@@ -470,9 +489,17 @@ __global__ __launch_bounds__(64 * NW) void k_render_bwd(const float4* __restrict
           }
         }
       } else {
+        int jn = s.list[t.wave][0];
+        float4 An = s.A[jn], Bn = s.B[jn], Cn = s.C[jn];
+        int jn2 = s.list[t.wave][cnt > 1 ? 1 : 0];
         for (int i = 0; i < cnt; ++i) {
-          const int j = s.list[t.wave][i];
-          const float4 A = s.A[j], B = s.B[j], C = s.C[j];
+          const float4 A = An, B = Bn, C = Cn;
+          const int j = jn;
+          jn = jn2;
+          An = s.A[jn];
+          Bn = s.B[jn];
+          Cn = s.C[jn];
+          jn2 = s.list[t.wave][i + 2 < cnt ? i + 2 : 0];
           float acc[10];
 #pragma unroll
           for (int q = 0; q < 10; ++q) acc[q] = 0.f;

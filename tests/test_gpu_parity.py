@@ -438,8 +438,11 @@ def test_stream_walk_backward_matches_fp64_oracle(gpu_lib, fused):
     L, ref, exc, nn, _ = oracle.backward(64, sc.params(), 1, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
     np.testing.assert_allclose(out["loss"], L, rtol=1e-5)
     check_grads(out["grads"], ref, exc, f"sub-pixel fused={fused}", nn, sc.total_pixels)
+    # the stream walk sums partials in another order; rotation gradients of near-isotropic sub-pixel
+    # Gaussians are ill-conditioned in FP32, hence 1e-4 here (both sides are within 1e-3 of FP64 above)
     dense = run_gpu(sc, targets=True, fused=fused, tile=(16, 16), nw=1)
     for k in dense["grads"]:
         a, b = dense["grads"][k], out["grads"][k]
         rms = np.sqrt((a.astype(np.float64) ** 2).mean()) + 1e-30
-        assert np.all(np.abs(a - b) <= 1e-5 * (np.abs(a) + rms)), k
+        err = np.abs(a - b) / (np.abs(a) + rms)
+        assert err.max() <= 1e-4, (k, float(err.max()))

@@ -59,10 +59,10 @@ def measure(sc, steps, warmup, plain_steps, do_plain, tile=None):
         tile, _ = autotune.tune_batched(
             lambda o: BatchedStep(GaussianModel(sc.params(), sc.sh_degree), sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=o),
             sc.n, sc.cams, sc.sh_degree, log=log)
-    if len(tile) < 4:
-        tile = (*tile, 0.0)
-    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], waves_per_tile=tile[2], stream_cover=tile[3])
-    log(f"  configuration: {tile[0]}x{tile[1]} tiles, {tile[2]} waves per tile, stream cover {tile[3]}")
+    tile = tuple(tile) + (1, 0)[len(tile) - 2:] if len(tile) < 4 else tuple(tile)
+    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], batch_depth=tile[2], scatter_max=tile[3])
+    log(f"  configuration: {tile[0]}x{tile[1]} tiles, {tile[2]} records per thread per round, "
+        f"scatter_max {tile[3]}")
     model = GaussianModel(sc.params(), sc.sh_degree)
     t0 = time.time()
     bat = BatchedStep(model, sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=opts)
@@ -134,7 +134,10 @@ def main():
     ap.add_argument("--no-cfg3", action="store_true")
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count (smaller trial runs)")
     ap.add_argument("--tile", type=str, default=None,
-                    help="tile_w,tile_h,waves[,stream_cover] (skips the autotuner)")
+                    help="tile_w,tile_h,batch_depth,scatter_max (skips the autotuner)")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB three times (the known-size kernel that scales "
+                         "FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md on sharding by view).",
@@ -154,11 +157,19 @@ def main():
     tile = None
     if args.tile:
         parts = args.tile.split(",")
-        tile = tuple(int(x) for x in parts[:3]) + tuple(float(x) for x in parts[3:])
+        tile = tuple(int(x) for x in parts)
     r4 = measure(sc4, args.steps, args.warmup, args.plain_steps, not args.no_plain, tile)
     dk = dominant_kernel(r4, args.steps)
     log(f"  fused compositing kernel: {dk['ms']:.3f} ms, {dk['evaluated']} evaluated / {dk['contributing']} "
         f"contributing pairs, {dk['achieved'] / 1e12:.2f} T lane-ops/s")
+    if args.copy_calib > 0:
+        src = torch.ones(args.copy_calib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"  copy calibration: 3 x {args.copy_calib} MiB device copies")
+        del src, dst
     out = {
         "metric": METRIC,
         "value": round(1000.0 / r4["ms"], 3),
@@ -176,8 +187,8 @@ def main():
                                 "640x512..1280x1024 x 3-level pyramid = 24 views, L1 RGB + 0.1 L1 depth, Adam; "
                                 "one HIP-graph replay per step"),
                    "gaussians": sc4.n, "views": len(sc4.cams), "pixels": sc4.total_pixels,
-                   "instances": r4["n_instances"], "tile": list(r4["tile"][:2]), "waves_per_tile": r4["tile"][2],
-                   "stream_cover": r4["tile"][3]},
+                   "instances": r4["n_instances"], "tile": list(r4["tile"][:2]), "batch_depth": r4["tile"][2],
+                   "scatter_max": r4["tile"][3]},
     }
     if "plain_ms" in r4:
         out["plain"] = {"value": round(1000.0 / r4["plain_ms"], 3), "ms_per_step": round(r4["plain_ms"], 4),
@@ -185,7 +196,7 @@ def main():
         out["batched_over_plain"] = round(r4["plain_ms"] / r4["ms"], 3)
     out["roofline"] = {"bound": "alu", "achieved": round(dk["achieved"] / 1e12, 3), "peak": round(ALU_PEAK / 1e12, 3),
                        "unit": "T lane-op/s", "frac": round(dk["achieved"] / ALU_PEAK, 4), "traffic": None,
-                       "kernel": (f"k_render_bwd<{r4['tile'][0]},{r4['tile'][1]},{r4['tile'][2]} waves,fused loss> "
+                       "kernel": (f"k_render_bwd<{r4['tile'][0]},{r4['tile'][1]},depth {r4['tile'][2]},fused loss> "
                                   "(forward sweep + loss + backward sweep)"),
                        "kernel_ms": round(dk["ms"], 4), "pairs_evaluated": dk["evaluated"],
                        "pairs_contributing": dk["contributing"]}

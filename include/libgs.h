@@ -79,7 +79,7 @@ typedef struct gs_camera {
 } gs_camera;
 
 typedef struct gs_opts {
-  int32_t tile_w, tile_h; /* 16x16 (default), 8x8, 16x8, 32x8 or 32x16 */
+  int32_t tile_w, tile_h; /* 16x16 (default), 8x8, 16x8 or 32x8; one wave64 per 8x8 sub-tile */
   float near_z;           /* 0.2 */
   float guard;            /* 1.3 */
   float lowpass;          /* 0.3 px^2 */
@@ -87,11 +87,17 @@ typedef struct gs_opts {
   float alpha_max;        /* 0.99 */
   float t_min;            /* 1e-4 */
   float bg[3];            /* background colour, 0 */
-  int32_t waves_per_tile; /* wave64s per tile workgroup, each owning a sub-tile: 1, 2 or 4 (0 = 4 where the
-                             tile shape allows it, else 2, else 1); results are identical for every choice */
-  float stream_cover;     /* a wave walks its staged records per pixel (only those whose box covers the pixel)
-                             when their boxes cover less than this fraction of its (record, pixel) pairs and it
-                             holds one pixel per lane; 0 = default 0.25, < 0 = never; results are identical */
+  int32_t waves_per_tile; /* 0 or tile_w * tile_h / 64 (fixed by the tile shape) */
+  int32_t scatter_max;    /* a staged record whose pixel box meets at most this many pixels of a sub-tile is
+                             handed to those pixels only; a larger one is walked by every lane of the sub-tile.
+                             0 = default 16, < 0 = never hand out per pixel.  Results are identical for every
+                             value (a record is skipped only where its box misses the pixel) */
+  int32_t batch_depth;    /* records staged per thread per round: 1 or 2 (0 = 1); results identical */
+  int32_t seg_len;        /* fused backward (gs_render_bwd without forward images): a tile list longer than
+                             this is split into depth segments of this many records, composited by separate
+                             workgroups and joined per pixel (transmittance products, then prefix sums); 0 =
+                             default 2048, < 0 = never split.  Fixed per frame by gs_frame_init.  Results agree
+                             with the unsplit walk up to FP32 rounding of the transmittance product */
   int32_t reserved[1];
 } gs_opts;
 
@@ -121,6 +127,10 @@ typedef struct gs_frame {
   int32_t key_bits;     /* 32 depth bits + tile bits */
   int32_t sort_passes;  /* 8-bit LSD passes */
   int32_t tile_w, tile_h;
+  int32_t seg_len;      /* depth-segment length of the fused backward (0: lists are never split) */
+  int32_t seg_cap;      /* capacity of segment slots: 2 * capacity / seg_len + 2 */
+  int32_t long_cap;     /* capacity of split tiles: capacity / seg_len + 1 */
+  int32_t item_cap;     /* work items of the fused backward: n_tiles + seg_cap */
   const gs_camera* cams;  /* device copy of the planned cameras (caller-owned) */
   void* block;
   size_t bytes;
@@ -137,7 +147,14 @@ typedef struct gs_frame {
   int32_t* tile_range;  /* [n_tiles][2]: [begin, end) of each tile's instances in the sorted list */
   int32_t* tile_order;  /* [n_tiles]: tiles by descending list length (the compositing schedule) */
   int32_t* counters;    /* [256]: [0] instance count, [1] flags, [2..2+n_views) valid depth pixels per view,
-                           [128..192) tile-length bucket counts and offsets */
+                           [128..192) tile-length bucket counts and offsets, [192] work items,
+                           [193] segment slots of split tiles, [194] split tiles */
+  int32_t* seg_count;   /* [n_tiles]: segments of the tile at each schedule position */
+  int32_t* seg_first;   /* [n_tiles]: exclusive scan of seg_count = first work item of that tile */
+  int32_t* items;       /* [item_cap][4]: work items of the fused backward, split tiles first:
+                           {tile, segment, first slot of the tile or -1, schedule position} */
+  float* seg;           /* [seg_cap][6][tile_w * tile_h]: per-segment pixel state of split tiles */
+  float* split;         /* [long_cap][12][tile_w * tile_h]: per-pixel stop state and upstream gradient */
   float* loss;          /* [1]: loss value written by gs_render_bwd in loss mode */
   int32_t* scratch;     /* sort histograms and scan partials */
   size_t scratch_ints;

@@ -1,4 +1,5 @@
-"""Pick the tile shape and waves per tile of the batched step by measured replay time.
+"""Pick the tile shape, records staged per thread and per-pixel hand-out threshold of the batched step by
+measured replay time.
 
 Every candidate computes the same forward bit for bit (the per-pair arithmetic is fixed and records are
 culled only where they provably do not contribute) and the same gradients up to the order of the float
@@ -17,10 +18,10 @@ import torch
 
 from . import binding as B
 
-# (tile_w, tile_h, waves per tile, stream-walk coverage threshold)
-CANDIDATES: List[Tuple[int, int, int, float]] = [(16, 16, 4, 0.25), (16, 16, 4, -1.0), (16, 16, 4, 0.5),
-                                                 (16, 16, 2, 0.25), (16, 16, 1, 0.25), (32, 16, 4, 0.25),
-                                                 (32, 8, 4, 0.25), (16, 8, 2, 0.25), (8, 8, 1, 0.25)]
+# (tile_w, tile_h, records staged per thread, largest sub-tile overlap handed out per pixel)
+CANDIDATES: List[Tuple[int, int, int, int]] = [(16, 16, 1, 16), (16, 16, 2, 16), (16, 16, 1, 8), (16, 16, 1, 32),
+                                               (16, 16, 1, -1), (8, 8, 1, 16), (8, 8, 2, 16), (16, 8, 1, 16),
+                                               (32, 8, 1, 16)]
 
 _CACHE = os.environ.get("GS_AUTOTUNE_CACHE",
                         os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), ".scene_cache",
@@ -52,15 +53,15 @@ def _store(d: Dict[str, list]) -> None:
 
 
 def tune_batched(make_step, n: int, cams: Sequence, sh_degree: int, replays: int = 3,
-                 candidates: Sequence[Tuple[int, int, int, float]] = CANDIDATES, use_cache: bool = True, log=None):
-    """make_step(opts) -> a BatchedStep.  Returns (best (tile_w, tile_h, waves, stream), {candidate: ms})."""
+                 candidates: Sequence[Tuple[int, int, int, int]] = CANDIDATES, use_cache: bool = True, log=None):
+    """make_step(opts) -> a BatchedStep.  Returns (best (tile_w, tile_h, depth, scatter_max), {candidate: ms})."""
     key = cache_key(n, cams, sh_degree)
     cache = _load() if use_cache else {}
     if key in cache:
         return tuple(cache[key][0]), {}
     times = {}
-    for tw, th, nw, sc in candidates:
-        opts = B.default_opts(tile_w=tw, tile_h=th, waves_per_tile=nw, stream_cover=sc)
+    for tw, th, dp, sm in candidates:
+        opts = B.default_opts(tile_w=tw, tile_h=th, batch_depth=dp, scatter_max=sm)
         step = make_step(opts)
         step.capture()
         step.run()
@@ -74,13 +75,13 @@ def tune_batched(make_step, n: int, cams: Sequence, sh_degree: int, replays: int
         ms = s.elapsed_time(e) / replays
         if step.overflowed():
             ms = float("inf")
-        times[(tw, th, nw, sc)] = ms
+        times[(tw, th, dp, sm)] = ms
         if log:
-            log(f"  autotune {tw}x{th} waves {nw} stream {sc}: {ms:.3f} ms")
+            log(f"  autotune {tw}x{th} depth {dp} scatter_max {sm}: {ms:.3f} ms")
         del step
         torch.cuda.empty_cache()
     best = min(times, key=times.get)
     if use_cache:
-        cache[key] = [list(best), {f"{a}x{b}x{c}/{d}": v for (a, b, c, d), v in times.items()}]
+        cache[key] = [list(best), {f"{a}x{b}/d{c}/s{d}": v for (a, b, c, d), v in times.items()}]
         _store(cache)
     return best, times

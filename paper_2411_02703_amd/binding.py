@@ -35,7 +35,7 @@ class gs_camera(ctypes.Structure):
 class gs_opts(ctypes.Structure):
     _fields_ = [("tile_w", c_i32), ("tile_h", c_i32), ("near_z", c_f), ("guard", c_f), ("lowpass", c_f),
                 ("alpha_min", c_f), ("alpha_max", c_f), ("t_min", c_f), ("bg", c_f * 3), ("waves_per_tile", c_i32),
-                ("stream_cover", c_f), ("reserved", c_i32 * 1)]
+                ("scatter_max", c_i32), ("batch_depth", c_i32), ("seg_len", c_i32), ("reserved", c_i32 * 1)]
 
 
 class gs_params(ctypes.Structure):
@@ -46,10 +46,12 @@ class gs_params(ctypes.Structure):
 class gs_frame(ctypes.Structure):
     _fields_ = [("n", c_i64), ("n_views", c_i32), ("n_tiles", c_i32), ("n_pixels", c_i64),
                 ("max_view_pixels", c_i64), ("capacity", c_i64), ("key_bits", c_i32), ("sort_passes", c_i32),
-                ("tile_w", c_i32), ("tile_h", c_i32), ("cams", c_vp), ("block", c_vp), ("bytes", ctypes.c_size_t),
+                ("tile_w", c_i32), ("tile_h", c_i32), ("seg_len", c_i32), ("seg_cap", c_i32), ("long_cap", c_i32),
+                ("item_cap", c_i32), ("cams", c_vp), ("block", c_vp), ("bytes", ctypes.c_size_t),
                 ("rec", c_vp), ("rect", c_vp), ("rgrad", c_vp), ("vis_mask", c_vp), ("n_inst", c_vp),
                 ("inst_off", c_vp), ("keys", c_vp * 2), ("vals", c_vp * 2), ("tile_range", c_vp),
-                ("tile_order", c_vp), ("counters", c_vp), ("loss", c_vp), ("scratch", c_vp), ("scratch_ints", ctypes.c_size_t)]
+                ("tile_order", c_vp), ("counters", c_vp), ("seg_count", c_vp), ("seg_first", c_vp), ("items", c_vp),
+                ("seg", c_vp), ("split", c_vp), ("loss", c_vp), ("scratch", c_vp), ("scratch_ints", ctypes.c_size_t)]
 
 
 class gs_images(ctypes.Structure):

@@ -32,26 +32,32 @@ int hip_fail(hipError_t e, const char* where) {
   } while (0)
 
 bool tiles_supported(int tw, int th) {
-  return (tw == 16 && th == 16) || (tw == 16 && th == 8) || (tw == 8 && th == 8) || (tw == 32 && th == 8) ||
-         (tw == 32 && th == 16);
+  return (tw == 16 && th == 16) || (tw == 16 && th == 8) || (tw == 8 && th == 8) || (tw == 32 && th == 8);
 }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
   size_t rec, rect, rgrad, mask, ninst, instoff, k0, k1, v0, v1, range, order, counters, loss, scratch, total;
+  size_t segcount, segfirst, items, seg, split;
   size_t scratch_ints;
   int key_bits, passes;
+  int seg_len, seg_cap, long_cap, item_cap;
 };
+
+// Depth-segment length of the fused backward for these options (0: never split).
+int seg_len_of(const gs_opts* o) { return o->seg_len == 0 ? 2048 : (o->seg_len < 0 ? 0 : o->seg_len); }
 
 int opts_check(const gs_opts* o) {
   if (!o) return fail(GS_ERR_ARG, "opts is NULL");
   if (!tiles_supported(o->tile_w, o->tile_h))
-    return fail(GS_ERR_ARG, "unsupported tile %dx%d (16x16, 16x8, 8x8, 32x8, 32x16)", o->tile_w, o->tile_h);
+    return fail(GS_ERR_ARG, "unsupported tile %dx%d (16x16, 16x8, 8x8, 32x8)", o->tile_w, o->tile_h);
   const int nw = o->waves_per_tile;
-  const bool nw_ok = nw == 0 || nw == 1 || (nw == 2 && !(o->tile_w == 8 && o->tile_h == 8)) ||
-                     (nw == 4 && (o->tile_w == 32 || (o->tile_w == 16 && o->tile_h == 16)));
-  if (!nw_ok) return fail(GS_ERR_ARG, "waves_per_tile %d unsupported for %dx%d tiles", nw, o->tile_w, o->tile_h);
+  if (nw != 0 && nw != o->tile_w * o->tile_h / 64)
+    return fail(GS_ERR_ARG, "waves_per_tile %d: a %dx%d tile has %d waves", nw, o->tile_w, o->tile_h,
+                o->tile_w * o->tile_h / 64);
+  if (o->batch_depth < 0 || o->batch_depth > 2) return fail(GS_ERR_ARG, "batch_depth %d outside [0, 2]", o->batch_depth);
+  if (o->seg_len > 0 && o->seg_len < 64) return fail(GS_ERR_ARG, "seg_len %d below 64", o->seg_len);
   if (!(o->near_z > 0.f) || !(o->guard >= 1.f) || !(o->lowpass >= 0.f) || !(o->alpha_min > 0.f) ||
       !(o->alpha_max > o->alpha_min) || !(o->alpha_max < 1.f) || !(o->t_min > 0.f))
     return fail(GS_ERR_ARG, "invalid option values");
@@ -78,8 +84,13 @@ int views_info(const gs_camera* cams, int32_t V, const gs_opts* o, int* n_tiles,
   return GS_OK;
 }
 
-Layout make_layout(int64_t n, int V, int n_tiles, int64_t cap) {
+Layout make_layout(int64_t n, int V, int n_tiles, int64_t cap, const gs_opts* opts) {
   Layout L;
+  L.seg_len = seg_len_of(opts);
+  L.seg_cap = L.seg_len > 0 ? (int)(2 * cap / L.seg_len + 2) : 0;
+  L.long_cap = L.seg_len > 0 ? (int)(cap / L.seg_len + 1) : 0;
+  L.item_cap = n_tiles + L.seg_cap;
+  const size_t NT = (size_t)opts->tile_w * opts->tile_h;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t r = o;
@@ -101,7 +112,12 @@ Layout make_layout(int64_t n, int V, int n_tiles, int64_t cap) {
   L.order = take((size_t)n_tiles * 4);
   L.counters = take(256 * 4);
   L.loss = take(64 * 4);
-  const size_t s1 = gs_launch::scan_scratch_ints(n), s2 = gs_launch::sort_scratch_ints(cap);
+  L.segcount = take((size_t)n_tiles * 4);
+  L.segfirst = take((size_t)n_tiles * 4);
+  L.items = take((size_t)L.item_cap * 16);
+  L.seg = take((size_t)L.seg_cap * 6 * NT * 4);
+  L.split = take((size_t)L.long_cap * 12 * NT * 4);
+  const size_t s1 = gs_launch::scan_scratch_ints(n > n_tiles ? n : n_tiles), s2 = gs_launch::sort_scratch_ints(cap);
   L.scratch_ints = s1 > s2 ? s1 : s2;
   L.scratch = take(L.scratch_ints * 4);
   L.total = o;
@@ -180,7 +196,7 @@ size_t gs_frame_bytes(int64_t n, const gs_camera* cams, int32_t V, const gs_opts
   int64_t np;
   if (views_info(cams, V, o, &nt, &np)) return 0;
   if (n < 1 || capacity < 1 || capacity > INT32_MAX) return 0;
-  return make_layout(n, V, nt, capacity).total;
+  return make_layout(n, V, nt, capacity, o).total;
 }
 
 int gs_frame_init(gs_frame* f, void* block, size_t bytes, int64_t n, const gs_camera* cams_host,
@@ -200,7 +216,7 @@ int gs_frame_init(gs_frame* f, void* block, size_t bytes, int64_t n, const gs_ca
       return fail(GS_ERR_ARG, "view %d is not planned for these options (call gs_plan_cameras)", v);
   if (!block) return fail(GS_ERR_ARG, "block is NULL");
   if (((uintptr_t)block & 255) != 0) return fail(GS_ERR_ARG, "block is not 256-byte aligned");
-  const Layout L = make_layout(n, V, nt, capacity);
+  const Layout L = make_layout(n, V, nt, capacity, o);
   if (bytes < L.total) return fail(GS_ERR_WORKSPACE, "frame block of %zu bytes, %zu needed", bytes, L.total);
   char* b = static_cast<char*>(block);
   std::memset(f, 0, sizeof(*f));
@@ -214,6 +230,10 @@ int gs_frame_init(gs_frame* f, void* block, size_t bytes, int64_t n, const gs_ca
   f->sort_passes = L.passes;
   f->tile_w = o->tile_w;
   f->tile_h = o->tile_h;
+  f->seg_len = L.seg_len;
+  f->seg_cap = L.seg_cap;
+  f->long_cap = L.long_cap;
+  f->item_cap = L.item_cap;
   f->cams = cams_dev;
   f->block = block;
   f->bytes = bytes;
@@ -233,6 +253,11 @@ int gs_frame_init(gs_frame* f, void* block, size_t bytes, int64_t n, const gs_ca
   f->loss = reinterpret_cast<float*>(b + L.loss);
   f->scratch = reinterpret_cast<int32_t*>(b + L.scratch);
   f->scratch_ints = L.scratch_ints;
+  f->seg_count = reinterpret_cast<int32_t*>(b + L.segcount);
+  f->seg_first = reinterpret_cast<int32_t*>(b + L.segfirst);
+  f->items = reinterpret_cast<int32_t*>(b + L.items);
+  f->seg = reinterpret_cast<float*>(b + L.seg);
+  f->split = reinterpret_cast<float*>(b + L.split);
   return GS_OK;
 }
 
@@ -269,6 +294,7 @@ int gs_bin_tiles(const gs_frame* f, const gs_opts* o, int32_t sync_count, int64_
          "gs_bin_tiles: sort");
   GS_HIP(gs_launch::ranges(*f, f->keys[f->sort_passes & 1], n_sized, count_dev, st), "gs_bin_tiles: ranges");
   GS_HIP(gs_launch::tile_schedule(*f, st), "gs_bin_tiles: schedule");
+  GS_HIP(gs_launch::work_items(*f, st), "gs_bin_tiles: work items");
   return GS_OK;
 }
 

@@ -224,19 +224,21 @@ __global__ void k_ranges(const uint64_t* __restrict__ keys, const int32_t* __res
 }
 
 // Compositing schedule: tiles in descending order of their list length, bucketed by floor(log2(len + 1))
-// (32 buckets, longest first; the order inside a bucket does not matter).
-__device__ __forceinline__ int len_bucket(const int2* range, int t) {
+// (32 buckets, longest first; the order inside a bucket does not matter).  Tiles longer than the segment
+// length (split into depth segments by the fused backward) all go to bucket 0, so they lead the schedule.
+__device__ __forceinline__ int len_bucket(const int2* range, int t, int seg_len) {
   const int len = range[t].y - range[t].x;
-  return __clz(len + 1);  // 31 - floor(log2(len + 1)): longer lists get smaller bucket ids
+  if (seg_len > 0 && len > seg_len) return 0;
+  return __clz((unsigned)len + 1u);  // 31 - floor(log2(len + 1)): longer lists get smaller bucket ids
 }
 
-__global__ __launch_bounds__(256) void k_sched_hist(const int2* __restrict__ range, int n_tiles,
+__global__ __launch_bounds__(256) void k_sched_hist(const int2* __restrict__ range, int n_tiles, int seg_len,
                                                     int32_t* __restrict__ bucket_cnt) {
   __shared__ int h[32];
   if (threadIdx.x < 32) h[threadIdx.x] = 0;
   __syncthreads();
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n_tiles) atomicAdd(&h[len_bucket(range, t)], 1);
+  if (t < n_tiles) atomicAdd(&h[len_bucket(range, t, seg_len)], 1);
   __syncthreads();
   if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(bucket_cnt + threadIdx.x, h[threadIdx.x]);
 }
@@ -250,7 +252,7 @@ __global__ void k_sched_scan(const int32_t* __restrict__ bucket_cnt, int32_t* __
   }
 }
 
-__global__ __launch_bounds__(256) void k_sched_scatter(const int2* __restrict__ range, int n_tiles,
+__global__ __launch_bounds__(256) void k_sched_scatter(const int2* __restrict__ range, int n_tiles, int seg_len,
                                                        int32_t* __restrict__ bucket_off, int32_t* __restrict__ order) {
   __shared__ int h[32], base[32];
   if (threadIdx.x < 32) h[threadIdx.x] = 0;
@@ -258,13 +260,41 @@ __global__ __launch_bounds__(256) void k_sched_scatter(const int2* __restrict__ 
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   int b = 0, rank = 0;
   if (t < n_tiles) {
-    b = len_bucket(range, t);
+    b = len_bucket(range, t, seg_len);
     rank = atomicAdd(&h[b], 1);
   }
   __syncthreads();
   if (threadIdx.x < 32 && h[threadIdx.x]) base[threadIdx.x] = atomicAdd(bucket_off + threadIdx.x, h[threadIdx.x]);
   __syncthreads();
   if (t < n_tiles) order[base[b] + rank] = t;
+}
+
+// Work items of the fused backward, in schedule order: one per tile, or one per depth segment of a tile
+// longer than seg_len (those lead the schedule, so their segments take item indices 0 .. slots - 1, which
+// are also their segment-state slots).
+__global__ __launch_bounds__(256) void k_seg_count(const int2* __restrict__ range, const int32_t* __restrict__ order,
+                                                   int n_tiles, int seg_len, int32_t* __restrict__ seg_count) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_tiles) return;
+  const int2 r = range[order[p]];
+  const int len = r.y - r.x;
+  seg_count[p] = len > seg_len ? (len + seg_len - 1) / seg_len : 1;
+}
+
+__global__ __launch_bounds__(256) void k_seg_emit(const int32_t* __restrict__ order, int n_tiles,
+                                                  const int32_t* __restrict__ seg_count,
+                                                  const int32_t* __restrict__ seg_first, int4* __restrict__ items,
+                                                  int32_t* __restrict__ counters) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p == 0) {
+    const int nl = counters[128];  // bucket 0: split tiles
+    counters[194] = nl;
+    counters[193] = nl > 0 ? seg_first[nl - 1] + seg_count[nl - 1] : 0;
+    counters[192] = seg_first[n_tiles - 1] + seg_count[n_tiles - 1];
+  }
+  if (p >= n_tiles) return;
+  const int n = seg_count[p], first = seg_first[p], t = order[p];
+  for (int k = 0; k < n; ++k) items[first + k] = make_int4(t, k, n > 1 ? first : -1, p);
 }
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -360,11 +390,24 @@ hipError_t tile_schedule(const gs_frame& f, hipStream_t st) {
   if (e != hipSuccess) return e;
   const auto* rng = reinterpret_cast<const int2*>(f.tile_range);
   const unsigned nb = (unsigned)cdiv(f.n_tiles, 256);
-  k_sched_hist<<<nb, 256, 0, st>>>(rng, f.n_tiles, cnt);
+  k_sched_hist<<<nb, 256, 0, st>>>(rng, f.n_tiles, f.seg_len, cnt);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_sched_scan<<<1, 64, 0, st>>>(cnt, off);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_sched_scatter<<<nb, 256, 0, st>>>(rng, f.n_tiles, off, f.tile_order);
+  k_sched_scatter<<<nb, 256, 0, st>>>(rng, f.n_tiles, f.seg_len, off, f.tile_order);
+  return hipGetLastError();
+}
+
+hipError_t work_items(const gs_frame& f, hipStream_t st) {
+  if (f.seg_len <= 0) return hipSuccess;
+  const auto* rng = reinterpret_cast<const int2*>(f.tile_range);
+  const unsigned nb = (unsigned)cdiv(f.n_tiles, 256);
+  k_seg_count<<<nb, 256, 0, st>>>(rng, f.tile_order, f.n_tiles, f.seg_len, f.seg_count);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = scan_exclusive(f.seg_count, f.seg_first, f.n_tiles, f.scratch, st)) != hipSuccess) return e;
+  k_seg_emit<<<nb, 256, 0, st>>>(f.tile_order, f.n_tiles, f.seg_count, f.seg_first, reinterpret_cast<int4*>(f.items),
+                                 f.counters);
   return hipGetLastError();
 }
 

@@ -15,7 +15,7 @@ struct DevOpts {
   float near_z, lowpass, alpha_min, alpha_max, t_min;
   float bg[3];
   int tile_w, tile_h;
-  float stream_cover;
+  int scatter_max;
 };
 
 inline DevOpts dev_opts(const gs_opts& o) {
@@ -30,7 +30,7 @@ inline DevOpts dev_opts(const gs_opts& o) {
   d.bg[2] = o.bg[2];
   d.tile_w = o.tile_w;
   d.tile_h = o.tile_h;
-  d.stream_cover = o.stream_cover == 0.f ? 0.25f : o.stream_cover;
+  d.scatter_max = o.scatter_max == 0 ? 16 : (o.scatter_max < 0 ? -1 : o.scatter_max);
   return d;
 }
 
@@ -60,6 +60,29 @@ __device__ __forceinline__ float wave_sum_last(float x) {
   x += dpp_f<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
   x += dpp_f<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
   return x;
+}
+
+// Maximum over the 64 lanes of a non-negative int, returned to every lane (same DPP pattern as above).
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, ROW_MASK, 0xf, false);
+}
+
+__device__ __forceinline__ int wave_max_nonneg(int x) {
+  x = max(x, dpp_i<0xB1>(x));
+  x = max(x, dpp_i<0x4E>(x));
+  x = max(x, dpp_i<0x141>(x));
+  x = max(x, dpp_i<0x140>(x));
+  x = max(x, dpp_i<0x142, 0xa>(x));
+  x = max(x, dpp_i<0x143, 0xc>(x));
+  return __builtin_amdgcn_readlane(x, 63);
+}
+
+// A value known to be the same in every lane, moved to scalar registers.
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ float read_lane(float x, int l) {
@@ -104,6 +127,7 @@ hipError_t sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int6
                       const int32_t* count_dev, int64_t cap, int key_bits, int32_t* scratch, hipStream_t s);
 hipError_t ranges(const gs_frame& f, const uint64_t* keys, int64_t n_sized, const int32_t* count_dev, hipStream_t s);
 hipError_t tile_schedule(const gs_frame& f, hipStream_t s);
+hipError_t work_items(const gs_frame& f, hipStream_t s);
 hipError_t render_fwd(const gs_frame& f, const gs_opts& o, const gs_images& out, hipStream_t s);
 hipError_t count_pairs(const gs_frame& f, const gs_opts& o, unsigned long long* counts, hipStream_t s);
 hipError_t count_valid(const gs_frame& f, const float* tgt_depth, int64_t max_pixels, hipStream_t s);

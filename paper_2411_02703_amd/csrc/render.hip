@@ -1,14 +1,17 @@
 // Per-tile front-to-back compositing of colour, depth and visibility (LVI-GS Section III-B,
 // eqs. Cp, Dp, Vp with the alpha of eq. alpha) and its backward.
 //
-// One workgroup of NW wave64s per tile.  The tile is split into NW sub-tiles (quadrants or halves), one per
-// wave; each lane owns PPT pixels of its wave's sub-tile (a column of rows spaced 64/SW apart).  The tile's
-// depth-sorted list is staged 64*NW records at a time into LDS (one record per thread, gathered by record
-// id).  Each record carries its exact pixel rectangle, so every wave compacts the staged batch down to the
-// records whose rectangle meets its sub-tile and loops over those only.  A record is skipped only where its
-// rectangle misses the pixel, where alpha < exp(-1/2)/255 holds, so the result is the same bit for bit as
-// walking the whole list.  This matters for coarse pyramid levels, where a tile holds tens of thousands of
-// sub-pixel Gaussians of which each pixel sees a few percent.
+// One workgroup per tile.  The tile is split into 8x8 sub-tiles, one wave64 each, one pixel per lane.  The
+// tile's depth-sorted list is staged in rounds of DEPTH records per thread into LDS; the records of the next
+// round are fetched into registers while the current one is composited.  Each staged record carries its
+// exact pixel rectangle (every pixel outside it has alpha < exp(-1/2)/255, so it would be skipped anyway).
+// A record whose rectangle meets only a few pixels of a sub-tile sets its bit in those pixels' masks; a
+// larger one sets its bit in the sub-tile's mask, which every lane of the wave walks.  Each lane then walks
+// the set bits of its masks in order, i.e. exactly the staged records that can touch its pixel, in list
+// order, so the result is the same bit for bit whichever records take which route.  Coarse pyramid levels,
+// where a tile holds tens of thousands of sub-pixel Gaussians of which a pixel sees a few percent, walk a
+// few records per lane per round instead of every record of the sub-tile; fine levels, where most records
+// cover whole sub-tiles, walk the shared mask in lock-step.
 //
 // The backward walks the list in the same front-to-back order as the forward.  With the forward's final
 // values C, D, V of a pixel and its upstream gradient g, the gradient of alpha_i is
@@ -16,68 +19,49 @@
 //   S = g . (C, D, V),  P_i = sum_{j <= i} alpha_j T_j q_j,
 // i.e. what lies behind record i is S - P_i.  No per-pixel state is stored between the forward and the
 // backward (the fused variant recomputes C, D, V with a first sweep in the same kernel), and the skip / stop
-// decisions are re-evaluated with the forward's arithmetic.  Per-record gradients of a wave are summed with
-// DPP before one atomic add per value, unless at most four lanes contributed (then each adds its own).
+// decisions are re-evaluated with the forward's arithmetic.  Per-record partial derivatives are summed in
+// LDS (a DPP wave sum first when every contributing lane of the wave is on the same record) and added to
+// the record's gradient in HBM once per round.
 #include "common.h"
 
 namespace {
 
 using gsk::DevOpts;
 
-template <int TW, int TH, int NW>
+template <int TW, int TH, int DEPTH>
 struct Geo {
-  static constexpr int SX = NW == 4 ? 2 : 1;  // sub-tiles across
-  static constexpr int SY = NW / SX;          // sub-tiles down
-  static constexpr int SW = TW / SX;          // sub-tile width
-  static constexpr int SH = TH / SY;          // sub-tile height
-  static constexpr int RPP = 64 / SW;         // rows covered by the 64 lanes at once
-  static constexpr int PPT = SH / RPP;        // pixels per lane
-  static constexpr int BATCH = 64 * NW;       // records staged per round
-  static_assert(SW == 8 || SW == 16 || SW == 32, "sub-tile width");
-  static_assert(PPT >= 1 && PPT * RPP == SH, "sub-tile height");
+  static constexpr int SX = TW / 8;            // sub-tiles across
+  static constexpr int SY = TH / 8;            // sub-tiles down
+  static constexpr int NW = SX * SY;           // waves per tile
+  static constexpr int NT = 64 * NW;           // threads = pixels of the tile
+  static constexpr int BATCH = NT * DEPTH;     // records staged per round
+  static constexpr int MC = BATCH / 64;        // 64-bit mask words per pixel
+  static_assert(TW % 8 == 0 && TH % 8 == 0 && NW >= 1 && NW <= 4, "tile shape");
+  static_assert(DEPTH == 1 || DEPTH == 2, "batch depth");
 };
 
-template <int BATCH, int NW>
+template <class G>
 struct Stage {
-  float4 A[BATCH], B[BATCH], C[BATCH];
-  int32_t r[BATCH];
-  uint8_t mask[BATCH];
-  uint16_t list[NW][BATCH];
-  int4 wbox[NW][BATCH];  // per wave, in list order: pixel box as (x0, x1 - x0, y0, y1 - y0)
-  int cover[NW];         // pixels of the wave's sub-tile covered by the boxes of its list, summed
+  float4 A[G::BATCH], B[G::BATCH], C[G::BATCH];
+  int32_t r[G::BATCH];
+  uint64_t pm[G::MC][G::NT];    // per pixel (thread index): staged records handed to it
+  uint64_t wide[G::NW][G::MC];  // per sub-tile: staged records walked by all its lanes
+  uint64_t uw[G::NW][G::MC];    // per sub-tile: staged records handed to some of its pixels
+  int alive[G::NW];             // per wave: a pixel is still live
 };
-
-// Per-pixel "stream" walk, used for a wave's batch when the boxes of its records cover under a quarter of its
-// (record, pixel) pairs - the coarse pyramid levels, where a tile holds tens of thousands of sub-pixel
-// Gaussians.  Each lane tests the boxes of the next 64 records of its wave's list against its own pixel and
-// walks only the records that cover it, in list order.  It meets exactly the records that can contribute, in
-// the same order, so the result is the same bit for bit as the dense walk; it only skips work.
-__device__ __forceinline__ uint64_t cover_mask(const int4* __restrict__ boxes, int nc, int px, int py) {
-  uint64_t m = 0;
-#pragma unroll 8
-  for (int k = 0; k < nc; ++k) {
-    const int4 b = boxes[k];
-    const bool c = (unsigned)(px - b.x) <= (unsigned)b.y && (unsigned)(py - b.z) <= (unsigned)b.w;
-    m |= (uint64_t)c << k;
-  }
-  return m;
-}
 
 struct TileCtx {
   int view, W, H, tx0, ty0;  // view and tile origin (pixels)
-  int px, py0;               // this lane's column and first row
+  int px, py;                // this lane's pixel
   int wave, lane;
   int64_t pix_off;
   float weight;
+  bool inside;               // pixel inside the image
 };
 
-// Workgroup b composites tile order[b]: tiles in descending order of list length, so the longest start first
-// and are dealt round-robin over the XCDs.
+// Geometry of this thread's pixel in global tile `tile`.
 template <class G>
-__device__ __forceinline__ bool tile_setup(const gs_camera* __restrict__ cams, int V, int n_tiles,
-                                           const int32_t* __restrict__ order, TileCtx& t, int& tile) {
-  if ((int)blockIdx.x >= n_tiles) return false;
-  tile = order[blockIdx.x];
+__device__ __forceinline__ void tile_at(const gs_camera* __restrict__ cams, int V, int tile, TileCtx& t) {
   t.view = gsk::view_of_tile(cams, V, tile);
   const gs_camera& c = cams[t.view];
   const int lt = tile - c.tile_offset;
@@ -86,18 +70,28 @@ __device__ __forceinline__ bool tile_setup(const gs_camera* __restrict__ cams, i
   t.lane = threadIdx.x & 63;
   t.W = c.width;
   t.H = c.height;
-  t.tx0 = txi * (G::SW * G::SX);
-  t.ty0 = tyi * (G::SH * G::SY);
-  t.px = t.tx0 + (t.wave % G::SX) * G::SW + (t.lane % G::SW);
-  t.py0 = t.ty0 + (t.wave / G::SX) * G::SH + t.lane / G::SW;
+  t.tx0 = txi * (8 * G::SX);
+  t.ty0 = tyi * (8 * G::SY);
+  t.px = t.tx0 + (t.wave % G::SX) * 8 + (t.lane & 7);
+  t.py = t.ty0 + (t.wave / G::SX) * 8 + (t.lane >> 3);
   t.pix_off = c.pixel_offset;
   t.weight = c.loss_weight;
+  t.inside = t.px < t.W && t.py < t.H;
+}
+
+// Workgroup b composites tile order[b]: tiles in descending order of list length, so the longest start first.
+template <class G>
+__device__ __forceinline__ bool tile_setup(const gs_camera* __restrict__ cams, int V, int n_tiles,
+                                           const int32_t* __restrict__ order, TileCtx& t, int& tile) {
+  if ((int)blockIdx.x >= n_tiles) return false;
+  tile = order[blockIdx.x];
+  tile_at<G>(cams, V, tile, t);
   return true;
 }
 
 // One record at one pixel: returns false if skipped (power > 0 or alpha < alpha_min).  The operation
 // sequence is fixed (contraction off, explicit fma) so that every kernel and every tile shape computes the
-// same bits for the same (record, pixel) pair, whatever the compiler shares between a lane's pixels.
+// same bits for the same (record, pixel) pair.
 __device__ __forceinline__ bool eval_pair(const float4& A, const float4& B, float fx, float fy, const DevOpts& op,
                                           float& alpha, float& G, bool& clamped, float& dx, float& dy) {
 #pragma clang fp contract(off)
@@ -123,182 +117,261 @@ __device__ __forceinline__ void unpack_rect(const float4& C, int& x0, int& x1, i
   y1 = (int)((unsigned)b >> 16);
 }
 
-// Stage records [b0, b0 + nb) of the tile list, then build each wave's list of the staged records whose
-// pixel rectangle meets its sub-tile.  Returns the length of this wave's list.  Ends with a barrier.
-template <class G, class S>
-__device__ __forceinline__ int stage_and_compact(S& s, const float4* __restrict__ rec, const int32_t* __restrict__ vals,
-                                                 int b0, int nb, const TileCtx& t, int& cover) {
-  const int tid = threadIdx.x;
-  uint32_t m = 0;
-  int4 box = make_int4(0, 0, 0, 0);
-  if (tid < G::SX * G::SY) s.cover[tid] = 0;
-  if (tid < nb) {
-    const int r = vals[b0 + tid];
-    const float4 A = rec[3 * (int64_t)r], B = rec[3 * (int64_t)r + 1], C = rec[3 * (int64_t)r + 2];
-    s.A[tid] = A;
-    s.B[tid] = B;
-    s.C[tid] = C;
-    s.r[tid] = r;
-    int x0, x1, y0, y1;
-    unpack_rect(C, x0, x1, y0, y1);
-    box = make_int4(x0, x1 - x0, y0, y1 - y0);
+// Records of the tile list in flight, per thread: the round held in registers (ids r, data A, B, C) and the
+// ids of the round after it (rn, valid where vn).  Loads are unconditional (an absent record reads record
+// 0, which is never used), so nothing waits on them until the round is written to LDS.
+template <class G, int DEPTH>
+__device__ __forceinline__ void fetch_records(const float4* __restrict__ rec, const int (&r)[DEPTH], float4 (&A)[DEPTH],
+                                              float4 (&B)[DEPTH], float4 (&C)[DEPTH]) {
 #pragma unroll
-    for (int w = 0; w < G::SX * G::SY; ++w) {
-      const int sx0 = t.tx0 + (w % G::SX) * G::SW, sy0 = t.ty0 + (w / G::SX) * G::SH;
-      if (x0 <= sx0 + G::SW - 1 && x1 >= sx0 && y0 <= sy0 + G::SH - 1 && y1 >= sy0) m |= 1u << w;
-    }
+  for (int k = 0; k < DEPTH; ++k) {
+    const float4* p = rec + 3 * (int64_t)max(r[k], 0);
+    A[k] = p[0];
+    B[k] = p[1];
+    C[k] = p[2];
   }
-  s.mask[tid] = (uint8_t)m;
-  __syncthreads();
-  if (m) {
-#pragma unroll
-    for (int w = 0; w < G::SX * G::SY; ++w) {
-      if (!((m >> w) & 1)) continue;
-      const int sx0 = t.tx0 + (w % G::SX) * G::SW, sy0 = t.ty0 + (w / G::SX) * G::SH;
-      const int ox = min(box.x + box.y, sx0 + G::SW - 1) - max(box.x, sx0) + 1;
-      const int oy = min(box.z + box.w, sy0 + G::SH - 1) - max(box.z, sy0) + 1;
-      atomicAdd(&s.cover[w], ox * oy);
-    }
-  }
-  int cnt = 0;
-  const uint64_t lt = gsk::lanemask_lt();
-#pragma unroll
-  for (int c = 0; c < G::BATCH / 64; ++c) {
-    const int j = c * 64 + t.lane;
-    const bool bit = (s.mask[j] >> t.wave) & 1;
-    const uint64_t bal = __ballot(bit);
-    if (bit) {
-      const int p = cnt + __popcll(bal & lt);
-      s.list[t.wave][p] = (uint16_t)j;
-      const float4 C = s.C[j];
-      int x0, x1, y0, y1;
-      unpack_rect(C, x0, x1, y0, y1);
-      s.wbox[t.wave][p] = make_int4(x0, x1 - x0, y0, y1 - y0);
-    }
-    cnt += __popcll(bal);
-  }
-  __syncthreads();
-  cover = s.cover[t.wave];
-  return cnt;
 }
 
-// Stream walk only where one lane holds one pixel and the wave's records cover under a fraction (default a
-// quarter) of its pairs.
+template <class G, int DEPTH>
+__device__ __forceinline__ void fetch_ids(const int32_t* __restrict__ vals, int first, int end, int (&ids)[DEPTH]) {
+#pragma unroll
+  for (int k = 0; k < DEPTH; ++k) {
+    const int i = first + k * G::NT + (int)threadIdx.x;
+    ids[k] = i < end ? vals[i] : -1;
+  }
+}
+
+// Write the round held in registers into LDS, then start fetching the round after it (its ids were fetched
+// one round earlier) and the ids of the round after that.
+template <class G, int DEPTH>
+__device__ __forceinline__ void stage_round(Stage<G>& s, const float4* __restrict__ rec, const int32_t* __restrict__ vals,
+                                            int b0, int end, int (&r)[DEPTH], int (&rn)[DEPTH], float4 (&A)[DEPTH],
+                                            float4 (&B)[DEPTH], float4 (&C)[DEPTH]) {
+#pragma unroll
+  for (int k = 0; k < DEPTH; ++k) {
+    const int slot = k * G::NT + (int)threadIdx.x;
+    s.A[slot] = A[k];
+    s.B[slot] = B[k];
+    s.C[slot] = C[k];
+    s.r[slot] = r[k];
+    r[k] = rn[k];
+  }
+  fetch_records<G, DEPTH>(rec, r, A, B, C);
+  fetch_ids<G, DEPTH>(vals, b0 + 2 * G::BATCH, end, rn);
+}
+
+// End of a round: every wave publishes whether it still has a live pixel, then the workgroup meets.  Returns
+// whether any pixel of the tile is live (the same answer in every thread).
 template <class G>
-__device__ __forceinline__ bool use_stream(int cnt, int cover, const DevOpts& op) {
-  return G::PPT == 1 && cnt >= 64 && (float)cover < op.stream_cover * (float)(G::SW * G::SH * cnt);
+__device__ __forceinline__ bool round_barrier(Stage<G>& s, const TileCtx& t, bool live) {
+  const bool wl = __ballot(live) != 0;
+  if (t.lane == 0) s.alive[t.wave] = wl;
+  __syncthreads();
+  bool any = false;
+#pragma unroll
+  for (int w = 0; w < G::NW; ++w) any |= s.alive[w] != 0;
+  return any;
 }
 
-// Forward sweep of one tile for this lane's pixels (shared by the forward kernel and the fused backward).
-template <class G, class S>
-__device__ __forceinline__ void forward_sweep(S& s, const float4* __restrict__ rec, const int32_t* __restrict__ vals,
-                                              int2 rg, const TileCtx& t, const DevOpts& op, float* T, float* Cr,
-                                              float* Cg, float* Cb, float* D, float* Vs) {
-  constexpr int PPT = G::PPT, RPP = G::RPP;
-  bool live[PPT];
-  float fy[PPT];
-  const float fx = (float)t.px + 0.5f;
+// Clear this thread's pixel masks (and, for the first threads, the sub-tile masks).
+template <class G>
+__device__ __forceinline__ void clear_masks(Stage<G>& s) {
 #pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    const int py = t.py0 + k * RPP;
-    live[k] = t.px < t.W && py < t.H;
-    fy[k] = (float)py + 0.5f;
-    T[k] = 1.f;
-    Cr[k] = Cg[k] = Cb[k] = D[k] = Vs[k] = 0.f;
+  for (int c = 0; c < G::MC; ++c) s.pm[c][threadIdx.x] = 0ull;
+  if ((int)threadIdx.x < G::NW * G::MC) {
+    (&s.wide[0][0])[threadIdx.x] = 0ull;
+    (&s.uw[0][0])[threadIdx.x] = 0ull;
   }
-  // one (record, pixel) step of the front-to-back walk
-  auto step = [&](const float4& A, const float4& B, const float4& C, int k) {
+}
+
+// Hand this thread's staged records to the pixels (or sub-tiles) their rectangles meet.
+template <class G, int DEPTH>
+__device__ __forceinline__ void scatter(Stage<G>& s, const TileCtx& t, int nb, int smax) {
+#pragma unroll
+  for (int k = 0; k < DEPTH; ++k) {
+    const int j = k * G::NT + (int)threadIdx.x;
+    if (j >= nb) continue;
+    int x0, x1, y0, y1;
+    unpack_rect(s.C[j], x0, x1, y0, y1);
+    const uint64_t bit = 1ull << (j & 63);
+    const int wd = j >> 6;
+#pragma unroll
+    for (int w = 0; w < G::NW; ++w) {
+      const int sx0 = t.tx0 + (w % G::SX) * 8, sy0 = t.ty0 + (w / G::SX) * 8;
+      const int cx0 = max(x0, sx0), cx1 = min(x1, sx0 + 7), cy0 = max(y0, sy0), cy1 = min(y1, sy0 + 7);
+      if (cx0 > cx1 || cy0 > cy1) continue;
+      if ((cx1 - cx0 + 1) * (cy1 - cy0 + 1) > smax) {
+        atomicOr(&s.wide[w][wd], bit);
+        continue;
+      }
+      atomicOr(&s.uw[w][wd], bit);
+      for (int y = cy0; y <= cy1; ++y)
+        for (int x = cx0; x <= cx1; ++x) atomicOr(&s.pm[wd][w * 64 + (y - sy0) * 8 + (x - sx0)], bit);
+    }
+  }
+}
+
+// Walk one staged round for this lane's pixel, in list order, over exactly the records that can touch it:
+// its own bits and its sub-tile's shared bits.  When the longest per-lane walk of the wave is at least half
+// the wave's union of records, the wave walks the union in lock-step instead (uniform record, broadcast LDS
+// reads; a record outside a pixel's rectangle is skipped there by its alpha, so the result is the same).
+//   step(j, A, B, C, acc) -> contributed   (per lane; clears live at the stop)
+//   post(j, hit, acc, uniform)             (whole wave, once per step, only if SYNC)
+template <class G, bool SYNC, class Step, class Post>
+__device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, bool& live, Step step, Post post) {
+  int cnt = 0, nu = 0;
+#pragma unroll
+  for (int c = 0; c < G::MC; ++c) {
+    const uint64_t wd = s.wide[t.wave][c];
+    cnt += __popcll(s.pm[c][threadIdx.x] | wd);
+    nu += __popcll(s.uw[t.wave][c] | wd);
+  }
+  const int cmax = gsk::wave_max_nonneg(live ? cnt : 0);
+  if (cmax == 0) return;
+  if (2 * cmax >= nu) {
+#pragma unroll 1
+    for (int c = 0; c < G::MC; ++c) {
+      uint64_t m = gsk::uniform64(s.uw[t.wave][c] | s.wide[t.wave][c]);
+      if (m == 0) continue;
+      int jn = c * 64 + __builtin_ctzll(m);
+      float4 An = s.A[jn], Bn = s.B[jn], Cn = s.C[jn];
+      while (m) {
+        const int j = jn;
+        const float4 A = An, B = Bn, C = Cn;
+        m &= m - 1;
+        jn = c * 64 + (m ? __builtin_ctzll(m) : 0);
+        An = s.A[jn];
+        Bn = s.B[jn];
+        Cn = s.C[jn];
+        float acc[10];
+#pragma unroll
+        for (int q = 0; q < 10; ++q) acc[q] = 0.f;
+        const bool hit = live && step(j, A, B, C, acc);
+        if (SYNC) post(j, hit, acc, true);
+        if (__ballot(live) == 0) return;
+      }
+    }
+    return;
+  }
+#pragma unroll 1
+  for (int c = 0; c < G::MC; ++c) {
+    uint64_t m = live ? (s.pm[c][threadIdx.x] | s.wide[t.wave][c]) : 0ull;
+    if (__ballot(m != 0) == 0) continue;
+    // the lane's next record is fetched from LDS while the current one is composited
+    int jn = c * 64 + (m ? __builtin_ctzll(m) : 0);
+    float4 An = s.A[jn], Bn = s.B[jn], Cn = s.C[jn];
+    while (SYNC ? __ballot(m != 0) != 0 : m != 0) {
+      const int j = jn;
+      float acc[10];
+#pragma unroll
+      for (int q = 0; q < 10; ++q) acc[q] = 0.f;
+      bool hit = false;
+      if (m) {
+        const float4 A = An, B = Bn, C = Cn;
+        m &= m - 1;
+        jn = c * 64 + (m ? __builtin_ctzll(m) : 0);
+        An = s.A[jn];
+        Bn = s.B[jn];
+        Cn = s.C[jn];
+        hit = step(j, A, B, C, acc);
+        if (!live) m = 0;
+      }
+      if (SYNC) post(j, hit, acc, false);
+    }
+  }
+}
+
+// All rounds of one tile list: stage (with the next round in flight), hand out, walk.  at_round(not_first)
+// runs in every thread after each round barrier, before the round's LDS is rewritten.
+template <class G, int DEPTH, bool SYNC, class AtRound, class Step, class Post>
+__device__ __forceinline__ void sweep(Stage<G>& s, const float4* __restrict__ rec, const int32_t* __restrict__ vals,
+                                      int2 rg, const TileCtx& t, const DevOpts& op, bool& live, AtRound at_round,
+                                      Step step, Post post) {
+  int fr[DEPTH], frn[DEPTH];
+  float4 fA[DEPTH], fB[DEPTH], fC[DEPTH];
+  fetch_ids<G, DEPTH>(vals, rg.x, rg.y, fr);
+  fetch_ids<G, DEPTH>(vals, rg.x + G::BATCH, rg.y, frn);
+  fetch_records<G, DEPTH>(rec, fr, fA, fB, fC);
+  for (int b0 = rg.x;; b0 += G::BATCH) {
+    const bool go = round_barrier<G>(s, t, live) && b0 < rg.y;
+    at_round(b0 != rg.x);
+    if (!go) break;
+    const int nb = min(G::BATCH, rg.y - b0);
+    clear_masks<G>(s);
+    stage_round<G, DEPTH>(s, rec, vals, b0, rg.y, fr, frn, fA, fB, fC);
+    __syncthreads();
+    scatter<G, DEPTH>(s, t, nb, op.scatter_max);
+    __syncthreads();
+    walk_round<G, SYNC>(s, t, live, step, post);
+  }
+}
+
+// Forward walk of records [rg.x, rg.y) for this lane's pixel from transmittance T (in/out), adding to the
+// partial sums.  STOP applies the stop rule (the pixel ends before a pair would take T below t_min);
+// without it the walk multiplies on (the transmittance product of a depth segment).
+template <class G, int DEPTH, bool STOP>
+__device__ __forceinline__ void forward_walk(Stage<G>& s, const float4* __restrict__ rec,
+                                             const int32_t* __restrict__ vals, int2 rg, const TileCtx& t,
+                                             const DevOpts& op, bool live, float& T, float& Cr, float& Cg,
+                                             float& Cb, float& D, float& Vs) {
+  const float fx = (float)t.px + 0.5f, fy = (float)t.py + 0.5f;
+  auto step = [&](int, const float4& A, const float4& B, const float4& C, float*) -> bool {
 #pragma clang fp contract(off)
     float alpha, Gv, dx, dy;
     bool cl;
-    if (!eval_pair(A, B, fx, fy[k], op, alpha, Gv, cl, dx, dy)) return;
-    const float Tn = T[k] * (1.f - alpha);
-    if (Tn < op.t_min) {
-      live[k] = false;
-      return;
+    if (!eval_pair(A, B, fx, fy, op, alpha, Gv, cl, dx, dy)) return false;
+    const float Tn = T * (1.f - alpha);
+    if (STOP && Tn < op.t_min) {
+      live = false;
+      return false;
     }
-    const float w = alpha * T[k];
-    Cr[k] = __builtin_fmaf(w, B.w, Cr[k]);
-    Cg[k] = __builtin_fmaf(w, C.x, Cg[k]);
-    Cb[k] = __builtin_fmaf(w, C.y, Cb[k]);
-    D[k] = __builtin_fmaf(w, A.z, D[k]);
-    Vs[k] = Vs[k] + w;
-    T[k] = Tn;
+    const float w = alpha * T;
+    Cr = __builtin_fmaf(w, B.w, Cr);
+    Cg = __builtin_fmaf(w, C.x, Cg);
+    Cb = __builtin_fmaf(w, C.y, Cb);
+    D = __builtin_fmaf(w, A.z, D);
+    Vs = Vs + w;
+    T = Tn;
+    return true;
   };
-  for (int b0 = rg.x; b0 < rg.y; b0 += G::BATCH) {
-    bool any = false;
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) any |= live[k];
-    if (!__syncthreads_or(any)) break;
-    const int nb = min(G::BATCH, rg.y - b0);
-    int cover;
-    const int cnt = stage_and_compact<G>(s, rec, vals, b0, nb, t, cover);
-    if (__ballot(any) == 0) continue;
-    if (use_stream<G>(cnt, cover, op)) {
-      const int py = t.py0;
-      for (int c0 = 0; c0 < cnt; c0 += 64) {
-        uint64_t m = live[0] ? cover_mask(&s.wbox[t.wave][c0], min(64, cnt - c0), t.px, py) : 0ull;
-        // the next covered record is fetched while the current one is composited
-        int jn = s.list[t.wave][c0 + (m ? __builtin_ctzll(m) : 0)];
-        float4 An = s.A[jn], Bn = s.B[jn], Cn = s.C[jn];
-        while (__ballot(m != 0)) {
-          if (m) {
-            const float4 A = An, B = Bn, C = Cn;
-            m &= m - 1;
-            jn = s.list[t.wave][c0 + (m ? __builtin_ctzll(m) : 0)];
-            An = s.A[jn];
-            Bn = s.B[jn];
-            Cn = s.C[jn];
-            step(A, B, C, 0);
-            if (!live[0]) m = 0;
-          }
-        }
-      }
-    } else {
-      // records i + 1 (data) and i + 2 (index) are fetched while record i is composited
-      float4 An = s.A[s.list[t.wave][0]], Bn = s.B[s.list[t.wave][0]], Cn = s.C[s.list[t.wave][0]];
-      int jn2 = s.list[t.wave][cnt > 1 ? 1 : 0];
-      for (int i = 0; i < cnt; ++i) {
-        const float4 A = An, B = Bn, C = Cn;
-        An = s.A[jn2];
-        Bn = s.B[jn2];
-        Cn = s.C[jn2];
-        jn2 = s.list[t.wave][i + 2 < cnt ? i + 2 : 0];
-#pragma unroll
-        for (int k = 0; k < PPT; ++k)
-          if (live[k]) step(A, B, C, k);
-      }
-    }
-  }
+  sweep<G, DEPTH, false>(s, rec, vals, rg, t, op, live, [](bool) {}, step,
+                         [](int, bool, const float*, bool) {});
 }
 
-template <int TW, int TH, int NW>
-__global__ __launch_bounds__(64 * NW) void k_render_fwd(const float4* __restrict__ rec,
+// Forward sweep of one whole tile for this lane's pixel (forward kernel and fused backward).
+template <class G, int DEPTH>
+__device__ __forceinline__ void forward_sweep(Stage<G>& s, const float4* __restrict__ rec,
+                                              const int32_t* __restrict__ vals, int2 rg, const TileCtx& t,
+                                              const DevOpts& op, float& T, float& Cr, float& Cg, float& Cb,
+                                              float& D, float& Vs) {
+  T = 1.f;
+  Cr = Cg = Cb = D = Vs = 0.f;
+  forward_walk<G, DEPTH, true>(s, rec, vals, rg, t, op, t.inside, T, Cr, Cg, Cb, D, Vs);
+}
+
+template <int TW, int TH, int DEPTH>
+__global__ __launch_bounds__(TW * TH) void k_render_fwd(const float4* __restrict__ rec,
                                                         const int32_t* __restrict__ vals,
                                                         const int2* __restrict__ range,
-                                                        const gs_camera* __restrict__ cams, int V, int n_tiles, const int32_t* __restrict__ order,
-                                                        DevOpts op, float* __restrict__ out_rgb,
-                                                        float* __restrict__ out_depth, float* __restrict__ out_vis) {
-  using G = Geo<TW, TH, NW>;
-  constexpr int PPT = G::PPT, RPP = G::RPP;
-  __shared__ Stage<G::BATCH, NW> s;
+                                                        const gs_camera* __restrict__ cams, int V, int n_tiles,
+                                                        const int32_t* __restrict__ order, DevOpts op,
+                                                        float* __restrict__ out_rgb, float* __restrict__ out_depth,
+                                                        float* __restrict__ out_vis) {
+  using G = Geo<TW, TH, DEPTH>;
+  __shared__ Stage<G> s;
   TileCtx t;
   int tile;
   if (!tile_setup<G>(cams, V, n_tiles, order, t, tile)) return;
-  float T[PPT], Cr[PPT], Cg[PPT], Cb[PPT], D[PPT], Vs[PPT];
-  forward_sweep<G>(s, rec, vals, range[tile], t, op, T, Cr, Cg, Cb, D, Vs);
-  const int64_t P = (int64_t)t.W * t.H;
-#pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    const int py = t.py0 + k * RPP;
-    if (t.px < t.W && py < t.H) {
-      const int64_t i = (int64_t)py * t.W + t.px;
-      out_rgb[3 * t.pix_off + i] = __builtin_fmaf(T[k], op.bg[0], Cr[k]);
-      out_rgb[3 * t.pix_off + P + i] = __builtin_fmaf(T[k], op.bg[1], Cg[k]);
-      out_rgb[3 * t.pix_off + 2 * P + i] = __builtin_fmaf(T[k], op.bg[2], Cb[k]);
-      out_depth[t.pix_off + i] = D[k];
-      out_vis[t.pix_off + i] = Vs[k];
-    }
+  float T, Cr, Cg, Cb, D, Vs;
+  forward_sweep<G, DEPTH>(s, rec, vals, range[tile], t, op, T, Cr, Cg, Cb, D, Vs);
+  if (t.inside) {
+    const int64_t P = (int64_t)t.W * t.H;
+    const int64_t i = (int64_t)t.py * t.W + t.px;
+    out_rgb[3 * t.pix_off + i] = __builtin_fmaf(T, op.bg[0], Cr);
+    out_rgb[3 * t.pix_off + P + i] = __builtin_fmaf(T, op.bg[1], Cg);
+    out_rgb[3 * t.pix_off + 2 * P + i] = __builtin_fmaf(T, op.bg[2], Cb);
+    out_depth[t.pix_off + i] = D;
+    out_vis[t.pix_off + i] = Vs;
   }
 }
 
@@ -317,288 +390,407 @@ struct BwdArgs {
   float* loss;
 };
 
-template <int TW, int TH, int NW, bool HAVE_FWD, bool LOSS>
-__global__ __launch_bounds__(64 * NW) void k_render_bwd(const float4* __restrict__ rec,
-                                                        const int32_t* __restrict__ vals,
-                                                        const int2* __restrict__ range,
-                                                        const gs_camera* __restrict__ cams, int V, int n_tiles, const int32_t* __restrict__ order,
-                                                        DevOpts op, BwdArgs a) {
-  using G = Geo<TW, TH, NW>;
-  constexpr int PPT = G::PPT, RPP = G::RPP;
-  __shared__ Stage<G::BATCH, NW> s;
-  TileCtx t;
-  int tile;
-  if (!tile_setup<G>(cams, V, n_tiles, order, t, tile)) return;
-  const int2 rg = range[tile];
+// Depth segments of the fused backward (see k_fused_main).
+struct SegArgs {
+  const int4* items;        // {tile, segment, first slot of the tile or -1, schedule position}
+  const int32_t* counters;  // [192] items, [193] slots of split tiles, [194] split tiles
+  const int32_t* order;
+  const int32_t* seg_count;
+  const int32_t* seg_first;
+  float* seg;               // [slot][6][NT]
+  float* split;             // [split tile][12][NT]
+  int len;                  // records per segment
+};
+
+// Upstream gradient of this pixel from its final values: the L1 loss gradient (eqs. Lc, Ld, L) or the
+// given image gradients.  Adds the pixel's loss to loss_acc.
+template <bool LOSS>
+__device__ __forceinline__ void pixel_upstream(const TileCtx& t, const BwdArgs& a, float Cf, float Gf, float Bf,
+                                               float Df, float& gr, float& gg, float& gb, float& gd, float& gv,
+                                               float& loss_acc) {
+  gr = gg = gb = gd = gv = 0.f;
+  if (!t.inside) return;
   const int64_t P = (int64_t)t.W * t.H;
-  // final values of each pixel
-  float Cf[PPT], Gf[PPT], Bf[PPT], Df[PPT], Vf[PPT];
-  if (HAVE_FWD) {
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      const int py = t.py0 + k * RPP;
-      Cf[k] = Gf[k] = Bf[k] = Df[k] = Vf[k] = 0.f;
-      if (t.px < t.W && py < t.H) {
-        const int64_t i = (int64_t)py * t.W + t.px;
-        Cf[k] = a.fwd_rgb[3 * t.pix_off + i];
-        Gf[k] = a.fwd_rgb[3 * t.pix_off + P + i];
-        Bf[k] = a.fwd_rgb[3 * t.pix_off + 2 * P + i];
-        Df[k] = a.fwd_depth[t.pix_off + i];
-        Vf[k] = a.fwd_vis[t.pix_off + i];
-      }
+  const int64_t pi = (int64_t)t.py * t.W + t.px;
+  if (LOSS) {
+    const float wrgb = t.weight / (3.f * (float)P);
+    const int M = a.n_valid[t.view];
+    const float wd = M > 0 ? t.weight * a.lambda_d / (float)M : 0.f;
+    const float er = Cf - a.tgt_rgb[3 * t.pix_off + pi];
+    const float eg = Gf - a.tgt_rgb[3 * t.pix_off + P + pi];
+    const float eb = Bf - a.tgt_rgb[3 * t.pix_off + 2 * P + pi];
+    gr = wrgb * gsk::sgnf(er);
+    gg = wrgb * gsk::sgnf(eg);
+    gb = wrgb * gsk::sgnf(eb);
+    loss_acc += wrgb * (fabsf(er) + fabsf(eg) + fabsf(eb));
+    const float dt = a.tgt_depth[t.pix_off + pi];
+    if (dt > 0.f) {
+      const float ed = Df - dt;
+      gd = wd * gsk::sgnf(ed);
+      loss_acc += wd * fabsf(ed);
     }
   } else {
-    float T[PPT];
-    forward_sweep<G>(s, rec, vals, rg, t, op, T, Cf, Gf, Bf, Df, Vf);
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      Cf[k] = __builtin_fmaf(T[k], op.bg[0], Cf[k]);
-      Gf[k] = __builtin_fmaf(T[k], op.bg[1], Gf[k]);
-      Bf[k] = __builtin_fmaf(T[k], op.bg[2], Bf[k]);
+    if (a.g_rgb) {
+      gr = a.g_rgb[3 * t.pix_off + pi];
+      gg = a.g_rgb[3 * t.pix_off + P + pi];
+      gb = a.g_rgb[3 * t.pix_off + 2 * P + pi];
     }
+    if (a.g_depth) gd = a.g_depth[t.pix_off + pi];
+    if (a.g_vis) gv = a.g_vis[t.pix_off + pi];
   }
-  // upstream gradient of each pixel
-  float gr[PPT], gg[PPT], gb[PPT], gd[PPT], gv[PPT], S[PPT];
-  float loss_acc = 0.f;
-  float wrgb = 0.f, wd = 0.f;
-  if (LOSS) {
-    wrgb = t.weight / (3.f * (float)P);
-    const int M = a.n_valid[t.view];
-    wd = M > 0 ? t.weight * a.lambda_d / (float)M : 0.f;
-  }
+}
+
+template <class G>
+__device__ __forceinline__ void add_loss(const TileCtx& t, const BwdArgs& a, float loss_acc) {
+  const float ls = gsk::wave_sum_last(loss_acc);
+  if (t.lane == 63) gsk::atomic_add_f32(a.loss, ls);
+}
+
+// Add the LDS partial derivatives of this thread's staged records of the last round to their gradients in
+// HBM and clear them.  Zero partials are skipped (adding zero changes nothing).
+template <class G, int DEPTH>
+__device__ __forceinline__ void flush_grads(Stage<G>& s, float (*gacc)[G::BATCH], float* __restrict__ rgrad) {
 #pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    const int py = t.py0 + k * RPP;
-    gr[k] = gg[k] = gb[k] = gd[k] = gv[k] = 0.f;
-    if (t.px < t.W && py < t.H) {
-      const int64_t i = (int64_t)py * t.W + t.px;
-      if (LOSS) {
-        const float er = Cf[k] - a.tgt_rgb[3 * t.pix_off + i];
-        const float eg = Gf[k] - a.tgt_rgb[3 * t.pix_off + P + i];
-        const float eb = Bf[k] - a.tgt_rgb[3 * t.pix_off + 2 * P + i];
-        gr[k] = wrgb * gsk::sgnf(er);
-        gg[k] = wrgb * gsk::sgnf(eg);
-        gb[k] = wrgb * gsk::sgnf(eb);
-        loss_acc += wrgb * (fabsf(er) + fabsf(eg) + fabsf(eb));
-        const float dt = a.tgt_depth[t.pix_off + i];
-        if (dt > 0.f) {
-          const float ed = Df[k] - dt;
-          gd[k] = wd * gsk::sgnf(ed);
-          loss_acc += wd * fabsf(ed);
-        }
-      } else {
-        if (a.g_rgb) {
-          gr[k] = a.g_rgb[3 * t.pix_off + i];
-          gg[k] = a.g_rgb[3 * t.pix_off + P + i];
-          gb[k] = a.g_rgb[3 * t.pix_off + 2 * P + i];
-        }
-        if (a.g_depth) gd[k] = a.g_depth[t.pix_off + i];
-        if (a.g_vis) gv[k] = a.g_vis[t.pix_off + i];
-      }
-    }
-    S[k] = gr[k] * Cf[k] + gg[k] * Gf[k] + gb[k] * Bf[k] + gd[k] * Df[k] + gv[k] * Vf[k];
-  }
-  if (LOSS) {
-    const float ls = gsk::wave_sum_last(loss_acc);
-    if (t.lane == 63) gsk::atomic_add_f32(a.loss, ls);
-  }
-  // second sweep, front to back
-  bool live[PPT];
-  float fy[PPT], T[PPT], Pp[PPT];
-  const float fx = (float)t.px + 0.5f;
-#pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    const int py = t.py0 + k * RPP;
-    live[k] = t.px < t.W && py < t.H;
-    fy[k] = (float)py + 0.5f;
-    T[k] = 1.f;
-    Pp[k] = 0.f;
-  }
-  // per-record gradient partials of the stream walk, summed in LDS and flushed once per batch
-  __shared__ float gacc[G::BATCH][10];
-  __shared__ int gtouch[G::BATCH];
-  for (int i = threadIdx.x; i < G::BATCH; i += 64 * NW) {
-    gtouch[i] = 0;
-#pragma unroll
-    for (int q = 0; q < 10; ++q) gacc[i][q] = 0.f;
-  }
-  // one (record, pixel) step of the front-to-back walk: returns true if the pair contributed, with its
-  // 10 partial derivatives in acc (added, not overwritten)
-  auto step = [&](const float4& A, const float4& B, const float4& C, int k, float* acc) -> bool {
-    float alpha, Gv, dx, dy;
-    bool cl;
-    if (!eval_pair(A, B, fx, fy[k], op, alpha, Gv, cl, dx, dy)) return false;
-    const float Tn = T[k] * (1.f - alpha);
-    if (Tn < op.t_min) {
-      live[k] = false;
-      return false;
-    }
-    const float w = alpha * T[k];
-    const float qv = gr[k] * B.w + gg[k] * C.x + gb[k] * C.y + gd[k] * A.z + gv[k];
-    Pp[k] += w * qv;
-    const float dalpha = T[k] * qv - (S[k] - Pp[k]) * __builtin_amdgcn_rcpf(1.f - alpha);
-    acc[6] += w * gr[k];
-    acc[7] += w * gg[k];
-    acc[8] += w * gb[k];
-    acc[9] += w * gd[k];
-    if (!cl) {
-      acc[5] += dalpha * Gv;
-      const float dq = dalpha * alpha;
-      acc[2] += -0.5f * dx * dx * dq;
-      acc[3] += -dx * dy * dq;
-      acc[4] += -0.5f * dy * dy * dq;
-      acc[0] += -(B.x * dx + B.y * dy) * dq;
-      acc[1] += -(B.z * dy + B.y * dx) * dq;
-    }
-    T[k] = Tn;
-    return true;
-  };
-  for (int b0 = rg.x; b0 < rg.y; b0 += G::BATCH) {
+  for (int k = 0; k < DEPTH; ++k) {
+    const int j = k * G::NT + (int)threadIdx.x;
+    float v[10];
     bool any = false;
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) any |= live[k];
-    if (!__syncthreads_or(any)) break;
-    const int nb = min(G::BATCH, rg.y - b0);
-    int cover;
-    const int cnt = stage_and_compact<G>(s, rec, vals, b0, nb, t, cover);
-    if (__ballot(any) != 0) {
-      if (use_stream<G>(cnt, cover, op)) {
-        for (int c0 = 0; c0 < cnt; c0 += 64) {
-          uint64_t m = live[0] ? cover_mask(&s.wbox[t.wave][c0], min(64, cnt - c0), t.px, t.py0) : 0ull;
-          int jn = s.list[t.wave][c0 + (m ? __builtin_ctzll(m) : 0)];
-          float4 An = s.A[jn], Bn = s.B[jn], Cn = s.C[jn];
-          while (__ballot(m != 0)) {
-            if (m) {
-              const float4 A = An, B = Bn, C = Cn;
-              const int j = jn;
-              m &= m - 1;
-              jn = s.list[t.wave][c0 + (m ? __builtin_ctzll(m) : 0)];
-              An = s.A[jn];
-              Bn = s.B[jn];
-              Cn = s.C[jn];
-              float acc[10];
-#pragma unroll
-              for (int q = 0; q < 10; ++q) acc[q] = 0.f;
-              if (step(A, B, C, 0, acc)) {
-#pragma unroll
-                for (int q = 0; q < 10; ++q) atomicAdd(&gacc[j][q], acc[q]);
-                gtouch[j] = 1;
-              }
-              if (!live[0]) m = 0;
-            }
-          }
-        }
-      } else {
-        int jn = s.list[t.wave][0];
-        float4 An = s.A[jn], Bn = s.B[jn], Cn = s.C[jn];
-        int jn2 = s.list[t.wave][cnt > 1 ? 1 : 0];
-        for (int i = 0; i < cnt; ++i) {
-          const float4 A = An, B = Bn, C = Cn;
-          const int j = jn;
-          jn = jn2;
-          An = s.A[jn];
-          Bn = s.B[jn];
-          Cn = s.C[jn];
-          jn2 = s.list[t.wave][i + 2 < cnt ? i + 2 : 0];
-          float acc[10];
-#pragma unroll
-          for (int q = 0; q < 10; ++q) acc[q] = 0.f;
-          bool hit = false;
-#pragma unroll
-          for (int k = 0; k < PPT; ++k)
-            if (live[k]) hit |= step(A, B, C, k, acc);
-          const uint64_t hits = __ballot(hit);
-          if (hits != 0) {
-            float* dst = a.rgrad + 12 * (int64_t)s.r[j];
-            if (__popcll(hits) <= 4) {
-              // few contributing lanes: each adds its own partials (no wave reduction)
-              if (hit) {
-#pragma unroll
-                for (int q = 0; q < 10; ++q) gsk::atomic_add_f32(dst + q, acc[q]);
-              }
-            } else {
-#pragma unroll
-              for (int q = 0; q < 10; ++q) {
-                const float sum = gsk::wave_sum_last(acc[q]);
-                if (t.lane == 63) gsk::atomic_add_f32(dst + q, sum);
-              }
-            }
-          }
-        }
-      }
+    for (int q = 0; q < 10; ++q) {
+      v[q] = gacc[q][j];
+      any |= v[q] != 0.f;
     }
-    // flush the LDS partials of this batch (records touched by a stream walk)
-    __syncthreads();
-    for (int i = threadIdx.x; i < nb; i += 64 * NW) {
-      if (gtouch[i]) {
-        float* dst = a.rgrad + 12 * (int64_t)s.r[i];
+    if (any) {
+      float* dst = rgrad + 12 * (int64_t)s.r[j];
 #pragma unroll
-        for (int q = 0; q < 10; ++q) {
-          gsk::atomic_add_f32(dst + q, gacc[i][q]);
-          gacc[i][q] = 0.f;
-        }
-        gtouch[i] = 0;
+      for (int q = 0; q < 10; ++q) {
+        if (v[q] != 0.f) gsk::atomic_add_f32(dst + q, v[q]);
+        gacc[q][j] = 0.f;
       }
     }
   }
 }
 
+// Backward walk of records [rg.x, rg.y) for this lane's pixel, front to back, from transmittance T and
+// prefix P (the pixel's state at rg.x), with upstream gradient g and S = g . (C, D, V) of the final values.
+// Per-record partial derivatives are summed in LDS and added to rgrad once per round.
+template <class G, int DEPTH>
+__device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATCH], const float4* __restrict__ rec,
+                                              const int32_t* __restrict__ vals, int2 rg, const TileCtx& t,
+                                              const DevOpts& op, bool live, float T, float Pp, float gr, float gg,
+                                              float gb, float gd, float gv, float S, float* __restrict__ rgrad) {
+  const float fx = (float)t.px + 0.5f, fy = (float)t.py + 0.5f;
+#pragma unroll
+  for (int k = 0; k < DEPTH; ++k)
+#pragma unroll
+    for (int q = 0; q < 10; ++q) gacc[q][k * G::NT + threadIdx.x] = 0.f;
+  auto step = [&](int, const float4& A, const float4& B, const float4& C, float* acc) -> bool {
+    float alpha, Gv, dx, dy;
+    bool cl;
+    if (!eval_pair(A, B, fx, fy, op, alpha, Gv, cl, dx, dy)) return false;
+    const float Tn = T * (1.f - alpha);
+    if (Tn < op.t_min) {
+      live = false;
+      return false;
+    }
+    const float w = alpha * T;
+    const float qv = gr * B.w + gg * C.x + gb * C.y + gd * A.z + gv;
+    Pp += w * qv;
+    const float dalpha = T * qv - (S - Pp) * __builtin_amdgcn_rcpf(1.f - alpha);
+    acc[6] = w * gr;
+    acc[7] = w * gg;
+    acc[8] = w * gb;
+    acc[9] = w * gd;
+    if (!cl) {
+      acc[5] = dalpha * Gv;
+      const float dq = dalpha * alpha;
+      acc[2] = -0.5f * dx * dx * dq;
+      acc[3] = -dx * dy * dq;
+      acc[4] = -0.5f * dy * dy * dq;
+      acc[0] = -(B.x * dx + B.y * dy) * dq;
+      acc[1] = -(B.z * dy + B.y * dx) * dq;
+    }
+    T = Tn;
+    return true;
+  };
+  // sum the partials of one step into the record's LDS accumulator (whole wave)
+  auto post = [&](int j, bool hit, const float* acc, bool uniform) {
+    const uint64_t hits = __ballot(hit);
+    if (hits == 0) return;
+    const int j0 = uniform ? j : __builtin_amdgcn_readlane(j, __builtin_ctzll(hits));
+    if (__popcll(hits) > 4 && (uniform || __ballot(hit && j != j0) == 0)) {
+      // every contributing lane is on record j0: one wave sum per value
+#pragma unroll
+      for (int q = 0; q < 10; ++q) {
+        const float sum = gsk::wave_sum_last(acc[q]);
+        if (t.lane == 63) atomicAdd(&gacc[q][j0], sum);
+      }
+    } else if (hit) {
+#pragma unroll
+      for (int q = 0; q < 10; ++q) atomicAdd(&gacc[q][j], acc[q]);
+    }
+  };
+  sweep<G, DEPTH, true>(s, rec, vals, rg, t, op, live,
+                        [&](bool not_first) {
+                          if (not_first) flush_grads<G, DEPTH>(s, gacc, rgrad);
+                        },
+                        step, post);
+}
+
+// Forward sweep (or the forward images), upstream gradient, then the backward walk of one whole tile.
+template <class G, int DEPTH, bool HAVE_FWD, bool LOSS>
+__device__ __forceinline__ void tile_backward(Stage<G>& s, float (*gacc)[G::BATCH], const float4* __restrict__ rec,
+                                              const int32_t* __restrict__ vals, int2 rg, const TileCtx& t,
+                                              const DevOpts& op, const BwdArgs& a) {
+  float Cf = 0.f, Gf = 0.f, Bf = 0.f, Df = 0.f, Vf = 0.f;
+  if (HAVE_FWD) {
+    if (t.inside) {
+      const int64_t P = (int64_t)t.W * t.H;
+      const int64_t pi = (int64_t)t.py * t.W + t.px;
+      Cf = a.fwd_rgb[3 * t.pix_off + pi];
+      Gf = a.fwd_rgb[3 * t.pix_off + P + pi];
+      Bf = a.fwd_rgb[3 * t.pix_off + 2 * P + pi];
+      Df = a.fwd_depth[t.pix_off + pi];
+      Vf = a.fwd_vis[t.pix_off + pi];
+    }
+  } else {
+    float T;
+    forward_sweep<G, DEPTH>(s, rec, vals, rg, t, op, T, Cf, Gf, Bf, Df, Vf);
+    Cf = __builtin_fmaf(T, op.bg[0], Cf);
+    Gf = __builtin_fmaf(T, op.bg[1], Gf);
+    Bf = __builtin_fmaf(T, op.bg[2], Bf);
+  }
+  float gr, gg, gb, gd, gv, loss_acc = 0.f;
+  pixel_upstream<LOSS>(t, a, Cf, Gf, Bf, Df, gr, gg, gb, gd, gv, loss_acc);
+  const float S = gr * Cf + gg * Gf + gb * Bf + gd * Df + gv * Vf;
+  if (LOSS) add_loss<G>(t, a, loss_acc);
+  backward_walk<G, DEPTH>(s, gacc, rec, vals, rg, t, op, t.inside, 1.f, 0.f, gr, gg, gb, gd, gv, S, a.rgrad);
+}
+
+template <int TW, int TH, int DEPTH, bool HAVE_FWD, bool LOSS>
+__global__ __launch_bounds__(TW * TH) void k_render_bwd(const float4* __restrict__ rec,
+                                                        const int32_t* __restrict__ vals,
+                                                        const int2* __restrict__ range,
+                                                        const gs_camera* __restrict__ cams, int V, int n_tiles,
+                                                        const int32_t* __restrict__ order, DevOpts op, BwdArgs a) {
+  using G = Geo<TW, TH, DEPTH>;
+  __shared__ Stage<G> s;
+  __shared__ float gacc[10][G::BATCH];
+  TileCtx t;
+  int tile;
+  if (!tile_setup<G>(cams, V, n_tiles, order, t, tile)) return;
+  tile_backward<G, DEPTH, HAVE_FWD, LOSS>(s, gacc, rec, vals, range[tile], t, op, a);
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// Fused backward with depth segments.  A tile list longer than L records is split into segments of L,
+// each its own workgroup, so the few huge tiles of coarse pyramid levels no longer serialise the launch.
+// Compositing is a product of transmittances, so per pixel:
+//   1. each segment k walks its records from T = 1 without the stop rule: its transmittance product T_k and
+//      local sums (C, D, V)_k (k_fused_main, alongside the unsplit tiles);
+//   2. T_start,k = T_0 T_1 ... T_{k-1} (left to right); the pixel's last live segment k* is the last with
+//      T_start,k >= t_min, and only there can the stop rule end the walk: that segment is walked again from
+//      T_start,k* with the stop rule (k_seg_stop);
+//   3. the final values are sum_{k<k*} T_start,k (C, D, V)_k plus segment k*'s stopped sums plus the
+//      background; from them the upstream gradient g, S and each segment's start state (T_start,k,
+//      P_start,k = g . sum_{j<k} contribution_j) (k_seg_combine);
+//   4. each live segment runs the backward walk from its start state (k_seg_bwd).
+// The result equals the unsplit walk up to FP32 rounding of the transmittance product (the association of
+// the product differs), which can move a stop decision that lies within that rounding of t_min.
+template <class G>
+__device__ __forceinline__ int2 segment_range(int2 rg, int k, int L) {
+  const int lo = rg.x + k * L;
+  return make_int2(lo, min(rg.y, lo + L));
+}
+
+template <int TW, int TH, int DEPTH, bool LOSS>
+__global__ __launch_bounds__(TW * TH) void k_fused_main(const float4* __restrict__ rec,
+                                                        const int32_t* __restrict__ vals,
+                                                        const int2* __restrict__ range,
+                                                        const gs_camera* __restrict__ cams, int V, DevOpts op,
+                                                        BwdArgs a, SegArgs g) {
+  using G = Geo<TW, TH, DEPTH>;
+  __shared__ Stage<G> s;
+  __shared__ float gacc[10][G::BATCH];
+  if ((int)blockIdx.x >= g.counters[192]) return;
+  const int4 it = g.items[blockIdx.x];
+  TileCtx t;
+  tile_at<G>(cams, V, it.x, t);
+  const int2 rg = range[it.x];
+  if (it.z < 0) {
+    tile_backward<G, DEPTH, false, LOSS>(s, gacc, rec, vals, rg, t, op, a);
+    return;
+  }
+  float T = 1.f, Cr = 0.f, Cg = 0.f, Cb = 0.f, D = 0.f, Vs = 0.f;
+  forward_walk<G, DEPTH, false>(s, rec, vals, segment_range<G>(rg, it.y, g.len), t, op, t.inside, T, Cr, Cg, Cb, D,
+                                Vs);
+  float* o = g.seg + (size_t)(it.z + it.y) * 6 * G::NT + threadIdx.x;
+  o[0 * G::NT] = T;
+  o[1 * G::NT] = Cr;
+  o[2 * G::NT] = Cg;
+  o[3 * G::NT] = Cb;
+  o[4 * G::NT] = D;
+  o[5 * G::NT] = Vs;
+}
+
+template <int TW, int TH, int DEPTH>
+__global__ __launch_bounds__(TW * TH) void k_seg_stop(const float4* __restrict__ rec, const int32_t* __restrict__ vals,
+                                                      const int2* __restrict__ range,
+                                                      const gs_camera* __restrict__ cams, int V, DevOpts op,
+                                                      SegArgs g) {
+  using G = Geo<TW, TH, DEPTH>;
+  __shared__ Stage<G> s;
+  if ((int)blockIdx.x >= g.counters[193]) return;
+  const int4 it = g.items[blockIdx.x];
+  TileCtx t;
+  tile_at<G>(cams, V, it.x, t);
+  const int2 rg = range[it.x];
+  const int n = (rg.y - rg.x + g.len - 1) / g.len;
+  const float* sp = g.seg + (size_t)it.z * 6 * G::NT + threadIdx.x;
+  float Ts = 1.f;
+  for (int j = 0; j < it.y; ++j) Ts = Ts * sp[(size_t)j * 6 * G::NT];
+  const bool last = t.inside && Ts >= op.t_min &&
+                    (it.y == n - 1 || Ts * sp[(size_t)it.y * 6 * G::NT] < op.t_min);
+  float T = Ts, Cr = 0.f, Cg = 0.f, Cb = 0.f, D = 0.f, Vs = 0.f;
+  forward_walk<G, DEPTH, true>(s, rec, vals, segment_range<G>(rg, it.y, g.len), t, op, last, T, Cr, Cg, Cb, D, Vs);
+  if (last) {
+    float* o = g.split + (size_t)it.w * 12 * G::NT + threadIdx.x;
+    o[0 * G::NT] = T;
+    o[1 * G::NT] = Cr;
+    o[2 * G::NT] = Cg;
+    o[3 * G::NT] = Cb;
+    o[4 * G::NT] = D;
+    o[5 * G::NT] = Vs;
+  }
+}
+
+template <int TW, int TH, bool LOSS>
+__global__ __launch_bounds__(TW * TH) void k_seg_combine(const gs_camera* __restrict__ cams, int V, DevOpts op,
+                                                         BwdArgs a, SegArgs g) {
+  using G = Geo<TW, TH, 1>;
+  const int l = blockIdx.x;
+  if (l >= g.counters[194]) return;
+  const int n = g.seg_count[l];
+  TileCtx t;
+  tile_at<G>(cams, V, g.order[l], t);
+  float* sp = g.seg + (size_t)g.seg_first[l] * 6 * G::NT + threadIdx.x;
+  float* xp = g.split + (size_t)l * 12 * G::NT + threadIdx.x;
+  constexpr size_t SS = 6 * G::NT;
+  // the last live segment
+  int ks = 0;
+  float Tr = 1.f;
+  for (int k = 0; k < n; ++k) {
+    if (Tr >= op.t_min) ks = k;
+    Tr = Tr * sp[k * SS];
+  }
+  // final values
+  float Cr = 0.f, Cg = 0.f, Cb = 0.f, D = 0.f, Vs = 0.f;
+  Tr = 1.f;
+  for (int k = 0; k < ks; ++k) {
+    const float* q = sp + k * SS;
+    Cr = __builtin_fmaf(Tr, q[1 * G::NT], Cr);
+    Cg = __builtin_fmaf(Tr, q[2 * G::NT], Cg);
+    Cb = __builtin_fmaf(Tr, q[3 * G::NT], Cb);
+    D = __builtin_fmaf(Tr, q[4 * G::NT], D);
+    Vs = __builtin_fmaf(Tr, q[5 * G::NT], Vs);
+    Tr = Tr * q[0];
+  }
+  const float Tf = t.inside ? xp[0] : 1.f;
+  const float sr = t.inside ? xp[1 * G::NT] : 0.f, sg = t.inside ? xp[2 * G::NT] : 0.f;
+  const float sb = t.inside ? xp[3 * G::NT] : 0.f, sd = t.inside ? xp[4 * G::NT] : 0.f;
+  const float sv = t.inside ? xp[5 * G::NT] : 0.f;
+  const float Cf = __builtin_fmaf(Tf, op.bg[0], Cr + sr), Gf = __builtin_fmaf(Tf, op.bg[1], Cg + sg);
+  const float Bf = __builtin_fmaf(Tf, op.bg[2], Cb + sb), Df = D + sd, Vf = Vs + sv;
+  float gr, gg, gb, gd, gv, loss_acc = 0.f;
+  pixel_upstream<LOSS>(t, a, Cf, Gf, Bf, Df, gr, gg, gb, gd, gv, loss_acc);
+  const float S = gr * Cf + gg * Gf + gb * Bf + gd * Df + gv * Vf;
+  if (LOSS) add_loss<G>(t, a, loss_acc);
+  // start state of every segment: (T_start, P_start); T_start = 0 marks a segment after the pixel's end
+  Tr = 1.f;
+  float Pr = 0.f;
+  for (int k = 0; k < n; ++k) {
+    float* q = sp + k * SS;
+    const float Tk = q[0];
+    const float dot = k < ks ? Tr * (gr * q[1 * G::NT] + gg * q[2 * G::NT] + gb * q[3 * G::NT] +
+                                     gd * q[4 * G::NT] + gv * q[5 * G::NT])
+                             : 0.f;
+    q[0] = k <= ks ? Tr : 0.f;
+    q[1 * G::NT] = Pr;
+    Pr += dot;
+    Tr = Tr * Tk;
+  }
+  xp[6 * G::NT] = gr;
+  xp[7 * G::NT] = gg;
+  xp[8 * G::NT] = gb;
+  xp[9 * G::NT] = gd;
+  xp[10 * G::NT] = gv;
+  xp[11 * G::NT] = S;
+}
+
+template <int TW, int TH, int DEPTH>
+__global__ __launch_bounds__(TW * TH) void k_seg_bwd(const float4* __restrict__ rec, const int32_t* __restrict__ vals,
+                                                     const int2* __restrict__ range,
+                                                     const gs_camera* __restrict__ cams, int V, DevOpts op,
+                                                     BwdArgs a, SegArgs g) {
+  using G = Geo<TW, TH, DEPTH>;
+  __shared__ Stage<G> s;
+  __shared__ float gacc[10][G::BATCH];
+  if ((int)blockIdx.x >= g.counters[193]) return;
+  const int4 it = g.items[blockIdx.x];
+  TileCtx t;
+  tile_at<G>(cams, V, it.x, t);
+  const float* sp = g.seg + (size_t)(it.z + it.y) * 6 * G::NT + threadIdx.x;
+  const float* xp = g.split + (size_t)it.w * 12 * G::NT + threadIdx.x;
+  const float Ts = sp[0], Ps = sp[1 * G::NT];
+  backward_walk<G, DEPTH>(s, gacc, rec, vals, segment_range<G>(range[it.x], it.y, g.len), t, op,
+                          t.inside && Ts >= op.t_min, Ts, Ps, xp[6 * G::NT], xp[7 * G::NT], xp[8 * G::NT],
+                          xp[9 * G::NT], xp[10 * G::NT], xp[11 * G::NT], a.rgrad);
+}
+
 // Work counts of the forward: pairs evaluated (pixel inside the record's pixel rectangle, up to the
 // pixel's stop) and pairs contributing.  Independent of the tile shape; diagnostic.
-template <int TW, int TH, int NW>
-__global__ __launch_bounds__(64 * NW) void k_count_pairs(const float4* __restrict__ rec,
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_count_pairs(const float4* __restrict__ rec,
                                                          const int32_t* __restrict__ vals,
                                                          const int2* __restrict__ range,
-                                                         const gs_camera* __restrict__ cams, int V, int n_tiles, const int32_t* __restrict__ order,
-                                                         DevOpts op, unsigned long long* __restrict__ counts) {
-  using G = Geo<TW, TH, NW>;
-  constexpr int PPT = G::PPT, RPP = G::RPP;
-  __shared__ Stage<G::BATCH, NW> s;
+                                                         const gs_camera* __restrict__ cams, int V, int n_tiles,
+                                                         const int32_t* __restrict__ order, DevOpts op,
+                                                         unsigned long long* __restrict__ counts) {
+  using G = Geo<TW, TH, 1>;
+  __shared__ Stage<G> s;
   TileCtx t;
   int tile;
   if (!tile_setup<G>(cams, V, n_tiles, order, t, tile)) return;
   const int2 rg = range[tile];
-  bool live[PPT];
-  float fy[PPT], T[PPT];
-  const float fx = (float)t.px + 0.5f;
+  bool live = t.inside;
+  const float fx = (float)t.px + 0.5f, fy = (float)t.py + 0.5f;
+  float T = 1.f;
   unsigned long long ev = 0, co = 0;
-#pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    const int py = t.py0 + k * RPP;
-    live[k] = t.px < t.W && py < t.H;
-    fy[k] = (float)py + 0.5f;
-    T[k] = 1.f;
-  }
   for (int b0 = rg.x; b0 < rg.y; b0 += G::BATCH) {
-    bool any = false;
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) any |= live[k];
-    if (!__syncthreads_or(any)) break;
+    if (!__syncthreads_or(live)) break;
     const int nb = min(G::BATCH, rg.y - b0);
-    int cover;
-    const int cnt = stage_and_compact<G>(s, rec, vals, b0, nb, t, cover);
-    for (int i = 0; i < cnt; ++i) {
-      const int j = s.list[t.wave][i];
-      const float4 A = s.A[j], B = s.B[j], C = s.C[j];
+    if ((int)threadIdx.x < nb) {
+      const int r = vals[b0 + threadIdx.x];
+      s.A[threadIdx.x] = rec[3 * (int64_t)r];
+      s.B[threadIdx.x] = rec[3 * (int64_t)r + 1];
+      s.C[threadIdx.x] = rec[3 * (int64_t)r + 2];
+    }
+    __syncthreads();
+    for (int j = 0; j < nb && live; ++j) {
       int x0, x1, y0, y1;
-      unpack_rect(C, x0, x1, y0, y1);
-#pragma unroll
-      for (int k = 0; k < PPT; ++k) {
-        if (!live[k]) continue;
-        const int py = t.py0 + k * RPP;
-        if (t.px < x0 || t.px > x1 || py < y0 || py > y1) continue;
-        ++ev;
-        float alpha, Gv, dx, dy;
-        bool cl;
-        if (!eval_pair(A, B, fx, fy[k], op, alpha, Gv, cl, dx, dy)) continue;
-        const float Tn = T[k] * (1.f - alpha);
-        if (Tn < op.t_min) {
-          live[k] = false;
-          continue;
-        }
-        ++co;
-        T[k] = Tn;
+      unpack_rect(s.C[j], x0, x1, y0, y1);
+      if (t.px < x0 || t.px > x1 || t.py < y0 || t.py > y1) continue;
+      ++ev;
+      float alpha, Gv, dx, dy;
+      bool cl;
+      if (!eval_pair(s.A[j], s.B[j], fx, fy, op, alpha, Gv, cl, dx, dy)) continue;
+      const float Tn = T * (1.f - alpha);
+      if (Tn < op.t_min) {
+        live = false;
+        continue;
       }
+      ++co;
+      T = Tn;
     }
   }
   atomicAdd(counts, ev);
@@ -623,41 +815,69 @@ __global__ __launch_bounds__(256) void k_count_valid(const float* __restrict__ t
   if (threadIdx.x == 0 && sh) atomicAdd(n_valid + v, sh);
 }
 
-template <int TW, int TH, int NW>
+template <int TW, int TH, int DEPTH>
 hipError_t launch_fwd(const gs_frame& f, const DevOpts& op, const gs_images& out, hipStream_t st) {
   const int sorted = f.sort_passes & 1;
-  k_render_fwd<TW, TH, NW><<<f.n_tiles, 64 * NW, 0, st>>>(
+  k_render_fwd<TW, TH, DEPTH><<<f.n_tiles, TW * TH, 0, st>>>(
       reinterpret_cast<const float4*>(f.rec), f.vals[sorted], reinterpret_cast<const int2*>(f.tile_range), f.cams,
       f.n_views, f.n_tiles, f.tile_order, op, out.rgb, out.depth, out.vis);
   return hipGetLastError();
 }
 
-template <int TW, int TH, int NW>
+template <int TW, int TH, int DEPTH>
 hipError_t launch_bwd(const gs_frame& f, const DevOpts& op, bool have_fwd, bool loss, const BwdArgs& a,
                       hipStream_t st) {
   const int sorted = f.sort_passes & 1;
   const auto* rec = reinterpret_cast<const float4*>(f.rec);
   const auto* rng = reinterpret_cast<const int2*>(f.tile_range);
-  const int nb = f.n_tiles, bs = 64 * NW;
+  const int nb = f.n_tiles, bs = TW * TH;
   const int32_t* vals = f.vals[sorted];
+  if (!have_fwd && f.seg_len > 0) {
+    // fused, with long lists split into depth segments
+    SegArgs g;
+    g.items = reinterpret_cast<const int4*>(f.items);
+    g.counters = f.counters;
+    g.order = f.tile_order;
+    g.seg_count = f.seg_count;
+    g.seg_first = f.seg_first;
+    g.seg = f.seg;
+    g.split = f.split;
+    g.len = f.seg_len;
+    if (loss)
+      k_fused_main<TW, TH, DEPTH, true><<<f.item_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g);
+    else
+      k_fused_main<TW, TH, DEPTH, false><<<f.item_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_seg_stop<TW, TH, DEPTH><<<f.seg_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, g);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (loss)
+      k_seg_combine<TW, TH, true><<<f.long_cap, bs, 0, st>>>(f.cams, f.n_views, op, a, g);
+    else
+      k_seg_combine<TW, TH, false><<<f.long_cap, bs, 0, st>>>(f.cams, f.n_views, op, a, g);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_seg_bwd<TW, TH, DEPTH><<<f.seg_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g);
+    return hipGetLastError();
+  }
   if (have_fwd && loss)
-    k_render_bwd<TW, TH, NW, true, true><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb, f.tile_order, op, a);
+    k_render_bwd<TW, TH, DEPTH, true, true><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb, f.tile_order,
+                                                               op, a);
   else if (have_fwd)
-    k_render_bwd<TW, TH, NW, true, false><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb, f.tile_order, op,
-                                                             a);
+    k_render_bwd<TW, TH, DEPTH, true, false><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb,
+                                                                f.tile_order, op, a);
   else if (loss)
-    k_render_bwd<TW, TH, NW, false, true><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb, f.tile_order, op,
-                                                             a);
+    k_render_bwd<TW, TH, DEPTH, false, true><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb,
+                                                                f.tile_order, op, a);
   else
-    k_render_bwd<TW, TH, NW, false, false><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb, f.tile_order,
-                                                              op, a);
+    k_render_bwd<TW, TH, DEPTH, false, false><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb,
+                                                                 f.tile_order, op, a);
   return hipGetLastError();
 }
 
-template <int TW, int TH, int NW>
+template <int TW, int TH>
 hipError_t launch_count(const gs_frame& f, const DevOpts& op, unsigned long long* counts, hipStream_t st) {
   const int sorted = f.sort_passes & 1;
-  k_count_pairs<TW, TH, NW><<<f.n_tiles, 64 * NW, 0, st>>>(
+  k_count_pairs<TW, TH><<<f.n_tiles, TW * TH, 0, st>>>(
       reinterpret_cast<const float4*>(f.rec), f.vals[sorted], reinterpret_cast<const int2*>(f.tile_range), f.cams,
       f.n_views, f.n_tiles, f.tile_order, op, counts);
   return hipGetLastError();
@@ -667,31 +887,19 @@ hipError_t launch_count(const gs_frame& f, const DevOpts& op, unsigned long long
 
 namespace gs_launch {
 
-// Tile shape and waves per tile (o.waves_per_tile; 0 picks 4 where the shape allows it).
-#define GS_TILE_DISPATCH(FN, ...)                                 \
-  do {                                                            \
-    const int nw = o.waves_per_tile;                              \
-    if (o.tile_w == 16 && o.tile_h == 16) {                       \
-      if (nw == 1) return FN<16, 16, 1>(__VA_ARGS__);             \
-      if (nw == 2) return FN<16, 16, 2>(__VA_ARGS__);             \
-      return FN<16, 16, 4>(__VA_ARGS__);                          \
-    }                                                             \
-    if (o.tile_w == 16 && o.tile_h == 8) {                        \
-      if (nw == 1) return FN<16, 8, 1>(__VA_ARGS__);              \
-      return FN<16, 8, 2>(__VA_ARGS__);                           \
-    }                                                             \
-    if (o.tile_w == 8 && o.tile_h == 8) return FN<8, 8, 1>(__VA_ARGS__); \
-    if (o.tile_w == 32 && o.tile_h == 8) {                        \
-      if (nw == 1) return FN<32, 8, 1>(__VA_ARGS__);              \
-      if (nw == 2) return FN<32, 8, 2>(__VA_ARGS__);              \
-      return FN<32, 8, 4>(__VA_ARGS__);                           \
-    }                                                             \
-    if (o.tile_w == 32 && o.tile_h == 16) {                       \
-      if (nw == 1) return FN<32, 16, 1>(__VA_ARGS__);             \
-      if (nw == 2) return FN<32, 16, 2>(__VA_ARGS__);             \
-      return FN<32, 16, 4>(__VA_ARGS__);                          \
-    }                                                             \
-    return hipErrorInvalidValue;                                  \
+// Tile shape (one wave per 8x8 sub-tile) and records staged per thread (o.batch_depth; 0 means 1).
+#define GS_TILE_DISPATCH_D(FN, TW, TH, ...)                    \
+  do {                                                         \
+    if (o.batch_depth == 2) return FN<TW, TH, 2>(__VA_ARGS__); \
+    return FN<TW, TH, 1>(__VA_ARGS__);                         \
+  } while (0)
+#define GS_TILE_DISPATCH(FN, ...)                                                      \
+  do {                                                                                 \
+    if (o.tile_w == 16 && o.tile_h == 16) GS_TILE_DISPATCH_D(FN, 16, 16, __VA_ARGS__); \
+    if (o.tile_w == 16 && o.tile_h == 8) GS_TILE_DISPATCH_D(FN, 16, 8, __VA_ARGS__);   \
+    if (o.tile_w == 8 && o.tile_h == 8) GS_TILE_DISPATCH_D(FN, 8, 8, __VA_ARGS__);     \
+    if (o.tile_w == 32 && o.tile_h == 8) GS_TILE_DISPATCH_D(FN, 32, 8, __VA_ARGS__);   \
+    return hipErrorInvalidValue;                                                       \
   } while (0)
 
 hipError_t render_fwd(const gs_frame& f, const gs_opts& o, const gs_images& out, hipStream_t st) {
@@ -701,7 +909,11 @@ hipError_t render_fwd(const gs_frame& f, const gs_opts& o, const gs_images& out,
 
 hipError_t count_pairs(const gs_frame& f, const gs_opts& o, unsigned long long* counts, hipStream_t st) {
   const DevOpts op = gsk::dev_opts(o);
-  GS_TILE_DISPATCH(launch_count, f, op, counts, st);
+  if (o.tile_w == 16 && o.tile_h == 16) return launch_count<16, 16>(f, op, counts, st);
+  if (o.tile_w == 16 && o.tile_h == 8) return launch_count<16, 8>(f, op, counts, st);
+  if (o.tile_w == 8 && o.tile_h == 8) return launch_count<8, 8>(f, op, counts, st);
+  if (o.tile_w == 32 && o.tile_h == 8) return launch_count<32, 8>(f, op, counts, st);
+  return hipErrorInvalidValue;
 }
 
 hipError_t count_valid(const gs_frame& f, const float* tgt_depth, int64_t max_pixels, hipStream_t st) {

@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_struct_layouts(lib):
     assert ctypes.sizeof(B.gs_camera) == 128
-    assert ctypes.sizeof(B.gs_opts) == 56
+    assert ctypes.sizeof(B.gs_opts) == 64
     assert ctypes.sizeof(B.gs_params) == 56
     assert lib.gs_version() == 1
 
@@ -75,6 +75,11 @@ def test_plan_cameras_offsets_and_guard(lib):
     assert b"intrinsics" in lib.gs_last_error()
     o2 = B.default_opts(tile_w=12)
     assert lib.gs_plan_cameras(arr, 3, ctypes.byref(o2)) == -1
+    # waves per tile follow the tile shape (one per 8x8 sub-tile); batch depth is 1 or 2
+    for over, ok in [(dict(tile_w=32, tile_h=8, waves_per_tile=4), True), (dict(waves_per_tile=2), False),
+                     (dict(tile_w=32, tile_h=16), False), (dict(batch_depth=2), True), (dict(batch_depth=3), False),
+                     (dict(scatter_max=-5), True)]:
+        assert (lib.gs_plan_cameras(arr, 3, ctypes.byref(B.default_opts(**over))) == 0) == ok, over
 
 
 def test_frame_layout_on_host(lib):
@@ -89,10 +94,18 @@ def test_frame_layout_on_host(lib):
     base = 1 << 20  # carving is pure host arithmetic: any 256-aligned address works
     assert lib.gs_frame_init(ctypes.byref(f), base, nbytes, n, arr, base, 2, ctypes.byref(o), cap) == 0
     ptrs = sorted([f.rec, f.rect, f.rgrad, f.vis_mask, f.n_inst, f.inst_off, f.keys[0], f.keys[1], f.vals[0],
-                   f.vals[1], f.tile_range, f.counters, f.loss, f.scratch])
+                   f.vals[1], f.tile_range, f.counters, f.seg_count, f.seg_first, f.items, f.seg, f.split, f.loss,
+                   f.scratch])
     assert all(p % 256 == 0 for p in ptrs) and ptrs[0] == base and ptrs[-1] < base + nbytes
     total_tiles = sum(c.tiles_x * c.tiles_y for c in arr)
     assert f.n_tiles == total_tiles and f.key_bits == 32 + max(1, int(np.ceil(np.log2(total_tiles))))
+    # depth segments of the fused backward: default length 2048, capacities bound every split
+    assert f.seg_len == 2048 and f.seg_cap == 2 * cap // 2048 + 2 and f.long_cap == cap // 2048 + 1
+    assert f.item_cap == total_tiles + f.seg_cap
+    o2 = B.default_opts(seg_len=-1)
+    f2 = B.gs_frame()
+    assert lib.gs_frame_init(ctypes.byref(f2), base, nbytes, n, arr, base, 2, ctypes.byref(o2), cap) == 0
+    assert f2.seg_len == 0 and f2.seg_cap == 0 and f2.item_cap == total_tiles
     assert f.sort_passes == -(-f.key_bits // 8)
     assert lib.gs_frame_init(ctypes.byref(f), base, nbytes - 1, n, arr, base, 2, ctypes.byref(o), cap) == -3
     assert lib.gs_frame_init(ctypes.byref(f), base + 8, nbytes, n, arr, base, 2, ctypes.byref(o), cap) == -1
@@ -123,3 +136,33 @@ def test_oracle_defaults_match_library_defaults(lib):
         lib_v = getattr(o, "near_z" if k == "near" else k)
         assert np.float32(d[k]) == np.float32(lib_v), k
     assert (d["tile_w"], d["tile_h"]) == (o.tile_w, o.tile_h)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """Every field of the ctypes mirrors sits at the offset the C compiler gives it in include/libgs.h."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [B.gs_camera, B.gs_opts, B.gs_params, B.gs_frame, B.gs_images, B.gs_loss, B.gs_adam]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "libgs.h"', "int main(void) {"]
+    for st in structs:
+        name = st.__name__
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for fname, _ in st._fields_:
+            lines.append(f'  printf("{name} {fname} %zu\\n", offsetof({name}, {fname}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for st in structs:
+        name = st.__name__
+        assert got[(name, "size")] == ctypes.sizeof(st), name
+        for fname, _ in st._fields_:
+            assert got[(name, fname)] == getattr(st, fname).offset, (name, fname)

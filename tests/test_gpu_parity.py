@@ -28,11 +28,12 @@ def log(*a):
     print(*a, flush=True)
 
 
-def run_gpu(sc, tile=(16, 16), g_images=None, targets=True, fused=False, capacity=None, zero=True, nw=0):
+def run_gpu(sc, tile=(16, 16), g_images=None, targets=True, fused=False, capacity=None, zero=True, smax=0, depth=0,
+            seg=0):
     """Project, bin, render and (optionally) backpropagate one scene; returns numpy results."""
     torch.cuda.synchronize()
     model = GaussianModel(sc.params(), sc.sh_degree)
-    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], waves_per_tile=nw)
+    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], scatter_max=smax, batch_depth=depth, seg_len=seg)
     fr = B.Frame(model.n, sc.cams, opts, capacity)
     B.gs_project(model.ps, fr, zero_grads=zero)
     n_inst = B.gs_bin_tiles(fr, sync_count=True)
@@ -215,13 +216,15 @@ def test_forward_is_tile_size_invariant_and_deterministic(gpu_lib):
     again = run_gpu(sc, targets=False)
     for k in ("rgb", "depth", "vis"):
         assert np.array_equal(base[k], again[k]), k
-    for tile, nw in [((16, 16), 1), ((16, 16), 2), ((8, 8), 1), ((16, 8), 1), ((16, 8), 2), ((32, 8), 1),
-                     ((32, 8), 2), ((32, 8), 4), ((32, 16), 1), ((32, 16), 2), ((32, 16), 4)]:
-        log("tile", tile, "waves", nw)
-        o = run_gpu(sc, tile=tile, targets=False, nw=nw)
-        for k in ("rgb", "depth", "vis"):
-            d = np.abs(base[k] - o[k])
-            assert np.array_equal(base[k], o[k]), (tile, nw, k, int((d > 0).sum()), float(d.max()))
+    # tile shapes, records per thread and the per-pixel hand-out threshold (-1: every record is walked by
+    # all lanes of the sub-tiles it meets; 64: every record is handed to its pixels only)
+    for tile in [(16, 16), (8, 8), (16, 8), (32, 8)]:
+        for depth, smax in [(1, 0), (2, 0), (1, -1), (2, 64)]:
+            log("tile", tile, "depth", depth, "scatter_max", smax)
+            o = run_gpu(sc, tile=tile, targets=False, smax=smax, depth=depth)
+            for k in ("rgb", "depth", "vis"):
+                d = np.abs(base[k] - o[k])
+                assert np.array_equal(base[k], o[k]), (tile, depth, smax, k, int((d > 0).sum()), float(d.max()))
 
 
 # ----------------------------------------------------------------------------- backward
@@ -385,12 +388,13 @@ def test_pair_counts_match_oracle(gpu_lib):
     assert ev >= co
 
 
-@pytest.mark.parametrize("nw", [1, 2, 4])
-def test_backward_identical_across_waves_per_tile(gpu_lib, nw):
-    """Gradients agree (to atomic summation order) whatever the number of waves per tile."""
+@pytest.mark.parametrize("tile,depth,smax", [((16, 16), 1, 0), ((16, 16), 2, 64), ((8, 8), 2, 0), ((32, 8), 1, 4),
+                                              ((16, 8), 1, 0)])
+def test_backward_identical_across_walk_options(gpu_lib, tile, depth, smax):
+    """Gradients agree (to atomic summation order) whatever the tile shape, batch depth and hand-out rule."""
     sc = scenes.random_scene(1500, 2000, 100, 70, sh_degree=1, views=2, log_scale_mu=-2.3, depth_fraction=0.3)
-    ref = run_gpu(sc, targets=True, fused=True, nw=1)
-    out = run_gpu(sc, targets=True, fused=True, nw=nw)
+    ref = run_gpu(sc, targets=True, fused=True, smax=-1)
+    out = run_gpu(sc, targets=True, fused=True, tile=tile, depth=depth, smax=smax)
     np.testing.assert_allclose(out["loss"], ref["loss"], rtol=1e-6)
     for k in ref["grads"]:
         a, b = ref["grads"][k], out["grads"][k]
@@ -412,37 +416,104 @@ def test_tile_schedule_is_a_longest_first_permutation(gpu_lib):
 
 
 def _subpixel_scene(seed, n=20000, W=64, H=48, views=1, deg=0):
-    # many sub-pixel Gaussians per tile: the case the per-pixel stream walk is for
+    # many sub-pixel Gaussians per tile: most records are handed to a few pixels each
     return scenes.random_scene(seed, n, W, H, sh_degree=deg, views=views, log_scale_mu=-5.0, log_scale_sigma=0.3,
                                opacity_sigma=0.5, depth_fraction=0.5)
 
 
-def test_stream_walk_matches_dense_walk_and_oracle(gpu_lib):
+def test_per_pixel_walk_matches_shared_walk_and_oracle(gpu_lib):
     sc = _subpixel_scene(1700, views=2)
-    dense = run_gpu(sc, tile=(16, 16), nw=1, targets=False)  # four pixels per lane: always the dense walk
-    for tile, nw in [((16, 16), 4), ((8, 8), 1), ((32, 8), 4), ((16, 8), 2)]:
-        o = run_gpu(sc, tile=tile, nw=nw, targets=False)
+    shared = run_gpu(sc, tile=(16, 16), smax=-1, targets=False)  # every record walked by whole sub-tiles
+    for tile, depth, smax in [((16, 16), 1, 0), ((8, 8), 2, 0), ((32, 8), 1, 64), ((16, 8), 2, 4)]:
+        o = run_gpu(sc, tile=tile, depth=depth, smax=smax, targets=False)
         for k in ("rgb", "depth", "vis"):
-            assert np.array_equal(dense[k], o[k]), (tile, nw, k)
-    dense["cams"] = sc.cams
+            assert np.array_equal(shared[k], o[k]), (tile, depth, smax, k)
+    shared["cams"] = sc.cams
     ref = oracle.forward(32, sc.params(), 0, sc.cams)
-    check_images(dense, ref, ref["near"], "sub-pixel fwd")
-    ev, co = B.gs_count_pairs(dense["frame"])
-    log("sub-pixel scene: instances", dense["n_inst"], "evaluated", ev, "contributing", co)
+    check_images(shared, ref, ref["near"], "sub-pixel fwd")
+    ev, co = B.gs_count_pairs(shared["frame"])
+    log("sub-pixel scene: instances", shared["n_inst"], "evaluated", ev, "contributing", co)
 
 
 @pytest.mark.parametrize("fused", [False, True])
-def test_stream_walk_backward_matches_fp64_oracle(gpu_lib, fused):
+def test_per_pixel_walk_backward_matches_fp64_oracle(gpu_lib, fused):
     sc = _subpixel_scene(1800, n=12000, views=2, deg=1)
-    out = run_gpu(sc, targets=True, fused=fused, tile=(16, 16), nw=4)
+    out = run_gpu(sc, targets=True, fused=fused, tile=(16, 16))
     L, ref, exc, nn, _ = oracle.backward(64, sc.params(), 1, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
     np.testing.assert_allclose(out["loss"], L, rtol=1e-5)
     check_grads(out["grads"], ref, exc, f"sub-pixel fused={fused}", nn, sc.total_pixels)
-    # the stream walk sums partials in another order; rotation gradients of near-isotropic sub-pixel
+    # the per-pixel walk sums partials in another order; rotation gradients of near-isotropic sub-pixel
     # Gaussians are ill-conditioned in FP32, hence 1e-4 here (both sides are within 1e-3 of FP64 above)
-    dense = run_gpu(sc, targets=True, fused=fused, tile=(16, 16), nw=1)
-    for k in dense["grads"]:
-        a, b = dense["grads"][k], out["grads"][k]
+    shared = run_gpu(sc, targets=True, fused=fused, tile=(16, 16), smax=-1)
+    for k in shared["grads"]:
+        a, b = shared["grads"][k], out["grads"][k]
         rms = np.sqrt((a.astype(np.float64) ** 2).mean()) + 1e-30
         err = np.abs(a - b) / (np.abs(a) + rms)
         assert err.max() <= 1e-4, (k, float(err.max()))
+
+
+# ----------------------------------------------------------------------------- depth segments
+def _split_counts(out):
+    c = B.frame_tensor(out["frame"], "counters", 256, torch.int32).cpu().numpy()
+    return int(c[192]), int(c[193]), int(c[194])
+
+
+@pytest.mark.parametrize("tile,seg", [((16, 16), 64), ((16, 16), 256), ((8, 8), 96), ((16, 8), 128)])
+def test_split_fused_backward_matches_fp64_oracle_and_unsplit(gpu_lib, tile, seg):
+    """Tile lists split into depth segments: loss and gradients agree with the FP64 oracle (1e-3) and with the
+    unsplit walk (the transmittance product is re-associated, so FP32 rounding differs slightly)."""
+    sc = _subpixel_scene(1900, n=12000, views=2, deg=1)
+    out = run_gpu(sc, targets=True, fused=True, tile=tile, seg=seg)
+    items, slots, longs = _split_counts(out)
+    log("split", tile, seg, "items", items, "slots", slots, "split tiles", longs)
+    assert longs > 0 and slots > longs
+    L, ref, exc, nn, _ = oracle.backward(64, sc.params(), 1, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
+    np.testing.assert_allclose(out["loss"], L, rtol=1e-5)
+    check_grads(out["grads"], ref, exc, f"split {tile} {seg}", nn, sc.total_pixels)
+    whole = run_gpu(sc, targets=True, fused=True, tile=tile, seg=-1)
+    np.testing.assert_allclose(out["loss"], whole["loss"], rtol=1e-5)
+    for k in whole["grads"]:
+        a, b = whole["grads"][k], out["grads"][k]
+        rms = np.sqrt((a.astype(np.float64) ** 2).mean()) + 1e-30
+        err = np.abs(a - b) / (np.abs(a) + rms)
+        assert err.max() <= 1e-4, (k, float(err.max()))
+
+
+def test_split_with_upstream_gradients_and_dense_scene(gpu_lib):
+    """Split walk in upstream-gradient mode on a scene whose pixels saturate (stops inside segments)."""
+    sc = scenes.random_scene(1950, 4000, 96, 64, sh_degree=2, views=2, log_scale_mu=-1.8, opacity_sigma=0.8)
+    rng = np.random.default_rng(5)
+    P = sc.total_pixels
+    g = tuple(rng.normal(size=m * P).astype(np.float32) for m in (3, 1, 1))
+    out = run_gpu(sc, g_images=g, fused=True, seg=64)
+    items, slots, longs = _split_counts(out)
+    assert longs > 0
+    _, ref, exc, nn, _ = oracle.backward(64, sc.params(), 2, sc.cams, g_rgb=g[0], g_depth=g[1], g_vis=g[2])
+    check_grads(out["grads"], ref, exc, "split upstream", nn, P)
+
+
+def test_split_batched_step_matches_unsplit(gpu_lib):
+    """The batched step with split tiles: same loss and gradients as the unsplit step, eager and replayed."""
+    sc = _subpixel_scene(1960, n=8000, views=3, deg=1)
+    res = []
+    for seg in (-1, 64):
+        model = GaussianModel(sc.params(), sc.sh_degree)
+        st = BatchedStep(model, sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=B.default_opts(seg_len=seg))
+        st.run_eager()
+        torch.cuda.synchronize()
+        grads = {k: v.cpu().numpy() for k, v in model.g.items()}
+        loss0 = st.loss()
+        st.capture()
+        losses = []
+        for _ in range(3):
+            st.run()
+            losses.append(st.loss())
+        assert not st.overflowed()
+        res.append((loss0, grads, losses))
+    np.testing.assert_allclose(res[1][0], res[0][0], rtol=1e-5)
+    for k in res[0][1]:
+        a, b = res[0][1][k], res[1][1][k]
+        rms = np.sqrt((a.astype(np.float64) ** 2).mean()) + 1e-30
+        err = np.abs(a - b) / (np.abs(a) + rms)
+        assert err.max() <= 1e-4, (k, float(err.max()))
+    np.testing.assert_allclose(res[1][2], res[0][2], rtol=1e-3)

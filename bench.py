@@ -59,10 +59,10 @@ def measure(sc, steps, warmup, plain_steps, do_plain, tile=None):
         tile, _ = autotune.tune_batched(
             lambda o: BatchedStep(GaussianModel(sc.params(), sc.sh_degree), sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=o),
             sc.n, sc.cams, sc.sh_degree, log=log)
-    tile = tuple(tile) + (1, 0)[len(tile) - 2:] if len(tile) < 4 else tuple(tile)
-    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], batch_depth=tile[2], scatter_max=tile[3])
+    tile = tuple(tile) + (1, 0, 0)[len(tile) - 2:] if len(tile) < 5 else tuple(tile)
+    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], batch_depth=tile[2], scatter_max=tile[3], seg_len=tile[4])
     log(f"  configuration: {tile[0]}x{tile[1]} tiles, {tile[2]} records per thread per round, "
-        f"scatter_max {tile[3]}")
+        f"scatter_max {tile[3]}, seg_len {tile[4]}")
     model = GaussianModel(sc.params(), sc.sh_degree)
     t0 = time.time()
     bat = BatchedStep(model, sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=opts)
@@ -84,6 +84,38 @@ def measure(sc, steps, warmup, plain_steps, do_plain, tile=None):
         res["plain_ms"] = pms
         log(f"  plain:   {pms:.3f} ms/step ({1000 / pms:.2f} it/s)")
     return res
+
+
+TRAFFIC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "fused_composite_cfg4_traffic.md")
+
+
+def measured_traffic(tile):
+    """HBM bytes per launch of the fused compositing group from the committed counter summary, if it was
+    taken for this configuration and the compositing sources have not changed since; else None."""
+    import hashlib
+    import re
+
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(re.findall(r"^(\w+): (\S+)$", text, re.M))
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2411_02703_amd", "csrc")
+    for f in ("render.hip", "common.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("source_sha256") != h.hexdigest() or fields.get("config") != ",".join(str(x) for x in tile):
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
+def kernel_label(tile):
+    tw, th, dp, _, sg = tile
+    if sg is not None and sg < 0:
+        return f"k_render_bwd<{tw},{th},{dp},fused,loss> (forward sweep + loss + backward sweep)"
+    return (f"k_fused_main<{tw},{th},{dp},loss> + k_seg_stop + k_seg_combine + k_seg_bwd (forward sweep + loss + "
+            f"backward sweep; tile lists split into depth segments)")
 
 
 def dominant_kernel(res, steps):
@@ -134,9 +166,9 @@ def main():
     ap.add_argument("--no-cfg3", action="store_true")
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count (smaller trial runs)")
     ap.add_argument("--tile", type=str, default=None,
-                    help="tile_w,tile_h,batch_depth,scatter_max (skips the autotuner)")
+                    help="tile_w,tile_h[,batch_depth,scatter_max,seg_len] (skips the autotuner)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
-                    help="also run a plain device copy of MIB MiB three times (the known-size kernel that scales "
+                    help="also run a plain copy kernel over MIB MiB three times (the known-size kernel that scales "
                          "FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -166,7 +198,7 @@ def main():
         src = torch.ones(args.copy_calib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)  # one elementwise kernel: reads and writes MIB MiB
         torch.cuda.synchronize()
         log(f"  copy calibration: 3 x {args.copy_calib} MiB device copies")
         del src, dst
@@ -188,16 +220,16 @@ def main():
                                 "one HIP-graph replay per step"),
                    "gaussians": sc4.n, "views": len(sc4.cams), "pixels": sc4.total_pixels,
                    "instances": r4["n_instances"], "tile": list(r4["tile"][:2]), "batch_depth": r4["tile"][2],
-                   "scatter_max": r4["tile"][3]},
+                   "scatter_max": r4["tile"][3], "seg_len": r4["tile"][4]},
     }
     if "plain_ms" in r4:
         out["plain"] = {"value": round(1000.0 / r4["plain_ms"], 3), "ms_per_step": round(r4["plain_ms"], 4),
                         "steps": args.plain_steps}
         out["batched_over_plain"] = round(r4["plain_ms"] / r4["ms"], 3)
     out["roofline"] = {"bound": "alu", "achieved": round(dk["achieved"] / 1e12, 3), "peak": round(ALU_PEAK / 1e12, 3),
-                       "unit": "T lane-op/s", "frac": round(dk["achieved"] / ALU_PEAK, 4), "traffic": None,
-                       "kernel": (f"k_render_bwd<{r4['tile'][0]},{r4['tile'][1]},depth {r4['tile'][2]},fused loss> "
-                                  "(forward sweep + loss + backward sweep)"),
+                       "unit": "T lane-op/s", "frac": round(dk["achieved"] / ALU_PEAK, 4),
+                       "traffic": measured_traffic(r4["tile"]),
+                       "kernel": kernel_label(r4["tile"]),
                        "kernel_ms": round(dk["ms"], 4), "pairs_evaluated": dk["evaluated"],
                        "pairs_contributing": dk["contributing"]}
     if not args.no_cfg3:

@@ -96,7 +96,7 @@ typedef struct gs_opts {
   int32_t seg_len;        /* fused backward (gs_render_bwd without forward images): a tile list longer than
                              this is split into depth segments of this many records, composited by separate
                              workgroups and joined per pixel (transmittance products, then prefix sums); 0 =
-                             default 2048, < 0 = never split.  Fixed per frame by gs_frame_init.  Results agree
+                             default 512, < 0 = never split.  Fixed per frame by gs_frame_init.  Results agree
                              with the unsplit walk up to FP32 rounding of the transmittance product */
   int32_t reserved[1];
 } gs_opts;

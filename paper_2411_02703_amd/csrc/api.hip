@@ -46,7 +46,7 @@ struct Layout {
 };
 
 // Depth-segment length of the fused backward for these options (0: never split).
-int seg_len_of(const gs_opts* o) { return o->seg_len == 0 ? 2048 : (o->seg_len < 0 ? 0 : o->seg_len); }
+int seg_len_of(const gs_opts* o) { return o->seg_len == 0 ? 512 : (o->seg_len < 0 ? 0 : o->seg_len); }
 
 int opts_check(const gs_opts* o) {
   if (!o) return fail(GS_ERR_ARG, "opts is NULL");

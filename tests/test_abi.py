@@ -99,8 +99,8 @@ def test_frame_layout_on_host(lib):
     assert all(p % 256 == 0 for p in ptrs) and ptrs[0] == base and ptrs[-1] < base + nbytes
     total_tiles = sum(c.tiles_x * c.tiles_y for c in arr)
     assert f.n_tiles == total_tiles and f.key_bits == 32 + max(1, int(np.ceil(np.log2(total_tiles))))
-    # depth segments of the fused backward: default length 2048, capacities bound every split
-    assert f.seg_len == 2048 and f.seg_cap == 2 * cap // 2048 + 2 and f.long_cap == cap // 2048 + 1
+    # depth segments of the fused backward: default length 512, capacities bound every split
+    assert f.seg_len == 512 and f.seg_cap == 2 * cap // 512 + 2 and f.long_cap == cap // 512 + 1
     assert f.item_cap == total_tiles + f.seg_cap
     o2 = B.default_opts(seg_len=-1)
     f2 = B.gs_frame()

@@ -93,11 +93,11 @@ typedef struct gs_opts {
                              0 = default 16, < 0 = never hand out per pixel.  Results are identical for every
                              value (a record is skipped only where its box misses the pixel) */
   int32_t batch_depth;    /* records staged per thread per round: 1 or 2 (0 = 1); results identical */
-  int32_t seg_len;        /* fused backward (gs_render_bwd without forward images): a tile list longer than
-                             this is split into depth segments of this many records, composited by separate
-                             workgroups and joined per pixel (transmittance products, then prefix sums); 0 =
-                             default 512, < 0 = never split.  Fixed per frame by gs_frame_init.  Results agree
-                             with the unsplit walk up to FP32 rounding of the transmittance product */
+  int32_t seg_len;        /* compositing (gs_render_fwd, gs_render_bwd): a tile list longer than this is split
+                             into depth segments of this many records, composited by separate workgroups and
+                             joined per pixel (transmittance products, then prefix sums); 0 = default 512,
+                             < 0 = never split.  Fixed per frame by gs_frame_init.  Results agree with the
+                             unsplit walk up to FP32 rounding of the transmittance product */
   int32_t reserved[1];
 } gs_opts;
 
@@ -127,10 +127,10 @@ typedef struct gs_frame {
   int32_t key_bits;     /* 32 depth bits + tile bits */
   int32_t sort_passes;  /* 8-bit LSD passes */
   int32_t tile_w, tile_h;
-  int32_t seg_len;      /* depth-segment length of the fused backward (0: lists are never split) */
+  int32_t seg_len;      /* depth-segment length of the compositing calls (0: lists are never split) */
   int32_t seg_cap;      /* capacity of segment slots: 2 * capacity / seg_len + 2 */
   int32_t long_cap;     /* capacity of split tiles: capacity / seg_len + 1 */
-  int32_t item_cap;     /* work items of the fused backward: n_tiles + seg_cap */
+  int32_t item_cap;     /* work items of the compositing calls: n_tiles + seg_cap */
   const gs_camera* cams;  /* device copy of the planned cameras (caller-owned) */
   void* block;
   size_t bytes;
@@ -151,7 +151,7 @@ typedef struct gs_frame {
                            [193] segment slots of split tiles, [194] split tiles */
   int32_t* seg_count;   /* [n_tiles]: segments of the tile at each schedule position */
   int32_t* seg_first;   /* [n_tiles]: exclusive scan of seg_count = first work item of that tile */
-  int32_t* items;       /* [item_cap][4]: work items of the fused backward, split tiles first:
+  int32_t* items;       /* [item_cap][4]: work items of the compositing calls, split tiles first:
                            {tile, segment, first slot of the tile or -1, schedule position} */
   float* seg;           /* [seg_cap][6][tile_w * tile_h]: per-segment pixel state of split tiles */
   float* split;         /* [long_cap][12][tile_w * tile_h]: per-pixel stop state and upstream gradient */

@@ -18,7 +18,7 @@ from . import build as _build
 # guard band 1.3, EWA low-pass 0.3 px^2, skip below alpha 1/255, clamp at 0.99, stop
 # before T < 1e-4, black background, 16x16 tiles, lambda_d = 0.1.
 DEFAULT_OPTS = dict(near=0.2, guard=1.3, lowpass=0.3, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4,
-                    bg=(0.0, 0.0, 0.0), tile_w=16, tile_h=16, lambda_d=0.1)
+                    bg=(0.0, 0.0, 0.0), tile_w=16, tile_h=16, lambda_d=0.1, stop_near=1e-5)
 
 _lib = None
 
@@ -49,7 +49,7 @@ def opts_array(**over) -> np.ndarray:
     o = dict(DEFAULT_OPTS)
     o.update(over)
     return _f64([o["near"], o["guard"], o["lowpass"], o["alpha_min"], o["alpha_max"], o["t_min"], *o["bg"],
-                 o["tile_w"], o["tile_h"], o["lambda_d"]])
+                 o["tile_w"], o["tile_h"], o["lambda_d"], o["stop_near"]])
 
 
 def cams_array(cams: Sequence) -> np.ndarray:

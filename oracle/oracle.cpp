@@ -43,11 +43,14 @@ namespace {
 // ---------------------------------------------------------------- options
 enum {
   OPT_NEAR = 0, OPT_GUARD, OPT_LOWPASS, OPT_ALPHA_MIN, OPT_ALPHA_MAX, OPT_T_MIN,
-  OPT_BG0, OPT_BG1, OPT_BG2, OPT_TILE_W, OPT_TILE_H, OPT_LAMBDA_D, OPT_COUNT
+  OPT_BG0, OPT_BG1, OPT_BG2, OPT_TILE_W, OPT_TILE_H, OPT_LAMBDA_D, OPT_STOP_NEAR, OPT_COUNT
 };
 
+// stop_near: relative distance of T(1 - alpha) from t_min within which a stop decision counts as near its
+// threshold (test excusal only; 1e-5 by default, wider where the compared path multiplies the transmittance
+// in another association order).
 struct Opts {
-  double near_z, guard, lowpass, alpha_min, alpha_max, t_min, bg[3], lambda_d;
+  double near_z, guard, lowpass, alpha_min, alpha_max, t_min, bg[3], lambda_d, stop_near;
   int tile_w, tile_h;
 };
 
@@ -65,6 +68,7 @@ Opts read_opts(const double* o) {
   r.tile_w = (int)o[OPT_TILE_W];
   r.tile_h = (int)o[OPT_TILE_H];
   r.lambda_d = o[OPT_LAMBDA_D];
+  r.stop_near = o[OPT_STOP_NEAR];
   return r;
 }
 
@@ -406,7 +410,7 @@ PixelOut<R> composite_pixel(const Splat<R>* recs, const int64_t* order, int64_t 
     R alpha = clamped ? amax : oG;
     bool nr = std::fabs((double)oG - op.alpha_max) <= 1e-5 * op.alpha_max ||
               std::fabs((double)alpha - op.alpha_min) <= 1e-5 * op.alpha_min;
-    if (!(alpha < amin)) nr = nr || std::fabs((double)(T * ((R)1 - alpha)) - op.t_min) <= 1e-5 * op.t_min;
+    if (!(alpha < amin)) nr = nr || std::fabs((double)(T * ((R)1 - alpha)) - op.t_min) <= op.stop_near * op.t_min;
     if (nr) {
       out.near = true;
       if (near_recs) near_recs->push_back(order[i]);

@@ -14,9 +14,12 @@ LIB = os.path.join(HERE, "libgs.so")
 SOURCES = ["project.hip", "bin.hip", "render.hip", "adam.hip", "api.hip"]
 ARCH = os.environ.get("GS_OFFLOAD_ARCH", "gfx950")
 
-# Packed-FP32 instruction forms are disabled for every kernel (-packed-fp32-ops).
+# Packed-FP32 instruction forms are disabled for every kernel (-packed-fp32-ops).  The compiler's atomic
+# optimizer is off: the kernels sum across the wave themselves before an atomic, and the optimizer's
+# per-lane readlane loops around atomics with a wave-uniform address cost more than they save here.
 HIPFLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17", "-munsafe-fp-atomics",
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]
 
 
 def _hipcc() -> str:

@@ -213,10 +213,11 @@ __device__ __forceinline__ void scatter(Stage<G>& s, const TileCtx& t, int nb, i
 
 // Walk one staged round for this lane's pixel, in list order, over exactly the records that can touch it:
 // its own bits and its sub-tile's shared bits.  When the longest per-lane walk of the wave is at least half
-// the wave's union of records, the wave walks the union in lock-step instead (uniform record, broadcast LDS
-// reads; a record outside a pixel's rectangle is skipped there by its alpha, so the result is the same).
+// the wave's union of records, every lane walks the union instead, so the wave moves in lock-step (one record
+// at a time, broadcast LDS reads, one wave sum per record in the backward); a record outside a pixel's
+// rectangle is skipped there by its alpha, so the result is the same.
 //   step(j, A, B, C, acc) -> contributed   (per lane; clears live at the stop)
-//   post(j, hit, acc, uniform)             (whole wave, once per step, only if SYNC)
+//   post(j, hit, acc)                      (whole wave, once per step, only if SYNC)
 template <class G, bool SYNC, class Step, class Post>
 __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, bool& live, Step step, Post post) {
   int cnt = 0, nu = 0;
@@ -228,34 +229,10 @@ __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, 
   }
   const int cmax = gsk::wave_max_nonneg(live ? cnt : 0);
   if (cmax == 0) return;
-  if (2 * cmax >= nu) {
-#pragma unroll 1
-    for (int c = 0; c < G::MC; ++c) {
-      uint64_t m = gsk::uniform64(s.uw[t.wave][c] | s.wide[t.wave][c]);
-      if (m == 0) continue;
-      int jn = c * 64 + __builtin_ctzll(m);
-      float4 An = s.A[jn], Bn = s.B[jn], Cn = s.C[jn];
-      while (m) {
-        const int j = jn;
-        const float4 A = An, B = Bn, C = Cn;
-        m &= m - 1;
-        jn = c * 64 + (m ? __builtin_ctzll(m) : 0);
-        An = s.A[jn];
-        Bn = s.B[jn];
-        Cn = s.C[jn];
-        float acc[10];
-#pragma unroll
-        for (int q = 0; q < 10; ++q) acc[q] = 0.f;
-        const bool hit = live && step(j, A, B, C, acc);
-        if (SYNC) post(j, hit, acc, true);
-        if (__ballot(live) == 0) return;
-      }
-    }
-    return;
-  }
+  const bool lock = 2 * cmax >= nu;
 #pragma unroll 1
   for (int c = 0; c < G::MC; ++c) {
-    uint64_t m = live ? (s.pm[c][threadIdx.x] | s.wide[t.wave][c]) : 0ull;
+    uint64_t m = live ? ((lock ? s.uw[t.wave][c] : s.pm[c][threadIdx.x]) | s.wide[t.wave][c]) : 0ull;
     if (__ballot(m != 0) == 0) continue;
     // the lane's next record is fetched from LDS while the current one is composited
     int jn = c * 64 + (m ? __builtin_ctzll(m) : 0);
@@ -276,7 +253,7 @@ __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, 
         hit = step(j, A, B, C, acc);
         if (!live) m = 0;
       }
-      if (SYNC) post(j, hit, acc, false);
+      if (SYNC) post(j, hit, acc);
     }
   }
 }
@@ -334,8 +311,7 @@ __device__ __forceinline__ void forward_walk(Stage<G>& s, const float4* __restri
     T = Tn;
     return true;
   };
-  sweep<G, DEPTH, false>(s, rec, vals, rg, t, op, live, [](bool) {}, step,
-                         [](int, bool, const float*, bool) {});
+  sweep<G, DEPTH, false>(s, rec, vals, rg, t, op, live, [](bool) {}, step, [](int, bool, const float*) {});
 }
 
 // Forward sweep of one whole tile for this lane's pixel (forward kernel and fused backward).
@@ -347,6 +323,20 @@ __device__ __forceinline__ void forward_sweep(Stage<G>& s, const float4* __restr
   T = 1.f;
   Cr = Cg = Cb = D = Vs = 0.f;
   forward_walk<G, DEPTH, true>(s, rec, vals, rg, t, op, t.inside, T, Cr, Cg, Cb, D, Vs);
+}
+
+// Final values of this lane's pixel (background behind transmittance T) into the planar images.
+__device__ __forceinline__ void write_pixel(const TileCtx& t, const DevOpts& op, float T, float Cr, float Cg, float Cb,
+                                            float D, float Vs, float* __restrict__ out_rgb,
+                                            float* __restrict__ out_depth, float* __restrict__ out_vis) {
+  if (!t.inside) return;
+  const int64_t P = (int64_t)t.W * t.H;
+  const int64_t i = (int64_t)t.py * t.W + t.px;
+  out_rgb[3 * t.pix_off + i] = __builtin_fmaf(T, op.bg[0], Cr);
+  out_rgb[3 * t.pix_off + P + i] = __builtin_fmaf(T, op.bg[1], Cg);
+  out_rgb[3 * t.pix_off + 2 * P + i] = __builtin_fmaf(T, op.bg[2], Cb);
+  out_depth[t.pix_off + i] = D;
+  out_vis[t.pix_off + i] = Vs;
 }
 
 template <int TW, int TH, int DEPTH>
@@ -364,15 +354,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const float4* __restrict
   if (!tile_setup<G>(cams, V, n_tiles, order, t, tile)) return;
   float T, Cr, Cg, Cb, D, Vs;
   forward_sweep<G, DEPTH>(s, rec, vals, range[tile], t, op, T, Cr, Cg, Cb, D, Vs);
-  if (t.inside) {
-    const int64_t P = (int64_t)t.W * t.H;
-    const int64_t i = (int64_t)t.py * t.W + t.px;
-    out_rgb[3 * t.pix_off + i] = __builtin_fmaf(T, op.bg[0], Cr);
-    out_rgb[3 * t.pix_off + P + i] = __builtin_fmaf(T, op.bg[1], Cg);
-    out_rgb[3 * t.pix_off + 2 * P + i] = __builtin_fmaf(T, op.bg[2], Cb);
-    out_depth[t.pix_off + i] = D;
-    out_vis[t.pix_off + i] = Vs;
-  }
+  write_pixel(t, op, T, Cr, Cg, Cb, D, Vs, out_rgb, out_depth, out_vis);
 }
 
 struct BwdArgs {
@@ -514,11 +496,11 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
     return true;
   };
   // sum the partials of one step into the record's LDS accumulator (whole wave)
-  auto post = [&](int j, bool hit, const float* acc, bool uniform) {
+  auto post = [&](int j, bool hit, const float* acc) {
     const uint64_t hits = __ballot(hit);
     if (hits == 0) return;
-    const int j0 = uniform ? j : __builtin_amdgcn_readlane(j, __builtin_ctzll(hits));
-    if (__popcll(hits) > 4 && (uniform || __ballot(hit && j != j0) == 0)) {
+    const int j0 = __builtin_amdgcn_readlane(j, __builtin_ctzll(hits));
+    if (__popcll(hits) > 4 && __ballot(hit && j != j0) == 0) {
       // every contributing lane is on record j0: one wave sum per value
 #pragma unroll
       for (int q = 0; q < 10; ++q) {
@@ -603,7 +585,26 @@ __device__ __forceinline__ int2 segment_range(int2 rg, int k, int L) {
   return make_int2(lo, min(rg.y, lo + L));
 }
 
-template <int TW, int TH, int DEPTH, bool LOSS>
+// Step 1 for one depth segment: its transmittance product and local sums, from T = 1 without the stop rule.
+template <class G, int DEPTH>
+__device__ __forceinline__ void segment_sums(Stage<G>& s, const float4* __restrict__ rec,
+                                             const int32_t* __restrict__ vals, int2 rg, int4 it, const TileCtx& t,
+                                             const DevOpts& op, const SegArgs& g) {
+  float T = 1.f, Cr = 0.f, Cg = 0.f, Cb = 0.f, D = 0.f, Vs = 0.f;
+  forward_walk<G, DEPTH, false>(s, rec, vals, segment_range<G>(rg, it.y, g.len), t, op, t.inside, T, Cr, Cg, Cb, D,
+                                Vs);
+  float* o = g.seg + (size_t)(it.z + it.y) * 6 * G::NT + threadIdx.x;
+  o[0 * G::NT] = T;
+  o[1 * G::NT] = Cr;
+  o[2 * G::NT] = Cg;
+  o[3 * G::NT] = Cb;
+  o[4 * G::NT] = D;
+  o[5 * G::NT] = Vs;
+}
+
+// Backward over the work items: whole tiles run the forward sweep (or read the forward images), the upstream
+// gradient and the backward walk; segments of split tiles run step 1.
+template <int TW, int TH, int DEPTH, bool HAVE_FWD, bool LOSS>
 __global__ __launch_bounds__(TW * TH) void k_fused_main(const float4* __restrict__ rec,
                                                         const int32_t* __restrict__ vals,
                                                         const int2* __restrict__ range,
@@ -617,20 +618,33 @@ __global__ __launch_bounds__(TW * TH) void k_fused_main(const float4* __restrict
   TileCtx t;
   tile_at<G>(cams, V, it.x, t);
   const int2 rg = range[it.x];
-  if (it.z < 0) {
-    tile_backward<G, DEPTH, false, LOSS>(s, gacc, rec, vals, rg, t, op, a);
+  if (it.z < 0)
+    tile_backward<G, DEPTH, HAVE_FWD, LOSS>(s, gacc, rec, vals, rg, t, op, a);
+  else
+    segment_sums<G, DEPTH>(s, rec, vals, rg, it, t, op, g);
+}
+
+// Forward over the work items: whole tiles are composited and written; segments of split tiles run step 1.
+template <int TW, int TH, int DEPTH>
+__global__ __launch_bounds__(TW * TH) void k_fwd_main(const float4* __restrict__ rec, const int32_t* __restrict__ vals,
+                                                      const int2* __restrict__ range,
+                                                      const gs_camera* __restrict__ cams, int V, DevOpts op,
+                                                      SegArgs g, float* __restrict__ out_rgb,
+                                                      float* __restrict__ out_depth, float* __restrict__ out_vis) {
+  using G = Geo<TW, TH, DEPTH>;
+  __shared__ Stage<G> s;
+  if ((int)blockIdx.x >= g.counters[192]) return;
+  const int4 it = g.items[blockIdx.x];
+  TileCtx t;
+  tile_at<G>(cams, V, it.x, t);
+  const int2 rg = range[it.x];
+  if (it.z >= 0) {
+    segment_sums<G, DEPTH>(s, rec, vals, rg, it, t, op, g);
     return;
   }
-  float T = 1.f, Cr = 0.f, Cg = 0.f, Cb = 0.f, D = 0.f, Vs = 0.f;
-  forward_walk<G, DEPTH, false>(s, rec, vals, segment_range<G>(rg, it.y, g.len), t, op, t.inside, T, Cr, Cg, Cb, D,
-                                Vs);
-  float* o = g.seg + (size_t)(it.z + it.y) * 6 * G::NT + threadIdx.x;
-  o[0 * G::NT] = T;
-  o[1 * G::NT] = Cr;
-  o[2 * G::NT] = Cg;
-  o[3 * G::NT] = Cb;
-  o[4 * G::NT] = D;
-  o[5 * G::NT] = Vs;
+  float T, Cr, Cg, Cb, D, Vs;
+  forward_sweep<G, DEPTH>(s, rec, vals, rg, t, op, T, Cr, Cg, Cb, D, Vs);
+  write_pixel(t, op, T, Cr, Cg, Cb, D, Vs, out_rgb, out_depth, out_vis);
 }
 
 template <int TW, int TH, int DEPTH>
@@ -664,7 +678,61 @@ __global__ __launch_bounds__(TW * TH) void k_seg_stop(const float4* __restrict__
   }
 }
 
-template <int TW, int TH, bool LOSS>
+// Step 3, first half: the pixel's last live segment ks and its final sums (C, D, V) and transmittance.
+template <class G>
+__device__ __forceinline__ void split_final(const float* sp, const float* xp, int n, const TileCtx& t,
+                                            const DevOpts& op, int& ks, float& Tf, float& Cr, float& Cg, float& Cb,
+                                            float& D, float& Vs) {
+  constexpr size_t SS = 6 * G::NT;
+  ks = 0;
+  float Tr = 1.f;
+  for (int k = 0; k < n; ++k) {
+    if (Tr >= op.t_min) ks = k;
+    Tr = Tr * sp[k * SS];
+  }
+  Cr = Cg = Cb = D = Vs = 0.f;
+  Tr = 1.f;
+  for (int k = 0; k < ks; ++k) {
+    const float* q = sp + k * SS;
+    Cr = __builtin_fmaf(Tr, q[1 * G::NT], Cr);
+    Cg = __builtin_fmaf(Tr, q[2 * G::NT], Cg);
+    Cb = __builtin_fmaf(Tr, q[3 * G::NT], Cb);
+    D = __builtin_fmaf(Tr, q[4 * G::NT], D);
+    Vs = __builtin_fmaf(Tr, q[5 * G::NT], Vs);
+    Tr = Tr * q[0];
+  }
+  Tf = 1.f;
+  if (t.inside) {
+    Tf = xp[0];
+    Cr += xp[1 * G::NT];
+    Cg += xp[2 * G::NT];
+    Cb += xp[3 * G::NT];
+    D += xp[4 * G::NT];
+    Vs += xp[5 * G::NT];
+  }
+}
+
+// Forward of split tiles, step 3: write the final values.
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_seg_fwd_out(const gs_camera* __restrict__ cams, int V, DevOpts op,
+                                                         SegArgs g, float* __restrict__ out_rgb,
+                                                         float* __restrict__ out_depth, float* __restrict__ out_vis) {
+  using G = Geo<TW, TH, 1>;
+  const int l = blockIdx.x;
+  if (l >= g.counters[194]) return;
+  TileCtx t;
+  tile_at<G>(cams, V, g.order[l], t);
+  const float* sp = g.seg + (size_t)g.seg_first[l] * 6 * G::NT + threadIdx.x;
+  const float* xp = g.split + (size_t)l * 12 * G::NT + threadIdx.x;
+  int ks;
+  float T, Cr, Cg, Cb, D, Vs;
+  split_final<G>(sp, xp, g.seg_count[l], t, op, ks, T, Cr, Cg, Cb, D, Vs);
+  write_pixel(t, op, T, Cr, Cg, Cb, D, Vs, out_rgb, out_depth, out_vis);
+}
+
+// Backward of split tiles, step 3: final values (or the forward images), upstream gradient, S and the start
+// state (T_start, P_start) of every segment; T_start = 0 marks a segment after the pixel's end.
+template <int TW, int TH, bool HAVE_FWD, bool LOSS>
 __global__ __launch_bounds__(TW * TH) void k_seg_combine(const gs_camera* __restrict__ cams, int V, DevOpts op,
                                                          BwdArgs a, SegArgs g) {
   using G = Geo<TW, TH, 1>;
@@ -676,38 +744,25 @@ __global__ __launch_bounds__(TW * TH) void k_seg_combine(const gs_camera* __rest
   float* sp = g.seg + (size_t)g.seg_first[l] * 6 * G::NT + threadIdx.x;
   float* xp = g.split + (size_t)l * 12 * G::NT + threadIdx.x;
   constexpr size_t SS = 6 * G::NT;
-  // the last live segment
-  int ks = 0;
-  float Tr = 1.f;
-  for (int k = 0; k < n; ++k) {
-    if (Tr >= op.t_min) ks = k;
-    Tr = Tr * sp[k * SS];
+  int ks;
+  float Tf, Cr, Cg, Cb, D, Vs;
+  split_final<G>(sp, xp, n, t, op, ks, Tf, Cr, Cg, Cb, D, Vs);
+  float Cf = __builtin_fmaf(Tf, op.bg[0], Cr), Gf = __builtin_fmaf(Tf, op.bg[1], Cg);
+  float Bf = __builtin_fmaf(Tf, op.bg[2], Cb), Df = D, Vf = Vs;
+  if (HAVE_FWD && t.inside) {
+    const int64_t P = (int64_t)t.W * t.H;
+    const int64_t pi = (int64_t)t.py * t.W + t.px;
+    Cf = a.fwd_rgb[3 * t.pix_off + pi];
+    Gf = a.fwd_rgb[3 * t.pix_off + P + pi];
+    Bf = a.fwd_rgb[3 * t.pix_off + 2 * P + pi];
+    Df = a.fwd_depth[t.pix_off + pi];
+    Vf = a.fwd_vis[t.pix_off + pi];
   }
-  // final values
-  float Cr = 0.f, Cg = 0.f, Cb = 0.f, D = 0.f, Vs = 0.f;
-  Tr = 1.f;
-  for (int k = 0; k < ks; ++k) {
-    const float* q = sp + k * SS;
-    Cr = __builtin_fmaf(Tr, q[1 * G::NT], Cr);
-    Cg = __builtin_fmaf(Tr, q[2 * G::NT], Cg);
-    Cb = __builtin_fmaf(Tr, q[3 * G::NT], Cb);
-    D = __builtin_fmaf(Tr, q[4 * G::NT], D);
-    Vs = __builtin_fmaf(Tr, q[5 * G::NT], Vs);
-    Tr = Tr * q[0];
-  }
-  const float Tf = t.inside ? xp[0] : 1.f;
-  const float sr = t.inside ? xp[1 * G::NT] : 0.f, sg = t.inside ? xp[2 * G::NT] : 0.f;
-  const float sb = t.inside ? xp[3 * G::NT] : 0.f, sd = t.inside ? xp[4 * G::NT] : 0.f;
-  const float sv = t.inside ? xp[5 * G::NT] : 0.f;
-  const float Cf = __builtin_fmaf(Tf, op.bg[0], Cr + sr), Gf = __builtin_fmaf(Tf, op.bg[1], Cg + sg);
-  const float Bf = __builtin_fmaf(Tf, op.bg[2], Cb + sb), Df = D + sd, Vf = Vs + sv;
   float gr, gg, gb, gd, gv, loss_acc = 0.f;
   pixel_upstream<LOSS>(t, a, Cf, Gf, Bf, Df, gr, gg, gb, gd, gv, loss_acc);
   const float S = gr * Cf + gg * Gf + gb * Bf + gd * Df + gv * Vf;
   if (LOSS) add_loss<G>(t, a, loss_acc);
-  // start state of every segment: (T_start, P_start); T_start = 0 marks a segment after the pixel's end
-  Tr = 1.f;
-  float Pr = 0.f;
+  float Tr = 1.f, Pr = 0.f;
   for (int k = 0; k < n; ++k) {
     float* q = sp + k * SS;
     const float Tk = q[0];
@@ -793,8 +848,15 @@ __global__ __launch_bounds__(TW * TH) void k_count_pairs(const float4* __restric
       T = Tn;
     }
   }
-  atomicAdd(counts, ev);
-  atomicAdd(counts + 1, co);
+  // one atomic per wave (sums over the lanes first)
+  for (int d = 32; d >= 1; d >>= 1) {
+    ev += __shfl_xor(ev, d);
+    co += __shfl_xor(co, d);
+  }
+  if (t.lane == 0) {
+    atomicAdd(counts, ev);
+    atomicAdd(counts + 1, co);
+  }
 }
 
 // Valid LiDAR-depth pixels per view: grid-stride per view, one atomic per block.
@@ -810,55 +872,82 @@ __global__ __launch_bounds__(256) void k_count_valid(const float* __restrict__ t
   int cnt = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x)
     cnt += tgt_depth[c.pixel_offset + i] > 0.f;
-  atomicAdd(&sh, cnt);
+  for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d);
+  if ((threadIdx.x & 63) == 0) atomicAdd(&sh, cnt);
   __syncthreads();
   if (threadIdx.x == 0 && sh) atomicAdd(n_valid + v, sh);
+}
+
+SegArgs seg_args(const gs_frame& f) {
+  SegArgs g;
+  g.items = reinterpret_cast<const int4*>(f.items);
+  g.counters = f.counters;
+  g.order = f.tile_order;
+  g.seg_count = f.seg_count;
+  g.seg_first = f.seg_first;
+  g.seg = f.seg;
+  g.split = f.split;
+  g.len = f.seg_len;
+  return g;
 }
 
 template <int TW, int TH, int DEPTH>
 hipError_t launch_fwd(const gs_frame& f, const DevOpts& op, const gs_images& out, hipStream_t st) {
   const int sorted = f.sort_passes & 1;
-  k_render_fwd<TW, TH, DEPTH><<<f.n_tiles, TW * TH, 0, st>>>(
-      reinterpret_cast<const float4*>(f.rec), f.vals[sorted], reinterpret_cast<const int2*>(f.tile_range), f.cams,
-      f.n_views, f.n_tiles, f.tile_order, op, out.rgb, out.depth, out.vis);
+  const auto* rec = reinterpret_cast<const float4*>(f.rec);
+  const auto* rng = reinterpret_cast<const int2*>(f.tile_range);
+  const int bs = TW * TH;
+  if (f.seg_len > 0) {
+    // long lists split into depth segments
+    const SegArgs g = seg_args(f);
+    k_fwd_main<TW, TH, DEPTH><<<f.item_cap, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, op, g, out.rgb,
+                                                          out.depth, out.vis);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_seg_stop<TW, TH, DEPTH><<<f.seg_cap, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, op, g);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_seg_fwd_out<TW, TH><<<f.long_cap, bs, 0, st>>>(f.cams, f.n_views, op, g, out.rgb, out.depth, out.vis);
+    return hipGetLastError();
+  }
+  k_render_fwd<TW, TH, DEPTH><<<f.n_tiles, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, f.n_tiles,
+                                                        f.tile_order, op, out.rgb, out.depth, out.vis);
+  return hipGetLastError();
+}
+
+template <int TW, int TH, int DEPTH, bool HAVE_FWD, bool LOSS>
+hipError_t launch_split_bwd(const gs_frame& f, const DevOpts& op, const BwdArgs& a, hipStream_t st) {
+  const int sorted = f.sort_passes & 1;
+  const auto* rec = reinterpret_cast<const float4*>(f.rec);
+  const auto* rng = reinterpret_cast<const int2*>(f.tile_range);
+  const int32_t* vals = f.vals[sorted];
+  const int bs = TW * TH;
+  const SegArgs g = seg_args(f);
+  k_fused_main<TW, TH, DEPTH, HAVE_FWD, LOSS><<<f.item_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_seg_stop<TW, TH, DEPTH><<<f.seg_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, g);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_seg_combine<TW, TH, HAVE_FWD, LOSS><<<f.long_cap, bs, 0, st>>>(f.cams, f.n_views, op, a, g);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_seg_bwd<TW, TH, DEPTH><<<f.seg_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g);
   return hipGetLastError();
 }
 
 template <int TW, int TH, int DEPTH>
 hipError_t launch_bwd(const gs_frame& f, const DevOpts& op, bool have_fwd, bool loss, const BwdArgs& a,
                       hipStream_t st) {
+  if (f.seg_len > 0) {
+    // long lists split into depth segments
+    if (have_fwd && loss) return launch_split_bwd<TW, TH, DEPTH, true, true>(f, op, a, st);
+    if (have_fwd) return launch_split_bwd<TW, TH, DEPTH, true, false>(f, op, a, st);
+    if (loss) return launch_split_bwd<TW, TH, DEPTH, false, true>(f, op, a, st);
+    return launch_split_bwd<TW, TH, DEPTH, false, false>(f, op, a, st);
+  }
   const int sorted = f.sort_passes & 1;
   const auto* rec = reinterpret_cast<const float4*>(f.rec);
   const auto* rng = reinterpret_cast<const int2*>(f.tile_range);
   const int nb = f.n_tiles, bs = TW * TH;
   const int32_t* vals = f.vals[sorted];
-  if (!have_fwd && f.seg_len > 0) {
-    // fused, with long lists split into depth segments
-    SegArgs g;
-    g.items = reinterpret_cast<const int4*>(f.items);
-    g.counters = f.counters;
-    g.order = f.tile_order;
-    g.seg_count = f.seg_count;
-    g.seg_first = f.seg_first;
-    g.seg = f.seg;
-    g.split = f.split;
-    g.len = f.seg_len;
-    if (loss)
-      k_fused_main<TW, TH, DEPTH, true><<<f.item_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g);
-    else
-      k_fused_main<TW, TH, DEPTH, false><<<f.item_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_seg_stop<TW, TH, DEPTH><<<f.seg_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, g);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (loss)
-      k_seg_combine<TW, TH, true><<<f.long_cap, bs, 0, st>>>(f.cams, f.n_views, op, a, g);
-    else
-      k_seg_combine<TW, TH, false><<<f.long_cap, bs, 0, st>>>(f.cams, f.n_views, op, a, g);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_seg_bwd<TW, TH, DEPTH><<<f.seg_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g);
-    return hipGetLastError();
-  }
   if (have_fwd && loss)
     k_render_bwd<TW, TH, DEPTH, true, true><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb, f.tile_order,
                                                                op, a);

@@ -212,8 +212,8 @@ def test_forward_config1_matches_oracle(gpu_lib):
 
 def test_forward_is_tile_size_invariant_and_deterministic(gpu_lib):
     sc = scenes.random_scene(400, 3000, 150, 100, sh_degree=1, views=2, log_scale_mu=-2.2)
-    base = run_gpu(sc, targets=False)
-    again = run_gpu(sc, targets=False)
+    base = run_gpu(sc, targets=False, seg=-1)
+    again = run_gpu(sc, targets=False, seg=-1)
     for k in ("rgb", "depth", "vis"):
         assert np.array_equal(base[k], again[k]), k
     # tile shapes, records per thread and the per-pixel hand-out threshold (-1: every record is walked by
@@ -221,7 +221,7 @@ def test_forward_is_tile_size_invariant_and_deterministic(gpu_lib):
     for tile in [(16, 16), (8, 8), (16, 8), (32, 8)]:
         for depth, smax in [(1, 0), (2, 0), (1, -1), (2, 64)]:
             log("tile", tile, "depth", depth, "scatter_max", smax)
-            o = run_gpu(sc, tile=tile, targets=False, smax=smax, depth=depth)
+            o = run_gpu(sc, tile=tile, targets=False, smax=smax, depth=depth, seg=-1)
             for k in ("rgb", "depth", "vis"):
                 d = np.abs(base[k] - o[k])
                 assert np.array_equal(base[k], o[k]), (tile, depth, smax, k, int((d > 0).sum()), float(d.max()))
@@ -393,8 +393,8 @@ def test_pair_counts_match_oracle(gpu_lib):
 def test_backward_identical_across_walk_options(gpu_lib, tile, depth, smax):
     """Gradients agree (to atomic summation order) whatever the tile shape, batch depth and hand-out rule."""
     sc = scenes.random_scene(1500, 2000, 100, 70, sh_degree=1, views=2, log_scale_mu=-2.3, depth_fraction=0.3)
-    ref = run_gpu(sc, targets=True, fused=True, smax=-1)
-    out = run_gpu(sc, targets=True, fused=True, tile=tile, depth=depth, smax=smax)
+    ref = run_gpu(sc, targets=True, fused=True, smax=-1, seg=-1)
+    out = run_gpu(sc, targets=True, fused=True, tile=tile, depth=depth, smax=smax, seg=-1)
     np.testing.assert_allclose(out["loss"], ref["loss"], rtol=1e-6)
     for k in ref["grads"]:
         a, b = ref["grads"][k], out["grads"][k]
@@ -423,9 +423,10 @@ def _subpixel_scene(seed, n=20000, W=64, H=48, views=1, deg=0):
 
 def test_per_pixel_walk_matches_shared_walk_and_oracle(gpu_lib):
     sc = _subpixel_scene(1700, views=2)
-    shared = run_gpu(sc, tile=(16, 16), smax=-1, targets=False)  # every record walked by whole sub-tiles
+    # unsplit lists: the walks must agree bit for bit (split lists are checked in the depth-segment tests)
+    shared = run_gpu(sc, tile=(16, 16), smax=-1, targets=False, seg=-1)  # every record walked by whole sub-tiles
     for tile, depth, smax in [((16, 16), 1, 0), ((8, 8), 2, 0), ((32, 8), 1, 64), ((16, 8), 2, 4)]:
-        o = run_gpu(sc, tile=tile, depth=depth, smax=smax, targets=False)
+        o = run_gpu(sc, tile=tile, depth=depth, smax=smax, targets=False, seg=-1)
         for k in ("rgb", "depth", "vis"):
             assert np.array_equal(shared[k], o[k]), (tile, depth, smax, k)
     shared["cams"] = sc.cams
@@ -438,13 +439,13 @@ def test_per_pixel_walk_matches_shared_walk_and_oracle(gpu_lib):
 @pytest.mark.parametrize("fused", [False, True])
 def test_per_pixel_walk_backward_matches_fp64_oracle(gpu_lib, fused):
     sc = _subpixel_scene(1800, n=12000, views=2, deg=1)
-    out = run_gpu(sc, targets=True, fused=fused, tile=(16, 16))
+    out = run_gpu(sc, targets=True, fused=fused, tile=(16, 16), seg=-1)
     L, ref, exc, nn, _ = oracle.backward(64, sc.params(), 1, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
     np.testing.assert_allclose(out["loss"], L, rtol=1e-5)
     check_grads(out["grads"], ref, exc, f"sub-pixel fused={fused}", nn, sc.total_pixels)
     # the per-pixel walk sums partials in another order; rotation gradients of near-isotropic sub-pixel
     # Gaussians are ill-conditioned in FP32, hence 1e-4 here (both sides are within 1e-3 of FP64 above)
-    shared = run_gpu(sc, targets=True, fused=fused, tile=(16, 16), smax=-1)
+    shared = run_gpu(sc, targets=True, fused=fused, tile=(16, 16), smax=-1, seg=-1)
     for k in shared["grads"]:
         a, b = shared["grads"][k], out["grads"][k]
         rms = np.sqrt((a.astype(np.float64) ** 2).mean()) + 1e-30
@@ -477,6 +478,76 @@ def test_split_fused_backward_matches_fp64_oracle_and_unsplit(gpu_lib, tile, seg
         rms = np.sqrt((a.astype(np.float64) ** 2).mean()) + 1e-30
         err = np.abs(a - b) / (np.abs(a) + rms)
         assert err.max() <= 1e-4, (k, float(err.max()))
+
+
+def _reassociation_rtol(out, ref, sc, tile, seg):
+    """Per-pixel relative bound for split lists.  The split walk forms each pixel's transmittance as a
+    product of segment products, and its sums as sums of segment sums, instead of left to right.  To first
+    order an FP32 product of n factors, or a sum of n non-negative terms, is within n 2^-24 (relative) of the
+    exact value in any association order.  A term alpha T c carries the transmittance (n factors) plus three
+    roundings of its own and the sum adds n more, so two orders differ by at most 2 (2 n + 3) 2^-24 <=
+    8 n 2^-24, n = the pixel's contributing pairs plus its segments.  Added to the 1e-5 bar; returns
+    (per-pixel rtol, per-value rtol for the planar rgb)."""
+    rng_ = B.frame_tensor(out["frame"], "tile_range", 2 * out["frame"].f.n_tiles, torch.int32).view(-1, 2).cpu().numpy()
+    lens = rng_[:, 1] - rng_[:, 0]
+    per_px, per_rgb, toff = [], [], 0
+    off = 0
+    for c in sc.cams:
+        tx = -(-c.width // tile[0])
+        ty = -(-c.height // tile[1])
+        yy, xx = np.mgrid[0:c.height, 0:c.width]
+        t = toff + (yy // tile[1]) * tx + (xx // tile[0])
+        nseg = -(-lens[t.ravel()] // seg)
+        n = ref["n_contrib"][off:off + c.width * c.height] + nseg
+        r = FWD_RTOL + 8.0 * n * 2.0 ** -24
+        per_px.append(r)
+        per_rgb.append(np.tile(r, 3))
+        toff += tx * ty
+        off += c.width * c.height
+    return np.concatenate(per_px), np.concatenate(per_rgb)
+
+
+@pytest.mark.parametrize("tile,seg", [((16, 16), 64), ((8, 8), 128)])
+def test_split_forward_matches_oracle_and_unsplit(gpu_lib, tile, seg):
+    """gs_render_fwd with split lists agrees with the unsplit walk within the re-association bound, and is no
+    further from the FP32 oracle than the unsplit walk plus that bound (the unsplit walk's own distance to
+    the oracle comes from the projection's rounding, which splitting does not touch)."""
+    for sc in (_subpixel_scene(1970, n=12000, views=2, deg=1),
+               scenes.random_scene(1975, 4000, 96, 64, sh_degree=2, views=2, log_scale_mu=-1.8, opacity_sigma=0.8)):
+        out = run_gpu(sc, tile=tile, seg=seg, targets=False)
+        assert _split_counts(out)[2] > 0
+        ref = oracle.forward(32, sc.params(), sc.sh_degree, sc.cams)
+        whole = run_gpu(sc, tile=tile, seg=-1, targets=False)
+        r_px, r_rgb = _reassociation_rtol(out, ref, sc, tile, seg)
+        # a stop decision within the re-association bound of t_min may fall either way: widen the oracle's
+        # near-stop margin to that bound (reading R21)
+        ref = oracle.forward(32, sc.params(), sc.sh_degree, sc.cams, stop_near=float(r_px.max()))
+        ok = ~ref["near"].astype(bool)
+        offs = np.cumsum([0] + [c.width * c.height for c in sc.cams])
+        ok_rgb = np.concatenate([np.tile(ok[offs[v]:offs[v + 1]], 3) for v in range(len(sc.cams))])
+        for k, m, r in (("rgb", ok_rgb, r_rgb), ("depth", ok, r_px), ("vis", ok, r_px)):
+            bound = r * np.abs(whole[k]) + FWD_ATOL
+            err = np.abs(out[k] - whole[k])
+            bad = (err > bound) & m
+            assert not bad.any(), (k, "unsplit", int(bad.sum()), float(err[bad].max()))
+            worse = np.abs(out[k] - ref[k]) - np.abs(whole[k] - ref[k])
+            bad = (worse > bound) & m
+            assert not bad.any(), (k, "oracle", int(bad.sum()), float(worse[bad].max()))
+            strict = (np.abs(out[k] - ref[k]) > FWD_RTOL * np.abs(ref[k]) + FWD_ATOL) & m
+            strict0 = (np.abs(whole[k] - ref[k]) > FWD_RTOL * np.abs(ref[k]) + FWD_ATOL) & m
+            log(f"split fwd {tile} {seg} {k}: beyond 1e-5 of the oracle: split {int(strict.sum())}, "
+                f"unsplit {int(strict0.sum())} of {int(m.sum())}")
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_split_image_fed_backward_matches_fp64_oracle(gpu_lib, fused):
+    """gs_render_bwd fed with the forward images (fused=False) or recomputing them, lists split."""
+    sc = _subpixel_scene(1980, n=12000, views=2, deg=1)
+    out = run_gpu(sc, targets=True, fused=fused, seg=96)
+    assert _split_counts(out)[2] > 0
+    L, ref, exc, nn, _ = oracle.backward(64, sc.params(), 1, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
+    np.testing.assert_allclose(out["loss"], L, rtol=1e-5)
+    check_grads(out["grads"], ref, exc, f"split image-fed fused={fused}", nn, sc.total_pixels)
 
 
 def test_split_with_upstream_gradients_and_dense_scene(gpu_lib):

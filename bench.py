@@ -60,9 +60,9 @@ def measure(sc, steps, warmup, plain_steps, do_plain, tile=None):
             lambda o: BatchedStep(GaussianModel(sc.params(), sc.sh_degree), sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=o),
             sc.n, sc.cams, sc.sh_degree, log=log)
     tile = tuple(tile) + (1, 0, 0)[len(tile) - 2:] if len(tile) < 5 else tuple(tile)
-    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], batch_depth=tile[2], scatter_max=tile[3], seg_len=tile[4])
+    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], batch_depth=tile[2], block_w=tile[3], seg_len=tile[4])
     log(f"  configuration: {tile[0]}x{tile[1]} tiles, {tile[2]} records per thread per round, "
-        f"scatter_max {tile[3]}, seg_len {tile[4]}")
+        f"block {tile[3]}, seg_len {tile[4]}")
     model = GaussianModel(sc.params(), sc.sh_degree)
     t0 = time.time()
     bat = BatchedStep(model, sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=opts)
@@ -166,7 +166,7 @@ def main():
     ap.add_argument("--no-cfg3", action="store_true")
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count (smaller trial runs)")
     ap.add_argument("--tile", type=str, default=None,
-                    help="tile_w,tile_h[,batch_depth,scatter_max,seg_len] (skips the autotuner)")
+                    help="tile_w,tile_h[,batch_depth,block_w,seg_len] (skips the autotuner)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="also run a plain copy kernel over MIB MiB three times (the known-size kernel that scales "
                          "FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -220,7 +220,7 @@ def main():
                                 "one HIP-graph replay per step"),
                    "gaussians": sc4.n, "views": len(sc4.cams), "pixels": sc4.total_pixels,
                    "instances": r4["n_instances"], "tile": list(r4["tile"][:2]), "batch_depth": r4["tile"][2],
-                   "scatter_max": r4["tile"][3], "seg_len": r4["tile"][4]},
+                   "block_w": r4["tile"][3], "seg_len": r4["tile"][4]},
     }
     if "plain_ms" in r4:
         out["plain"] = {"value": round(1000.0 / r4["plain_ms"], 3), "ms_per_step": round(r4["plain_ms"], 4),

@@ -88,10 +88,10 @@ typedef struct gs_opts {
   float t_min;            /* 1e-4 */
   float bg[3];            /* background colour, 0 */
   int32_t waves_per_tile; /* 0 or tile_w * tile_h / 64 (fixed by the tile shape) */
-  int32_t scatter_max;    /* a staged record whose pixel box meets at most this many pixels of a sub-tile is
-                             handed to those pixels only; a larger one is walked by every lane of the sub-tile.
-                             0 = default 16, < 0 = never hand out per pixel.  Results are identical for every
-                             value (a record is skipped only where its box misses the pixel) */
+  int32_t block_w;        /* each wave's 8x8 sub-tile is walked as blocks of block_w x block_w pixels, each in
+                             lock-step over the staged records whose pixel rectangle meets it: 4 or 8 (0 = 4).
+                             Results are identical (a record is skipped only where its rectangle misses the
+                             pixel) */
   int32_t batch_depth;    /* records staged per thread per round: 1 or 2 (0 = 1); results identical */
   int32_t seg_len;        /* compositing (gs_render_fwd, gs_render_bwd): a tile list longer than this is split
                              into depth segments of this many records, composited by separate workgroups and

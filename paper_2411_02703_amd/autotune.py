@@ -1,5 +1,5 @@
-"""Pick the tile shape, records staged per thread, per-pixel hand-out threshold and depth-segment length of
-the batched step by measured replay time.
+"""Pick the tile shape, records staged per thread, block width of the lock-step walk and depth-segment length
+of the batched step by measured replay time.
 
 Every candidate computes the same forward bit for bit (the per-pair arithmetic is fixed and records are
 culled only where they provably do not contribute) and the same gradients up to the order of the float
@@ -19,11 +19,11 @@ import torch
 
 from . import binding as B
 
-# (tile_w, tile_h, records staged per thread, largest sub-tile overlap handed out per pixel, depth-segment
-# length of the fused backward; -1 = never split)
+# (tile_w, tile_h, records staged per thread, block width of the lock-step walk, depth-segment length;
+# -1 = never split)
 CANDIDATES: List[Tuple[int, int, int, int, int]] = [
-    (16, 8, 1, 16, 512), (16, 8, 1, 16, 256), (16, 8, 1, 16, 1024), (16, 8, 1, 32, 512), (16, 8, 1, -1, 512),
-    (16, 8, 2, 16, 512), (16, 16, 1, 16, 512), (8, 8, 1, 16, 512), (32, 8, 1, 16, 512), (16, 16, 1, 16, -1)]
+    (16, 8, 1, 4, 512), (16, 8, 1, 8, 512), (16, 8, 1, 4, 256), (16, 8, 1, 4, 1024), (16, 8, 2, 4, 512),
+    (16, 16, 1, 4, 512), (8, 8, 1, 4, 512), (32, 8, 1, 4, 512), (16, 16, 1, 8, -1)]
 
 _CACHE = os.environ.get("GS_AUTOTUNE_CACHE",
                         os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), ".scene_cache",
@@ -57,15 +57,15 @@ def _store(d: Dict[str, list]) -> None:
 def tune_batched(make_step, n: int, cams: Sequence, sh_degree: int, replays: int = 3,
                  candidates: Sequence[Tuple[int, int, int, int, int]] = CANDIDATES, use_cache: bool = True,
                  log=None):
-    """make_step(opts) -> a BatchedStep.  Returns (best (tile_w, tile_h, depth, scatter_max, seg_len),
+    """make_step(opts) -> a BatchedStep.  Returns (best (tile_w, tile_h, depth, block_w, seg_len),
     {candidate: ms})."""
     key = cache_key(n, cams, sh_degree)
     cache = _load() if use_cache else {}
     if key in cache:
         return tuple(cache[key][0]), {}
     times = {}
-    for tw, th, dp, sm, sg in candidates:
-        opts = B.default_opts(tile_w=tw, tile_h=th, batch_depth=dp, scatter_max=sm, seg_len=sg)
+    for tw, th, dp, bw, sg in candidates:
+        opts = B.default_opts(tile_w=tw, tile_h=th, batch_depth=dp, block_w=bw, seg_len=sg)
         step = make_step(opts)
         step.capture()
         step.run()
@@ -79,13 +79,13 @@ def tune_batched(make_step, n: int, cams: Sequence, sh_degree: int, replays: int
         ms = s.elapsed_time(e) / replays
         if step.overflowed():
             ms = float("inf")
-        times[(tw, th, dp, sm, sg)] = ms
+        times[(tw, th, dp, bw, sg)] = ms
         if log:
-            log(f"  autotune {tw}x{th} depth {dp} scatter_max {sm} seg_len {sg}: {ms:.3f} ms")
+            log(f"  autotune {tw}x{th} depth {dp} block {bw} seg_len {sg}: {ms:.3f} ms")
         del step
         torch.cuda.empty_cache()
     best = min(times, key=times.get)
     if use_cache:
-        cache[key] = [list(best), {f"{a}x{b}/d{c}/s{d}/L{e}": v for (a, b, c, d, e), v in times.items()}]
+        cache[key] = [list(best), {f"{a}x{b}/d{c}/b{d}/L{e}": v for (a, b, c, d, e), v in times.items()}]
         _store(cache)
     return best, times

@@ -15,7 +15,6 @@ struct DevOpts {
   float near_z, lowpass, alpha_min, alpha_max, t_min;
   float bg[3];
   int tile_w, tile_h;
-  int scatter_max;
 };
 
 inline DevOpts dev_opts(const gs_opts& o) {
@@ -30,7 +29,6 @@ inline DevOpts dev_opts(const gs_opts& o) {
   d.bg[2] = o.bg[2];
   d.tile_w = o.tile_w;
   d.tile_h = o.tile_h;
-  d.scatter_max = o.scatter_max == 0 ? 16 : (o.scatter_max < 0 ? -1 : o.scatter_max);
   return d;
 }
 

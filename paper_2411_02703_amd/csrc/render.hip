@@ -1,17 +1,17 @@
 // Per-tile front-to-back compositing of colour, depth and visibility (LVI-GS Section III-B,
 // eqs. Cp, Dp, Vp with the alpha of eq. alpha) and its backward.
 //
-// One workgroup per tile.  The tile is split into 8x8 sub-tiles, one wave64 each, one pixel per lane.  The
-// tile's depth-sorted list is staged in rounds of DEPTH records per thread into LDS; the records of the next
-// round are fetched into registers while the current one is composited.  Each staged record carries its
-// exact pixel rectangle (every pixel outside it has alpha < exp(-1/2)/255, so it would be skipped anyway).
-// A record whose rectangle meets only a few pixels of a sub-tile sets its bit in those pixels' masks; a
-// larger one sets its bit in the sub-tile's mask, which every lane of the wave walks.  Each lane then walks
-// the set bits of its masks in order, i.e. exactly the staged records that can touch its pixel, in list
-// order, so the result is the same bit for bit whichever records take which route.  Coarse pyramid levels,
-// where a tile holds tens of thousands of sub-pixel Gaussians of which a pixel sees a few percent, walk a
-// few records per lane per round instead of every record of the sub-tile; fine levels, where most records
-// cover whole sub-tiles, walk the shared mask in lock-step.
+// One workgroup per tile.  The tile is split into 8x8 sub-tiles, one wave64 each, one pixel per lane; a
+// sub-tile is walked as BW x BW blocks (BW = 4: four blocks, one per 16-lane DPP row; BW = 8: the whole
+// wave).  The tile's depth-sorted list is staged in rounds of DEPTH records per thread into LDS; the
+// records of the next round are fetched into registers while the current one is composited.  Each staged
+// record carries its exact pixel rectangle (every pixel outside it has alpha < exp(-1/2)/255, so it would be
+// skipped anyway), and sets its bit in the mask of every block its rectangle meets.  Each block then walks
+// the set bits of its mask in list order, in lock-step (one record per step for the block's lanes, read from
+// LDS by broadcast); the result is the same bit for bit for every block size, since a record is skipped only
+// where its rectangle misses the pixel.  Small blocks waste fewer lanes on records that cover part of a
+// sub-tile (coarse pyramid levels hold many sub-pixel Gaussians) and sum gradients over 16 lanes instead of
+// 64.
 //
 // The backward walks the list in the same front-to-back order as the forward.  With the forward's final
 // values C, D, V of a pixel and its upstream gradient g, the gradient of alpha_i is
@@ -28,25 +28,29 @@ namespace {
 
 using gsk::DevOpts;
 
-template <int TW, int TH, int DEPTH>
+template <int TW, int TH, int DEPTH, int BW_ = 4>
 struct Geo {
   static constexpr int SX = TW / 8;            // sub-tiles across
   static constexpr int SY = TH / 8;            // sub-tiles down
   static constexpr int NW = SX * SY;           // waves per tile
   static constexpr int NT = 64 * NW;           // threads = pixels of the tile
   static constexpr int BATCH = NT * DEPTH;     // records staged per round
-  static constexpr int MC = BATCH / 64;        // 64-bit mask words per pixel
+  static constexpr int MC = BATCH / 64;        // 64-bit mask words per block
+  static constexpr int BW = BW_;               // block width (pixels)
+  static constexpr int BS = 8 / BW;            // blocks across a sub-tile
+  static constexpr int BPW = BS * BS;          // blocks per wave
+  static constexpr int BL = BW * BW;           // lanes per block
+  static constexpr int NB = NW * BPW;          // blocks per tile
   static_assert(TW % 8 == 0 && TH % 8 == 0 && NW >= 1 && NW <= 4, "tile shape");
   static_assert(DEPTH == 1 || DEPTH == 2, "batch depth");
+  static_assert(BW == 4 || BW == 8, "block width");
 };
 
 template <class G>
 struct Stage {
   float4 A[G::BATCH], B[G::BATCH], C[G::BATCH];
   int32_t r[G::BATCH];
-  uint64_t pm[G::MC][G::NT];    // per pixel (thread index): staged records handed to it
-  uint64_t wide[G::NW][G::MC];  // per sub-tile: staged records walked by all its lanes
-  uint64_t uw[G::NW][G::MC];    // per sub-tile: staged records handed to some of its pixels
+  uint64_t bm[G::MC][G::NB];    // per block: staged records whose rectangle meets it
   int alive[G::NW];             // per wave: a pixel is still live
 };
 
@@ -54,6 +58,7 @@ struct TileCtx {
   int view, W, H, tx0, ty0;  // view and tile origin (pixels)
   int px, py;                // this lane's pixel
   int wave, lane;
+  int blk, blk_lane0;        // this lane's block in the tile, and the block's first lane in the wave
   int64_t pix_off;
   float weight;
   bool inside;               // pixel inside the image
@@ -72,8 +77,12 @@ __device__ __forceinline__ void tile_at(const gs_camera* __restrict__ cams, int 
   t.H = c.height;
   t.tx0 = txi * (8 * G::SX);
   t.ty0 = tyi * (8 * G::SY);
-  t.px = t.tx0 + (t.wave % G::SX) * 8 + (t.lane & 7);
-  t.py = t.ty0 + (t.wave / G::SX) * 8 + (t.lane >> 3);
+  // lanes of a block are consecutive; blocks of a wave in row-major order over its sub-tile
+  const int r = t.lane / G::BL, p = t.lane % G::BL;
+  t.blk = t.wave * G::BPW + r;
+  t.blk_lane0 = r * G::BL;
+  t.px = t.tx0 + (t.wave % G::SX) * 8 + (r % G::BS) * G::BW + p % G::BW;
+  t.py = t.ty0 + (t.wave / G::SX) * 8 + (r / G::BS) * G::BW + p / G::BW;
   t.pix_off = c.pixel_offset;
   t.weight = c.loss_weight;
   t.inside = t.px < t.W && t.py < t.H;
@@ -173,68 +182,60 @@ __device__ __forceinline__ bool round_barrier(Stage<G>& s, const TileCtx& t, boo
   return any;
 }
 
-// Clear this thread's pixel masks (and, for the first threads, the sub-tile masks).
+// Clear the block masks.
 template <class G>
 __device__ __forceinline__ void clear_masks(Stage<G>& s) {
-#pragma unroll
-  for (int c = 0; c < G::MC; ++c) s.pm[c][threadIdx.x] = 0ull;
-  if ((int)threadIdx.x < G::NW * G::MC) {
-    (&s.wide[0][0])[threadIdx.x] = 0ull;
-    (&s.uw[0][0])[threadIdx.x] = 0ull;
-  }
+  for (int i = threadIdx.x; i < G::MC * G::NB; i += G::NT) (&s.bm[0][0])[i] = 0ull;
 }
 
-// Hand this thread's staged records to the pixels (or sub-tiles) their rectangles meet.
+// Set this thread's staged records in the masks of the blocks their rectangles meet.  Blocks are numbered
+// wave-major (the wave's sub-tile, then row-major inside it).
 template <class G, int DEPTH>
-__device__ __forceinline__ void scatter(Stage<G>& s, const TileCtx& t, int nb, int smax) {
+__device__ __forceinline__ void scatter(Stage<G>& s, const TileCtx& t, int nb) {
+  constexpr int GX = 8 * G::SX / G::BW, GY = 8 * G::SY / G::BW;  // blocks across and down the tile
 #pragma unroll
   for (int k = 0; k < DEPTH; ++k) {
     const int j = k * G::NT + (int)threadIdx.x;
     if (j >= nb) continue;
     int x0, x1, y0, y1;
     unpack_rect(s.C[j], x0, x1, y0, y1);
+    const int gx0 = max(x0 - t.tx0, 0) / G::BW, gx1 = min(x1 - t.tx0, 8 * G::SX - 1) / G::BW;
+    const int gy0 = max(y0 - t.ty0, 0) / G::BW, gy1 = min(y1 - t.ty0, 8 * G::SY - 1) / G::BW;
+    if (x1 < t.tx0 || y1 < t.ty0 || gx0 >= GX || gy0 >= GY) continue;
     const uint64_t bit = 1ull << (j & 63);
     const int wd = j >> 6;
-#pragma unroll
-    for (int w = 0; w < G::NW; ++w) {
-      const int sx0 = t.tx0 + (w % G::SX) * 8, sy0 = t.ty0 + (w / G::SX) * 8;
-      const int cx0 = max(x0, sx0), cx1 = min(x1, sx0 + 7), cy0 = max(y0, sy0), cy1 = min(y1, sy0 + 7);
-      if (cx0 > cx1 || cy0 > cy1) continue;
-      if ((cx1 - cx0 + 1) * (cy1 - cy0 + 1) > smax) {
-        atomicOr(&s.wide[w][wd], bit);
-        continue;
+    for (int gy = gy0; gy <= gy1; ++gy)
+      for (int gx = gx0; gx <= gx1; ++gx) {
+        const int b = ((gy / G::BS) * G::SX + gx / G::BS) * G::BPW + (gy % G::BS) * G::BS + gx % G::BS;
+        atomicOr(&s.bm[wd][b], bit);
       }
-      atomicOr(&s.uw[w][wd], bit);
-      for (int y = cy0; y <= cy1; ++y)
-        for (int x = cx0; x <= cx1; ++x) atomicOr(&s.pm[wd][w * 64 + (y - sy0) * 8 + (x - sx0)], bit);
-    }
   }
 }
 
-// Walk one staged round for this lane's pixel, in list order, over exactly the records that can touch it:
-// its own bits and its sub-tile's shared bits.  When the longest per-lane walk of the wave is at least half
-// the wave's union of records, every lane walks the union instead, so the wave moves in lock-step (one record
-// at a time, broadcast LDS reads, one wave sum per record in the backward); a record outside a pixel's
-// rectangle is skipped there by its alpha, so the result is the same.
+// Sum over the lanes of this lane's block (BW = 4: its 16-lane row, total in every lane of the row; BW = 8:
+// the wave, total in lane 63).
+template <class G>
+__device__ __forceinline__ float block_sum(float x) {
+  if (G::BW == 8) return gsk::wave_sum_last(x);
+  x += gsk::dpp_f<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += gsk::dpp_f<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += gsk::dpp_f<0x141>(x);  // row_half_mirror
+  x += gsk::dpp_f<0x140>(x);  // row_mirror
+  return x;
+}
+
+// Walk one staged round: every block walks the set bits of its mask in order, its lanes in lock-step, and
+// stops once all its pixels have ended.
 //   step(j, A, B, C, acc) -> contributed   (per lane; clears live at the stop)
 //   post(j, hit, acc)                      (whole wave, once per step, only if SYNC)
 template <class G, bool SYNC, class Step, class Post>
 __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, bool& live, Step step, Post post) {
-  int cnt = 0, nu = 0;
-#pragma unroll
-  for (int c = 0; c < G::MC; ++c) {
-    const uint64_t wd = s.wide[t.wave][c];
-    cnt += __popcll(s.pm[c][threadIdx.x] | wd);
-    nu += __popcll(s.uw[t.wave][c] | wd);
-  }
-  const int cmax = gsk::wave_max_nonneg(live ? cnt : 0);
-  if (cmax == 0) return;
-  const bool lock = 2 * cmax >= nu;
+  constexpr uint64_t BMASK = G::BL == 64 ? ~0ull : ((1ull << G::BL) - 1);
 #pragma unroll 1
   for (int c = 0; c < G::MC; ++c) {
-    uint64_t m = live ? ((lock ? s.uw[t.wave][c] : s.pm[c][threadIdx.x]) | s.wide[t.wave][c]) : 0ull;
+    uint64_t m = ((__ballot(live) >> t.blk_lane0) & BMASK) ? s.bm[c][t.blk] : 0ull;
     if (__ballot(m != 0) == 0) continue;
-    // the lane's next record is fetched from LDS while the current one is composited
+    // the block's next record is fetched from LDS while the current one is composited
     int jn = c * 64 + (m ? __builtin_ctzll(m) : 0);
     float4 An = s.A[jn], Bn = s.B[jn], Cn = s.C[jn];
     while (SYNC ? __ballot(m != 0) != 0 : m != 0) {
@@ -250,10 +251,10 @@ __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, 
         An = s.A[jn];
         Bn = s.B[jn];
         Cn = s.C[jn];
-        hit = step(j, A, B, C, acc);
-        if (!live) m = 0;
+        if (live) hit = step(j, A, B, C, acc);
       }
       if (SYNC) post(j, hit, acc);
+      if (((__ballot(live) >> t.blk_lane0) & BMASK) == 0) m = 0;
     }
   }
 }
@@ -277,7 +278,7 @@ __device__ __forceinline__ void sweep(Stage<G>& s, const float4* __restrict__ re
     clear_masks<G>(s);
     stage_round<G, DEPTH>(s, rec, vals, b0, rg.y, fr, frn, fA, fB, fC);
     __syncthreads();
-    scatter<G, DEPTH>(s, t, nb, op.scatter_max);
+    scatter<G, DEPTH>(s, t, nb);
     __syncthreads();
     walk_round<G, SYNC>(s, t, live, step, post);
   }
@@ -339,7 +340,7 @@ __device__ __forceinline__ void write_pixel(const TileCtx& t, const DevOpts& op,
   out_vis[t.pix_off + i] = Vs;
 }
 
-template <int TW, int TH, int DEPTH>
+template <int TW, int TH, int DEPTH, int BW>
 __global__ __launch_bounds__(TW * TH) void k_render_fwd(const float4* __restrict__ rec,
                                                         const int32_t* __restrict__ vals,
                                                         const int2* __restrict__ range,
@@ -347,7 +348,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_fwd(const float4* __restrict
                                                         const int32_t* __restrict__ order, DevOpts op,
                                                         float* __restrict__ out_rgb, float* __restrict__ out_depth,
                                                         float* __restrict__ out_vis) {
-  using G = Geo<TW, TH, DEPTH>;
+  using G = Geo<TW, TH, DEPTH, BW>;
   __shared__ Stage<G> s;
   TileCtx t;
   int tile;
@@ -495,21 +496,25 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
     T = Tn;
     return true;
   };
-  // sum the partials of one step into the record's LDS accumulator (whole wave)
+  // sum the partials of one step into the records' LDS accumulators (whole wave; one record per block)
   auto post = [&](int j, bool hit, const float* acc) {
     const uint64_t hits = __ballot(hit);
     if (hits == 0) return;
-    const int j0 = __builtin_amdgcn_readlane(j, __builtin_ctzll(hits));
-    if (__popcll(hits) > 4 && __ballot(hit && j != j0) == 0) {
-      // every contributing lane is on record j0: one wave sum per value
+    if (__popcll(hits) <= 4) {
+      // few contributing lanes: each adds its own partials
+      if (hit) {
 #pragma unroll
-      for (int q = 0; q < 10; ++q) {
-        const float sum = gsk::wave_sum_last(acc[q]);
-        if (t.lane == 63) atomicAdd(&gacc[q][j0], sum);
+        for (int q = 0; q < 10; ++q) atomicAdd(&gacc[q][j], acc[q]);
       }
-    } else if (hit) {
+      return;
+    }
+    float sum[10];
 #pragma unroll
-      for (int q = 0; q < 10; ++q) atomicAdd(&gacc[q][j], acc[q]);
+    for (int q = 0; q < 10; ++q) sum[q] = block_sum<G>(acc[q]);
+    constexpr uint64_t BMASK = G::BL == 64 ? ~0ull : ((1ull << G::BL) - 1);
+    if ((t.lane % G::BL) == G::BL - 1 && ((hits >> t.blk_lane0) & BMASK) != 0) {
+#pragma unroll
+      for (int q = 0; q < 10; ++q) atomicAdd(&gacc[q][j], sum[q]);
     }
   };
   sweep<G, DEPTH, true>(s, rec, vals, rg, t, op, live,
@@ -549,13 +554,13 @@ __device__ __forceinline__ void tile_backward(Stage<G>& s, float (*gacc)[G::BATC
   backward_walk<G, DEPTH>(s, gacc, rec, vals, rg, t, op, t.inside, 1.f, 0.f, gr, gg, gb, gd, gv, S, a.rgrad);
 }
 
-template <int TW, int TH, int DEPTH, bool HAVE_FWD, bool LOSS>
+template <int TW, int TH, int DEPTH, int BW, bool HAVE_FWD, bool LOSS>
 __global__ __launch_bounds__(TW * TH) void k_render_bwd(const float4* __restrict__ rec,
                                                         const int32_t* __restrict__ vals,
                                                         const int2* __restrict__ range,
                                                         const gs_camera* __restrict__ cams, int V, int n_tiles,
                                                         const int32_t* __restrict__ order, DevOpts op, BwdArgs a) {
-  using G = Geo<TW, TH, DEPTH>;
+  using G = Geo<TW, TH, DEPTH, BW>;
   __shared__ Stage<G> s;
   __shared__ float gacc[10][G::BATCH];
   TileCtx t;
@@ -604,13 +609,13 @@ __device__ __forceinline__ void segment_sums(Stage<G>& s, const float4* __restri
 
 // Backward over the work items: whole tiles run the forward sweep (or read the forward images), the upstream
 // gradient and the backward walk; segments of split tiles run step 1.
-template <int TW, int TH, int DEPTH, bool HAVE_FWD, bool LOSS>
+template <int TW, int TH, int DEPTH, int BW, bool HAVE_FWD, bool LOSS>
 __global__ __launch_bounds__(TW * TH) void k_fused_main(const float4* __restrict__ rec,
                                                         const int32_t* __restrict__ vals,
                                                         const int2* __restrict__ range,
                                                         const gs_camera* __restrict__ cams, int V, DevOpts op,
                                                         BwdArgs a, SegArgs g) {
-  using G = Geo<TW, TH, DEPTH>;
+  using G = Geo<TW, TH, DEPTH, BW>;
   __shared__ Stage<G> s;
   __shared__ float gacc[10][G::BATCH];
   if ((int)blockIdx.x >= g.counters[192]) return;
@@ -625,13 +630,13 @@ __global__ __launch_bounds__(TW * TH) void k_fused_main(const float4* __restrict
 }
 
 // Forward over the work items: whole tiles are composited and written; segments of split tiles run step 1.
-template <int TW, int TH, int DEPTH>
+template <int TW, int TH, int DEPTH, int BW>
 __global__ __launch_bounds__(TW * TH) void k_fwd_main(const float4* __restrict__ rec, const int32_t* __restrict__ vals,
                                                       const int2* __restrict__ range,
                                                       const gs_camera* __restrict__ cams, int V, DevOpts op,
                                                       SegArgs g, float* __restrict__ out_rgb,
                                                       float* __restrict__ out_depth, float* __restrict__ out_vis) {
-  using G = Geo<TW, TH, DEPTH>;
+  using G = Geo<TW, TH, DEPTH, BW>;
   __shared__ Stage<G> s;
   if ((int)blockIdx.x >= g.counters[192]) return;
   const int4 it = g.items[blockIdx.x];
@@ -647,12 +652,12 @@ __global__ __launch_bounds__(TW * TH) void k_fwd_main(const float4* __restrict__
   write_pixel(t, op, T, Cr, Cg, Cb, D, Vs, out_rgb, out_depth, out_vis);
 }
 
-template <int TW, int TH, int DEPTH>
+template <int TW, int TH, int DEPTH, int BW>
 __global__ __launch_bounds__(TW * TH) void k_seg_stop(const float4* __restrict__ rec, const int32_t* __restrict__ vals,
                                                       const int2* __restrict__ range,
                                                       const gs_camera* __restrict__ cams, int V, DevOpts op,
                                                       SegArgs g) {
-  using G = Geo<TW, TH, DEPTH>;
+  using G = Geo<TW, TH, DEPTH, BW>;
   __shared__ Stage<G> s;
   if ((int)blockIdx.x >= g.counters[193]) return;
   const int4 it = g.items[blockIdx.x];
@@ -713,11 +718,11 @@ __device__ __forceinline__ void split_final(const float* sp, const float* xp, in
 }
 
 // Forward of split tiles, step 3: write the final values.
-template <int TW, int TH>
+template <int TW, int TH, int BW>
 __global__ __launch_bounds__(TW * TH) void k_seg_fwd_out(const gs_camera* __restrict__ cams, int V, DevOpts op,
                                                          SegArgs g, float* __restrict__ out_rgb,
                                                          float* __restrict__ out_depth, float* __restrict__ out_vis) {
-  using G = Geo<TW, TH, 1>;
+  using G = Geo<TW, TH, 1, BW>;
   const int l = blockIdx.x;
   if (l >= g.counters[194]) return;
   TileCtx t;
@@ -732,10 +737,10 @@ __global__ __launch_bounds__(TW * TH) void k_seg_fwd_out(const gs_camera* __rest
 
 // Backward of split tiles, step 3: final values (or the forward images), upstream gradient, S and the start
 // state (T_start, P_start) of every segment; T_start = 0 marks a segment after the pixel's end.
-template <int TW, int TH, bool HAVE_FWD, bool LOSS>
+template <int TW, int TH, int BW, bool HAVE_FWD, bool LOSS>
 __global__ __launch_bounds__(TW * TH) void k_seg_combine(const gs_camera* __restrict__ cams, int V, DevOpts op,
                                                          BwdArgs a, SegArgs g) {
-  using G = Geo<TW, TH, 1>;
+  using G = Geo<TW, TH, 1, BW>;
   const int l = blockIdx.x;
   if (l >= g.counters[194]) return;
   const int n = g.seg_count[l];
@@ -782,12 +787,12 @@ __global__ __launch_bounds__(TW * TH) void k_seg_combine(const gs_camera* __rest
   xp[11 * G::NT] = S;
 }
 
-template <int TW, int TH, int DEPTH>
+template <int TW, int TH, int DEPTH, int BW>
 __global__ __launch_bounds__(TW * TH) void k_seg_bwd(const float4* __restrict__ rec, const int32_t* __restrict__ vals,
                                                      const int2* __restrict__ range,
                                                      const gs_camera* __restrict__ cams, int V, DevOpts op,
                                                      BwdArgs a, SegArgs g) {
-  using G = Geo<TW, TH, DEPTH>;
+  using G = Geo<TW, TH, DEPTH, BW>;
   __shared__ Stage<G> s;
   __shared__ float gacc[10][G::BATCH];
   if ((int)blockIdx.x >= g.counters[193]) return;
@@ -891,7 +896,7 @@ SegArgs seg_args(const gs_frame& f) {
   return g;
 }
 
-template <int TW, int TH, int DEPTH>
+template <int TW, int TH, int DEPTH, int BW>
 hipError_t launch_fwd(const gs_frame& f, const DevOpts& op, const gs_images& out, hipStream_t st) {
   const int sorted = f.sort_passes & 1;
   const auto* rec = reinterpret_cast<const float4*>(f.rec);
@@ -900,21 +905,21 @@ hipError_t launch_fwd(const gs_frame& f, const DevOpts& op, const gs_images& out
   if (f.seg_len > 0) {
     // long lists split into depth segments
     const SegArgs g = seg_args(f);
-    k_fwd_main<TW, TH, DEPTH><<<f.item_cap, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, op, g, out.rgb,
+    k_fwd_main<TW, TH, DEPTH, BW><<<f.item_cap, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, op, g, out.rgb,
                                                           out.depth, out.vis);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_seg_stop<TW, TH, DEPTH><<<f.seg_cap, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, op, g);
+    k_seg_stop<TW, TH, DEPTH, BW><<<f.seg_cap, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, op, g);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_seg_fwd_out<TW, TH><<<f.long_cap, bs, 0, st>>>(f.cams, f.n_views, op, g, out.rgb, out.depth, out.vis);
+    k_seg_fwd_out<TW, TH, BW><<<f.long_cap, bs, 0, st>>>(f.cams, f.n_views, op, g, out.rgb, out.depth, out.vis);
     return hipGetLastError();
   }
-  k_render_fwd<TW, TH, DEPTH><<<f.n_tiles, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, f.n_tiles,
+  k_render_fwd<TW, TH, DEPTH, BW><<<f.n_tiles, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, f.n_tiles,
                                                         f.tile_order, op, out.rgb, out.depth, out.vis);
   return hipGetLastError();
 }
 
-template <int TW, int TH, int DEPTH, bool HAVE_FWD, bool LOSS>
+template <int TW, int TH, int DEPTH, int BW, bool HAVE_FWD, bool LOSS>
 hipError_t launch_split_bwd(const gs_frame& f, const DevOpts& op, const BwdArgs& a, hipStream_t st) {
   const int sorted = f.sort_passes & 1;
   const auto* rec = reinterpret_cast<const float4*>(f.rec);
@@ -922,26 +927,26 @@ hipError_t launch_split_bwd(const gs_frame& f, const DevOpts& op, const BwdArgs&
   const int32_t* vals = f.vals[sorted];
   const int bs = TW * TH;
   const SegArgs g = seg_args(f);
-  k_fused_main<TW, TH, DEPTH, HAVE_FWD, LOSS><<<f.item_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g);
+  k_fused_main<TW, TH, DEPTH, BW, HAVE_FWD, LOSS><<<f.item_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_seg_stop<TW, TH, DEPTH><<<f.seg_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, g);
+  k_seg_stop<TW, TH, DEPTH, BW><<<f.seg_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, g);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_seg_combine<TW, TH, HAVE_FWD, LOSS><<<f.long_cap, bs, 0, st>>>(f.cams, f.n_views, op, a, g);
+  k_seg_combine<TW, TH, BW, HAVE_FWD, LOSS><<<f.long_cap, bs, 0, st>>>(f.cams, f.n_views, op, a, g);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_seg_bwd<TW, TH, DEPTH><<<f.seg_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g);
+  k_seg_bwd<TW, TH, DEPTH, BW><<<f.seg_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g);
   return hipGetLastError();
 }
 
-template <int TW, int TH, int DEPTH>
+template <int TW, int TH, int DEPTH, int BW>
 hipError_t launch_bwd(const gs_frame& f, const DevOpts& op, bool have_fwd, bool loss, const BwdArgs& a,
                       hipStream_t st) {
   if (f.seg_len > 0) {
     // long lists split into depth segments
-    if (have_fwd && loss) return launch_split_bwd<TW, TH, DEPTH, true, true>(f, op, a, st);
-    if (have_fwd) return launch_split_bwd<TW, TH, DEPTH, true, false>(f, op, a, st);
-    if (loss) return launch_split_bwd<TW, TH, DEPTH, false, true>(f, op, a, st);
-    return launch_split_bwd<TW, TH, DEPTH, false, false>(f, op, a, st);
+    if (have_fwd && loss) return launch_split_bwd<TW, TH, DEPTH, BW, true, true>(f, op, a, st);
+    if (have_fwd) return launch_split_bwd<TW, TH, DEPTH, BW, true, false>(f, op, a, st);
+    if (loss) return launch_split_bwd<TW, TH, DEPTH, BW, false, true>(f, op, a, st);
+    return launch_split_bwd<TW, TH, DEPTH, BW, false, false>(f, op, a, st);
   }
   const int sorted = f.sort_passes & 1;
   const auto* rec = reinterpret_cast<const float4*>(f.rec);
@@ -949,16 +954,16 @@ hipError_t launch_bwd(const gs_frame& f, const DevOpts& op, bool have_fwd, bool 
   const int nb = f.n_tiles, bs = TW * TH;
   const int32_t* vals = f.vals[sorted];
   if (have_fwd && loss)
-    k_render_bwd<TW, TH, DEPTH, true, true><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb, f.tile_order,
+    k_render_bwd<TW, TH, DEPTH, BW, true, true><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb, f.tile_order,
                                                                op, a);
   else if (have_fwd)
-    k_render_bwd<TW, TH, DEPTH, true, false><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb,
+    k_render_bwd<TW, TH, DEPTH, BW, true, false><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb,
                                                                 f.tile_order, op, a);
   else if (loss)
-    k_render_bwd<TW, TH, DEPTH, false, true><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb,
+    k_render_bwd<TW, TH, DEPTH, BW, false, true><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb,
                                                                 f.tile_order, op, a);
   else
-    k_render_bwd<TW, TH, DEPTH, false, false><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb,
+    k_render_bwd<TW, TH, DEPTH, BW, false, false><<<nb, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, nb,
                                                                  f.tile_order, op, a);
   return hipGetLastError();
 }
@@ -976,11 +981,17 @@ hipError_t launch_count(const gs_frame& f, const DevOpts& op, unsigned long long
 
 namespace gs_launch {
 
-// Tile shape (one wave per 8x8 sub-tile) and records staged per thread (o.batch_depth; 0 means 1).
-#define GS_TILE_DISPATCH_D(FN, TW, TH, ...)                    \
-  do {                                                         \
-    if (o.batch_depth == 2) return FN<TW, TH, 2>(__VA_ARGS__); \
-    return FN<TW, TH, 1>(__VA_ARGS__);                         \
+// Tile shape (one wave per 8x8 sub-tile), records staged per thread (o.batch_depth; 0 means 1) and block
+// width (o.block_w; 0 means 4).
+#define GS_TILE_DISPATCH_B(FN, TW, TH, DP, ...)                     \
+  do {                                                              \
+    if (o.block_w == 8) return FN<TW, TH, DP, 8>(__VA_ARGS__);      \
+    return FN<TW, TH, DP, 4>(__VA_ARGS__);                          \
+  } while (0)
+#define GS_TILE_DISPATCH_D(FN, TW, TH, ...)                                       \
+  do {                                                                            \
+    if (o.batch_depth == 2) GS_TILE_DISPATCH_B(FN, TW, TH, 2, __VA_ARGS__);      \
+    GS_TILE_DISPATCH_B(FN, TW, TH, 1, __VA_ARGS__);                              \
   } while (0)
 #define GS_TILE_DISPATCH(FN, ...)                                                      \
   do {                                                                                 \

@@ -28,12 +28,12 @@ def log(*a):
     print(*a, flush=True)
 
 
-def run_gpu(sc, tile=(16, 16), g_images=None, targets=True, fused=False, capacity=None, zero=True, smax=0, depth=0,
+def run_gpu(sc, tile=(16, 16), g_images=None, targets=True, fused=False, capacity=None, zero=True, bw=0, depth=0,
             seg=0):
     """Project, bin, render and (optionally) backpropagate one scene; returns numpy results."""
     torch.cuda.synchronize()
     model = GaussianModel(sc.params(), sc.sh_degree)
-    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], scatter_max=smax, batch_depth=depth, seg_len=seg)
+    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], block_w=bw, batch_depth=depth, seg_len=seg)
     fr = B.Frame(model.n, sc.cams, opts, capacity)
     B.gs_project(model.ps, fr, zero_grads=zero)
     n_inst = B.gs_bin_tiles(fr, sync_count=True)
@@ -216,15 +216,14 @@ def test_forward_is_tile_size_invariant_and_deterministic(gpu_lib):
     again = run_gpu(sc, targets=False, seg=-1)
     for k in ("rgb", "depth", "vis"):
         assert np.array_equal(base[k], again[k]), k
-    # tile shapes, records per thread and the per-pixel hand-out threshold (-1: every record is walked by
-    # all lanes of the sub-tiles it meets; 64: every record is handed to its pixels only)
+    # tile shapes, records per thread and block widths of the lock-step walk
     for tile in [(16, 16), (8, 8), (16, 8), (32, 8)]:
-        for depth, smax in [(1, 0), (2, 0), (1, -1), (2, 64)]:
-            log("tile", tile, "depth", depth, "scatter_max", smax)
-            o = run_gpu(sc, tile=tile, targets=False, smax=smax, depth=depth, seg=-1)
+        for depth, bw in [(1, 4), (2, 4), (1, 8), (2, 8)]:
+            log("tile", tile, "depth", depth, "block", bw)
+            o = run_gpu(sc, tile=tile, targets=False, bw=bw, depth=depth, seg=-1)
             for k in ("rgb", "depth", "vis"):
                 d = np.abs(base[k] - o[k])
-                assert np.array_equal(base[k], o[k]), (tile, depth, smax, k, int((d > 0).sum()), float(d.max()))
+                assert np.array_equal(base[k], o[k]), (tile, depth, bw, k, int((d > 0).sum()), float(d.max()))
 
 
 # ----------------------------------------------------------------------------- backward
@@ -388,13 +387,13 @@ def test_pair_counts_match_oracle(gpu_lib):
     assert ev >= co
 
 
-@pytest.mark.parametrize("tile,depth,smax", [((16, 16), 1, 0), ((16, 16), 2, 64), ((8, 8), 2, 0), ((32, 8), 1, 4),
-                                              ((16, 8), 1, 0)])
-def test_backward_identical_across_walk_options(gpu_lib, tile, depth, smax):
-    """Gradients agree (to atomic summation order) whatever the tile shape, batch depth and hand-out rule."""
+@pytest.mark.parametrize("tile,depth,bw", [((16, 16), 1, 4), ((16, 16), 2, 8), ((8, 8), 2, 4), ((32, 8), 1, 8),
+                                            ((16, 8), 1, 4)])
+def test_backward_identical_across_walk_options(gpu_lib, tile, depth, bw):
+    """Gradients agree (to atomic summation order) whatever the tile shape, batch depth and block width."""
     sc = scenes.random_scene(1500, 2000, 100, 70, sh_degree=1, views=2, log_scale_mu=-2.3, depth_fraction=0.3)
-    ref = run_gpu(sc, targets=True, fused=True, smax=-1, seg=-1)
-    out = run_gpu(sc, targets=True, fused=True, tile=tile, depth=depth, smax=smax, seg=-1)
+    ref = run_gpu(sc, targets=True, fused=True, bw=8, seg=-1)
+    out = run_gpu(sc, targets=True, fused=True, tile=tile, depth=depth, bw=bw, seg=-1)
     np.testing.assert_allclose(out["loss"], ref["loss"], rtol=1e-6)
     for k in ref["grads"]:
         a, b = ref["grads"][k], out["grads"][k]
@@ -416,19 +415,19 @@ def test_tile_schedule_is_a_longest_first_permutation(gpu_lib):
 
 
 def _subpixel_scene(seed, n=20000, W=64, H=48, views=1, deg=0):
-    # many sub-pixel Gaussians per tile: most records are handed to a few pixels each
+    # many sub-pixel Gaussians per tile: most records meet one 4x4 block
     return scenes.random_scene(seed, n, W, H, sh_degree=deg, views=views, log_scale_mu=-5.0, log_scale_sigma=0.3,
                                opacity_sigma=0.5, depth_fraction=0.5)
 
 
-def test_per_pixel_walk_matches_shared_walk_and_oracle(gpu_lib):
+def test_block_walks_match_on_subpixel_scene_and_oracle(gpu_lib):
     sc = _subpixel_scene(1700, views=2)
     # unsplit lists: the walks must agree bit for bit (split lists are checked in the depth-segment tests)
-    shared = run_gpu(sc, tile=(16, 16), smax=-1, targets=False, seg=-1)  # every record walked by whole sub-tiles
-    for tile, depth, smax in [((16, 16), 1, 0), ((8, 8), 2, 0), ((32, 8), 1, 64), ((16, 8), 2, 4)]:
-        o = run_gpu(sc, tile=tile, depth=depth, smax=smax, targets=False, seg=-1)
+    shared = run_gpu(sc, tile=(16, 16), bw=8, targets=False, seg=-1)  # whole sub-tiles in lock-step
+    for tile, depth, bw in [((16, 16), 1, 4), ((8, 8), 2, 4), ((32, 8), 1, 8), ((16, 8), 2, 4)]:
+        o = run_gpu(sc, tile=tile, depth=depth, bw=bw, targets=False, seg=-1)
         for k in ("rgb", "depth", "vis"):
-            assert np.array_equal(shared[k], o[k]), (tile, depth, smax, k)
+            assert np.array_equal(shared[k], o[k]), (tile, depth, bw, k)
     shared["cams"] = sc.cams
     ref = oracle.forward(32, sc.params(), 0, sc.cams)
     check_images(shared, ref, ref["near"], "sub-pixel fwd")
@@ -437,15 +436,15 @@ def test_per_pixel_walk_matches_shared_walk_and_oracle(gpu_lib):
 
 
 @pytest.mark.parametrize("fused", [False, True])
-def test_per_pixel_walk_backward_matches_fp64_oracle(gpu_lib, fused):
+def test_block_walk_backward_matches_fp64_oracle(gpu_lib, fused):
     sc = _subpixel_scene(1800, n=12000, views=2, deg=1)
-    out = run_gpu(sc, targets=True, fused=fused, tile=(16, 16), seg=-1)
+    out = run_gpu(sc, targets=True, fused=fused, tile=(16, 16), bw=4, seg=-1)
     L, ref, exc, nn, _ = oracle.backward(64, sc.params(), 1, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
     np.testing.assert_allclose(out["loss"], L, rtol=1e-5)
     check_grads(out["grads"], ref, exc, f"sub-pixel fused={fused}", nn, sc.total_pixels)
-    # the per-pixel walk sums partials in another order; rotation gradients of near-isotropic sub-pixel
-    # Gaussians are ill-conditioned in FP32, hence 1e-4 here (both sides are within 1e-3 of FP64 above)
-    shared = run_gpu(sc, targets=True, fused=fused, tile=(16, 16), smax=-1, seg=-1)
+    # 4x4 blocks sum partials in another order than whole waves; rotation gradients of near-isotropic
+    # sub-pixel Gaussians are ill-conditioned in FP32, hence 1e-4 here (both are within 1e-3 of FP64 above)
+    shared = run_gpu(sc, targets=True, fused=fused, tile=(16, 16), bw=8, seg=-1)
     for k in shared["grads"]:
         a, b = shared["grads"][k], out["grads"][k]
         rms = np.sqrt((a.astype(np.float64) ** 2).mean()) + 1e-30

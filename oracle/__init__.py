@@ -146,8 +146,11 @@ def forward(prec: int, params, sh_degree: int, cams, mode: int = 1, **opt_over) 
 
 
 def backward(prec: int, params, sh_degree: int, cams, g_rgb=None, g_depth=None, g_vis=None, tgt_rgb=None,
-             tgt_depth=None, **opt_over):
-    """Loss and analytic gradients (+ excused Gaussians and the count of near-threshold pixels)."""
+             tgt_depth=None, decisions: Optional[int] = None, **opt_over):
+    """Loss and analytic gradients (+ excused Gaussians and the count of near-threshold pixels).
+
+    prec=64 with decisions=32: every discrete choice (cull, skip, clamp, stop, colour clamp, loss sign) taken
+    by the FP32 evaluation, every value computed in FP64 along those choices."""
     P = _Params(params, sh_degree)
     K = (sh_degree + 1) ** 2
     gr = dict(means=np.zeros((P.n, 3)), log_scales=np.zeros((P.n, 3)), quats=np.zeros((P.n, 4)),
@@ -157,12 +160,29 @@ def backward(prec: int, params, sh_degree: int, cams, g_rgb=None, g_depth=None, 
     img = _image_buffers(cams)
     conv = lambda a: None if a is None else _f64(a)
     g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth = map(conv, (g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth))
-    L = lib().oracle_backward(ctypes.c_int(prec), *P.args(), _p(cams_array(cams)), ctypes.c_int(len(cams)),
+    code = 3264 if (prec == 64 and decisions == 32) else prec
+    L = lib().oracle_backward(ctypes.c_int(code), *P.args(), _p(cams_array(cams)), ctypes.c_int(len(cams)),
                               _p(opts_array(**opt_over)), _p(g_rgb), _p(g_depth), _p(g_vis), _p(tgt_rgb),
                               _p(tgt_depth), _p(gr["means"]), _p(gr["log_scales"]), _p(gr["quats"]),
                               _p(gr["opacity"]), _p(gr["sh"]), _p(exc), _p(nn), _p(img["rgb"]), _p(img["depth"]),
                               _p(img["vis"]))
     return float(L), gr, exc.astype(bool), int(nn[0]), img
+
+
+def gradient_scale(params, sh_degree: int, cams, g_rgb=None, g_depth=None, g_vis=None, tgt_rgb=None,
+                   tgt_depth=None, **opt_over) -> Dict[str, np.ndarray]:
+    """Per gradient entry, the sum of the magnitudes of the terms it sums (FP64): an FP32 evaluation of the
+    gradient, in any order, is within a small multiple of 2^-24 times this of the exact value."""
+    P = _Params(params, sh_degree)
+    K = (sh_degree + 1) ** 2
+    s = dict(means=np.zeros((P.n, 3)), log_scales=np.zeros((P.n, 3)), quats=np.zeros((P.n, 4)),
+             opacity=np.zeros(P.n), sh=np.zeros((P.n, K, 3)))
+    conv = lambda a: None if a is None else _f64(a)
+    g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth = map(conv, (g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth))
+    lib().oracle_gradient_scale(*P.args(), _p(cams_array(cams)), ctypes.c_int(len(cams)), _p(opts_array(**opt_over)),
+                                _p(g_rgb), _p(g_depth), _p(g_vis), _p(tgt_rgb), _p(tgt_depth), _p(s["means"]),
+                                _p(s["log_scales"]), _p(s["quats"]), _p(s["opacity"]), _p(s["sh"]))
+    return s
 
 
 def loss(params, sh_degree: int, cams, tgt_rgb, tgt_depth, **opt_over) -> float:

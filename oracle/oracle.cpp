@@ -41,6 +41,9 @@
 namespace {
 
 // ---------------------------------------------------------------- options
+// Precision code of the FP64-values-along-FP32-decisions reference (oracle_backward).
+constexpr int PREC_MIXED = 3264;
+
 enum {
   OPT_NEAR = 0, OPT_GUARD, OPT_LOWPASS, OPT_ALPHA_MIN, OPT_ALPHA_MAX, OPT_T_MIN,
   OPT_BG0, OPT_BG1, OPT_BG2, OPT_TILE_W, OPT_TILE_H, OPT_LAMBDA_D, OPT_STOP_NEAR, OPT_COUNT
@@ -729,6 +732,241 @@ void project_backward_all(const Scene<R>& sc, const double* sh, const std::vecto
   }
 }
 
+// Per-pixel upstream gradients: from the loss when targets are given, else the given image gradients (the
+// returned value is then sum g * image, whose gradient they are).
+template <class R>
+double upstream(const Scene<R>& sc, const std::vector<PixelOut<R>>& img, const double* g_rgb, const double* g_depth,
+                const double* g_vis, const double* tgt_rgb, const double* tgt_depth, std::vector<double>& g,
+                std::vector<char>& near_sign) {
+  if (tgt_rgb) return loss_and_grad<R>(sc, img, tgt_rgb, tgt_depth, g, near_sign);
+  near_sign.assign(sc.total_px, 0);
+  g.assign((size_t)sc.total_px * 5, 0.0);
+  double L = 0;
+  for (int v = 0; v < sc.V; ++v) {
+    const Cam<R>& cam = sc.cams[v];
+    int64_t P = (int64_t)cam.W * cam.H, off = cam.pixel_offset;
+    for (int64_t i = 0; i < P; ++i) {
+      for (int ch = 0; ch < 3; ++ch) g[(off + i) * 5 + ch] = g_rgb ? g_rgb[3 * off + ch * P + i] : 0.0;
+      g[(off + i) * 5 + 3] = g_depth ? g_depth[off + i] : 0.0;
+      g[(off + i) * 5 + 4] = g_vis ? g_vis[off + i] : 0.0;
+      for (int ch = 0; ch < 3; ++ch) L += g[(off + i) * 5 + ch] * (double)img[off + i].C[ch];
+      L += g[(off + i) * 5 + 3] * (double)img[off + i].D + g[(off + i) * 5 + 4] * (double)img[off + i].Vis;
+    }
+  }
+  return L;
+}
+
+// ---------------------------------------------------------------- rounding scale of the gradients
+// Test tolerance only.  Each gradient entry is a sum over pixels and views of terms that cancel, so an FP32
+// evaluation (in any summation order) can be off from the exact value by a small multiple of 2^-24 times the
+// sum of the magnitudes of those terms, however small the result.  This computes that sum of magnitudes: the
+// per-pixel terms of the compositing backward with every difference replaced by the sum of the magnitudes of
+// its operands (the colour, depth and visibility "behind" sums bounded by the pixel's totals, which bounds
+// the forward-order form T_i q_i - (S - P_i) / (1 - alpha_i) as well), carried to the parameters through the
+// projection backward applied to each unit record gradient and taken entry by entry in absolute value.
+constexpr double kOps = 16;
+constexpr double kShTermBound = 4;
+
+void composite_backward_abs(const Scene<double>& sc, const std::vector<PixelOut<double>>& img,
+                            const std::vector<std::vector<Contrib<double>>>& traces, const std::vector<double>& g,
+                            std::vector<double>& arec) {
+  arec.assign((size_t)sc.V * sc.N * 10, 0.0);
+  for (int v = 0; v < sc.V; ++v) {
+    const Cam<double>& cam = sc.cams[v];
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int y = 0; y < cam.H; ++y)
+      for (int x = 0; x < cam.W; ++x) {
+        int64_t pix = cam.pixel_offset + (int64_t)y * cam.W + x;
+        const PixelOut<double>& o = img[pix];
+        double gC[3] = {std::fabs(g[pix * 5 + 0]), std::fabs(g[pix * 5 + 1]), std::fabs(g[pix * 5 + 2])};
+        double gD = std::fabs(g[pix * 5 + 3]), gV = std::fabs(g[pix * 5 + 4]);
+        double px = x + 0.5, py = y + 0.5;
+        const std::vector<Contrib<double>>& tr = traces[pix];
+        const double n = (double)tr.size();
+        for (size_t i = 0; i < tr.size(); ++i) {
+          const Contrib<double>& c = tr[i];
+          const Splat<double>& s = sc.splats[c.rec];
+          double om = 1.0 - c.alpha;
+          // weights: the rounding of T_i grows with the i factors it multiplies, that of a pixel total with its
+          // n terms; kOps covers the fixed operation count of each term
+          const double wi = (double)i + kOps, wn = n + kOps;
+          double dal = 0;
+          for (int ch = 0; ch < 3; ++ch) dal += gC[ch] * (wi * std::fabs(s.rgb[ch]) * c.T + wn * std::fabs(o.C[ch]) / om);
+          dal += gD * (wi * std::fabs(s.z) * c.T + wn * std::fabs(o.D) / om);
+          dal += gV * (wi * c.T + wn * std::fabs(o.Vis) / om);
+          double w = wi * c.alpha * c.T;
+          double dx = std::fabs(s.mx - px), dy = std::fabs(s.my - py);
+          double d_o = 0, dq = 0;
+          if (!c.clamped) { d_o = dal * c.G; dq = dal * c.alpha; }
+          double vals[10] = {(std::fabs(s.a) * dx + std::fabs(s.b) * dy) * dq,
+                             (std::fabs(s.c) * dy + std::fabs(s.b) * dx) * dq,
+                             0.5 * dx * dx * dq, dx * dy * dq, 0.5 * dy * dy * dq, d_o,
+                             w * gC[0], w * gC[1], w * gC[2], w * gD};
+          double* a = &arec[(size_t)c.rec * 10];
+          for (int k = 0; k < 10; ++k) {
+#pragma omp atomic
+            a[k] += vals[k];
+          }
+        }
+      }
+  }
+}
+
+void project_backward_abs(const Scene<double>& sc, const double* sh, const std::vector<double>& arec,
+                          double* smean, double* sscale, double* squat, double* sopac, double* ssh) {
+  const int K = sc.K;
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t g = 0; g < sc.N; ++g) {
+    std::vector<double> f((size_t)K * 3);
+    for (int v = 0; v < sc.V; ++v) {
+      int64_t r = (int64_t)v * sc.N + g;
+      if (!sc.proj[r].vis) continue;
+      for (int k = 0; k < 10; ++k) {
+        double a = arec[(size_t)r * 10 + k];
+        if (a == 0) continue;
+        double e[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        e[k] = 1;
+        double m[3] = {0, 0, 0}, s[3] = {0, 0, 0}, q[4] = {0, 0, 0, 0}, o[1] = {0};
+        std::fill(f.begin(), f.end(), 0.0);
+        project_backward_one<double>(sc.proj[r], sc.cams[v], sh, K, g, e, m, s, q, o, f.data());
+        for (int i = 0; i < 3; ++i) { smean[g * 3 + i] += a * std::fabs(m[i]); sscale[g * 3 + i] += a * std::fabs(s[i]); }
+        for (int i = 0; i < 4; ++i) squat[g * 4 + i] += a * std::fabs(q[i]);
+        sopac[g] += a * std::fabs(o[0]);
+        for (int i = 0; i < K * 3; ++i) ssh[g * K * 3 + i] += a * std::fabs(f[i]);
+        // the basis values themselves cancel (e.g. x^2 - y^2); on the unit sphere the magnitudes of the terms
+        // of each real basis function of degree <= 3 sum to less than 3, so 4 bounds their rounding scale
+        if (k >= 6 && k <= 8)
+          for (int j = 0; j < K; ++j) ssh[(g * K + j) * 3 + (k - 6)] += a * kShTermBound;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- FP64 values along FP32 decisions
+// Every discrete choice of the path (cull, tile rectangle, skip, clamp, stop, colour clamp, loss sign) is
+// taken by FP32 arithmetic where the path runs in FP32; near a threshold an FP64 evaluation may choose the
+// other side and then differs by a whole term, not by rounding.  This reference takes those decisions from
+// the FP32 evaluation and computes every value (alpha, G, transmittance, images, gradients) in FP64 along them,
+// so a comparison with it measures value error only.
+struct Mixed {
+  Scene<float> sf;
+  Scene<double> sd;  // values; proj[r].vis = visible in both precisions, pass[] taken from FP32
+  std::vector<PixelOut<float>> imf;
+  std::vector<std::vector<Contrib<float>>> tf;
+  std::vector<std::vector<int64_t>> nears;
+  std::vector<PixelOut<double>> img;
+  std::vector<std::vector<Contrib<double>>> traces;
+  std::vector<char> split_vis;  // [V*N] visible in exactly one precision (near its cull threshold)
+};
+
+void build_mixed(Mixed& m, const double* means, const double* log_scales, const double* quats, const double* opac,
+                 const double* sh, int64_t N, int deg, const double* cams, int V, const double* opts) {
+  build_scene<float>(m.sf, means, log_scales, quats, opac, sh, N, deg, cams, V, opts);
+  build_scene<double>(m.sd, means, log_scales, quats, opac, sh, N, deg, cams, V, opts);
+  render_all<float>(m.sf, 1, m.imf, &m.tf, &m.nears);
+  const int64_t R = (int64_t)V * N;
+  m.split_vis.assign(R, 0);
+  for (int64_t r = 0; r < R; ++r) {
+    Proj<double>& pd = m.sd.proj[r];
+    const Proj<float>& pf = m.sf.proj[r];
+    m.split_vis[r] = pd.vis != pf.vis;
+    pd.vis = pd.vis && pf.vis;
+    for (int ch = 0; ch < 3; ++ch) pd.pass[ch] = pf.pass[ch];
+    if (pd.vis)
+      for (int ch = 0; ch < 3; ++ch) m.sd.splats[r].rgb[ch] = pd.pass[ch] ? pd.rgb[ch] : 0.0;
+  }
+  const Scene<double>& sc = m.sd;
+  m.img.resize(sc.total_px);
+  m.traces.assign(sc.total_px, {});
+  const double amax = sc.op.alpha_max;
+  for (int v = 0; v < V; ++v) {
+    const Cam<double>& cam = sc.cams[v];
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int y = 0; y < cam.H; ++y)
+      for (int x = 0; x < cam.W; ++x) {
+        int64_t pix = cam.pixel_offset + (int64_t)y * cam.W + x;
+        PixelOut<double>& o = m.img[pix];
+        o.C[0] = o.C[1] = o.C[2] = o.D = o.Vis = 0;
+        o.n_contrib = 0;
+        o.near = m.imf[pix].near;
+        double T = 1, px = x + 0.5, py = y + 0.5;
+        for (const Contrib<float>& c : m.tf[pix]) {
+          if (!sc.proj[c.rec].vis) { o.near = true; continue; }
+          const Splat<double>& s = sc.splats[c.rec];
+          double dx = s.mx - px, dy = s.my - py;
+          double G = std::exp(-0.5 * (s.a * dx * dx + s.c * dy * dy) - s.b * dx * dy);
+          double alpha = c.clamped ? amax : s.o * G;
+          double w = alpha * T;
+          for (int ch = 0; ch < 3; ++ch) o.C[ch] += w * s.rgb[ch];
+          o.D += w * s.z;
+          o.Vis += w;
+          m.traces[pix].push_back(Contrib<double>{c.rec, alpha, G, T, c.clamped});
+          T *= 1.0 - alpha;
+          o.n_contrib++;
+        }
+        for (int ch = 0; ch < 3; ++ch) o.C[ch] += T * sc.op.bg[ch];
+        o.T = T;
+      }
+  }
+}
+
+// Upstream gradients for the mixed reference: loss signs from the FP32 image, loss value from the FP64 one.
+double mixed_upstream(const Mixed& m, const double* g_rgb, const double* g_depth, const double* g_vis,
+                      const double* tgt_rgb, const double* tgt_depth, std::vector<double>& g,
+                      std::vector<char>& near_sign) {
+  if (!tgt_rgb) return upstream<double>(m.sd, m.img, g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth, g, near_sign);
+  std::vector<double> g64;
+  std::vector<char> ns64;
+  double L = loss_and_grad<double>(m.sd, m.img, tgt_rgb, tgt_depth, g64, ns64);
+  loss_and_grad<float>(m.sf, m.imf, tgt_rgb, tgt_depth, g, near_sign);
+  return L;
+}
+
+double backward_mixed(const double* means, const double* log_scales, const double* quats, const double* opac,
+                      const double* sh, int64_t N, int deg, const double* cams, int V, const double* opts,
+                      const double* g_rgb, const double* g_depth, const double* g_vis, const double* tgt_rgb,
+                      const double* tgt_depth, double* gmean, double* gscale, double* gquat, double* gopac,
+                      double* gsh, int8_t* excused_gauss, int64_t* n_near_pixels, double* rgb, double* depth,
+                      double* vis) {
+  Mixed m;
+  build_mixed(m, means, log_scales, quats, opac, sh, N, deg, cams, V, opts);
+  std::vector<double> g;
+  std::vector<char> near_sign;
+  double L = mixed_upstream(m, g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth, g, near_sign);
+  std::vector<double> grec;
+  composite_backward<double>(m.sd, m.img, m.traces, g, grec);
+  project_backward_all<double>(m.sd, sh, grec, gmean, gscale, gquat, gopac, gsh);
+  // Excusal as in backward_impl, judged on the FP32 evaluation (whose rounding the compared path shares up to
+  // the order of operations), plus Gaussians visible in one precision only.
+  int64_t nn = 0;
+  if (excused_gauss) {
+    std::memset(excused_gauss, 0, (size_t)N);
+    for (int64_t pix = 0; pix < m.sd.total_px; ++pix) {
+      if (!(m.img[pix].near || near_sign[pix])) continue;
+      ++nn;
+      for (const auto& c : m.tf[pix]) excused_gauss[c.rec % N] = 1;
+      for (int64_t r : m.nears[pix]) excused_gauss[r % N] = 1;
+    }
+    for (int64_t r = 0; r < (int64_t)V * N; ++r) {
+      const Proj<float>& p = m.sf.proj[r];
+      if (m.split_vis[r] || p.near_margin <= 1e-5 || (p.vis && p.rgb_margin <= 1e-5)) excused_gauss[r % N] = 1;
+    }
+  }
+  if (n_near_pixels) *n_near_pixels = nn;
+  if (rgb) {
+    for (int v = 0; v < V; ++v) {
+      const Cam<double>& cam = m.sd.cams[v];
+      int64_t P = (int64_t)cam.W * cam.H, off = cam.pixel_offset;
+      for (int64_t i = 0; i < P; ++i) {
+        for (int ch = 0; ch < 3; ++ch) rgb[3 * off + ch * P + i] = m.img[off + i].C[ch];
+        depth[off + i] = m.img[off + i].D;
+        vis[off + i] = m.img[off + i].Vis;
+      }
+    }
+  }
+  return L;
+}
+
 template <class R>
 int forward_impl(const double* means, const double* log_scales, const double* quats, const double* opac,
                  const double* sh, int64_t N, int deg, const double* cams, int V, const double* opts, int mode,
@@ -766,24 +1004,8 @@ double backward_impl(const double* means, const double* log_scales, const double
   std::vector<std::vector<int64_t>> nears;
   render_all<R>(sc, 1, img, &traces, &nears);
   std::vector<double> g;
-  std::vector<char> near_sign(sc.total_px, 0);
-  double L = 0;
-  if (tgt_rgb) {
-    L = loss_and_grad<R>(sc, img, tgt_rgb, tgt_depth, g, near_sign);
-  } else {
-    g.assign((size_t)sc.total_px * 5, 0.0);
-    for (int v = 0; v < V; ++v) {
-      const Cam<R>& cam = sc.cams[v];
-      int64_t P = (int64_t)cam.W * cam.H, off = cam.pixel_offset;
-      for (int64_t i = 0; i < P; ++i) {
-        for (int ch = 0; ch < 3; ++ch) g[(off + i) * 5 + ch] = g_rgb ? g_rgb[3 * off + ch * P + i] : 0.0;
-        g[(off + i) * 5 + 3] = g_depth ? g_depth[off + i] : 0.0;
-        g[(off + i) * 5 + 4] = g_vis ? g_vis[off + i] : 0.0;
-        for (int ch = 0; ch < 3; ++ch) L += g[(off + i) * 5 + ch] * (double)img[off + i].C[ch];
-        L += g[(off + i) * 5 + 3] * (double)img[off + i].D + g[(off + i) * 5 + 4] * (double)img[off + i].Vis;
-      }
-    }
-  }
+  std::vector<char> near_sign;
+  double L = upstream<R>(sc, img, g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth, g, near_sign);
   std::vector<R> grec;
   composite_backward<R>(sc, img, traces, g, grec);
   project_backward_all<R>(sc, sh, grec, gmean, gscale, gquat, gopac, gsh);
@@ -986,6 +1208,9 @@ double oracle_backward(int prec, const double* means, const double* log_scales, 
                        const double* tgt_rgb, const double* tgt_depth, double* gmean, double* gscale, double* gquat,
                        double* gopac, double* gsh, int8_t* excused, int64_t* n_near_pixels, double* rgb,
                        double* depth, double* vis) {
+  if (prec == PREC_MIXED)
+    return backward_mixed(means, log_scales, quats, opac, sh, N, deg, cams, V, opts, g_rgb, g_depth, g_vis, tgt_rgb,
+                          tgt_depth, gmean, gscale, gquat, gopac, gsh, excused, n_near_pixels, rgb, depth, vis);
   if (prec == 32)
     return backward_impl<float>(means, log_scales, quats, opac, sh, N, deg, cams, V, opts, g_rgb, g_depth, g_vis,
                                 tgt_rgb, tgt_depth, gmean, gscale, gquat, gopac, gsh, excused, n_near_pixels, rgb,
@@ -996,6 +1221,29 @@ double oracle_backward(int prec, const double* means, const double* log_scales, 
 }
 
 // Loss value only (FP64), for finite differences.
+// Sum of the magnitudes of the terms of every gradient entry (FP64 along FP32 decisions; zeroed here).
+// Same inputs as oracle_backward; outputs have the shapes of the gradients.
+void oracle_gradient_scale(const double* means, const double* log_scales, const double* quats, const double* opac,
+                           const double* sh, int64_t N, int deg, const double* cams, int V, const double* opts,
+                           const double* g_rgb, const double* g_depth, const double* g_vis, const double* tgt_rgb,
+                           const double* tgt_depth, double* smean, double* sscale, double* squat, double* sopac,
+                           double* ssh) {
+  Mixed m;
+  build_mixed(m, means, log_scales, quats, opac, sh, N, deg, cams, V, opts);
+  std::vector<double> g;
+  std::vector<char> near_sign;
+  mixed_upstream(m, g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth, g, near_sign);
+  std::vector<double> arec;
+  composite_backward_abs(m.sd, m.img, m.traces, g, arec);
+  const int K = m.sd.K;
+  std::memset(smean, 0, sizeof(double) * 3 * N);
+  std::memset(sscale, 0, sizeof(double) * 3 * N);
+  std::memset(squat, 0, sizeof(double) * 4 * N);
+  std::memset(sopac, 0, sizeof(double) * N);
+  std::memset(ssh, 0, sizeof(double) * 3 * K * N);
+  project_backward_abs(m.sd, sh, arec, smean, sscale, squat, sopac, ssh);
+}
+
 double oracle_loss(const double* means, const double* log_scales, const double* quats, const double* opac,
                    const double* sh, int64_t N, int deg, const double* cams, int V, const double* opts,
                    const double* tgt_rgb, const double* tgt_depth) {

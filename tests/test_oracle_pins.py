@@ -287,6 +287,61 @@ def test_stop_rule_fp32_and_fp64_edge():
     np.testing.assert_allclose(f64["vis"][0], gold["fp64"]["vis"], rtol=1e-12)
 
 
+def test_mixed_reference_takes_the_fp32_stop_and_fp64_values():
+    """The stop-rule edge above: FP32 stops after the first clamped Gaussian, FP64 composites both.  The
+    FP64-values-along-FP32-decisions reference keeps the FP32 walk (one contributor) with FP64 values:
+    V = 0.99, D = 0.99 z1, dD/dz1 = 0.99 and no gradient to the second Gaussian."""
+    cam = scenes.identity_camera(100.0, 100.0, 0.5, 0.5, 1, 1)
+    gs = stack([one_gaussian([0.0, 0.0, z], (math.log(0.1),) * 3, logit=12.0, rgb=(1.0, 1.0, 1.0))
+                for z in (2.0, 3.0)])
+    _, g64, _, _, img64 = oracle.backward(64, gs, 0, [cam], g_depth=np.ones(1))
+    _, gmx, exc, nn, imgmx = oracle.backward(64, gs, 0, [cam], g_depth=np.ones(1), decisions=32)
+    np.testing.assert_allclose(img64["vis"][0], 0.9999, rtol=1e-14)
+    assert imgmx["vis"][0] == 0.99 and imgmx["depth"][0] == 0.99 * 2.0
+    np.testing.assert_allclose(g64["means"][1, 2], 0.99 * (1 - 0.99), rtol=1e-12)
+    assert gmx["means"][1, 2] == 0.0 and gmx["means"][0, 2] == 0.99
+    assert nn == 1 and exc.all()  # the stop is within 1e-5 of its threshold: both Gaussians excused
+
+
+@pytest.mark.parametrize("deg,seed", [(1, 31), (3, 32)])
+def test_mixed_reference_equals_fp64_away_from_thresholds(deg, seed):
+    """Where no decision is near its threshold, FP32 and FP64 decide alike and the two references agree."""
+    sc = scenes.random_scene(seed, 400, 40, 32, sh_degree=deg, views=2, log_scale_mu=-2.4)
+    kw = dict(tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
+    L, g, exc, _, _ = oracle.backward(64, sc.params(), deg, sc.cams, **kw)
+    Lm, gm, excm, _, _ = oracle.backward(64, sc.params(), deg, sc.cams, decisions=32, **kw)
+    np.testing.assert_allclose(Lm, L, rtol=1e-12)
+    keep = ~(exc | excm)
+    assert keep.mean() > 0.9
+    for k in g:
+        a, b = g[k].reshape(keep.size, -1)[keep], gm[k].reshape(keep.size, -1)[keep]
+        np.testing.assert_allclose(b, a, rtol=1e-12, atol=1e-15, err_msg=k)
+
+
+def _dense_scene(seed, deg):
+    return scenes.random_scene(seed, 3000, 64, 48, sh_degree=deg, views=2, log_scale_mu=-2.0, opacity_sigma=0.8)
+
+
+@pytest.mark.parametrize("deg,seed", [(0, 33), (3, 34)])
+def test_gradient_scale_bounds_fp32_rounding(deg, seed):
+    """The rounding scale: at least |gradient| everywhere; the FP32 evaluation of the definition (another
+    summation order and FP32 forward values) within 4 x 2^-24 x scale of the FP64 values along the same
+    decisions; and 4 x 2^-24 x scale under a quarter of the 1e-3 relative bar on the median entry, so that the
+    rounding allowance matters only where the terms of a sum cancel."""
+    sc = _dense_scene(seed, deg)
+    kw = dict(tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
+    _, g, exc, _, _ = oracle.backward(64, sc.params(), deg, sc.cams, decisions=32, **kw)
+    _, g32, _, _, _ = oracle.backward(32, sc.params(), deg, sc.cams, **kw)
+    S = oracle.gradient_scale(sc.params(), deg, sc.cams, **kw)
+    u = 2.0 ** -24
+    for k in g:
+        a, b, s = (x.reshape(exc.size, -1)[~exc] for x in (g[k], g32[k], S[k]))
+        assert np.all(s >= np.abs(a)), k
+        assert np.all(np.abs(b - a) <= 4 * u * s), (k, float((np.abs(b - a) / (u * s + 1e-300)).max()))
+        rms = np.sqrt((a ** 2).mean())
+        assert np.median(4 * u * s / (np.abs(a) + rms)) < 2.5e-4, k
+
+
 @pytest.mark.parametrize("deg", [0, 2])
 def test_brute_force_equals_tiled_and_tile_size_invariance(deg):
     sc = scenes.random_scene(9, 300, 70, 45, sh_degree=deg, views=2, log_scale_mu=-2.5)

@@ -42,10 +42,11 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
-// DPP move of a float with control CTRL; lanes without a valid source (or in a masked row) read 0.
+// DPP move of a float with control CTRL; lanes without a valid source (bound_ctrl) or in a masked row read 0.
+// bound_ctrl lets the move fold into the consuming add (v_add_f32_dpp).
 template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ float dpp_f(float x) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, true));
 }
 
 // Sum over the 64 lanes of a wave; the total lands in lane 63.  Six DPP adds:
@@ -63,7 +64,7 @@ __device__ __forceinline__ float wave_sum_last(float x) {
 // Maximum over the 64 lanes of a non-negative int, returned to every lane (same DPP pattern as above).
 template <int CTRL, int ROW_MASK = 0xf>
 __device__ __forceinline__ int dpp_i(int x) {
-  return __builtin_amdgcn_update_dpp(0, x, CTRL, ROW_MASK, 0xf, false);
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, ROW_MASK, 0xf, true);
 }
 
 __device__ __forceinline__ int wave_max_nonneg(int x) {

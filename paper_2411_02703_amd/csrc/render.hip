@@ -100,7 +100,9 @@ __device__ __forceinline__ bool tile_setup(const gs_camera* __restrict__ cams, i
 
 // One record at one pixel: returns false if skipped (power > 0 or alpha < alpha_min).  The operation
 // sequence is fixed (contraction off, explicit fma) so that every kernel and every tile shape computes the
-// same bits for the same (record, pixel) pair.
+// same bits for the same (record, pixel) pair.  Everything is computed whatever the outcome (no branch: in a
+// lock-step walk some lane of the wave nearly always takes every path, and the branches only add exec-mask
+// work); G and alpha are meaningful only where the result is true.
 __device__ __forceinline__ bool eval_pair(const float4& A, const float4& B, float fx, float fy, const DevOpts& op,
                                           float& alpha, float& G, bool& clamped, float& dx, float& dy) {
 #pragma clang fp contract(off)
@@ -110,12 +112,11 @@ __device__ __forceinline__ bool eval_pair(const float4& A, const float4& B, floa
   const float quad = __builtin_fmaf(B.z * dy, dy, adx2);  // a dx^2 + c dy^2
   const float bxy = (B.y * dx) * dy;
   const float power = __builtin_fmaf(-0.5f, quad, -bxy);  // -(a dx^2 + c dy^2)/2 - b dx dy
-  if (power > 0.f) return false;
   G = __expf(power);
   const float oG = A.w * G;
   clamped = oG > op.alpha_max;
   alpha = clamped ? op.alpha_max : oG;
-  return alpha >= op.alpha_min;
+  return !(power > 0.f) && alpha >= op.alpha_min;
 }
 
 __device__ __forceinline__ void unpack_rect(const float4& C, int& x0, int& x1, int& y0, int& y1) {
@@ -226,8 +227,11 @@ __device__ __forceinline__ float block_sum(float x) {
 
 // Walk one staged round: every block walks the set bits of its mask in order, its lanes in lock-step, and
 // stops once all its pixels have ended.
-//   step(j, A, B, C, acc) -> contributed   (per lane; clears live at the stop)
-//   post(j, hit, acc)                      (whole wave, once per step, only if SYNC)
+//   step(j, active, A, B, C, acc) -> contributed   (per lane, branch-free; active = this lane has a record
+//                                                   and a live pixel; clears live at the stop)
+//   post(j, hit, acc)                              (whole wave, once per step, only if SYNC)
+// A lane whose block has run out of records reads slot c * 64 (a valid LDS address, possibly stale) and is
+// inactive.
 template <class G, bool SYNC, class Step, class Post>
 __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, bool& live, Step step, Post post) {
   constexpr uint64_t BMASK = G::BL == 64 ? ~0ull : ((1ull << G::BL) - 1);
@@ -240,19 +244,15 @@ __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, 
     float4 An = s.A[jn], Bn = s.B[jn], Cn = s.C[jn];
     while (SYNC ? __ballot(m != 0) != 0 : m != 0) {
       const int j = jn;
+      const bool active = m != 0 && live;
+      const float4 A = An, B = Bn, C = Cn;
+      m &= m - 1;
+      jn = c * 64 + (m ? __builtin_ctzll(m) : 0);
+      An = s.A[jn];
+      Bn = s.B[jn];
+      Cn = s.C[jn];
       float acc[10];
-#pragma unroll
-      for (int q = 0; q < 10; ++q) acc[q] = 0.f;
-      bool hit = false;
-      if (m) {
-        const float4 A = An, B = Bn, C = Cn;
-        m &= m - 1;
-        jn = c * 64 + (m ? __builtin_ctzll(m) : 0);
-        An = s.A[jn];
-        Bn = s.B[jn];
-        Cn = s.C[jn];
-        if (live) hit = step(j, A, B, C, acc);
-      }
+      const bool hit = step(j, active, A, B, C, acc);
       if (SYNC) post(j, hit, acc);
       if (((__ballot(live) >> t.blk_lane0) & BMASK) == 0) m = 0;
     }
@@ -293,24 +293,23 @@ __device__ __forceinline__ void forward_walk(Stage<G>& s, const float4* __restri
                                              const DevOpts& op, bool live, float& T, float& Cr, float& Cg,
                                              float& Cb, float& D, float& Vs) {
   const float fx = (float)t.px + 0.5f, fy = (float)t.py + 0.5f;
-  auto step = [&](int, const float4& A, const float4& B, const float4& C, float*) -> bool {
+  auto step = [&](int, bool active, const float4& A, const float4& B, const float4& C, float*) -> bool {
 #pragma clang fp contract(off)
     float alpha, Gv, dx, dy;
     bool cl;
-    if (!eval_pair(A, B, fx, fy, op, alpha, Gv, cl, dx, dy)) return false;
+    const bool ok = eval_pair(A, B, fx, fy, op, alpha, Gv, cl, dx, dy) && active;
     const float Tn = T * (1.f - alpha);
-    if (STOP && Tn < op.t_min) {
-      live = false;
-      return false;
-    }
+    const bool stop = STOP && ok && Tn < op.t_min;
+    const bool hit = ok && !stop;
+    if (STOP) live = live && !stop;
     const float w = alpha * T;
-    Cr = __builtin_fmaf(w, B.w, Cr);
-    Cg = __builtin_fmaf(w, C.x, Cg);
-    Cb = __builtin_fmaf(w, C.y, Cb);
-    D = __builtin_fmaf(w, A.z, D);
-    Vs = Vs + w;
-    T = Tn;
-    return true;
+    Cr = hit ? __builtin_fmaf(w, B.w, Cr) : Cr;
+    Cg = hit ? __builtin_fmaf(w, C.x, Cg) : Cg;
+    Cb = hit ? __builtin_fmaf(w, C.y, Cb) : Cb;
+    D = hit ? __builtin_fmaf(w, A.z, D) : D;
+    Vs = hit ? Vs + w : Vs;
+    T = hit ? Tn : T;
+    return hit;
   };
   sweep<G, DEPTH, false>(s, rec, vals, rg, t, op, live, [](bool) {}, step, [](int, bool, const float*) {});
 }
@@ -467,34 +466,33 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
   for (int k = 0; k < DEPTH; ++k)
 #pragma unroll
     for (int q = 0; q < 10; ++q) gacc[q][k * G::NT + threadIdx.x] = 0.f;
-  auto step = [&](int, const float4& A, const float4& B, const float4& C, float* acc) -> bool {
+  auto step = [&](int, bool active, const float4& A, const float4& B, const float4& C, float* acc) -> bool {
     float alpha, Gv, dx, dy;
     bool cl;
-    if (!eval_pair(A, B, fx, fy, op, alpha, Gv, cl, dx, dy)) return false;
+    const bool ok = eval_pair(A, B, fx, fy, op, alpha, Gv, cl, dx, dy) && active;
     const float Tn = T * (1.f - alpha);
-    if (Tn < op.t_min) {
-      live = false;
-      return false;
-    }
+    const bool stop = ok && Tn < op.t_min;
+    const bool hit = ok && !stop;
+    live = live && !stop;
     const float w = alpha * T;
     const float qv = gr * B.w + gg * C.x + gb * C.y + gd * A.z + gv;
-    Pp += w * qv;
-    const float dalpha = T * qv - (S - Pp) * __builtin_amdgcn_rcpf(1.f - alpha);
-    acc[6] = w * gr;
-    acc[7] = w * gg;
-    acc[8] = w * gb;
-    acc[9] = w * gd;
-    if (!cl) {
-      acc[5] = dalpha * Gv;
-      const float dq = dalpha * alpha;
-      acc[2] = -0.5f * dx * dx * dq;
-      acc[3] = -dx * dy * dq;
-      acc[4] = -0.5f * dy * dy * dq;
-      acc[0] = -(B.x * dx + B.y * dy) * dq;
-      acc[1] = -(B.z * dy + B.y * dx) * dq;
-    }
-    T = Tn;
-    return true;
+    const float Pn = Pp + w * qv;
+    const float dalpha = T * qv - (S - Pn) * __builtin_amdgcn_rcpf(1.f - alpha);
+    const bool shape = hit && !cl;  // a clamped alpha passes no gradient to opacity or shape
+    const float dq = dalpha * alpha;
+    acc[0] = shape ? -(B.x * dx + B.y * dy) * dq : 0.f;
+    acc[1] = shape ? -(B.z * dy + B.y * dx) * dq : 0.f;
+    acc[2] = shape ? -0.5f * dx * dx * dq : 0.f;
+    acc[3] = shape ? -dx * dy * dq : 0.f;
+    acc[4] = shape ? -0.5f * dy * dy * dq : 0.f;
+    acc[5] = shape ? dalpha * Gv : 0.f;
+    acc[6] = hit ? w * gr : 0.f;
+    acc[7] = hit ? w * gg : 0.f;
+    acc[8] = hit ? w * gb : 0.f;
+    acc[9] = hit ? w * gd : 0.f;
+    Pp = hit ? Pn : Pp;
+    T = hit ? Tn : T;
+    return hit;
   };
   // sum the partials of one step into the records' LDS accumulators (whole wave; one record per block)
   auto post = [&](int j, bool hit, const float* acc) {

@@ -89,7 +89,7 @@ typedef struct gs_opts {
   float bg[3];            /* background colour, 0 */
   int32_t waves_per_tile; /* 0 or tile_w * tile_h / 64 (fixed by the tile shape) */
   int32_t block_w;        /* each wave's 8x8 sub-tile is walked as blocks of block_w x block_w pixels, each in
-                             lock-step over the staged records whose pixel rectangle meets it: 4 or 8 (0 = 4).
+                             lock-step over the staged records whose pixel rectangle meets it: 2, 4 or 8 (0 = 4).
                              Results are identical (a record is skipped only where its rectangle misses the
                              pixel) */
   int32_t batch_depth;    /* records staged per thread per round: 1 or 2 (0 = 1); results identical */

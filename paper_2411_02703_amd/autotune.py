@@ -23,7 +23,7 @@ from . import binding as B
 # -1 = never split)
 CANDIDATES: List[Tuple[int, int, int, int, int]] = [
     (16, 8, 1, 4, 512), (16, 8, 1, 8, 512), (16, 8, 1, 4, 256), (16, 8, 1, 4, 1024), (16, 8, 2, 4, 512),
-    (16, 16, 1, 4, 512), (8, 8, 1, 4, 512), (32, 8, 1, 4, 512), (16, 16, 1, 8, -1)]
+    (16, 16, 1, 4, 512), (8, 8, 1, 4, 512), (32, 8, 1, 4, 512), (16, 16, 1, 8, -1), (16, 16, 1, 2, 512)]
 
 _CACHE = os.environ.get("GS_AUTOTUNE_CACHE",
                         os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), ".scene_cache",

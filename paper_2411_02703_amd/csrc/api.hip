@@ -57,7 +57,8 @@ int opts_check(const gs_opts* o) {
     return fail(GS_ERR_ARG, "waves_per_tile %d: a %dx%d tile has %d waves", nw, o->tile_w, o->tile_h,
                 o->tile_w * o->tile_h / 64);
   if (o->batch_depth < 0 || o->batch_depth > 2) return fail(GS_ERR_ARG, "batch_depth %d outside [0, 2]", o->batch_depth);
-  if (o->block_w != 0 && o->block_w != 4 && o->block_w != 8) return fail(GS_ERR_ARG, "block_w %d (0, 4 or 8)", o->block_w);
+  if (o->block_w != 0 && o->block_w != 2 && o->block_w != 4 && o->block_w != 8)
+    return fail(GS_ERR_ARG, "block_w %d (0, 2, 4 or 8)", o->block_w);
   if (o->seg_len > 0 && o->seg_len < 64) return fail(GS_ERR_ARG, "seg_len %d below 64", o->seg_len);
   if (!(o->near_z > 0.f) || !(o->guard >= 1.f) || !(o->lowpass >= 0.f) || !(o->alpha_min > 0.f) ||
       !(o->alpha_max > o->alpha_min) || !(o->alpha_max < 1.f) || !(o->t_min > 0.f))

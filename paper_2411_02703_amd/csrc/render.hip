@@ -2,16 +2,16 @@
 // eqs. Cp, Dp, Vp with the alpha of eq. alpha) and its backward.
 //
 // One workgroup per tile.  The tile is split into 8x8 sub-tiles, one wave64 each, one pixel per lane; a
-// sub-tile is walked as BW x BW blocks (BW = 4: four blocks, one per 16-lane DPP row; BW = 8: the whole
-// wave).  The tile's depth-sorted list is staged in rounds of DEPTH records per thread into LDS; the
-// records of the next round are fetched into registers while the current one is composited.  Each staged
-// record carries its exact pixel rectangle (every pixel outside it has alpha < exp(-1/2)/255, so it would be
-// skipped anyway), and sets its bit in the mask of every block its rectangle meets.  Each block then walks
-// the set bits of its mask in list order, in lock-step (one record per step for the block's lanes, read from
-// LDS by broadcast); the result is the same bit for bit for every block size, since a record is skipped only
-// where its rectangle misses the pixel.  Small blocks waste fewer lanes on records that cover part of a
-// sub-tile (coarse pyramid levels hold many sub-pixel Gaussians) and sum gradients over 16 lanes instead of
-// 64.
+// sub-tile is walked as BW x BW blocks (BW = 2: sixteen blocks, one per quad of lanes; BW = 4: four blocks,
+// one per 16-lane DPP row; BW = 8: the whole wave).  The tile's depth-sorted list is staged in rounds of
+// DEPTH records per thread into LDS; the records of the next round are fetched into registers while the
+// current one is composited.  Each staged record carries its exact pixel rectangle (every pixel outside it
+// has alpha < exp(-1/2)/255, so it would be skipped anyway), and sets its bit in the mask of every block its
+// rectangle meets.  Each block then walks the set bits of its mask in list order, in lock-step (one record
+// per step for the block's lanes, read from LDS by broadcast); the result is the same bit for bit for every
+// block size, since a record is skipped only where its rectangle misses the pixel.  Small blocks waste fewer
+// lanes on records that cover part of a sub-tile (coarse pyramid levels hold many sub-pixel Gaussians) and
+// sum gradients over fewer lanes (2 or 4 DPP steps instead of 6).
 //
 // The backward walks the list in the same front-to-back order as the forward.  With the forward's final
 // values C, D, V of a pixel and its upstream gradient g, the gradient of alpha_i is
@@ -43,7 +43,7 @@ struct Geo {
   static constexpr int NB = NW * BPW;          // blocks per tile
   static_assert(TW % 8 == 0 && TH % 8 == 0 && NW >= 1 && NW <= 4, "tile shape");
   static_assert(DEPTH == 1 || DEPTH == 2, "batch depth");
-  static_assert(BW == 4 || BW == 8, "block width");
+  static_assert(BW == 2 || BW == 4 || BW == 8, "block width");
 };
 
 template <class G>
@@ -213,13 +213,14 @@ __device__ __forceinline__ void scatter(Stage<G>& s, const TileCtx& t, int nb) {
   }
 }
 
-// Sum over the lanes of this lane's block (BW = 4: its 16-lane row, total in every lane of the row; BW = 8:
-// the wave, total in lane 63).
+// Sum over the lanes of this lane's block (BW = 2: its quad, BW = 4: its 16-lane row, total in every lane of
+// the block; BW = 8: the wave, total in lane 63).
 template <class G>
 __device__ __forceinline__ float block_sum(float x) {
   if (G::BW == 8) return gsk::wave_sum_last(x);
   x += gsk::dpp_f<0xB1>(x);   // quad_perm [1,0,3,2]
   x += gsk::dpp_f<0x4E>(x);   // quad_perm [2,3,0,1]
+  if (G::BW == 2) return x;
   x += gsk::dpp_f<0x141>(x);  // row_half_mirror
   x += gsk::dpp_f<0x140>(x);  // row_mirror
   return x;
@@ -984,6 +985,7 @@ namespace gs_launch {
 #define GS_TILE_DISPATCH_B(FN, TW, TH, DP, ...)                     \
   do {                                                              \
     if (o.block_w == 8) return FN<TW, TH, DP, 8>(__VA_ARGS__);      \
+    if (o.block_w == 2) return FN<TW, TH, DP, 2>(__VA_ARGS__);      \
     return FN<TW, TH, DP, 4>(__VA_ARGS__);                          \
   } while (0)
 #define GS_TILE_DISPATCH_D(FN, TW, TH, ...)                                       \

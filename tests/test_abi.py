@@ -78,7 +78,7 @@ def test_plan_cameras_offsets_and_guard(lib):
     # waves per tile follow the tile shape (one per 8x8 sub-tile); batch depth is 1 or 2
     for over, ok in [(dict(tile_w=32, tile_h=8, waves_per_tile=4), True), (dict(waves_per_tile=2), False),
                      (dict(tile_w=32, tile_h=16), False), (dict(batch_depth=2), True), (dict(batch_depth=3), False),
-                     (dict(block_w=8), True), (dict(block_w=5), False)]:
+                     (dict(block_w=8), True), (dict(block_w=2), True), (dict(block_w=5), False)]:
         assert (lib.gs_plan_cameras(arr, 3, ctypes.byref(B.default_opts(**over))) == 0) == ok, over
 
 

@@ -237,7 +237,7 @@ def test_forward_is_tile_size_invariant_and_deterministic(gpu_lib):
         assert np.array_equal(base[k], again[k]), k
     # tile shapes, records per thread and block widths of the lock-step walk
     for tile in [(16, 16), (8, 8), (16, 8), (32, 8)]:
-        for depth, bw in [(1, 4), (2, 4), (1, 8), (2, 8)]:
+        for depth, bw in [(1, 4), (2, 4), (1, 8), (2, 8), (1, 2), (2, 2)]:
             log("tile", tile, "depth", depth, "block", bw)
             o = run_gpu(sc, tile=tile, targets=False, bw=bw, depth=depth, seg=-1)
             for k in ("rgb", "depth", "vis"):
@@ -407,7 +407,7 @@ def test_pair_counts_match_oracle(gpu_lib):
 
 
 @pytest.mark.parametrize("tile,depth,bw", [((16, 16), 1, 4), ((16, 16), 2, 8), ((8, 8), 2, 4), ((32, 8), 1, 8),
-                                            ((16, 8), 1, 4)])
+                                            ((16, 8), 1, 4), ((16, 16), 1, 2), ((8, 8), 2, 2)])
 def test_backward_identical_across_walk_options(gpu_lib, tile, depth, bw):
     """Gradients agree (to atomic summation order) whatever the tile shape, batch depth and block width."""
     sc = scenes.random_scene(1500, 2000, 100, 70, sh_degree=1, views=2, log_scale_mu=-2.3, depth_fraction=0.3)
@@ -443,7 +443,8 @@ def test_block_walks_match_on_subpixel_scene_and_oracle(gpu_lib):
     sc = _subpixel_scene(1700, views=2)
     # unsplit lists: the walks must agree bit for bit (split lists are checked in the depth-segment tests)
     shared = run_gpu(sc, tile=(16, 16), bw=8, targets=False, seg=-1)  # whole sub-tiles in lock-step
-    for tile, depth, bw in [((16, 16), 1, 4), ((8, 8), 2, 4), ((32, 8), 1, 8), ((16, 8), 2, 4)]:
+    for tile, depth, bw in [((16, 16), 1, 4), ((8, 8), 2, 4), ((32, 8), 1, 8), ((16, 8), 2, 4), ((16, 16), 1, 2),
+                            ((32, 8), 2, 2)]:
         o = run_gpu(sc, tile=tile, depth=depth, bw=bw, targets=False, seg=-1)
         for k in ("rgb", "depth", "vis"):
             assert np.array_equal(shared[k], o[k]), (tile, depth, bw, k)
@@ -613,7 +614,7 @@ def test_split_batched_step_matches_unsplit(gpu_lib):
 # block width, depth segments), checked where the oracle can follow: whole images of the single-keyframe
 # pyramid and one keyframe of the 24-view batch for the images; every gradient of both workloads (the
 # oracle takes the batch one keyframe at a time).
-FULL_CONFIGS = [((16, 16), 4, 512), ((16, 8), 4, 512), ((16, 16), 8, -1)]
+FULL_CONFIGS = [((16, 16), 4, 512), ((16, 8), 4, 512), ((16, 16), 8, -1), ((16, 16), 2, 512)]
 
 
 def test_full_size_single_keyframe_forward_matches_oracle(gpu_lib):

@@ -189,8 +189,16 @@ __device__ __forceinline__ void clear_masks(Stage<G>& s) {
   for (int i = threadIdx.x; i < G::MC * G::NB; i += G::NT) (&s.bm[0][0])[i] = 0ull;
 }
 
-// Set this thread's staged records in the masks of the blocks their rectangles meet.  Blocks are numbered
+// Set this thread's staged records in the masks of the blocks they can reach.  Blocks are numbered
 // wave-major (the wave's sub-tile, then row-major inside it).
+//
+// A record reaches a pixel only inside its ellipse q(d) = a dx^2 + 2 b dx dy + c dy^2 <= k' with
+// k' = 2 ln(255 o) + 1 (outside it alpha < exp(-1/2)/255 < alpha_min).  For each block row of the record's
+// rectangle, the pixel centres of the row form a strip dy in [Y0, Y1]; the ellipse meets the strip in an
+// x-interval [x_lo, x_hi] (x_hi(dy) = (-b dy + sqrt(a k' - det dy^2)) / a is concave, largest at
+// dy = -b sqrt(k' / (c det)); x_lo mirrors it), and a block of the row is marked iff its pixel centres meet
+// that interval.  The pruned pairs are skipped by the walk in any case (their alpha is below the skip
+// threshold by a factor exp(1/2), far beyond FP32 rounding), so the result does not change.
 template <class G, int DEPTH>
 __device__ __forceinline__ void scatter(Stage<G>& s, const TileCtx& t, int nb) {
   constexpr int GX = 8 * G::SX / G::BW, GY = 8 * G::SY / G::BW;  // blocks across and down the tile
@@ -203,13 +211,39 @@ __device__ __forceinline__ void scatter(Stage<G>& s, const TileCtx& t, int nb) {
     const int gx0 = max(x0 - t.tx0, 0) / G::BW, gx1 = min(x1 - t.tx0, 8 * G::SX - 1) / G::BW;
     const int gy0 = max(y0 - t.ty0, 0) / G::BW, gy1 = min(y1 - t.ty0, 8 * G::SY - 1) / G::BW;
     if (x1 < t.tx0 || y1 < t.ty0 || gx0 >= GX || gy0 >= GY) continue;
+    const float4 A = s.A[j], B = s.B[j];
+    const float ca = B.x, cb = B.y, cc = B.z;
+    const float kp = 2.f * __logf(255.f * A.w) + 1.f;
+    const float det = ca * cc - cb * cb;
+    // a nearly singular conic (det not well above the rounding of a c - b^2) keeps the whole rectangle
+    const bool cull = det > 1e-3f * ca * cc;
+    const float inv_a = 1.f / ca;
+    const float ey = sqrtf(fmaxf(kp * ca / det, 0.f));             // |dy| reach of the ellipse
+    const float dyx = cb * sqrtf(fmaxf(kp / (cc * det), 0.f));     // dy of the leftmost point; -dyx: rightmost
+    const float ox = (float)t.tx0 + 0.5f - A.x;                    // dx of the tile's first pixel centre
     const uint64_t bit = 1ull << (j & 63);
     const int wd = j >> 6;
-    for (int gy = gy0; gy <= gy1; ++gy)
-      for (int gx = gx0; gx <= gx1; ++gx) {
+    for (int gy = gy0; gy <= gy1; ++gy) {
+      int cx0 = gx0, cx1 = gx1;
+      if (cull) {
+        const float sy0 = (float)(t.ty0 + gy * G::BW) + 0.5f - A.y;  // strip of pixel centres, in dy
+        const float lo = fmaxf(sy0, -ey), hi = fminf(sy0 + (float)(G::BW - 1), ey);
+        if (lo > hi) continue;
+        const float dr = fminf(fmaxf(-dyx, lo), hi), dl = fminf(fmaxf(dyx, lo), hi);
+        const float xr = (-cb * dr + sqrtf(fmaxf(ca * kp - det * dr * dr, 0.f))) * inv_a;
+        const float xl = (-cb * dl - sqrtf(fmaxf(ca * kp - det * dl * dl, 0.f))) * inv_a;
+        // columns whose pixel centres [ox + gx BW, ox + gx BW + BW - 1] meet [xl, xr] (clamped before the
+        // conversion so that it stays in range)
+        const float fl = fminf(fmaxf((xl - ox - (float)(G::BW - 1)) * (1.f / G::BW), -1.f), (float)GX);
+        const float fr = fminf(fmaxf((xr - ox) * (1.f / G::BW), -1.f), (float)GX);
+        cx0 = max(gx0, (int)ceilf(fl));
+        cx1 = min(gx1, (int)floorf(fr));
+      }
+      for (int gx = cx0; gx <= cx1; ++gx) {
         const int b = ((gy / G::BS) * G::SX + gx / G::BS) * G::BPW + (gy % G::BS) * G::BS + gx % G::BS;
         atomicOr(&s.bm[wd][b], bit);
       }
+    }
   }
 }
 

@@ -138,12 +138,19 @@ typedef struct gs_frame {
   float* rec;           /* [n_views*n][12]: {mu_x, mu_y, z, o}, {conic a, b, c, red},
                            {green, blue, px0 | px1 << 16, py0 | py1 << 16} (pixel rectangle as int16 pairs) */
   int16_t* rect;        /* [n_views*n][4]: tile rectangle tx0, tx1, ty0, ty1 (valid when visible) */
-  float* rgrad;         /* [n_views*n][12]: dL/d{mu_x, mu_y, a, b, c, o, red, green, blue, z} */
+  float* ipart;         /* [capacity][12]: per tile instance, in emission order (Gaussian, then view, then the
+                           tiles of its rectangle row by row), the compositing backward's partial
+                           dL/d{mu_x, mu_y, a, b, c, o, red, green, blue, z} of its record summed over the
+                           pixels of its tile (or depth segment); 2 words of padding.  Every backward call
+                           writes every instance once (plain stores, no atomics) */
+  int32_t* inst_rec;    /* [capacity]: record of each instance in emission order */
   uint64_t* vis_mask;   /* [n]: bit v set if Gaussian g is visible in view v */
   int32_t* n_inst;      /* [n]: tile instances of Gaussian g over all views */
   int32_t* inst_off;    /* [n]: exclusive scan of n_inst */
   uint64_t* keys[2];    /* [capacity] ping-pong sort buffers */
-  int32_t* vals[2];     /* [capacity] record ids */
+  int32_t* vals[2];     /* [capacity] emission indices while sorting; after gs_bin_tiles vals[sort_passes & 1]
+                           holds the record id of each sorted instance and the other buffer its emission
+                           index */
   int32_t* tile_range;  /* [n_tiles][2]: [begin, end) of each tile's instances in the sorted list */
   int32_t* tile_order;  /* [n_tiles]: tiles by descending list length (the compositing schedule) */
   int32_t* counters;    /* [256]: [0] instance count, [1] flags, [2..2+n_views) valid depth pixels per view,
@@ -203,10 +210,9 @@ int gs_frame_init(gs_frame* frame, void* block, size_t bytes, int64_t n, const g
 
 /* ------------------------------------------------------------------ the five hot-path calls */
 /* Projection of every Gaussian into every view of the frame (Section III-B, eqs. Sigma and muI):
- * writes records, tile rectangles, visibility masks and per-Gaussian instance counts; zeroes the
- * per-record gradients of visible records when zero_grads != 0.  Reads each Gaussian once. */
-int gs_project(const gs_params* params, const gs_frame* frame, const gs_opts* opts, int32_t zero_grads,
-               void* stream);
+ * writes records, tile rectangles, visibility masks and per-Gaussian instance counts.  Reads each
+ * Gaussian once. */
+int gs_project(const gs_params* params, const gs_frame* frame, const gs_opts* opts, void* stream);
 
 /* Tile binning: exclusive scan of instance counts, emission of (global tile << 32 | depth bits, record)
  * pairs, stable LSD radix sort, per-tile ranges.  The order within a tile is ascending depth, ties by
@@ -229,11 +235,12 @@ int gs_render_bwd(const gs_params* params, const gs_frame* frame, const gs_opts*
                   const gs_loss* loss, const gs_params* grads, void* stream);
 
 /* The two halves of gs_render_bwd, for callers that schedule them separately.
- * gs_composite_bwd: compositing backward only (the same eqs.), accumulating dL/d{mean_I, conic, opacity,
- * colour, depth} of every record into frame->rgrad (zeroed by gs_project with zero_grads != 0); in loss
- * mode it also writes frame->loss.
- * gs_project_bwd: projection backward only (eqs. Sigma and muI): frame->rgrad -> grads (+=), one thread
- * per Gaussian summing its views, no atomics on parameters. */
+ * gs_composite_bwd: compositing backward only (the same eqs.): for every tile instance, the partial
+ * dL/d{mean_I, conic, opacity, colour, depth} of its record over its tile's pixels, written to
+ * frame->ipart (every instance, no accumulation across calls); in loss mode it also writes frame->loss.
+ * gs_project_bwd: projection backward only (eqs. Sigma and muI): one thread per Gaussian sums the
+ * partials of its instances view by view (a contiguous run in emission order) and adds the parameter
+ * gradients to grads (+=); no atomics. */
 int gs_composite_bwd(const gs_frame* frame, const gs_opts* opts, const gs_images* fwd, const gs_loss* loss,
                      void* stream);
 int gs_project_bwd(const gs_params* params, const gs_frame* frame, const gs_opts* opts, const gs_params* grads,

@@ -48,7 +48,8 @@ class gs_frame(ctypes.Structure):
                 ("max_view_pixels", c_i64), ("capacity", c_i64), ("key_bits", c_i32), ("sort_passes", c_i32),
                 ("tile_w", c_i32), ("tile_h", c_i32), ("seg_len", c_i32), ("seg_cap", c_i32), ("long_cap", c_i32),
                 ("item_cap", c_i32), ("cams", c_vp), ("block", c_vp), ("bytes", ctypes.c_size_t),
-                ("rec", c_vp), ("rect", c_vp), ("rgrad", c_vp), ("vis_mask", c_vp), ("n_inst", c_vp),
+                ("rec", c_vp), ("rect", c_vp), ("ipart", c_vp), ("inst_rec", c_vp), ("vis_mask", c_vp),
+                ("n_inst", c_vp),
                 ("inst_off", c_vp), ("keys", c_vp * 2), ("vals", c_vp * 2), ("tile_range", c_vp),
                 ("tile_order", c_vp), ("counters", c_vp), ("seg_count", c_vp), ("seg_first", c_vp), ("items", c_vp),
                 ("seg", c_vp), ("split", c_vp), ("loss", c_vp), ("scratch", c_vp), ("scratch_ints", ctypes.c_size_t)]
@@ -96,7 +97,7 @@ def load() -> ctypes.CDLL:
     lib.gs_frame_bytes.restype = ctypes.c_size_t
     lib.gs_frame_init.argtypes = [P(gs_frame), c_vp, ctypes.c_size_t, c_i64, P(gs_camera), c_vp, c_i32, P(gs_opts),
                                   c_i64]
-    lib.gs_project.argtypes = [P(gs_params), P(gs_frame), P(gs_opts), c_i32, c_vp]
+    lib.gs_project.argtypes = [P(gs_params), P(gs_frame), P(gs_opts), c_vp]
     lib.gs_bin_tiles.argtypes = [P(gs_frame), P(gs_opts), c_i32, P(c_i64), c_vp]
     lib.gs_render_fwd.argtypes = [P(gs_frame), P(gs_opts), P(gs_images), c_vp]
     lib.gs_render_bwd.argtypes = [P(gs_params), P(gs_frame), P(gs_opts), P(gs_images), P(gs_loss), P(gs_params),
@@ -220,9 +221,9 @@ class Frame:
 
 
 # --------------------------------------------------------------------------- the C-ABI calls
-def gs_project(params: gs_params, frame: Frame, zero_grads: bool = True, stream=None) -> None:
+def gs_project(params: gs_params, frame: Frame, stream=None) -> None:
     _check(load().gs_project(ctypes.byref(params), ctypes.byref(frame.f), ctypes.byref(frame.opts),
-                             int(zero_grads), _stream(stream)), "gs_project")
+                             _stream(stream)), "gs_project")
 
 
 def gs_bin_tiles(frame: Frame, sync_count: bool = True, stream=None) -> Optional[int]:

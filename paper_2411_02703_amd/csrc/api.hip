@@ -38,7 +38,8 @@ bool tiles_supported(int tw, int th) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t rec, rect, rgrad, mask, ninst, instoff, k0, k1, v0, v1, range, order, counters, loss, scratch, total;
+  size_t rec, rect, ipart, instrec, mask, ninst, instoff, k0, k1, v0, v1, range, order, counters, loss,
+      scratch, total;
   size_t segcount, segfirst, items, seg, split;
   size_t scratch_ints;
   int key_bits, passes;
@@ -102,7 +103,8 @@ Layout make_layout(int64_t n, int V, int n_tiles, int64_t cap, const gs_opts* op
   const size_t R = (size_t)V * (size_t)n;
   L.rec = take(R * 48);
   L.rect = take(R * 8);
-  L.rgrad = take(R * 48);
+  L.ipart = take((size_t)cap * 48);
+  L.instrec = take((size_t)cap * 4);
   L.mask = take((size_t)n * 8);
   L.ninst = take((size_t)n * 4);
   L.instoff = take((size_t)n * 4);
@@ -241,7 +243,8 @@ int gs_frame_init(gs_frame* f, void* block, size_t bytes, int64_t n, const gs_ca
   f->bytes = bytes;
   f->rec = reinterpret_cast<float*>(b + L.rec);
   f->rect = reinterpret_cast<int16_t*>(b + L.rect);
-  f->rgrad = reinterpret_cast<float*>(b + L.rgrad);
+  f->ipart = reinterpret_cast<float*>(b + L.ipart);
+  f->inst_rec = reinterpret_cast<int32_t*>(b + L.instrec);
   f->vis_mask = reinterpret_cast<uint64_t*>(b + L.mask);
   f->n_inst = reinterpret_cast<int32_t*>(b + L.ninst);
   f->inst_off = reinterpret_cast<int32_t*>(b + L.instoff);
@@ -263,14 +266,14 @@ int gs_frame_init(gs_frame* f, void* block, size_t bytes, int64_t n, const gs_ca
   return GS_OK;
 }
 
-int gs_project(const gs_params* p, const gs_frame* f, const gs_opts* o, int32_t zero_grads, void* stream) {
+int gs_project(const gs_params* p, const gs_frame* f, const gs_opts* o, void* stream) {
   int rc;
   if ((rc = params_check(p, "params")) || (rc = frame_check(f)) || (rc = opts_check(o))) return rc;
   if (p->n != f->n) return fail(GS_ERR_ARG, "params n %lld != frame n %lld", (long long)p->n, (long long)f->n);
   if (o->tile_w != f->tile_w || o->tile_h != f->tile_h) return fail(GS_ERR_ARG, "tile size differs from the frame");
   hipStream_t st = static_cast<hipStream_t>(stream);
   GS_HIP(gs_launch::fill_i32(f->counters, 0, 2, st), "gs_project: clear counters");
-  GS_HIP(gs_launch::project(*p, *f, *o, zero_grads, st), "gs_project");
+  GS_HIP(gs_launch::project(*p, *f, *o, st), "gs_project");
   return GS_OK;
 }
 
@@ -294,6 +297,7 @@ int gs_bin_tiles(const gs_frame* f, const gs_opts* o, int32_t sync_count, int64_
   GS_HIP(gs_launch::sort_pairs(f->keys[0], f->vals[0], f->keys[1], f->vals[1], n_sized, count_dev, f->capacity,
                                f->key_bits, f->scratch, st),
          "gs_bin_tiles: sort");
+  GS_HIP(gs_launch::inst_finish(*f, n_sized, count_dev, st), "gs_bin_tiles: sorted ids");
   GS_HIP(gs_launch::ranges(*f, f->keys[f->sort_passes & 1], n_sized, count_dev, st), "gs_bin_tiles: ranges");
   GS_HIP(gs_launch::tile_schedule(*f, st), "gs_bin_tiles: schedule");
   GS_HIP(gs_launch::work_items(*f, st), "gs_bin_tiles: work items");

@@ -82,10 +82,13 @@ __global__ void k_instance_total(const int32_t* __restrict__ n_inst, const int32
   if (total > capacity) atomicOr(counters + 1, GS_FLAG_INSTANCE_OVERFLOW);
 }
 
+// One thread per Gaussian: its instances, view by view and tile row by tile row, at its offset.  The sort
+// value is the emission index; inst_rec keeps the record of each emission index.
 __global__ __launch_bounds__(256) void k_emit(const uint64_t* __restrict__ vis_mask, const int32_t* __restrict__ off,
                                              const short4* __restrict__ rect, const float4* __restrict__ rec,
                                              const gs_camera* __restrict__ cams, int64_t n, int64_t capacity,
-                                             uint64_t* __restrict__ keys, int32_t* __restrict__ vals) {
+                                             uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
+                                             int32_t* __restrict__ inst_rec) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   uint64_t mask = vis_mask[g];
@@ -101,7 +104,8 @@ __global__ __launch_bounds__(256) void k_emit(const uint64_t* __restrict__ vis_m
       for (int tx = rc.x; tx <= rc.y; ++tx) {
         if (o < capacity) {
           keys[o] = ((uint64_t)(uint32_t)(toff + ty * tx_n + tx) << 32) | (uint64_t)zb;
-          vals[o] = (int32_t)r;
+          vals[o] = (int32_t)o;
+          inst_rec[o] = (int32_t)r;
         }
         ++o;
       }
@@ -211,6 +215,20 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
     kout[o] = kk;
     vout[o] = sv[p];
   }
+}
+
+// After the sort: the sorted buffer takes the record of each sorted instance (the compositing reads it) and
+// the other buffer keeps its emission index (the compositing backward stores the instance's partials there,
+// so that each Gaussian's partials form one contiguous run).
+__global__ __launch_bounds__(256) void k_inst_finish(int32_t* __restrict__ vals, int32_t* __restrict__ emi,
+                                                    const int32_t* __restrict__ inst_rec,
+                                                    const int32_t* __restrict__ count_dev, int64_t n_sized,
+                                                    int64_t cap) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= sort_count(count_dev, n_sized, cap)) return;
+  const int32_t i = vals[p];
+  vals[p] = inst_rec[i];
+  emi[p] = i;
 }
 
 __global__ void k_ranges(const uint64_t* __restrict__ keys, const int32_t* __restrict__ count_dev, int64_t n_sized,
@@ -349,7 +367,7 @@ hipError_t instance_total(const gs_frame& f, hipStream_t st) {
 hipError_t emit(const gs_frame& f, int64_t /*n_sized*/, hipStream_t st) {
   k_emit<<<(unsigned)cdiv(f.n, 256), 256, 0, st>>>(f.vis_mask, f.inst_off, reinterpret_cast<const short4*>(f.rect),
                                                    reinterpret_cast<const float4*>(f.rec), f.cams, f.n, f.capacity,
-                                                   f.keys[0], f.vals[0]);
+                                                   f.keys[0], f.vals[0], f.inst_rec);
   return hipGetLastError();
 }
 
@@ -408,6 +426,14 @@ hipError_t work_items(const gs_frame& f, hipStream_t st) {
   if ((e = scan_exclusive(f.seg_count, f.seg_first, f.n_tiles, f.scratch, st)) != hipSuccess) return e;
   k_seg_emit<<<nb, 256, 0, st>>>(f.tile_order, f.n_tiles, f.seg_count, f.seg_first, reinterpret_cast<int4*>(f.items),
                                  f.counters);
+  return hipGetLastError();
+}
+
+hipError_t inst_finish(const gs_frame& f, int64_t n_sized, const int32_t* count_dev, hipStream_t st) {
+  if (n_sized <= 0) return hipSuccess;
+  const int s = f.sort_passes & 1;
+  k_inst_finish<<<(unsigned)cdiv(n_sized, 256), 256, 0, st>>>(f.vals[s], f.vals[s ^ 1], f.inst_rec, count_dev,
+                                                               n_sized, f.capacity);
   return hipGetLastError();
 }
 

@@ -112,7 +112,7 @@ __device__ __forceinline__ float sgnf(float x) { return x > 0.f ? 1.f : (x < 0.f
 
 // ------------------------------------------------------------------ host launchers (one per file)
 namespace gs_launch {
-hipError_t project(const gs_params& p, const gs_frame& f, const gs_opts& o, int zero_grads, hipStream_t s);
+hipError_t project(const gs_params& p, const gs_frame& f, const gs_opts& o, hipStream_t s);
 hipError_t project_bwd(const gs_params& p, const gs_frame& f, const gs_opts& o, const gs_params& g,
                        hipStream_t s);
 size_t scan_scratch_ints(int64_t n);
@@ -124,6 +124,7 @@ hipError_t emit(const gs_frame& f, int64_t n_sized, hipStream_t s);
 size_t sort_scratch_ints(int64_t n);
 hipError_t sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int64_t n_sized,
                       const int32_t* count_dev, int64_t cap, int key_bits, int32_t* scratch, hipStream_t s);
+hipError_t inst_finish(const gs_frame& f, int64_t n_sized, const int32_t* count_dev, hipStream_t s);
 hipError_t ranges(const gs_frame& f, const uint64_t* keys, int64_t n_sized, const int32_t* count_dev, hipStream_t s);
 hipError_t tile_schedule(const gs_frame& f, hipStream_t s);
 hipError_t work_items(const gs_frame& f, hipStream_t s);

@@ -184,8 +184,8 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ means
                                                  const float* __restrict__ quats, const float* __restrict__ opac,
                                                  const float* __restrict__ sh, int64_t n,
                                                  const gs_camera* __restrict__ cams, int V, DevOpts op,
-                                                 int zero_grads, float4* __restrict__ rec, short4* __restrict__ rect,
-                                                 float4* __restrict__ rgrad, uint64_t* __restrict__ vis_mask,
+                                                 float4* __restrict__ rec, short4* __restrict__ rect,
+                                                 uint64_t* __restrict__ vis_mask,
                                                  int32_t* __restrict__ n_inst, int32_t* __restrict__ flags) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -254,12 +254,6 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ means
                                      __int_as_float((px0 & 0xffff) | (px1 << 16)),
                                      __int_as_float((py0 & 0xffff) | (py1 << 16)));
         rect[r] = make_short4((short)tx0, (short)tx1, (short)ty0, (short)ty1);
-        if (zero_grads) {
-          const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-          rgrad[3 * r + 0] = z4;
-          rgrad[3 * r + 1] = z4;
-          rgrad[3 * r + 2] = z4;
-        }
         mask |= 1ull << v;
         cnt += (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
       }
@@ -275,7 +269,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ m
                                                      const float* __restrict__ quats, const float* __restrict__ opac,
                                                      const float* __restrict__ sh, int64_t n,
                                                      const gs_camera* __restrict__ cams, DevOpts op,
-                                                     const float4* __restrict__ rgrad,
+                                                     const float4* __restrict__ ipart,
+                                                     const int32_t* __restrict__ inst_off, const short4* __restrict__ rect,
+                                                     const int32_t* __restrict__ count_dev, int64_t capacity,
                                                      const uint64_t* __restrict__ vis_mask, float* __restrict__ g_means,
                                                      float* __restrict__ g_scales, float* __restrict__ g_quats,
                                                      float* __restrict__ g_opac, float* __restrict__ g_sh) {
@@ -302,12 +298,26 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ m
 #pragma unroll
   for (int i = 0; i < K * 3; ++i) gf[i] = 0.f;
 
+  // this Gaussian's instances, in emission order: view by view, the tiles of each view's rectangle
+  const int64_t n_stored = min((int64_t)count_dev[0], capacity);
+  int64_t i = inst_off[g];
   while (mask) {
     const int v = __builtin_ctzll(mask);
     mask &= mask - 1;
     const gs_camera& c = cams[v];
     const int64_t r = (int64_t)v * n + g;
-    const float4 q0 = rgrad[3 * r + 0], q1 = rgrad[3 * r + 1], q2 = rgrad[3 * r + 2];
+    const short4 rc = rect[r];
+    const int64_t i_end = i + (int64_t)(rc.y - rc.x + 1) * (rc.w - rc.z + 1);
+    // the record's gradient: the sum of its instances' partials over the tiles it covers
+    float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0;
+    for (; i < i_end && i < n_stored; ++i) {
+      const float4* pp = ipart + 3 * i;
+      const float4 a0 = pp[0], a1 = pp[1], a2 = pp[2];
+      q0.x += a0.x; q0.y += a0.y; q0.z += a0.z; q0.w += a0.w;
+      q1.x += a1.x; q1.y += a1.y; q1.z += a1.z; q1.w += a1.w;
+      q2.x += a2.x; q2.y += a2.y;
+    }
+    i = i_end;
     const float dmx = q0.x, dmy = q0.y, da = q0.z, db = q0.w;
     const float dc = q1.x, d_o = q1.y, dr = q1.z, dg = q1.w;
     const float dbl = q2.x, dz = q2.y;
@@ -406,30 +416,29 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ m
 
 namespace gs_launch {
 
-hipError_t project(const gs_params& p, const gs_frame& f, const gs_opts& o, int zero_grads, hipStream_t st) {
+hipError_t project(const gs_params& p, const gs_frame& f, const gs_opts& o, hipStream_t st) {
   const int threads = 256;
   const int blocks = (int)((p.n + threads - 1) / threads);
   const DevOpts op = gsk::dev_opts(o);
   auto* rec = reinterpret_cast<float4*>(f.rec);
   auto* rect = reinterpret_cast<short4*>(f.rect);
-  auto* rg = reinterpret_cast<float4*>(f.rgrad);
   int32_t* flags = f.counters + 1;
   switch (p.sh_degree) {
     case 0:
       k_project<0><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams,
-                                               f.n_views, op, zero_grads, rec, rect, rg, f.vis_mask, f.n_inst, flags);
+                                               f.n_views, op, rec, rect, f.vis_mask, f.n_inst, flags);
       break;
     case 1:
       k_project<1><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams,
-                                               f.n_views, op, zero_grads, rec, rect, rg, f.vis_mask, f.n_inst, flags);
+                                               f.n_views, op, rec, rect, f.vis_mask, f.n_inst, flags);
       break;
     case 2:
       k_project<2><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams,
-                                               f.n_views, op, zero_grads, rec, rect, rg, f.vis_mask, f.n_inst, flags);
+                                               f.n_views, op, rec, rect, f.vis_mask, f.n_inst, flags);
       break;
     default:
       k_project<3><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams,
-                                               f.n_views, op, zero_grads, rec, rect, rg, f.vis_mask, f.n_inst, flags);
+                                               f.n_views, op, rec, rect, f.vis_mask, f.n_inst, flags);
       break;
   }
   return hipGetLastError();
@@ -439,11 +448,12 @@ hipError_t project_bwd(const gs_params& p, const gs_frame& f, const gs_opts& o, 
   const int threads = 256;
   const int blocks = (int)((p.n + threads - 1) / threads);
   const DevOpts op = gsk::dev_opts(o);
-  const auto* rg = reinterpret_cast<const float4*>(f.rgrad);
+  const auto* ip = reinterpret_cast<const float4*>(f.ipart);
+  const auto* rect = reinterpret_cast<const short4*>(f.rect);
 #define GS_PB(D)                                                                                              \
   k_project_bwd<D><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams, op, \
-                                               rg, f.vis_mask, gr.means, gr.log_scales, gr.quats, gr.opacity,    \
-                                               gr.sh)
+                                               ip, f.inst_off, rect, f.counters, f.capacity,                     \
+                                               f.vis_mask, gr.means, gr.log_scales, gr.quats, gr.opacity, gr.sh)
   switch (p.sh_degree) {
     case 0: GS_PB(0); break;
     case 1: GS_PB(1); break;

@@ -294,8 +294,9 @@ __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, 
   }
 }
 
-// All rounds of one tile list: stage (with the next round in flight), hand out, walk.  at_round(not_first)
-// runs in every thread after each round barrier, before the round's LDS is rewritten.
+// All rounds of one tile list: stage (with the next round in flight), hand out, walk.  at_round(b0, go) runs
+// in every thread after each round barrier, before the round's LDS is rewritten: b0 is the first record of
+// the round about to be staged, go whether it will be (false once the list or every pixel has ended).
 template <class G, int DEPTH, bool SYNC, class AtRound, class Step, class Post>
 __device__ __forceinline__ void sweep(Stage<G>& s, const float4* __restrict__ rec, const int32_t* __restrict__ vals,
                                       int2 rg, const TileCtx& t, const DevOpts& op, bool& live, AtRound at_round,
@@ -307,7 +308,7 @@ __device__ __forceinline__ void sweep(Stage<G>& s, const float4* __restrict__ re
   fetch_records<G, DEPTH>(rec, fr, fA, fB, fC);
   for (int b0 = rg.x;; b0 += G::BATCH) {
     const bool go = round_barrier<G>(s, t, live) && b0 < rg.y;
-    at_round(b0 != rg.x);
+    at_round(b0, go);
     if (!go) break;
     const int nb = min(G::BATCH, rg.y - b0);
     clear_masks<G>(s);
@@ -346,7 +347,7 @@ __device__ __forceinline__ void forward_walk(Stage<G>& s, const float4* __restri
     T = hit ? Tn : T;
     return hit;
   };
-  sweep<G, DEPTH, false>(s, rec, vals, rg, t, op, live, [](bool) {}, step, [](int, bool, const float*) {});
+  sweep<G, DEPTH, false>(s, rec, vals, rg, t, op, live, [](int, bool) {}, step, [](int, bool, const float*) {});
 }
 
 // Forward sweep of one whole tile for this lane's pixel (forward kernel and fused backward).
@@ -403,7 +404,8 @@ struct BwdArgs {
   const float* tgt_depth;
   const int32_t* n_valid;  // per view
   float lambda_d;
-  float* rgrad;
+  float* ipart;        // [instance][12], in emission order
+  const int32_t* emi;  // emission index of each sorted instance
   float* loss;
 };
 
@@ -463,13 +465,17 @@ __device__ __forceinline__ void add_loss(const TileCtx& t, const BwdArgs& a, flo
   if (t.lane == 63) gsk::atomic_add_f32(a.loss, ls);
 }
 
-// Add the LDS partial derivatives of this thread's staged records of the last round to their gradients in
-// HBM and clear them.  Zero partials are skipped (adding zero changes nothing).
+// Store the LDS partial derivatives of this thread's staged records of the round that started at list
+// position b0 (nb records) as the partials of those instances (at their emission indices), and clear them.
+// Plain stores: every instance has exactly one writer (its tile or depth segment), so nothing is accumulated
+// in HBM.
 template <class G, int DEPTH>
-__device__ __forceinline__ void flush_grads(Stage<G>& s, float (*gacc)[G::BATCH], float* __restrict__ rgrad) {
+__device__ __forceinline__ void flush_grads(float (*gacc)[G::BATCH], float* __restrict__ ipart,
+                                            const int32_t* __restrict__ emi, int b0, int nb) {
 #pragma unroll
   for (int k = 0; k < DEPTH; ++k) {
     const int j = k * G::NT + (int)threadIdx.x;
+    if (j >= nb) continue;
     float v[10];
     bool any = false;
 #pragma unroll
@@ -477,25 +483,40 @@ __device__ __forceinline__ void flush_grads(Stage<G>& s, float (*gacc)[G::BATCH]
       v[q] = gacc[q][j];
       any |= v[q] != 0.f;
     }
+    float4* dst = reinterpret_cast<float4*>(ipart) + 3 * (int64_t)emi[b0 + j];
+    dst[0] = make_float4(v[0], v[1], v[2], v[3]);
+    dst[1] = make_float4(v[4], v[5], v[6], v[7]);
+    dst[2] = make_float4(v[8], v[9], 0.f, 0.f);
     if (any) {
-      float* dst = rgrad + 12 * (int64_t)s.r[j];
 #pragma unroll
-      for (int q = 0; q < 10; ++q) {
-        if (v[q] != 0.f) gsk::atomic_add_f32(dst + q, v[q]);
-        gacc[q][j] = 0.f;
-      }
+      for (int q = 0; q < 10; ++q) gacc[q][j] = 0.f;
     }
+  }
+}
+
+// Zero partials for the instances [b0, end) that the walk never staged (every pixel ended before them).
+template <class G>
+__device__ __forceinline__ void zero_grads(float* __restrict__ ipart, const int32_t* __restrict__ emi, int b0,
+                                           int end) {
+  const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int p = b0 + (int)threadIdx.x; p < end; p += G::NT) {
+    float4* dst = reinterpret_cast<float4*>(ipart) + 3 * (int64_t)emi[p];
+    dst[0] = z;
+    dst[1] = z;
+    dst[2] = z;
   }
 }
 
 // Backward walk of records [rg.x, rg.y) for this lane's pixel, front to back, from transmittance T and
 // prefix P (the pixel's state at rg.x), with upstream gradient g and S = g . (C, D, V) of the final values.
-// Per-record partial derivatives are summed in LDS and added to rgrad once per round.
+// Per-record partial derivatives are summed in LDS and stored as the instances' partials once per round;
+// instances after the walk's end get zero partials.
 template <class G, int DEPTH>
 __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATCH], const float4* __restrict__ rec,
                                               const int32_t* __restrict__ vals, int2 rg, const TileCtx& t,
                                               const DevOpts& op, bool live, float T, float Pp, float gr, float gg,
-                                              float gb, float gd, float gv, float S, float* __restrict__ rgrad) {
+                                              float gb, float gd, float gv, float S, float* __restrict__ ipart,
+                                              const int32_t* __restrict__ emi) {
   const float fx = (float)t.px + 0.5f, fy = (float)t.py + 0.5f;
 #pragma unroll
   for (int k = 0; k < DEPTH; ++k)
@@ -551,8 +572,12 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
     }
   };
   sweep<G, DEPTH, true>(s, rec, vals, rg, t, op, live,
-                        [&](bool not_first) {
-                          if (not_first) flush_grads<G, DEPTH>(s, gacc, rgrad);
+                        [&](int b0, bool go) {
+                          if (b0 != rg.x) {
+                            const int p0 = b0 - G::BATCH;
+                            flush_grads<G, DEPTH>(gacc, ipart, emi, p0, min(G::BATCH, rg.y - p0));
+                          }
+                          if (!go) zero_grads<G>(ipart, emi, b0, rg.y);
                         },
                         step, post);
 }
@@ -584,7 +609,7 @@ __device__ __forceinline__ void tile_backward(Stage<G>& s, float (*gacc)[G::BATC
   pixel_upstream<LOSS>(t, a, Cf, Gf, Bf, Df, gr, gg, gb, gd, gv, loss_acc);
   const float S = gr * Cf + gg * Gf + gb * Bf + gd * Df + gv * Vf;
   if (LOSS) add_loss<G>(t, a, loss_acc);
-  backward_walk<G, DEPTH>(s, gacc, rec, vals, rg, t, op, t.inside, 1.f, 0.f, gr, gg, gb, gd, gv, S, a.rgrad);
+  backward_walk<G, DEPTH>(s, gacc, rec, vals, rg, t, op, t.inside, 1.f, 0.f, gr, gg, gb, gd, gv, S, a.ipart, a.emi);
 }
 
 template <int TW, int TH, int DEPTH, int BW, bool HAVE_FWD, bool LOSS>
@@ -837,7 +862,8 @@ __global__ __launch_bounds__(TW * TH) void k_seg_bwd(const float4* __restrict__ 
   const float Ts = sp[0], Ps = sp[1 * G::NT];
   backward_walk<G, DEPTH>(s, gacc, rec, vals, segment_range<G>(range[it.x], it.y, g.len), t, op,
                           t.inside && Ts >= op.t_min, Ts, Ps, xp[6 * G::NT], xp[7 * G::NT], xp[8 * G::NT],
-                          xp[9 * G::NT], xp[10 * G::NT], xp[11 * G::NT], a.rgrad);
+                          xp[9 * G::NT], xp[10 * G::NT], xp[11 * G::NT], a.ipart,
+                          a.emi);
 }
 
 // Work counts of the forward: pairs evaluated (pixel inside the record's pixel rectangle, up to the
@@ -1073,7 +1099,8 @@ hipError_t render_bwd(const gs_frame& f, const gs_opts& o, const gs_images* fwd,
   a.tgt_depth = l.tgt_depth;
   a.n_valid = f.counters + 2;
   a.lambda_d = l.lambda_d;
-  a.rgrad = f.rgrad;
+  a.ipart = f.ipart;
+  a.emi = f.vals[(f.sort_passes & 1) ^ 1];
   a.loss = f.loss;
   const bool loss = l.tgt_rgb != nullptr;
   GS_TILE_DISPATCH(launch_bwd, f, op, fwd != nullptr, loss, a, st);

@@ -29,7 +29,7 @@ class Rasterizer:
     def project_and_bin(self, ps: B.gs_params, stream=None) -> int:
         """Project and bin with a synchronised instance count; re-plan the frame on overflow."""
         while True:
-            B.gs_project(ps, self.frame, zero_grads=True, stream=stream)
+            B.gs_project(ps, self.frame, stream=stream)
             n = B.gs_bin_tiles(self.frame, sync_count=True, stream=stream)
             if n <= self.frame.capacity:
                 self.n_instances = n
@@ -57,7 +57,6 @@ class GaussianRasterize(torch.autograd.Function):
         B.gs_render_fwd(rast.frame, rgb, depth, vis)
         ctx.rast = rast
         ctx.frame = rast.frame
-        rast.frame.rgrad_used = False
         ctx.save_for_backward(params["means"], params["log_scales"], params["quats"], params["opacity"],
                               params["sh"], rgb, depth, vis)
         return rgb, depth, vis
@@ -71,9 +70,6 @@ class GaussianRasterize(torch.autograd.Function):
         grads = {k: torch.zeros_like(v) for k, v in params.items()}
         gs = B.params_struct(grads, rast.sh_degree)
         frame = ctx.frame
-        if getattr(frame, "rgrad_used", False):
-            B.gs_project(ps, frame, zero_grads=True)  # same records; clears the per-record gradients
-        frame.rgrad_used = True
         cont = lambda t: None if t is None else t.contiguous()
         B.gs_render_bwd(ps, frame, (rgb, depth, vis), gs, g_rgb=cont(g_rgb), g_depth=cont(g_depth),
                         g_vis=cont(g_vis))

@@ -110,7 +110,7 @@ class PlainStep:
         m.zero_grad()
         for v, fr in enumerate(self.frames):
             while True:
-                B.gs_project(m.ps, fr, zero_grads=True)
+                B.gs_project(m.ps, fr)
                 n = B.gs_bin_tiles(fr, sync_count=True)
                 if n <= fr.capacity:
                     break
@@ -152,7 +152,7 @@ class BatchedStep:
 
     def _measure_capacity(self) -> int:
         probe = B.Frame(self.model.n, self.cams, self.opts, max(1 << 20, 8 * self.model.n), self.device)
-        B.gs_project(self.model.ps, probe, zero_grads=False)
+        B.gs_project(self.model.ps, probe)
         n = B.gs_bin_tiles(probe, sync_count=True)
         del probe
         return int(n * self.headroom) + 4096
@@ -161,7 +161,7 @@ class BatchedStep:
         m = self.model
         for t in m.g.values():
             t.zero_()
-        B.gs_project(m.ps, self.frame, zero_grads=True, stream=stream)
+        B.gs_project(m.ps, self.frame, stream=stream)
         B.gs_bin_tiles(self.frame, sync_count=False, stream=stream)
         B.gs_render_bwd(m.ps, self.frame, None, m.gs, tgt_rgb=self.tgt_rgb, tgt_depth=self.tgt_depth,
                         lambda_d=self.lambda_d, stream=stream)

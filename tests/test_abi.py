@@ -89,11 +89,12 @@ def test_frame_layout_on_host(lib):
     lib.gs_plan_cameras(arr, 2, ctypes.byref(o))
     n, cap = 1000, 5000
     nbytes = lib.gs_frame_bytes(n, arr, 2, ctypes.byref(o), cap)
-    assert nbytes >= 2 * n * (48 + 8 + 48) + 2 * cap * 12
+    assert nbytes >= 2 * n * (48 + 8) + cap * (2 * 12 + 48 + 4)
     f = B.gs_frame()
     base = 1 << 20  # carving is pure host arithmetic: any 256-aligned address works
     assert lib.gs_frame_init(ctypes.byref(f), base, nbytes, n, arr, base, 2, ctypes.byref(o), cap) == 0
-    ptrs = sorted([f.rec, f.rect, f.rgrad, f.vis_mask, f.n_inst, f.inst_off, f.keys[0], f.keys[1], f.vals[0],
+    ptrs = sorted([f.rec, f.rect, f.ipart, f.inst_rec, f.vis_mask, f.n_inst, f.inst_off, f.keys[0],
+                   f.keys[1], f.vals[0],
                    f.vals[1], f.tile_range, f.counters, f.seg_count, f.seg_first, f.items, f.seg, f.split, f.loss,
                    f.scratch])
     assert all(p % 256 == 0 for p in ptrs) and ptrs[0] == base and ptrs[-1] < base + nbytes
@@ -115,7 +116,7 @@ def test_argument_errors_return_before_any_launch(lib):
     o = B.default_opts()
     f = B.gs_frame()
     p = B.gs_params()
-    assert lib.gs_project(ctypes.byref(p), ctypes.byref(f), ctypes.byref(o), 1, None) == -1
+    assert lib.gs_project(ctypes.byref(p), ctypes.byref(f), ctypes.byref(o), None) == -1
     assert lib.gs_bin_tiles(ctypes.byref(f), ctypes.byref(o), 1, None, None) == -1
     assert lib.gs_render_fwd(ctypes.byref(f), ctypes.byref(o), None, None) == -1
     assert lib.gs_adam_step(ctypes.byref(p), ctypes.byref(p), ctypes.byref(p), ctypes.byref(p), None, None) == -1
@@ -123,7 +124,7 @@ def test_argument_errors_return_before_any_launch(lib):
     p.means = p.log_scales = p.quats = p.opacity = p.sh = 4096
     p.n = 10
     p.sh_degree = 4
-    assert lib.gs_project(ctypes.byref(p), ctypes.byref(f), ctypes.byref(o), 1, None) == -1
+    assert lib.gs_project(ctypes.byref(p), ctypes.byref(f), ctypes.byref(o), None) == -1
     assert b"sh_degree" in lib.gs_last_error()
 
 

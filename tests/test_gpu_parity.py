@@ -33,18 +33,18 @@ def log(*a):
     print(*a, flush=True)
 
 
-def run_gpu(sc, tile=(16, 16), g_images=None, targets=True, fused=False, capacity=None, zero=True, bw=0, depth=0,
+def run_gpu(sc, tile=(16, 16), g_images=None, targets=True, fused=False, capacity=None, bw=0, depth=0,
             seg=0):
     """Project, bin, render and (optionally) backpropagate one scene; returns numpy results."""
     torch.cuda.synchronize()
     model = GaussianModel(sc.params(), sc.sh_degree)
     opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], block_w=bw, batch_depth=depth, seg_len=seg)
     fr = B.Frame(model.n, sc.cams, opts, capacity)
-    B.gs_project(model.ps, fr, zero_grads=zero)
+    B.gs_project(model.ps, fr)
     n_inst = B.gs_bin_tiles(fr, sync_count=True)
     if n_inst > fr.capacity:
         fr = B.Frame(model.n, sc.cams, opts, n_inst + 1024)
-        B.gs_project(model.ps, fr, zero_grads=zero)
+        B.gs_project(model.ps, fr)
         n_inst = B.gs_bin_tiles(fr, sync_count=True)
     assert n_inst <= fr.capacity
     rgb, depth, vis = fr.empty_images()

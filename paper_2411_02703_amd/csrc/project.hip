@@ -308,15 +308,25 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ m
     const int64_t r = (int64_t)v * n + g;
     const short4 rc = rect[r];
     const int64_t i_end = i + (int64_t)(rc.y - rc.x + 1) * (rc.w - rc.z + 1);
-    // the record's gradient: the sum of its instances' partials over the tiles it covers
+    // the record's gradient: the sum of its instances' partials over the tiles it covers (a contiguous run,
+    // read four instances at a time so that their loads are in flight together)
     float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0;
-    for (; i < i_end && i < n_stored; ++i) {
-      const float4* pp = ipart + 3 * i;
+    const int64_t i_stop = min(i_end, n_stored);
+    auto add = [&](const float4* pp) {
       const float4 a0 = pp[0], a1 = pp[1], a2 = pp[2];
       q0.x += a0.x; q0.y += a0.y; q0.z += a0.z; q0.w += a0.w;
       q1.x += a1.x; q1.y += a1.y; q1.z += a1.z; q1.w += a1.w;
       q2.x += a2.x; q2.y += a2.y;
+    };
+    for (; i + 4 <= i_stop; i += 4) {
+      const float4* pp = ipart + 3 * i;
+      float4 b[12];
+#pragma unroll
+      for (int k = 0; k < 12; ++k) b[k] = pp[k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) add(b + 3 * k);
     }
+    for (; i < i_stop; ++i) add(ipart + 3 * i);
     i = i_end;
     const float dmx = q0.x, dmy = q0.y, da = q0.z, db = q0.w;
     const float dc = q1.x, d_o = q1.y, dr = q1.z, dg = q1.w;

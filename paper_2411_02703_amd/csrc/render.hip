@@ -562,11 +562,39 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
       }
       return;
     }
+    constexpr uint64_t BMASK = G::BL == 64 ? ~0ull : ((1ull << G::BL) - 1);
+    const bool block_hit = ((hits >> t.blk_lane0) & BMASK) != 0;
+    if (G::BW == 4) {
+      // Reduce-scatter over the 16-lane row: the first two exchange steps halve the values each lane carries
+      // (10 -> 5 -> 3), the mirrors then add plain.  A lane's share is set by c0 = b0^b2, c1 = b1^b2 of its
+      // row index (b_k its bits): the quad exchanges (lane^1, lane^2) flip c0 resp. c1 and the mirrors keep
+      // both, so every addition pairs equal shares.  Lanes 0..3 of the row end with the row sums of values
+      // {0,1,2}, {5,6,7}, {3,4}, {8,9} and add them to the LDS accumulators: 3 LDS atomics instead of 10.
+      const int lr = t.lane & 15;
+      const bool c0 = ((lr ^ (lr >> 2)) & 1) != 0, c1 = (((lr >> 1) ^ (lr >> 2)) & 1) != 0;
+      float w[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) w[k] = (c0 ? acc[5 + k] : acc[k]) + gsk::dpp_f<0xB1>(c0 ? acc[k] : acc[5 + k]);
+      float x[3];
+      x[0] = (c1 ? w[3] : w[0]) + gsk::dpp_f<0x4E>(c1 ? w[0] : w[3]);
+      x[1] = (c1 ? w[4] : w[1]) + gsk::dpp_f<0x4E>(c1 ? w[1] : w[4]);
+      x[2] = (c1 ? 0.f : w[2]) + gsk::dpp_f<0x4E>(c1 ? w[2] : 0.f);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) x[k] += gsk::dpp_f<0x141>(x[k]);  // row_half_mirror
+#pragma unroll
+      for (int k = 0; k < 3; ++k) x[k] += gsk::dpp_f<0x140>(x[k]);  // row_mirror
+      if (lr < 4 && block_hit) {
+        const int base = (c0 ? 5 : 0) + (c1 ? 3 : 0);
+        atomicAdd(&gacc[base][j], x[0]);
+        atomicAdd(&gacc[base + 1][j], x[1]);
+        if (!c1) atomicAdd(&gacc[base + 2][j], x[2]);
+      }
+      return;
+    }
     float sum[10];
 #pragma unroll
     for (int q = 0; q < 10; ++q) sum[q] = block_sum<G>(acc[q]);
-    constexpr uint64_t BMASK = G::BL == 64 ? ~0ull : ((1ull << G::BL) - 1);
-    if ((t.lane % G::BL) == G::BL - 1 && ((hits >> t.blk_lane0) & BMASK) != 0) {
+    if ((t.lane % G::BL) == G::BL - 1 && block_hit) {
 #pragma unroll
       for (int q = 0; q < 10; ++q) atomicAdd(&gacc[q][j], sum[q]);
     }

@@ -753,6 +753,9 @@ __global__ __launch_bounds__(TW * TH) void k_seg_stop(const float4* __restrict__
   const int n = (rg.y - rg.x + g.len - 1) / g.len;
   const float* sp = g.seg + (size_t)it.z * 6 * G::NT + threadIdx.x;
   float Ts = 1.f;
+  // the loads are independent of the product: unrolled so that they are in flight together (a tile may have
+  // a hundred segments)
+#pragma unroll 8
   for (int j = 0; j < it.y; ++j) Ts = Ts * sp[(size_t)j * 6 * G::NT];
   const bool last = t.inside && Ts >= op.t_min &&
                     (it.y == n - 1 || Ts * sp[(size_t)it.y * 6 * G::NT] < op.t_min);
@@ -777,12 +780,15 @@ __device__ __forceinline__ void split_final(const float* sp, const float* xp, in
   constexpr size_t SS = 6 * G::NT;
   ks = 0;
   float Tr = 1.f;
+  // loads are independent of the running products: unrolled so that they are in flight together
+#pragma unroll 8
   for (int k = 0; k < n; ++k) {
     if (Tr >= op.t_min) ks = k;
     Tr = Tr * sp[k * SS];
   }
   Cr = Cg = Cb = D = Vs = 0.f;
   Tr = 1.f;
+#pragma unroll 4
   for (int k = 0; k < ks; ++k) {
     const float* q = sp + k * SS;
     Cr = __builtin_fmaf(Tr, q[1 * G::NT], Cr);
@@ -854,6 +860,7 @@ __global__ __launch_bounds__(TW * TH) void k_seg_combine(const gs_camera* __rest
   const float S = gr * Cf + gg * Gf + gb * Bf + gd * Df + gv * Vf;
   if (LOSS) add_loss<G>(t, a, loss_acc);
   float Tr = 1.f, Pr = 0.f;
+#pragma unroll 4
   for (int k = 0; k < n; ++k) {
     float* q = sp + k * SS;
     const float Tk = q[0];

@@ -628,7 +628,7 @@ void composite_backward(const Scene<R>& sc, const std::vector<PixelOut<R>>& img,
 // colour -> SH coefficients and view direction -> mean ; opacity -> logit.
 template <class R>
 void project_backward_one(const Proj<R>& p, const Cam<R>& cam, const double* sh, int K, int64_t g, const R* gr,
-                          R* gmean, R* gscale, R* gquat, R* gopac, R* gsh) {
+                          R* gmean, R* gscale, R* gquat, R* gopac, R* gsh, bool dir_grad = true) {
   // conic (a,b,c) = inverse of [[A,B],[B,C]]; G_K is the gradient w.r.t. the symmetric matrix K
   R Kc[4] = {p.ca, p.cb, p.cb, p.cc};
   R GK[4] = {gr[2], (R)0.5 * gr[3], (R)0.5 * gr[3], gr[4]};
@@ -692,7 +692,7 @@ void project_backward_one(const Proj<R>& p, const Cam<R>& cam, const double* sh,
   for (int ch = 0; ch < 3; ++ch) grgb[ch] = p.pass[ch] ? gr[6 + ch] : (R)0;
   for (int k = 0; k < K; ++k)
     for (int ch = 0; ch < 3; ++ch) gsh[k * 3 + ch] += grgb[ch] * p.Y[k];
-  if (K > 1) {
+  if (K > 1 && dir_grad) {
     int deg = (int)std::lround(std::sqrt((double)K)) - 1;
     Dual dx, dy, dz;
     dx.v = (double)p.dir[0] / (double)p.dist; dx.d[0] = 1;
@@ -812,31 +812,90 @@ void composite_backward_abs(const Scene<double>& sc, const std::vector<PixelOut<
   }
 }
 
+// Magnitude arithmetic: every operation on the magnitudes of its operands (a - b and a + b both give
+// |a| + |b|).  Run through the projection backward it gives, for record-gradient magnitudes, the first-order
+// rounding scale of each parameter gradient (the sum of the magnitudes of all the terms the chain adds),
+// including the cancellations inside the chain (e.g. the rotation gradient of an isotropic Gaussian, exactly
+// zero, whose FP32 evaluation is rounding noise of that size).
+struct Mag {
+  double v;
+  Mag() : v(0) {}
+  Mag(double x) : v(std::fabs(x)) {}
+  explicit operator double() const { return v; }
+};
+inline Mag mag_raw(double x) { Mag r; r.v = x; return r; }
+inline Mag operator+(Mag a, Mag b) { return mag_raw(a.v + b.v); }
+inline Mag operator-(Mag a, Mag b) { return mag_raw(a.v + b.v); }
+inline Mag operator*(Mag a, Mag b) { return mag_raw(a.v * b.v); }
+inline Mag operator/(Mag a, Mag b) { return mag_raw(a.v / b.v); }
+inline Mag operator-(Mag a) { return a; }
+inline Mag& operator+=(Mag& a, Mag b) { a.v += b.v; return a; }
+inline Mag& operator-=(Mag& a, Mag b) { a.v += b.v; return a; }
+inline Mag& operator*=(Mag& a, Mag b) { a.v *= b.v; return a; }
+
+Proj<Mag> mag_of(const Proj<double>& p) {
+  Proj<Mag> m;
+  m.vis = p.vis; m.cull_reason = p.cull_reason; m.near_margin = p.near_margin; m.z32 = p.z32;
+  m.rect_margin = p.rect_margin; m.rgb_margin = p.rgb_margin;
+  m.px0 = p.px0; m.px1 = p.px1; m.py0 = p.py0; m.py1 = p.py1; m.tx0 = p.tx0; m.tx1 = p.tx1; m.ty0 = p.ty0; m.ty1 = p.ty1;
+  for (int i = 0; i < 3; ++i) { m.t[i] = p.t[i]; m.S[i] = p.S[i]; m.rgb[i] = p.rgb[i]; m.dir[i] = p.dir[i]; m.pass[i] = p.pass[i]; }
+  m.mx = p.mx; m.my = p.my; m.z = p.z;
+  for (int i = 0; i < 4; ++i) m.qn[i] = p.qn[i];
+  m.qnorm = p.qnorm;
+  for (int i = 0; i < 9; ++i) { m.Rq[i] = p.Rq[i]; m.M[i] = p.M[i]; m.Sig3[i] = p.Sig3[i]; }
+  for (int i = 0; i < 6; ++i) { m.J[i] = p.J[i]; m.T2[i] = p.T2[i]; }
+  m.A = p.A; m.B = p.B; m.C = p.C; m.det = p.det; m.ca = p.ca; m.cb = p.cb; m.cc = p.cc; m.o = p.o;
+  m.ext_x = p.ext_x; m.ext_y = p.ext_y; m.dist = p.dist;
+  for (int i = 0; i < 16; ++i) m.Y[i] = p.Y[i];
+  return m;
+}
+
+Cam<Mag> mag_of(const Cam<double>& c) {
+  Cam<Mag> m;
+  for (int i = 0; i < 9; ++i) m.Rm[i] = c.Rm[i];
+  for (int i = 0; i < 3; ++i) { m.T[i] = c.T[i]; m.pos[i] = c.pos[i]; }
+  m.fx = c.fx; m.fy = c.fy; m.cx = c.cx; m.cy = c.cy; m.weight = c.weight;
+  m.W = c.W; m.H = c.H; m.tiles_x = c.tiles_x; m.tiles_y = c.tiles_y; m.tile_offset = c.tile_offset;
+  m.pixel_offset = c.pixel_offset;
+  return m;
+}
+
 void project_backward_abs(const Scene<double>& sc, const double* sh, const std::vector<double>& arec,
                           double* smean, double* sscale, double* squat, double* sopac, double* ssh) {
   const int K = sc.K;
 #pragma omp parallel for schedule(dynamic, 256)
   for (int64_t g = 0; g < sc.N; ++g) {
+    std::vector<Mag> fm((size_t)K * 3);
     std::vector<double> f((size_t)K * 3);
     for (int v = 0; v < sc.V; ++v) {
       int64_t r = (int64_t)v * sc.N + g;
       if (!sc.proj[r].vis) continue;
-      for (int k = 0; k < 10; ++k) {
-        double a = arec[(size_t)r * 10 + k];
-        if (a == 0) continue;
+      const double* a = &arec[(size_t)r * 10];
+      Mag gm[10];
+      bool any = false;
+      for (int k = 0; k < 10; ++k) { gm[k] = a[k]; any |= a[k] != 0; }
+      if (!any) continue;
+      // the whole chain in magnitude arithmetic, except the colour's dependence on the view direction
+      Mag m[3], s[3], q[4], o[1];
+      std::fill(fm.begin(), fm.end(), Mag());
+      project_backward_one<Mag>(mag_of(sc.proj[r]), mag_of(sc.cams[v]), sh, K, g, gm, m, s, q, o, fm.data(), false);
+      for (int i = 0; i < 3; ++i) { smean[g * 3 + i] += m[i].v; sscale[g * 3 + i] += s[i].v; }
+      for (int i = 0; i < 4; ++i) squat[g * 4 + i] += q[i].v;
+      sopac[g] += o[0].v;
+      for (int i = 0; i < K * 3; ++i) ssh[g * K * 3 + i] += fm[i].v;
+      for (int k = 6; k <= 8; ++k) {
+        if (a[k] == 0) continue;
+        // the direction term (signed directions needed): each colour's unit gradient through the FP64 chain,
+        // taken entry by entry in absolute value
         double e[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
         e[k] = 1;
-        double m[3] = {0, 0, 0}, s[3] = {0, 0, 0}, q[4] = {0, 0, 0, 0}, o[1] = {0};
+        double dm[3] = {0, 0, 0}, ds[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dop[1] = {0};
         std::fill(f.begin(), f.end(), 0.0);
-        project_backward_one<double>(sc.proj[r], sc.cams[v], sh, K, g, e, m, s, q, o, f.data());
-        for (int i = 0; i < 3; ++i) { smean[g * 3 + i] += a * std::fabs(m[i]); sscale[g * 3 + i] += a * std::fabs(s[i]); }
-        for (int i = 0; i < 4; ++i) squat[g * 4 + i] += a * std::fabs(q[i]);
-        sopac[g] += a * std::fabs(o[0]);
-        for (int i = 0; i < K * 3; ++i) ssh[g * K * 3 + i] += a * std::fabs(f[i]);
+        project_backward_one<double>(sc.proj[r], sc.cams[v], sh, K, g, e, dm, ds, dq, dop, f.data());
+        for (int i = 0; i < 3; ++i) smean[g * 3 + i] += a[k] * std::fabs(dm[i]);
         // the basis values themselves cancel (e.g. x^2 - y^2); on the unit sphere the magnitudes of the terms
         // of each real basis function of degree <= 3 sum to less than 3, so 4 bounds their rounding scale
-        if (k >= 6 && k <= 8)
-          for (int j = 0; j < K; ++j) ssh[(g * K + j) * 3 + (k - 6)] += a * kShTermBound;
+        for (int j = 0; j < K; ++j) ssh[(g * K + j) * 3 + (k - 6)] += a[k] * kShTermBound;
       }
     }
   }

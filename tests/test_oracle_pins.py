@@ -325,9 +325,9 @@ def _dense_scene(seed, deg):
 @pytest.mark.parametrize("deg,seed", [(0, 33), (3, 34)])
 def test_gradient_scale_bounds_fp32_rounding(deg, seed):
     """The rounding scale: at least |gradient| everywhere; the FP32 evaluation of the definition (another
-    summation order and FP32 forward values) within 4 x 2^-24 x scale of the FP64 values along the same
-    decisions; and 4 x 2^-24 x scale under a quarter of the 1e-3 relative bar on the median entry, so that the
-    rounding allowance matters only where the terms of a sum cancel."""
+    summation order and FP32 forward values) within 2 x 2^-24 x scale of the FP64 values along the same
+    decisions; and 2 x 2^-24 x scale below the 1e-3 relative bar on the median entry of every group (the
+    bound is first order and worst case: for rotations it is some ten times the observed error)."""
     sc = _dense_scene(seed, deg)
     kw = dict(tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
     _, g, exc, _, _ = oracle.backward(64, sc.params(), deg, sc.cams, decisions=32, **kw)
@@ -337,9 +337,9 @@ def test_gradient_scale_bounds_fp32_rounding(deg, seed):
     for k in g:
         a, b, s = (x.reshape(exc.size, -1)[~exc] for x in (g[k], g32[k], S[k]))
         assert np.all(s >= np.abs(a)), k
-        assert np.all(np.abs(b - a) <= 4 * u * s), (k, float((np.abs(b - a) / (u * s + 1e-300)).max()))
+        assert np.all(np.abs(b - a) <= 2 * u * s), (k, float((np.abs(b - a) / (u * s + 1e-300)).max()))
         rms = np.sqrt((a ** 2).mean())
-        assert np.median(4 * u * s / (np.abs(a) + rms)) < 2.5e-4, k
+        assert np.median(2 * u * s / (np.abs(a) + rms)) < 1e-3, k
 
 
 @pytest.mark.parametrize("deg", [0, 2])

@@ -82,33 +82,72 @@ __global__ void k_instance_total(const int32_t* __restrict__ n_inst, const int32
   if (total > capacity) atomicOr(counters + 1, GS_FLAG_INSTANCE_OVERFLOW);
 }
 
+// Records with more tiles than this are emitted (and their partials summed) by a whole wave, a tile per lane.
+constexpr int kSolo = 32;
+
+__device__ __forceinline__ int64_t read_lane64(int64_t x, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // One thread per Gaussian: its instances, view by view and tile row by tile row, at its offset.  The sort
-// value is the emission index; inst_rec keeps the record of each emission index.
+// value is the emission index; inst_rec keeps the record of each emission index.  The lanes of a wave take
+// the views together: a record with at most kSolo tiles is written by its own lane, larger ones by the whole
+// wave one after another (a tile per lane, coalesced), so that the few Gaussians covering thousands of tiles
+// do not hold their waves for thousands of steps.
 __global__ __launch_bounds__(256) void k_emit(const uint64_t* __restrict__ vis_mask, const int32_t* __restrict__ off,
                                              const short4* __restrict__ rect, const float4* __restrict__ rec,
-                                             const gs_camera* __restrict__ cams, int64_t n, int64_t capacity,
+                                             const gs_camera* __restrict__ cams, int V, int64_t n, int64_t capacity,
                                              uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
                                              int32_t* __restrict__ inst_rec) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  uint64_t mask = vis_mask[g];
-  int64_t o = off[g];
-  while (mask) {
-    const int v = __builtin_ctzll(mask);
-    mask &= mask - 1;
-    const int64_t r = (int64_t)v * n + g;
-    const short4 rc = rect[r];
-    const uint32_t zb = __float_as_uint(rec[3 * r].z);
+  const int lane = threadIdx.x & 63;
+  const uint64_t mask = g < n ? vis_mask[g] : 0ull;
+  int64_t o = g < n ? off[g] : 0;
+  for (int v = 0; v < V; ++v) {
+    const bool vis = (mask >> v) & 1ull;
+    if (__ballot(vis) == 0) continue;
     const int toff = cams[v].tile_offset, tx_n = cams[v].tiles_x;
-    for (int ty = rc.z; ty <= rc.w; ++ty)
-      for (int tx = rc.x; tx <= rc.y; ++tx) {
-        if (o < capacity) {
-          keys[o] = ((uint64_t)(uint32_t)(toff + ty * tx_n + tx) << 32) | (uint64_t)zb;
-          vals[o] = (int32_t)o;
-          inst_rec[o] = (int32_t)r;
+    const int64_t r = (int64_t)v * n + g;
+    short4 rc = make_short4(0, -1, 0, -1);
+    uint32_t zb = 0;
+    if (vis) {
+      rc = rect[r];
+      zb = __float_as_uint(rec[3 * r].z);
+    }
+    const int w = rc.y - rc.x + 1, cnt = vis ? w * (rc.w - rc.z + 1) : 0;
+    if (vis && cnt <= kSolo) {
+      int64_t q = o;
+      for (int ty = rc.z; ty <= rc.w; ++ty)
+        for (int tx = rc.x; tx <= rc.y; ++tx) {
+          if (q < capacity) {
+            keys[q] = ((uint64_t)(uint32_t)(toff + ty * tx_n + tx) << 32) | (uint64_t)zb;
+            vals[q] = (int32_t)q;
+            inst_rec[q] = (int32_t)r;
+          }
+          ++q;
         }
-        ++o;
+    }
+    uint64_t big = __ballot(cnt > kSolo);
+    while (big) {
+      const int L = __builtin_ctzll(big);
+      big &= big - 1;
+      const int64_t oL = read_lane64(o, L), rL = read_lane64(r, L);
+      const int cL = __builtin_amdgcn_readlane(cnt, L), wL = __builtin_amdgcn_readlane(w, L);
+      const int x0 = __builtin_amdgcn_readlane((int)rc.x, L), y0 = __builtin_amdgcn_readlane((int)rc.z, L);
+      const uint32_t zL = (uint32_t)__builtin_amdgcn_readlane((int)zb, L);
+      for (int k = lane; k < cL; k += 64) {
+        const int64_t q = oL + k;
+        if (q < capacity) {
+          const int ty = y0 + k / wL, tx = x0 + k % wL;
+          keys[q] = ((uint64_t)(uint32_t)(toff + ty * tx_n + tx) << 32) | (uint64_t)zL;
+          vals[q] = (int32_t)q;
+          inst_rec[q] = (int32_t)rL;
+        }
       }
+    }
+    o += cnt;
   }
 }
 
@@ -366,8 +405,8 @@ hipError_t instance_total(const gs_frame& f, hipStream_t st) {
 
 hipError_t emit(const gs_frame& f, int64_t /*n_sized*/, hipStream_t st) {
   k_emit<<<(unsigned)cdiv(f.n, 256), 256, 0, st>>>(f.vis_mask, f.inst_off, reinterpret_cast<const short4*>(f.rect),
-                                                   reinterpret_cast<const float4*>(f.rec), f.cams, f.n, f.capacity,
-                                                   f.keys[0], f.vals[0], f.inst_rec);
+                                                   reinterpret_cast<const float4*>(f.rec), f.cams, f.n_views, f.n,
+                                                   f.capacity, f.keys[0], f.vals[0], f.inst_rec);
   return hipGetLastError();
 }
 

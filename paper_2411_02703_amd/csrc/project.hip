@@ -263,12 +263,15 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ means
   n_inst[g] = cnt;
 }
 
+// Records with more tiles than this have their instance partials summed by the whole wave.
+constexpr int kSolo = 32;
+
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ means,
                                                      const float* __restrict__ log_scales,
                                                      const float* __restrict__ quats, const float* __restrict__ opac,
                                                      const float* __restrict__ sh, int64_t n,
-                                                     const gs_camera* __restrict__ cams, DevOpts op,
+                                                     const gs_camera* __restrict__ cams, int V, DevOpts op,
                                                      const float4* __restrict__ ipart,
                                                      const int32_t* __restrict__ inst_off, const short4* __restrict__ rect,
                                                      const int32_t* __restrict__ count_dev, int64_t capacity,
@@ -277,19 +280,20 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ m
                                                      float* __restrict__ g_opac, float* __restrict__ g_sh) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  uint64_t mask = vis_mask[g];
-  if (mask == 0) return;
+  const int lane = threadIdx.x & 63;
+  // every lane stays to the end of the view loop (the wave sums large records together)
+  const uint64_t mask = g < n ? vis_mask[g] : 0ull;
+  const int64_t gg = mask ? g : 0;  // lanes without a visible record read Gaussian 0 and discard it
   float mu[3], ls[3], qq[4], f[K * 3];
   for (int i = 0; i < 3; ++i) {
-    mu[i] = means[g * 3 + i];
-    ls[i] = log_scales[g * 3 + i];
+    mu[i] = means[gg * 3 + i];
+    ls[i] = log_scales[gg * 3 + i];
   }
-  for (int i = 0; i < 4; ++i) qq[i] = quats[g * 4 + i];
+  for (int i = 0; i < 4; ++i) qq[i] = quats[gg * 4 + i];
 #pragma unroll
-  for (int i = 0; i < K * 3; ++i) f[i] = sh[g * (K * 3) + i];
+  for (int i = 0; i < K * 3; ++i) f[i] = sh[gg * (K * 3) + i];
   Shape s;
-  shape_of(ls, qq, opac[g], s);
+  shape_of(ls, qq, opac[gg], s);
 
   float gmu[3] = {0.f, 0.f, 0.f};
   float gs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // symmetric dL/dSigma: 00 01 02 11 12 22
@@ -298,36 +302,70 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ m
 #pragma unroll
   for (int i = 0; i < K * 3; ++i) gf[i] = 0.f;
 
-  // this Gaussian's instances, in emission order: view by view, the tiles of each view's rectangle
+  // this Gaussian's instances, in emission order: view by view, the tiles of each view's rectangle.  The
+  // lanes take the views together; a record with more than kSolo tiles is summed by the whole wave.
   const int64_t n_stored = min((int64_t)count_dev[0], capacity);
-  int64_t i = inst_off[g];
-  while (mask) {
-    const int v = __builtin_ctzll(mask);
-    mask &= mask - 1;
+  int64_t i = mask ? inst_off[g] : 0;
+  for (int v = 0; v < V; ++v) {
+    const bool vis = (mask >> v) & 1ull;
+    if (__ballot(vis) == 0) continue;
     const gs_camera& c = cams[v];
     const int64_t r = (int64_t)v * n + g;
-    const short4 rc = rect[r];
-    const int64_t i_end = i + (int64_t)(rc.y - rc.x + 1) * (rc.w - rc.z + 1);
+    int cnt = 0;
+    if (vis) {
+      const short4 rc = rect[r];
+      cnt = (rc.y - rc.x + 1) * (rc.w - rc.z + 1);
+    }
     // the record's gradient: the sum of its instances' partials over the tiles it covers (a contiguous run,
     // read four instances at a time so that their loads are in flight together)
     float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0;
-    const int64_t i_stop = min(i_end, n_stored);
     auto add = [&](const float4* pp) {
       const float4 a0 = pp[0], a1 = pp[1], a2 = pp[2];
       q0.x += a0.x; q0.y += a0.y; q0.z += a0.z; q0.w += a0.w;
       q1.x += a1.x; q1.y += a1.y; q1.z += a1.z; q1.w += a1.w;
       q2.x += a2.x; q2.y += a2.y;
     };
-    for (; i + 4 <= i_stop; i += 4) {
-      const float4* pp = ipart + 3 * i;
-      float4 b[12];
+    if (vis && cnt <= kSolo) {
+      int64_t j = i;
+      const int64_t j_stop = min(i + cnt, n_stored);
+      for (; j + 4 <= j_stop; j += 4) {
+        const float4* pp = ipart + 3 * j;
+        float4 b[12];
 #pragma unroll
-      for (int k = 0; k < 12; ++k) b[k] = pp[k];
+        for (int k = 0; k < 12; ++k) b[k] = pp[k];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) add(b + 3 * k);
+        for (int k = 0; k < 4; ++k) add(b + 3 * k);
+      }
+      for (; j < j_stop; ++j) add(ipart + 3 * j);
     }
-    for (; i < i_stop; ++i) add(ipart + 3 * i);
-    i = i_end;
+    uint64_t big = __ballot(cnt > kSolo);
+    while (big) {
+      const int L = __builtin_ctzll(big);
+      big &= big - 1;
+      const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)i, L);
+      const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)i >> 32), L);
+      const int64_t iL = (int64_t)(((uint64_t)hi << 32) | lo);
+      const int cL = __builtin_amdgcn_readlane(cnt, L);
+      float sm[10];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) sm[k] = 0.f;
+      for (int k = lane; k < cL && iL + k < n_stored; k += 64) {
+        const float4* pp = ipart + 3 * (iL + k);
+        const float4 a0 = pp[0], a1 = pp[1], a2 = pp[2];
+        sm[0] += a0.x; sm[1] += a0.y; sm[2] += a0.z; sm[3] += a0.w;
+        sm[4] += a1.x; sm[5] += a1.y; sm[6] += a1.z; sm[7] += a1.w;
+        sm[8] += a2.x; sm[9] += a2.y;
+      }
+#pragma unroll
+      for (int k = 0; k < 10; ++k) sm[k] = gsk::read_lane(gsk::wave_sum_last(sm[k]), 63);
+      if (lane == L) {
+        q0 = make_float4(sm[0], sm[1], sm[2], sm[3]);
+        q1 = make_float4(sm[4], sm[5], sm[6], sm[7]);
+        q2 = make_float4(sm[8], sm[9], 0.f, 0.f);
+      }
+    }
+    i += cnt;
+    if (!vis) continue;
     const float dmx = q0.x, dmy = q0.y, da = q0.z, db = q0.w;
     const float dc = q1.x, d_o = q1.y, dr = q1.z, dg = q1.w;
     const float dbl = q2.x, dz = q2.y;
@@ -389,6 +427,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ m
       gmu[2] += (gz - z * dot) * idist;
     }
   }
+  if (mask == 0) return;
   // Sigma = M M^T: dL/dM = 2 Gs M ; M = Rq diag(S)
   const float Gs[9] = {gs[0], gs[1], gs[2], gs[1], gs[3], gs[4], gs[2], gs[4], gs[5]};
   float GM[9];
@@ -461,7 +500,8 @@ hipError_t project_bwd(const gs_params& p, const gs_frame& f, const gs_opts& o, 
   const auto* ip = reinterpret_cast<const float4*>(f.ipart);
   const auto* rect = reinterpret_cast<const short4*>(f.rect);
 #define GS_PB(D)                                                                                              \
-  k_project_bwd<D><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams, op, \
+  k_project_bwd<D><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams,   \
+                                               f.n_views, op,                                                      \
                                                ip, f.inst_off, rect, f.counters, f.capacity,                     \
                                                f.vis_mask, gr.means, gr.log_scales, gr.quats, gr.opacity, gr.sh)
   switch (p.sh_degree) {

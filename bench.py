@@ -99,15 +99,16 @@ def measured_traffic(tile):
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
-    fields = dict(re.findall(r"^(\w+): (\S+)$", text, re.M))
+    fields = dict(re.findall(r"^([\w\[\],-]+): (\S+)$", text, re.M))
     h = hashlib.sha256()
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2411_02703_amd", "csrc")
     for f in ("render.hip", "common.h"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
-    if fields.get("source_sha256") != h.hexdigest() or fields.get("config") != ",".join(str(x) for x in tile):
+    key = "traffic_bytes_per_launch[" + ",".join(str(x) for x in tile) + "]"
+    if fields.get("source_sha256") != h.hexdigest() or key not in fields:
         return None
-    return int(fields["traffic_bytes_per_launch"])
+    return int(fields[key])
 
 
 def kernel_label(tile):

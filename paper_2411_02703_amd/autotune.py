@@ -20,10 +20,12 @@ import torch
 from . import binding as B
 
 # (tile_w, tile_h, records staged per thread, block width of the lock-step walk, depth-segment length;
-# -1 = never split)
+# -1 = never split).  The first is the default: another candidate is chosen only if it is faster by more than
+# TIE (measurement noise would otherwise flip between near-equal ones from run to run).
 CANDIDATES: List[Tuple[int, int, int, int, int]] = [
-    (16, 8, 1, 4, 512), (16, 8, 1, 8, 512), (16, 8, 1, 4, 256), (16, 8, 1, 4, 1024), (16, 8, 2, 4, 512),
-    (16, 16, 1, 4, 512), (8, 8, 1, 4, 512), (32, 8, 1, 4, 512), (16, 16, 1, 8, -1), (16, 16, 1, 2, 512)]
+    (16, 16, 1, 4, 512), (16, 16, 1, 4, 1024), (16, 8, 1, 4, 512), (16, 8, 1, 4, 1024), (16, 8, 1, 8, 512),
+    (16, 8, 2, 4, 512), (8, 8, 1, 4, 512), (32, 8, 1, 4, 512), (16, 16, 1, 8, -1), (16, 16, 1, 2, 512)]
+TIE = 0.02
 
 _CACHE = os.environ.get("GS_AUTOTUNE_CACHE",
                         os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), ".scene_cache",
@@ -84,7 +86,8 @@ def tune_batched(make_step, n: int, cams: Sequence, sh_degree: int, replays: int
             log(f"  autotune {tw}x{th} depth {dp} block {bw} seg_len {sg}: {ms:.3f} ms")
         del step
         torch.cuda.empty_cache()
-    best = min(times, key=times.get)
+    fastest = min(times.values())
+    best = next(c for c in times if times[c] <= fastest * (1.0 + TIE))
     if use_cache:
         cache[key] = [list(best), {f"{a}x{b}/d{c}/b{d}/L{e}": v for (a, b, c, d, e), v in times.items()}]
         _store(cache)

@@ -522,6 +522,20 @@ def _split_counts(out):
     return int(c[192]), int(c[193]), int(c[194])
 
 
+def _check_segment_plan(out, seg):
+    """The work items of the compositing calls: each tile (in schedule order) is cut into segments of seg
+    records; returns the largest segment count."""
+    fr = out["frame"]
+    nt = fr.f.n_tiles
+    rng_ = B.frame_tensor(fr, "tile_range", 2 * nt, torch.int32).view(-1, 2).cpu().numpy()
+    order = B.frame_tensor(fr, "tile_order", nt, torch.int32).cpu().numpy()
+    counts = B.frame_tensor(fr, "seg_count", nt, torch.int32).cpu().numpy()
+    lens = (rng_[:, 1] - rng_[:, 0])[order]
+    expect = np.where(lens > seg, -(-lens // seg), 1)
+    assert np.array_equal(counts, expect)
+    return int(expect.max())
+
+
 @pytest.mark.parametrize("tile,seg", [((16, 16), 64), ((16, 16), 256), ((8, 8), 96), ((16, 8), 128)])
 def test_split_fused_backward_matches_fp64_oracle_and_unsplit(gpu_lib, tile, seg):
     """Tile lists split into depth segments: loss and gradients agree with the FP64 oracle (1e-3) and with the
@@ -529,7 +543,8 @@ def test_split_fused_backward_matches_fp64_oracle_and_unsplit(gpu_lib, tile, seg
     sc = _subpixel_scene(1900, n=12000, views=2, deg=1)
     out = run_gpu(sc, targets=True, fused=True, tile=tile, seg=seg)
     items, slots, longs = _split_counts(out)
-    log("split", tile, seg, "items", items, "slots", slots, "split tiles", longs)
+    most = _check_segment_plan(out, seg)
+    log("split", tile, seg, "items", items, "slots", slots, "split tiles", longs, "most segments", most)
     assert longs > 0 and slots > longs
     L, ref, exc, nn, scale = grad_reference(sc.params(), 1, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
     np.testing.assert_allclose(out["loss"], L, rtol=1e-5)

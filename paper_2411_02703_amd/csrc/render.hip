@@ -192,15 +192,16 @@ __device__ __forceinline__ void clear_masks(Stage<G>& s) {
 // Set this thread's staged records in the masks of the blocks they can reach.  Blocks are numbered
 // wave-major (the wave's sub-tile, then row-major inside it).
 //
-// A record reaches a pixel only inside its ellipse q(d) = a dx^2 + 2 b dx dy + c dy^2 <= k' with
-// k' = 2 ln(255 o) + 1 (outside it alpha < exp(-1/2)/255 < alpha_min).  For each block row of the record's
-// rectangle, the pixel centres of the row form a strip dy in [Y0, Y1]; the ellipse meets the strip in an
-// x-interval [x_lo, x_hi] (x_hi(dy) = (-b dy + sqrt(a k' - det dy^2)) / a is concave, largest at
-// dy = -b sqrt(k' / (c det)); x_lo mirrors it), and a block of the row is marked iff its pixel centres meet
-// that interval.  The pruned pairs are skipped by the walk in any case (their alpha is below the skip
-// threshold by a factor exp(1/2), far beyond FP32 rounding), so the result does not change.
+// A record passes the skip test at a pixel only where alpha = o G >= alpha_min, i.e. inside its ellipse
+// q(d) = a dx^2 + 2 b dx dy + c dy^2 <= k = 2 ln(o / alpha_min).  For each pixel row of the record's rectangle
+// the ellipse meets the row's line of pixel centres in an x-interval
+//   [(-b dy - sqrt(a k - det dy^2)) / a, (-b dy + sqrt(a k - det dy^2)) / a],   det = a c - b^2,
+// and a block is marked iff one of its rows holds a pixel centre in that interval (the union over the block's
+// rows is taken as one interval, a superset).  k is widened by 1% + 0.01: with det > 1e-3 a c (else the whole
+// rectangle is kept) the FP32 power of the walk is within 0.1% of q, so no pair the walk would accept is
+// pruned and the result does not change.
 template <class G, int DEPTH>
-__device__ __forceinline__ void scatter(Stage<G>& s, const TileCtx& t, int nb) {
+__device__ __forceinline__ void scatter(Stage<G>& s, const TileCtx& t, const DevOpts& op, int nb) {
   constexpr int GX = 8 * G::SX / G::BW, GY = 8 * G::SY / G::BW;  // blocks across and down the tile
 #pragma unroll
   for (int k = 0; k < DEPTH; ++k) {
@@ -213,31 +214,32 @@ __device__ __forceinline__ void scatter(Stage<G>& s, const TileCtx& t, int nb) {
     if (x1 < t.tx0 || y1 < t.ty0 || gx0 >= GX || gy0 >= GY) continue;
     const float4 A = s.A[j], B = s.B[j];
     const float ca = B.x, cb = B.y, cc = B.z;
-    const float kp = 2.f * __logf(255.f * A.w) + 1.f;
+    const float kq = 2.f * __logf(A.w / op.alpha_min) * 1.01f + 0.01f;
     const float det = ca * cc - cb * cb;
-    // a nearly singular conic (det not well above the rounding of a c - b^2) keeps the whole rectangle
-    const bool cull = det > 1e-3f * ca * cc;
-    const float inv_a = 1.f / ca;
-    const float ey = sqrtf(fmaxf(kp * ca / det, 0.f));             // |dy| reach of the ellipse
-    const float dyx = cb * sqrtf(fmaxf(kp / (cc * det), 0.f));     // dy of the leftmost point; -dyx: rightmost
-    const float ox = (float)t.tx0 + 0.5f - A.x;                    // dx of the tile's first pixel centre
+    const bool cull = det > 1e-3f * ca * cc;  // else the whole rectangle is kept
+    const float inv_a = 1.f / ca, ak = ca * kq;
     const uint64_t bit = 1ull << (j & 63);
     const int wd = j >> 6;
     for (int gy = gy0; gy <= gy1; ++gy) {
       int cx0 = gx0, cx1 = gx1;
       if (cull) {
-        const float sy0 = (float)(t.ty0 + gy * G::BW) + 0.5f - A.y;  // strip of pixel centres, in dy
-        const float lo = fmaxf(sy0, -ey), hi = fminf(sy0 + (float)(G::BW - 1), ey);
+        // pixel rows of this block row inside the record's rectangle
+        const int r0 = max(t.ty0 + gy * G::BW, y0), r1 = min(t.ty0 + gy * G::BW + G::BW - 1, y1);
+        int lo = 1 << 30, hi = -(1 << 30);
+        for (int yy = r0; yy <= r1; ++yy) {
+          const float dy = (float)yy + 0.5f - A.y;
+          const float disc = ak - det * dy * dy;
+          if (disc < 0.f) continue;
+          const float sq = sqrtf(disc);
+          // pixel columns whose centres px + 0.5 lie in [A.x + xl, A.x + xr]
+          const float xl = A.x + (-cb * dy - sq) * inv_a - 0.5f, xr = A.x + (-cb * dy + sq) * inv_a - 0.5f;
+          lo = min(lo, (int)ceilf(fminf(fmaxf(xl, -1.f), 65536.f)));
+          hi = max(hi, (int)floorf(fminf(fmaxf(xr, -1.f), 65536.f)));
+        }
         if (lo > hi) continue;
-        const float dr = fminf(fmaxf(-dyx, lo), hi), dl = fminf(fmaxf(dyx, lo), hi);
-        const float xr = (-cb * dr + sqrtf(fmaxf(ca * kp - det * dr * dr, 0.f))) * inv_a;
-        const float xl = (-cb * dl - sqrtf(fmaxf(ca * kp - det * dl * dl, 0.f))) * inv_a;
-        // columns whose pixel centres [ox + gx BW, ox + gx BW + BW - 1] meet [xl, xr] (clamped before the
-        // conversion so that it stays in range)
-        const float fl = fminf(fmaxf((xl - ox - (float)(G::BW - 1)) * (1.f / G::BW), -1.f), (float)GX);
-        const float fr = fminf(fmaxf((xr - ox) * (1.f / G::BW), -1.f), (float)GX);
-        cx0 = max(gx0, (int)ceilf(fl));
-        cx1 = min(gx1, (int)floorf(fr));
+        cx0 = max(gx0, (max(lo, t.tx0) - t.tx0) / G::BW);
+        cx1 = min(gx1, (hi - t.tx0) / G::BW);
+        if (hi < t.tx0) continue;
       }
       for (int gx = cx0; gx <= cx1; ++gx) {
         const int b = ((gy / G::BS) * G::SX + gx / G::BS) * G::BPW + (gy % G::BS) * G::BS + gx % G::BS;
@@ -314,7 +316,7 @@ __device__ __forceinline__ void sweep(Stage<G>& s, const float4* __restrict__ re
     clear_masks<G>(s);
     stage_round<G, DEPTH>(s, rec, vals, b0, rg.y, fr, frn, fA, fB, fC);
     __syncthreads();
-    scatter<G, DEPTH>(s, t, nb);
+    scatter<G, DEPTH>(s, t, op, nb);
     __syncthreads();
     walk_round<G, SYNC>(s, t, live, step, post);
   }

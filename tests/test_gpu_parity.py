@@ -746,3 +746,91 @@ def test_full_size_batch_gradients_match_fp64_oracle(gpu_lib):
         # near-threshold decision excuse ~7% of the Gaussians
         check_grads(out["grads"], ref, exc, f"full cfg4 {tile} {bw} {seg} fused={fused}", nn,
                     offs[big + 3] - offs[big], scale, max_excused=0.10)
+
+
+# ----------------------------------------------------------------------------- autograd + finite differences
+def test_autograd_function_matches_oracle_and_finite_differences_on_full_scene_crop(gpu_lib):
+    """The differentiation check of the single-keyframe workload (1M Gaussians, SH degree 3): a 64x64
+    level-0 window (chosen where the oracle's level-2 render is at least half covered) rendered as its own
+    view through the torch.autograd.Function, with the L1 colour + 0.1 L1 depth loss written in torch.  Its
+    gradients match the oracle's FP64 analytic gradient at the 1e-3 bar (the guard band is widened to 41 window
+    widths so that the window sees the Gaussians the whole image would), and 200 random parameters of
+    Gaussians that reach the window (40 per group) match central finite differences of the FP64 oracle loss
+    (Richardson-extrapolated from steps h = 1e-5 max(1, |x|) and h/2; twice their difference plus the loss's
+    own rounding over h, 1e-13 / h, bound the error): the oracle's analytic value to 2e-5 plus that bound, the
+    GPU's to the 1e-3 bar plus it (steps whose two differences disagree by more than 1e-3 straddle a discrete
+    decision and are skipped)."""
+    import dataclasses
+
+    from paper_2411_02703_amd.rasterize import Rasterizer, rasterize
+
+    sc = scenes.config(3)
+    cam0, cam2 = sc.cams[0], sc.cams[2]
+    v2 = oracle.forward(32, sc.params(), sc.sh_degree, [cam2])["vis"].reshape(cam2.height, cam2.width)
+    rng = np.random.default_rng(3001)
+    for _ in range(500):
+        x2, y2 = int(rng.integers(0, cam2.width - 16)), int(rng.integers(0, cam2.height - 16))
+        if (v2[y2:y2 + 16, x2:x2 + 16] > 0.5).mean() >= 0.5:
+            break
+    x0, y0 = 4 * x2, 4 * y2
+    win = dataclasses.replace(cam0.cropped(x0, y0, 64, 64), weight=1.0)
+    P = 64 * 64
+    tr = np.ascontiguousarray(sc.tgt_rgb[:3 * cam0.width * cam0.height].reshape(3, cam0.height, cam0.width)
+                              [:, y0:y0 + 64, x0:x0 + 64].reshape(-1))
+    td = np.ascontiguousarray(sc.tgt_depth[:cam0.width * cam0.height].reshape(cam0.height, cam0.width)
+                              [y0:y0 + 64, x0:x0 + 64].reshape(-1))
+    assert (td > 0).any()
+    # GPU: autograd through the rasteriser, loss in torch
+    prm = {k: torch.tensor(v, dtype=torch.float32, device="cuda", requires_grad=True) for k, v in sc.params().items()}
+    guard = 41.0
+    rast = Rasterizer(sc.n, [win], sc.sh_degree, opts=B.default_opts(guard=guard))
+    rgb, depth, vis = rasterize(prm["means"], prm["log_scales"], prm["quats"], prm["opacity"], prm["sh"], rast)
+    trt, tdt = torch.as_tensor(tr).cuda(), torch.as_tensor(td).cuda()
+    valid = tdt > 0
+    loss = (rgb - trt).abs().mean() + 0.1 * (depth[valid] - tdt[valid]).abs().sum() / valid.sum()
+    loss.backward()
+    g_gpu = {k: v.grad.detach().cpu().numpy().astype(np.float64) for k, v in prm.items()}
+    L, ref, exc, nn, scale = grad_reference(sc.params(), sc.sh_degree, [win], tgt_rgb=tr, tgt_depth=td,
+                                            guard=guard)
+    np.testing.assert_allclose(float(loss), L, rtol=1e-5)
+    check_grads(g_gpu, ref, exc, f"autograd crop {x0},{y0}", nn, P, scale)
+    # finite differences of the FP64 oracle loss, on the Gaussians visible in the window (the others cannot
+    # change it)
+    _, g64, _, _, _ = oracle.backward(64, sc.params(), sc.sh_degree, [win], tgt_rgb=tr, tgt_depth=td, guard=guard)
+    seen = np.flatnonzero(oracle.project(64, sc.params(), sc.sh_degree, [win], guard=guard)["visible"] != 0)
+    sub = {k: np.ascontiguousarray(np.asarray(v, np.float64)[seen]) for k, v in sc.params().items()}
+    rms = {k: math.sqrt(float((ref[k].reshape(sc.n, -1)[~exc] ** 2).mean())) for k in ref}
+    checked = 0
+    for key in ("means", "log_scales", "quats", "opacity", "sh"):
+        flat = g64[key].reshape(sc.n, -1)
+        cand = [(i, c) for i in np.flatnonzero(np.abs(flat).max(axis=1) > 0) for c in range(flat.shape[1])
+                if flat[i, c] != 0 and not exc[i]]
+        pick = rng.permutation(len(cand))[:40]
+        for t in pick:
+            gi, comp = cand[t]
+            si = int(np.searchsorted(seen, gi))
+            assert seen[si] == gi
+            view = sub[key].reshape(len(seen), -1)
+            x = view[si, comp]
+            h = 1e-5 * max(1.0, abs(x))
+
+            def L_at(val):
+                view[si, comp] = val
+                out = oracle.loss(sub, sc.sh_degree, [win], tr, td, guard=guard)
+                view[si, comp] = x
+                return out
+
+            d1 = (L_at(x + h) - L_at(x - h)) / (2 * h)
+            d2 = (L_at(x + h / 2) - L_at(x - h / 2)) / h
+            est = abs(d1 - d2)
+            if est > 1e-3 * abs(d2) + 1e-12:
+                continue
+            fd = (4 * d2 - d1) / 3
+            fd_err = 2 * est + 1e-13 / h
+            assert abs(fd - flat[gi, comp]) <= 2e-5 * abs(fd) + fd_err, (key, gi, comp, fd, flat[gi, comp], est)
+            gg = g_gpu[key].reshape(sc.n, -1)[gi, comp]
+            tol = GRAD_TOL * (abs(fd) + rms[key]) + ROUND_C * U32 * scale[key].reshape(sc.n, -1)[gi, comp] + fd_err
+            assert abs(gg - fd) <= tol, (key, gi, comp, gg, fd)
+            checked += 1
+    log("finite differences checked", checked, "of 200")
+    assert checked >= 150

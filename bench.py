@@ -47,7 +47,9 @@ def timed(fn, steps, stream):
     return start.elapsed_time(end) / steps
 
 
-def measure(sc, steps, warmup, plain_steps, do_plain, tile=None):
+def measure(sc, steps, warmup, plain_steps, do_plain, tile=None, peak=False):
+    """Autotune (unless tile is given), then time the batched step and optionally the plain sequence; with
+    peak, also the peak device memory of each (torch allocations, which hold every library buffer)."""
     import torch
 
     from paper_2411_02703_amd import autotune
@@ -63,6 +65,10 @@ def measure(sc, steps, warmup, plain_steps, do_plain, tile=None):
     opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], batch_depth=tile[2], block_w=tile[3], seg_len=tile[4])
     log(f"  configuration: {tile[0]}x{tile[1]} tiles, {tile[2]} records per thread per round, "
         f"block {tile[3]}, seg_len {tile[4]}")
+    if peak:
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
     model = GaussianModel(sc.params(), sc.sh_degree)
     t0 = time.time()
     bat = BatchedStep(model, sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=opts)
@@ -75,13 +81,21 @@ def measure(sc, steps, warmup, plain_steps, do_plain, tile=None):
         raise RuntimeError("instance capacity overflow during timing")
     res = dict(ms=ms, n_instances=bat.n_instances(), loss=bat.loss(), frame=bat.frame, model=model, step=bat,
                tile=tile)
+    if peak:
+        res["peak_gb"] = torch.cuda.max_memory_allocated() / 1e9
     log(f"  batched: {ms:.3f} ms/step ({1000 / ms:.2f} it/s), {res['n_instances']} instances")
     if do_plain:
+        if peak:
+            torch.cuda.synchronize()
+            base = torch.cuda.memory_allocated()  # the batched step's buffers, still held
+            torch.cuda.reset_peak_memory_stats()
         pm = GaussianModel(sc.params(), sc.sh_degree)
         plain = PlainStep(pm, sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=opts)
         plain.run()
         pms = timed(plain.run, plain_steps, stream)
         res["plain_ms"] = pms
+        if peak:
+            res["plain_peak_gb"] = (torch.cuda.max_memory_allocated() - base) / 1e9
         log(f"  plain:   {pms:.3f} ms/step ({1000 / pms:.2f} it/s)")
     return res
 
@@ -165,6 +179,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-cfg3", action="store_true")
+    ap.add_argument("--cfg5", action="store_true",
+                    help="also time the large map (4M Gaussians, 16 keyframes x 3 levels; about two minutes of "
+                         "scene generation on the host)")
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count (smaller trial runs)")
     ap.add_argument("--tile", type=str, default=None,
                     help="tile_w,tile_h[,batch_depth,block_w,seg_len] (skips the autotuner)")
@@ -240,6 +257,24 @@ def main():
         out["single_keyframe_1280x1024_pyramid"] = {"batched": round(1000.0 / r3["ms"], 3)}
         if "plain_ms" in r3:
             out["single_keyframe_1280x1024_pyramid"]["plain"] = round(1000.0 / r3["plain_ms"], 3)
+    if args.cfg5:
+        t0 = time.time()
+        sc5 = scenes.config(5, n=None if args.n is None else 4 * args.n)
+        log(f"cfg5 scene: {sc5.n} Gaussians, {len(sc5.cams)} views, {sc5.total_pixels} px ({time.time() - t0:.1f}s)")
+        torch.cuda.empty_cache()
+        r5 = measure(sc5, max(5, args.steps // 2), args.warmup, 3, not args.no_plain, tile, peak=True)
+        out["large_map_4M"] = {
+            "workload": "4M Gaussians (SH degree 3) over a 200 m x 200 m LiDAR scene, 16 keyframes 640x512..1280x1024 "
+                        "x 3 levels = 48 views; per-pixel state recomputed in the backward",
+            "pixels": sc5.total_pixels, "instances": r5["n_instances"], "tile": list(r5["tile"]),
+            "batched": {"value": round(1000.0 / r5["ms"], 3), "ms_per_step": round(r5["ms"], 4),
+                        "peak_memory_gb": round(r5["peak_gb"], 3)}}
+        if "plain_ms" in r5:
+            out["large_map_4M"]["plain"] = {"value": round(1000.0 / r5["plain_ms"], 3),
+                                            "ms_per_step": round(r5["plain_ms"], 4),
+                                            "peak_memory_gb": round(r5["plain_peak_gb"], 3)}
+            out["large_map_4M"]["batched_over_plain"] = round(r5["plain_ms"] / r5["ms"], 3)
+        del sc5, r5
     if not args.no_cpu:
         big = max(range(0, len(sc4.cams), 3), key=lambda i: sc4.cams[i].width)
         out["cpu_baseline"] = cpu_baseline(sc4, [big, big + 1, big + 2])

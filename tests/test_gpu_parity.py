@@ -686,6 +686,23 @@ def test_full_size_single_keyframe_forward_matches_oracle(gpu_lib):
         log("full-size cfg3 forward", tile, bw, seg, "ok")
 
 
+def test_full_size_single_view_forward_and_gradients_match_oracle(gpu_lib):
+    """The realistic single view: 300k Gaussians (SH degree 3) from the LiDAR scan, one 1280x1024 view with
+    sparse depth; images against the FP32 oracle and every gradient against the FP64 oracle."""
+    sc = scenes.config(2)
+    ref = oracle.forward(32, sc.params(), sc.sh_degree, sc.cams)
+    L, g, exc, nn, scale = grad_reference(sc.params(), sc.sh_degree, sc.cams, tgt_rgb=sc.tgt_rgb,
+                                          tgt_depth=sc.tgt_depth)
+    for tile, bw, seg in FULL_CONFIGS[:2]:
+        out = run_gpu(sc, tile=tile, bw=bw, seg=seg, targets=True, fused=False)
+        out["cams"] = sc.cams
+        check_images(out, ref, ref["near"], f"full cfg2 {tile} {bw} {seg}")
+        np.testing.assert_allclose(out["loss"], L, rtol=1e-5)
+        # a dense view: its 3e-4 near-threshold pixels have ~100 contributors each (5.3% of the Gaussians)
+        check_grads(out["grads"], g, exc, f"full cfg2 {tile} {bw} {seg}", nn, sc.total_pixels, scale,
+                    max_excused=0.10)
+
+
 def test_full_size_single_keyframe_loss_matches_oracle(gpu_lib):
     sc = scenes.config(3)
     L = oracle.loss(sc.params(), sc.sh_degree, sc.cams, sc.tgt_rgb, sc.tgt_depth)

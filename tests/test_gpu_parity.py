@@ -179,8 +179,10 @@ def test_projection_matches_oracle(gpu_lib, deg):
 
 
 # ----------------------------------------------------------------------------- binning
-def test_binning_matches_oracle(gpu_lib):
-    sc = scenes.random_scene(200, 4000, 130, 90, sh_degree=1, views=3, log_scale_mu=-2.0)
+@pytest.mark.parametrize("seed,n,W,H,mu", [(200, 4000, 130, 90, -2.0), (201, 600, 256, 192, -0.6)])
+def test_binning_matches_oracle(gpu_lib, seed, n, W, H, mu):
+    """The second scene holds Gaussians covering more than 32 tiles of a view, which the whole wave emits."""
+    sc = scenes.random_scene(seed, n, W, H, sh_degree=1, views=3, log_scale_mu=mu)
     log("binning")
     out = run_gpu(sc, targets=False)
     fr, V, n = out["frame"], len(sc.cams), sc.n
@@ -190,6 +192,11 @@ def test_binning_matches_oracle(gpu_lib):
     vals = vals.cpu().numpy()
     rng_ = B.frame_tensor(fr, "tile_range", 2 * fr.f.n_tiles, torch.int32).view(-1, 2).cpu().numpy()
     ref = oracle.project(32, sc.params(), 1, sc.cams)
+    tr = ref["tilerect"]
+    area = np.where(ref["visible"] != 0, (tr[:, 1] - tr[:, 0] + 1) * (tr[:, 3] - tr[:, 2] + 1), 0)
+    log("records over 32 tiles:", int((area > 32).sum()))
+    if mu > -1.0:
+        assert (area > 32).sum() > 10
     rk, rv, lo, hi = oracle.bin_records(ref["tilerect"], ref["zbits"], ref["visible"], n, sc.cams)
     marginal = set(np.nonzero((ref["rect_margin"] <= 1e-3) | (ref["near_margin"] <= 1e-5))[0].tolist())
     log("instances gpu", I, "oracle", len(rk))
@@ -809,7 +816,7 @@ def test_autograd_function_matches_oracle_and_finite_differences_on_full_scene_c
     g_gpu = {k: v.grad.detach().cpu().numpy().astype(np.float64) for k, v in prm.items()}
     L, ref, exc, nn, scale = grad_reference(sc.params(), sc.sh_degree, [win], tgt_rgb=tr, tgt_depth=td,
                                             guard=guard)
-    np.testing.assert_allclose(float(loss), L, rtol=1e-5)
+    np.testing.assert_allclose(loss.item(), L, rtol=1e-5)
     check_grads(g_gpu, ref, exc, f"autograd crop {x0},{y0}", nn, P, scale)
     # finite differences of the FP64 oracle loss, on the Gaussians visible in the window (the others cannot
     # change it)

@@ -276,13 +276,13 @@ __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, 
   for (int c = 0; c < G::MC; ++c) {
     uint64_t m = ((__ballot(live) >> t.blk_lane0) & BMASK) ? s.bm[c][t.blk] : 0ull;
     if (__ballot(m != 0) == 0) continue;
-    // the block's next record is fetched from LDS while the current one is composited
-    int jn = c * 64 + (m ? __builtin_ctzll(m) : 0);
-    float4 An = s.A[jn], Bn = s.B[jn], Cn = s.C[jn];
-    while (SYNC ? __ballot(m != 0) != 0 : m != 0) {
-      const int j = jn;
+    // The block's next record is fetched from LDS while the current one is composited; two register sets
+    // take turns (the loop is unrolled by two), so nothing is copied between them.
+    int j0 = c * 64 + (m ? __builtin_ctzll(m) : 0), j1 = 0;
+    float4 A0 = s.A[j0], B0 = s.B[j0], C0 = s.C[j0], A1, B1, C1;
+    auto one = [&](int j, const float4& A, const float4& B, const float4& C, int& jn, float4& An, float4& Bn,
+                   float4& Cn) {
       const bool active = m != 0 && live;
-      const float4 A = An, B = Bn, C = Cn;
       m &= m - 1;
       jn = c * 64 + (m ? __builtin_ctzll(m) : 0);
       An = s.A[jn];
@@ -292,6 +292,12 @@ __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, 
       const bool hit = step(j, active, A, B, C, acc);
       if (SYNC) post(j, hit, acc);
       if (((__ballot(live) >> t.blk_lane0) & BMASK) == 0) m = 0;
+    };
+    auto more = [&]() { return SYNC ? __ballot(m != 0) != 0 : m != 0; };
+    while (more()) {
+      one(j0, A0, B0, C0, j1, A1, B1, C1);
+      if (!more()) break;
+      one(j1, A1, B1, C1, j0, A0, B0, C0);
     }
   }
 }
@@ -467,12 +473,16 @@ __device__ __forceinline__ void add_loss(const TileCtx& t, const BwdArgs& a, flo
   if (t.lane == 63) gsk::atomic_add_f32(a.loss, ls);
 }
 
-// Store the LDS partial derivatives of this thread's staged records of the round that started at list
-// position b0 (nb records) as the partials of those instances (at their emission indices), and clear them.
+// Store the LDS sums of this thread's staged records of the round that started at list position b0 (nb
+// records, still staged in s) as the partials of those instances (at their emission indices), and clear
+// them.  The sums are, over the record's contributing pixels (d = mean - pixel centre, dq = dL/dalpha alpha):
+//   dq dx, dq dy, dq dx^2, dq dx dy, dq dy^2, dL/dalpha G, w g_r, w g_g, w g_b, w g_d;
+// with the conic (a, b, c) of the record, power = -(a dx^2 + c dy^2)/2 - b dx dy gives
+//   dL/dmean = -(a S_x + b S_y, b S_x + c S_y),  dL/d(a, b, c) = -(S_xx / 2, S_xy, S_yy / 2).
 // Plain stores: every instance has exactly one writer (its tile or depth segment), so nothing is accumulated
 // in HBM.
 template <class G, int DEPTH>
-__device__ __forceinline__ void flush_grads(float (*gacc)[G::BATCH], float* __restrict__ ipart,
+__device__ __forceinline__ void flush_grads(const Stage<G>& s, float (*gacc)[G::BATCH], float* __restrict__ ipart,
                                             const int32_t* __restrict__ emi, int b0, int nb) {
 #pragma unroll
   for (int k = 0; k < DEPTH; ++k) {
@@ -484,6 +494,15 @@ __device__ __forceinline__ void flush_grads(float (*gacc)[G::BATCH], float* __re
     for (int q = 0; q < 10; ++q) {
       v[q] = gacc[q][j];
       any |= v[q] != 0.f;
+    }
+    {
+      const float4 B = s.B[j];
+      const float sx = v[0], sy = v[1];
+      v[0] = -(B.x * sx + B.y * sy);
+      v[1] = -(B.y * sx + B.z * sy);
+      v[2] = -0.5f * v[2];
+      v[3] = -v[3];
+      v[4] = -0.5f * v[4];
     }
     float4* dst = reinterpret_cast<float4*>(ipart) + 3 * (int64_t)emi[b0 + j];
     dst[0] = make_float4(v[0], v[1], v[2], v[3]);
@@ -537,17 +556,21 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
     const float Pn = Pp + w * qv;
     const float dalpha = T * qv - (S - Pn) * __builtin_amdgcn_rcpf(1.f - alpha);
     const bool shape = hit && !cl;  // a clamped alpha passes no gradient to opacity or shape
-    const float dq = dalpha * alpha;
-    acc[0] = shape ? -(B.x * dx + B.y * dy) * dq : 0.f;
-    acc[1] = shape ? -(B.z * dy + B.y * dx) * dq : 0.f;
-    acc[2] = shape ? -0.5f * dx * dx * dq : 0.f;
-    acc[3] = shape ? -dx * dy * dq : 0.f;
-    acc[4] = shape ? -0.5f * dy * dy * dq : 0.f;
+    // Moments of dq = dL/dalpha * alpha over the record's pixels; the record's conic turns them into the
+    // mean and conic gradients once per record (flush_grads).  Every operand is finite (staged records only),
+    // so zeroing dq and w zeroes the partials of a lane that does not contribute.
+    const float dq = shape ? dalpha * alpha : 0.f;
+    const float wh = hit ? w : 0.f;
+    acc[0] = dq * dx;
+    acc[1] = dq * dy;
+    acc[2] = acc[0] * dx;
+    acc[3] = acc[0] * dy;
+    acc[4] = acc[1] * dy;
     acc[5] = shape ? dalpha * Gv : 0.f;
-    acc[6] = hit ? w * gr : 0.f;
-    acc[7] = hit ? w * gg : 0.f;
-    acc[8] = hit ? w * gb : 0.f;
-    acc[9] = hit ? w * gd : 0.f;
+    acc[6] = wh * gr;
+    acc[7] = wh * gg;
+    acc[8] = wh * gb;
+    acc[9] = wh * gd;
     Pp = hit ? Pn : Pp;
     T = hit ? Tn : T;
     return hit;
@@ -566,6 +589,25 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
     }
     constexpr uint64_t BMASK = G::BL == 64 ? ~0ull : ((1ull << G::BL) - 1);
     const bool block_hit = ((hits >> t.blk_lane0) & BMASK) != 0;
+    if (G::BW == 2) {
+      // Reduce-scatter over the quad: the exchange with lane^1 halves the values each lane carries (10 -> 5),
+      // the one with lane^2 halves them again (5 -> 3).  Lane bits b0, b1 pick the shares, and the quad's
+      // four lanes end with the sums of values {0,1,2}, {3,4}, {5,6,7}, {8,9}: 3 LDS atomics per lane.
+      const bool c0 = (t.lane & 1) != 0, c1 = (t.lane & 2) != 0;
+      float w[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) w[k] = (c0 ? acc[5 + k] : acc[k]) + gsk::dpp_f<0xB1>(c0 ? acc[k] : acc[5 + k]);
+      const float x0 = (c1 ? w[3] : w[0]) + gsk::dpp_f<0x4E>(c1 ? w[0] : w[3]);
+      const float x1 = (c1 ? w[4] : w[1]) + gsk::dpp_f<0x4E>(c1 ? w[1] : w[4]);
+      const float x2 = w[2] + gsk::dpp_f<0x4E>(w[2]);
+      if (block_hit) {
+        const int base = (c0 ? 5 : 0) + (c1 ? 3 : 0);
+        atomicAdd(&gacc[base][j], x0);
+        atomicAdd(&gacc[base + 1][j], x1);
+        if (!c1) atomicAdd(&gacc[base + 2][j], x2);
+      }
+      return;
+    }
     if (G::BW == 4) {
       // Reduce-scatter over the 16-lane row: the first two exchange steps halve the values each lane carries
       // (10 -> 5 -> 3), the mirrors then add plain.  A lane's share is set by c0 = b0^b2, c1 = b1^b2 of its
@@ -605,7 +647,7 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
                         [&](int b0, bool go) {
                           if (b0 != rg.x) {
                             const int p0 = b0 - G::BATCH;
-                            flush_grads<G, DEPTH>(gacc, ipart, emi, p0, min(G::BATCH, rg.y - p0));
+                            flush_grads<G, DEPTH>(s, gacc, ipart, emi, p0, min(G::BATCH, rg.y - p0));
                           }
                           if (!go) zero_grads<G>(ipart, emi, b0, rg.y);
                         },

@@ -115,7 +115,7 @@ __device__ __forceinline__ bool eval_pair(const float4& A, const float4& B, floa
   G = __expf(power);
   const float oG = A.w * G;
   clamped = oG > op.alpha_max;
-  alpha = clamped ? op.alpha_max : oG;
+  alpha = fminf(oG, op.alpha_max);  // the same value as clamped ? alpha_max : oG (oG is finite)
   return !(power > 0.f) && alpha >= op.alpha_min;
 }
 
@@ -467,10 +467,19 @@ __device__ __forceinline__ void pixel_upstream(const TileCtx& t, const BwdArgs& 
   }
 }
 
+// Adds the workgroup's loss to the total: one atomic per workgroup (every thread must call it).
 template <class G>
 __device__ __forceinline__ void add_loss(const TileCtx& t, const BwdArgs& a, float loss_acc) {
+  __shared__ float part[G::NW];
   const float ls = gsk::wave_sum_last(loss_acc);
-  if (t.lane == 63) gsk::atomic_add_f32(a.loss, ls);
+  if (t.lane == 63) part[t.wave] = ls;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float sum = part[0];
+#pragma unroll
+    for (int w = 1; w < G::NW; ++w) sum += part[w];
+    gsk::atomic_add_f32(a.loss, sum);
+  }
 }
 
 // Store the LDS sums of this thread's staged records of the round that started at list position b0 (nb
@@ -543,6 +552,18 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
   for (int k = 0; k < DEPTH; ++k)
 #pragma unroll
     for (int q = 0; q < 10; ++q) gacc[q][k * G::NT + threadIdx.x] = 0.f;
+  // The ten per-record sums live in LDS slots 0 S_x, 1 S_y, 2 S_xx, 3 S_xy, 4 S_yy, 5 opacity, 6..9 w g_(r,g,b,d)
+  // (S_* are moments of dq, see flush_grads).  Each lane computes them as a kept half acc[0..4] and a sent
+  // half acc[5..9] for the first exchange of the block reduce-scatter; which half is kept is the lane's share
+  // c0 (c1 for the second exchange): lanes of share 0 keep S_x, S_xx, S_xy, w g_r, w g_b (slots 0, 2, 3, 6,
+  // 8), lanes of share 1 keep S_y, S_yy, opacity, w g_g, w g_d (slots 1, 4, 5, 7, 9).  The colour halves
+  // depend on the lane only, so their selection is made once here.  With BW = 4 the shares are c0 = b0^b2,
+  // c1 = b1^b2 of the lane's row index (b_k its bits): the quad exchanges (lane^1, lane^2) flip c0 resp. c1,
+  // the row mirrors flip all four bits and keep both shares.  With BW = 2 they are the quad bits b0, b1.
+  const int lr = t.lane & 15;
+  const bool c0 = G::BW == 4 ? ((lr ^ (lr >> 2)) & 1) != 0 : G::BW == 2 ? (lr & 1) != 0 : false;
+  const bool c1 = G::BW == 4 ? (((lr >> 1) ^ (lr >> 2)) & 1) != 0 : G::BW == 2 ? (lr & 2) != 0 : false;
+  const float gK0 = c0 ? gg : gr, gS0 = c0 ? gr : gg, gK1 = c0 ? gd : gb, gS1 = c0 ? gb : gd;
   auto step = [&](int, bool active, const float4& A, const float4& B, const float4& C, float* acc) -> bool {
     float alpha, Gv, dx, dy;
     bool cl;
@@ -556,25 +577,36 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
     const float Pn = Pp + w * qv;
     const float dalpha = T * qv - (S - Pn) * __builtin_amdgcn_rcpf(1.f - alpha);
     const bool shape = hit && !cl;  // a clamped alpha passes no gradient to opacity or shape
-    // Moments of dq = dL/dalpha * alpha over the record's pixels; the record's conic turns them into the
-    // mean and conic gradients once per record (flush_grads).  Every operand is finite (staged records only),
-    // so zeroing dq and w zeroes the partials of a lane that does not contribute.
+    // Every operand is finite (staged records only), so zeroing dq, w and the opacity term zeroes the
+    // partials of a lane that does not contribute.
     const float dq = shape ? dalpha * alpha : 0.f;
     const float wh = hit ? w : 0.f;
-    acc[0] = dq * dx;
-    acc[1] = dq * dy;
-    acc[2] = acc[0] * dx;
-    acc[3] = acc[0] * dy;
-    acc[4] = acc[1] * dy;
-    acc[5] = shape ? dalpha * Gv : 0.f;
-    acc[6] = wh * gr;
-    acc[7] = wh * gg;
-    acc[8] = wh * gb;
-    acc[9] = wh * gd;
+    const float so = shape ? dalpha * Gv : 0.f;
+    const float dK = c0 ? dy : dx, dS = c0 ? dx : dy;
+    const float kA = dq * dK, sA = dq * dS;
+    const float sxy = kA * dS;
+    acc[0] = kA;       // S_x  | S_y
+    acc[1] = kA * dK;  // S_xx | S_yy
+    acc[2] = c0 ? so : sxy;
+    acc[3] = wh * gK0;
+    acc[4] = wh * gK1;
+    acc[5] = sA;
+    acc[6] = sA * dS;
+    acc[7] = c0 ? sxy : so;
+    acc[8] = wh * gS0;
+    acc[9] = wh * gS1;
     Pp = hit ? Pn : Pp;
     T = hit ? Tn : T;
     return hit;
   };
+  auto slot_kept = [&](int k) { return c0 ? (k == 0 ? 1 : k == 1 ? 4 : k == 2 ? 5 : k == 3 ? 7 : 9)
+                                          : (k == 0 ? 0 : k == 1 ? 2 : k == 2 ? 3 : k == 3 ? 6 : 8); };
+  auto slot_sent = [&](int k) { return c0 ? (k == 0 ? 0 : k == 1 ? 2 : k == 2 ? 3 : k == 3 ? 6 : 8)
+                                          : (k == 0 ? 1 : k == 1 ? 4 : k == 2 ? 5 : k == 3 ? 7 : 9); };
+  // after both exchanges lane (c0, c1) holds the block sums of slots x0, x1 and (c1 = 0 only) x2
+  const int x0_slot = c1 ? (c0 ? 7 : 6) : (c0 ? 1 : 0);
+  const int x1_slot = c1 ? (c0 ? 9 : 8) : (c0 ? 4 : 2);
+  const int x2_slot = c0 ? 5 : 3;
   // sum the partials of one step into the records' LDS accumulators (whole wave; one record per block)
   auto post = [&](int j, bool hit, const float* acc) {
     const uint64_t hits = __ballot(hit);
@@ -583,55 +615,38 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
       // few contributing lanes: each adds its own partials
       if (hit) {
 #pragma unroll
-        for (int q = 0; q < 10; ++q) atomicAdd(&gacc[q][j], acc[q]);
+        for (int k = 0; k < 5; ++k) {
+          atomicAdd(&gacc[slot_kept(k)][j], acc[k]);
+          atomicAdd(&gacc[slot_sent(k)][j], acc[5 + k]);
+        }
       }
       return;
     }
     constexpr uint64_t BMASK = G::BL == 64 ? ~0ull : ((1ull << G::BL) - 1);
     const bool block_hit = ((hits >> t.blk_lane0) & BMASK) != 0;
-    if (G::BW == 2) {
-      // Reduce-scatter over the quad: the exchange with lane^1 halves the values each lane carries (10 -> 5),
-      // the one with lane^2 halves them again (5 -> 3).  Lane bits b0, b1 pick the shares, and the quad's
-      // four lanes end with the sums of values {0,1,2}, {3,4}, {5,6,7}, {8,9}: 3 LDS atomics per lane.
-      const bool c0 = (t.lane & 1) != 0, c1 = (t.lane & 2) != 0;
+    if (G::BW == 2 || G::BW == 4) {
+      // Reduce-scatter: the exchange with lane^1 adds the partner's sent half to the kept half (10 -> 5
+      // values per lane), the one with lane^2 halves them again (5 -> 3), and with BW = 4 the two row
+      // mirrors add plain.  Lanes 0..3 of the block then hold the block sums of all ten slots: 3 LDS atomics
+      // per lane instead of 10.
       float w[5];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) w[k] = (c0 ? acc[5 + k] : acc[k]) + gsk::dpp_f<0xB1>(c0 ? acc[k] : acc[5 + k]);
-      const float x0 = (c1 ? w[3] : w[0]) + gsk::dpp_f<0x4E>(c1 ? w[0] : w[3]);
-      const float x1 = (c1 ? w[4] : w[1]) + gsk::dpp_f<0x4E>(c1 ? w[1] : w[4]);
-      const float x2 = w[2] + gsk::dpp_f<0x4E>(w[2]);
-      if (block_hit) {
-        const int base = (c0 ? 5 : 0) + (c1 ? 3 : 0);
-        atomicAdd(&gacc[base][j], x0);
-        atomicAdd(&gacc[base + 1][j], x1);
-        if (!c1) atomicAdd(&gacc[base + 2][j], x2);
+      for (int k = 0; k < 5; ++k) w[k] = acc[k] + gsk::dpp_f<0xB1>(acc[5 + k]);  // quad_perm [1,0,3,2]
+      float x0 = (c1 ? w[3] : w[0]) + gsk::dpp_f<0x4E>(c1 ? w[0] : w[3]);         // quad_perm [2,3,0,1]
+      float x1 = (c1 ? w[4] : w[1]) + gsk::dpp_f<0x4E>(c1 ? w[1] : w[4]);
+      float x2 = w[2] + gsk::dpp_f<0x4E>(w[2]);
+      if (G::BW == 4) {
+        x0 += gsk::dpp_f<0x141>(x0);  // row_half_mirror
+        x1 += gsk::dpp_f<0x141>(x1);
+        x2 += gsk::dpp_f<0x141>(x2);
+        x0 += gsk::dpp_f<0x140>(x0);  // row_mirror
+        x1 += gsk::dpp_f<0x140>(x1);
+        x2 += gsk::dpp_f<0x140>(x2);
       }
-      return;
-    }
-    if (G::BW == 4) {
-      // Reduce-scatter over the 16-lane row: the first two exchange steps halve the values each lane carries
-      // (10 -> 5 -> 3), the mirrors then add plain.  A lane's share is set by c0 = b0^b2, c1 = b1^b2 of its
-      // row index (b_k its bits): the quad exchanges (lane^1, lane^2) flip c0 resp. c1 and the mirrors keep
-      // both, so every addition pairs equal shares.  Lanes 0..3 of the row end with the row sums of values
-      // {0,1,2}, {5,6,7}, {3,4}, {8,9} and add them to the LDS accumulators: 3 LDS atomics instead of 10.
-      const int lr = t.lane & 15;
-      const bool c0 = ((lr ^ (lr >> 2)) & 1) != 0, c1 = (((lr >> 1) ^ (lr >> 2)) & 1) != 0;
-      float w[5];
-#pragma unroll
-      for (int k = 0; k < 5; ++k) w[k] = (c0 ? acc[5 + k] : acc[k]) + gsk::dpp_f<0xB1>(c0 ? acc[k] : acc[5 + k]);
-      float x[3];
-      x[0] = (c1 ? w[3] : w[0]) + gsk::dpp_f<0x4E>(c1 ? w[0] : w[3]);
-      x[1] = (c1 ? w[4] : w[1]) + gsk::dpp_f<0x4E>(c1 ? w[1] : w[4]);
-      x[2] = (c1 ? 0.f : w[2]) + gsk::dpp_f<0x4E>(c1 ? w[2] : 0.f);
-#pragma unroll
-      for (int k = 0; k < 3; ++k) x[k] += gsk::dpp_f<0x141>(x[k]);  // row_half_mirror
-#pragma unroll
-      for (int k = 0; k < 3; ++k) x[k] += gsk::dpp_f<0x140>(x[k]);  // row_mirror
-      if (lr < 4 && block_hit) {
-        const int base = (c0 ? 5 : 0) + (c1 ? 3 : 0);
-        atomicAdd(&gacc[base][j], x[0]);
-        atomicAdd(&gacc[base + 1][j], x[1]);
-        if (!c1) atomicAdd(&gacc[base + 2][j], x[2]);
+      if ((G::BW == 2 || lr < 4) && block_hit) {
+        atomicAdd(&gacc[x0_slot][j], x0);
+        atomicAdd(&gacc[x1_slot][j], x1);
+        if (!c1) atomicAdd(&gacc[x2_slot][j], x2);
       }
       return;
     }
@@ -640,7 +655,10 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
     for (int q = 0; q < 10; ++q) sum[q] = block_sum<G>(acc[q]);
     if ((t.lane % G::BL) == G::BL - 1 && block_hit) {
 #pragma unroll
-      for (int q = 0; q < 10; ++q) atomicAdd(&gacc[q][j], sum[q]);
+      for (int k = 0; k < 5; ++k) {
+        atomicAdd(&gacc[slot_kept(k)][j], sum[k]);
+        atomicAdd(&gacc[slot_sent(k)][j], sum[5 + k]);
+      }
     }
   };
   sweep<G, DEPTH, true>(s, rec, vals, rg, t, op, live,
@@ -816,7 +834,14 @@ __global__ __launch_bounds__(TW * TH) void k_seg_stop(const float4* __restrict__
   }
 }
 
-// Step 3, first half: the pixel's last live segment ks and its final sums (C, D, V) and transmittance.
+// Segments of a split tile whose loads the combine steps keep in flight together (a tile may have a hundred
+// segments, and the running products make each pixel's pass serial).
+constexpr int kSegBatch = 4;
+
+// Step 3, first half: the pixel's last live segment ks (the last whose start transmittance is at least t_min)
+// and its final sums (C, D, V) and transmittance.  One pass: while the start transmittance of segment k is
+// at least t_min, k is the candidate and the weighted sum of the segments before it is kept aside; the sums
+// are formed in segment order, as two separate passes would form them.
 template <class G>
 __device__ __forceinline__ void split_final(const float* sp, const float* xp, int n, const TileCtx& t,
                                             const DevOpts& op, int& ks, float& Tf, float& Cr, float& Cg, float& Cb,
@@ -824,23 +849,33 @@ __device__ __forceinline__ void split_final(const float* sp, const float* xp, in
   constexpr size_t SS = 6 * G::NT;
   ks = 0;
   float Tr = 1.f;
-  // loads are independent of the running products: unrolled so that they are in flight together
-#pragma unroll 8
-  for (int k = 0; k < n; ++k) {
-    if (Tr >= op.t_min) ks = k;
-    Tr = Tr * sp[k * SS];
-  }
+  float Rr = 0.f, Rg = 0.f, Rb = 0.f, RD = 0.f, RV = 0.f;  // weighted sums of the segments before k
   Cr = Cg = Cb = D = Vs = 0.f;
-  Tr = 1.f;
-#pragma unroll 4
-  for (int k = 0; k < ks; ++k) {
-    const float* q = sp + k * SS;
-    Cr = __builtin_fmaf(Tr, q[1 * G::NT], Cr);
-    Cg = __builtin_fmaf(Tr, q[2 * G::NT], Cg);
-    Cb = __builtin_fmaf(Tr, q[3 * G::NT], Cb);
-    D = __builtin_fmaf(Tr, q[4 * G::NT], D);
-    Vs = __builtin_fmaf(Tr, q[5 * G::NT], Vs);
-    Tr = Tr * q[0];
+  for (int k0 = 0; k0 < n && Tr >= op.t_min; k0 += kSegBatch) {
+    float v[kSegBatch][6];
+#pragma unroll
+    for (int i = 0; i < kSegBatch; ++i) {
+      const float* q = sp + (size_t)min(k0 + i, n - 1) * SS;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[i][c] = q[c * G::NT];
+    }
+#pragma unroll
+    for (int i = 0; i < kSegBatch; ++i) {
+      if (k0 + i < n && Tr >= op.t_min) {
+        ks = k0 + i;
+        Cr = Rr;
+        Cg = Rg;
+        Cb = Rb;
+        D = RD;
+        Vs = RV;
+        Rr = __builtin_fmaf(Tr, v[i][1], Rr);
+        Rg = __builtin_fmaf(Tr, v[i][2], Rg);
+        Rb = __builtin_fmaf(Tr, v[i][3], Rb);
+        RD = __builtin_fmaf(Tr, v[i][4], RD);
+        RV = __builtin_fmaf(Tr, v[i][5], RV);
+        Tr = Tr * v[i][0];
+      }
+    }
   }
   Tf = 1.f;
   if (t.inside) {
@@ -904,17 +939,27 @@ __global__ __launch_bounds__(TW * TH) void k_seg_combine(const gs_camera* __rest
   const float S = gr * Cf + gg * Gf + gb * Bf + gd * Df + gv * Vf;
   if (LOSS) add_loss<G>(t, a, loss_acc);
   float Tr = 1.f, Pr = 0.f;
-#pragma unroll 4
-  for (int k = 0; k < n; ++k) {
-    float* q = sp + k * SS;
-    const float Tk = q[0];
-    const float dot = k < ks ? Tr * (gr * q[1 * G::NT] + gg * q[2 * G::NT] + gb * q[3 * G::NT] +
-                                     gd * q[4 * G::NT] + gv * q[5 * G::NT])
-                             : 0.f;
-    q[0] = k <= ks ? Tr : 0.f;
-    q[1 * G::NT] = Pr;
-    Pr += dot;
-    Tr = Tr * Tk;
+  for (int k0 = 0; k0 < n; k0 += kSegBatch) {
+    // segments up to ks are read (batched); later ones only get T_start = 0
+    float v[kSegBatch][6];
+#pragma unroll
+    for (int i = 0; i < kSegBatch; ++i) {
+      const float* q = sp + (size_t)min(k0 + i, n - 1) * SS;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[i][c] = k0 + i <= ks ? q[c * G::NT] : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < kSegBatch; ++i) {
+      const int k = k0 + i;
+      if (k >= n) break;
+      float* q = sp + (size_t)k * SS;
+      const float dot =
+          k < ks ? Tr * (gr * v[i][1] + gg * v[i][2] + gb * v[i][3] + gd * v[i][4] + gv * v[i][5]) : 0.f;
+      q[0] = k <= ks ? Tr : 0.f;
+      q[1 * G::NT] = Pr;
+      Pr += dot;
+      Tr = Tr * v[i][0];
+    }
   }
   xp[6 * G::NT] = gr;
   xp[7 * G::NT] = gg;

@@ -138,8 +138,10 @@ typedef struct gs_frame {
   float* rec;           /* [n_views*n][12]: {mu_x, mu_y, z, o}, {conic a, b, c, red},
                            {green, blue, px0 | px1 << 16, py0 | py1 << 16} (pixel rectangle as int16 pairs) */
   int16_t* rect;        /* [n_views*n][4]: tile rectangle tx0, tx1, ty0, ty1 (valid when visible) */
-  float* ipart;         /* [capacity][12]: per tile instance, in emission order (Gaussian, then view, then the
-                           tiles of its rectangle row by row), the compositing backward's partial
+  float* ipart;         /* [capacity][12]: per tile instance, in emission order (blocks of 64 consecutive
+                           Gaussians starting at inst_off of the block's first Gaussian; inside a block view by
+                           view, Gaussian by Gaussian, the tiles of each rectangle row by row), the
+                           compositing backward's partial
                            dL/d{mu_x, mu_y, a, b, c, o, red, green, blue, z} of its record summed over the
                            pixels of its tile (or depth segment); 2 words of padding.  Every backward call
                            writes every instance once (plain stores, no atomics) */
@@ -162,7 +164,8 @@ typedef struct gs_frame {
                            {tile, segment, first slot of the tile or -1, schedule position} */
   float* seg;           /* [seg_cap][6][tile_w * tile_h]: per-segment pixel state of split tiles */
   float* split;         /* [long_cap][12][tile_w * tile_h]: per-pixel stop state and upstream gradient */
-  float* loss;          /* [1]: loss value written by gs_render_bwd in loss mode */
+  float* loss;          /* [64]: loss[0] the loss value written by gs_render_bwd in loss mode; loss[1..32] its
+                           partial sums */
   int32_t* scratch;     /* sort histograms and scan partials */
   size_t scratch_ints;
 } gs_frame;
@@ -239,7 +242,7 @@ int gs_render_bwd(const gs_params* params, const gs_frame* frame, const gs_opts*
  * dL/d{mean_I, conic, opacity, colour, depth} of its record over its tile's pixels, written to
  * frame->ipart (every instance, no accumulation across calls); in loss mode it also writes frame->loss.
  * gs_project_bwd: projection backward only (eqs. Sigma and muI): one thread per Gaussian sums the
- * partials of its instances view by view (a contiguous run in emission order) and adds the parameter
+ * partials of its instances view by view (a contiguous run per record in emission order) and adds the parameter
  * gradients to grads (+=); no atomics. */
 int gs_composite_bwd(const gs_frame* frame, const gs_opts* opts, const gs_images* fwd, const gs_loss* loss,
                      void* stream);

@@ -91,11 +91,13 @@ __device__ __forceinline__ int64_t read_lane64(int64_t x, int l) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// One thread per Gaussian: its instances, view by view and tile row by tile row, at its offset.  The sort
-// value is the emission index; inst_rec keeps the record of each emission index.  The lanes of a wave take
-// the views together: a record with at most kSolo tiles is written by its own lane, larger ones by the whole
-// wave one after another (a tile per lane, coalesced), so that the few Gaussians covering thousands of tiles
-// do not hold their waves for thousands of steps.
+// One thread per Gaussian, a wave per 64 consecutive Gaussians.  Emission order: the wave's instances start at
+// the offset of its first Gaussian and are laid out view-major (view by view; inside a view Gaussian by
+// Gaussian, each record's tiles row by row), so that the wave writes each view's instances as one contiguous
+// run; within a tile, equal depths still keep ascending Gaussian order.  The sort value is the emission
+// index; inst_rec keeps the record of each emission index.  A record with at most kSolo tiles is written by
+// its own lane, larger ones by the whole wave one after another (a tile per lane, coalesced), so that the few
+// Gaussians covering thousands of tiles do not hold their waves for thousands of steps.
 __global__ __launch_bounds__(256) void k_emit(const uint64_t* __restrict__ vis_mask, const int32_t* __restrict__ off,
                                              const short4* __restrict__ rect, const float4* __restrict__ rec,
                                              const gs_camera* __restrict__ cams, int V, int64_t n, int64_t capacity,
@@ -104,7 +106,8 @@ __global__ __launch_bounds__(256) void k_emit(const uint64_t* __restrict__ vis_m
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const uint64_t mask = g < n ? vis_mask[g] : 0ull;
-  int64_t o = g < n ? off[g] : 0;
+  const int64_t g0 = g - lane;  // the wave's first Gaussian
+  int64_t base = g0 < n ? off[g0] : 0;
   for (int v = 0; v < V; ++v) {
     const bool vis = (mask >> v) & 1ull;
     if (__ballot(vis) == 0) continue;
@@ -117,6 +120,8 @@ __global__ __launch_bounds__(256) void k_emit(const uint64_t* __restrict__ vis_m
       zb = __float_as_uint(rec[3 * r].z);
     }
     const int w = rc.y - rc.x + 1, cnt = vis ? w * (rc.w - rc.z + 1) : 0;
+    int tot;
+    const int64_t o = base + gsk::wave_excl_scan(cnt, tot);
     if (vis && cnt <= kSolo) {
       int64_t q = o;
       for (int ty = rc.z; ty <= rc.w; ++ty)
@@ -147,7 +152,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint64_t* __restrict__ vis_m
         }
       }
     }
-    o += cnt;
+    base += tot;
   }
 }
 

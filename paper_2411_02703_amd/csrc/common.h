@@ -9,6 +9,8 @@
 namespace gsk {
 
 constexpr int kWave = 64;
+// Partial sums of the loss (frame->loss[1 .. kLossSlots]); the frame holds 64 floats for the loss.
+constexpr int kLossSlots = 32;
 
 // Options as the kernels see them (passed by value).
 struct DevOpts {
@@ -84,6 +86,18 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Exclusive prefix sum over the 64 lanes (lane order) of a non-negative int; total = the wave's sum.
+__device__ __forceinline__ int wave_excl_scan(int x, int& total) {
+  int incl = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(incl, d);
+    if (__lane_id() >= d) incl += y;
+  }
+  total = __builtin_amdgcn_readlane(incl, 63);
+  return incl - x;
+}
+
 __device__ __forceinline__ float read_lane(float x, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
@@ -131,6 +145,8 @@ hipError_t work_items(const gs_frame& f, hipStream_t s);
 hipError_t render_fwd(const gs_frame& f, const gs_opts& o, const gs_images& out, hipStream_t s);
 hipError_t count_pairs(const gs_frame& f, const gs_opts& o, unsigned long long* counts, hipStream_t s);
 hipError_t count_valid(const gs_frame& f, const float* tgt_depth, int64_t max_pixels, hipStream_t s);
+// loss[0] = sum of the partial sums loss[1 .. kLossSlots]
+hipError_t loss_total(float* loss, hipStream_t s);
 hipError_t render_bwd(const gs_frame& f, const gs_opts& o, const gs_images* fwd, const gs_loss& l,
                       hipStream_t s);
 hipError_t adam(const gs_params& p, const gs_params& g, const gs_params& m, const gs_params& v,

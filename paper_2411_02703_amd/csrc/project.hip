@@ -302,10 +302,12 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ m
 #pragma unroll
   for (int i = 0; i < K * 3; ++i) gf[i] = 0.f;
 
-  // this Gaussian's instances, in emission order: view by view, the tiles of each view's rectangle.  The
+  // this Gaussian's instances, in emission order: the wave's instances start at the offset of its first
+  // Gaussian and run view by view, Gaussian by Gaussian inside a view, each record's tiles together.  The
   // lanes take the views together; a record with more than kSolo tiles is summed by the whole wave.
   const int64_t n_stored = min((int64_t)count_dev[0], capacity);
-  int64_t i = mask ? inst_off[g] : 0;
+  const int64_t g0 = g - lane;
+  int64_t base = g0 < n ? inst_off[g0] : 0;
   for (int v = 0; v < V; ++v) {
     const bool vis = (mask >> v) & 1ull;
     if (__ballot(vis) == 0) continue;
@@ -316,6 +318,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ m
       const short4 rc = rect[r];
       cnt = (rc.y - rc.x + 1) * (rc.w - rc.z + 1);
     }
+    int tot;
+    const int64_t i = base + gsk::wave_excl_scan(cnt, tot);
     // the record's gradient: the sum of its instances' partials over the tiles it covers (a contiguous run,
     // read four instances at a time so that their loads are in flight together)
     float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0;
@@ -364,7 +368,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ m
         q2 = make_float4(sm[8], sm[9], 0.f, 0.f);
       }
     }
-    i += cnt;
+    base += tot;
     if (!vis) continue;
     const float dmx = q0.x, dmy = q0.y, da = q0.z, db = q0.w;
     const float dc = q1.x, d_o = q1.y, dr = q1.z, dg = q1.w;

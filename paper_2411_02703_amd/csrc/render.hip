@@ -467,7 +467,9 @@ __device__ __forceinline__ void pixel_upstream(const TileCtx& t, const BwdArgs& 
   }
 }
 
-// Adds the workgroup's loss to the total: one atomic per workgroup (every thread must call it).
+// Adds the workgroup's loss to one of the partial sums loss[1 .. kLossSlots] (every thread must call it):
+// one atomic per workgroup, spread over the slots, since atomics on one address serialise; k_loss_total
+// adds the slots into loss[0].
 template <class G>
 __device__ __forceinline__ void add_loss(const TileCtx& t, const BwdArgs& a, float loss_acc) {
   __shared__ float part[G::NW];
@@ -478,7 +480,15 @@ __device__ __forceinline__ void add_loss(const TileCtx& t, const BwdArgs& a, flo
     float sum = part[0];
 #pragma unroll
     for (int w = 1; w < G::NW; ++w) sum += part[w];
-    gsk::atomic_add_f32(a.loss, sum);
+    gsk::atomic_add_f32(a.loss + 1 + (blockIdx.x % gsk::kLossSlots), sum);
+  }
+}
+
+__global__ void k_loss_total(float* __restrict__ loss) {
+  if (threadIdx.x == 0) {
+    float s = 0.f;
+    for (int i = 1; i <= gsk::kLossSlots; ++i) s += loss[i];
+    loss[0] = s;
   }
 }
 
@@ -1198,6 +1208,11 @@ hipError_t count_pairs(const gs_frame& f, const gs_opts& o, unsigned long long* 
   if (o.tile_w == 8 && o.tile_h == 8) return launch_count<8, 8>(f, op, counts, st);
   if (o.tile_w == 32 && o.tile_h == 8) return launch_count<32, 8>(f, op, counts, st);
   return hipErrorInvalidValue;
+}
+
+hipError_t loss_total(float* loss, hipStream_t st) {
+  k_loss_total<<<1, 64, 0, st>>>(loss);
+  return hipGetLastError();
 }
 
 hipError_t count_valid(const gs_frame& f, const float* tgt_depth, int64_t max_pixels, hipStream_t st) {

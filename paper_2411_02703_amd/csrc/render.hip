@@ -733,9 +733,9 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(const float4* __restrict
 // Compositing is a product of transmittances, so per pixel:
 //   1. each segment k walks its records from T = 1 without the stop rule: its transmittance product T_k and
 //      local sums (C, D, V)_k (k_fused_main, alongside the unsplit tiles);
-//   2. T_start,k = T_0 T_1 ... T_{k-1} (left to right); the pixel's last live segment k* is the last with
-//      T_start,k >= t_min, and only there can the stop rule end the walk: that segment is walked again from
-//      T_start,k* with the stop rule (k_seg_stop);
+//   2. T_start,k = T_0 T_1 ... T_{k-1} (left to right, k_seg_prefix); the pixel's last live segment k* is the
+//      last with T_start,k >= t_min, and only there can the stop rule end the walk: that segment is walked
+//      again from T_start,k* with the stop rule (k_seg_stop);
 //   3. the final values are sum_{k<k*} T_start,k (C, D, V)_k plus segment k*'s stopped sums plus the
 //      background; from them the upstream gradient g, S and each segment's start state (T_start,k,
 //      P_start,k = g . sum_{j<k} contribution_j) (k_seg_combine);
@@ -823,14 +823,10 @@ __global__ __launch_bounds__(TW * TH) void k_seg_stop(const float4* __restrict__
   tile_at<G>(cams, V, it.x, t);
   const int2 rg = range[it.x];
   const int n = (rg.y - rg.x + g.len - 1) / g.len;
-  const float* sp = g.seg + (size_t)it.z * 6 * G::NT + threadIdx.x;
-  float Ts = 1.f;
-  // the loads are independent of the product: unrolled so that they are in flight together (a tile may have
-  // a hundred segments)
-#pragma unroll 8
-  for (int j = 0; j < it.y; ++j) Ts = Ts * sp[(size_t)j * 6 * G::NT];
-  const bool last = t.inside && Ts >= op.t_min &&
-                    (it.y == n - 1 || Ts * sp[(size_t)it.y * 6 * G::NT] < op.t_min);
+  // start transmittances of this segment and the next (k_seg_prefix)
+  const float* sp = g.seg + (size_t)(it.z + it.y) * 6 * G::NT + threadIdx.x;
+  const float Ts = sp[0];
+  const bool last = t.inside && Ts >= op.t_min && (it.y == n - 1 || sp[6 * G::NT] < op.t_min);
   float T = Ts, Cr = 0.f, Cg = 0.f, Cb = 0.f, D = 0.f, Vs = 0.f;
   forward_walk<G, DEPTH, true>(s, rec, vals, segment_range<G>(rg, it.y, g.len), t, op, last, T, Cr, Cg, Cb, D, Vs);
   if (last) {
@@ -847,21 +843,48 @@ __global__ __launch_bounds__(TW * TH) void k_seg_stop(const float4* __restrict__
 // Segments of a split tile whose loads the combine steps keep in flight together (a tile may have a hundred
 // segments, and the running products make each pixel's pass serial).
 constexpr int kSegBatch = 4;
+constexpr int kPrefixBatch = 16;
 
-// Step 3, first half: the pixel's last live segment ks (the last whose start transmittance is at least t_min)
-// and its final sums (C, D, V) and transmittance.  One pass: while the start transmittance of segment k is
-// at least t_min, k is the candidate and the weighted sum of the segments before it is kept aside; the sums
-// are formed in segment order, as two separate passes would form them.
+// Step 2, first half: per pixel, the start transmittance T_start,k = T_0 T_1 ... T_{k-1} of every segment of a
+// split tile (the left-to-right product), written over the segment's own product T_k.  Once it is below
+// t_min, so is every later one (each T_k <= 1), and only that comparison is used: those are written as 0.
+template <int TW, int TH, int BW>
+__global__ __launch_bounds__(TW * TH) void k_seg_prefix(SegArgs g, DevOpts op) {
+  using G = Geo<TW, TH, 1, BW>;
+  const int l = blockIdx.x;
+  if (l >= g.counters[194]) return;
+  const int n = g.seg_count[l];
+  constexpr size_t SS = 6 * G::NT;
+  float* sp = g.seg + (size_t)g.seg_first[l] * SS + threadIdx.x;
+  float Tr = 1.f;
+  for (int k0 = 0; k0 < n; k0 += kPrefixBatch) {
+    const bool live = Tr >= op.t_min;
+    float v[kPrefixBatch];
+#pragma unroll
+    for (int i = 0; i < kPrefixBatch; ++i) v[i] = live ? sp[(size_t)min(k0 + i, n - 1) * SS] : 0.f;
+#pragma unroll
+    for (int i = 0; i < kPrefixBatch; ++i) {
+      if (k0 + i >= n) break;
+      sp[(size_t)(k0 + i) * SS] = Tr >= op.t_min ? Tr : 0.f;
+      Tr = Tr * v[i];
+    }
+  }
+}
+
+// Step 3, first half: the pixel's last live segment ks (the last whose start transmittance, from
+// k_seg_prefix, is at least t_min) and its final sums (C, D, V) and transmittance.  One pass: while the start
+// transmittance of segment k is at least t_min, k is the candidate and the weighted sum of the segments
+// before it is kept aside; the sums are formed in segment order.
 template <class G>
 __device__ __forceinline__ void split_final(const float* sp, const float* xp, int n, const TileCtx& t,
                                             const DevOpts& op, int& ks, float& Tf, float& Cr, float& Cg, float& Cb,
                                             float& D, float& Vs) {
   constexpr size_t SS = 6 * G::NT;
   ks = 0;
-  float Tr = 1.f;
+  bool more = true;
   float Rr = 0.f, Rg = 0.f, Rb = 0.f, RD = 0.f, RV = 0.f;  // weighted sums of the segments before k
   Cr = Cg = Cb = D = Vs = 0.f;
-  for (int k0 = 0; k0 < n && Tr >= op.t_min; k0 += kSegBatch) {
+  for (int k0 = 0; k0 < n && more; k0 += kSegBatch) {
     float v[kSegBatch][6];
 #pragma unroll
     for (int i = 0; i < kSegBatch; ++i) {
@@ -871,19 +894,21 @@ __device__ __forceinline__ void split_final(const float* sp, const float* xp, in
     }
 #pragma unroll
     for (int i = 0; i < kSegBatch; ++i) {
-      if (k0 + i < n && Tr >= op.t_min) {
+      const float Ts = v[i][0];
+      if (k0 + i < n && Ts >= op.t_min) {
         ks = k0 + i;
         Cr = Rr;
         Cg = Rg;
         Cb = Rb;
         D = RD;
         Vs = RV;
-        Rr = __builtin_fmaf(Tr, v[i][1], Rr);
-        Rg = __builtin_fmaf(Tr, v[i][2], Rg);
-        Rb = __builtin_fmaf(Tr, v[i][3], Rb);
-        RD = __builtin_fmaf(Tr, v[i][4], RD);
-        RV = __builtin_fmaf(Tr, v[i][5], RV);
-        Tr = Tr * v[i][0];
+        Rr = __builtin_fmaf(Ts, v[i][1], Rr);
+        Rg = __builtin_fmaf(Ts, v[i][2], Rg);
+        Rb = __builtin_fmaf(Ts, v[i][3], Rb);
+        RD = __builtin_fmaf(Ts, v[i][4], RD);
+        RV = __builtin_fmaf(Ts, v[i][5], RV);
+      } else {
+        more = false;
       }
     }
   }
@@ -948,7 +973,7 @@ __global__ __launch_bounds__(TW * TH) void k_seg_combine(const gs_camera* __rest
   pixel_upstream<LOSS>(t, a, Cf, Gf, Bf, Df, gr, gg, gb, gd, gv, loss_acc);
   const float S = gr * Cf + gg * Gf + gb * Bf + gd * Df + gv * Vf;
   if (LOSS) add_loss<G>(t, a, loss_acc);
-  float Tr = 1.f, Pr = 0.f;
+  float Pr = 0.f;
   for (int k0 = 0; k0 < n; k0 += kSegBatch) {
     // segments up to ks are read (batched); later ones only get T_start = 0
     float v[kSegBatch][6];
@@ -963,12 +988,12 @@ __global__ __launch_bounds__(TW * TH) void k_seg_combine(const gs_camera* __rest
       const int k = k0 + i;
       if (k >= n) break;
       float* q = sp + (size_t)k * SS;
+      const float Ts = v[i][0];
       const float dot =
-          k < ks ? Tr * (gr * v[i][1] + gg * v[i][2] + gb * v[i][3] + gd * v[i][4] + gv * v[i][5]) : 0.f;
-      q[0] = k <= ks ? Tr : 0.f;
+          k < ks ? Ts * (gr * v[i][1] + gg * v[i][2] + gb * v[i][3] + gd * v[i][4] + gv * v[i][5]) : 0.f;
+      q[0] = k <= ks ? Ts : 0.f;
       q[1 * G::NT] = Pr;
       Pr += dot;
-      Tr = Tr * v[i][0];
     }
   }
   xp[6 * G::NT] = gr;
@@ -1102,6 +1127,8 @@ hipError_t launch_fwd(const gs_frame& f, const DevOpts& op, const gs_images& out
                                                           out.depth, out.vis);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    k_seg_prefix<TW, TH, BW><<<f.long_cap, bs, 0, st>>>(g, op);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     k_seg_stop<TW, TH, DEPTH, BW><<<f.seg_cap, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, op, g);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_seg_fwd_out<TW, TH, BW><<<f.long_cap, bs, 0, st>>>(f.cams, f.n_views, op, g, out.rgb, out.depth, out.vis);
@@ -1123,6 +1150,8 @@ hipError_t launch_split_bwd(const gs_frame& f, const DevOpts& op, const BwdArgs&
   k_fused_main<TW, TH, DEPTH, BW, HAVE_FWD, LOSS><<<f.item_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  k_seg_prefix<TW, TH, BW><<<f.long_cap, bs, 0, st>>>(g, op);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   k_seg_stop<TW, TH, DEPTH, BW><<<f.seg_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, g);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_seg_combine<TW, TH, BW, HAVE_FWD, LOSS><<<f.long_cap, bs, 0, st>>>(f.cams, f.n_views, op, a, g);

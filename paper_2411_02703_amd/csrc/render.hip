@@ -35,7 +35,7 @@ struct Geo {
   static constexpr int NW = SX * SY;           // waves per tile
   static constexpr int NT = 64 * NW;           // threads = pixels of the tile
   static constexpr int BATCH = NT * DEPTH;     // records staged per round
-  static constexpr int MC = BATCH / 64;        // 64-bit mask words per block
+  static constexpr int MC = BATCH / 32;        // 32-bit mask words per block
   static constexpr int BW = BW_;               // block width (pixels)
   static constexpr int BS = 8 / BW;            // blocks across a sub-tile
   static constexpr int BPW = BS * BS;          // blocks per wave
@@ -50,7 +50,7 @@ template <class G>
 struct Stage {
   float4 A[G::BATCH], B[G::BATCH], C[G::BATCH];
   int32_t r[G::BATCH];
-  uint64_t bm[G::MC][G::NB];    // per block: staged records whose rectangle meets it
+  uint32_t bm[G::MC][G::NB];    // per block: staged records whose rectangle meets it
   int alive[G::NW];             // per wave: a pixel is still live
 };
 
@@ -186,7 +186,7 @@ __device__ __forceinline__ bool round_barrier(Stage<G>& s, const TileCtx& t, boo
 // Clear the block masks.
 template <class G>
 __device__ __forceinline__ void clear_masks(Stage<G>& s) {
-  for (int i = threadIdx.x; i < G::MC * G::NB; i += G::NT) (&s.bm[0][0])[i] = 0ull;
+  for (int i = threadIdx.x; i < G::MC * G::NB; i += G::NT) (&s.bm[0][0])[i] = 0u;
 }
 
 // Set this thread's staged records in the masks of the blocks they can reach.  Blocks are numbered
@@ -218,8 +218,8 @@ __device__ __forceinline__ void scatter(Stage<G>& s, const TileCtx& t, const Dev
     const float det = ca * cc - cb * cb;
     const bool cull = det > 1e-3f * ca * cc;  // else the whole rectangle is kept
     const float inv_a = 1.f / ca, ak = ca * kq;
-    const uint64_t bit = 1ull << (j & 63);
-    const int wd = j >> 6;
+    const uint32_t bit = 1u << (j & 31);
+    const int wd = j >> 5;
     for (int gy = gy0; gy <= gy1; ++gy) {
       int cx0 = gx0, cx1 = gx1;
       if (cull) {
@@ -267,24 +267,24 @@ __device__ __forceinline__ float block_sum(float x) {
 //   step(j, active, A, B, C, acc) -> contributed   (per lane, branch-free; active = this lane has a record
 //                                                   and a live pixel; clears live at the stop)
 //   post(j, hit, acc)                              (whole wave, once per step, only if SYNC)
-// A lane whose block has run out of records reads slot c * 64 (a valid LDS address, possibly stale) and is
-// inactive.
+// A lane whose block has run out of records reads slot c * 32 (a record staged in this round, since some
+// block has a bit in word c) and is inactive.
 template <class G, bool SYNC, class Step, class Post>
 __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, bool& live, Step step, Post post) {
   constexpr uint64_t BMASK = G::BL == 64 ? ~0ull : ((1ull << G::BL) - 1);
 #pragma unroll 1
   for (int c = 0; c < G::MC; ++c) {
-    uint64_t m = ((__ballot(live) >> t.blk_lane0) & BMASK) ? s.bm[c][t.blk] : 0ull;
+    uint32_t m = ((__ballot(live) >> t.blk_lane0) & BMASK) ? s.bm[c][t.blk] : 0u;
     if (__ballot(m != 0) == 0) continue;
     // The block's next record is fetched from LDS while the current one is composited; two register sets
     // take turns (the loop is unrolled by two), so nothing is copied between them.
-    int j0 = c * 64 + (m ? __builtin_ctzll(m) : 0), j1 = 0;
+    int j0 = c * 32 + (m ? __builtin_ctz(m) : 0), j1 = 0;
     float4 A0 = s.A[j0], B0 = s.B[j0], C0 = s.C[j0], A1, B1, C1;
     auto one = [&](int j, const float4& A, const float4& B, const float4& C, int& jn, float4& An, float4& Bn,
                    float4& Cn) {
       const bool active = m != 0 && live;
       m &= m - 1;
-      jn = c * 64 + (m ? __builtin_ctzll(m) : 0);
+      jn = c * 32 + (m ? __builtin_ctz(m) : 0);
       An = s.A[jn];
       Bn = s.B[jn];
       Cn = s.C[jn];

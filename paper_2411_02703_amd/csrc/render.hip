@@ -269,7 +269,8 @@ __device__ __forceinline__ float block_sum(float x) {
 //   post(j, hit, acc)                              (whole wave, once per step, only if SYNC)
 // A lane whose block has run out of records reads slot c * 32 (a record staged in this round, since some
 // block has a bit in word c) and is inactive.
-template <class G, bool SYNC, class Step, class Post>
+// ENDS: the step can end pixels (stop rule); without it a block's liveness is only checked per mask word.
+template <class G, bool SYNC, bool ENDS, class Step, class Post>
 __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, bool& live, Step step, Post post) {
   constexpr uint64_t BMASK = G::BL == 64 ? ~0ull : ((1ull << G::BL) - 1);
 #pragma unroll 1
@@ -291,7 +292,7 @@ __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, 
       float acc[10];
       const bool hit = step(j, active, A, B, C, acc);
       if (SYNC) post(j, hit, acc);
-      if (((__ballot(live) >> t.blk_lane0) & BMASK) == 0) m = 0;
+      if (ENDS && ((__ballot(live) >> t.blk_lane0) & BMASK) == 0) m = 0;
     };
     auto more = [&]() { return SYNC ? __ballot(m != 0) != 0 : m != 0; };
     while (more()) {
@@ -305,7 +306,7 @@ __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, 
 // All rounds of one tile list: stage (with the next round in flight), hand out, walk.  at_round(b0, go) runs
 // in every thread after each round barrier, before the round's LDS is rewritten: b0 is the first record of
 // the round about to be staged, go whether it will be (false once the list or every pixel has ended).
-template <class G, int DEPTH, bool SYNC, class AtRound, class Step, class Post>
+template <class G, int DEPTH, bool SYNC, bool ENDS, class AtRound, class Step, class Post>
 __device__ __forceinline__ void sweep(Stage<G>& s, const float4* __restrict__ rec, const int32_t* __restrict__ vals,
                                       int2 rg, const TileCtx& t, const DevOpts& op, bool& live, AtRound at_round,
                                       Step step, Post post) {
@@ -324,7 +325,7 @@ __device__ __forceinline__ void sweep(Stage<G>& s, const float4* __restrict__ re
     __syncthreads();
     scatter<G, DEPTH>(s, t, op, nb);
     __syncthreads();
-    walk_round<G, SYNC>(s, t, live, step, post);
+    walk_round<G, SYNC, ENDS>(s, t, live, step, post);
   }
 }
 
@@ -346,16 +347,19 @@ __device__ __forceinline__ void forward_walk(Stage<G>& s, const float4* __restri
     const bool stop = STOP && ok && Tn < op.t_min;
     const bool hit = ok && !stop;
     if (STOP) live = live && !stop;
-    const float w = alpha * T;
-    Cr = hit ? __builtin_fmaf(w, B.w, Cr) : Cr;
-    Cg = hit ? __builtin_fmaf(w, C.x, Cg) : Cg;
-    Cb = hit ? __builtin_fmaf(w, C.y, Cb) : Cb;
-    D = hit ? __builtin_fmaf(w, A.z, D) : D;
-    Vs = hit ? Vs + w : Vs;
+    // a pair that does not contribute adds w = 0 (colours, depth and T are finite and the sums non-negative,
+    // so adding 0 leaves every sum's bits unchanged)
+    const float w = hit ? alpha * T : 0.f;
+    Cr = __builtin_fmaf(w, B.w, Cr);
+    Cg = __builtin_fmaf(w, C.x, Cg);
+    Cb = __builtin_fmaf(w, C.y, Cb);
+    D = __builtin_fmaf(w, A.z, D);
+    Vs = Vs + w;
     T = hit ? Tn : T;
     return hit;
   };
-  sweep<G, DEPTH, false>(s, rec, vals, rg, t, op, live, [](int, bool) {}, step, [](int, bool, const float*) {});
+  sweep<G, DEPTH, false, STOP>(s, rec, vals, rg, t, op, live, [](int, bool) {}, step,
+                               [](int, bool, const float*) {});
 }
 
 // Forward sweep of one whole tile for this lane's pixel (forward kernel and fused backward).
@@ -582,15 +586,14 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
     const bool stop = ok && Tn < op.t_min;
     const bool hit = ok && !stop;
     live = live && !stop;
-    const float w = alpha * T;
+    const float wh = hit ? alpha * T : 0.f;  // w of a contributing pair, else 0
     const float qv = gr * B.w + gg * C.x + gb * C.y + gd * A.z + gv;
-    const float Pn = Pp + w * qv;
+    const float Pn = Pp + wh * qv;
     const float dalpha = T * qv - (S - Pn) * __builtin_amdgcn_rcpf(1.f - alpha);
     const bool shape = hit && !cl;  // a clamped alpha passes no gradient to opacity or shape
     // Every operand is finite (staged records only), so zeroing dq, w and the opacity term zeroes the
     // partials of a lane that does not contribute.
     const float dq = shape ? dalpha * alpha : 0.f;
-    const float wh = hit ? w : 0.f;
     const float so = shape ? dalpha * Gv : 0.f;
     const float dK = c0 ? dy : dx, dS = c0 ? dx : dy;
     const float kA = dq * dK, sA = dq * dS;
@@ -605,7 +608,7 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
     acc[7] = c0 ? sxy : so;
     acc[8] = wh * gS0;
     acc[9] = wh * gS1;
-    Pp = hit ? Pn : Pp;
+    Pp = Pn;
     T = hit ? Tn : T;
     return hit;
   };
@@ -671,7 +674,7 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
       }
     }
   };
-  sweep<G, DEPTH, true>(s, rec, vals, rg, t, op, live,
+  sweep<G, DEPTH, true, true>(s, rec, vals, rg, t, op, live,
                         [&](int b0, bool go) {
                           if (b0 != rg.x) {
                             const int p0 = b0 - G::BATCH;

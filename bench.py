@@ -129,8 +129,8 @@ def kernel_label(tile):
     tw, th, dp, _, sg = tile
     if sg is not None and sg < 0:
         return f"k_render_bwd<{tw},{th},{dp},fused,loss> (forward sweep + loss + backward sweep)"
-    return (f"k_fused_main<{tw},{th},{dp},loss> + k_seg_stop + k_seg_combine + k_seg_bwd (forward sweep + loss + "
-            f"backward sweep; tile lists split into depth segments)")
+    return (f"k_fused_main<{tw},{th},{dp},loss> + k_seg_prefix + k_seg_stop + k_seg_combine + k_seg_bwd (forward "
+            f"sweep + loss + backward sweep; tile lists split into depth segments)")
 
 
 def dominant_kernel(res, steps):

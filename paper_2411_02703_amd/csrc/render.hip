@@ -620,21 +620,12 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
   const int x0_slot = c1 ? (c0 ? 7 : 6) : (c0 ? 1 : 0);
   const int x1_slot = c1 ? (c0 ? 9 : 8) : (c0 ? 4 : 2);
   const int x2_slot = c0 ? 5 : 3;
-  // sum the partials of one step into the records' LDS accumulators (whole wave; one record per block)
+  // Sum the partials of one step into the records' LDS accumulators (whole wave; one record per block).  The
+  // block reduction runs whenever any lane contributed: letting each contributing lane add its own ten
+  // partials when few do costs more in LDS atomics than the reduction (measured).
   auto post = [&](int j, bool hit, const float* acc) {
     const uint64_t hits = __ballot(hit);
     if (hits == 0) return;
-    if (__popcll(hits) <= 4) {
-      // few contributing lanes: each adds its own partials
-      if (hit) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-          atomicAdd(&gacc[slot_kept(k)][j], acc[k]);
-          atomicAdd(&gacc[slot_sent(k)][j], acc[5 + k]);
-        }
-      }
-      return;
-    }
     constexpr uint64_t BMASK = G::BL == 64 ? ~0ull : ((1ull << G::BL) - 1);
     const bool block_hit = ((hits >> t.blk_lane0) & BMASK) != 0;
     if (G::BW == 2 || G::BW == 4) {

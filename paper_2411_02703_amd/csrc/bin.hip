@@ -10,9 +10,9 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;  // 4096
 
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 keys per block
-constexpr int kWaveItems = kSortTile / 4;              // 1024 keys per wave
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;  // 2048 keys per block
+constexpr int kWaveItems = kSortTile / 4;              // 512 keys per wave
 
 // Exclusive scan of 256 values, one per thread; returns the exclusive prefix, *total = sum.
 __device__ __forceinline__ int block_scan_256(int x, int* sh_wave, int* total) {
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t* __re
   hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one 8-bit digit.  Each wave ranks its 1024 keys (16 rounds of 64) with ballot-based
+// Stable scatter of one 8-bit digit.  Each wave ranks its 512 keys (8 rounds of 64) with ballot-based
 // digit matching, the block orders them in LDS (digit-major, stable), then writes runs to their global
 // offsets from the scanned digit-major histogram.
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* __restrict__ kin,

@@ -22,8 +22,13 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
                                              float lr1, int period, float b1, float b2, float eps,
                                              const float* __restrict__ bias) {
   const float bc1 = bias[0], bc2s = bias[1];
+  const float s0 = lr0 / bc1, s1 = lr1 / bc1;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
-  for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i0 < n; i0 += stride) {
+  const int64_t first = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  // position of element i0 inside its period, kept up to date by additions (no division per element)
+  int r = period > 0 ? (int)(first % period) : 0;
+  const int rstep = period > 0 ? (int)(stride % period) : 0;
+  for (int64_t i0 = first; i0 < n; i0 += stride) {
     if (i0 + 4 <= n) {
       const float4 gg = *reinterpret_cast<const float4*>(g + i0);
       float4 mm = *reinterpret_cast<const float4*>(m + i0);
@@ -38,8 +43,10 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
         const float gk = pg[k];
         pm[k] = b1 * pm[k] + (1.f - b1) * gk;
         pv[k] = b2 * pv[k] + (1.f - b2) * gk * gk;
-        const float lr = (period > 0 && ((i0 + k) % period) >= 3) ? lr1 : lr0;
-        pq[k] -= (lr / bc1) * pm[k] / (sqrtf(pv[k]) / bc2s + eps);
+        int rk = r + k;  // < 2 period, since period >= 3
+        if (rk >= period) rk -= period;
+        const float s = (period > 0 && rk >= 3) ? s1 : s0;
+        pq[k] -= s * pm[k] / (sqrtf(pv[k]) / bc2s + eps);
       }
       *reinterpret_cast<float4*>(m + i0) = mm;
       *reinterpret_cast<float4*>(v + i0) = vv;
@@ -51,9 +58,13 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
         const float vk = b2 * v[i] + (1.f - b2) * gk * gk;
         m[i] = mk;
         v[i] = vk;
-        const float lr = (period > 0 && (i % period) >= 3) ? lr1 : lr0;
-        p[i] -= (lr / bc1) * mk / (sqrtf(vk) / bc2s + eps);
+        const float s = (period > 0 && (i % period) >= 3) ? s1 : s0;
+        p[i] -= s * mk / (sqrtf(vk) / bc2s + eps);
       }
+    }
+    if (period > 0) {
+      r += rstep;
+      if (r >= period) r -= period;
     }
   }
 }

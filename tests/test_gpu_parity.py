@@ -330,12 +330,17 @@ def test_batched_graph_step_matches_plain_step(gpu_lib):
     bat.run_eager()
     torch.cuda.synchronize()
     np.testing.assert_allclose(bat.loss(), plain.loss(), rtol=1e-5)
+    # The two orders of the LDS float additions differ, so gradients agree up to FP32 rounding of their terms
+    # (the rotation gradients of near-isotropic Gaussians are pure rounding); Adam's first step moves a
+    # parameter by about lr * sign(g), so parameters are compared where the sign is above that rounding.
+    scale = oracle.gradient_scale(sc.params(), 1, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
     for k in ma.g:
         a, b = ma.g[k].cpu().numpy(), mb.g[k].cpu().numpy()
-        rms = np.sqrt((a.astype(np.float64) ** 2).mean()) + 1e-30
-        assert np.all(np.abs(a - b) <= 1e-5 * (np.abs(a) + rms)), k
-    for k in ma.p:
-        np.testing.assert_allclose(mb.p[k].cpu().numpy(), ma.p[k].cpu().numpy(), rtol=1e-5, atol=1e-7)
+        rnd = ROUND_C * U32 * scale[k].reshape(a.shape)
+        assert np.all(np.abs(b.astype(np.float64) - a) <= 1e-5 * np.abs(a) + 2 * rnd), k
+        firm = (np.abs(a) > 4 * rnd) | (rnd == 0)  # rnd == 0: no term at all, the gradient is exactly 0
+        log(k, "parameters with a sign set by rounding:", int((~firm).sum()))
+        np.testing.assert_allclose(mb.p[k].cpu().numpy()[firm], ma.p[k].cpu().numpy()[firm], rtol=1e-5, atol=1e-7)
 
 
 def test_graph_replays_match_eager(gpu_lib):
@@ -346,14 +351,23 @@ def test_graph_replays_match_eager(gpu_lib):
     graph = BatchedStep(mg, sc.cams, sc.tgt_rgb, sc.tgt_depth)
     graph.capture()  # capture warms up with one eager step
     eager.run_eager()
+    # Adam moves a parameter by about lr * sign(g) per step, and the order of the LDS float additions varies
+    # from run to run: parameters are compared while every gradient they took had a sign set by more than
+    # FP32 rounding (the rotation gradients of near-isotropic Gaussians are pure rounding).
+    scale = oracle.gradient_scale(sc.params(), 2, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
+    rnd = {k: ROUND_C * U32 * scale[k].reshape(tuple(me.p[k].shape)) for k in me.p}
+    firm = {k: (np.abs(me.g[k].cpu().numpy()) > 8 * rnd[k]) | (rnd[k] == 0) for k in me.p}
     for it in range(4):
         eager.run_eager()
         graph.run()
         torch.cuda.synchronize()
         np.testing.assert_allclose(graph.loss(), eager.loss(), rtol=1e-5)
         for k in me.p:
-            np.testing.assert_allclose(mg.p[k].cpu().numpy(), me.p[k].cpu().numpy(), rtol=1e-5, atol=1e-6,
-                                       err_msg=f"replay {it} {k}")
+            firm[k] &= (np.abs(me.g[k].cpu().numpy()) > 8 * rnd[k]) | (rnd[k] == 0)
+            np.testing.assert_allclose(mg.p[k].cpu().numpy()[firm[k]], me.p[k].cpu().numpy()[firm[k]], rtol=1e-5,
+                                       atol=1e-6, err_msg=f"replay {it} {k}")
+        log(f"replay {it}: parameters compared", sum(int(f.sum()) for f in firm.values()), "of",
+            sum(f.size for f in firm.values()))
         _ = torch.ones(10, device="cuda").sum().item()  # eager work between replays
     assert not graph.overflowed()
 

@@ -479,10 +479,12 @@ def test_backward_identical_across_walk_options(gpu_lib, tile, depth, bw):
     ref = run_gpu(sc, targets=True, fused=True, bw=8, seg=-1)
     out = run_gpu(sc, targets=True, fused=True, tile=tile, depth=depth, bw=bw, seg=-1)
     np.testing.assert_allclose(out["loss"], ref["loss"], rtol=1e-6)
+    scale = oracle.gradient_scale(sc.params(), 1, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
     for k in ref["grads"]:
         a, b = ref["grads"][k], out["grads"][k]
         rms = np.sqrt((a.astype(np.float64) ** 2).mean()) + 1e-30
-        assert np.all(np.abs(a - b) <= 1e-5 * (np.abs(a) + rms)), k
+        rnd = ROUND_C * U32 * scale[k].reshape(a.shape)  # the LDS additions run in another order
+        assert np.all(np.abs(b.astype(np.float64) - a) <= 1e-5 * (np.abs(a) + rms) + 2 * rnd), k
 
 
 def test_tile_schedule_is_a_longest_first_permutation(gpu_lib):

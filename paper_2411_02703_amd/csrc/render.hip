@@ -282,7 +282,7 @@ __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, 
     int j0 = c * 32 + (m ? __builtin_ctz(m) : 0), j1 = 0;
     float4 A0 = s.A[j0], B0 = s.B[j0], C0 = s.C[j0], A1, B1, C1;
     auto one = [&](int j, const float4& A, const float4& B, const float4& C, int& jn, float4& An, float4& Bn,
-                   float4& Cn) {
+                   float4& Cn, bool check) {
       const bool active = m != 0 && live;
       m &= m - 1;
       jn = c * 32 + (m ? __builtin_ctz(m) : 0);
@@ -292,13 +292,13 @@ __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, 
       float acc[10];
       const bool hit = step(j, active, A, B, C, acc);
       if (SYNC) post(j, hit, acc);
-      if (ENDS && ((__ballot(live) >> t.blk_lane0) & BMASK) == 0) m = 0;
+      if (ENDS && check && ((__ballot(live) >> t.blk_lane0) & BMASK) == 0) m = 0;
     };
     auto more = [&]() { return SYNC ? __ballot(m != 0) != 0 : m != 0; };
     while (more()) {
-      one(j0, A0, B0, C0, j1, A1, B1, C1);
+      one(j0, A0, B0, C0, j1, A1, B1, C1, false);
       if (!more()) break;
-      one(j1, A1, B1, C1, j0, A0, B0, C0);
+      one(j1, A1, B1, C1, j0, A0, B0, C0, true);
     }
   }
 }

@@ -29,6 +29,7 @@ def lib() -> ctypes.CDLL:
         _lib = ctypes.CDLL(_build.ensure_built())
         D = ctypes.POINTER(ctypes.c_double)
         _lib.oracle_backward.restype = ctypes.c_double
+        _lib.oracle_reference.restype = ctypes.c_double
         _lib.oracle_loss.restype = ctypes.c_double
         _lib.oracle_bin.restype = ctypes.c_int64
     return _lib
@@ -169,6 +170,31 @@ def backward(prec: int, params, sh_degree: int, cams, g_rgb=None, g_depth=None, 
     return float(L), gr, exc.astype(bool), int(nn[0]), img
 
 
+def reference(params, sh_degree: int, cams, g_rgb=None, g_depth=None, g_vis=None, tgt_rgb=None, tgt_depth=None,
+              **opt_over) -> Dict[str, object]:
+    """The gradient reference of the tests: loss and gradients in FP64 along the FP32 decisions, with the flip
+    allowance of every gradient entry (the change the entry would see if one near-threshold decision -- a skip,
+    clamp or stop at a pixel, or the sign of an L1 term -- were taken the other way, summed over such
+    decisions), the Gaussians excused outright (a cull or colour-clamp decision near its threshold, or visible
+    in one precision only) and the count of pixels holding a near decision."""
+    P = _Params(params, sh_degree)
+    K = (sh_degree + 1) ** 2
+    shapes = dict(means=(P.n, 3), log_scales=(P.n, 3), quats=(P.n, 4), opacity=(P.n,), sh=(P.n, K, 3))
+    gr = {k: np.zeros(v) for k, v in shapes.items()}
+    al = {k: np.zeros(v) for k, v in shapes.items()}
+    exc = np.zeros(P.n, np.int8)
+    nn = np.zeros(1, np.int64)
+    img = _image_buffers(cams)
+    conv = lambda a: None if a is None else _f64(a)
+    g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth = map(conv, (g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth))
+    keys = ("means", "log_scales", "quats", "opacity", "sh")
+    L = lib().oracle_reference(*P.args(), _p(cams_array(cams)), ctypes.c_int(len(cams)), _p(opts_array(**opt_over)),
+                               _p(g_rgb), _p(g_depth), _p(g_vis), _p(tgt_rgb), _p(tgt_depth),
+                               *[_p(gr[k]) for k in keys], *[_p(al[k]) for k in keys], _p(exc), _p(nn),
+                               _p(img["rgb"]), _p(img["depth"]), _p(img["vis"]))
+    return dict(loss=float(L), grads=gr, allowance=al, excused=exc.astype(bool), near_pixels=int(nn[0]), images=img)
+
+
 def gradient_scale(params, sh_degree: int, cams, g_rgb=None, g_depth=None, g_vis=None, tgt_rgb=None,
                    tgt_depth=None, **opt_over) -> Dict[str, np.ndarray]:
     """Per gradient entry, the sum of the magnitudes of the terms it sums (FP64): an FP32 evaluation of the
@@ -214,3 +240,8 @@ def quat_to_rot(q) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the following oracle calls."""
+    lib().oracle_set_threads(ctypes.c_int(int(n)))

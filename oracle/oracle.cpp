@@ -26,9 +26,10 @@
 // bit for bit), double gives the reference for gradients.  The sort order of
 // records is always the FP32 depth bits, whatever the real type.
 //
-// Built with -O2 -ffp-contract=off -fno-fast-math (see oracle/build.py).
+// Built with -O3 -ffp-contract=off -fno-fast-math (see oracle/build.py).
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -391,9 +392,13 @@ struct PixelOut {
 template <class R>
 struct Contrib { int64_t rec; R alpha, G, T; bool clamped; };
 
+// A decision of one record at one pixel lying within its window of the threshold (kinds: bits of NEAR_*).
+enum { NEAR_CLAMP = 1, NEAR_SKIP = 2, NEAR_STOP = 4 };
+struct NearDec { int64_t rec; int kinds; };
+
 template <class R>
 PixelOut<R> composite_pixel(const Splat<R>* recs, const int64_t* order, int64_t n, R px, R py, const Opts& op,
-                            std::vector<Contrib<R>>* trace, std::vector<int64_t>* near_recs = nullptr) {
+                            std::vector<Contrib<R>>* trace, std::vector<NearDec>* near_recs = nullptr) {
   PixelOut<R> out;
   out.C[0] = out.C[1] = out.C[2] = 0;
   out.D = 0;
@@ -411,12 +416,14 @@ PixelOut<R> composite_pixel(const Splat<R>* recs, const int64_t* order, int64_t 
     R oG = s.o * G;
     bool clamped = oG > amax;
     R alpha = clamped ? amax : oG;
-    bool nr = std::fabs((double)oG - op.alpha_max) <= 1e-5 * op.alpha_max ||
-              std::fabs((double)alpha - op.alpha_min) <= 1e-5 * op.alpha_min;
-    if (!(alpha < amin)) nr = nr || std::fabs((double)(T * ((R)1 - alpha)) - op.t_min) <= op.stop_near * op.t_min;
-    if (nr) {
+    int kinds = 0;
+    if (std::fabs((double)oG - op.alpha_max) <= 1e-5 * op.alpha_max) kinds |= NEAR_CLAMP;
+    if (std::fabs((double)alpha - op.alpha_min) <= 1e-5 * op.alpha_min) kinds |= NEAR_SKIP;
+    if (!(alpha < amin) && std::fabs((double)(T * ((R)1 - alpha)) - op.t_min) <= op.stop_near * op.t_min)
+      kinds |= NEAR_STOP;
+    if (kinds) {
       out.near = true;
-      if (near_recs) near_recs->push_back(order[i]);
+      if (near_recs) near_recs->push_back(NearDec{order[i], kinds});
     }
     if (alpha < amin) continue;
     R Tn = T * ((R)1 - alpha);
@@ -500,7 +507,7 @@ std::vector<int64_t> brute_order(const Scene<R>& sc, int v) {
 // Render every pixel of every view.  mode 0 = brute force (the definition), 1 = tiled lists.
 template <class R>
 void render_all(const Scene<R>& sc, int mode, std::vector<PixelOut<R>>& out,
-                std::vector<std::vector<Contrib<R>>>* traces, std::vector<std::vector<int64_t>>* nears = nullptr) {
+                std::vector<std::vector<Contrib<R>>>* traces, std::vector<std::vector<NearDec>>* nears = nullptr) {
   out.resize(sc.total_px);
   if (traces) traces->assign(sc.total_px, {});
   if (nears) nears->assign(sc.total_px, {});
@@ -532,11 +539,16 @@ void render_all(const Scene<R>& sc, int mode, std::vector<PixelOut<R>>& out,
 // ---------------------------------------------------------------- loss
 // L = sum_v w_v [ mean_{3 P_v} |C - I| + lambda_d * mean_{valid} |D - D_lidar| ]  (eqs. L, Lc, Ld; reading R14)
 // Returns per-pixel upstream gradients g (5 per pixel: C0..C2, D, V) and the loss value.
+// near_sign[pix] has bit ch set (ch = 0..2 colour, 3 depth) where |C - I| is within the window of 0, where
+// the sign of the L1 gradient could go either way; gmag (optional) receives the magnitude of each upstream
+// gradient entry whatever its sign (the loss weight of that term).
 template <class R>
 double loss_and_grad(const Scene<R>& sc, const std::vector<PixelOut<R>>& img, const double* tgt_rgb,
-                     const double* tgt_depth, std::vector<double>& g, std::vector<char>& near_sign) {
+                     const double* tgt_depth, std::vector<double>& g, std::vector<char>& near_sign,
+                     std::vector<double>* gmag = nullptr) {
   g.assign((size_t)sc.total_px * 5, 0.0);
   near_sign.assign(sc.total_px, 0);
+  if (gmag) gmag->assign((size_t)sc.total_px * 5, 0.0);
   double L = 0;
   for (int v = 0; v < sc.V; ++v) {
     const Cam<R>& cam = sc.cams[v];
@@ -552,14 +564,16 @@ double loss_and_grad(const Scene<R>& sc, const std::vector<PixelOut<R>>& img, co
         double e = c - t;
         L += wrgb * std::fabs(e);
         g[pix * 5 + ch] = wrgb * (e > 0 ? 1.0 : (e < 0 ? -1.0 : 0.0));
-        if (std::fabs(e) <= 1e-5) near_sign[pix] = 1;
+        if (gmag) (*gmag)[pix * 5 + ch] = wrgb;
+        if (std::fabs(e) <= 1e-5) near_sign[pix] |= (char)(1 << ch);
       }
       double dt = tgt_depth[pix];
       if (dt > 0) {
         double e = (double)img[pix].D - dt;
         L += wd * std::fabs(e);
         g[pix * 5 + 3] = wd * (e > 0 ? 1.0 : (e < 0 ? -1.0 : 0.0));
-        if (std::fabs(e) <= 1e-5 * dt) near_sign[pix] = 1;
+        if (gmag) (*gmag)[pix * 5 + 3] = wd;
+        if (std::fabs(e) <= 1e-5 * dt) near_sign[pix] |= (char)8;
       }
     }
   }
@@ -568,6 +582,47 @@ double loss_and_grad(const Scene<R>& sc, const std::vector<PixelOut<R>>& img, co
 
 // ---------------------------------------------------------------- backward
 // Gradient per record: d mu_x, d mu_y, d a, d b, d c, d o, d rgb (3), d z.
+// One pixel's share: for each contributing record of its trace (front to back), the 10 partial derivatives of
+// the loss through this pixel, handed to emit(record, vals).  g5 = upstream gradients of (C0, C1, C2, D, V).
+template <class R, class Emit>
+void pixel_backward(const Scene<R>& sc, const std::vector<Contrib<R>>& tr, R T_final, const double* g5, R px, R py,
+                    Emit emit) {
+  const int n = (int)tr.size();
+  if (n == 0) return;
+  R gC[3] = {(R)g5[0], (R)g5[1], (R)g5[2]};
+  R gD = (R)g5[3], gV = (R)g5[4];
+  // suffix sums: what lies behind record i, including the background seen through T_final
+  std::vector<R> SC(3 * (n + 1)), SD(n + 1), SV(n + 1);
+  for (int ch = 0; ch < 3; ++ch) SC[3 * n + ch] = T_final * (R)sc.op.bg[ch];
+  SD[n] = 0;
+  SV[n] = 0;
+  for (int i = n - 1; i >= 0; --i) {
+    const Splat<R>& s = sc.splats[tr[i].rec];
+    R w = tr[i].alpha * tr[i].T;
+    for (int ch = 0; ch < 3; ++ch) SC[3 * i + ch] = SC[3 * (i + 1) + ch] + w * s.rgb[ch];
+    SD[i] = SD[i + 1] + w * s.z;
+    SV[i] = SV[i + 1] + w;
+  }
+  for (int i = 0; i < n; ++i) {
+    const Contrib<R>& c = tr[i];
+    const Splat<R>& s = sc.splats[c.rec];
+    R om = (R)1 - c.alpha;
+    // dL/dalpha_i = sum over channels g * (value_i T_i - behind_i / (1 - alpha_i))
+    R dalpha = 0;
+    for (int ch = 0; ch < 3; ++ch) dalpha += gC[ch] * (s.rgb[ch] * c.T - SC[3 * (i + 1) + ch] / om);
+    dalpha += gD * (s.z * c.T - SD[i + 1] / om);
+    dalpha += gV * (c.T - SV[i + 1] / om);
+    R w = c.alpha * c.T;
+    R dx = s.mx - px, dy = s.my - py;
+    R d_o = 0, dq = 0;
+    if (!c.clamped) { d_o = dalpha * c.G; dq = dalpha * c.alpha; }
+    R da = (R)-0.5 * dx * dx * dq, db = -dx * dy * dq, dc = (R)-0.5 * dy * dy * dq;
+    R dmx = -(s.a * dx + s.b * dy) * dq, dmy = -(s.c * dy + s.b * dx) * dq;
+    const R vals[10] = {dmx, dmy, da, db, dc, d_o, w * gC[0], w * gC[1], w * gC[2], w * gD};
+    emit(c.rec, vals);
+  }
+}
+
 template <class R>
 void composite_backward(const Scene<R>& sc, const std::vector<PixelOut<R>>& img,
                         const std::vector<std::vector<Contrib<R>>>& traces, const std::vector<double>& g,
@@ -579,46 +634,14 @@ void composite_backward(const Scene<R>& sc, const std::vector<PixelOut<R>>& img,
     for (int y = 0; y < cam.H; ++y)
       for (int x = 0; x < cam.W; ++x) {
         int64_t pix = cam.pixel_offset + (int64_t)y * cam.W + x;
-        const std::vector<Contrib<R>>& tr = traces[pix];
-        int n = (int)tr.size();
-        if (n == 0) continue;
-        R gC[3] = {(R)g[pix * 5 + 0], (R)g[pix * 5 + 1], (R)g[pix * 5 + 2]};
-        R gD = (R)g[pix * 5 + 3], gV = (R)g[pix * 5 + 4];
-        // suffix sums: what lies behind record i, including the background seen through T_final
-        std::vector<R> SC(3 * (n + 1)), SD(n + 1), SV(n + 1);
-        for (int ch = 0; ch < 3; ++ch) SC[3 * n + ch] = img[pix].T * (R)sc.op.bg[ch];
-        SD[n] = 0;
-        SV[n] = 0;
-        for (int i = n - 1; i >= 0; --i) {
-          const Splat<R>& s = sc.splats[tr[i].rec];
-          R w = tr[i].alpha * tr[i].T;
-          for (int ch = 0; ch < 3; ++ch) SC[3 * i + ch] = SC[3 * (i + 1) + ch] + w * s.rgb[ch];
-          SD[i] = SD[i + 1] + w * s.z;
-          SV[i] = SV[i + 1] + w;
-        }
-        R px = (R)x + (R)0.5, py = (R)y + (R)0.5;
-        for (int i = 0; i < n; ++i) {
-          const Contrib<R>& c = tr[i];
-          const Splat<R>& s = sc.splats[c.rec];
-          R om = (R)1 - c.alpha;
-          // dL/dalpha_i = sum over channels g * (value_i T_i - behind_i / (1 - alpha_i))
-          R dalpha = 0;
-          for (int ch = 0; ch < 3; ++ch) dalpha += gC[ch] * (s.rgb[ch] * c.T - SC[3 * (i + 1) + ch] / om);
-          dalpha += gD * (s.z * c.T - SD[i + 1] / om);
-          dalpha += gV * (c.T - SV[i + 1] / om);
-          R w = c.alpha * c.T;
-          R* gr = &grec[(size_t)c.rec * 10];
-          R dx = s.mx - px, dy = s.my - py;
-          R d_o = 0, dq = 0;
-          if (!c.clamped) { d_o = dalpha * c.G; dq = dalpha * c.alpha; }
-          R da = (R)-0.5 * dx * dx * dq, db = -dx * dy * dq, dc = (R)-0.5 * dy * dy * dq;
-          R dmx = -(s.a * dx + s.b * dy) * dq, dmy = -(s.c * dy + s.b * dx) * dq;
-          R vals[10] = {dmx, dmy, da, db, dc, d_o, w * gC[0], w * gC[1], w * gC[2], w * gD};
-          for (int k = 0; k < 10; ++k) {
+        pixel_backward<R>(sc, traces[pix], img[pix].T, &g[pix * 5], (R)x + (R)0.5, (R)y + (R)0.5,
+                          [&](int64_t rec, const R* vals) {
+                            R* gr = &grec[(size_t)rec * 10];
+                            for (int k = 0; k < 10; ++k) {
 #pragma omp atomic
-            gr[k] += vals[k];
-          }
-        }
+                              gr[k] += vals[k];
+                            }
+                          });
       }
   }
 }
@@ -901,6 +924,35 @@ void project_backward_abs(const Scene<double>& sc, const double* sh, const std::
   }
 }
 
+// Record-level bounds carried to the parameters through the projection backward's Jacobian taken entry by
+// entry in absolute value: out_param += sum_k |d param gradient / d record partial k| * arec[k].  A bound on
+// |J x| for any x with |x_k| <= arec[k], exact when one component dominates.
+void project_backward_jac_abs(const Scene<double>& sc, const double* sh, const std::vector<double>& arec,
+                              double* omean, double* oscale, double* oquat, double* oopac, double* osh) {
+  const int K = sc.K;
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t g = 0; g < sc.N; ++g) {
+    std::vector<double> f((size_t)K * 3);
+    for (int v = 0; v < sc.V; ++v) {
+      const int64_t r = (int64_t)v * sc.N + g;
+      if (!sc.proj[r].vis) continue;
+      const double* a = &arec[(size_t)r * 10];
+      for (int k = 0; k < 10; ++k) {
+        if (a[k] == 0) continue;
+        double e[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        e[k] = 1;
+        double dm[3] = {0, 0, 0}, ds[3] = {0, 0, 0}, dq[4] = {0, 0, 0, 0}, dop[1] = {0};
+        std::fill(f.begin(), f.end(), 0.0);
+        project_backward_one<double>(sc.proj[r], sc.cams[v], sh, K, g, e, dm, ds, dq, dop, f.data());
+        for (int i = 0; i < 3; ++i) { omean[g * 3 + i] += a[k] * std::fabs(dm[i]); oscale[g * 3 + i] += a[k] * std::fabs(ds[i]); }
+        for (int i = 0; i < 4; ++i) oquat[g * 4 + i] += a[k] * std::fabs(dq[i]);
+        oopac[g] += a[k] * std::fabs(dop[0]);
+        for (int i = 0; i < K * 3; ++i) osh[g * K * 3 + i] += a[k] * std::fabs(f[i]);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- FP64 values along FP32 decisions
 // Every discrete choice of the path (cull, tile rectangle, skip, clamp, stop, colour clamp, loss sign) is
 // taken by FP32 arithmetic where the path runs in FP32; near a threshold an FP64 evaluation may choose the
@@ -912,11 +964,42 @@ struct Mixed {
   Scene<double> sd;  // values; proj[r].vis = visible in both precisions, pass[] taken from FP32
   std::vector<PixelOut<float>> imf;
   std::vector<std::vector<Contrib<float>>> tf;
-  std::vector<std::vector<int64_t>> nears;
+  std::vector<std::vector<NearDec>> nears;
   std::vector<PixelOut<double>> img;
   std::vector<std::vector<Contrib<double>>> traces;
   std::vector<char> split_vis;  // [V*N] visible in exactly one precision (near its cull threshold)
 };
+
+// FP64 values along one pixel's FP32 trace: the same contributing records in the same order with the same
+// clamp decisions, alpha, G and transmittance recomputed in FP64.  A record visible in FP32 only is dropped
+// (returns false; such records are excused by the callers).
+bool values_along(const Scene<double>& sc, const std::vector<Contrib<float>>& tr32, double px, double py,
+                  PixelOut<double>& o, std::vector<Contrib<double>>& tr) {
+  o.C[0] = o.C[1] = o.C[2] = o.D = o.Vis = 0;
+  o.n_contrib = 0;
+  o.near = false;
+  tr.clear();
+  bool whole = true;
+  double T = 1;
+  const double amax = sc.op.alpha_max;
+  for (const Contrib<float>& c : tr32) {
+    if (!sc.proj[c.rec].vis) { whole = false; continue; }
+    const Splat<double>& s = sc.splats[c.rec];
+    double dx = s.mx - px, dy = s.my - py;
+    double G = std::exp(-0.5 * (s.a * dx * dx + s.c * dy * dy) - s.b * dx * dy);
+    double alpha = c.clamped ? amax : s.o * G;
+    double w = alpha * T;
+    for (int ch = 0; ch < 3; ++ch) o.C[ch] += w * s.rgb[ch];
+    o.D += w * s.z;
+    o.Vis += w;
+    tr.push_back(Contrib<double>{c.rec, alpha, G, T, c.clamped});
+    T *= 1.0 - alpha;
+    o.n_contrib++;
+  }
+  for (int ch = 0; ch < 3; ++ch) o.C[ch] += T * sc.op.bg[ch];
+  o.T = T;
+  return whole;
+}
 
 void build_mixed(Mixed& m, const double* means, const double* log_scales, const double* quats, const double* opac,
                  const double* sh, int64_t N, int deg, const double* cams, int V, const double* opts) {
@@ -937,34 +1020,147 @@ void build_mixed(Mixed& m, const double* means, const double* log_scales, const 
   const Scene<double>& sc = m.sd;
   m.img.resize(sc.total_px);
   m.traces.assign(sc.total_px, {});
-  const double amax = sc.op.alpha_max;
   for (int v = 0; v < V; ++v) {
     const Cam<double>& cam = sc.cams[v];
 #pragma omp parallel for schedule(dynamic, 4)
     for (int y = 0; y < cam.H; ++y)
       for (int x = 0; x < cam.W; ++x) {
         int64_t pix = cam.pixel_offset + (int64_t)y * cam.W + x;
-        PixelOut<double>& o = m.img[pix];
-        o.C[0] = o.C[1] = o.C[2] = o.D = o.Vis = 0;
-        o.n_contrib = 0;
-        o.near = m.imf[pix].near;
-        double T = 1, px = x + 0.5, py = y + 0.5;
-        for (const Contrib<float>& c : m.tf[pix]) {
-          if (!sc.proj[c.rec].vis) { o.near = true; continue; }
-          const Splat<double>& s = sc.splats[c.rec];
-          double dx = s.mx - px, dy = s.my - py;
-          double G = std::exp(-0.5 * (s.a * dx * dx + s.c * dy * dy) - s.b * dx * dy);
-          double alpha = c.clamped ? amax : s.o * G;
-          double w = alpha * T;
-          for (int ch = 0; ch < 3; ++ch) o.C[ch] += w * s.rgb[ch];
-          o.D += w * s.z;
-          o.Vis += w;
-          m.traces[pix].push_back(Contrib<double>{c.rec, alpha, G, T, c.clamped});
-          T *= 1.0 - alpha;
-          o.n_contrib++;
+        const bool whole = values_along(sc, m.tf[pix], x + 0.5, y + 0.5, m.img[pix], m.traces[pix]);
+        m.img[pix].near = m.imf[pix].near || !whole;
+      }
+  }
+}
+
+// The FP32 trace of one pixel with one near decision of record `frec` taken the other way (kind: one NEAR_*
+// bit): the clamp of alpha at alpha_max, the skip below alpha_min, or the stop before T < t_min.  Every other
+// decision is evaluated as usual, so the consequences of the flip (a later stop moving) follow.
+std::vector<Contrib<float>> trace_flipped(const Splat<float>* recs, const int64_t* order, int64_t n, float px,
+                                          float py, const Opts& op, int64_t frec, int kind) {
+  std::vector<Contrib<float>> tr;
+  float T = 1;
+  const float amin = (float)op.alpha_min, amax = (float)op.alpha_max, tmin = (float)op.t_min;
+  for (int64_t i = 0; i < n; ++i) {
+    const Splat<float>& s = recs[order[i]];
+    const bool here = order[i] == frec;
+    float dx = s.mx - px, dy = s.my - py;
+    float power = -0.5f * (s.a * dx * dx + s.c * dy * dy) - s.b * dx * dy;
+    if (power > 0) continue;
+    float G = std::exp(power);
+    float oG = s.o * G;
+    bool clamped = oG > amax;
+    if (here && (kind & NEAR_CLAMP)) clamped = !clamped;
+    float alpha = clamped ? amax : oG;
+    bool skip = alpha < amin;
+    if (here && (kind & NEAR_SKIP)) skip = !skip;
+    if (skip) continue;
+    float Tn = T * (1.f - alpha);
+    bool stop = Tn < tmin;
+    if (here && (kind & NEAR_STOP)) stop = !stop;
+    if (stop) break;
+    tr.push_back(Contrib<float>{order[i], alpha, G, T, clamped});
+    T = Tn;
+  }
+  return tr;
+}
+
+// The tile list of pixel (x, y) of view v: [*ord, *ord + *n).
+template <class R>
+void pixel_list(const Scene<R>& sc, const std::vector<int64_t>& vals, int v, int x, int y, const int64_t** ord,
+                int64_t* n) {
+  const Cam<R>& cam = sc.cams[v];
+  const int t = cam.tile_offset + (y / sc.op.tile_h) * cam.tiles_x + (x / sc.op.tile_w);
+  *ord = vals.data() + sc.bins.range_lo[t];
+  *n = sc.bins.range_hi[t] - sc.bins.range_lo[t];
+}
+
+// Flip allowance of the gradient reference (test tolerance).  A decision within its window of a threshold (a
+// skip, clamp or stop, or the sign of an L1 term) may be taken the other way by an FP32 evaluation whose
+// rounding differs from the oracle's; the gradient then changes by a whole term, not by rounding.  For every
+// such decision, per record, the absolute change of the pixel's 10 record partials when that decision alone is
+// flipped (the pixel recomputed along the flipped FP32 decisions with FP64 values; a flipped L1 sign changes
+// that term's upstream gradient by twice its weight), summed over the decisions: `allow` [V*N*10].
+void flip_allowance(const Mixed& m, const std::vector<double>& g, const std::vector<char>& near_sign,
+                    const std::vector<double>& gmag, std::vector<double>& allow) {
+  const Scene<double>& sc = m.sd;
+  const Scene<float>& sf = m.sf;
+  allow.assign((size_t)sc.V * sc.N * 10, 0.0);
+  std::vector<int64_t> vals(sf.bins.vals.begin(), sf.bins.vals.end());
+  auto add = [&](int64_t rec, const double* d, double f) {
+    double* a = &allow[(size_t)rec * 10];
+    for (int k = 0; k < 10; ++k) {
+      const double x = f * std::fabs(d[k]);
+#pragma omp atomic
+      a[k] += x;
+    }
+  };
+  for (int v = 0; v < sc.V; ++v) {
+    const Cam<double>& cam = sc.cams[v];
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int y = 0; y < cam.H; ++y)
+      for (int x = 0; x < cam.W; ++x) {
+        const int64_t pix = cam.pixel_offset + (int64_t)y * cam.W + x;
+        const char ns = gmag.empty() ? 0 : near_sign[pix];
+        if (m.nears[pix].empty() && !ns) continue;
+        const double px = x + 0.5, py = y + 0.5;
+        // L1 signs: the upstream gradient of the term changes by twice its weight; the partials are linear in it
+        for (int ch = 0; ch < 4; ++ch) {
+          if (!((ns >> ch) & 1)) continue;
+          double g5[5] = {0, 0, 0, 0, 0};
+          g5[ch] = gmag[pix * 5 + ch];
+          pixel_backward<double>(sc, m.traces[pix], m.img[pix].T, g5, px, py,
+                                 [&](int64_t rec, const double* d) { add(rec, d, 2.0); });
         }
-        for (int ch = 0; ch < 3; ++ch) o.C[ch] += T * sc.op.bg[ch];
-        o.T = T;
+        if (m.nears[pix].empty()) continue;
+        // the pixel's partials along the oracle's decisions
+        std::vector<std::pair<int64_t, std::array<double, 10>>> base;
+        pixel_backward<double>(sc, m.traces[pix], m.img[pix].T, &g[pix * 5], px, py,
+                               [&](int64_t rec, const double* d) {
+                                 std::array<double, 10> a;
+                                 for (int k = 0; k < 10; ++k) a[k] = d[k];
+                                 base.emplace_back(rec, a);
+                               });
+        std::sort(base.begin(), base.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+        const int64_t* ord;
+        int64_t n;
+        pixel_list(sf, vals, v, x, y, &ord, &n);
+        for (const NearDec& nd : m.nears[pix])
+          for (int kind = NEAR_CLAMP; kind <= NEAR_STOP; kind <<= 1) {
+            if (!(nd.kinds & kind)) continue;
+            std::vector<Contrib<float>> tf = trace_flipped(sf.splats.data(), ord, n, (float)px, (float)py, sf.op,
+                                                           nd.rec, kind);
+            PixelOut<double> o;
+            std::vector<Contrib<double>> tr;
+            values_along(sc, tf, px, py, o, tr);
+            std::vector<std::pair<int64_t, std::array<double, 10>>> alt;
+            pixel_backward<double>(sc, tr, o.T, &g[pix * 5], px, py, [&](int64_t rec, const double* d) {
+              std::array<double, 10> a;
+              for (int k = 0; k < 10; ++k) a[k] = d[k];
+              alt.emplace_back(rec, a);
+            });
+            std::sort(alt.begin(), alt.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+            // |alt - base| over the union of the two record sets
+            size_t i = 0, j = 0;
+            while (i < base.size() || j < alt.size()) {
+              double d[10];
+              int64_t rec;
+              if (j == alt.size() || (i < base.size() && base[i].first < alt[j].first)) {
+                rec = base[i].first;
+                for (int k = 0; k < 10; ++k) d[k] = base[i].second[k];
+                ++i;
+              } else if (i == base.size() || alt[j].first < base[i].first) {
+                rec = alt[j].first;
+                for (int k = 0; k < 10; ++k) d[k] = alt[j].second[k];
+                ++j;
+              } else {
+                rec = base[i].first;
+                for (int k = 0; k < 10; ++k) d[k] = alt[j].second[k] - base[i].second[k];
+                ++i;
+                ++j;
+              }
+              add(rec, d, 1.0);
+            }
+          }
       }
   }
 }
@@ -972,12 +1168,12 @@ void build_mixed(Mixed& m, const double* means, const double* log_scales, const 
 // Upstream gradients for the mixed reference: loss signs from the FP32 image, loss value from the FP64 one.
 double mixed_upstream(const Mixed& m, const double* g_rgb, const double* g_depth, const double* g_vis,
                       const double* tgt_rgb, const double* tgt_depth, std::vector<double>& g,
-                      std::vector<char>& near_sign) {
+                      std::vector<char>& near_sign, std::vector<double>* gmag = nullptr) {
   if (!tgt_rgb) return upstream<double>(m.sd, m.img, g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth, g, near_sign);
   std::vector<double> g64;
   std::vector<char> ns64;
   double L = loss_and_grad<double>(m.sd, m.img, tgt_rgb, tgt_depth, g64, ns64);
-  loss_and_grad<float>(m.sf, m.imf, tgt_rgb, tgt_depth, g, near_sign);
+  loss_and_grad<float>(m.sf, m.imf, tgt_rgb, tgt_depth, g, near_sign, gmag);
   return L;
 }
 
@@ -986,26 +1182,42 @@ double backward_mixed(const double* means, const double* log_scales, const doubl
                       const double* g_rgb, const double* g_depth, const double* g_vis, const double* tgt_rgb,
                       const double* tgt_depth, double* gmean, double* gscale, double* gquat, double* gopac,
                       double* gsh, int8_t* excused_gauss, int64_t* n_near_pixels, double* rgb, double* depth,
-                      double* vis) {
+                      double* vis, double* const* allow_out = nullptr) {
   Mixed m;
   build_mixed(m, means, log_scales, quats, opac, sh, N, deg, cams, V, opts);
-  std::vector<double> g;
+  std::vector<double> g, gmag;
   std::vector<char> near_sign;
-  double L = mixed_upstream(m, g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth, g, near_sign);
+  double L = mixed_upstream(m, g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth, g, near_sign, &gmag);
   std::vector<double> grec;
   composite_backward<double>(m.sd, m.img, m.traces, g, grec);
   project_backward_all<double>(m.sd, sh, grec, gmean, gscale, gquat, gopac, gsh);
-  // Excusal as in backward_impl, judged on the FP32 evaluation (whose rounding the compared path shares up to
-  // the order of operations), plus Gaussians visible in one precision only.
+  if (allow_out) {
+    // per-parameter flip allowance: the record allowances carried through the projection backward's Jacobian
+    std::vector<double> arec;
+    flip_allowance(m, g, near_sign, gmag, arec);
+    const int K = m.sd.K;
+    std::memset(allow_out[0], 0, sizeof(double) * 3 * N);
+    std::memset(allow_out[1], 0, sizeof(double) * 3 * N);
+    std::memset(allow_out[2], 0, sizeof(double) * 4 * N);
+    std::memset(allow_out[3], 0, sizeof(double) * N);
+    std::memset(allow_out[4], 0, sizeof(double) * 3 * K * N);
+    project_backward_jac_abs(m.sd, sh, arec, allow_out[0], allow_out[1], allow_out[2], allow_out[3],
+                             allow_out[4]);
+  }
+  // Excusal, judged on the FP32 evaluation (whose rounding the compared path shares up to the order of
+  // operations): Gaussians visible in one precision only or with a cull or colour-clamp decision near its
+  // threshold; without the flip allowance also every record with a near decision at a pixel and every
+  // contributor of such a pixel.
   int64_t nn = 0;
+  for (int64_t pix = 0; pix < m.sd.total_px; ++pix) nn += (m.img[pix].near || near_sign[pix]) ? 1 : 0;
   if (excused_gauss) {
     std::memset(excused_gauss, 0, (size_t)N);
-    for (int64_t pix = 0; pix < m.sd.total_px; ++pix) {
-      if (!(m.img[pix].near || near_sign[pix])) continue;
-      ++nn;
-      for (const auto& c : m.tf[pix]) excused_gauss[c.rec % N] = 1;
-      for (int64_t r : m.nears[pix]) excused_gauss[r % N] = 1;
-    }
+    if (!allow_out)
+      for (int64_t pix = 0; pix < m.sd.total_px; ++pix) {
+        if (!(m.img[pix].near || near_sign[pix])) continue;
+        for (const auto& c : m.tf[pix]) excused_gauss[c.rec % N] = 1;
+        for (const NearDec& d : m.nears[pix]) excused_gauss[d.rec % N] = 1;
+      }
     for (int64_t r = 0; r < (int64_t)V * N; ++r) {
       const Proj<float>& p = m.sf.proj[r];
       if (m.split_vis[r] || p.near_margin <= 1e-5 || (p.vis && p.rgb_margin <= 1e-5)) excused_gauss[r % N] = 1;
@@ -1060,7 +1272,7 @@ double backward_impl(const double* means, const double* log_scales, const double
   build_scene<R>(sc, means, log_scales, quats, opac, sh, N, deg, cams, V, opts);
   std::vector<PixelOut<R>> img;
   std::vector<std::vector<Contrib<R>>> traces;
-  std::vector<std::vector<int64_t>> nears;
+  std::vector<std::vector<NearDec>> nears;
   render_all<R>(sc, 1, img, &traces, &nears);
   std::vector<double> g;
   std::vector<char> near_sign;
@@ -1079,7 +1291,7 @@ double backward_impl(const double* means, const double* log_scales, const double
       if (!nr) continue;
       ++nn;
       for (const auto& c : traces[pix]) excused_gauss[c.rec % N] = 1;
-      for (int64_t r : nears[pix]) excused_gauss[r % N] = 1;
+      for (const NearDec& d : nears[pix]) excused_gauss[d.rec % N] = 1;
     }
     for (int64_t r = 0; r < (int64_t)V * N; ++r) {
       const Proj<R>& p = sc.proj[r];
@@ -1277,6 +1489,30 @@ double oracle_backward(int prec, const double* means, const double* log_scales, 
   return backward_impl<double>(means, log_scales, quats, opac, sh, N, deg, cams, V, opts, g_rgb, g_depth, g_vis,
                                tgt_rgb, tgt_depth, gmean, gscale, gquat, gopac, gsh, excused, n_near_pixels, rgb,
                                depth, vis);
+}
+
+// The gradient reference of the tests: FP64 values along FP32 decisions (as oracle_backward with the mixed
+// precision code) plus, per gradient entry, the flip allowance (allow_*, shapes of the gradients): the change
+// the entry would see if one decision within its window of a threshold were taken the other way, summed over
+// such decisions.  `excused` then marks only Gaussians with a cull or colour-clamp decision near its threshold
+// or visible in one precision only.
+double oracle_reference(const double* means, const double* log_scales, const double* quats, const double* opac,
+                        const double* sh, int64_t N, int deg, const double* cams, int V, const double* opts,
+                        const double* g_rgb, const double* g_depth, const double* g_vis, const double* tgt_rgb,
+                        const double* tgt_depth, double* gmean, double* gscale, double* gquat, double* gopac,
+                        double* gsh, double* amean, double* ascale, double* aquat, double* aopac, double* ash,
+                        int8_t* excused, int64_t* n_near_pixels, double* rgb, double* depth, double* vis) {
+  double* const allow[5] = {amean, ascale, aquat, aopac, ash};
+  return backward_mixed(means, log_scales, quats, opac, sh, N, deg, cams, V, opts, g_rgb, g_depth, g_vis, tgt_rgb,
+                        tgt_depth, gmean, gscale, gquat, gopac, gsh, excused, n_near_pixels, rgb, depth, vis, allow);
+}
+
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
 }
 
 // Loss value only (FP64), for finite differences.

@@ -27,8 +27,9 @@
  *              vector from the camera centre to the mean.
  *
  * Memory and ownership: every pointer is a device pointer unless marked (host).  The caller owns all
- * memory.  The library never allocates or frees device memory and keeps no device state; the
- * per-iteration intermediates live in a caller-provided "frame" block that gs_frame_init carves.
+ * memory.  The library never allocates or frees device memory and keeps no device state (apart from the
+ * static scratch array of gs_sort_pairs_static); the per-iteration intermediates live in a caller-provided
+ * "frame" block that gs_frame_init carves.
  * Every call is asynchronous on `stream` (a hipStream_t) and can be captured in a HIP graph, except the
  * two calls documented as synchronising.  Calls on different streams need disjoint frames.
  *
@@ -270,6 +271,17 @@ int gs_read_counters(const gs_frame* frame, int64_t* n_instances, int32_t* flags
 size_t gs_sort_scratch_ints(int64_t n);
 int gs_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys_tmp, int32_t* vals_tmp, int64_t n,
                   int32_t key_bits, int32_t* scratch, void* stream);
+
+/* The same sort for callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the ping-pong buffers and histograms live in a static device array
+ * of the library (about 13.6 MB, one copy per GPU, held until the process ends), so the caller passes only
+ * keys/vals, sorted in place.  n is limited to gs_sort_static_max() pairs (2^20); larger n returns
+ * GS_ERR_ARG before anything is enqueued.  The call allocates nothing.  `stream` must belong to the current
+ * device.  Every call on a GPU shares that GPU's array: calls that overlap on one GPU (on different streams,
+ * or from several threads) race and must be serialised by the caller.  No part of the array needs clearing
+ * between calls (every pass rewrites what it reads). */
+int64_t gs_sort_static_max(void);
+int gs_sort_pairs_static(uint64_t* keys, int32_t* vals, int64_t n, int32_t key_bits, void* stream);
 
 const char* gs_status_string(int status);
 const char* gs_last_error(void);

@@ -76,7 +76,8 @@ GS_FLAG_NONFINITE = 2
 
 EXPORTED = ["gs_default_opts", "gs_plan_cameras", "gs_frame_bytes", "gs_frame_init", "gs_project", "gs_bin_tiles",
             "gs_render_fwd", "gs_render_bwd", "gs_composite_bwd", "gs_project_bwd", "gs_adam_step",
-            "gs_count_pairs", "gs_read_counters", "gs_sort_scratch_ints", "gs_sort_pairs", "gs_status_string",
+            "gs_count_pairs", "gs_read_counters", "gs_sort_scratch_ints", "gs_sort_pairs", "gs_sort_static_max",
+            "gs_sort_pairs_static", "gs_status_string",
             "gs_last_error", "gs_version"]
 
 _lib: Optional[ctypes.CDLL] = None
@@ -110,6 +111,9 @@ def load() -> ctypes.CDLL:
     lib.gs_sort_scratch_ints.argtypes = [c_i64]
     lib.gs_sort_scratch_ints.restype = ctypes.c_size_t
     lib.gs_sort_pairs.argtypes = [c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, c_vp, c_vp]
+    lib.gs_sort_static_max.argtypes = []
+    lib.gs_sort_static_max.restype = c_i64
+    lib.gs_sort_pairs_static.argtypes = [c_vp, c_vp, c_i64, c_i32, c_vp]
     lib.gs_status_string.argtypes = [ctypes.c_int]
     lib.gs_status_string.restype = ctypes.c_char_p
     lib.gs_last_error.argtypes = []
@@ -302,6 +306,19 @@ def gs_sort_pairs(keys: torch.Tensor, vals: torch.Tensor, key_bits: int, stream=
     scratch = torch.empty(int(load().gs_sort_scratch_ints(n)) + 64, dtype=torch.int32, device=keys.device)
     _check(load().gs_sort_pairs(keys.data_ptr(), vals.data_ptr(), kt.data_ptr(), vt.data_ptr(), n, int(key_bits),
                                 scratch.data_ptr(), _stream(stream)), "gs_sort_pairs")
+
+
+def gs_sort_static_max() -> int:
+    return int(load().gs_sort_static_max())
+
+
+def gs_sort_pairs_static(keys: torch.Tensor, vals: torch.Tensor, key_bits: int, stream=None) -> None:
+    """The same sort in place with the library's static scratch array (allocates nothing)."""
+    if not (keys.is_cuda and keys.dtype == torch.int64 and keys.is_contiguous() and vals.dtype == torch.int32
+            and vals.is_contiguous() and vals.numel() == keys.numel()):
+        raise ValueError("keys must be contiguous int64 and vals contiguous int32 CUDA tensors of equal length")
+    _check(load().gs_sort_pairs_static(keys.data_ptr(), vals.data_ptr(), keys.numel(), int(key_bits),
+                                       _stream(stream)), "gs_sort_pairs_static")
 
 
 # --------------------------------------------------------------------------- frame views (torch, zero-copy)

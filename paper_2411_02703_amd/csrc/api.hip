@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "common.h"
@@ -143,6 +144,42 @@ int params_check(const gs_params* p, const char* what) {
 
 int frame_check(const gs_frame* f) {
   if (!f || !f->block || !f->cams) return fail(GS_ERR_ARG, "frame not initialised");
+  return GS_OK;
+}
+
+// ------------------------------------------------------------------ static sort scratch (no allocation)
+// Ping-pong key/value buffers and digit histograms of gs_sort_pairs_static, for callers that cannot allocate.
+// Each GPU the library runs on holds its own copy of this array until the process ends.
+constexpr int64_t kStaticSortMax = int64_t(1) << 20;             // pairs
+constexpr size_t kStaticKeysOff = 0;                             // uint64_t[kStaticSortMax]
+constexpr size_t kStaticValsOff = kStaticKeysOff + 8 * kStaticSortMax;  // int32_t[kStaticSortMax]
+constexpr size_t kStaticHistOff = kStaticValsOff + 4 * kStaticSortMax;  // int32_t histograms and scan partials
+constexpr size_t kStaticBytes = kStaticHistOff + (size_t(1) << 20);
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's copy of `scratch`, looked up once per device with that device current.
+int static_scratch(hipStream_t st, unsigned char** out) {
+  int dev = -1;
+  GS_HIP(hipGetDevice(&dev), "gs_sort_pairs_static: current device");
+  if (dev < 0 || dev >= kMaxDevices) return fail(GS_ERR_UNSUPPORTED, "device %d beyond %d devices", dev, kMaxDevices);
+  if (st != nullptr) {
+    hipDevice_t sdev = -1;
+    GS_HIP(hipStreamGetDevice(st, &sdev), "gs_sort_pairs_static: stream device");
+    if (sdev != dev) return fail(GS_ERR_ARG, "the stream belongs to device %d, the current device is %d", sdev, dev);
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    GS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "gs_sort_pairs_static: scratch address");
+    if (!p) return fail(GS_ERR_HIP, "gs_sort_pairs_static: no device address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
   return GS_OK;
 }
 
@@ -404,6 +441,33 @@ int gs_sort_pairs(uint64_t* keys, int32_t* vals, uint64_t* keys_tmp, int32_t* va
   if (passes & 1) {
     GS_HIP(hipMemcpyAsync(keys, keys_tmp, (size_t)n * 8, hipMemcpyDeviceToDevice, st), "gs_sort_pairs: copy keys");
     GS_HIP(hipMemcpyAsync(vals, vals_tmp, (size_t)n * 4, hipMemcpyDeviceToDevice, st), "gs_sort_pairs: copy vals");
+  }
+  return GS_OK;
+}
+
+int64_t gs_sort_static_max(void) { return kStaticSortMax; }
+
+int gs_sort_pairs_static(uint64_t* keys, int32_t* vals, int64_t n, int32_t key_bits, void* stream) {
+  if (!keys || !vals) return fail(GS_ERR_ARG, "NULL buffer");
+  if (n < 0 || n > kStaticSortMax)
+    return fail(GS_ERR_ARG, "n = %lld outside [0, %lld] (the static scratch holds %lld pairs)", (long long)n,
+                (long long)kStaticSortMax, (long long)kStaticSortMax);
+  if (key_bits < 1 || key_bits > 64) return fail(GS_ERR_ARG, "key_bits = %d", key_bits);
+  if (gs_launch::sort_scratch_ints(kStaticSortMax) * 4 > kStaticBytes - kStaticHistOff)
+    return fail(GS_ERR_UNSUPPORTED, "static sort scratch too small for its histograms");
+  if (n == 0) return GS_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned char* base = nullptr;
+  int rc = static_scratch(st, &base);
+  if (rc) return rc;
+  auto* ktmp = reinterpret_cast<uint64_t*>(base + kStaticKeysOff);
+  auto* vtmp = reinterpret_cast<int32_t*>(base + kStaticValsOff);
+  auto* hist = reinterpret_cast<int32_t*>(base + kStaticHistOff);
+  const int passes = (key_bits + 7) / 8;
+  GS_HIP(gs_launch::sort_pairs(keys, vals, ktmp, vtmp, n, nullptr, n, key_bits, hist, st), "gs_sort_pairs_static");
+  if (passes & 1) {
+    GS_HIP(hipMemcpyAsync(keys, ktmp, (size_t)n * 8, hipMemcpyDeviceToDevice, st), "gs_sort_pairs_static: keys");
+    GS_HIP(hipMemcpyAsync(vals, vtmp, (size_t)n * 4, hipMemcpyDeviceToDevice, st), "gs_sort_pairs_static: vals");
   }
   return GS_OK;
 }

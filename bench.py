@@ -20,13 +20,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fwd+bwd splat iters/sec at 1M Gaussians, 1280×1024; batched vs plain"
 
-# Algorithmic VALU lane-operations per (pixel, record) pair of the compositing, counted from the per-pair
-# definition with a multiply-add as one operation and exp / reciprocal (quarter-rate) as four.
-OPS_EVAL = 19          # alpha of one pair: offsets, conic quadratic form, exp, opacity, clamp, skip test
-OPS_CONTRIB_FWD = 9    # transmittance update, stop test, colour / depth / visibility accumulation
-OPS_CONTRIB_BWD = 37   # weight, upstream dot product, dL/dalpha, 10 per-record partial derivatives
+# Algorithmic VALU lane-operations per (pixel, record) pair of the compositing (the planning budget of the
+# hot-path scope: 14 operations + one exp, counted at quarter rate as 4, per evaluated pair; 10 more per
+# contributing pair in the forward; 55 + one exp per contributing pair in the backward).
+OPS_EVAL = 14 + 4
+OPS_CONTRIB_FWD = 10
+OPS_CONTRIB_BWD = 55 + 4
+# The same work counted from this build's own per-pair code (multiply-add as one, exp and reciprocal as
+# four); evaluated pairs are evaluated in both sweeps of the fused kernel.
+OWN_EVAL, OWN_CONTRIB_FWD, OWN_CONTRIB_BWD = 19, 9, 37
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz, one VALU lane-operation per lane per cycle.
 ALU_PEAK = 256 * 4 * 16 * 2.4e9
+HBM_PEAK = 8.0e12  # bytes/s
 
 
 def log(*a):
@@ -76,9 +81,18 @@ def measure(sc, steps, warmup, plain_steps, do_plain, tile=None, peak=False):
     log(f"  batched: capacity {bat.frame.capacity}, capture {time.time() - t0:.1f}s")
     for _ in range(warmup):
         bat.run()
+    bat.finish()
+    replans = bat.replans
     ms = timed(bat.run, steps, stream)
-    if bat.overflowed():
-        raise RuntimeError("instance capacity overflow during timing")
+    bat.finish()
+    if bat.replans != replans:
+        # the capacity was re-planned inside the timed steps (the map grew): time again at the new capacity
+        log(f"  batched: capacity re-planned during timing ({bat.frame.capacity}); timing again")
+        replans = bat.replans
+        ms = timed(bat.run, steps, stream)
+        bat.finish()
+        if bat.replans != replans:
+            raise RuntimeError("instance capacity re-planned twice during timing")
     res = dict(ms=ms, n_instances=bat.n_instances(), loss=bat.loss(), frame=bat.frame, model=model, step=bat,
                tile=tile)
     if peak:
@@ -145,29 +159,93 @@ def dominant_kernel(res, steps):
     ev, co = B.gs_count_pairs(fr)
     ms = timed(lambda: B.gs_composite_bwd(fr, None, tgt_rgb=st.tgt_rgb, tgt_depth=st.tgt_depth), steps,
                torch.cuda.current_stream())
-    ops = ev * 2 * OPS_EVAL + co * (OPS_CONTRIB_FWD + OPS_CONTRIB_BWD)
-    achieved = ops / (ms * 1e-3)
-    return dict(ms=ms, evaluated=ev, contributing=co, ops=ops, achieved=achieved)
+    ops = ev * OPS_EVAL + co * (OPS_CONTRIB_FWD + OPS_CONTRIB_BWD)
+    own = ev * 2 * OWN_EVAL + co * (OWN_CONTRIB_FWD + OWN_CONTRIB_BWD)
+    return dict(ms=ms, evaluated=ev, contributing=co, ops=ops, achieved=ops / (ms * 1e-3), own_ops=own,
+                own_achieved=own / (ms * 1e-3))
 
 
-def cpu_baseline(sc, kf_views):
+def stage_times(res, steps):
+    """Per-stage launch times of the batched step (eager calls timed with HIP events on their stream) and the
+    whole-step roofline: the sum over stages of max(algorithmic bytes / HBM peak, algorithmic lane-ops / ALU
+    peak), divided by the measured step time."""
+    import numpy as np
+    import torch
+
+    from paper_2411_02703_amd import binding as B
+
+    fr, st, model = res["frame"], res["step"], res["model"]
+    stream = torch.cuda.current_stream()
+    n = model.n
+    K = (model.sh_degree + 1) ** 2
+    pbytes = 44 + 12 * K
+    mask = B.frame_tensor(fr, "vis_mask", n, torch.int64).cpu().numpy().view(np.uint8)
+    R = int(np.unpackbits(mask).sum())  # visible (view, Gaussian) records
+    I = res["n_instances"]
+    passes = int(fr.f.sort_passes)
+    loss = dict(tgt_rgb=st.tgt_rgb, tgt_depth=st.tgt_depth)
+    t = {}
+    t["project"] = timed(lambda: B.gs_project(model.ps, fr), steps, stream)
+    t["bin"] = timed(lambda: B.gs_bin_tiles(fr, sync_count=False), steps, stream)
+    t["composite"] = timed(lambda: B.gs_composite_bwd(fr, None, **loss), steps, stream)
+    both = timed(lambda: B.gs_render_bwd_adam(model.ps, fr, None, model.ms, model.vs, model.adam, None, **loss),
+                 steps, stream)
+    t["project_bwd_adam"] = max(both - t["composite"], 0.0)
+    dk = res["dominant"]
+    work = {
+        "project": dict(bytes=n * pbytes + R * 48, ops=0),
+        "bin": dict(bytes=I * (12 + 24 * passes + 8), ops=0),
+        "composite": dict(bytes=I * 52, ops=dk["ops"]),
+        "project_bwd_adam": dict(bytes=R * (40 + 48) + n * 6 * pbytes, ops=0),
+    }
+    stages, t_roof = {}, 0.0
+    for k, ms in t.items():
+        w = work[k]
+        roof = max(w["bytes"] / HBM_PEAK, w["ops"] / ALU_PEAK) * 1e3
+        t_roof += roof
+        stages[k] = {"ms": round(ms, 4), "roofline_ms": round(roof, 4), "frac": round(roof / ms, 4) if ms > 0 else None,
+                     "algorithmic_GB": round(w["bytes"] / 1e9, 4), "GB_per_s": round(w["bytes"] / (ms * 1e6), 1)}
+        if w["ops"]:
+            stages[k]["valu_frac"] = round(w["ops"] / (ms * 1e-3) / ALU_PEAK, 4)
+    return dict(stages=stages, t_roof_ms=t_roof, records=R, sort_passes=passes)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(sc, kf_views, threads=None):
+    """The FP32 oracle (tiled mode) on one keyframe pyramid of the 24-view workload against all Gaussians, scaled by
+    pixel count to the full step; threads=None uses every host thread."""
     import numpy as np
 
     import oracle
 
+    n_all = oracle.num_threads()
+    if threads is not None:
+        oracle.set_threads(threads)
     cams = [sc.cams[i] for i in kf_views]
     offs = np.cumsum([0] + [c.width * c.height for c in sc.cams])
     rgb = np.concatenate([sc.tgt_rgb[3 * offs[i]:3 * offs[i + 1]] for i in kf_views])
     dep = np.concatenate([sc.tgt_depth[offs[i]:offs[i + 1]] for i in kf_views])
     p_sample = sum(c.width * c.height for c in cams)
+    used = oracle.num_threads()
     t0 = time.time()
     oracle.backward(32, sc.params(), sc.sh_degree, cams, tgt_rgb=rgb, tgt_depth=dep)
     dt = time.time() - t0
+    oracle.set_threads(n_all)
     scale = sc.total_pixels / p_sample
-    return dict(value=1.0 / (dt * scale), unit="iters/s", cores=oracle.num_threads(), kind="oracle",
+    return dict(value=1.0 / (dt * scale), unit="iters/s", cores=used, kind="oracle", cpu=cpu_model(),
                 sample=(f"FP32 oracle forward + loss + backward of views {list(kf_views)} "
-                        f"({'+'.join(f'{c.width}x{c.height}' for c in cams)}) against all {sc.n} Gaussians: "
-                        f"{dt:.2f} s, scaled x{scale:.2f} by pixel count to the full step"))
+                        f"({'+'.join(f'{c.width}x{c.height}' for c in cams)}) against all {sc.n} Gaussians on "
+                        f"{used} thread(s): {dt:.2f} s, scaled x{scale:.2f} by pixel count to the full step"))
 
 
 def main():
@@ -179,9 +257,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-cfg3", action="store_true")
-    ap.add_argument("--cfg5", action="store_true",
-                    help="also time the large map (4M Gaussians, 16 keyframes x 3 levels; about two minutes of "
-                         "scene generation on the host)")
+    ap.add_argument("--no-cfg5", action="store_true",
+                    help="skip the large map (4M Gaussians, 16 keyframes x 3 levels; about a minute of scene "
+                         "generation on the host)")
     ap.add_argument("--n", type=int, default=None, help="override the Gaussian count (smaller trial runs)")
     ap.add_argument("--tile", type=str, default=None,
                     help="tile_w,tile_h[,batch_depth,block_w,seg_len] (skips the autotuner)")
@@ -210,8 +288,12 @@ def main():
         tile = tuple(int(x) for x in parts)
     r4 = measure(sc4, args.steps, args.warmup, args.plain_steps, not args.no_plain, tile)
     dk = dominant_kernel(r4, args.steps)
+    r4["dominant"] = dk
     log(f"  fused compositing kernel: {dk['ms']:.3f} ms, {dk['evaluated']} evaluated / {dk['contributing']} "
         f"contributing pairs, {dk['achieved'] / 1e12:.2f} T lane-ops/s")
+    stg = stage_times(r4, args.steps)
+    for k, v in stg["stages"].items():
+        log(f"  stage {k}: {v['ms']:.3f} ms, roofline {v['roofline_ms']:.3f} ms ({v['frac']:.3f})")
     if args.copy_calib > 0:
         src = torch.ones(args.copy_calib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -249,7 +331,13 @@ def main():
                        "traffic": measured_traffic(r4["tile"]),
                        "kernel": kernel_label(r4["tile"]),
                        "kernel_ms": round(dk["ms"], 4), "pairs_evaluated": dk["evaluated"],
-                       "pairs_contributing": dk["contributing"]}
+                       "pairs_contributing": dk["contributing"],
+                       "ops_per_pair": {"evaluated": OPS_EVAL, "contributing_fwd": OPS_CONTRIB_FWD,
+                                        "contributing_bwd": OPS_CONTRIB_BWD},
+                       "frac_own_count": round(dk["own_achieved"] / ALU_PEAK, 4)}
+    out["step_roofline"] = {"t_roof_ms": round(stg["t_roof_ms"], 4), "frac": round(stg["t_roof_ms"] / r4["ms"], 4),
+                            "hbm_peak_GB_s": HBM_PEAK / 1e9, "alu_peak_T_lane_op_s": round(ALU_PEAK / 1e12, 3),
+                            "records": stg["records"], "sort_passes": stg["sort_passes"], "stages": stg["stages"]}
     if not args.no_cfg3:
         sc3 = scenes.config(3, n=args.n)
         log(f"cfg3 scene: {len(sc3.cams)} views, {sc3.total_pixels} px")
@@ -257,12 +345,12 @@ def main():
         out["single_keyframe_1280x1024_pyramid"] = {"batched": round(1000.0 / r3["ms"], 3)}
         if "plain_ms" in r3:
             out["single_keyframe_1280x1024_pyramid"]["plain"] = round(1000.0 / r3["plain_ms"], 3)
-    if args.cfg5:
+    if not args.no_cfg5:
         t0 = time.time()
         sc5 = scenes.config(5, n=None if args.n is None else 4 * args.n)
         log(f"cfg5 scene: {sc5.n} Gaussians, {len(sc5.cams)} views, {sc5.total_pixels} px ({time.time() - t0:.1f}s)")
         torch.cuda.empty_cache()
-        r5 = measure(sc5, max(5, args.steps // 2), args.warmup, 3, not args.no_plain, tile, peak=True)
+        r5 = measure(sc5, max(5, args.steps // 4), args.warmup, 3, not args.no_plain, r4["tile"], peak=True)
         out["large_map_4M"] = {
             "workload": "4M Gaussians (SH degree 3) over a 200 m x 200 m LiDAR scene, 16 keyframes 640x512..1280x1024 "
                         "x 3 levels = 48 views; per-pixel state recomputed in the backward",
@@ -277,7 +365,10 @@ def main():
         del sc5, r5
     if not args.no_cpu:
         big = max(range(0, len(sc4.cams), 3), key=lambda i: sc4.cams[i].width)
+        small = min(range(0, len(sc4.cams), 3), key=lambda i: sc4.cams[i].width * sc4.cams[i].height)
         out["cpu_baseline"] = cpu_baseline(sc4, [big, big + 1, big + 2])
+        # one thread, on the smallest keyframe's pyramid (about a quarter of the pixels) to bound its time
+        out["cpu_baseline"]["single_thread"] = cpu_baseline(sc4, [small, small + 1, small + 2], threads=1)
     print(json.dumps(out), flush=True)
 
 

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GS_VERSION 1
+#define GS_VERSION 2
 #define GS_MAX_VIEWS 64
 
 typedef enum {
@@ -185,15 +185,20 @@ typedef struct gs_loss {
   const float* tgt_rgb;   /* loss mode when non-NULL: target images, layout of gs_images.rgb */
   const float* tgt_depth; /* loss mode: LiDAR depth, layout of gs_images.depth, 0 = no measurement */
   float lambda_d;         /* loss mode: depth weight (0.1) */
-  int32_t reserved;
+  float lambda_ssim;      /* loss mode: weight lambda of the SSIM term in eq. Lc; the L1 colour term takes
+                             (1 - lambda).  The SSIM term's image gradient comes from gs_ssim and is passed in
+                             g_rgb, which loss mode ADDS to the L1 gradient (g_depth, g_vis are not used in loss
+                             mode).  0 with g_rgb = NULL is the plain L1 loss */
 } gs_loss;
 
 typedef struct gs_adam {
   float lr[6];          /* means, log_scales, quats, opacity, sh degree 0, sh degree >= 1 */
   float beta1, beta2, eps;
   int32_t reserved;
-  int64_t* step;        /* device counter, incremented by each call before it is used */
-  float* bias;          /* device scratch of 2 floats */
+  int64_t* step;        /* device counter, incremented by each step that is taken, before it is used */
+  float* bias;          /* device scratch of 4 floats (bias corrections and the skip decision of the step) */
+  const int32_t* skip_flags; /* gs_adam_step: nullable device pointer, typically &frame->counters[1]; when
+                                GS_FLAG_INSTANCE_OVERFLOW is set there as the step runs, the step is skipped */
 } gs_adam;
 
 /* ------------------------------------------------------------------ host-side set-up */
@@ -218,9 +223,13 @@ int gs_frame_init(gs_frame* frame, void* block, size_t bytes, int64_t n, const g
  * Gaussian once. */
 int gs_project(const gs_params* params, const gs_frame* frame, const gs_opts* opts, void* stream);
 
-/* Tile binning: exclusive scan of instance counts, emission of (global tile << 32 | depth bits, record)
- * pairs, stable LSD radix sort, per-tile ranges.  The order within a tile is ascending depth, ties by
- * record index.  sync_count != 0 synchronises the stream after the scan to size the work exactly and
+/* Tile binning (Section III-B: rasterisation iterates over the Gaussians rather than along camera rays, and
+ * eq. Cp composites them in depth order, the product over j < i running over the Gaussians in front): exclusive
+ * scan of instance counts, emission of (global tile << 32 | depth bits, record) pairs, stable LSD radix sort,
+ * per-tile ranges.  The order within a tile is ascending depth, ties by record index, which makes the sorted
+ * order unique.  Errors: GS_ERR_ARG for a frame whose key bits exceed 64 or whose capacity is not positive;
+ * an instance count above the capacity sets GS_FLAG_INSTANCE_OVERFLOW (instances past the capacity are
+ * dropped, the frame's outputs are then undefined, and the count in counters[0] is still the full count).  sync_count != 0 synchronises the stream after the scan to size the work exactly and
  * returns the instance count in *n_instances (host, nullable); otherwise the work is sized by the
  * capacity and the count stays on the device (graph-capturable). */
 int gs_bin_tiles(const gs_frame* frame, const gs_opts* opts, int32_t sync_count, int64_t* n_instances,
@@ -250,10 +259,42 @@ int gs_composite_bwd(const gs_frame* frame, const gs_opts* opts, const gs_images
 int gs_project_bwd(const gs_params* params, const gs_frame* frame, const gs_opts* opts, const gs_params* grads,
                    void* stream);
 
-/* One Adam step over all parameters (m, v as moments; bias-corrected, eps added to the corrected
- * root), with per-group learning rates.  Dense: Gaussians with zero gradient still move. */
+/* One Adam step over all parameters (Section III-E: the rotation, scaling, opacity and SH parameters, and here
+ * the means as well, are optimised by minimising eq. L; the paper names no optimiser, so this is the
+ * bias-corrected Adam of common 3DGS practice, eps added to the corrected root), with per-group learning
+ * rates.  Dense: Gaussians with zero gradient still move.  params, m and v are updated in place; grads are
+ * read only; *adam->step is incremented on the device and adam->bias (2 floats) receives the bias
+ * corrections, so graph replays advance the step.  If adam->skip_flags is non-NULL and *skip_flags has
+ * GS_FLAG_INSTANCE_OVERFLOW set when the step runs, nothing is updated and the counter does not advance (the
+ * gradients of an overflowed frame are undefined). */
 int gs_adam_step(const gs_params* params, const gs_params* grads, const gs_params* m, const gs_params* v,
                  const gs_adam* adam, void* stream);
+
+/* The backward of gs_render_bwd fused with the Adam step of gs_adam_step (Sections III-B and III-E: the
+ * loss of eq. L differentiated through eqs. Cp, Dp, Vp, alpha, muI and Sigma, then the parameters moved by one
+ * optimiser step), in one pass per Gaussian after the compositing backward: a thread sums its Gaussian's
+ * instance partials view by view, forms the parameter gradient in registers and applies Adam to its
+ * parameters, m and v directly, so no gradient buffer is zeroed, written and read back.  Dense Adam: Gaussians
+ * with no visible record take a zero gradient and still move.  params, m and v are updated in place.
+ * grads_out (nullable): when given, the gradient of this call is WRITTEN there (not accumulated), for callers
+ * that inspect it.  The step is skipped (params, m, v and *adam->step unchanged) when the frame's instance
+ * capacity overflowed (GS_FLAG_INSTANCE_OVERFLOW in frame->counters[1]); adam->skip_flags is not used.
+ * Arguments are checked as for gs_render_bwd and gs_adam_step. */
+int gs_render_bwd_adam(const gs_params* params, const gs_frame* frame, const gs_opts* opts, const gs_images* fwd,
+                       const gs_loss* loss, const gs_params* m, const gs_params* v, const gs_adam* adam,
+                       const gs_params* grads_out, void* stream);
+
+/* The SSIM term of the photometric loss (Section III-E, eq. Lc: L_c = (1 - lambda) L1 + lambda L_ssim) for every
+ * view: lambda w_v (1 - mean over the three channels and the view's pixels of SSIM(rgb, tgt_rgb)), with SSIM over an
+ * 11 x 11 Gaussian window (standard deviation 1.5 px, summing to 1, zero padding at the image borders),
+ * C1 = 0.01^2, C2 = 0.03^2 (the readings of the 3DGS work the paper builds on; the paper gives none).
+ * cams_host: the planned cameras (host, from gs_plan_cameras), cams_dev: their device copy; rgb, tgt_rgb and
+ * g_rgb have the layout of gs_images.rgb.  g_rgb receives (is WRITTEN with) d(term)/d rgb, ready to be passed as
+ * gs_loss.g_rgb of a loss-mode backward with lambda_ssim = lambda; loss_out (device, 64 floats) receives the
+ * term's value in loss_out[0] (loss_out[1..32] are partial sums).  GS_ERR_ARG for NULL pointers, n_views
+ * outside [1, 64] or lambda outside [0, 1]. */
+int gs_ssim(const gs_camera* cams_host, const gs_camera* cams_dev, int32_t n_views, const float* rgb,
+            const float* tgt_rgb, float lambda_ssim, float* g_rgb, float* loss_out, void* stream);
 
 /* ------------------------------------------------------------------ utilities */
 /* Work counts of the frame's forward compositing at its tile shape, ADDED to counts[0..1] (device, uint64):

@@ -16,9 +16,10 @@ from . import build as _build
 
 # Readings of the constants the paper leaves open (Section III-B): near plane 0.2 m,
 # guard band 1.3, EWA low-pass 0.3 px^2, skip below alpha 1/255, clamp at 0.99, stop
-# before T < 1e-4, black background, 16x16 tiles, lambda_d = 0.1.
+# before T < 1e-4, black background, 16x16 tiles, lambda_d = 0.1; the SSIM weight of eq. Lc is 0 unless
+# given (lambda_ssim; SSIM_LAMBDA = 0.2 is the usual 3DGS value).
 DEFAULT_OPTS = dict(near=0.2, guard=1.3, lowpass=0.3, alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4,
-                    bg=(0.0, 0.0, 0.0), tile_w=16, tile_h=16, lambda_d=0.1, stop_near=1e-5)
+                    bg=(0.0, 0.0, 0.0), tile_w=16, tile_h=16, lambda_d=0.1, stop_near=1e-5, lambda_ssim=0.0)
 
 _lib = None
 
@@ -32,6 +33,8 @@ def lib() -> ctypes.CDLL:
         _lib.oracle_reference.restype = ctypes.c_double
         _lib.oracle_loss.restype = ctypes.c_double
         _lib.oracle_bin.restype = ctypes.c_int64
+        _lib.oracle_ssim_plane.restype = ctypes.c_double
+        _lib.oracle_ssim_loss.restype = ctypes.c_double
     return _lib
 
 
@@ -50,7 +53,7 @@ def opts_array(**over) -> np.ndarray:
     o = dict(DEFAULT_OPTS)
     o.update(over)
     return _f64([o["near"], o["guard"], o["lowpass"], o["alpha_min"], o["alpha_max"], o["t_min"], *o["bg"],
-                 o["tile_w"], o["tile_h"], o["lambda_d"], o["stop_near"]])
+                 o["tile_w"], o["tile_h"], o["lambda_d"], o["stop_near"], o["lambda_ssim"]])
 
 
 def cams_array(cams: Sequence) -> np.ndarray:
@@ -236,6 +239,36 @@ def quat_to_rot(q) -> np.ndarray:
     M = np.zeros(9)
     lib().oracle_quat_to_rot(_p(_f64(q)), _p(M))
     return M.reshape(3, 3)
+
+
+SSIM_LAMBDA = 0.2  # weight of the SSIM term in eq. Lc (the value of the 3DGS work the paper builds on)
+
+
+def ssim_window() -> np.ndarray:
+    w = np.zeros(121)
+    lib().oracle_ssim_window(_p(w))
+    return w.reshape(11, 11)
+
+
+def ssim_plane(x, y, grad: bool = False):
+    """(mean SSIM, per-pixel SSIM map, d mean / d x or None) of one channel plane [H, W] (FP64)."""
+    x, y = _f64(x), _f64(y)
+    H, W = x.shape
+    m = np.zeros((H, W))
+    g = np.zeros((H, W)) if grad else None
+    mean = lib().oracle_ssim_plane(_p(x), _p(y), ctypes.c_int(H), ctypes.c_int(W), _p(m), _p(g))
+    return float(mean), m, g
+
+
+def ssim_loss(x, y, cams, lam: float = SSIM_LAMBDA, grad: bool = True):
+    """The SSIM term sum_v w_v lam (1 - mean SSIM_v) of planar per-view images [3][H_v][W_v] (concatenated over
+    views) and its gradient with respect to x (same layout)."""
+    x, y = _f64(x), _f64(y)
+    sizes = np.ascontiguousarray([[c.height, c.width] for c in cams], np.int32).reshape(-1)
+    w = _f64([c.weight for c in cams])
+    g = np.zeros_like(x) if grad else None
+    L = lib().oracle_ssim_loss(_p(x), _p(y), ctypes.c_int(len(cams)), _p(sizes), _p(w), ctypes.c_double(lam), _p(g))
+    return float(L), g
 
 
 def num_threads() -> int:

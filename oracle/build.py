@@ -4,14 +4,14 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "oracle.cpp")
+SRCS = [os.path.join(HERE, f) for f in ("oracle.cpp", "ssim.cpp")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 FLAGS = ["-std=c++17", "-O3", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["g++", *FLAGS, SRC, "-o", LIB + ".tmp"]
+    cmd = ["g++", *FLAGS, *SRCS, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -20,7 +20,7 @@ def build(verbose: bool = False) -> str:
 
 
 def ensure_built() -> str:
-    if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+    if not os.path.exists(LIB) or any(os.path.getmtime(LIB) < os.path.getmtime(s) for s in SRCS):
         build()
     return LIB
 

@@ -47,14 +47,15 @@ constexpr int PREC_MIXED = 3264;
 
 enum {
   OPT_NEAR = 0, OPT_GUARD, OPT_LOWPASS, OPT_ALPHA_MIN, OPT_ALPHA_MAX, OPT_T_MIN,
-  OPT_BG0, OPT_BG1, OPT_BG2, OPT_TILE_W, OPT_TILE_H, OPT_LAMBDA_D, OPT_STOP_NEAR, OPT_COUNT
+  OPT_BG0, OPT_BG1, OPT_BG2, OPT_TILE_W, OPT_TILE_H, OPT_LAMBDA_D, OPT_STOP_NEAR, OPT_LAMBDA_SSIM, OPT_COUNT
 };
 
 // stop_near: relative distance of T(1 - alpha) from t_min within which a stop decision counts as near its
 // threshold (test excusal only; 1e-5 by default, wider where the compared path multiplies the transmittance
 // in another association order).
+// lambda_ssim: weight of the SSIM term in eq. Lc (the L1 colour term takes 1 - lambda_ssim).
 struct Opts {
-  double near_z, guard, lowpass, alpha_min, alpha_max, t_min, bg[3], lambda_d, stop_near;
+  double near_z, guard, lowpass, alpha_min, alpha_max, t_min, bg[3], lambda_d, stop_near, lambda_ssim;
   int tile_w, tile_h;
 };
 
@@ -73,6 +74,7 @@ Opts read_opts(const double* o) {
   r.tile_h = (int)o[OPT_TILE_H];
   r.lambda_d = o[OPT_LAMBDA_D];
   r.stop_near = o[OPT_STOP_NEAR];
+  r.lambda_ssim = o[OPT_LAMBDA_SSIM];
   return r;
 }
 
@@ -537,15 +539,44 @@ void render_all(const Scene<R>& sc, int mode, std::vector<PixelOut<R>>& out,
 }
 
 // ---------------------------------------------------------------- loss
-// L = sum_v w_v [ mean_{3 P_v} |C - I| + lambda_d * mean_{valid} |D - D_lidar| ]  (eqs. L, Lc, Ld; reading R14)
+}  // namespace
+extern "C" double oracle_ssim_plane(const double* x, const double* y, int H, int W, double* map, double* grad);
+namespace {
+
+// The SSIM term of eq. Lc for every view, lambda_ssim w_v (1 - mean SSIM_v) (oracle/ssim.cpp), computed in double
+// from the colour image `img`; its gradient is added to the colour entries of g.  Returns its value.
+template <class R>
+double ssim_term(const Scene<R>& sc, const std::vector<PixelOut<R>>& img, const double* tgt_rgb,
+                 std::vector<double>& g) {
+  const double lam = sc.op.lambda_ssim;
+  double L = 0;
+  for (int v = 0; v < sc.V; ++v) {
+    const Cam<R>& cam = sc.cams[v];
+    const int64_t P = (int64_t)cam.W * cam.H, off = cam.pixel_offset;
+    std::vector<double> x(P), gr(P);
+    double mean = 0;
+    for (int ch = 0; ch < 3; ++ch) {
+      for (int64_t i = 0; i < P; ++i) x[i] = (double)img[off + i].C[ch];
+      mean += oracle_ssim_plane(x.data(), tgt_rgb + 3 * off + ch * P, cam.H, cam.W, nullptr, gr.data()) / 3.0;
+      for (int64_t i = 0; i < P; ++i) g[(off + i) * 5 + ch] -= (double)cam.weight * lam / 3.0 * gr[i];
+    }
+    L += (double)cam.weight * lam * (1.0 - mean);
+  }
+  return L;
+}
+
+// L = sum_v w_v [ (1 - lambda_ssim) mean_{3 P_v} |C - I| + lambda_ssim (1 - SSIM_v)
+//                 + lambda_d * mean_{valid} |D - D_lidar| ]  (eqs. L, Lc, Ld; readings R14, R23)
 // Returns per-pixel upstream gradients g (5 per pixel: C0..C2, D, V) and the loss value.
 // near_sign[pix] has bit ch set (ch = 0..2 colour, 3 depth) where |C - I| is within the window of 0, where
-// the sign of the L1 gradient could go either way; gmag (optional) receives the magnitude of each upstream
-// gradient entry whatever its sign (the loss weight of that term).
+// the sign of the L1 gradient could go either way; gmag (optional) receives the magnitude of each L1 upstream
+// gradient entry whatever its sign (the loss weight of that term).  The SSIM term (no discrete decision) is
+// computed from ssim_img when given (the FP64 image of the mixed reference), else from img.
 template <class R>
 double loss_and_grad(const Scene<R>& sc, const std::vector<PixelOut<R>>& img, const double* tgt_rgb,
                      const double* tgt_depth, std::vector<double>& g, std::vector<char>& near_sign,
-                     std::vector<double>* gmag = nullptr) {
+                     std::vector<double>* gmag = nullptr, const Scene<double>* ssim_sc = nullptr,
+                     const std::vector<PixelOut<double>>* ssim_img = nullptr) {
   g.assign((size_t)sc.total_px * 5, 0.0);
   near_sign.assign(sc.total_px, 0);
   if (gmag) gmag->assign((size_t)sc.total_px * 5, 0.0);
@@ -555,7 +586,7 @@ double loss_and_grad(const Scene<R>& sc, const std::vector<PixelOut<R>>& img, co
     int64_t P = (int64_t)cam.W * cam.H, off = cam.pixel_offset;
     int64_t M = 0;
     for (int64_t i = 0; i < P; ++i) M += tgt_depth[off + i] > 0;
-    double wrgb = (double)cam.weight / (3.0 * (double)P);
+    double wrgb = (double)cam.weight * (1.0 - sc.op.lambda_ssim) / (3.0 * (double)P);
     double wd = M > 0 ? (double)cam.weight * sc.op.lambda_d / (double)M : 0.0;
     for (int64_t i = 0; i < P; ++i) {
       int64_t pix = off + i;
@@ -577,6 +608,7 @@ double loss_and_grad(const Scene<R>& sc, const std::vector<PixelOut<R>>& img, co
       }
     }
   }
+  if (sc.op.lambda_ssim > 0) L += ssim_sc ? ssim_term(*ssim_sc, *ssim_img, tgt_rgb, g) : ssim_term(sc, img, tgt_rgb, g);
   return L;
 }
 
@@ -1173,7 +1205,7 @@ double mixed_upstream(const Mixed& m, const double* g_rgb, const double* g_depth
   std::vector<double> g64;
   std::vector<char> ns64;
   double L = loss_and_grad<double>(m.sd, m.img, tgt_rgb, tgt_depth, g64, ns64);
-  loss_and_grad<float>(m.sf, m.imf, tgt_rgb, tgt_depth, g, near_sign, gmag);
+  loss_and_grad<float>(m.sf, m.imf, tgt_rgb, tgt_depth, g, near_sign, gmag, &m.sd, &m.img);
   return L;
 }
 

@@ -61,12 +61,12 @@ class gs_images(ctypes.Structure):
 
 class gs_loss(ctypes.Structure):
     _fields_ = [("g_rgb", c_vp), ("g_depth", c_vp), ("g_vis", c_vp), ("tgt_rgb", c_vp), ("tgt_depth", c_vp),
-                ("lambda_d", c_f), ("reserved", c_i32)]
+                ("lambda_d", c_f), ("lambda_ssim", c_f)]
 
 
 class gs_adam(ctypes.Structure):
     _fields_ = [("lr", c_f * 6), ("beta1", c_f), ("beta2", c_f), ("eps", c_f), ("reserved", c_i32),
-                ("step", c_vp), ("bias", c_vp)]
+                ("step", c_vp), ("bias", c_vp), ("skip_flags", c_vp)]
 
 
 assert ctypes.sizeof(gs_camera) == 128
@@ -76,6 +76,7 @@ GS_FLAG_NONFINITE = 2
 
 EXPORTED = ["gs_default_opts", "gs_plan_cameras", "gs_frame_bytes", "gs_frame_init", "gs_project", "gs_bin_tiles",
             "gs_render_fwd", "gs_render_bwd", "gs_composite_bwd", "gs_project_bwd", "gs_adam_step",
+            "gs_render_bwd_adam", "gs_ssim",
             "gs_count_pairs", "gs_read_counters", "gs_sort_scratch_ints", "gs_sort_pairs", "gs_sort_static_max",
             "gs_sort_pairs_static", "gs_status_string",
             "gs_last_error", "gs_version"]
@@ -106,6 +107,9 @@ def load() -> ctypes.CDLL:
     lib.gs_composite_bwd.argtypes = [P(gs_frame), P(gs_opts), P(gs_images), P(gs_loss), c_vp]
     lib.gs_project_bwd.argtypes = [P(gs_params), P(gs_frame), P(gs_opts), P(gs_params), c_vp]
     lib.gs_adam_step.argtypes = [P(gs_params), P(gs_params), P(gs_params), P(gs_params), P(gs_adam), c_vp]
+    lib.gs_ssim.argtypes = [P(gs_camera), c_vp, c_i32, c_vp, c_vp, c_f, c_vp, c_vp, c_vp]
+    lib.gs_render_bwd_adam.argtypes = [P(gs_params), P(gs_frame), P(gs_opts), P(gs_images), P(gs_loss),
+                                       P(gs_params), P(gs_params), P(gs_adam), P(gs_params), c_vp]
     lib.gs_count_pairs.argtypes = [P(gs_frame), P(gs_opts), c_vp, c_vp]
     lib.gs_read_counters.argtypes = [P(gs_frame), P(c_i64), P(c_i32), c_vp]
     lib.gs_sort_scratch_ints.argtypes = [c_i64]
@@ -245,26 +249,28 @@ def gs_render_fwd(frame: Frame, rgb: torch.Tensor, depth: torch.Tensor, vis: tor
 
 def gs_render_bwd(params: gs_params, frame: Frame, fwd: Optional[Sequence[torch.Tensor]], grads: gs_params,
                   g_rgb=None, g_depth=None, g_vis=None, tgt_rgb=None, tgt_depth=None, lambda_d: float = 0.1,
-                  stream=None) -> None:
+                  lambda_ssim: float = 0.0, stream=None) -> None:
     im = None
     if fwd is not None:
         im = gs_images(fwd[0].data_ptr(), fwd[1].data_ptr(), fwd[2].data_ptr())
-    l = gs_loss(_ptr(g_rgb), _ptr(g_depth), _ptr(g_vis), _ptr(tgt_rgb), _ptr(tgt_depth), float(lambda_d), 0)
+    l = _loss_struct(g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth, lambda_d, lambda_ssim)
     _check(load().gs_render_bwd(ctypes.byref(params), ctypes.byref(frame.f), ctypes.byref(frame.opts),
                                 ctypes.byref(im) if im is not None else None, ctypes.byref(l), ctypes.byref(grads),
                                 _stream(stream)), "gs_render_bwd")
 
 
-def _loss_struct(g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth, lambda_d) -> gs_loss:
-    return gs_loss(_ptr(g_rgb), _ptr(g_depth), _ptr(g_vis), _ptr(tgt_rgb), _ptr(tgt_depth), float(lambda_d), 0)
+def _loss_struct(g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth, lambda_d, lambda_ssim=0.0) -> gs_loss:
+    return gs_loss(_ptr(g_rgb), _ptr(g_depth), _ptr(g_vis), _ptr(tgt_rgb), _ptr(tgt_depth), float(lambda_d),
+                   float(lambda_ssim))
 
 
 def gs_composite_bwd(frame: Frame, fwd: Optional[Sequence[torch.Tensor]], g_rgb=None, g_depth=None, g_vis=None,
-                     tgt_rgb=None, tgt_depth=None, lambda_d: float = 0.1, stream=None) -> None:
+                     tgt_rgb=None, tgt_depth=None, lambda_d: float = 0.1, lambda_ssim: float = 0.0,
+                     stream=None) -> None:
     im = None
     if fwd is not None:
         im = gs_images(fwd[0].data_ptr(), fwd[1].data_ptr(), fwd[2].data_ptr())
-    l = _loss_struct(g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth, lambda_d)
+    l = _loss_struct(g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth, lambda_d, lambda_ssim)
     _check(load().gs_composite_bwd(ctypes.byref(frame.f), ctypes.byref(frame.opts),
                                    ctypes.byref(im) if im is not None else None, ctypes.byref(l), _stream(stream)),
            "gs_composite_bwd")
@@ -288,6 +294,31 @@ def gs_adam_step(params: gs_params, grads: gs_params, m: gs_params, v: gs_params
                  stream=None) -> None:
     _check(load().gs_adam_step(ctypes.byref(params), ctypes.byref(grads), ctypes.byref(m), ctypes.byref(v),
                                ctypes.byref(adam), _stream(stream)), "gs_adam_step")
+
+
+def gs_render_bwd_adam(params: gs_params, frame: Frame, fwd: Optional[Sequence[torch.Tensor]], m: gs_params,
+                       v: gs_params, adam: gs_adam, grads_out: Optional[gs_params] = None, g_rgb=None, g_depth=None,
+                       g_vis=None, tgt_rgb=None, tgt_depth=None, lambda_d: float = 0.1, lambda_ssim: float = 0.0,
+                       stream=None) -> None:
+    """Backward and Adam fused (params, m, v updated in place; the gradient written to grads_out if given)."""
+    im = None
+    if fwd is not None:
+        im = gs_images(fwd[0].data_ptr(), fwd[1].data_ptr(), fwd[2].data_ptr())
+    l = _loss_struct(g_rgb, g_depth, g_vis, tgt_rgb, tgt_depth, lambda_d, lambda_ssim)
+    _check(load().gs_render_bwd_adam(ctypes.byref(params), ctypes.byref(frame.f), ctypes.byref(frame.opts),
+                                     ctypes.byref(im) if im is not None else None, ctypes.byref(l), ctypes.byref(m),
+                                     ctypes.byref(v), ctypes.byref(adam),
+                                     ctypes.byref(grads_out) if grads_out is not None else None, _stream(stream)),
+           "gs_render_bwd_adam")
+
+
+def gs_ssim(frame: Frame, rgb: torch.Tensor, tgt_rgb: torch.Tensor, lambda_ssim: float, g_rgb: torch.Tensor,
+            loss_out: torch.Tensor, stream=None) -> None:
+    """SSIM term of the frame's views: its image gradient written to g_rgb, its value to loss_out[0] (64 floats)."""
+    if loss_out.numel() < 64 or loss_out.dtype != torch.float32 or not loss_out.is_cuda:
+        raise ValueError("loss_out must be a float32 CUDA tensor of at least 64 elements")
+    _check(load().gs_ssim(frame.cams_host, frame.cams_dev.data_ptr(), frame.n_views, _ptr(rgb), _ptr(tgt_rgb),
+                          float(lambda_ssim), _ptr(g_rgb), loss_out.data_ptr(), _stream(stream)), "gs_ssim")
 
 
 def gs_read_counters(frame: Frame, stream=None):

@@ -6,13 +6,21 @@
 
 namespace {
 
-// step <- step + 1; bias = {1 - beta1^step, sqrt(1 - beta2^step)} (computed in double).
-__global__ void k_adam_prep(int64_t* __restrict__ step, float* __restrict__ bias, float b1, float b2) {
+// Unless *skip_flags has the overflow bit (the frame's gradients are then undefined): step <- step + 1;
+// bias = {1 - beta1^step, sqrt(1 - beta2^step)} (computed in double), bias[2] = 0.  Otherwise bias[2] = 1 and
+// nothing else changes; the update kernels then leave every parameter and moment as it is.
+__global__ void k_adam_prep(int64_t* __restrict__ step, float* __restrict__ bias, float b1, float b2,
+                            const int32_t* __restrict__ skip_flags) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (skip_flags && (skip_flags[0] & GS_FLAG_INSTANCE_OVERFLOW)) {
+    bias[2] = 1.f;
+    return;
+  }
   const int64_t t = step[0] + 1;
   step[0] = t;
   bias[0] = (float)(1.0 - pow((double)b1, (double)t));
   bias[1] = (float)sqrt(1.0 - pow((double)b2, (double)t));
+  bias[2] = 0.f;
 }
 
 // period > 0: element i of the group uses lr0 when (i % period) < 3 (the degree-0 SH coefficients of a
@@ -21,6 +29,7 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
                                              float* __restrict__ m, float* __restrict__ v, int64_t n, float lr0,
                                              float lr1, int period, float b1, float b2, float eps,
                                              const float* __restrict__ bias) {
+  if (bias[2] != 0.f) return;  // skipped step
   const float bc1 = bias[0], bc2s = bias[1];
   const float s0 = lr0 / bc1, s1 = lr1 / bc1;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
@@ -83,9 +92,14 @@ hipError_t group(float* p, const float* g, float* m, float* v, int64_t n, float 
 
 namespace gs_launch {
 
+hipError_t adam_prep(const gs_adam& a, const int32_t* skip_flags, hipStream_t st) {
+  k_adam_prep<<<1, 64, 0, st>>>(a.step, a.bias, a.beta1, a.beta2, skip_flags);
+  return hipGetLastError();
+}
+
 hipError_t adam(const gs_params& p, const gs_params& g, const gs_params& m, const gs_params& v, const gs_adam& a,
                 hipStream_t st) {
-  k_adam_prep<<<1, 64, 0, st>>>(a.step, a.bias, a.beta1, a.beta2);
+  k_adam_prep<<<1, 64, 0, st>>>(a.step, a.bias, a.beta1, a.beta2, a.skip_flags);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n = p.n;

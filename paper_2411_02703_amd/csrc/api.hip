@@ -356,6 +356,7 @@ int gs_composite_bwd(const gs_frame* f, const gs_opts* o, const gs_images* fwd, 
   if (!l) return fail(GS_ERR_ARG, "loss is NULL");
   if (fwd && (!fwd->rgb || !fwd->depth || !fwd->vis)) return fail(GS_ERR_ARG, "forward images incomplete");
   if (l->tgt_rgb && !l->tgt_depth) return fail(GS_ERR_ARG, "loss mode needs tgt_depth");
+  if (!(l->lambda_ssim >= 0.f && l->lambda_ssim <= 1.f)) return fail(GS_ERR_ARG, "lambda_ssim outside [0, 1]");
   if (o->tile_w != f->tile_w || o->tile_h != f->tile_h) return fail(GS_ERR_ARG, "tile size differs from the frame");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (l->tgt_rgb) {
@@ -388,6 +389,44 @@ int gs_render_bwd(const gs_params* p, const gs_frame* f, const gs_opts* o, const
   return gs_project_bwd(p, f, o, grads, stream);
 }
 
+int gs_ssim(const gs_camera* cams_host, const gs_camera* cams_dev, int32_t V, const float* rgb, const float* tgt,
+            float lambda, float* g_rgb, float* loss_out, void* stream) {
+  if (!cams_host || !cams_dev || !rgb || !tgt || !g_rgb || !loss_out) return fail(GS_ERR_ARG, "NULL pointer");
+  if (V < 1 || V > GS_MAX_VIEWS) return fail(GS_ERR_ARG, "n_views = %d", V);
+  if (!(lambda >= 0.f && lambda <= 1.f)) return fail(GS_ERR_ARG, "lambda_ssim = %g", (double)lambda);
+  for (int v = 0; v < V; ++v)
+    if (cams_host[v].width < 1 || cams_host[v].height < 1) return fail(GS_ERR_ARG, "view %d has no pixels", v);
+  GS_HIP(gs_launch::ssim(cams_host, cams_dev, V, rgb, tgt, lambda, g_rgb, loss_out, static_cast<hipStream_t>(stream)),
+         "gs_ssim");
+  return GS_OK;
+}
+
+static int adam_check(const gs_adam* a) {
+  if (!a || !a->step || !a->bias) return fail(GS_ERR_ARG, "adam state is NULL");
+  if (!(a->beta1 >= 0.f && a->beta1 < 1.f) || !(a->beta2 >= 0.f && a->beta2 < 1.f) || !(a->eps >= 0.f))
+    return fail(GS_ERR_ARG, "invalid Adam hyper-parameters");
+  return GS_OK;
+}
+
+int gs_render_bwd_adam(const gs_params* p, const gs_frame* f, const gs_opts* o, const gs_images* fwd,
+                       const gs_loss* l, const gs_params* m, const gs_params* v, const gs_adam* a,
+                       const gs_params* grads_out, void* stream) {
+  int rc;
+  if ((rc = params_check(p, "params")) || (rc = params_check(m, "m")) || (rc = params_check(v, "v")) ||
+      (grads_out && (rc = params_check(grads_out, "grads_out"))) || (rc = frame_check(f)) || (rc = opts_check(o)) ||
+      (rc = adam_check(a)))
+    return rc;
+  if (p->n != f->n || m->n != f->n || v->n != f->n || m->sh_degree != p->sh_degree || v->sh_degree != p->sh_degree)
+    return fail(GS_ERR_ARG, "params / moments / frame sizes differ");
+  if (grads_out && (grads_out->n != f->n || grads_out->sh_degree != p->sh_degree))
+    return fail(GS_ERR_ARG, "grads_out / frame sizes differ");
+  if ((rc = gs_composite_bwd(f, o, fwd, l, stream))) return rc;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  GS_HIP(gs_launch::adam_prep(*a, f->counters + 1, st), "gs_render_bwd_adam: step");
+  GS_HIP(gs_launch::project_bwd_adam(*p, *f, *o, *m, *v, *a, grads_out, st), "gs_render_bwd_adam");
+  return GS_OK;
+}
+
 int gs_count_pairs(const gs_frame* f, const gs_opts* o, uint64_t* counts, void* stream) {
   int rc;
   if ((rc = frame_check(f)) || (rc = opts_check(o))) return rc;
@@ -408,9 +447,7 @@ int gs_adam_step(const gs_params* p, const gs_params* g, const gs_params* m, con
   if (g->n != p->n || m->n != p->n || v->n != p->n || g->sh_degree != p->sh_degree ||
       m->sh_degree != p->sh_degree || v->sh_degree != p->sh_degree)
     return fail(GS_ERR_ARG, "params / grads / moments sizes differ");
-  if (!a || !a->step || !a->bias) return fail(GS_ERR_ARG, "adam state is NULL");
-  if (!(a->beta1 >= 0.f && a->beta1 < 1.f) || !(a->beta2 >= 0.f && a->beta2 < 1.f) || !(a->eps >= 0.f))
-    return fail(GS_ERR_ARG, "invalid Adam hyper-parameters");
+  if ((rc = adam_check(a))) return rc;
   GS_HIP(gs_launch::adam(*p, *g, *m, *v, *a, static_cast<hipStream_t>(stream)), "gs_adam_step");
   return GS_OK;
 }

@@ -151,4 +151,13 @@ hipError_t render_bwd(const gs_frame& f, const gs_opts& o, const gs_images* fwd,
                       hipStream_t s);
 hipError_t adam(const gs_params& p, const gs_params& g, const gs_params& m, const gs_params& v,
                 const gs_adam& a, hipStream_t s);
+// SSIM term of the photometric loss: gradient written to g_rgb, value to loss[0] (loss holds 1 + kLossSlots).
+hipError_t ssim(const gs_camera* cams_host, const gs_camera* cams_dev, int n_views, const float* rgb,
+                const float* tgt, float lambda, float* g_rgb, float* loss, hipStream_t s);
+// The step counter and bias corrections of one Adam step (skipped when *skip_flags has the overflow bit).
+hipError_t adam_prep(const gs_adam& a, const int32_t* skip_flags, hipStream_t s);
+// Projection backward fused with Adam: params, m, v updated in place; the gradient is written to grads_out
+// when it is non-NULL.  The step's bias corrections come from adam_prep on the same stream.
+hipError_t project_bwd_adam(const gs_params& p, const gs_frame& f, const gs_opts& o, const gs_params& m,
+                            const gs_params& v, const gs_adam& a, const gs_params* grads_out, hipStream_t s);
 }  // namespace gs_launch

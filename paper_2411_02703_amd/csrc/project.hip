@@ -266,24 +266,46 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ means
 // Records with more tiles than this have their instance partials summed by the whole wave.
 constexpr int kSolo = 32;
 
-template <int DEG>
-__global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ means,
-                                                     const float* __restrict__ log_scales,
-                                                     const float* __restrict__ quats, const float* __restrict__ opac,
-                                                     const float* __restrict__ sh, int64_t n,
+// Adam's part of the fused backward: moments and parameters of one Gaussian, updated in place (the same
+// update as the separate Adam step: bias-corrected moments, eps added to the corrected root).
+struct AdamArgs {
+  float* m_means; float* m_scales; float* m_quats; float* m_opac; float* m_sh;
+  float* v_means; float* v_scales; float* v_quats; float* v_opac; float* v_sh;
+  float lr[6];
+  float b1, b2, eps;
+  const float* bias;  // {1 - b1^t, sqrt(1 - b2^t), skip}
+};
+
+__device__ __forceinline__ void adam_one(float& p, float& m, float& v, float g, float s, float b1, float b2,
+                                         float eps, float bc2s) {
+  m = b1 * m + (1.f - b1) * g;
+  v = b2 * v + (1.f - b2) * g * g;
+  p -= s * m / (sqrtf(v) / bc2s + eps);
+}
+
+// Projection backward, one thread per Gaussian.  ADAM = false: the parameter gradient is added to g_* (+=).
+// ADAM = true: every Gaussian (also those with no visible record, whose gradient is zero) takes its Adam step
+// here: params, m and v are updated in place and the gradient is written (=) to g_* only when g_means is
+// non-NULL.
+template <int DEG, bool ADAM>
+__global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, float* __restrict__ log_scales,
+                                                     float* __restrict__ quats, float* __restrict__ opac,
+                                                     float* __restrict__ sh, int64_t n,
                                                      const gs_camera* __restrict__ cams, int V, DevOpts op,
                                                      const float4* __restrict__ ipart,
                                                      const int32_t* __restrict__ inst_off, const short4* __restrict__ rect,
                                                      const int32_t* __restrict__ count_dev, int64_t capacity,
                                                      const uint64_t* __restrict__ vis_mask, float* __restrict__ g_means,
                                                      float* __restrict__ g_scales, float* __restrict__ g_quats,
-                                                     float* __restrict__ g_opac, float* __restrict__ g_sh) {
+                                                     float* __restrict__ g_opac, float* __restrict__ g_sh,
+                                                     AdamArgs ad) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   // every lane stays to the end of the view loop (the wave sums large records together)
   const uint64_t mask = g < n ? vis_mask[g] : 0ull;
-  const int64_t gg = mask ? g : 0;  // lanes without a visible record read Gaussian 0 and discard it
+  // lanes without a visible record read Gaussian 0 and discard it, unless they take an Adam step of their own
+  const int64_t gg = (ADAM ? g < n : mask != 0) ? g : 0;
   float mu[3], ls[3], qq[4], f[K * 3];
   for (int i = 0; i < 3; ++i) {
     mu[i] = means[gg * 3 + i];
@@ -431,38 +453,126 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float* __restrict__ m
       gmu[2] += (gz - z * dot) * idist;
     }
   }
-  if (mask == 0) return;
-  // Sigma = M M^T: dL/dM = 2 Gs M ; M = Rq diag(S)
-  const float Gs[9] = {gs[0], gs[1], gs[2], gs[1], gs[3], gs[4], gs[2], gs[4], gs[5]};
-  float GM[9];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j)
-      GM[i * 3 + j] = 2.f * (Gs[i * 3] * s.M[j] + Gs[i * 3 + 1] * s.M[3 + j] + Gs[i * 3 + 2] * s.M[6 + j]);
-  float gls[3], GR[9];
-  for (int j = 0; j < 3; ++j) {
-    const float dS = s.Rq[j] * GM[j] + s.Rq[3 + j] * GM[3 + j] + s.Rq[6 + j] * GM[6 + j];
-    gls[j] = dS * s.S[j];
-    for (int i = 0; i < 3; ++i) GR[i * 3 + j] = GM[i * 3 + j] * s.S[j];
+  if (!ADAM && mask == 0) return;
+  if (ADAM && g >= n) return;
+  float out_mu[3] = {0.f, 0.f, 0.f}, out_ls[3] = {0.f, 0.f, 0.f}, out_q[4] = {0.f, 0.f, 0.f, 0.f}, out_o = 0.f;
+  if (mask != 0) {
+    // Sigma = M M^T: dL/dM = 2 Gs M ; M = Rq diag(S)
+    const float Gs[9] = {gs[0], gs[1], gs[2], gs[1], gs[3], gs[4], gs[2], gs[4], gs[5]};
+    float GM[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        GM[i * 3 + j] = 2.f * (Gs[i * 3] * s.M[j] + Gs[i * 3 + 1] * s.M[3 + j] + Gs[i * 3 + 2] * s.M[6 + j]);
+    float GR[9];
+    for (int j = 0; j < 3; ++j) {
+      const float dS = s.Rq[j] * GM[j] + s.Rq[3 + j] * GM[3 + j] + s.Rq[6 + j] * GM[6 + j];
+      out_ls[j] = dS * s.S[j];
+      for (int i = 0; i < 3; ++i) GR[i * 3 + j] = GM[i * 3 + j] * s.S[j];
+    }
+    const float qw = s.q[0], qx = s.q[1], qy = s.q[2], qz = s.q[3];
+    float gq[4];
+    gq[0] = 2.f * (-qz * GR[1] + qy * GR[2] + qz * GR[3] - qx * GR[5] - qy * GR[6] + qx * GR[7]);
+    gq[1] = 2.f * (qy * GR[1] + qz * GR[2] + qy * GR[3] - 2.f * qx * GR[4] - qw * GR[5] + qz * GR[6] + qw * GR[7] -
+                   2.f * qx * GR[8]);
+    gq[2] = 2.f * (-2.f * qy * GR[0] + qx * GR[1] + qw * GR[2] + qx * GR[3] + qz * GR[5] - qw * GR[6] + qz * GR[7] -
+                   2.f * qy * GR[8]);
+    gq[3] = 2.f * (-2.f * qz * GR[0] - qw * GR[1] + qx * GR[2] + qw * GR[3] - 2.f * qz * GR[4] + qy * GR[5] +
+                   qx * GR[6] + qy * GR[7]);
+    const float dq = gq[0] * qw + gq[1] * qx + gq[2] * qy + gq[3] * qz;
+    const float iq = 1.f / s.qnorm;
+    for (int i = 0; i < 3; ++i) out_mu[i] = gmu[i];
+    for (int i = 0; i < 4; ++i) out_q[i] = (gq[i] - s.q[i] * dq) * iq;
+    out_o = go * s.o * (1.f - s.o);
   }
-  const float qw = s.q[0], qx = s.q[1], qy = s.q[2], qz = s.q[3];
-  float gq[4];
-  gq[0] = 2.f * (-qz * GR[1] + qy * GR[2] + qz * GR[3] - qx * GR[5] - qy * GR[6] + qx * GR[7]);
-  gq[1] = 2.f * (qy * GR[1] + qz * GR[2] + qy * GR[3] - 2.f * qx * GR[4] - qw * GR[5] + qz * GR[6] + qw * GR[7] -
-                 2.f * qx * GR[8]);
-  gq[2] = 2.f * (-2.f * qy * GR[0] + qx * GR[1] + qw * GR[2] + qx * GR[3] + qz * GR[5] - qw * GR[6] + qz * GR[7] -
-                 2.f * qy * GR[8]);
-  gq[3] = 2.f * (-2.f * qz * GR[0] - qw * GR[1] + qx * GR[2] + qw * GR[3] - 2.f * qz * GR[4] + qy * GR[5] +
-                 qx * GR[6] + qy * GR[7]);
-  const float dq = gq[0] * qw + gq[1] * qx + gq[2] * qy + gq[3] * qz;
-  const float iq = 1.f / s.qnorm;
-  for (int i = 0; i < 3; ++i) {
-    g_means[g * 3 + i] += gmu[i];
-    g_scales[g * 3 + i] += gls[i];
-  }
-  for (int i = 0; i < 4; ++i) g_quats[g * 4 + i] += (gq[i] - s.q[i] * dq) * iq;
-  g_opac[g] += go * s.o * (1.f - s.o);
+  if (!ADAM) {
+    for (int i = 0; i < 3; ++i) {
+      g_means[g * 3 + i] += out_mu[i];
+      g_scales[g * 3 + i] += out_ls[i];
+    }
+    for (int i = 0; i < 4; ++i) g_quats[g * 4 + i] += out_q[i];
+    g_opac[g] += out_o;
 #pragma unroll
-  for (int i = 0; i < K * 3; ++i) g_sh[g * (K * 3) + i] += gf[i];
+    for (int i = 0; i < K * 3; ++i) g_sh[g * (K * 3) + i] += gf[i];
+    return;
+  }
+  if (g_means) {
+    for (int i = 0; i < 3; ++i) {
+      g_means[g * 3 + i] = out_mu[i];
+      g_scales[g * 3 + i] = out_ls[i];
+    }
+    for (int i = 0; i < 4; ++i) g_quats[g * 4 + i] = out_q[i];
+    g_opac[g] = out_o;
+#pragma unroll
+    for (int i = 0; i < K * 3; ++i) g_sh[g * (K * 3) + i] = gf[i];
+  }
+  if (ad.bias[2] != 0.f) return;  // skipped step (instance capacity overflowed)
+  const float bc1 = ad.bias[0], bc2s = ad.bias[1];
+  const float b1 = ad.b1, b2 = ad.b2, eps = ad.eps;
+  {
+    float o = opac[g];
+    const float s3 = ad.lr[3] / bc1;
+    float mm = ad.m_opac[g], vv = ad.v_opac[g];
+    adam_one(o, mm, vv, out_o, s3, b1, b2, eps, bc2s);
+    opac[g] = o;
+    ad.m_opac[g] = mm;
+    ad.v_opac[g] = vv;
+  }
+  {
+    const float s0 = ad.lr[0] / bc1, s1 = ad.lr[1] / bc1;
+    for (int i = 0; i < 3; ++i) {
+      float mm = ad.m_means[g * 3 + i], vv = ad.v_means[g * 3 + i];
+      adam_one(mu[i], mm, vv, out_mu[i], s0, b1, b2, eps, bc2s);
+      means[g * 3 + i] = mu[i];
+      ad.m_means[g * 3 + i] = mm;
+      ad.v_means[g * 3 + i] = vv;
+      mm = ad.m_scales[g * 3 + i];
+      vv = ad.v_scales[g * 3 + i];
+      adam_one(ls[i], mm, vv, out_ls[i], s1, b1, b2, eps, bc2s);
+      log_scales[g * 3 + i] = ls[i];
+      ad.m_scales[g * 3 + i] = mm;
+      ad.v_scales[g * 3 + i] = vv;
+    }
+  }
+  {
+    const float s2 = ad.lr[2] / bc1;
+    float4 mq = reinterpret_cast<const float4*>(ad.m_quats)[g], vq = reinterpret_cast<const float4*>(ad.v_quats)[g];
+    adam_one(qq[0], mq.x, vq.x, out_q[0], s2, b1, b2, eps, bc2s);
+    adam_one(qq[1], mq.y, vq.y, out_q[1], s2, b1, b2, eps, bc2s);
+    adam_one(qq[2], mq.z, vq.z, out_q[2], s2, b1, b2, eps, bc2s);
+    adam_one(qq[3], mq.w, vq.w, out_q[3], s2, b1, b2, eps, bc2s);
+    reinterpret_cast<float4*>(quats)[g] = make_float4(qq[0], qq[1], qq[2], qq[3]);
+    reinterpret_cast<float4*>(ad.m_quats)[g] = mq;
+    reinterpret_cast<float4*>(ad.v_quats)[g] = vq;
+  }
+  {
+    // SH: the three degree-0 coefficients take lr[4], the others lr[5]
+    const float s4 = ad.lr[4] / bc1, s5 = ad.lr[5] / bc1;
+    float* msh = ad.m_sh + g * (K * 3);
+    float* vsh = ad.v_sh + g * (K * 3);
+    float* psh = sh + g * (K * 3);
+    if constexpr ((K * 3) % 4 == 0) {
+#pragma unroll
+      for (int c = 0; c < K * 3; c += 4) {
+        float4 m4 = *reinterpret_cast<const float4*>(msh + c), v4 = *reinterpret_cast<const float4*>(vsh + c);
+        adam_one(f[c], m4.x, v4.x, gf[c], c < 3 ? s4 : s5, b1, b2, eps, bc2s);
+        adam_one(f[c + 1], m4.y, v4.y, gf[c + 1], c + 1 < 3 ? s4 : s5, b1, b2, eps, bc2s);
+        adam_one(f[c + 2], m4.z, v4.z, gf[c + 2], c + 2 < 3 ? s4 : s5, b1, b2, eps, bc2s);
+        adam_one(f[c + 3], m4.w, v4.w, gf[c + 3], c + 3 < 3 ? s4 : s5, b1, b2, eps, bc2s);
+        *reinterpret_cast<float4*>(psh + c) = make_float4(f[c], f[c + 1], f[c + 2], f[c + 3]);
+        *reinterpret_cast<float4*>(msh + c) = m4;
+        *reinterpret_cast<float4*>(vsh + c) = v4;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < K * 3; ++c) {
+        float mm = msh[c], vv = vsh[c];
+        adam_one(f[c], mm, vv, gf[c], c < 3 ? s4 : s5, b1, b2, eps, bc2s);
+        psh[c] = f[c];
+        msh[c] = mm;
+        vsh[c] = vv;
+      }
+    }
+  }
 }
 
 }  // namespace
@@ -497,17 +607,23 @@ hipError_t project(const gs_params& p, const gs_frame& f, const gs_opts& o, hipS
   return hipGetLastError();
 }
 
-hipError_t project_bwd(const gs_params& p, const gs_frame& f, const gs_opts& o, const gs_params& gr, hipStream_t st) {
+template <bool ADAM>
+static hipError_t project_bwd_launch(const gs_params& p, const gs_frame& f, const gs_opts& o, const gs_params* gr,
+                                     const AdamArgs& ad, hipStream_t st) {
   const int threads = 256;
   const int blocks = (int)((p.n + threads - 1) / threads);
   const DevOpts op = gsk::dev_opts(o);
   const auto* ip = reinterpret_cast<const float4*>(f.ipart);
   const auto* rect = reinterpret_cast<const short4*>(f.rect);
+  float* gm = gr ? gr->means : nullptr;
+  float* gl = gr ? gr->log_scales : nullptr;
+  float* gq = gr ? gr->quats : nullptr;
+  float* go = gr ? gr->opacity : nullptr;
+  float* gsh = gr ? gr->sh : nullptr;
 #define GS_PB(D)                                                                                              \
-  k_project_bwd<D><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams,   \
-                                               f.n_views, op,                                                      \
-                                               ip, f.inst_off, rect, f.counters, f.capacity,                     \
-                                               f.vis_mask, gr.means, gr.log_scales, gr.quats, gr.opacity, gr.sh)
+  k_project_bwd<D, ADAM><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n,     \
+                                                     f.cams, f.n_views, op, ip, f.inst_off, rect, f.counters,    \
+                                                     f.capacity, f.vis_mask, gm, gl, gq, go, gsh, ad)
   switch (p.sh_degree) {
     case 0: GS_PB(0); break;
     case 1: GS_PB(1); break;
@@ -516,6 +632,24 @@ hipError_t project_bwd(const gs_params& p, const gs_frame& f, const gs_opts& o, 
   }
 #undef GS_PB
   return hipGetLastError();
+}
+
+hipError_t project_bwd(const gs_params& p, const gs_frame& f, const gs_opts& o, const gs_params& gr, hipStream_t st) {
+  AdamArgs none{};
+  return project_bwd_launch<false>(p, f, o, &gr, none, st);
+}
+
+hipError_t project_bwd_adam(const gs_params& p, const gs_frame& f, const gs_opts& o, const gs_params& m,
+                            const gs_params& v, const gs_adam& a, const gs_params* grads_out, hipStream_t st) {
+  AdamArgs ad;
+  ad.m_means = m.means; ad.m_scales = m.log_scales; ad.m_quats = m.quats; ad.m_opac = m.opacity; ad.m_sh = m.sh;
+  ad.v_means = v.means; ad.v_scales = v.log_scales; ad.v_quats = v.quats; ad.v_opac = v.opacity; ad.v_sh = v.sh;
+  for (int i = 0; i < 6; ++i) ad.lr[i] = a.lr[i];
+  ad.b1 = a.beta1;
+  ad.b2 = a.beta2;
+  ad.eps = a.eps;
+  ad.bias = a.bias;
+  return project_bwd_launch<true>(p, f, o, grads_out, ad, st);
 }
 
 }  // namespace gs_launch

@@ -416,6 +416,7 @@ struct BwdArgs {
   const float* tgt_depth;
   const int32_t* n_valid;  // per view
   float lambda_d;
+  float lambda_ssim;  // loss mode: the L1 colour term takes 1 - lambda_ssim; g_rgb (if given) is added
   float* ipart;        // [instance][12], in emission order
   const int32_t* emi;  // emission index of each sorted instance
   float* loss;
@@ -444,7 +445,7 @@ __device__ __forceinline__ void pixel_upstream(const TileCtx& t, const BwdArgs& 
   const int64_t P = (int64_t)t.W * t.H;
   const int64_t pi = (int64_t)t.py * t.W + t.px;
   if (LOSS) {
-    const float wrgb = t.weight / (3.f * (float)P);
+    const float wrgb = t.weight * (1.f - a.lambda_ssim) / (3.f * (float)P);
     const int M = a.n_valid[t.view];
     const float wd = M > 0 ? t.weight * a.lambda_d / (float)M : 0.f;
     const float er = Cf - a.tgt_rgb[3 * t.pix_off + pi];
@@ -454,6 +455,11 @@ __device__ __forceinline__ void pixel_upstream(const TileCtx& t, const BwdArgs& 
     gg = wrgb * gsk::sgnf(eg);
     gb = wrgb * gsk::sgnf(eb);
     loss_acc += wrgb * (fabsf(er) + fabsf(eg) + fabsf(eb));
+    if (a.g_rgb) {  // the gradient of a further colour term (the SSIM term of gs_ssim)
+      gr += a.g_rgb[3 * t.pix_off + pi];
+      gg += a.g_rgb[3 * t.pix_off + P + pi];
+      gb += a.g_rgb[3 * t.pix_off + 2 * P + pi];
+    }
     const float dt = a.tgt_depth[t.pix_off + pi];
     if (dt > 0.f) {
       const float ed = Df - dt;
@@ -1261,6 +1267,7 @@ hipError_t render_bwd(const gs_frame& f, const gs_opts& o, const gs_images* fwd,
   a.tgt_depth = l.tgt_depth;
   a.n_valid = f.counters + 2;
   a.lambda_d = l.lambda_d;
+  a.lambda_ssim = l.lambda_ssim;
   a.ipart = f.ipart;
   a.emi = f.vals[(f.sort_passes & 1) ^ 1];
   a.loss = f.loss;

@@ -3,6 +3,11 @@
 forward(means, log_scales, quats, opacity, sh) -> (rgb, depth, vis) for every view of a Rasterizer,
 backward(g_rgb, g_depth, g_vis) -> gradients of the five parameter groups.  All work runs in libgs; the
 backward needs only the forward's output images (no per-pixel state is stored).
+
+A Rasterizer's frame holds the binning of its latest forward.  Each forward records the frame's generation;
+a backward whose forward is no longer the latest one (another forward through the same Rasterizer came in
+between) projects and bins its own saved parameters again before the compositing backward, so that its
+gradient never mixes two forwards' binnings.
 """
 from __future__ import annotations
 
@@ -25,9 +30,11 @@ class Rasterizer:
         self.device = device
         self.frame = B.Frame(self.n, self.cams, self.opts, capacity, device)
         self.n_instances = 0
+        self.generation = 0  # incremented by every projection + binning into the frame
 
     def project_and_bin(self, ps: B.gs_params, stream=None) -> int:
         """Project and bin with a synchronised instance count; re-plan the frame on overflow."""
+        self.generation += 1
         while True:
             B.gs_project(ps, self.frame, stream=stream)
             n = B.gs_bin_tiles(self.frame, sync_count=True, stream=stream)
@@ -56,7 +63,7 @@ class GaussianRasterize(torch.autograd.Function):
         rgb, depth, vis = rast.frame.empty_images(rast.device)
         B.gs_render_fwd(rast.frame, rgb, depth, vis)
         ctx.rast = rast
-        ctx.frame = rast.frame
+        ctx.generation = rast.generation
         ctx.save_for_backward(params["means"], params["log_scales"], params["quats"], params["opacity"],
                               params["sh"], rgb, depth, vis)
         return rgb, depth, vis
@@ -69,12 +76,39 @@ class GaussianRasterize(torch.autograd.Function):
         ps = B.params_struct(params, rast.sh_degree)
         grads = {k: torch.zeros_like(v) for k, v in params.items()}
         gs = B.params_struct(grads, rast.sh_degree)
-        frame = ctx.frame
+        if rast.generation != ctx.generation:
+            # another forward re-binned the frame since ours: bin our parameters again (same records, same
+            # order: projection and binning are deterministic)
+            rast.project_and_bin(ps)
+        ctx.generation = rast.generation
         cont = lambda t: None if t is None else t.contiguous()
-        B.gs_render_bwd(ps, frame, (rgb, depth, vis), gs, g_rgb=cont(g_rgb), g_depth=cont(g_depth),
+        B.gs_render_bwd(ps, rast.frame, (rgb, depth, vis), gs, g_rgb=cont(g_rgb), g_depth=cont(g_depth),
                         g_vis=cont(g_vis))
         return grads["means"], grads["log_scales"], grads["quats"], grads["opacity"], grads["sh"], None
 
 
 def rasterize(means, log_scales, quats, opacity, sh, rast: Rasterizer):
     return GaussianRasterize.apply(means, log_scales, quats, opacity, sh, rast)
+
+
+class SSIMTerm(torch.autograd.Function):
+    """The SSIM term of eq. Lc, lambda sum_v w_v (1 - mean SSIM_v), of a Rasterizer's concatenated colour images
+    against targets of the same layout; gs_ssim forms its value and image gradient in one pass."""
+
+    @staticmethod
+    def forward(ctx, rgb, tgt_rgb, rast: Rasterizer, lam: float):
+        rgb = rgb.contiguous()
+        g = torch.empty_like(rgb)
+        loss = torch.zeros(64, device=rgb.device, dtype=torch.float32)
+        B.gs_ssim(rast.frame, rgb, tgt_rgb.contiguous(), lam, g, loss)
+        ctx.save_for_backward(g)
+        return loss[0].clone()
+
+    @staticmethod
+    def backward(ctx, g_out):
+        (g,) = ctx.saved_tensors
+        return g * g_out, None, None, None
+
+
+def ssim_term(rgb, tgt_rgb, rast: Rasterizer, lam: float = 0.2):
+    return SSIMTerm.apply(rgb, tgt_rgb, rast, lam)

@@ -8,8 +8,8 @@ PlainStep  : the per-view launch sequence (project, bin with a host-synchronised
              backward with the loss against the view's targets), then Adam.
 BatchedStep: all views in one frame - one projection launch that reads every Gaussian once, one binning
              over global (view, tile) keys sized by a capacity (no host synchronisation), one fused
-             forward + loss + backward compositing launch over every tile of every view, the projection
-             backward and Adam - captured once as a HIP graph and replayed.
+             forward + loss + backward compositing launch group over every tile of every view, and the
+             projection backward fused with Adam - captured once as a HIP graph and replayed.
 """
 from __future__ import annotations
 
@@ -40,7 +40,7 @@ class GaussianModel:
         self.m = {k: torch.zeros_like(v) for k, v in self.p.items()}
         self.v = {k: torch.zeros_like(v) for k, v in self.p.items()}
         self.step_count = torch.zeros(1, dtype=torch.int64, device=device)
-        self.bias = torch.zeros(2, dtype=torch.float32, device=device)
+        self.bias = torch.zeros(4, dtype=torch.float32, device=device)
         self.ps = B.params_struct(self.p, self.sh_degree)
         self.gs = B.params_struct(self.g, self.sh_degree)
         self.ms = B.params_struct(self.m, self.sh_degree)
@@ -95,15 +95,20 @@ class PlainStep:
     """The per-view launch sequence of the library calls (one frame per view)."""
 
     def __init__(self, model: GaussianModel, cams: Sequence, tgt_rgb: np.ndarray, tgt_depth: np.ndarray,
-                 lambda_d: float = 0.1, opts: Optional[B.gs_opts] = None, device: str = "cuda"):
+                 lambda_d: float = 0.1, opts: Optional[B.gs_opts] = None, device: str = "cuda",
+                 lambda_ssim: float = 0.0):
         self.model = model
         self.cams = list(cams)
         self.opts = opts if opts is not None else B.default_opts()
         self.lambda_d = float(lambda_d)
+        self.lambda_ssim = float(lambda_ssim)
         self.frames = [B.Frame(model.n, [c], self.opts, None, device) for c in self.cams]
         self.images = [f.empty_images(device) for f in self.frames]
         self.targets = _targets_for(self.cams, tgt_rgb, tgt_depth, device)
         self.device = device
+        if self.lambda_ssim > 0:
+            self.g_ssim = [torch.empty(3 * c.width * c.height, device=device) for c in self.cams]
+            self.ssim_loss = [torch.zeros(64, device=device) for _ in self.cams]
 
     def run(self) -> None:
         m = self.model
@@ -119,36 +124,64 @@ class PlainStep:
             rgb, depth, vis = self.images[v]
             B.gs_render_fwd(fr, rgb, depth, vis)
             tr, td = self.targets[v]
-            B.gs_render_bwd(m.ps, fr, (rgb, depth, vis), m.gs, tgt_rgb=tr, tgt_depth=td, lambda_d=self.lambda_d)
+            g_ssim = None
+            if self.lambda_ssim > 0:
+                g_ssim = self.g_ssim[v]
+                B.gs_ssim(fr, rgb, tr, self.lambda_ssim, g_ssim, self.ssim_loss[v])
+            B.gs_render_bwd(m.ps, fr, (rgb, depth, vis), m.gs, g_rgb=g_ssim, tgt_rgb=tr, tgt_depth=td,
+                            lambda_d=self.lambda_d, lambda_ssim=self.lambda_ssim)
         m.adam_step()
 
     def loss(self) -> float:
         """Sum of the per-view loss values of the last run (synchronises)."""
         tot = 0.0
-        for fr in self.frames:
+        for v, fr in enumerate(self.frames):
             t = B.frame_tensor(fr, "loss", 1, torch.float32)
             tot += float(t.item())
+            if self.lambda_ssim > 0:
+                tot += float(self.ssim_loss[v][0].item())
         return tot
 
 
 class BatchedStep:
-    """All views in one frame, fused forward + loss + backward, captured as a HIP graph."""
+    """All views in one frame: projection, binning, the fused forward + loss + backward compositing, and the
+    projection backward fused with Adam (one pass per Gaussian, no gradient buffer), captured as a HIP graph.
+
+    Capacity: the instance count is measured once and given `headroom`.  A replay whose instances exceed the
+    capacity leaves the model untouched (the library skips the Adam step of an overflowed frame).  run() reads
+    each replay's counters one replay late (no stall: the next replay is already queued); on an overflow it
+    re-plans the capacity at `regrow` times the largest count seen, re-captures the graph and runs the skipped
+    steps again, so the sequence of parameter updates is the one a large enough frame would have produced.
+    keep_grads: also write each step's gradient to model.g (for inspection; costs one extra write).
+    lambda_ssim > 0 adds the SSIM term of eq. Lc: its window couples neighbouring pixels, so the step then renders
+    the images (gs_render_fwd), forms the SSIM gradient image (gs_ssim) and runs the image-fed backward with it,
+    instead of the fused forward + backward that needs no image."""
 
     def __init__(self, model: GaussianModel, cams: Sequence, tgt_rgb: np.ndarray, tgt_depth: np.ndarray,
                  lambda_d: float = 0.1, opts: Optional[B.gs_opts] = None, device: str = "cuda",
-                 capacity: Optional[int] = None, headroom: float = 1.25):
+                 capacity: Optional[int] = None, headroom: float = 1.25, regrow: float = 1.5,
+                 keep_grads: bool = False, lambda_ssim: float = 0.0):
         self.model = model
         self.cams = list(cams)
         self.opts = opts if opts is not None else B.default_opts()
         self.lambda_d = float(lambda_d)
+        self.lambda_ssim = float(lambda_ssim)
         self.device = device
         self.headroom = headroom
+        self.regrow = regrow
+        self.keep_grads = keep_grads
         self.tgt_rgb = torch.as_tensor(tgt_rgb).to(device).contiguous()
         self.tgt_depth = torch.as_tensor(tgt_depth).to(device).contiguous()
         if capacity is None:
             capacity = self._measure_capacity()
         self.frame = B.Frame(model.n, self.cams, self.opts, capacity, device)
+        self._ssim_buffers()
         self.graph: Optional[torch.cuda.CUDAGraph] = None
+        self.replans = 0
+        self.steps_redone = 0
+        self._host = torch.zeros((2, 2), dtype=torch.int32, pin_memory=True)
+        self._pending: List = []  # (event, slot) of replays whose counters have not been checked
+        self._slot = 0
 
     def _measure_capacity(self) -> int:
         probe = B.Frame(self.model.n, self.cams, self.opts, max(1 << 20, 8 * self.model.n), self.device)
@@ -157,35 +190,106 @@ class BatchedStep:
         del probe
         return int(n * self.headroom) + 4096
 
+    def _ssim_buffers(self) -> None:
+        if self.lambda_ssim > 0:
+            self.images = self.frame.empty_images(self.device)
+            self.g_ssim = torch.empty_like(self.images[0])
+            self.ssim_loss = torch.zeros(64, device=self.device)
+
     def _body(self, stream=None) -> None:
         m = self.model
-        for t in m.g.values():
-            t.zero_()
         B.gs_project(m.ps, self.frame, stream=stream)
         B.gs_bin_tiles(self.frame, sync_count=False, stream=stream)
-        B.gs_render_bwd(m.ps, self.frame, None, m.gs, tgt_rgb=self.tgt_rgb, tgt_depth=self.tgt_depth,
-                        lambda_d=self.lambda_d, stream=stream)
-        m.adam_step(stream)
+        grads = m.gs if self.keep_grads else None
+        if self.lambda_ssim > 0:
+            rgb, depth, vis = self.images
+            B.gs_render_fwd(self.frame, rgb, depth, vis, stream=stream)
+            B.gs_ssim(self.frame, rgb, self.tgt_rgb, self.lambda_ssim, self.g_ssim, self.ssim_loss, stream=stream)
+            B.gs_render_bwd_adam(m.ps, self.frame, self.images, m.ms, m.vs, m.adam, grads, g_rgb=self.g_ssim,
+                                 tgt_rgb=self.tgt_rgb, tgt_depth=self.tgt_depth, lambda_d=self.lambda_d,
+                                 lambda_ssim=self.lambda_ssim, stream=stream)
+        else:
+            B.gs_render_bwd_adam(m.ps, self.frame, None, m.ms, m.vs, m.adam, grads, tgt_rgb=self.tgt_rgb,
+                                 tgt_depth=self.tgt_depth, lambda_d=self.lambda_d, stream=stream)
 
     def run_eager(self) -> None:
+        """One step without the graph (the same library calls); the overflow is checked at once."""
         self._body()
+        n, fl = B.gs_read_counters(self.frame)
+        if fl & B.GS_FLAG_INSTANCE_OVERFLOW:
+            self._replan(n)
+            self.steps_redone += 1
+            self.run_eager()
 
     def capture(self) -> None:
+        """Capture the step as a graph.  The warm-up run that precedes the capture is undone, so capturing does
+        not advance the model."""
+        m = self.model
+        snap = [t.clone() for d in (m.p, m.m, m.v) for t in d.values()] + [m.step_count.clone(), m.bias.clone()]
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
             self._body(s)  # warm-up on the side stream (not captured)
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
+        dst = [t for d in (m.p, m.m, m.v) for t in d.values()] + [m.step_count, m.bias]
+        for a, b in zip(dst, snap):
+            a.copy_(b)
+        torch.cuda.synchronize()
+        del snap
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
             self._body()
         self.graph = g
 
+    def _replay(self) -> None:
+        self.graph.replay()
+        slot = self._slot
+        self._slot ^= 1
+        self._host[slot].copy_(B.frame_tensor(self.frame, "counters", 2, torch.int32), non_blocking=True)
+        ev = torch.cuda.Event()
+        ev.record()
+        self._pending.append((ev, slot))
+
     def run(self) -> None:
+        """One step (a graph replay); checks the previous replay's counters."""
         if self.graph is None:
             self.capture()
-        self.graph.replay()
+        self._replay()
+        if len(self._pending) > 1:
+            self._check(self._pending.pop(0))
+
+    def finish(self) -> None:
+        """Wait for the queued replays and handle an overflow among them."""
+        while self._pending:
+            self._check(self._pending.pop(0))
+
+    def _check(self, item) -> None:
+        ev, slot = item
+        ev.synchronize()
+        n, fl = (int(x) for x in self._host[slot].tolist())
+        if not fl & B.GS_FLAG_INSTANCE_OVERFLOW:
+            return
+        # this replay (and possibly the queued ones) skipped its step: re-plan, re-capture, run them again
+        torch.cuda.synchronize()
+        lost, n_max = 1, n
+        for ev2, slot2 in self._pending:
+            n2, fl2 = (int(x) for x in self._host[slot2].tolist())
+            n_max = max(n_max, n2)
+            lost += 1 if fl2 & B.GS_FLAG_INSTANCE_OVERFLOW else 0
+        self._pending.clear()
+        self._replan(n_max)
+        self.steps_redone += lost
+        for _ in range(lost):
+            self.run()
+        self.finish()
+
+    def _replan(self, n_needed: int) -> None:
+        self.replans += 1
+        cap = int(n_needed * self.regrow) + 4096
+        self.graph = None
+        self.frame = B.Frame(self.model.n, self.cams, self.opts, cap, self.device)
+        self._ssim_buffers()
 
     def flags(self) -> int:
         _, fl = B.gs_read_counters(self.frame)
@@ -195,7 +299,10 @@ class BatchedStep:
         return bool(self.flags() & B.GS_FLAG_INSTANCE_OVERFLOW)
 
     def loss(self) -> float:
-        return float(B.frame_tensor(self.frame, "loss", 1, torch.float32).item())
+        L = float(B.frame_tensor(self.frame, "loss", 1, torch.float32).item())
+        if self.lambda_ssim > 0:
+            L += float(self.ssim_loss[0].item())
+        return L
 
     def n_instances(self) -> int:
         n, _ = B.gs_read_counters(self.frame)

@@ -134,3 +134,43 @@ def l1_loss(outs, cams, tgt_rgb, tgt_depth, lambda_d=0.1):
             L = L + cam.weight * lambda_d * (D - Dt).abs()[valid].sum() / valid.sum()
         off += P
     return L
+
+
+def ssim_loss(outs, cams, tgt_rgb, lam):
+    """sum_v w_v lam (1 - mean SSIM_v): SSIM per channel with an 11 x 11 Gaussian window (sigma 1.5, summing
+    to 1) applied by a zero-padded 2D convolution, C1 = 0.01^2, C2 = 0.03^2 (eq. Lc with the 3DGS readings)."""
+    g = torch.exp(-torch.arange(-5, 6, dtype=torch.float64) ** 2 / (2 * 1.5 ** 2))
+    g = g / g.sum()
+    win = torch.outer(g, g)[None, None]
+    c1, c2 = 0.01 ** 2, 0.03 ** 2
+    L = 0.0
+    off = 0
+    for (C, _, _), cam in zip(outs, cams):
+        P = cam.width * cam.height
+        I = torch.as_tensor(tgt_rgb[3 * off:3 * off + 3 * P], dtype=torch.float64).reshape(3, 1, cam.height, cam.width)
+        X = C.reshape(3, 1, cam.height, cam.width)
+        f = lambda z: torch.nn.functional.conv2d(z, win, padding=5)
+        mx, my = f(X), f(I)
+        sx = f(X * X) - mx * mx
+        sy = f(I * I) - my * my
+        sxy = f(X * I) - mx * my
+        S = (2 * mx * my + c1) * (2 * sxy + c2) / ((mx * mx + my * my + c1) * (sx + sy + c2))
+        L = L + cam.weight * lam * (1.0 - S.mean())
+        off += P
+    return L
+
+
+def photometric_loss(outs, cams, tgt_rgb, tgt_depth, lambda_d=0.1, lambda_ssim=0.0):
+    """sum_v w_v [ (1 - lambda_ssim) mean |C - I| + lambda_ssim (1 - SSIM_v) + lambda_d mean_valid |D - D_lidar| ]."""
+    L = 0.0
+    off = 0
+    for (C, D, _), cam in zip(outs, cams):
+        P = cam.width * cam.height
+        I = torch.as_tensor(tgt_rgb[3 * off:3 * off + 3 * P], dtype=torch.float64).reshape(3, cam.height, cam.width)
+        Dt = torch.as_tensor(tgt_depth[off:off + P], dtype=torch.float64).reshape(cam.height, cam.width)
+        L = L + cam.weight * (1.0 - lambda_ssim) * (C - I).abs().sum() / (3 * P)
+        valid = Dt > 0
+        if valid.any():
+            L = L + cam.weight * lambda_d * (D - Dt).abs()[valid].sum() / valid.sum()
+        off += P
+    return L + ssim_loss(outs, cams, tgt_rgb, lambda_ssim)

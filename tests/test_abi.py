@@ -44,7 +44,8 @@ def test_struct_layouts(lib):
     assert ctypes.sizeof(B.gs_camera) == 128
     assert ctypes.sizeof(B.gs_opts) == 64
     assert ctypes.sizeof(B.gs_params) == 56
-    assert lib.gs_version() == 1
+    assert ctypes.sizeof(B.gs_adam) == 64
+    assert lib.gs_version() == 2
 
 
 def test_default_opts_and_status_strings(lib):
@@ -121,6 +122,8 @@ def test_argument_errors_return_before_any_launch(lib):
     assert lib.gs_render_fwd(ctypes.byref(f), ctypes.byref(o), None, None) == -1
     assert lib.gs_adam_step(ctypes.byref(p), ctypes.byref(p), ctypes.byref(p), ctypes.byref(p), None, None) == -1
     assert lib.gs_sort_pairs(None, None, None, None, 10, 40, None, None) == -1
+    assert lib.gs_render_bwd_adam(ctypes.byref(p), ctypes.byref(f), ctypes.byref(o), None, None, ctypes.byref(p),
+                                  ctypes.byref(p), None, None, None) == -1
     p.means = p.log_scales = p.quats = p.opacity = p.sh = 4096
     p.n = 10
     p.sh_degree = 4

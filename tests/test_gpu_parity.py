@@ -6,10 +6,11 @@ absolute) of the FP32 oracle; gradients within 1e-3 of the FP64 oracle relative 
 RMS of the parameter group, plus 2 x 2^-24 times the oracle's rounding scale of the entry (the sum of the
 magnitudes of the terms it adds, weighted by their operation depth: where those terms cancel, no FP32
 evaluation gets closer).  The FP64 reference takes every discrete choice (cull, skip, clamp, stop, colour
-clamp, loss sign) as the FP32 evaluation takes it, as the kernels do.  Decisions that FP32 rounding in
-another order may still flip (a pair within 1e-5 of the 1/255 skip, the 0.99 clamp or the 1e-4 stop, a loss
-sign at |C - I| < 1e-5, a cull or colour clamp near its threshold) are excused where the oracle flags them,
-counted, and bounded.
+clamp, loss sign) as the FP32 evaluation takes it, as the kernels do.  A per-pixel decision that FP32
+rounding in another order may still flip (a pair within 1e-5 of the 1/255 skip, the 0.99 clamp or the 1e-4
+stop, a loss sign at |C - I| < 1e-5) adds its flip allowance to the bar of the entries it feeds: the change
+of that entry when the decision alone is taken the other way, computed by the oracle.  Only Gaussians with a
+cull or colour-clamp decision near its threshold are excused outright: at most 1e-3 of them.
 """
 import math
 
@@ -99,19 +100,28 @@ def check_images(gpu, ref, near, what=""):
 
 
 def grad_reference(params, deg, cams, **kw):
-    """FP64 loss and gradients along the FP32 decisions, excused Gaussians, near-threshold pixel count and
-    the FP32 rounding scale of every gradient entry."""
-    L, ref, exc, nn, _ = oracle.backward(64, params, deg, cams, decisions=32, **kw)
-    return L, ref, exc, nn, oracle.gradient_scale(params, deg, cams, **kw)
+    """FP64 loss and gradients along the FP32 decisions, their flip allowances, the Gaussians excused outright,
+    the near-threshold pixel count and the FP32 rounding scale of every gradient entry."""
+    r = oracle.reference(params, deg, cams, **kw)
+    ref = dict(r["grads"])
+    ref["_allowance"] = r["allowance"]
+    return r["loss"], ref, r["excused"], r["near_pixels"], oracle.gradient_scale(params, deg, cams, **kw)
 
 
-def check_grads(gpu, ref, excused, what="", near_pixels=0, n_pixels=1, scale=None, max_excused=0.05):
-    """Gradient bar; Gaussians touching a near-threshold pixel are excused (those pixels <= 1e-3 of all)."""
+MAX_EXCUSED = 1e-3
+
+
+def check_grads(gpu, ref, excused, what="", near_pixels=0, n_pixels=1, scale=None, max_excused=MAX_EXCUSED):
+    """Gradient bar plus each entry's flip allowance; Gaussians with a near cull or colour-clamp decision are
+    excused (at most max_excused of them, or 2 on tiny scenes); near-threshold pixels are at most 1e-3 of all."""
+    allow = ref.get("_allowance")
     n_exc = int(excused.sum())
     log(f"{what}: excused Gaussians {n_exc} / {excused.size}, near-threshold pixels {near_pixels} / {n_pixels}")
     assert near_pixels <= max(2, 1e-3 * n_pixels), (what, near_pixels)
-    assert n_exc <= max_excused * excused.size, (what, n_exc)
+    assert n_exc <= max(2, max_excused * excused.size), (what, n_exc)
     for k in ref:
+        if k.startswith("_"):
+            continue
         r = np.asarray(ref[k]).reshape(excused.size, -1)
         g = np.asarray(gpu[k], np.float64).reshape(excused.size, -1)
         keep = ~excused
@@ -125,13 +135,19 @@ def check_grads(gpu, ref, excused, what="", near_pixels=0, n_pixels=1, scale=Non
                 log(f"  {k}: {int(over.sum())} entries past the 1e-3 bar within the rounding term; "
                     f"max err / (2^-24 scale) there {float((err[over] / (U32 * s[over] + 1e-300)).max()):.3g}")
             tol = tol + ROUND_C * U32 * s
+        if allow is not None:
+            a = np.asarray(allow[k]).reshape(excused.size, -1)[keep]
+            over = err > tol
+            log(f"  {k}: {int((a > 0).sum())} entries hold a flip allowance, {int(over.sum())} of them use it")
+            tol = tol + a
         bad = err > tol
         assert not bad.any(), (f"{what} {k}: {bad.sum()} / {bad.size} off; worst err {err.max():.3e}, "
                                f"rms {rms:.3e}")
 
 
 # ----------------------------------------------------------------------------- sort (bit-exact)
-@pytest.mark.parametrize("n,bits", [(1, 40), (4095, 38), (4096, 40), (4097, 45), (100_003, 48), (1_300_001, 49)])
+@pytest.mark.parametrize("n,bits", [(1, 40), (4095, 38), (4096, 40), (4097, 45), (100_003, 48), (1_300_001, 49),
+                                    (16_000_001, 49)])
 def test_radix_sort_matches_stable_argsort(gpu_lib, n, bits):
     rng = np.random.default_rng(n)
     # few distinct high parts and many ties, like (tile, depth) keys
@@ -214,6 +230,38 @@ def test_binning_matches_oracle(gpu_lib, seed, n, W, H, mu):
     log("tiles differing only in marginal records:", n_diff, "marginal records:", len(marginal))
     if not marginal:
         assert np.array_equal(vals, rv) and np.array_equal(keys, rk)
+
+
+def test_full_size_batch_binning_is_bit_exact_from_gpu_records(gpu_lib):
+    """The 24-view batch (1M Gaussians, SH degree 3, ~14.7M instances, 48-bit keys), binned the way the batched
+    step bins it (sync_count=0: every grid sized by the capacity, the instance count read on the device).  The
+    GPU's own records (tile rectangles, depth bits, visibility) fed to the oracle's binning give the same
+    instance count, sorted keys, record ids and tile ranges, bit for bit, with no exclusions."""
+    sc = scenes.config(4)
+    model = GaussianModel(sc.params(), sc.sh_degree)
+    fr = B.Frame(model.n, sc.cams, B.default_opts(), 24_000_000)
+    log("full-size binning: project + bin (device count)")
+    B.gs_project(model.ps, fr)
+    assert B.gs_bin_tiles(fr, sync_count=False) is None
+    I, flags = B.gs_read_counters(fr)
+    log("instances", I, "flags", flags, "key bits", fr.f.key_bits, "passes", fr.f.sort_passes)
+    assert flags == 0 and 10_000_000 < I <= fr.capacity
+    keys, vals = B.sorted_pairs(fr, I)
+    keys = keys.cpu().numpy().view(np.uint64)
+    vals = vals.cpu().numpy()
+    nt = fr.f.n_tiles
+    rng_ = B.frame_tensor(fr, "tile_range", 2 * nt, torch.int32).view(-1, 2).cpu().numpy()
+    rec, rect, vis = gpu_records(fr, sc.n, len(sc.cams))
+    zbits = np.ascontiguousarray(rec[:, 2]).view(np.uint32)
+    del rec
+    rk, rv, lo, hi = oracle.bin_records(rect, zbits, vis.astype(np.int32), sc.n, sc.cams)
+    assert len(rk) == I
+    assert np.array_equal(keys, rk)
+    assert np.array_equal(vals.astype(np.int64), rv)
+    empty = lo == hi
+    assert np.array_equal(rng_[~empty, 0], lo[~empty]) and np.array_equal(rng_[~empty, 1], hi[~empty])
+    assert np.all(rng_[empty, 0] == rng_[empty, 1])
+    log("full-size binning bit-exact:", I, "instances,", int((~empty).sum()), "non-empty tiles of", nt)
 
 
 # ----------------------------------------------------------------------------- forward
@@ -320,13 +368,15 @@ def test_adam_matches_oracle(gpu_lib):
 
 # ----------------------------------------------------------------------------- batched step
 def test_batched_graph_step_matches_plain_step(gpu_lib):
+    """The batched step (one frame, fused compositing, projection backward fused with Adam) against the plain
+    per-view sequence (gs_render_bwd per view, then gs_adam_step): loss, gradients and parameters."""
     sc = scenes.random_scene(800, 3000, 120, 90, sh_degree=1, views=4, log_scale_mu=-2.3, depth_fraction=0.2)
     log("batched vs plain")
     ma = GaussianModel(sc.params(), 1)
     mb = GaussianModel(sc.params(), 1)
     plain = PlainStep(ma, sc.cams, sc.tgt_rgb, sc.tgt_depth)
     plain.run()
-    bat = BatchedStep(mb, sc.cams, sc.tgt_rgb, sc.tgt_depth)
+    bat = BatchedStep(mb, sc.cams, sc.tgt_rgb, sc.tgt_depth, keep_grads=True)
     bat.run_eager()
     torch.cuda.synchronize()
     np.testing.assert_allclose(bat.loss(), plain.loss(), rtol=1e-5)
@@ -347,19 +397,22 @@ def test_graph_replays_match_eager(gpu_lib):
     sc = scenes.random_scene(900, 2000, 96, 80, sh_degree=2, views=3, log_scale_mu=-2.3, depth_fraction=0.2)
     me = GaussianModel(sc.params(), 2)
     mg = GaussianModel(sc.params(), 2)
-    eager = BatchedStep(me, sc.cams, sc.tgt_rgb, sc.tgt_depth)
-    graph = BatchedStep(mg, sc.cams, sc.tgt_rgb, sc.tgt_depth)
-    graph.capture()  # capture warms up with one eager step
-    eager.run_eager()
+    eager = BatchedStep(me, sc.cams, sc.tgt_rgb, sc.tgt_depth, keep_grads=True)
+    graph = BatchedStep(mg, sc.cams, sc.tgt_rgb, sc.tgt_depth, keep_grads=True)
+    graph.capture()  # the warm-up before the capture is undone: the model has not moved
+    assert int(mg.step_count.item()) == 0
+    for k in me.p:
+        assert torch.equal(mg.p[k], me.p[k]), k
     # Adam moves a parameter by about lr * sign(g) per step, and the order of the LDS float additions varies
     # from run to run: parameters are compared while every gradient they took had a sign set by more than
     # FP32 rounding (the rotation gradients of near-isotropic Gaussians are pure rounding).
     scale = oracle.gradient_scale(sc.params(), 2, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
     rnd = {k: ROUND_C * U32 * scale[k].reshape(tuple(me.p[k].shape)) for k in me.p}
-    firm = {k: (np.abs(me.g[k].cpu().numpy()) > 8 * rnd[k]) | (rnd[k] == 0) for k in me.p}
+    firm = {k: np.ones(me.p[k].shape, bool) for k in me.p}
     for it in range(4):
         eager.run_eager()
         graph.run()
+        graph.finish()
         torch.cuda.synchronize()
         np.testing.assert_allclose(graph.loss(), eager.loss(), rtol=1e-5)
         for k in me.p:
@@ -369,7 +422,8 @@ def test_graph_replays_match_eager(gpu_lib):
         log(f"replay {it}: parameters compared", sum(int(f.sum()) for f in firm.values()), "of",
             sum(f.size for f in firm.values()))
         _ = torch.ones(10, device="cuda").sum().item()  # eager work between replays
-    assert not graph.overflowed()
+    assert not graph.overflowed() and graph.replans == 0
+    assert int(mg.step_count.item()) == int(me.step_count.item()) == 4
 
 
 # ----------------------------------------------------------------------------- edge cases
@@ -415,7 +469,7 @@ def test_backward_rewrites_every_instance_partial(gpu_lib):
     _backward_on_frame(sa, fr)
     model, g1 = _backward_on_frame(sb, fr)
     L, ref, exc, nn, scale = grad_reference(sb.params(), 1, sb.cams, tgt_rgb=sb.tgt_rgb, tgt_depth=sb.tgt_depth)
-    hidden = np.all(np.stack([np.abs(ref[k]).reshape(sb.n, -1).max(1) for k in ref]) == 0, axis=0)
+    hidden = np.all(np.stack([np.abs(ref[k]).reshape(sb.n, -1).max(1) for k in ref if not k.startswith("_")]) == 0, axis=0)
     log("hidden Gaussians", int(hidden.sum()))
     assert hidden.sum() > 1000
     for k in g1:
@@ -448,18 +502,84 @@ def test_nonfinite_parameters_are_flagged_and_culled(gpu_lib):
     assert np.isfinite(out["rgb"]).all()
 
 
-def test_capacity_overflow_is_flagged_without_fault(gpu_lib):
+def test_capacity_overflow_is_flagged_and_skips_the_adam_step(gpu_lib):
+    """An overflowed frame is flagged without fault, its count is the full instance count, and the fused
+    backward + Adam leaves parameters, moments and the step counter as they were."""
     sc = scenes.random_scene(1300, 2000, 96, 64, log_scale_mu=-2.0, depth_fraction=0.3)
     model = GaussianModel(sc.params(), 0)
-    step = BatchedStep(model, sc.cams, sc.tgt_rgb, sc.tgt_depth, capacity=100)
-    step.run_eager()
+    before = {k: v.clone() for k, v in model.p.items()}
+    fr = B.Frame(model.n, sc.cams, B.default_opts(), 100)
+    B.gs_project(model.ps, fr)
+    B.gs_bin_tiles(fr, sync_count=False)
+    tr, td = torch.as_tensor(sc.tgt_rgb).cuda(), torch.as_tensor(sc.tgt_depth).cuda()
+    B.gs_render_bwd_adam(model.ps, fr, None, model.ms, model.vs, model.adam, None, tgt_rgb=tr, tgt_depth=td)
+    n, flags = B.gs_read_counters(fr)
+    assert flags & B.GS_FLAG_INSTANCE_OVERFLOW and n > 100
+    assert int(model.step_count.item()) == 0
+    for k in model.p:
+        assert torch.equal(model.p[k], before[k]), k
+        assert not model.m[k].any() and not model.v[k].any(), k
+    # the separate Adam step gated on the same flag
+    model.adam.skip_flags = B.frame_tensor(fr, "counters", 2, torch.int32)[1:].data_ptr()
+    model.adam_step()
     torch.cuda.synchronize()
-    assert step.overflowed()
-    n = step.n_instances()
-    assert n > 100
-    ok = BatchedStep(GaussianModel(sc.params(), 0), sc.cams, sc.tgt_rgb, sc.tgt_depth)
-    ok.run_eager()
-    assert not ok.overflowed()
+    assert int(model.step_count.item()) == 0
+    for k in model.p:
+        assert torch.equal(model.p[k], before[k]), k
+
+
+def test_batched_step_replans_after_overflow_and_matches_a_sized_step(gpu_lib):
+    """A batched step that starts from a tiny capacity overflows; the library skips the overflowed steps, and the
+    step re-plans the capacity, re-captures the graph and runs the skipped steps again.  (a) Found by finish():
+    after one step, loss, gradients and parameters are those of a step sized right from the start.  (b) Found one
+    replay late by the next run(): both queued replays overflowed and both are redone, so two run() calls
+    still take exactly two steps, again matching the sized step."""
+    sc = scenes.random_scene(1310, 2500, 96, 64, sh_degree=1, views=3, log_scale_mu=-2.2, depth_fraction=0.3)
+    scale = oracle.gradient_scale(sc.params(), 1, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
+    mr = GaussianModel(sc.params(), 1)
+    sized = BatchedStep(mr, sc.cams, sc.tgt_rgb, sc.tgt_depth, keep_grads=True)
+    rnd = {k: ROUND_C * U32 * scale[k].reshape(tuple(mr.p[k].shape)) for k in mr.p}
+    firm = {k: np.ones(mr.p[k].shape, bool) for k in mr.p}
+    ref = []
+    for it in range(2):
+        sized.run()
+        sized.finish()
+        torch.cuda.synchronize()
+        for k in mr.p:
+            firm[k] &= (np.abs(mr.g[k].cpu().numpy()) > 8 * rnd[k]) | (rnd[k] == 0)
+        ref.append(dict(loss=sized.loss(), g={k: v.cpu().numpy().copy() for k, v in mr.g.items()},
+                        p={k: v.cpu().numpy().copy() for k, v in mr.p.items()},
+                        firm={k: v.copy() for k, v in firm.items()}))
+    assert sized.replans == 0
+    # (a) one step, the overflow found by finish()
+    ma = GaussianModel(sc.params(), 1)
+    small = BatchedStep(ma, sc.cams, sc.tgt_rgb, sc.tgt_depth, capacity=64, keep_grads=True)
+    small.run()
+    small.finish()
+    torch.cuda.synchronize()
+    log("(a) replans", small.replans, "steps redone", small.steps_redone, "capacity", small.frame.capacity)
+    assert small.replans == 1 and small.steps_redone == 1 and not small.overflowed()
+    assert int(ma.step_count.item()) == 1
+    np.testing.assert_allclose(small.loss(), ref[0]["loss"], rtol=1e-5)
+    for k in ma.p:
+        a, b = ma.g[k].cpu().numpy(), ref[0]["g"][k]
+        assert np.all(np.abs(a.astype(np.float64) - b) <= 1e-5 * np.abs(b) + 2 * rnd[k]), k
+        f = ref[0]["firm"][k]
+        np.testing.assert_allclose(ma.p[k].cpu().numpy()[f], ref[0]["p"][k][f], rtol=1e-5, atol=1e-7, err_msg=k)
+    # (b) two run() calls, the overflow found one replay late
+    mb = GaussianModel(sc.params(), 1)
+    late = BatchedStep(mb, sc.cams, sc.tgt_rgb, sc.tgt_depth, capacity=64, keep_grads=True)
+    late.run()
+    late.run()
+    log("(b) replans", late.replans, "steps redone", late.steps_redone)
+    assert late.replans == 1 and late.steps_redone == 2
+    late.finish()
+    torch.cuda.synchronize()
+    assert int(mb.step_count.item()) == 2 and not late.overflowed()
+    np.testing.assert_allclose(late.loss(), ref[1]["loss"], rtol=1e-5)
+    for k in mb.p:
+        f = ref[1]["firm"][k]
+        np.testing.assert_allclose(mb.p[k].cpu().numpy()[f], ref[1]["p"][k][f], rtol=1e-5, atol=1e-6, err_msg=k)
 
 
 def test_pair_counts_match_oracle(gpu_lib):
@@ -670,7 +790,8 @@ def test_split_batched_step_matches_unsplit(gpu_lib):
     res = []
     for seg in (-1, 64):
         model = GaussianModel(sc.params(), sc.sh_degree)
-        st = BatchedStep(model, sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=B.default_opts(seg_len=seg))
+        st = BatchedStep(model, sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=B.default_opts(seg_len=seg),
+                         keep_grads=True)
         st.run_eager()
         torch.cuda.synchronize()
         grads = {k: v.cpu().numpy() for k, v in model.g.items()}
@@ -679,8 +800,9 @@ def test_split_batched_step_matches_unsplit(gpu_lib):
         losses = []
         for _ in range(3):
             st.run()
+            st.finish()
             losses.append(st.loss())
-        assert not st.overflowed()
+        assert not st.overflowed() and st.replans == 0
         res.append((loss0, grads, losses))
     np.testing.assert_allclose(res[1][0], res[0][0], rtol=1e-5)
     for k in res[0][1]:
@@ -689,6 +811,108 @@ def test_split_batched_step_matches_unsplit(gpu_lib):
         err = np.abs(a - b) / (np.abs(a) + rms)
         assert err.max() <= 1e-4, (k, float(err.max()))
     np.testing.assert_allclose(res[1][2], res[0][2], rtol=1e-3)
+
+
+# ----------------------------------------------------------------------------- SSIM term (eq. Lc)
+SSIM_LAMBDA = 0.2
+
+
+@pytest.mark.parametrize("sizes", [[(40, 33)], [(16, 16), (70, 45), (5, 3), (1, 1)], [(128, 96), (64, 48), (32, 24)]])
+def test_ssim_term_matches_oracle(gpu_lib, sizes):
+    """gs_ssim on random images of several views (tile-aligned, ragged, smaller than one window, one pixel): the
+    value within 1e-5 of the FP64 oracle, the image gradient within 1e-4 of (|ref| + RMS).  The FP32 window
+    moments round at about 2^-24 per term over 121 terms, and the variances cancel about a factor 4 of it for
+    uniform images, so a few 1e-5 relative at most; 1e-4 leaves room for the divisions."""
+    cams = [scenes.identity_camera(0.8 * W, 0.8 * W, W / 2, H / 2, W, H) for W, H in sizes]
+    for i, c in enumerate(cams):
+        c.weight = 1.0 / (i + 1)
+    rng = np.random.default_rng(sum(W * H for W, H in sizes))
+    P = sum(W * H for W, H in sizes)
+    x = rng.uniform(size=3 * P).astype(np.float32)
+    y = rng.uniform(size=3 * P).astype(np.float32)
+    x[: 3 * P // 4] = np.clip(y[: 3 * P // 4] + rng.normal(0, 0.05, 3 * P // 4), 0, 1)  # partly similar images
+    fr = B.Frame(10, cams)
+    g = torch.empty(3 * P, device="cuda")
+    loss = torch.zeros(64, device="cuda")
+    log("ssim views", sizes)
+    B.gs_ssim(fr, torch.as_tensor(x).cuda(), torch.as_tensor(y).cuda(), SSIM_LAMBDA, g, loss)
+    torch.cuda.synchronize()
+    L, gref = oracle.ssim_loss(x, y, cams, SSIM_LAMBDA)
+    np.testing.assert_allclose(float(loss[0].item()), L, rtol=1e-5)
+    gg = g.cpu().numpy().astype(np.float64)
+    rms = math.sqrt(float((gref ** 2).mean()))
+    err = np.abs(gg - gref)
+    assert np.all(err <= 1e-4 * (np.abs(gref) + rms)), float((err / (np.abs(gref) + rms)).max())
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_backward_with_ssim_term_matches_fp64_oracle(gpu_lib, fused):
+    """L = (1 - lambda) L1 + lambda L_ssim + lambda_d L_d (eq. L with eq. Lc, lambda = 0.2): the rendered images
+    go through gs_ssim, whose gradient image the loss-mode backward adds to the L1 gradient (image-fed, or
+    recomputing the forward); loss and gradients against the FP64 oracle."""
+    sc = scenes.random_scene(2200, 2000, 90, 70, sh_degree=2, views=3, log_scale_mu=-2.3, depth_fraction=0.3)
+    model = GaussianModel(sc.params(), 2)
+    fr = B.Frame(model.n, sc.cams, B.default_opts(seg_len=128))
+    B.gs_project(model.ps, fr)
+    assert B.gs_bin_tiles(fr, sync_count=True) <= fr.capacity
+    rgb, depth, vis = fr.empty_images()
+    B.gs_render_fwd(fr, rgb, depth, vis)
+    tr, td = torch.as_tensor(sc.tgt_rgb).cuda(), torch.as_tensor(sc.tgt_depth).cuda()
+    g_ssim = torch.empty_like(rgb)
+    sloss = torch.zeros(64, device="cuda")
+    B.gs_ssim(fr, rgb, tr, SSIM_LAMBDA, g_ssim, sloss)
+    B.gs_render_bwd(model.ps, fr, None if fused else (rgb, depth, vis), model.gs, g_rgb=g_ssim, tgt_rgb=tr,
+                    tgt_depth=td, lambda_ssim=SSIM_LAMBDA)
+    torch.cuda.synchronize()
+    L_gpu = float(B.frame_tensor(fr, "loss", 1, torch.float32).item()) + float(sloss[0].item())
+    L, ref, exc, nn, scale = grad_reference(sc.params(), 2, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth,
+                                            lambda_ssim=SSIM_LAMBDA)
+    np.testing.assert_allclose(L_gpu, L, rtol=1e-5)
+    check_grads({k: v.cpu().numpy() for k, v in model.g.items()}, ref, exc, f"ssim fused={fused}", nn,
+                sc.total_pixels, scale)
+
+
+def test_batched_step_with_ssim_matches_plain_step_and_oracle(gpu_lib):
+    """The batched step with the SSIM term (render, gs_ssim, image-fed backward fused with Adam), eager and as a
+    graph replay, against the plain per-view sequence and the FP64 oracle."""
+    sc = scenes.random_scene(2300, 2500, 100, 80, sh_degree=1, views=3, log_scale_mu=-2.3, depth_fraction=0.3)
+    ma, mb, mc = (GaussianModel(sc.params(), 1) for _ in range(3))
+    plain = PlainStep(ma, sc.cams, sc.tgt_rgb, sc.tgt_depth, lambda_ssim=SSIM_LAMBDA)
+    plain.run()
+    bat = BatchedStep(mb, sc.cams, sc.tgt_rgb, sc.tgt_depth, keep_grads=True, lambda_ssim=SSIM_LAMBDA)
+    bat.run_eager()
+    gra = BatchedStep(mc, sc.cams, sc.tgt_rgb, sc.tgt_depth, keep_grads=True, lambda_ssim=SSIM_LAMBDA)
+    gra.run()
+    gra.finish()
+    torch.cuda.synchronize()
+    L, ref, exc, nn, scale = grad_reference(sc.params(), 1, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth,
+                                            lambda_ssim=SSIM_LAMBDA)
+    for name, st, m in (("plain", plain, ma), ("batched", bat, mb), ("graph", gra, mc)):
+        np.testing.assert_allclose(st.loss(), L, rtol=1e-5, err_msg=name)
+        check_grads({k: v.cpu().numpy() for k, v in m.g.items()}, ref, exc, f"ssim {name}", nn, sc.total_pixels,
+                    scale)
+    assert int(mc.step_count.item()) == 1 and gra.replans == 0
+
+
+def test_autograd_ssim_term_matches_oracle(gpu_lib):
+    """The SSIM term as a torch.autograd.Function on the rasteriser's images: the parameter gradient of
+    lambda L_ssim alone, against the oracle's upstream-gradient backward fed with the oracle's SSIM gradient of
+    the same images."""
+    from paper_2411_02703_amd.rasterize import Rasterizer, rasterize, ssim_term
+
+    sc = scenes.random_scene(2400, 1500, 80, 60, sh_degree=1, views=2, log_scale_mu=-2.3)
+    prm = {k: torch.tensor(v, dtype=torch.float32, device="cuda", requires_grad=True) for k, v in sc.params().items()}
+    rast = Rasterizer(sc.n, sc.cams, 1)
+    rgb, depth, vis = rasterize(prm["means"], prm["log_scales"], prm["quats"], prm["opacity"], prm["sh"], rast)
+    L = ssim_term(rgb, torch.as_tensor(sc.tgt_rgb).cuda(), rast, SSIM_LAMBDA)
+    L.backward()
+    img = rgb.detach().cpu().numpy()
+    L_ref, g_img = oracle.ssim_loss(img, sc.tgt_rgb, sc.cams, SSIM_LAMBDA)
+    np.testing.assert_allclose(L.item(), L_ref, rtol=1e-5)
+    zeros = np.zeros(sc.total_pixels)
+    _, ref, exc, nn, scale = grad_reference(sc.params(), 1, sc.cams, g_rgb=g_img, g_depth=zeros, g_vis=zeros)
+    check_grads({k: v.grad.cpu().numpy() for k, v in prm.items()}, ref, exc, "autograd ssim", nn, sc.total_pixels,
+                scale)
 
 
 # ----------------------------------------------------------------------------- full-size workloads
@@ -721,9 +945,7 @@ def test_full_size_single_view_forward_and_gradients_match_oracle(gpu_lib):
         out["cams"] = sc.cams
         check_images(out, ref, ref["near"], f"full cfg2 {tile} {bw} {seg}")
         np.testing.assert_allclose(out["loss"], L, rtol=1e-5)
-        # a dense view: its 3e-4 near-threshold pixels have ~100 contributors each (5.3% of the Gaussians)
-        check_grads(out["grads"], g, exc, f"full cfg2 {tile} {bw} {seg}", nn, sc.total_pixels, scale,
-                    max_excused=0.10)
+        check_grads(out["grads"], g, exc, f"full cfg2 {tile} {bw} {seg}", nn, sc.total_pixels, scale)
 
 
 def test_full_size_single_keyframe_loss_matches_oracle(gpu_lib):
@@ -782,10 +1004,94 @@ def test_full_size_batch_gradients_match_fp64_oracle(gpu_lib):
     for tile, bw, seg, fused in (((16, 16), 4, 512, True), ((16, 16), 8, -1, False)):
         out = run_gpu(sw, tile=tile, bw=bw, seg=seg, targets=True, fused=fused, capacity=24_000_000)
         np.testing.assert_allclose(out["loss"], L, rtol=1e-5)
-        # ~100 Gaussians contribute at each pixel of this keyframe, so the 4e-4 of its pixels that hold a
-        # near-threshold decision excuse ~7% of the Gaussians
         check_grads(out["grads"], ref, exc, f"full cfg4 {tile} {bw} {seg} fused={fused}", nn,
-                    offs[big + 3] - offs[big], scale, max_excused=0.10)
+                    offs[big + 3] - offs[big], scale)
+
+
+def test_autograd_two_forwards_through_one_rasterizer_before_backward(gpu_lib):
+    """Two forwards with different parameters through one Rasterizer (one frame) before a single backward:
+    the earlier forward's backward bins its own parameters again, so both gradients equal those of separate
+    renders (to the rounding of the LDS sums, whose order varies from run to run)."""
+    from paper_2411_02703_amd.rasterize import Rasterizer, rasterize
+
+    keys = ("means", "log_scales", "quats", "opacity", "sh")
+    sa = scenes.random_scene(2100, 1500, 80, 60, sh_degree=1, log_scale_mu=-2.3)
+    sb = scenes.random_scene(2101, 1500, 80, 60, sh_degree=1, log_scale_mu=-2.3)
+    cams = sa.cams  # both scenes use the same identity camera
+    P = sa.total_pixels
+    rng = np.random.default_rng(2102)
+    w = [rng.standard_normal(m * P).astype(np.float32) for m in (3, 1, 1)]
+    wt = [torch.as_tensor(x).cuda() for x in w]
+
+    def leaf(sc):
+        return {k: torch.tensor(v, dtype=torch.float32, device="cuda", requires_grad=True)
+                for k, v in sc.params().items()}
+
+    def weighted(out):
+        return sum((o * x).sum() for o, x in zip(out, wt))
+
+    shared = Rasterizer(sa.n, cams, 1)
+    pa, pb = leaf(sa), leaf(sb)
+    la = weighted(rasterize(*[pa[k] for k in keys], shared))
+    lb = weighted(rasterize(*[pb[k] for k in keys], shared))
+    (la + 2.0 * lb).backward()
+    qa, qb = leaf(sa), leaf(sb)
+    weighted(rasterize(*[qa[k] for k in keys], Rasterizer(sa.n, cams, 1))).backward()
+    (2.0 * weighted(rasterize(*[qb[k] for k in keys], Rasterizer(sb.n, cams, 1)))).backward()
+    for sc, got, want, f in ((sa, pa, qa, 1.0), (sb, pb, qb, 2.0)):
+        scale = oracle.gradient_scale(sc.params(), 1, cams, g_rgb=w[0], g_depth=w[1], g_vis=w[2])
+        for k in keys:
+            a = got[k].grad.cpu().numpy().astype(np.float64)
+            b = want[k].grad.cpu().numpy().astype(np.float64)
+            assert np.abs(b).max() > 0, k
+            rnd = ROUND_C * U32 * f * scale[k].reshape(a.shape)
+            assert np.all(np.abs(a - b) <= 1e-5 * np.abs(b) + 2 * rnd), k
+
+
+def test_full_size_batched_graph_step_matches_oracle_checked_path(gpu_lib):
+    """The headline path at full size: BatchedStep on the 24-view batch (capacity-sized binning, fused
+    compositing, projection backward fused with Adam, one graph replay).  With the loss weights of all views but
+    the largest keyframe's three levels set to 0 (every view is still rendered and walked backward), its loss
+    and pre-Adam gradients match the FP64 oracle at the gradient bar and equal those of the run_gpu path in the
+    same launch configuration to 1e-5 plus the rounding term; its Adam update equals gs_adam_step applied to
+    the same gradients."""
+    import dataclasses
+    sc = scenes.config(4)
+    big = max(range(0, len(sc.cams), 3), key=lambda i: sc.cams[i].width)
+    views = [big, big + 1, big + 2]
+    cams = [dataclasses.replace(c, weight=c.weight if i in views else 0.0) for i, c in enumerate(sc.cams)]
+    sw = dataclasses.replace(sc, cams=cams)
+    offs = np.cumsum([0] + [c.width * c.height for c in sc.cams])
+    tr = np.ascontiguousarray(sc.tgt_rgb[3 * offs[big]:3 * offs[big + 3]])
+    td = np.ascontiguousarray(sc.tgt_depth[offs[big]:offs[big + 3]])
+    L, ref, exc, nn, scale = grad_reference(sc.params(), sc.sh_degree, [cams[i] for i in views], tgt_rgb=tr,
+                                            tgt_depth=td)
+    model = GaussianModel(sc.params(), sc.sh_degree)
+    st = BatchedStep(model, cams, sc.tgt_rgb, sc.tgt_depth, keep_grads=True)
+    log("full-size batched step: capacity", st.frame.capacity)
+    st.run()
+    st.finish()
+    torch.cuda.synchronize()
+    assert st.replans == 0 and int(model.step_count.item()) == 1
+    gb = {k: v.cpu().numpy() for k, v in model.g.items()}
+    np.testing.assert_allclose(st.loss(), L, rtol=1e-5)
+    check_grads(gb, ref, exc, "full cfg4 batched graph step", nn, offs[big + 3] - offs[big], scale)
+    out = run_gpu(sw, targets=True, fused=True, capacity=24_000_000)
+    np.testing.assert_allclose(st.loss(), out["loss"], rtol=1e-5)
+    for k in gb:
+        a, b = gb[k].astype(np.float64), out["grads"][k].astype(np.float64)
+        rnd = ROUND_C * U32 * scale[k].reshape(a.shape)
+        assert np.all(np.abs(a - b) <= 1e-5 * np.abs(b) + 2 * rnd), k
+    # the fused Adam update against the separate Adam step on the same gradients
+    sep = GaussianModel(sc.params(), sc.sh_degree)
+    for k in sep.g:
+        sep.g[k].copy_(model.g[k])
+    sep.adam_step()
+    torch.cuda.synchronize()
+    for k in sep.p:
+        np.testing.assert_allclose(model.p[k].cpu().numpy(), sep.p[k].cpu().numpy(), rtol=1e-6, atol=1e-9,
+                                   err_msg=k)
+        np.testing.assert_allclose(model.v[k].cpu().numpy(), sep.v[k].cpu().numpy(), rtol=1e-6, atol=0, err_msg=k)
 
 
 # ----------------------------------------------------------------------------- autograd + finite differences
@@ -798,8 +1104,9 @@ def test_autograd_function_matches_oracle_and_finite_differences_on_full_scene_c
     Gaussians that reach the window (40 per group) match central finite differences of the FP64 oracle loss
     (Richardson-extrapolated from steps h = 1e-5 max(1, |x|) and h/2; twice their difference plus the loss's
     own rounding over h, 1e-13 / h, bound the error): the oracle's analytic value to 2e-5 plus that bound, the
-    GPU's to the 1e-3 bar plus it (steps whose two differences disagree by more than 1e-3 straddle a discrete
-    decision and are skipped)."""
+    GPU's to the 1e-3 bar plus it and the entry's flip allowance (steps whose two differences disagree by more
+    than 1e-4 relative straddle a discrete decision and are skipped; up to 80 candidates per group are drawn
+    until 40 are checked)."""
     import dataclasses
 
     from paper_2411_02703_amd.rasterize import Rasterizer, rasterize
@@ -839,14 +1146,17 @@ def test_autograd_function_matches_oracle_and_finite_differences_on_full_scene_c
     _, g64, _, _, _ = oracle.backward(64, sc.params(), sc.sh_degree, [win], tgt_rgb=tr, tgt_depth=td, guard=guard)
     seen = np.flatnonzero(oracle.project(64, sc.params(), sc.sh_degree, [win], guard=guard)["visible"] != 0)
     sub = {k: np.ascontiguousarray(np.asarray(v, np.float64)[seen]) for k, v in sc.params().items()}
-    rms = {k: math.sqrt(float((ref[k].reshape(sc.n, -1)[~exc] ** 2).mean())) for k in ref}
+    rms = {k: math.sqrt(float((ref[k].reshape(sc.n, -1)[~exc] ** 2).mean())) for k in ref if not k.startswith("_")}
     checked = 0
     for key in ("means", "log_scales", "quats", "opacity", "sh"):
         flat = g64[key].reshape(sc.n, -1)
         cand = [(i, c) for i in np.flatnonzero(np.abs(flat).max(axis=1) > 0) for c in range(flat.shape[1])
                 if flat[i, c] != 0 and not exc[i]]
-        pick = rng.permutation(len(cand))[:40]
+        pick = rng.permutation(len(cand))[:80]
+        done = 0
         for t in pick:
+            if done == 40:
+                break
             gi, comp = cand[t]
             si = int(np.searchsorted(seen, gi))
             assert seen[si] == gi
@@ -863,14 +1173,16 @@ def test_autograd_function_matches_oracle_and_finite_differences_on_full_scene_c
             d1 = (L_at(x + h) - L_at(x - h)) / (2 * h)
             d2 = (L_at(x + h / 2) - L_at(x - h / 2)) / h
             est = abs(d1 - d2)
-            if est > 1e-3 * abs(d2) + 1e-12:
-                continue
+            if est > 1e-4 * abs(d2) + 1e-12:
+                continue  # the two steps disagree: a discrete decision lies inside the step (a kink)
             fd = (4 * d2 - d1) / 3
             fd_err = 2 * est + 1e-13 / h
             assert abs(fd - flat[gi, comp]) <= 2e-5 * abs(fd) + fd_err, (key, gi, comp, fd, flat[gi, comp], est)
             gg = g_gpu[key].reshape(sc.n, -1)[gi, comp]
-            tol = GRAD_TOL * (abs(fd) + rms[key]) + ROUND_C * U32 * scale[key].reshape(sc.n, -1)[gi, comp] + fd_err
+            tol = (GRAD_TOL * (abs(fd) + rms[key]) + ROUND_C * U32 * scale[key].reshape(sc.n, -1)[gi, comp] + fd_err
+                   + ref["_allowance"][key].reshape(sc.n, -1)[gi, comp])
             assert abs(gg - fd) <= tol, (key, gi, comp, gg, fd)
             checked += 1
+            done += 1
     log("finite differences checked", checked, "of 200")
     assert checked >= 150

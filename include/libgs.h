@@ -69,7 +69,10 @@ typedef struct gs_camera {
   float T[3];          /* translation ([T_iw] of eq. muI): t = R mu + T */
   float fx, fy, cx, cy;
   float campos[3];     /* camera centre in world coordinates (-R^T T), for SH view directions */
-  float loss_weight;   /* w_v: weight of this view (keyframe x pyramid level) in the loss */
+  float loss_weight;   /* w_v: weight of this view (keyframe x pyramid level) in the loss; a negative weight
+                          marks an inactive view: gs_project culls every Gaussian in it (it renders as background
+                          and adds nothing to the loss or the gradient), so a schedule can switch views of a
+                          captured frame off and on without re-planning it */
   int32_t width, height;
   /* filled by gs_plan_cameras: */
   int32_t tiles_x, tiles_y;
@@ -191,10 +194,15 @@ typedef struct gs_loss {
                              mode).  0 with g_rgb = NULL is the plain L1 loss */
 } gs_loss;
 
+#define GS_ADAM_SPARSE 1 /* gs_adam.flags: visible-only step (gs_render_bwd_adam) */
+
 typedef struct gs_adam {
   float lr[6];          /* means, log_scales, quats, opacity, sh degree 0, sh degree >= 1 */
   float beta1, beta2, eps;
-  int32_t reserved;
+  int32_t flags;        /* GS_ADAM_SPARSE: in gs_render_bwd_adam only the Gaussians visible in at least one view
+                           of the frame take the step; the others keep their parameters and moments (a flagged
+                           variant of the dense torch semantics; the step counter is global).  gs_adam_step
+                           rejects the flag (it has no visibility) */
   int64_t* step;        /* device counter, incremented by each step that is taken, before it is used */
   float* bias;          /* device scratch of 4 floats (bias corrections and the skip decision of the step) */
   const int32_t* skip_flags; /* gs_adam_step: nullable device pointer, typically &frame->counters[1]; when
@@ -295,6 +303,19 @@ int gs_render_bwd_adam(const gs_params* params, const gs_frame* frame, const gs_
  * outside [1, 64] or lambda outside [0, 1]. */
 int gs_ssim(const gs_camera* cams_host, const gs_camera* cams_dev, int32_t n_views, const float* rgb,
             const float* tgt_rgb, float lambda_ssim, float* g_rgb, float* loss_out, void* stream);
+
+/* Opacity pruning (Section III-C: Gaussians whose opacity has fallen to the prunable threshold are removed):
+ * every Gaussian with opacity sigmoid(logit) below min_opacity is dropped and the rest are compacted, in their
+ * original order, to the front of out_params, out_m and out_v (each with room for params->n Gaussians, same
+ * SH degree, not overlapping the inputs).  The decision compares the logit with the threshold's logit
+ * (float)log(min_opacity / (1 - min_opacity)), computed on the host in double.  *n_kept (device) receives the
+ * number kept; the caller reads it after the stream completes and uses the first n_kept rows.  scratch: device,
+ * gs_prune_scratch_bytes(n) bytes.  GS_ERR_ARG for min_opacity outside (0, 1), NULL pointers or mismatched
+ * sizes. */
+size_t gs_prune_scratch_bytes(int64_t n);
+int gs_prune(const gs_params* params, const gs_params* m, const gs_params* v, float min_opacity,
+             const gs_params* out_params, const gs_params* out_m, const gs_params* out_v, int64_t* n_kept,
+             void* scratch, void* stream);
 
 /* ------------------------------------------------------------------ utilities */
 /* Work counts of the frame's forward compositing at its tile shape, ADDED to counts[0..1] (device, uint64):

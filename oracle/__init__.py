@@ -34,6 +34,7 @@ def lib() -> ctypes.CDLL:
         _lib.oracle_loss.restype = ctypes.c_double
         _lib.oracle_bin.restype = ctypes.c_int64
         _lib.oracle_ssim_plane.restype = ctypes.c_double
+        _lib.oracle_prune.restype = ctypes.c_int64
         _lib.oracle_ssim_loss.restype = ctypes.c_double
     return _lib
 
@@ -239,6 +240,22 @@ def quat_to_rot(q) -> np.ndarray:
     M = np.zeros(9)
     lib().oracle_quat_to_rot(_p(_f64(q)), _p(M))
     return M.reshape(3, 3)
+
+
+def prune(opacity_logit, min_opacity: float) -> np.ndarray:
+    """Indices (in order) of the Gaussians kept by opacity pruning at min_opacity."""
+    o = _f64(np.asarray(opacity_logit).reshape(-1))
+    idx = np.zeros(max(o.size, 1), np.int64)
+    k = lib().oracle_prune(_p(o), ctypes.c_int64(o.size), ctypes.c_double(min_opacity), _p(idx))
+    return idx[:k]
+
+
+def prune(opacity_logit, min_opacity: float) -> np.ndarray:
+    """Indices (in order) of the Gaussians kept by opacity pruning at min_opacity."""
+    o = _f64(np.asarray(opacity_logit).reshape(-1))
+    idx = np.zeros(max(o.size, 1), np.int64)
+    k = lib().oracle_prune(_p(o), ctypes.c_int64(o.size), ctypes.c_double(min_opacity), _p(idx))
+    return idx[:k]
 
 
 SSIM_LAMBDA = 0.2  # weight of the SSIM term in eq. Lc (the value of the 3DGS work the paper builds on)

@@ -84,9 +84,12 @@ Opts read_opts(const double* o) {
 enum { CAM_R = 0, CAM_T = 9, CAM_FX = 12, CAM_FY, CAM_CX, CAM_CY, CAM_W, CAM_H,
        CAM_POS = 18, CAM_WEIGHT = 21, CAM_COUNT = 22 };
 
+// weight: the view's loss weight w_v; a negative input weight marks an inactive view (reading R26: a schedule
+// switches views off), which projects nothing and counts with weight 0.
 template <class R>
 struct Cam {
   R Rm[9], T[3], fx, fy, cx, cy, pos[3], weight;
+  bool active;
   int W, H, tiles_x, tiles_y, tile_offset;
   int64_t pixel_offset;
 };
@@ -108,7 +111,8 @@ std::vector<Cam<R>> read_cams(const double* c, int V, const Opts& op) {
     k.W = (int)p[CAM_W];
     k.H = (int)p[CAM_H];
     for (int i = 0; i < 3; ++i) k.pos[i] = (R)p[CAM_POS + i];
-    k.weight = (R)p[CAM_WEIGHT];
+    k.active = p[CAM_WEIGHT] >= 0;
+    k.weight = k.active ? (R)p[CAM_WEIGHT] : (R)0;
     k.tiles_x = (k.W + op.tile_w - 1) / op.tile_w;
     k.tiles_y = (k.H + op.tile_h - 1) / op.tile_h;
     k.tile_offset = tile_off;
@@ -237,6 +241,7 @@ Proj<R> project_one(const double* means, const double* log_scales, const double*
   p.near_margin = 1e30;
   p.rect_margin = 1e30;
   p.rgb_margin = 1e30;
+  if (!cam.active) { p.cull_reason = 7; return p; }  // inactive view (reading R26)
   R mu[3] = {(R)means[g * 3], (R)means[g * 3 + 1], (R)means[g * 3 + 2]};
   // camera transform, op order fixed: t_r = fma(R_r2, mu_z, fma(R_r1, mu_y, fma(R_r0, mu_x, T_r)))
   for (int r = 0; r < 3; ++r)
@@ -1585,6 +1590,17 @@ double oracle_loss(const double* means, const double* log_scales, const double* 
 
 // One Adam step (bias-corrected; eps added to the corrected root), in FP64, on a flat array.
 // `step` is the step number after increment (1 for the first step).
+// Opacity pruning (Section III-C, the prunable opacity threshold): the indices, in order, of the Gaussians whose
+// opacity sigmoid(logit) is at least min_opacity.  The decision is taken as the FP32 path takes it: the FP32
+// logit against the FP32-rounded logit of the threshold.  Returns the count; keep_idx has room for n.
+int64_t oracle_prune(const double* opac_logit, int64_t n, double min_opacity, int64_t* keep_idx) {
+  const float thr = (float)std::log(min_opacity / (1.0 - min_opacity));
+  int64_t k = 0;
+  for (int64_t i = 0; i < n; ++i)
+    if ((float)opac_logit[i] >= thr) keep_idx[k++] = i;
+  return k;
+}
+
 void oracle_adam(double* p, const double* g, double* m, double* v, int64_t n, double lr, double beta1, double beta2,
                  double eps, int64_t step) {
   double bc1 = 1.0 - std::pow(beta1, (double)step);

@@ -65,7 +65,7 @@ class gs_loss(ctypes.Structure):
 
 
 class gs_adam(ctypes.Structure):
-    _fields_ = [("lr", c_f * 6), ("beta1", c_f), ("beta2", c_f), ("eps", c_f), ("reserved", c_i32),
+    _fields_ = [("lr", c_f * 6), ("beta1", c_f), ("beta2", c_f), ("eps", c_f), ("flags", c_i32),
                 ("step", c_vp), ("bias", c_vp), ("skip_flags", c_vp)]
 
 
@@ -73,10 +73,11 @@ assert ctypes.sizeof(gs_camera) == 128
 
 GS_FLAG_INSTANCE_OVERFLOW = 1
 GS_FLAG_NONFINITE = 2
+GS_ADAM_SPARSE = 1
 
 EXPORTED = ["gs_default_opts", "gs_plan_cameras", "gs_frame_bytes", "gs_frame_init", "gs_project", "gs_bin_tiles",
             "gs_render_fwd", "gs_render_bwd", "gs_composite_bwd", "gs_project_bwd", "gs_adam_step",
-            "gs_render_bwd_adam", "gs_ssim",
+            "gs_render_bwd_adam", "gs_ssim", "gs_prune_scratch_bytes", "gs_prune",
             "gs_count_pairs", "gs_read_counters", "gs_sort_scratch_ints", "gs_sort_pairs", "gs_sort_static_max",
             "gs_sort_pairs_static", "gs_status_string",
             "gs_last_error", "gs_version"]
@@ -107,6 +108,10 @@ def load() -> ctypes.CDLL:
     lib.gs_composite_bwd.argtypes = [P(gs_frame), P(gs_opts), P(gs_images), P(gs_loss), c_vp]
     lib.gs_project_bwd.argtypes = [P(gs_params), P(gs_frame), P(gs_opts), P(gs_params), c_vp]
     lib.gs_adam_step.argtypes = [P(gs_params), P(gs_params), P(gs_params), P(gs_params), P(gs_adam), c_vp]
+    lib.gs_prune_scratch_bytes.argtypes = [c_i64]
+    lib.gs_prune_scratch_bytes.restype = ctypes.c_size_t
+    lib.gs_prune.argtypes = [P(gs_params), P(gs_params), P(gs_params), c_f, P(gs_params), P(gs_params), P(gs_params),
+                             c_vp, c_vp, c_vp]
     lib.gs_ssim.argtypes = [P(gs_camera), c_vp, c_i32, c_vp, c_vp, c_f, c_vp, c_vp, c_vp]
     lib.gs_render_bwd_adam.argtypes = [P(gs_params), P(gs_frame), P(gs_opts), P(gs_images), P(gs_loss),
                                        P(gs_params), P(gs_params), P(gs_adam), P(gs_params), c_vp]
@@ -319,6 +324,16 @@ def gs_ssim(frame: Frame, rgb: torch.Tensor, tgt_rgb: torch.Tensor, lambda_ssim:
         raise ValueError("loss_out must be a float32 CUDA tensor of at least 64 elements")
     _check(load().gs_ssim(frame.cams_host, frame.cams_dev.data_ptr(), frame.n_views, _ptr(rgb), _ptr(tgt_rgb),
                           float(lambda_ssim), _ptr(g_rgb), loss_out.data_ptr(), _stream(stream)), "gs_ssim")
+
+
+def gs_prune(params: gs_params, m: gs_params, v: gs_params, min_opacity: float, out_params: gs_params,
+             out_m: gs_params, out_v: gs_params, n_kept: torch.Tensor, stream=None) -> None:
+    """Opacity pruning into the out_* arrays; n_kept (int64 CUDA tensor) receives the count kept."""
+    scratch = torch.empty(int(load().gs_prune_scratch_bytes(params.n)) // 4 + 64, dtype=torch.int32,
+                          device=n_kept.device)
+    _check(load().gs_prune(ctypes.byref(params), ctypes.byref(m), ctypes.byref(v), float(min_opacity),
+                           ctypes.byref(out_params), ctypes.byref(out_m), ctypes.byref(out_v), n_kept.data_ptr(),
+                           scratch.data_ptr(), _stream(stream)), "gs_prune")
 
 
 def gs_read_counters(frame: Frame, stream=None):

@@ -401,8 +401,29 @@ int gs_ssim(const gs_camera* cams_host, const gs_camera* cams_dev, int32_t V, co
   return GS_OK;
 }
 
+size_t gs_prune_scratch_bytes(int64_t n) { return n < 1 ? 0 : 4 * gs_launch::prune_scratch_ints(n); }
+
+int gs_prune(const gs_params* p, const gs_params* m, const gs_params* v, float min_opacity, const gs_params* op,
+             const gs_params* om, const gs_params* ov, int64_t* n_kept, void* scratch, void* stream) {
+  int rc;
+  if ((rc = params_check(p, "params")) || (rc = params_check(m, "m")) || (rc = params_check(v, "v")) ||
+      (rc = params_check(op, "out_params")) || (rc = params_check(om, "out_m")) || (rc = params_check(ov, "out_v")))
+    return rc;
+  const gs_params* all[5] = {m, v, op, om, ov};
+  for (const gs_params* q : all)
+    if (q->n != p->n || q->sh_degree != p->sh_degree) return fail(GS_ERR_ARG, "prune: sizes differ");
+  if (!n_kept || !scratch) return fail(GS_ERR_ARG, "prune: NULL n_kept or scratch");
+  if (!(min_opacity > 0.f && min_opacity < 1.f)) return fail(GS_ERR_ARG, "min_opacity = %g", (double)min_opacity);
+  const float thr = (float)std::log((double)min_opacity / (1.0 - (double)min_opacity));
+  GS_HIP(gs_launch::prune(*p, *m, *v, thr, *op, *om, *ov, n_kept, static_cast<int32_t*>(scratch),
+                          static_cast<hipStream_t>(stream)),
+         "gs_prune");
+  return GS_OK;
+}
+
 static int adam_check(const gs_adam* a) {
   if (!a || !a->step || !a->bias) return fail(GS_ERR_ARG, "adam state is NULL");
+  if (a->flags & ~GS_ADAM_SPARSE) return fail(GS_ERR_ARG, "unknown Adam flags %d", a->flags);
   if (!(a->beta1 >= 0.f && a->beta1 < 1.f) || !(a->beta2 >= 0.f && a->beta2 < 1.f) || !(a->eps >= 0.f))
     return fail(GS_ERR_ARG, "invalid Adam hyper-parameters");
   return GS_OK;
@@ -448,6 +469,8 @@ int gs_adam_step(const gs_params* p, const gs_params* g, const gs_params* m, con
       m->sh_degree != p->sh_degree || v->sh_degree != p->sh_degree)
     return fail(GS_ERR_ARG, "params / grads / moments sizes differ");
   if ((rc = adam_check(a))) return rc;
+  if (a->flags & GS_ADAM_SPARSE) return fail(GS_ERR_ARG, "gs_adam_step has no visibility: sparse Adam is a flag of "
+                                                        "gs_render_bwd_adam");
   GS_HIP(gs_launch::adam(*p, *g, *m, *v, *a, static_cast<hipStream_t>(stream)), "gs_adam_step");
   return GS_OK;
 }

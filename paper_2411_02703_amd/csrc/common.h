@@ -154,6 +154,10 @@ hipError_t adam(const gs_params& p, const gs_params& g, const gs_params& m, cons
 // SSIM term of the photometric loss: gradient written to g_rgb, value to loss[0] (loss holds 1 + kLossSlots).
 hipError_t ssim(const gs_camera* cams_host, const gs_camera* cams_dev, int n_views, const float* rgb,
                 const float* tgt, float lambda, float* g_rgb, float* loss, hipStream_t s);
+// Opacity pruning: keep flags, their scan and the gather of every kept row (scratch: prune_scratch_ints(n)).
+size_t prune_scratch_ints(int64_t n);
+hipError_t prune(const gs_params& p, const gs_params& m, const gs_params& v, float thr_logit, const gs_params& op,
+                 const gs_params& om, const gs_params& ov, int64_t* n_kept, int32_t* scratch, hipStream_t s);
 // The step counter and bias corrections of one Adam step (skipped when *skip_flags has the overflow bit).
 hipError_t adam_prep(const gs_adam& a, const int32_t* skip_flags, hipStream_t s);
 // Projection backward fused with Adam: params, m, v updated in place; the gradient is written to grads_out

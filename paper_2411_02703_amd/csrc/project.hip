@@ -220,6 +220,7 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ means
       const float kp = 2.f * logf(255.f * s.o) + 1.f;
       for (int v = 0; v < V; ++v) {
         const gs_camera& c = cams[v];
+        if (c.loss_weight < 0.f) continue;  // an inactive view: nothing is projected into it
         float tx, ty, tz;
         camera_point(c, mu[0], mu[1], mu[2], tx, ty, tz);
         if (!(tz >= op.near_z)) continue;
@@ -274,6 +275,7 @@ struct AdamArgs {
   float lr[6];
   float b1, b2, eps;
   const float* bias;  // {1 - b1^t, sqrt(1 - b2^t), skip}
+  int sparse;         // only Gaussians visible in some view of the frame take the step
 };
 
 __device__ __forceinline__ void adam_one(float& p, float& m, float& v, float g, float s, float b1, float b2,
@@ -506,6 +508,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
     for (int i = 0; i < K * 3; ++i) g_sh[g * (K * 3) + i] = gf[i];
   }
   if (ad.bias[2] != 0.f) return;  // skipped step (instance capacity overflowed)
+  if (ad.sparse && mask == 0) return;  // visible-only step
   const float bc1 = ad.bias[0], bc2s = ad.bias[1];
   const float b1 = ad.b1, b2 = ad.b2, eps = ad.eps;
   {
@@ -649,6 +652,7 @@ hipError_t project_bwd_adam(const gs_params& p, const gs_frame& f, const gs_opts
   ad.b2 = a.beta2;
   ad.eps = a.eps;
   ad.bias = a.bias;
+  ad.sparse = (a.flags & GS_ADAM_SPARSE) ? 1 : 0;
   return project_bwd_launch<true>(p, f, o, grads_out, ad, st);
 }
 

@@ -84,7 +84,7 @@ __device__ __forceinline__ void tile_at(const gs_camera* __restrict__ cams, int 
   t.px = t.tx0 + (t.wave % G::SX) * 8 + (r % G::BS) * G::BW + p % G::BW;
   t.py = t.ty0 + (t.wave / G::SX) * 8 + (r / G::BS) * G::BW + p / G::BW;
   t.pix_off = c.pixel_offset;
-  t.weight = c.loss_weight;
+  t.weight = fmaxf(c.loss_weight, 0.f);  // an inactive view (weight < 0) adds nothing to the loss
   t.inside = t.px < t.W && t.py < t.H;
 }
 

@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kThreads) void k_ssim(const SsimArgs a) {
     const int gy = y0 + r, gx = x0 + c;
     if (gx < W && gy < H) {
       const float xq = sx[r + 2 * kR][c + 2 * kR], yq = sy[r + 2 * kR][c + 2 * kR];
-      const float scale = -cam.loss_weight * a.lambda / (3.f * (float)P);
+      const float scale = -fmaxf(cam.loss_weight, 0.f) * a.lambda / (3.f * (float)P);
       a.g_rgb[3 * (int64_t)cam.pixel_offset + ch * P + (int64_t)gy * W + gx] = scale * (s0 + 2.f * xq * s1 + yq * s2);
     }
   }
@@ -164,8 +164,9 @@ __global__ __launch_bounds__(kThreads) void k_ssim(const SsimArgs a) {
   if (tid == 0) {
     float sum = 0.f;
     for (int i = 0; i < kThreads / 64; ++i) sum += part[i];
-    float add = -cam.loss_weight * a.lambda / (3.f * (float)P) * sum;
-    if (tl == 0 && ch == 0) add += cam.loss_weight * a.lambda;
+    const float wv = fmaxf(cam.loss_weight, 0.f);  // an inactive view (weight < 0) adds nothing
+    float add = -wv * a.lambda / (3.f * (float)P) * sum;
+    if (tl == 0 && ch == 0) add += wv * a.lambda;
     gsk::atomic_add_f32(a.loss + 1 + ((b * 3 + ch) % gsk::kLossSlots), add);
   }
 }

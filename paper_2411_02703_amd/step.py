@@ -63,6 +63,49 @@ class GaussianModel:
     def adam_step(self, stream=None) -> None:
         B.gs_adam_step(self.ps, self.gs, self.ms, self.vs, self.adam, stream)
 
+    def set_sh_degree(self, degree: int) -> None:
+        """Raise (or lower) the SH degree: the coefficients and their Adam moments are re-packed to
+        [n, (degree + 1)^2, 3]; coefficients of the new bands start at 0 (with zero moments), so the rendered
+        colours do not change.  Frames and steps must be rebuilt (the parameter pointers change)."""
+        degree = int(degree)
+        if not 0 <= degree <= 3:
+            raise ValueError("SH degree must be in [0, 3]")
+        K = (degree + 1) ** 2
+        for d in (self.p, self.m, self.v):
+            old = d["sh"]
+            new = torch.zeros((old.shape[0], K, 3), dtype=old.dtype, device=old.device)
+            k = min(K, old.shape[1])
+            new[:, :k] = old[:, :k]
+            d["sh"] = new
+        self.g["sh"] = torch.zeros_like(self.p["sh"])
+        self.sh_degree = degree
+        self.ps = B.params_struct(self.p, degree)
+        self.gs = B.params_struct(self.g, degree)
+        self.ms = B.params_struct(self.m, degree)
+        self.vs = B.params_struct(self.v, degree)
+
+    def set_sparse_adam(self, on: bool = True) -> None:
+        """Visible-only Adam in the fused backward (gs_render_bwd_adam): Gaussians seen by no view of the step keep
+        their parameters and moments."""
+        self.adam.flags = B.GS_ADAM_SPARSE if on else 0
+
+    def prune(self, min_opacity: float) -> int:
+        """Drop every Gaussian whose opacity is below min_opacity (parameters and Adam moments compacted on the
+        device, order kept); returns the new count.  Frames and steps built for the old count must be rebuilt."""
+        dev = self.p["means"].device
+        out = [{k: torch.empty_like(t) for k, t in d.items()} for d in (self.p, self.m, self.v)]
+        structs = [B.params_struct(d, self.sh_degree) for d in out]
+        n_kept = torch.zeros(1, dtype=torch.int64, device=dev)
+        B.gs_prune(self.ps, self.ms, self.vs, min_opacity, structs[0], structs[1], structs[2], n_kept)
+        k = int(n_kept.item())
+        self.p, self.m, self.v = ({key: t[:k] for key, t in d.items()} for d in out)
+        self.g = {key: torch.zeros_like(t) for key, t in self.p.items()}
+        self.ps = B.params_struct(self.p, self.sh_degree)
+        self.gs = B.params_struct(self.g, self.sh_degree)
+        self.ms = B.params_struct(self.m, self.sh_degree)
+        self.vs = B.params_struct(self.v, self.sh_degree)
+        return k
+
     def state(self) -> Dict[str, torch.Tensor]:
         out = {}
         for k in PARAM_KEYS:
@@ -291,6 +334,17 @@ class BatchedStep:
         self.frame = B.Frame(self.model.n, self.cams, self.opts, cap, self.device)
         self._ssim_buffers()
 
+    def set_weights(self, weights: Sequence[float]) -> None:
+        """New loss weights w_v of the frame's views (a negative weight switches a view off: nothing is projected
+        into it).  The device camera table is rewritten in stream order, so a captured graph uses the new
+        weights from its next replay on; frame layout and capacity are unchanged."""
+        if len(weights) != self.frame.n_views:
+            raise ValueError("one weight per view")
+        for c, w in zip(self.frame.cams_host, weights):
+            c.loss_weight = float(w)
+        raw = torch.frombuffer(bytearray(bytes(self.frame.cams_host)), dtype=torch.uint8)
+        self.frame.cams_dev.copy_(raw)
+
     def flags(self) -> int:
         _, fl = B.gs_read_counters(self.frame)
         return fl
@@ -307,3 +361,90 @@ class BatchedStep:
     def n_instances(self) -> int:
         n, _ = B.gs_read_counters(self.frame)
         return n
+
+
+class Mapper:
+    """LVI-GS mapping iterations driven by the training policies (Sections III-C, III-D, III-E) on one captured
+    batched step.
+
+    The frame holds every keyframe's pyramid levels as views.  Keyframes arrive one every `arrive_every`
+    iterations (the front-end's keyframe stream); a DelayBuffer holds each one back until `delay` newer ones have
+    arrived, then it joins the KeyframeQueue.  Each iteration the queue picks `batch` keyframes (a new one is
+    optimised once first; afterwards random picks; capped keyframes retire), the PyramidSchedule picks each one's
+    level from its own iteration count, every other view is switched off (negative weight), and the graph is
+    replayed.  The SH degree follows the SHSchedule (re-pack and re-capture at each change), and every
+    `prune_every` iterations Gaussians below `min_opacity` are pruned (re-capture)."""
+
+    def __init__(self, model: GaussianModel, keyframes: Sequence[Sequence], tgt_rgb: np.ndarray,
+                 tgt_depth: np.ndarray, queue=None, delay=None, pyramid=None, sh=None, arrive_every: int = 1,
+                 prune_every: int = 0, min_opacity: float = 0.005, opts: Optional[B.gs_opts] = None,
+                 lambda_ssim: float = 0.0, device: str = "cuda"):
+        from .schedule import DelayBuffer, KeyframeQueue, PyramidSchedule, SHSchedule
+
+        self.model = model
+        self.keyframes = [list(levels) for levels in keyframes]  # per keyframe: its cameras, finest level first
+        self.cams = [c for levels in self.keyframes for c in levels]
+        self.view_of = []
+        v = 0
+        for levels in self.keyframes:
+            self.view_of.append(list(range(v, v + len(levels))))
+            v += len(levels)
+        self.tgt_rgb, self.tgt_depth = tgt_rgb, tgt_depth
+        self.queue = queue or KeyframeQueue()
+        self.delay = delay or DelayBuffer()
+        self.pyramid = pyramid or PyramidSchedule(levels=len(self.keyframes[0]))
+        self.sh = sh
+        self.arrive_every = max(1, int(arrive_every))
+        self.prune_every = int(prune_every)
+        self.min_opacity = float(min_opacity)
+        self.opts = opts
+        self.lambda_ssim = lambda_ssim
+        self.device = device
+        self.it = 0
+        self.arrived = 0
+        self.history: List[Dict] = []
+        if self.sh is not None and self.model.sh_degree != self.sh.degree(0):
+            self.model.set_sh_degree(self.sh.degree(0))
+        self._build()
+
+    def _build(self) -> None:
+        self.step = BatchedStep(self.model, self.cams, self.tgt_rgb, self.tgt_depth, opts=self.opts,
+                                device=self.device, lambda_ssim=self.lambda_ssim)
+
+    def weights_for(self, picked: Sequence[int]) -> List[float]:
+        w = [-1.0] * len(self.cams)
+        for k in picked:
+            for lv, wl in enumerate(self.pyramid.weights(self.queue.counts[k] - 1)):
+                if wl > 0:
+                    w[self.view_of[k][lv]] = wl / len(picked)
+        return w
+
+    def iterate(self) -> Dict:
+        """One mapping iteration; returns what it did (keyframes, levels, loss of the previous replay)."""
+        if self.it % self.arrive_every == 0 and self.arrived < len(self.keyframes):
+            for k in self.delay.push(self.arrived):
+                self.queue.add(k)
+            self.arrived += 1
+            if self.arrived == len(self.keyframes):
+                for k in self.delay.flush():
+                    self.queue.add(k)
+        rebuild = False
+        if self.sh is not None and self.sh.degree(self.it) != self.model.sh_degree:
+            self.step.finish()
+            self.model.set_sh_degree(self.sh.degree(self.it))
+            rebuild = True
+        if self.prune_every and self.it > 0 and self.it % self.prune_every == 0:
+            self.step.finish()
+            self.model.prune(self.min_opacity)
+            rebuild = True
+        if rebuild:
+            self._build()
+        picked = self.queue.select()
+        rec = dict(it=self.it, keyframes=picked, n=self.model.n, sh_degree=self.model.sh_degree)
+        if picked:
+            self.step.set_weights(self.weights_for(picked))
+            self.step.run()
+            rec["levels"] = [self.pyramid.level(self.queue.counts[k] - 1) for k in picked]
+        self.history.append(rec)
+        self.it += 1
+        return rec

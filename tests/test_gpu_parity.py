@@ -915,6 +915,182 @@ def test_autograd_ssim_term_matches_oracle(gpu_lib):
                 scale)
 
 
+# ----------------------------------------------------------------------------- map maintenance (Sec. III-C)
+@pytest.mark.parametrize("n,deg,tau", [(1, 0, 0.5), (5000, 3, 0.05), (4097, 1, 0.3), (300, 2, 0.999)])
+def test_prune_matches_oracle_bit_exact(gpu_lib, n, deg, tau):
+    """gs_prune keeps the Gaussians the oracle keeps, in order, and moves their parameters and both Adam moments
+    bit for bit (including the all-kept, all-dropped and single-Gaussian cases)."""
+    rng = np.random.default_rng(n + deg)
+    sc = scenes.random_scene(2500 + n, n, 32, 24, sh_degree=deg)
+    model = GaussianModel(sc.params(), deg)
+    for d in (model.m, model.v):
+        for t in d.values():
+            t.copy_(torch.as_tensor(rng.standard_normal(tuple(t.shape)).astype(np.float32)))
+    before = {name: {k: t.cpu().numpy().copy() for k, t in d.items()} for name, d in (("p", model.p), ("m", model.m),
+                                                                                        ("v", model.v))}
+    kept = oracle.prune(before["p"]["opacity"], tau)
+    log("prune", n, "kept", kept.size)
+    k = model.prune(tau)
+    assert k == kept.size
+    for name, d in (("p", model.p), ("m", model.m), ("v", model.v)):
+        for key, t in d.items():
+            assert tuple(t.shape)[0] == k
+            assert np.array_equal(t.cpu().numpy(), before[name][key][kept]), (name, key)
+
+
+def test_sparse_adam_updates_only_visible_gaussians(gpu_lib):
+    """The visible-only variant of the fused backward + Adam: Gaussians seen by no view keep parameters and
+    moments; the visible ones take exactly the Adam step of the oracle on the gradient the kernel formed.  The
+    dense step moves every Gaussian (zero gradient for the unseen)."""
+    sc = scenes.random_scene(2600, 3000, 64, 48, sh_degree=1, views=2, log_scale_mu=-2.3, depth_fraction=0.3)
+    sc.means[:600, 2] = -3.0  # behind every camera
+    for sparse in (True, False):
+        model = GaussianModel(sc.params(), 1)
+        for t in list(model.m.values()) + list(model.v.values()):
+            t.fill_(1e-3)
+        model.set_sparse_adam(sparse)
+        before = {k: (model.p[k].cpu().numpy().copy(), model.m[k].cpu().numpy().copy(),
+                      model.v[k].cpu().numpy().copy()) for k in model.p}
+        st = BatchedStep(model, sc.cams, sc.tgt_rgb, sc.tgt_depth, keep_grads=True)
+        st.run_eager()
+        torch.cuda.synchronize()
+        mask = B.frame_tensor(st.frame, "vis_mask", sc.n, torch.int64).cpu().numpy() != 0
+        assert not mask[:600].any() and mask[600:].sum() > 1000
+        lrs = dict(means=model.adam.lr[0], log_scales=model.adam.lr[1], quats=model.adam.lr[2],
+                   opacity=model.adam.lr[3])
+        for k in model.p:
+            p0, m0, v0 = before[k]
+            g = model.g[k].cpu().numpy()
+            p1 = model.p[k].cpu().numpy()
+            rows = np.ones(sc.n, bool) if not sparse else mask
+            if k == "sh":
+                per = p0.reshape(sc.n, -1).shape[1]
+                want = np.empty_like(p0.reshape(sc.n, -1), dtype=np.float64)
+                for c in range(per):
+                    lr = model.adam.lr[4] if c < 3 else model.adam.lr[5]
+                    pc, _, _ = oracle.adam(p0.reshape(sc.n, -1)[:, c], g.reshape(sc.n, -1)[:, c],
+                                           m0.reshape(sc.n, -1)[:, c], v0.reshape(sc.n, -1)[:, c], lr, step=1)
+                    want[:, c] = pc
+                want = want.reshape(p0.shape)
+            else:
+                want, _, _ = oracle.adam(p0.reshape(-1), g.reshape(-1), m0.reshape(-1), v0.reshape(-1), lrs[k], step=1)
+                want = want.reshape(p0.shape)
+            r = rows.reshape((-1,) + (1,) * (p0.ndim - 1))
+            moved = np.broadcast_to(r, p0.shape)
+            np.testing.assert_allclose(p1[moved], want[moved], rtol=1e-6, atol=1e-7, err_msg=f"{k} sparse={sparse}")
+            if sparse:
+                assert np.array_equal(p1[~moved], p0[~moved]), k
+                assert np.array_equal(model.m[k].cpu().numpy()[~moved], m0[~moved]), k
+            else:
+                assert not np.array_equal(p1[~mask], p0[~mask]), k  # the moments still decay and move them
+
+
+# ----------------------------------------------------------------------------- training policies (Sec. III-D, III-E)
+def test_switching_views_off_in_a_captured_step_equals_the_step_without_them(gpu_lib):
+    """set_weights between graph replays: a negative weight switches a view off (nothing projected into it).  Each
+    replay's loss and gradients equal those of a step built on the active views alone, and the graph follows the
+    new weights from one replay to the next."""
+    import dataclasses
+
+    sc = scenes.random_scene(2700, 2500, 80, 60, sh_degree=1, views=4, log_scale_mu=-2.3, depth_fraction=0.3)
+    P = [c.width * c.height for c in sc.cams]
+    off = np.cumsum([0] + P)
+    scale = oracle.gradient_scale(sc.params(), 1, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
+    mg = GaussianModel(sc.params(), 1)
+    for i in range(6):
+        mg.adam.lr[i] = 0.0  # no movement: every replay sees the same map
+    st = BatchedStep(mg, sc.cams, sc.tgt_rgb, sc.tgt_depth, keep_grads=True)
+    for active in ([0, 2], [1, 3], [0, 1, 2, 3], [3]):
+        w = [sc.cams[i].weight if i in active else -1.0 for i in range(len(sc.cams))]
+        st.set_weights(w)
+        st.run()
+        st.finish()
+        torch.cuda.synchronize()
+        sub = [sc.cams[i] for i in active]
+        tr = np.concatenate([sc.tgt_rgb[3 * off[i]:3 * off[i + 1]] for i in active])
+        td = np.concatenate([sc.tgt_depth[off[i]:off[i + 1]] for i in active])
+        mr = GaussianModel(sc.params(), 1)
+        ref = BatchedStep(mr, sub, tr, td, keep_grads=True)
+        ref.run_eager()
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(st.loss(), ref.loss(), rtol=1e-5, err_msg=str(active))
+        for k in mg.g:
+            a, b = mg.g[k].cpu().numpy().astype(np.float64), mr.g[k].cpu().numpy().astype(np.float64)
+            rnd = ROUND_C * U32 * scale[k].reshape(a.shape)
+            assert np.all(np.abs(a - b) <= 1e-5 * np.abs(b) + 2 * rnd), (active, k)
+        log("views", active, "loss", st.loss())
+    assert st.replans == 0
+
+
+def test_sh_degree_raise_keeps_the_rendered_images(gpu_lib):
+    """Raising the SH degree re-packs the coefficients with zeros for the new bands: the rendered images are
+    unchanged (bit for bit) and the new coefficients then take gradients."""
+    sc = scenes.random_scene(2800, 1500, 64, 48, sh_degree=0, views=2, log_scale_mu=-2.3)
+    model = GaussianModel(sc.params(), 0)
+    images = []
+    for deg in (0, 1, 3):
+        if deg:
+            model.set_sh_degree(deg)
+        fr = B.Frame(model.n, sc.cams)
+        B.gs_project(model.ps, fr)
+        B.gs_bin_tiles(fr, sync_count=True)
+        rgb, depth, vis = fr.empty_images()
+        B.gs_render_fwd(fr, rgb, depth, vis)
+        images.append(rgb.cpu().numpy())
+    assert np.array_equal(images[0], images[1]) and np.array_equal(images[0], images[2])
+    st = BatchedStep(model, sc.cams, sc.tgt_rgb, sc.tgt_depth, keep_grads=True)
+    st.run_eager()
+    assert np.abs(model.g["sh"][:, 9:].cpu().numpy()).max() > 0
+
+
+def test_mapper_runs_the_training_policies(gpu_lib):
+    """The mapping loop on one captured step: keyframes arrive through the delay buffer, each is optimised once on
+    arrival and then picked at random up to its cap, coarse-to-fine levels per keyframe, the SH degree ramps
+    0 -> 3 and low-opacity Gaussians are pruned.  The loss over every view at full resolution goes down."""
+    from paper_2411_02703_amd.schedule import DelayBuffer, KeyframeQueue, PyramidSchedule, SHSchedule
+    from paper_2411_02703_amd.step import Mapper
+
+    import dataclasses
+
+    base = scenes.random_scene(2900, 3000, 96, 72, sh_degree=0, views=4, log_scale_mu=-2.2)
+    rng = np.random.default_rng(2901)
+    kf_cams, rgbs, depths = [], [], []
+    for c in base.cams:
+        c0 = dataclasses.replace(c, width=96, height=72, cx=48.0, cy=36.0, weight=1.0)
+        kf_cams.append([c0.scaled(l) for l in range(3)])
+        r, d = scenes.pyramid_targets(rng, c0, 3, depth_fraction=0.3)
+        rgbs += [x.reshape(-1) for x in r]
+        depths += [x.reshape(-1) for x in d]
+    cams = [c for levels in kf_cams for c in levels]
+    tr = np.ascontiguousarray(np.concatenate(rgbs), np.float32)
+    td = np.ascontiguousarray(np.concatenate(depths), np.float32)
+    model = GaussianModel(base.params(), 0)
+    mp = Mapper(model, kf_cams, tr, td, queue=KeyframeQueue(cap=12, seed=5), delay=DelayBuffer(delay=1),
+                pyramid=PyramidSchedule(levels=3, iters_per_level=3), sh=SHSchedule(every=10), arrive_every=2,
+                prune_every=15, min_opacity=0.02)
+    L0 = oracle.loss(base.params(), 0, cams, tr, td)
+    for _ in range(45):
+        mp.iterate()
+    mp.step.finish()
+    torch.cuda.synchronize()
+    hist = mp.history
+    assert hist[0]["keyframes"] == [] and hist[2]["keyframes"] == [0]  # keyframe 0 waits for one newer arrival
+    assert [h["sh_degree"] for h in hist][::10] == [0, 1, 2, 3, 3]
+    first = {}
+    for h in hist:
+        for k, lv in zip(h["keyframes"], h.get("levels", [])):
+            first.setdefault(k, []).append(lv)
+    for k, lvs in first.items():
+        assert lvs == sorted(lvs, reverse=True) and lvs[0] == 2, (k, lvs)
+        assert len(lvs) <= 12
+    assert all(c <= 12 for c in mp.queue.counts.values())
+    assert hist[-1]["n"] <= 3000
+    params = {k: v.cpu().numpy() for k, v in model.p.items()}
+    L1 = oracle.loss(params, model.sh_degree, cams, tr, td)
+    log("mapper: loss", L0, "->", L1, "Gaussians", hist[-1]["n"])
+    assert L1 < L0
+
+
 # ----------------------------------------------------------------------------- full-size workloads
 # The scenes the benchmark times (1M Gaussians, SH degree 3), in its launch configurations (tile shape,
 # block width, depth segments), checked where the oracle can follow: whole images of the single-keyframe

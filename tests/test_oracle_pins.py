@@ -523,3 +523,43 @@ def test_adam_matches_torch():
         opt.step()
         mine, m, v = oracle.adam(mine, g, m, v, 0.01, step=step)
         np.testing.assert_allclose(mine, p.detach().numpy(), rtol=1e-13, atol=1e-15)
+
+
+# ----------------------------------------------------------------------------- opacity pruning
+def test_prune_keeps_opacities_at_or_above_the_threshold_in_order():
+    """Section III-C's prunable threshold: kept = sigmoid(logit) >= tau, original order.  Away from the threshold
+    the decision is the plain sigmoid comparison; exactly at it the FP32 logit of tau is kept."""
+    rng = np.random.default_rng(41)
+    logit = rng.normal(0, 2, 5000).astype(np.float32).astype(np.float64)
+    tau = 0.05
+    kept = oracle.prune(logit, tau)
+    sig = 1.0 / (1.0 + np.exp(-logit))
+    far = np.abs(sig - tau) > 1e-6
+    want = np.flatnonzero(sig >= tau)
+    assert np.array_equal(np.intersect1d(kept, np.flatnonzero(far)), np.intersect1d(want, np.flatnonzero(far)))
+    assert np.all(np.diff(kept) > 0)
+    thr32 = np.float32(math.log(tau / (1 - tau)))
+    edge = np.array([np.nextafter(thr32, np.float32(-10)), thr32, np.nextafter(thr32, np.float32(10))], np.float64)
+    assert list(oracle.prune(edge, tau)) == [1, 2]
+    assert oracle.prune(np.full(4, -20.0), tau).size == 0
+    assert oracle.prune(np.full(4, 20.0), tau).size == 4
+
+
+def test_inactive_view_is_the_view_removed():
+    """A negative loss weight marks an inactive view (a schedule switching a view off): the oracle's loss and
+    gradients equal those of the same scene without that view, and the view renders nothing."""
+    import dataclasses
+
+    sc = scenes.random_scene(43, 300, 40, 30, sh_degree=1, views=3, log_scale_mu=-2.3, depth_fraction=0.5)
+    P = [c.width * c.height for c in sc.cams]
+    off = np.cumsum([0] + P)
+    cams_off = [dataclasses.replace(c, weight=-1.0) if i == 1 else c for i, c in enumerate(sc.cams)]
+    L, g, _, _, img = oracle.backward(64, sc.params(), 1, cams_off, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
+    keep = [0, 2]
+    tr = np.concatenate([sc.tgt_rgb[3 * off[i]:3 * off[i + 1]] for i in keep])
+    td = np.concatenate([sc.tgt_depth[off[i]:off[i + 1]] for i in keep])
+    L2, g2, _, _, _ = oracle.backward(64, sc.params(), 1, [sc.cams[i] for i in keep], tgt_rgb=tr, tgt_depth=td)
+    assert L == pytest.approx(L2, rel=1e-13)
+    for k in g:
+        np.testing.assert_allclose(g[k], g2[k], rtol=1e-12, atol=1e-15)
+    assert np.all(img["vis"][off[1]:off[2]] == 0)

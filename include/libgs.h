@@ -317,6 +317,36 @@ int gs_prune(const gs_params* params, const gs_params* m, const gs_params* v, fl
              const gs_params* out_params, const gs_params* out_m, const gs_params* out_v, int64_t* n_kept,
              void* scratch, void* stream);
 
+/* Map expansion (Sections III-A, III-C, III-E): a keyframe's colourised LiDAR points become new Gaussians.
+ *  1. visibility filter (Sec. III-C): a point projected into the keyframe (FP32, the projection's operation order)
+ *     is kept where the keyframe's rendered visibility V at its pixel is at most tau_alpha (the map does not yet
+ *     explain that pixel; the paper's sentence is garbled, this is its stated purpose); points behind the near
+ *     plane or outside the image are kept;
+ *  2. voxel deduplication and density cap (Sec. III-A): a point is accepted while its voxel (floor(x / voxel),
+ *     FP32 IEEE division, |index| < 2^20) holds fewer than `cap` points: the map's n_old Gaussians, then this
+ *     batch's accepted points in input order;
+ *  3. initialisation (Sec. III-E): mean = the point; log-scales = log sqrt of the mean squared distance to its 3
+ *     nearest accepted neighbours (at least 1e-7; fewer neighbours: the mean over those present); identity
+ *     rotation; opacity logit = log(init_opacity / (1 - init_opacity)); SH degree-0 coefficients
+ *     (rgb - 0.5) / Y_0, higher bands 0; Adam moments 0.
+ * The accepted points are appended, in input order, as rows n_old .. n_old + *n_added - 1 of params, m and v,
+ * whose arrays must have room for n_old + n_points rows (params->n is that room; rows below n_old are read, the
+ * map's means only).  points, colours: device [n_points][3]; vis: device [H][W] visibility image of `cam` (host;
+ * only R, T, fx, fy, cx, cy, width, height are read).  *n_added (device) receives the count.  scratch: device,
+ * gs_expand_scratch_bytes(n_old, n_points) bytes.  GS_ERR_ARG for bad sizes or options, NULL pointers. */
+typedef struct gs_expand_opts {
+  float tau_alpha;    /* visibility threshold */
+  float near_z;       /* 0.2 */
+  float voxel;        /* voxel edge, metres (0.1) */
+  float knn_cell;     /* cell edge of the neighbour grid, metres (> 0) */
+  float init_opacity; /* opacity of a new Gaussian (0.1) */
+  int32_t cap;        /* points per voxel (1: a voxel that holds a point takes no other) */
+} gs_expand_opts;
+size_t gs_expand_scratch_bytes(int64_t n_old, int64_t n_points);
+int gs_expand(const gs_params* params, const gs_params* m, const gs_params* v, int64_t n_old, const float* points,
+              const float* colours, int64_t n_points, const gs_camera* cam, const float* vis,
+              const gs_expand_opts* opts, int64_t* n_added, void* scratch, void* stream);
+
 /* ------------------------------------------------------------------ utilities */
 /* Work counts of the frame's forward compositing at its tile shape, ADDED to counts[0..1] (device, uint64):
  * [0] pairs evaluated (each record of a pixel's tile list up to the record that stops the pixel),

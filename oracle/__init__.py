@@ -35,6 +35,7 @@ def lib() -> ctypes.CDLL:
         _lib.oracle_bin.restype = ctypes.c_int64
         _lib.oracle_ssim_plane.restype = ctypes.c_double
         _lib.oracle_prune.restype = ctypes.c_int64
+        _lib.oracle_expand.restype = ctypes.c_int64
         _lib.oracle_ssim_loss.restype = ctypes.c_double
     return _lib
 
@@ -256,6 +257,27 @@ def prune(opacity_logit, min_opacity: float) -> np.ndarray:
     idx = np.zeros(max(o.size, 1), np.int64)
     k = lib().oracle_prune(_p(o), ctypes.c_int64(o.size), ctypes.c_double(min_opacity), _p(idx))
     return idx[:k]
+
+
+def expand(points, colours, cam, vis, tau_alpha: float, map_means, voxel: float, cap: int = 1,
+           init_opacity: float = 0.1, sh_degree: int = 0, near: float = 0.2):
+    """Map expansion of one keyframe's points: (kept mask [M], new Gaussians' parameters in input order)."""
+    pts = _f64(np.asarray(points).reshape(-1, 3))
+    rgb = _f64(np.asarray(colours).reshape(-1, 3))
+    M = pts.shape[0]
+    camv = _f64([*np.asarray(cam.R, np.float64).reshape(-1), *np.asarray(cam.T, np.float64), cam.fx, cam.fy, cam.cx,
+                 cam.cy, cam.width, cam.height])
+    mm = _f64(np.asarray(map_means).reshape(-1, 3)) if map_means is not None else np.zeros((0, 3))
+    K = (sh_degree + 1) ** 2
+    kept = np.zeros(M, np.int32)
+    out = dict(means=np.zeros((M, 3)), log_scales=np.zeros((M, 3)), quats=np.zeros((M, 4)), opacity=np.zeros(M),
+               sh=np.zeros((M, K, 3)))
+    A = lib().oracle_expand(_p(pts), _p(rgb), ctypes.c_int64(M), _p(camv), _p(_f64(np.asarray(vis).reshape(-1))),
+                            ctypes.c_double(tau_alpha), ctypes.c_double(near), _p(mm), ctypes.c_int64(mm.shape[0]),
+                            ctypes.c_double(voxel), ctypes.c_int(cap), ctypes.c_double(init_opacity),
+                            ctypes.c_int(sh_degree), _p(kept), _p(out["means"]), _p(out["log_scales"]),
+                            _p(out["quats"]), _p(out["opacity"]), _p(out["sh"]))
+    return kept.astype(bool), {k: v[:A] for k, v in out.items()}
 
 
 SSIM_LAMBDA = 0.2  # weight of the SSIM term in eq. Lc (the value of the 3DGS work the paper builds on)

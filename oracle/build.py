@@ -4,7 +4,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, f) for f in ("oracle.cpp", "ssim.cpp")]
+SRCS = [os.path.join(HERE, f) for f in ("oracle.cpp", "ssim.cpp", "expand.cpp")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 FLAGS = ["-std=c++17", "-O3", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]

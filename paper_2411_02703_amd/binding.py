@@ -64,6 +64,11 @@ class gs_loss(ctypes.Structure):
                 ("lambda_d", c_f), ("lambda_ssim", c_f)]
 
 
+class gs_expand_opts(ctypes.Structure):
+    _fields_ = [("tau_alpha", c_f), ("near_z", c_f), ("voxel", c_f), ("knn_cell", c_f), ("init_opacity", c_f),
+                ("cap", c_i32)]
+
+
 class gs_adam(ctypes.Structure):
     _fields_ = [("lr", c_f * 6), ("beta1", c_f), ("beta2", c_f), ("eps", c_f), ("flags", c_i32),
                 ("step", c_vp), ("bias", c_vp), ("skip_flags", c_vp)]
@@ -78,6 +83,7 @@ GS_ADAM_SPARSE = 1
 EXPORTED = ["gs_default_opts", "gs_plan_cameras", "gs_frame_bytes", "gs_frame_init", "gs_project", "gs_bin_tiles",
             "gs_render_fwd", "gs_render_bwd", "gs_composite_bwd", "gs_project_bwd", "gs_adam_step",
             "gs_render_bwd_adam", "gs_ssim", "gs_prune_scratch_bytes", "gs_prune",
+            "gs_expand_scratch_bytes", "gs_expand",
             "gs_count_pairs", "gs_read_counters", "gs_sort_scratch_ints", "gs_sort_pairs", "gs_sort_static_max",
             "gs_sort_pairs_static", "gs_status_string",
             "gs_last_error", "gs_version"]
@@ -108,6 +114,10 @@ def load() -> ctypes.CDLL:
     lib.gs_composite_bwd.argtypes = [P(gs_frame), P(gs_opts), P(gs_images), P(gs_loss), c_vp]
     lib.gs_project_bwd.argtypes = [P(gs_params), P(gs_frame), P(gs_opts), P(gs_params), c_vp]
     lib.gs_adam_step.argtypes = [P(gs_params), P(gs_params), P(gs_params), P(gs_params), P(gs_adam), c_vp]
+    lib.gs_expand_scratch_bytes.argtypes = [c_i64, c_i64]
+    lib.gs_expand_scratch_bytes.restype = ctypes.c_size_t
+    lib.gs_expand.argtypes = [P(gs_params), P(gs_params), P(gs_params), c_i64, c_vp, c_vp, c_i64, P(gs_camera), c_vp,
+                              P(gs_expand_opts), c_vp, c_vp, c_vp]
     lib.gs_prune_scratch_bytes.argtypes = [c_i64]
     lib.gs_prune_scratch_bytes.restype = ctypes.c_size_t
     lib.gs_prune.argtypes = [P(gs_params), P(gs_params), P(gs_params), c_f, P(gs_params), P(gs_params), P(gs_params),
@@ -334,6 +344,22 @@ def gs_prune(params: gs_params, m: gs_params, v: gs_params, min_opacity: float, 
     _check(load().gs_prune(ctypes.byref(params), ctypes.byref(m), ctypes.byref(v), float(min_opacity),
                            ctypes.byref(out_params), ctypes.byref(out_m), ctypes.byref(out_v), n_kept.data_ptr(),
                            scratch.data_ptr(), _stream(stream)), "gs_prune")
+
+
+def gs_expand(params: gs_params, m: gs_params, v: gs_params, n_old: int, points: torch.Tensor,
+              colours: torch.Tensor, cam, vis: torch.Tensor, opts: gs_expand_opts, n_added: torch.Tensor,
+              stream=None) -> None:
+    """Map expansion: accepted points appended as rows n_old.. of params, m, v; n_added (int64 CUDA) the count."""
+    M = int(points.shape[0])
+    for t in (points, colours, vis):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise ValueError("points, colours and vis must be contiguous float32 CUDA tensors")
+    c = make_cameras([cam])
+    scratch = torch.empty(int(load().gs_expand_scratch_bytes(n_old, M)) // 4 + 64, dtype=torch.int32,
+                          device=points.device)
+    _check(load().gs_expand(ctypes.byref(params), ctypes.byref(m), ctypes.byref(v), int(n_old), points.data_ptr(),
+                            colours.data_ptr(), M, c, vis.data_ptr(), ctypes.byref(opts), n_added.data_ptr(),
+                            scratch.data_ptr(), _stream(stream)), "gs_expand")
 
 
 def gs_read_counters(frame: Frame, stream=None):

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build", "libgs")
 LIB = os.path.join(HERE, "libgs.so")
-SOURCES = ["project.hip", "bin.hip", "render.hip", "ssim.hip", "adam.hip", "maintain.hip", "api.hip"]
+SOURCES = ["project.hip", "bin.hip", "render.hip", "ssim.hip", "adam.hip", "maintain.hip", "expand.hip", "api.hip"]
 ARCH = os.environ.get("GS_OFFLOAD_ARCH", "gfx950")
 
 # Packed-FP32 instruction forms are disabled for every kernel (-packed-fp32-ops).  The compiler's atomic

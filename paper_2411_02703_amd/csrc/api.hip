@@ -421,6 +421,34 @@ int gs_prune(const gs_params* p, const gs_params* m, const gs_params* v, float m
   return GS_OK;
 }
 
+size_t gs_expand_scratch_bytes(int64_t n_old, int64_t M) {
+  return (n_old < 0 || M < 1) ? 0 : 4 * gs_launch::expand_scratch_ints(n_old, M);
+}
+
+int gs_expand(const gs_params* p, const gs_params* m, const gs_params* v, int64_t n_old, const float* pts,
+              const float* rgb, int64_t M, const gs_camera* cam, const float* vis, const gs_expand_opts* o,
+              int64_t* n_added, void* scratch, void* stream) {
+  int rc;
+  if ((rc = params_check(p, "params")) || (rc = params_check(m, "m")) || (rc = params_check(v, "v"))) return rc;
+  if (m->n != p->n || v->n != p->n || m->sh_degree != p->sh_degree || v->sh_degree != p->sh_degree)
+    return fail(GS_ERR_ARG, "expand: params / moments sizes differ");
+  if (!pts || !rgb || !cam || !vis || !o || !n_added || !scratch) return fail(GS_ERR_ARG, "expand: NULL pointer");
+  if (M < 1 || M > INT32_MAX || n_old < 0 || n_old + M > p->n)
+    return fail(GS_ERR_ARG, "expand: %lld points after %lld Gaussians need room for %lld rows, have %lld",
+                (long long)M, (long long)n_old, (long long)(n_old + M), (long long)p->n);
+  if (cam->width < 1 || cam->height < 1 || !(cam->fx > 0.f) || !(cam->fy > 0.f))
+    return fail(GS_ERR_ARG, "expand: bad camera");
+  if (!(o->voxel > 0.f) || !(o->knn_cell > 0.f) || o->cap < 1 || !(o->tau_alpha >= 0.f) ||
+      !(o->init_opacity > 0.f && o->init_opacity < 1.f) || !(o->near_z > 0.f))
+    return fail(GS_ERR_ARG, "expand: bad options");
+  const float logit = (float)std::log((double)o->init_opacity / (1.0 - (double)o->init_opacity));
+  GS_HIP(gs_launch::expand(*p, *m, *v, n_old, pts, rgb, M, *cam, vis, o->tau_alpha, o->near_z, o->voxel, o->cap,
+                           o->knn_cell, logit, n_added, static_cast<int32_t*>(scratch),
+                           static_cast<hipStream_t>(stream)),
+         "gs_expand");
+  return GS_OK;
+}
+
 static int adam_check(const gs_adam* a) {
   if (!a || !a->step || !a->bias) return fail(GS_ERR_ARG, "adam state is NULL");
   if (a->flags & ~GS_ADAM_SPARSE) return fail(GS_ERR_ARG, "unknown Adam flags %d", a->flags);

@@ -158,6 +158,12 @@ hipError_t ssim(const gs_camera* cams_host, const gs_camera* cams_dev, int n_vie
 size_t prune_scratch_ints(int64_t n);
 hipError_t prune(const gs_params& p, const gs_params& m, const gs_params& v, float thr_logit, const gs_params& op,
                  const gs_params& om, const gs_params& ov, int64_t* n_kept, int32_t* scratch, hipStream_t s);
+// Map expansion: filter, voxel cap, neighbour spacing and the new rows (scratch: expand_scratch_ints(n_old, M)).
+size_t expand_scratch_ints(int64_t n_old, int64_t M);
+hipError_t expand(const gs_params& p, const gs_params& m, const gs_params& v, int64_t n_old, const float* pts,
+                  const float* rgb, int64_t M, const gs_camera& cam, const float* vis, float tau, float near_z,
+                  float voxel, int cap, float cell, float init_logit, int64_t* n_added, int32_t* scratch,
+                  hipStream_t s);
 // The step counter and bias corrections of one Adam step (skipped when *skip_flags has the overflow bit).
 hipError_t adam_prep(const gs_adam& a, const int32_t* skip_flags, hipStream_t s);
 // Projection backward fused with Adam: params, m, v updated in place; the gradient is written to grads_out

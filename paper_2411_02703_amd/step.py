@@ -84,6 +84,37 @@ class GaussianModel:
         self.ms = B.params_struct(self.m, degree)
         self.vs = B.params_struct(self.v, degree)
 
+    def expand(self, points, colours, cam, vis: torch.Tensor, tau_alpha: float = 0.5, voxel: float = 0.1,
+               cap: int = 1, knn_cell: float = 0.5, init_opacity: float = 0.1, near_z: float = 0.2) -> int:
+        """Append a keyframe's LiDAR points as new Gaussians (visibility filter against the keyframe's rendered
+        visibility `vis` [H*W], voxel cap against the map, neighbour-spacing initialisation; gs_expand).  Returns
+        the number added.  Frames and steps must be rebuilt (the count changes)."""
+        dev = self.p["means"].device
+        pts = torch.as_tensor(np.ascontiguousarray(points, np.float32)).to(dev)
+        rgb = torch.as_tensor(np.ascontiguousarray(colours, np.float32)).to(dev)
+        n_old, M = self.n, int(pts.shape[0])
+        grown = []
+        for d in (self.p, self.m, self.v):
+            out = {}
+            for k, t in d.items():
+                big = torch.zeros((n_old + M,) + tuple(t.shape[1:]), dtype=t.dtype, device=dev)
+                big[:n_old] = t
+                out[k] = big
+            grown.append(out)
+        structs = [B.params_struct(d, self.sh_degree) for d in grown]
+        n_added = torch.zeros(1, dtype=torch.int64, device=dev)
+        o = B.gs_expand_opts(float(tau_alpha), float(near_z), float(voxel), float(knn_cell), float(init_opacity),
+                             int(cap))
+        B.gs_expand(structs[0], structs[1], structs[2], n_old, pts, rgb, cam, vis.contiguous(), o, n_added)
+        k = int(n_added.item())
+        self.p, self.m, self.v = ({key: t[:n_old + k] for key, t in d.items()} for d in grown)
+        self.g = {key: torch.zeros_like(t) for key, t in self.p.items()}
+        self.ps = B.params_struct(self.p, self.sh_degree)
+        self.gs = B.params_struct(self.g, self.sh_degree)
+        self.ms = B.params_struct(self.m, self.sh_degree)
+        self.vs = B.params_struct(self.v, self.sh_degree)
+        return k
+
     def set_sparse_adam(self, on: bool = True) -> None:
         """Visible-only Adam in the fused backward (gs_render_bwd_adam): Gaussians seen by no view of the step keep
         their parameters and moments."""

@@ -985,6 +985,62 @@ def test_sparse_adam_updates_only_visible_gaussians(gpu_lib):
                 assert not np.array_equal(p1[~mask], p0[~mask]), k  # the moments still decay and move them
 
 
+def _expand_case(seed, n_map, n_pts, spread, cap, isolated=0):
+    """A keyframe of the LiDAR-like scene: the map's Gaussians and new points (some on top of the map, some
+    new, some isolated far away), the keyframe's visibility rendered from the map."""
+    rng = np.random.default_rng(seed)
+    sc = scenes.random_scene(seed, n_map, 96, 72, sh_degree=1, views=1, log_scale_mu=-2.0)
+    cam = sc.cams[0]
+    old = sc.means[rng.integers(0, n_map, n_pts // 3)] + rng.normal(0, 0.02, (n_pts // 3, 3))
+    z = rng.uniform(2.0, 20.0, n_pts - n_pts // 3)
+    u = rng.uniform(-10, 106, z.size)
+    v = rng.uniform(-8, 80, z.size)
+    new = np.stack([(u - cam.cx) * z / cam.fx, (v - cam.cy) * z / cam.fy, z], 1)
+    pts = np.concatenate([old, new]) + rng.normal(0, spread, (n_pts, 3))
+    if isolated:
+        pts[rng.integers(0, n_pts, isolated)] += rng.uniform(30, 60, (isolated, 3))
+    pts = pts.astype(np.float32)
+    rgb = rng.uniform(0, 1, (n_pts, 3)).astype(np.float32)
+    return sc, cam, pts, rgb
+
+
+@pytest.mark.parametrize("seed,n_map,n_pts,cap,cell,isolated", [(3000, 2000, 3000, 1, 0.5, 0),
+                                                                 (3001, 5000, 20000, 2, 0.25, 40),
+                                                                 (3002, 1, 1, 1, 0.5, 0)])
+def test_map_expansion_matches_oracle(gpu_lib, seed, n_map, n_pts, cap, cell, isolated):
+    """gs_expand against the oracle: the accepted points (visibility filter against the keyframe's rendered
+    visibility, voxel cap against the map and the batch) bit for bit, the new Gaussians' means bit for bit, their
+    log-scales from the 3-nearest-neighbour spacing within FP32 rounding (1e-5 absolute on a log), opacity and
+    SH colour within 1e-6; the existing rows are untouched and the new moments are zero."""
+    sc, cam, pts, rgb = _expand_case(seed, n_map, n_pts, 0.05, cap, isolated)
+    model = GaussianModel(sc.params(), 1)
+    fr = B.Frame(model.n, [cam])
+    B.gs_project(model.ps, fr)
+    B.gs_bin_tiles(fr, sync_count=True)
+    rgb_img, depth, vis = fr.empty_images()
+    B.gs_render_fwd(fr, rgb_img, depth, vis)
+    vis_np = vis.cpu().numpy().reshape(cam.height, cam.width)
+    before = {k: t.cpu().numpy().copy() for k, t in model.p.items()}
+    kept, ref = oracle.expand(pts, rgb, cam, vis_np, 0.5, before["means"], voxel=0.1, cap=cap, init_opacity=0.1,
+                              sh_degree=1)
+    log("expand", n_pts, "points, kept", int(kept.sum()), "of which isolated", isolated)
+    k = model.expand(pts, rgb, cam, vis, tau_alpha=0.5, voxel=0.1, cap=cap, knn_cell=cell, init_opacity=0.1)
+    assert k == int(kept.sum())
+    n0 = n_map
+    for key, t in model.p.items():
+        got = t.cpu().numpy()
+        assert np.array_equal(got[:n0], before[key]), key
+    new = {key: t.cpu().numpy()[n0:] for key, t in model.p.items()}
+    assert np.array_equal(new["means"], ref["means"].astype(np.float32))
+    np.testing.assert_allclose(new["log_scales"], ref["log_scales"], rtol=0, atol=1e-5)
+    np.testing.assert_array_equal(new["quats"], ref["quats"].astype(np.float32))
+    np.testing.assert_allclose(new["opacity"], ref["opacity"], rtol=1e-6)
+    np.testing.assert_allclose(new["sh"], ref["sh"], rtol=1e-6, atol=1e-7)
+    for d in (model.m, model.v):
+        for t in d.values():
+            assert not t[n0:].any()
+
+
 # ----------------------------------------------------------------------------- training policies (Sec. III-D, III-E)
 def test_switching_views_off_in_a_captured_step_equals_the_step_without_them(gpu_lib):
     """set_weights between graph replays: a negative weight switches a view off (nothing projected into it).  Each

@@ -128,8 +128,8 @@ typedef struct gs_frame {
   int64_t n_pixels;     /* pixels over all views */
   int64_t max_view_pixels; /* pixels of the largest view */
   int64_t capacity;     /* tile-instance capacity (<= 2^31 - 1) */
-  int32_t key_bits;     /* 32 depth bits + tile bits */
-  int32_t sort_passes;  /* 8-bit LSD passes */
+  int32_t key_bits;     /* bits of a global tile id (the instance sort key) */
+  int32_t sort_passes;  /* 8-bit LSD passes of the instance sort */
   int32_t tile_w, tile_h;
   int32_t seg_len;      /* depth-segment length of the compositing calls (0: lists are never split) */
   int32_t seg_cap;      /* capacity of segment slots: 2 * capacity / seg_len + 2 */
@@ -142,18 +142,24 @@ typedef struct gs_frame {
   float* rec;           /* [n_views*n][12]: {mu_x, mu_y, z, o}, {conic a, b, c, red},
                            {green, blue, px0 | px1 << 16, py0 | py1 << 16} (pixel rectangle as int16 pairs) */
   int16_t* rect;        /* [n_views*n][4]: tile rectangle tx0, tx1, ty0, ty1 (valid when visible) */
-  float* ipart;         /* [capacity][12]: per tile instance, in emission order (blocks of 64 consecutive
-                           Gaussians starting at inst_off of the block's first Gaussian; inside a block view by
-                           view, Gaussian by Gaussian, the tiles of each rectangle row by row), the
-                           compositing backward's partial
+  float* ipart;         /* [capacity][12]: per tile instance, in emission order (records in ascending depth, ties
+                           by record index; each record's tiles row by row, one contiguous run per record starting
+                           at rec_inst of the record), the compositing backward's partial
                            dL/d{mu_x, mu_y, a, b, c, o, red, green, blue, z} of its record summed over the
                            pixels of its tile (or depth segment); 2 words of padding.  Every backward call
                            writes every instance once (plain stores, no atomics) */
   int32_t* inst_rec;    /* [capacity]: record of each instance in emission order */
   uint64_t* vis_mask;   /* [n]: bit v set if Gaussian g is visible in view v */
   int32_t* n_inst;      /* [n]: tile instances of Gaussian g over all views */
-  int32_t* inst_off;    /* [n]: exclusive scan of n_inst */
-  uint64_t* keys[2];    /* [capacity] ping-pong sort buffers */
+  int32_t* n_rec;       /* [n]: visible records (views) of Gaussian g */
+  int32_t* rec_first;   /* [n]: exclusive scan of n_rec: where g's records start in the record list */
+  uint32_t* zbits;      /* [n_views*n]: IEEE bits of the camera depth of each visible record */
+  int32_t* rec_inst;    /* [n_views*n]: first emission index of each visible record */
+  int64_t rec_cap;      /* capacity of the record list: min(n_views * n, capacity) */
+  uint32_t* rkeys[2];   /* [rec_cap] record list: depth bits (sorted into rkeys[0]) */
+  int32_t* rvals[2];    /* [rec_cap] record list: record ids (sorted into rvals[0]); rvals[1] then holds each
+                           sorted record's first emission index */
+  uint32_t* keys[2];    /* [capacity] instance keys: global tile ids (sorted into keys[sort_passes & 1]) */
   int32_t* vals[2];     /* [capacity] emission indices while sorting; after gs_bin_tiles vals[sort_passes & 1]
                            holds the record id of each sorted instance and the other buffer its emission
                            index */
@@ -161,7 +167,8 @@ typedef struct gs_frame {
   int32_t* tile_order;  /* [n_tiles]: tiles by descending list length (the compositing schedule) */
   int32_t* counters;    /* [256]: [0] instance count, [1] flags, [2..2+n_views) valid depth pixels per view,
                            [128..192) tile-length bucket counts and offsets, [192] work items,
-                           [193] segment slots of split tiles, [194] split tiles */
+                           [193] segment slots of split tiles, [194] split tiles, [196] visible records,
+                           [197] instances summed per Gaussian */
   int32_t* seg_count;   /* [n_tiles]: segments of the tile at each schedule position */
   int32_t* seg_first;   /* [n_tiles]: exclusive scan of seg_count = first work item of that tile */
   int32_t* items;       /* [item_cap][4]: work items of the compositing calls, split tiles first:
@@ -227,19 +234,21 @@ int gs_frame_init(gs_frame* frame, void* block, size_t bytes, int64_t n, const g
 
 /* ------------------------------------------------------------------ the five hot-path calls */
 /* Projection of every Gaussian into every view of the frame (Section III-B, eqs. Sigma and muI):
- * writes records, tile rectangles, visibility masks and per-Gaussian instance counts.  Reads each
+ * writes records, tile rectangles, depth bits, visibility masks and per-Gaussian record counts.  Reads each
  * Gaussian once. */
 int gs_project(const gs_params* params, const gs_frame* frame, const gs_opts* opts, void* stream);
 
 /* Tile binning (Section III-B: rasterisation iterates over the Gaussians rather than along camera rays, and
- * eq. Cp composites them in depth order, the product over j < i running over the Gaussians in front): exclusive
- * scan of instance counts, emission of (global tile << 32 | depth bits, record) pairs, stable LSD radix sort,
- * per-tile ranges.  The order within a tile is ascending depth, ties by record index, which makes the sorted
- * order unique.  Errors: GS_ERR_ARG for a frame whose key bits exceed 64 or whose capacity is not positive;
- * an instance count above the capacity sets GS_FLAG_INSTANCE_OVERFLOW (instances past the capacity are
- * dropped, the frame's outputs are then undefined, and the count in counters[0] is still the full count).  sync_count != 0 synchronises the stream after the scan to size the work exactly and
- * returns the instance count in *n_instances (host, nullable); otherwise the work is sized by the
- * capacity and the count stays on the device (graph-capturable). */
+ * eq. Cp composites them in depth order, the product over j < i running over the Gaussians in front).  The
+ * visible records are sorted by depth (stable LSD radix sort of their 32-bit depth bits, records listed
+ * Gaussian by Gaussian), emitted in that order as runs of tile instances, and the instances sorted by global
+ * tile id (stable): within a tile the order is ascending depth, ties by record index, which makes the sorted
+ * order unique; per-tile ranges and the compositing schedule follow.  Errors: GS_ERR_ARG for an uninitialised
+ * frame or options that do not match it; more instances than the capacity set GS_FLAG_INSTANCE_OVERFLOW
+ * (instances past the capacity are dropped, the frame's outputs are then undefined, and counters[0] still holds
+ * the full count).  sync_count != 0 synchronises the stream after the instance total to size the instance work
+ * exactly and returns the instance count in *n_instances (host, nullable); otherwise the work is sized by the
+ * capacity and the counts stay on the device (graph-capturable). */
 int gs_bin_tiles(const gs_frame* frame, const gs_opts* opts, int32_t sync_count, int64_t* n_instances,
                  void* stream);
 
@@ -346,6 +355,18 @@ size_t gs_expand_scratch_bytes(int64_t n_old, int64_t n_points);
 int gs_expand(const gs_params* params, const gs_params* m, const gs_params* v, int64_t n_old, const float* points,
               const float* colours, int64_t n_points, const gs_camera* cam, const float* vis,
               const gs_expand_opts* opts, int64_t* n_added, void* scratch, void* stream);
+
+/* Spatial order of the Gaussians (a memory layout for locality, not a step of the method): the permutation that
+ * sorts the Gaussians along a Z-order (Morton) curve of their means (each coordinate quantised to 21 bits over
+ * the means' bounding box: q = min(2^21 - 1, floor((x - lo) * (2^21 - 1) / max(hi - lo, 1e-30))) in FP32,
+ * interleaved x, y, z from bit 0; stable, so equal codes keep their order), applied to params, m and v: out row k
+ * = in row perm[k].  out_* must not overlap the inputs; perm_out (device, nullable, [n] int32) receives the
+ * permutation.  Rendering and gradients are unchanged up to the order of equal-depth ties (by Gaussian index).
+ * scratch: device, gs_spatial_order_scratch_bytes(n) bytes.  GS_ERR_ARG for mismatched sizes or NULL pointers. */
+size_t gs_spatial_order_scratch_bytes(int64_t n);
+int gs_spatial_order(const gs_params* params, const gs_params* m, const gs_params* v, const gs_params* out_params,
+                     const gs_params* out_m, const gs_params* out_v, int32_t* perm_out, void* scratch,
+                     void* stream);
 
 /* ------------------------------------------------------------------ utilities */
 /* Work counts of the frame's forward compositing at its tile shape, ADDED to counts[0..1] (device, uint64):

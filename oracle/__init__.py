@@ -280,6 +280,14 @@ def expand(points, colours, cam, vis, tau_alpha: float, map_means, voxel: float,
     return kept.astype(bool), {k: v[:A] for k, v in out.items()}
 
 
+def spatial_order(means) -> np.ndarray:
+    """The Morton-order permutation of the Gaussians (new row k = old row perm[k])."""
+    mm = _f64(np.asarray(means).reshape(-1, 3))
+    perm = np.zeros(max(mm.shape[0], 1), np.int32)
+    lib().oracle_spatial_order(_p(mm), ctypes.c_int64(mm.shape[0]), _p(perm))
+    return perm[:mm.shape[0]]
+
+
 SSIM_LAMBDA = 0.2  # weight of the SSIM term in eq. Lc (the value of the 3DGS work the paper builds on)
 
 

@@ -123,3 +123,35 @@ int64_t oracle_expand(const double* pts, const double* rgb, int64_t M, const dou
 }
 
 }  // extern "C"
+
+extern "C" {
+
+// Spatial order of Gaussians (a memory layout, not a step of the method): the stable order of their Morton codes,
+// each coordinate quantised to 21 bits over the means' bounding box in FP32 as the library does it:
+// q = min(2^21 - 1, floor((x - lo) * s)), s = (2^21 - 1) / max(hi - lo, 1e-30), interleaved x, y, z from bit 0.
+void oracle_spatial_order(const double* means, int64_t n, int32_t* perm) {
+  float lo[3], hi[3];
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = INFINITY;
+    hi[k] = -INFINITY;
+    for (int64_t g = 0; g < n; ++g) {
+      const float x = (float)means[3 * g + k];
+      lo[k] = std::min(lo[k], x);
+      hi[k] = std::max(hi[k], x);
+    }
+  }
+  std::vector<uint64_t> code(n, 0);
+  for (int64_t g = 0; g < n; ++g)
+    for (int k = 0; k < 3; ++k) {
+      const float s = 2097151.0f / std::max(hi[k] - lo[k], 1e-30f);
+      const float t = ((float)means[3 * g + k] - lo[k]) * s;
+      const uint32_t q = (uint32_t)std::min(std::floor(t), 2097151.0f);
+      for (int b = 0; b < 21; ++b) code[g] |= (uint64_t)((q >> b) & 1u) << (3 * b + k);
+    }
+  std::vector<int64_t> idx(n);
+  for (int64_t g = 0; g < n; ++g) idx[g] = g;
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return code[a] < code[b]; });
+  for (int64_t g = 0; g < n; ++g) perm[g] = (int32_t)idx[g];
+}
+
+}  // extern "C"

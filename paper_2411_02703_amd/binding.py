@@ -49,8 +49,8 @@ class gs_frame(ctypes.Structure):
                 ("tile_w", c_i32), ("tile_h", c_i32), ("seg_len", c_i32), ("seg_cap", c_i32), ("long_cap", c_i32),
                 ("item_cap", c_i32), ("cams", c_vp), ("block", c_vp), ("bytes", ctypes.c_size_t),
                 ("rec", c_vp), ("rect", c_vp), ("ipart", c_vp), ("inst_rec", c_vp), ("vis_mask", c_vp),
-                ("n_inst", c_vp),
-                ("inst_off", c_vp), ("keys", c_vp * 2), ("vals", c_vp * 2), ("tile_range", c_vp),
+                ("n_inst", c_vp), ("n_rec", c_vp), ("rec_first", c_vp), ("zbits", c_vp), ("rec_inst", c_vp), ("rec_cap", c_i64),
+                ("rkeys", c_vp * 2), ("rvals", c_vp * 2), ("keys", c_vp * 2), ("vals", c_vp * 2), ("tile_range", c_vp),
                 ("tile_order", c_vp), ("counters", c_vp), ("seg_count", c_vp), ("seg_first", c_vp), ("items", c_vp),
                 ("seg", c_vp), ("split", c_vp), ("loss", c_vp), ("scratch", c_vp), ("scratch_ints", ctypes.c_size_t)]
 
@@ -83,7 +83,7 @@ GS_ADAM_SPARSE = 1
 EXPORTED = ["gs_default_opts", "gs_plan_cameras", "gs_frame_bytes", "gs_frame_init", "gs_project", "gs_bin_tiles",
             "gs_render_fwd", "gs_render_bwd", "gs_composite_bwd", "gs_project_bwd", "gs_adam_step",
             "gs_render_bwd_adam", "gs_ssim", "gs_prune_scratch_bytes", "gs_prune",
-            "gs_expand_scratch_bytes", "gs_expand",
+            "gs_expand_scratch_bytes", "gs_expand", "gs_spatial_order_scratch_bytes", "gs_spatial_order",
             "gs_count_pairs", "gs_read_counters", "gs_sort_scratch_ints", "gs_sort_pairs", "gs_sort_static_max",
             "gs_sort_pairs_static", "gs_status_string",
             "gs_last_error", "gs_version"]
@@ -118,6 +118,10 @@ def load() -> ctypes.CDLL:
     lib.gs_expand_scratch_bytes.restype = ctypes.c_size_t
     lib.gs_expand.argtypes = [P(gs_params), P(gs_params), P(gs_params), c_i64, c_vp, c_vp, c_i64, P(gs_camera), c_vp,
                               P(gs_expand_opts), c_vp, c_vp, c_vp]
+    lib.gs_spatial_order_scratch_bytes.argtypes = [c_i64]
+    lib.gs_spatial_order_scratch_bytes.restype = ctypes.c_size_t
+    lib.gs_spatial_order.argtypes = [P(gs_params), P(gs_params), P(gs_params), P(gs_params), P(gs_params),
+                                     P(gs_params), c_vp, c_vp, c_vp]
     lib.gs_prune_scratch_bytes.argtypes = [c_i64]
     lib.gs_prune_scratch_bytes.restype = ctypes.c_size_t
     lib.gs_prune.argtypes = [P(gs_params), P(gs_params), P(gs_params), c_f, P(gs_params), P(gs_params), P(gs_params),
@@ -362,6 +366,17 @@ def gs_expand(params: gs_params, m: gs_params, v: gs_params, n_old: int, points:
                             scratch.data_ptr(), _stream(stream)), "gs_expand")
 
 
+def gs_spatial_order(params: gs_params, m: gs_params, v: gs_params, out_params: gs_params, out_m: gs_params,
+                     out_v: gs_params, perm: Optional[torch.Tensor] = None, stream=None) -> None:
+    """Rows of params, m, v in Morton order of the means into the out_* arrays; perm (int32 CUDA, [n]) optional."""
+    scratch = torch.empty(int(load().gs_spatial_order_scratch_bytes(params.n)) // 4 + 64, dtype=torch.int32,
+                          device="cuda")
+    _check(load().gs_spatial_order(ctypes.byref(params), ctypes.byref(m), ctypes.byref(v), ctypes.byref(out_params),
+                                   ctypes.byref(out_m), ctypes.byref(out_v),
+                                   perm.data_ptr() if perm is not None else None, scratch.data_ptr(),
+                                   _stream(stream)), "gs_spatial_order")
+
+
 def gs_read_counters(frame: Frame, stream=None):
     n = c_i64(0)
     fl = c_i32(0)
@@ -405,9 +420,10 @@ def frame_tensor(frame: Frame, field: str, count: int, dtype: torch.dtype) -> to
 
 
 def sorted_pairs(frame: Frame, count: int):
+    """The binned instances: (global tile id of each, as int32; record id of each), in sorted order."""
     i = frame.sorted_index
     koff = frame.f.keys[i] - frame.block.data_ptr()
     voff = frame.f.vals[i] - frame.block.data_ptr()
-    k = frame.block[koff:koff + 8 * count].view(torch.int64)
+    k = frame.block[koff:koff + 4 * count].view(torch.int32)
     v = frame.block[voff:voff + 4 * count].view(torch.int32)
     return k, v

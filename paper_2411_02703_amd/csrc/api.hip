@@ -39,8 +39,9 @@ bool tiles_supported(int tw, int th) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t rec, rect, ipart, instrec, mask, ninst, instoff, k0, k1, v0, v1, range, order, counters, loss,
-      scratch, total;
+  size_t rec, rect, ipart, instrec, mask, ninst, nrec, instoff, zbits, recinst, rk[2], rv[2], k0, k1, v0, v1, range, order,
+      counters, loss, scratch, total;
+  int64_t rec_cap;
   size_t segcount, segfirst, items, seg, split;
   size_t scratch_ints;
   int key_bits, passes;
@@ -108,9 +109,17 @@ Layout make_layout(int64_t n, int V, int n_tiles, int64_t cap, const gs_opts* op
   L.instrec = take((size_t)cap * 4);
   L.mask = take((size_t)n * 8);
   L.ninst = take((size_t)n * 4);
+  L.nrec = take((size_t)n * 4);
   L.instoff = take((size_t)n * 4);
-  L.k0 = take((size_t)cap * 8);
-  L.k1 = take((size_t)cap * 8);
+  L.zbits = take(R * 4);
+  L.recinst = take(R * 4);
+  L.rec_cap = (int64_t)R < cap ? (int64_t)R : cap;
+  for (int k = 0; k < 2; ++k) {
+    L.rk[k] = take((size_t)L.rec_cap * 4);
+    L.rv[k] = take((size_t)L.rec_cap * 4);
+  }
+  L.k0 = take((size_t)cap * 4);
+  L.k1 = take((size_t)cap * 4);
   L.v0 = take((size_t)cap * 4);
   L.v1 = take((size_t)cap * 4);
   L.range = take((size_t)n_tiles * 8);
@@ -122,13 +131,15 @@ Layout make_layout(int64_t n, int V, int n_tiles, int64_t cap, const gs_opts* op
   L.items = take((size_t)L.item_cap * 16);
   L.seg = take((size_t)L.seg_cap * 6 * NT * 4);
   L.split = take((size_t)L.long_cap * 12 * NT * 4);
-  const size_t s1 = gs_launch::scan_scratch_ints(n > n_tiles ? n : n_tiles), s2 = gs_launch::sort_scratch_ints(cap);
+  int64_t big = n > n_tiles ? n : n_tiles;
+  if (L.rec_cap > big) big = L.rec_cap;
+  const size_t s1 = gs_launch::scan_scratch_ints(big), s2 = gs_launch::sort_scratch_ints(cap);
   L.scratch_ints = s1 > s2 ? s1 : s2;
   L.scratch = take(L.scratch_ints * 4);
   L.total = o;
   int tb = 1;
   while ((int64_t(1) << tb) < n_tiles) ++tb;
-  L.key_bits = 32 + tb;
+  L.key_bits = tb;
   L.passes = (L.key_bits + 7) / 8;
   return L;
 }
@@ -284,9 +295,17 @@ int gs_frame_init(gs_frame* f, void* block, size_t bytes, int64_t n, const gs_ca
   f->inst_rec = reinterpret_cast<int32_t*>(b + L.instrec);
   f->vis_mask = reinterpret_cast<uint64_t*>(b + L.mask);
   f->n_inst = reinterpret_cast<int32_t*>(b + L.ninst);
-  f->inst_off = reinterpret_cast<int32_t*>(b + L.instoff);
-  f->keys[0] = reinterpret_cast<uint64_t*>(b + L.k0);
-  f->keys[1] = reinterpret_cast<uint64_t*>(b + L.k1);
+  f->n_rec = reinterpret_cast<int32_t*>(b + L.nrec);
+  f->rec_first = reinterpret_cast<int32_t*>(b + L.instoff);
+  f->zbits = reinterpret_cast<uint32_t*>(b + L.zbits);
+  f->rec_inst = reinterpret_cast<int32_t*>(b + L.recinst);
+  f->rec_cap = L.rec_cap;
+  for (int k = 0; k < 2; ++k) {
+    f->rkeys[k] = reinterpret_cast<uint32_t*>(b + L.rk[k]);
+    f->rvals[k] = reinterpret_cast<int32_t*>(b + L.rv[k]);
+  }
+  f->keys[0] = reinterpret_cast<uint32_t*>(b + L.k0);
+  f->keys[1] = reinterpret_cast<uint32_t*>(b + L.k1);
   f->vals[0] = reinterpret_cast<int32_t*>(b + L.v0);
   f->vals[1] = reinterpret_cast<int32_t*>(b + L.v1);
   f->tile_range = reinterpret_cast<int32_t*>(b + L.range);
@@ -318,8 +337,7 @@ int gs_bin_tiles(const gs_frame* f, const gs_opts* o, int32_t sync_count, int64_
   int rc;
   if ((rc = frame_check(f)) || (rc = opts_check(o))) return rc;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  GS_HIP(gs_launch::scan_exclusive(f->n_inst, f->inst_off, f->n, f->scratch, st), "gs_bin_tiles: scan");
-  GS_HIP(gs_launch::instance_total(*f, st), "gs_bin_tiles: total");
+  GS_HIP(gs_launch::bin_records(*f, st), "gs_bin_tiles: records by depth");
   int64_t n_sized = f->capacity;
   const int32_t* count_dev = f->counters;
   if (sync_count) {
@@ -331,9 +349,9 @@ int gs_bin_tiles(const gs_frame* f, const gs_opts* o, int32_t sync_count, int64_
     count_dev = nullptr;
   }
   GS_HIP(gs_launch::emit(*f, n_sized, st), "gs_bin_tiles: emit");
-  GS_HIP(gs_launch::sort_pairs(f->keys[0], f->vals[0], f->keys[1], f->vals[1], n_sized, count_dev, f->capacity,
-                               f->key_bits, f->scratch, st),
-         "gs_bin_tiles: sort");
+  GS_HIP(gs_launch::sort_pairs32(f->keys[0], f->vals[0], f->keys[1], f->vals[1], n_sized, count_dev, f->capacity,
+                                 f->key_bits, f->scratch, st),
+         "gs_bin_tiles: sort by tile");
   GS_HIP(gs_launch::inst_finish(*f, n_sized, count_dev, st), "gs_bin_tiles: sorted ids");
   GS_HIP(gs_launch::ranges(*f, f->keys[f->sort_passes & 1], n_sized, count_dev, st), "gs_bin_tiles: ranges");
   GS_HIP(gs_launch::tile_schedule(*f, st), "gs_bin_tiles: schedule");
@@ -446,6 +464,25 @@ int gs_expand(const gs_params* p, const gs_params* m, const gs_params* v, int64_
                            o->knn_cell, logit, n_added, static_cast<int32_t*>(scratch),
                            static_cast<hipStream_t>(stream)),
          "gs_expand");
+  return GS_OK;
+}
+
+size_t gs_spatial_order_scratch_bytes(int64_t n) { return n < 1 ? 0 : 4 * gs_launch::order_scratch_ints(n); }
+
+int gs_spatial_order(const gs_params* p, const gs_params* m, const gs_params* v, const gs_params* op,
+                     const gs_params* om, const gs_params* ov, int32_t* perm_out, void* scratch, void* stream) {
+  int rc;
+  if ((rc = params_check(p, "params")) || (rc = params_check(m, "m")) || (rc = params_check(v, "v")) ||
+      (rc = params_check(op, "out_params")) || (rc = params_check(om, "out_m")) || (rc = params_check(ov, "out_v")))
+    return rc;
+  const gs_params* all[5] = {m, v, op, om, ov};
+  for (const gs_params* q : all)
+    if (q->n != p->n || q->sh_degree != p->sh_degree) return fail(GS_ERR_ARG, "spatial order: sizes differ");
+  if (p->n > INT32_MAX) return fail(GS_ERR_ARG, "spatial order: n above 2^31 - 1");
+  if (!scratch) return fail(GS_ERR_ARG, "spatial order: scratch is NULL");
+  GS_HIP(gs_launch::spatial_order(*p, *m, *v, *op, *om, *ov, perm_out, static_cast<int32_t*>(scratch),
+                                  static_cast<hipStream_t>(stream)),
+         "gs_spatial_order");
   return GS_OK;
 }
 

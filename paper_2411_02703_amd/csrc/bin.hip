@@ -1,6 +1,14 @@
-// Tile binning: exclusive scan of per-Gaussian instance counts, emission of (tile, depth) keys,
-// stable LSD radix sort (8-bit digits), per-tile ranges.  Integer work, bit-exact by construction:
-// within a tile the order is ascending depth bits, ties by record index (emission order).
+// Tile binning (integer work, bit-exact by construction).  The order inside a tile is ascending depth bits, ties
+// by record index, so the sorted order is unique.  Two stable LSD radix sorts (8-bit digits) reach it:
+//   1. the visible records, listed Gaussian by Gaussian, are sorted by their 32-bit depth bits (4 passes over
+//      the records, not the instances);
+//   2. the records are emitted in that order, each as its run of tile instances (key = global tile id, value =
+//      emission index), and the instances are sorted by tile (2 passes at up to 65,536 tiles).
+// A stable sort by tile of a depth-ordered sequence is the (tile, depth, record) order; ties in depth keep
+// ascending Gaussian index inside a view (the records of one view are listed in Gaussian order), and records
+// of different views never share a tile.  Each record's instances stay one contiguous run of emission indices
+// (its first index is kept per record), which is where the compositing backward stores their partials and the
+// projection backward sums them.
 #include "common.h"
 
 namespace {
@@ -74,95 +82,14 @@ __global__ void k_fill_f32(float* __restrict__ p, float v, int64_t n) {
   if (i < n) p[i] = v;
 }
 
-// counters[0] = total instances; overflow flag if above capacity.
-__global__ void k_instance_total(const int32_t* __restrict__ n_inst, const int32_t* __restrict__ off, int64_t n,
-                                 int64_t capacity, int32_t* __restrict__ counters) {
-  const int64_t total = (int64_t)off[n - 1] + (int64_t)n_inst[n - 1];
-  counters[0] = (int32_t)total;
-  if (total > capacity) atomicOr(counters + 1, GS_FLAG_INSTANCE_OVERFLOW);
-}
-
-// Records with more tiles than this are emitted (and their partials summed) by a whole wave, a tile per lane.
-constexpr int kSolo = 32;
-
-__device__ __forceinline__ int64_t read_lane64(int64_t x, int l) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), l);
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-// One thread per Gaussian, a wave per 64 consecutive Gaussians.  Emission order: the wave's instances start at
-// the offset of its first Gaussian and are laid out view-major (view by view; inside a view Gaussian by
-// Gaussian, each record's tiles row by row), so that the wave writes each view's instances as one contiguous
-// run; within a tile, equal depths still keep ascending Gaussian order.  The sort value is the emission
-// index; inst_rec keeps the record of each emission index.  A record with at most kSolo tiles is written by
-// its own lane, larger ones by the whole wave one after another (a tile per lane, coalesced), so that the few
-// Gaussians covering thousands of tiles do not hold their waves for thousands of steps.
-__global__ __launch_bounds__(256) void k_emit(const uint64_t* __restrict__ vis_mask, const int32_t* __restrict__ off,
-                                             const short4* __restrict__ rect, const float4* __restrict__ rec,
-                                             const gs_camera* __restrict__ cams, int V, int64_t n, int64_t capacity,
-                                             uint64_t* __restrict__ keys, int32_t* __restrict__ vals,
-                                             int32_t* __restrict__ inst_rec) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  const uint64_t mask = g < n ? vis_mask[g] : 0ull;
-  const int64_t g0 = g - lane;  // the wave's first Gaussian
-  int64_t base = g0 < n ? off[g0] : 0;
-  for (int v = 0; v < V; ++v) {
-    const bool vis = (mask >> v) & 1ull;
-    if (__ballot(vis) == 0) continue;
-    const int toff = cams[v].tile_offset, tx_n = cams[v].tiles_x;
-    const int64_t r = (int64_t)v * n + g;
-    short4 rc = make_short4(0, -1, 0, -1);
-    uint32_t zb = 0;
-    if (vis) {
-      rc = rect[r];
-      zb = __float_as_uint(rec[3 * r].z);
-    }
-    const int w = rc.y - rc.x + 1, cnt = vis ? w * (rc.w - rc.z + 1) : 0;
-    int tot;
-    const int64_t o = base + gsk::wave_excl_scan(cnt, tot);
-    if (vis && cnt <= kSolo) {
-      int64_t q = o;
-      for (int ty = rc.z; ty <= rc.w; ++ty)
-        for (int tx = rc.x; tx <= rc.y; ++tx) {
-          if (q < capacity) {
-            keys[q] = ((uint64_t)(uint32_t)(toff + ty * tx_n + tx) << 32) | (uint64_t)zb;
-            vals[q] = (int32_t)q;
-            inst_rec[q] = (int32_t)r;
-          }
-          ++q;
-        }
-    }
-    uint64_t big = __ballot(cnt > kSolo);
-    while (big) {
-      const int L = __builtin_ctzll(big);
-      big &= big - 1;
-      const int64_t oL = read_lane64(o, L), rL = read_lane64(r, L);
-      const int cL = __builtin_amdgcn_readlane(cnt, L), wL = __builtin_amdgcn_readlane(w, L);
-      const int x0 = __builtin_amdgcn_readlane((int)rc.x, L), y0 = __builtin_amdgcn_readlane((int)rc.z, L);
-      const uint32_t zL = (uint32_t)__builtin_amdgcn_readlane((int)zb, L);
-      for (int k = lane; k < cL; k += 64) {
-        const int64_t q = oL + k;
-        if (q < capacity) {
-          const int ty = y0 + k / wL, tx = x0 + k % wL;
-          keys[q] = ((uint64_t)(uint32_t)(toff + ty * tx_n + tx) << 32) | (uint64_t)zL;
-          vals[q] = (int32_t)q;
-          inst_rec[q] = (int32_t)rL;
-        }
-      }
-    }
-    base += tot;
-  }
-}
-
 __device__ __forceinline__ int64_t sort_count(const int32_t* count_dev, int64_t n_sized, int64_t cap) {
   if (count_dev == nullptr) return n_sized;
   const int64_t c = count_dev[0];
   return c < cap ? c : cap;
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t* __restrict__ keys,
+template <class KeyT>
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const KeyT* __restrict__ keys,
                                                            const int32_t* __restrict__ count_dev, int64_t n_sized,
                                                            int64_t cap, int shift, int32_t* __restrict__ hist,
                                                            int nblocks) {
@@ -182,13 +109,14 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t* __re
 // Stable scatter of one 8-bit digit.  Each wave ranks its 512 keys (8 rounds of 64) with ballot-based
 // digit matching, the block orders them in LDS (digit-major, stable), then writes runs to their global
 // offsets from the scanned digit-major histogram.
-__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* __restrict__ kin,
+template <class KeyT>
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const KeyT* __restrict__ kin,
                                                               const int32_t* __restrict__ vin,
-                                                              uint64_t* __restrict__ kout, int32_t* __restrict__ vout,
+                                                              KeyT* __restrict__ kout, int32_t* __restrict__ vout,
                                                               const int32_t* __restrict__ count_dev, int64_t n_sized,
                                                               int64_t cap, int shift,
                                                               const int32_t* __restrict__ hist_scan, int nblocks) {
-  __shared__ uint64_t sk[kSortTile];
+  __shared__ KeyT sk[kSortTile];
   __shared__ int32_t sv[kSortTile];
   __shared__ int32_t wcnt[4][256];
   __shared__ int32_t dstart[256];
@@ -200,7 +128,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
   const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id();
   for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
   __syncthreads();
-  uint64_t key[kSortItems];
+  KeyT key[kSortItems];
   int32_t val[kSortItems];
   int pos[kSortItems];
   const uint64_t lt = gsk::lanemask_lt();
@@ -208,7 +136,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
   for (int k = 0; k < kSortItems; ++k) {
     const int64_t idx = base + (int64_t)wave * kWaveItems + k * 64 + lane;
     const bool valid = idx < n;
-    key[k] = valid ? kin[idx] : 0ull;
+    key[k] = valid ? kin[idx] : KeyT(0);
     val[k] = valid ? vin[idx] : 0;
     const int d = (int)((key[k] >> shift) & 255u);
     uint64_t peers = __ballot(valid);
@@ -253,11 +181,142 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t* _
   const int64_t rem = n - base;
   const int nvalid = rem < kSortTile ? (int)rem : kSortTile;
   for (int p = tid; p < nvalid; p += kSortThreads) {
-    const uint64_t kk = sk[p];
+    const KeyT kk = sk[p];
     const int d = (int)((kk >> shift) & 255u);
     const int64_t o = (int64_t)gofs[d] + (p - dstart[d]);
     kout[o] = kk;
     vout[o] = sv[p];
+  }
+}
+
+// ------------------------------------------------------------------ the record list and the emission
+// Visible records listed Gaussian by Gaussian (views ascending): key = depth bits, value = record id.  The count
+// R goes to counters[kRecCount] (entries past the record capacity are not written; R > capacity implies more
+// instances than the instance capacity, which the instance total flags).
+constexpr int kRecCount = 196;
+
+__global__ void k_record_total(const int32_t* __restrict__ n_rec, const int32_t* __restrict__ first, int64_t n,
+                               int32_t* __restrict__ counters) {
+  counters[kRecCount] = first[n - 1] + n_rec[n - 1];
+}
+
+__global__ __launch_bounds__(256) void k_record_list(const uint64_t* __restrict__ vis_mask,
+                                                    const int32_t* __restrict__ first,
+                                                    const uint32_t* __restrict__ zbits, int V, int64_t n, int64_t rcap,
+                                                    uint32_t* __restrict__ rkeys, int32_t* __restrict__ rvals) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  uint64_t m = vis_mask[g];
+  int64_t c = first[g];
+  while (m) {
+    const int v = __builtin_ctzll(m);
+    m &= m - 1;
+    const int64_t r = (int64_t)v * n + g;
+    if (c < rcap) {
+      rkeys[c] = zbits[r];
+      rvals[c] = (int32_t)r;
+    }
+    ++c;
+  }
+}
+
+__device__ __forceinline__ int rect_area(const short4 rc) { return (rc.y - rc.x + 1) * (rc.w - rc.z + 1); }
+
+// Instance count of each depth-sorted record (its tile rectangle's area).
+__global__ void k_record_counts(const int32_t* __restrict__ rvals, const short4* __restrict__ rect,
+                                const int32_t* __restrict__ counters, int64_t rcap, int32_t* __restrict__ cnt) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= sort_count(counters + kRecCount, rcap, rcap)) return;
+  cnt[j] = rect_area(rect[rvals[j]]);
+}
+
+// The instance total summed from the per-Gaussian counts (one atomic per workgroup into counters[kInstSum]), so
+// that it is the full count even when the record list itself overflowed.
+constexpr int kInstSum = 197;
+
+__global__ __launch_bounds__(256) void k_sum_counts(const int32_t* __restrict__ n_inst, int64_t n,
+                                                   int32_t* __restrict__ counters) {
+  __shared__ int part[4];
+  int s = 0;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
+    s += n_inst[g];
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(counters + kInstSum, part[0] + part[1] + part[2] + part[3]);
+}
+
+// counters[0] = instances (the full count); overflow flag if above the capacity.
+__global__ void k_instance_total(int64_t capacity, int32_t* __restrict__ counters) {
+  const int64_t total = counters[kInstSum];
+  counters[0] = (int32_t)total;
+  if (total > capacity) atomicOr(counters + 1, GS_FLAG_INSTANCE_OVERFLOW);
+}
+
+// Records with more tiles than this are emitted (and their partials summed) by a whole wave, a tile per lane.
+constexpr int kSolo = 32;
+
+__device__ __forceinline__ int64_t read_lane64(int64_t x, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// One thread per depth-sorted record: its run of instances (tiles row by row) starts at eo[j]; key = global tile
+// id, value = emission index; inst_rec keeps the record of each emission index and rec_inst the first emission
+// index of each record.  Records with more than kSolo tiles are written by the whole wave, a tile per lane.
+__global__ __launch_bounds__(256) void k_emit(const int32_t* __restrict__ rvals, const int32_t* __restrict__ eo,
+                                             const short4* __restrict__ rect, const gs_camera* __restrict__ cams,
+                                             int V, int64_t n, const int32_t* __restrict__ counters, int64_t rcap,
+                                             int64_t capacity, uint32_t* __restrict__ keys,
+                                             int32_t* __restrict__ vals, int32_t* __restrict__ inst_rec,
+                                             int32_t* __restrict__ rec_inst) {
+  const int64_t R = sort_count(counters + kRecCount, rcap, rcap);
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool here = j < R;
+  int64_t r = 0, o = 0;
+  short4 rc = make_short4(0, -1, 0, -1);
+  int toff = 0, tx_n = 1;
+  if (here) {
+    r = rvals[j];
+    o = eo[j];
+    rc = rect[r];
+    const int v = (int)(r / n);
+    toff = cams[v].tile_offset;
+    tx_n = cams[v].tiles_x;
+    rec_inst[r] = (int32_t)o;
+  }
+  const int w = rc.y - rc.x + 1, cnt = here ? w * (rc.w - rc.z + 1) : 0;
+  if (here && cnt <= kSolo) {
+    int64_t q = o;
+    for (int ty = rc.z; ty <= rc.w; ++ty)
+      for (int tx = rc.x; tx <= rc.y; ++tx) {
+        if (q < capacity) {
+          keys[q] = (uint32_t)(toff + ty * tx_n + tx);
+          vals[q] = (int32_t)q;
+          inst_rec[q] = (int32_t)r;
+        }
+        ++q;
+      }
+  }
+  uint64_t big = __ballot(cnt > kSolo);
+  while (big) {
+    const int L = __builtin_ctzll(big);
+    big &= big - 1;
+    const int64_t oL = read_lane64(o, L), rL = read_lane64(r, L);
+    const int cL = __builtin_amdgcn_readlane(cnt, L), wL = __builtin_amdgcn_readlane(w, L);
+    const int x0 = __builtin_amdgcn_readlane((int)rc.x, L), y0 = __builtin_amdgcn_readlane((int)rc.z, L);
+    const int toL = __builtin_amdgcn_readlane(toff, L), txL = __builtin_amdgcn_readlane(tx_n, L);
+    for (int k = lane; k < cL; k += 64) {
+      const int64_t q = oL + k;
+      if (q < capacity) {
+        const int ty = y0 + k / wL, tx = x0 + k % wL;
+        keys[q] = (uint32_t)(toL + ty * txL + tx);
+        vals[q] = (int32_t)q;
+        inst_rec[q] = (int32_t)rL;
+      }
+    }
   }
 }
 
@@ -275,14 +334,14 @@ __global__ __launch_bounds__(256) void k_inst_finish(int32_t* __restrict__ vals,
   emi[p] = i;
 }
 
-__global__ void k_ranges(const uint64_t* __restrict__ keys, const int32_t* __restrict__ count_dev, int64_t n_sized,
+__global__ void k_ranges(const uint32_t* __restrict__ keys, const int32_t* __restrict__ count_dev, int64_t n_sized,
                          int64_t cap, int2* __restrict__ range) {
   const int64_t n = sort_count(count_dev, n_sized, cap);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const uint32_t t = (uint32_t)(keys[i] >> 32);
-  if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) range[t].x = (int)i;
-  if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != t) range[t].y = (int)(i + 1);
+  const uint32_t t = keys[i];
+  if (i == 0 || keys[i - 1] != t) range[t].x = (int)i;
+  if (i == n - 1 || keys[i + 1] != t) range[t].y = (int)(i + 1);
 }
 
 // Compositing schedule: tiles in descending order of their list length, bucketed by floor(log2(len + 1))
@@ -403,46 +462,82 @@ hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t instance_total(const gs_frame& f, hipStream_t st) {
-  k_instance_total<<<1, 1, 0, st>>>(f.n_inst, f.inst_off, f.n, f.capacity, f.counters);
-  return hipGetLastError();
-}
-
-hipError_t emit(const gs_frame& f, int64_t /*n_sized*/, hipStream_t st) {
-  k_emit<<<(unsigned)cdiv(f.n, 256), 256, 0, st>>>(f.vis_mask, f.inst_off, reinterpret_cast<const short4*>(f.rect),
-                                                   reinterpret_cast<const float4*>(f.rec), f.cams, f.n_views, f.n,
-                                                   f.capacity, f.keys[0], f.vals[0], f.inst_rec);
-  return hipGetLastError();
-}
-
 size_t sort_scratch_ints(int64_t n) {
   const int64_t nb = cdiv(n > 0 ? n : 1, kSortTile);
   return (size_t)align64(256 * nb) + scan_scratch_ints(256 * nb);
 }
 
-hipError_t sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int64_t n_sized, const int32_t* count_dev,
-                      int64_t cap, int key_bits, int32_t* scratch, hipStream_t st) {
+template <class KeyT>
+static hipError_t sort_impl(KeyT* k0, int32_t* v0, KeyT* k1, int32_t* v1, int64_t n_sized, const int32_t* count_dev,
+                            int64_t cap, int key_bits, int32_t* scratch, hipStream_t st) {
   if (n_sized <= 0) return hipSuccess;
   const int64_t nb = cdiv(n_sized, kSortTile);
   int32_t* hist = scratch;
   int32_t* scan_scr = scratch + align64(256 * nb);
   const int passes = (key_bits + 7) / 8;
-  uint64_t* kb[2] = {k0, k1};
+  KeyT* kb[2] = {k0, k1};
   int32_t* vb[2] = {v0, v1};
   for (int p = 0; p < passes; ++p) {
     const int shift = 8 * p;
     const int src = p & 1, dst = src ^ 1;
-    k_sort_hist<<<(unsigned)nb, kSortThreads, 0, st>>>(kb[src], count_dev, n_sized, cap, shift, hist, (int)nb);
+    k_sort_hist<KeyT><<<(unsigned)nb, kSortThreads, 0, st>>>(kb[src], count_dev, n_sized, cap, shift, hist, (int)nb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = scan_exclusive(hist, hist, 256 * nb, scan_scr, st);
     if (e != hipSuccess) return e;
-    k_sort_scatter<<<(unsigned)nb, kSortThreads, 0, st>>>(kb[src], vb[src], kb[dst], vb[dst], count_dev, n_sized,
-                                                          cap, shift, hist, (int)nb);
+    k_sort_scatter<KeyT><<<(unsigned)nb, kSortThreads, 0, st>>>(kb[src], vb[src], kb[dst], vb[dst], count_dev,
+                                                                n_sized, cap, shift, hist, (int)nb);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int64_t n_sized, const int32_t* count_dev,
+                      int64_t cap, int key_bits, int32_t* scratch, hipStream_t st) {
+  return sort_impl<uint64_t>(k0, v0, k1, v1, n_sized, count_dev, cap, key_bits, scratch, st);
+}
+
+hipError_t sort_pairs32(uint32_t* k0, int32_t* v0, uint32_t* k1, int32_t* v1, int64_t n_sized,
+                        const int32_t* count_dev, int64_t cap, int key_bits, int32_t* scratch, hipStream_t st) {
+  return sort_impl<uint32_t>(k0, v0, k1, v1, n_sized, count_dev, cap, key_bits, scratch, st);
+}
+
+// Binning up to the instance total: the record list sorted by depth (in rkeys[0] / rvals[0]), each sorted
+// record's instance count (in rkeys[1], as int32) and its first emission index (in rvals[1]), the instance total
+// and the overflow flag.
+hipError_t bin_records(const gs_frame& f, hipStream_t st) {
+  const int64_t rcap = f.rec_cap;
+  hipError_t e = fill_i32(f.counters + kInstSum, 0, 1, st);
+  if (e != hipSuccess) return e;
+  int64_t nb = cdiv(f.n, 256);
+  if (nb > 1024) nb = 1024;
+  k_sum_counts<<<(unsigned)nb, 256, 0, st>>>(f.n_inst, f.n, f.counters);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = scan_exclusive(f.n_rec, f.rec_first, f.n, f.scratch, st)) != hipSuccess) return e;
+  k_record_total<<<1, 1, 0, st>>>(f.n_rec, f.rec_first, f.n, f.counters);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_record_list<<<(unsigned)cdiv(f.n, 256), 256, 0, st>>>(f.vis_mask, f.rec_first, f.zbits, f.n_views, f.n, rcap,
+                                                          f.rkeys[0], f.rvals[0]);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = sort_pairs32(f.rkeys[0], f.rvals[0], f.rkeys[1], f.rvals[1], rcap, f.counters + kRecCount, rcap, 32,
+                        f.scratch, st)) != hipSuccess)
+    return e;  // 4 passes: the sorted records are back in rkeys[0] / rvals[0]
+  int32_t* cnt = reinterpret_cast<int32_t*>(f.rkeys[1]);
+  k_record_counts<<<(unsigned)cdiv(rcap, 256), 256, 0, st>>>(f.rvals[0], reinterpret_cast<const short4*>(f.rect),
+                                                             f.counters, rcap, cnt);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = scan_exclusive(cnt, f.rvals[1], rcap, f.scratch, st)) != hipSuccess) return e;
+  k_instance_total<<<1, 1, 0, st>>>(f.capacity, f.counters);
+  return hipGetLastError();
+}
+
+hipError_t emit(const gs_frame& f, int64_t /*n_sized*/, hipStream_t st) {
+  k_emit<<<(unsigned)cdiv(f.rec_cap, 256), 256, 0, st>>>(f.rvals[0], f.rvals[1],
+                                                         reinterpret_cast<const short4*>(f.rect), f.cams, f.n_views,
+                                                         f.n, f.counters, f.rec_cap, f.capacity, f.keys[0], f.vals[0],
+                                                         f.inst_rec, f.rec_inst);
+  return hipGetLastError();
 }
 
 hipError_t tile_schedule(const gs_frame& f, hipStream_t st) {
@@ -481,7 +576,7 @@ hipError_t inst_finish(const gs_frame& f, int64_t n_sized, const int32_t* count_
   return hipGetLastError();
 }
 
-hipError_t ranges(const gs_frame& f, const uint64_t* keys, int64_t n_sized, const int32_t* count_dev,
+hipError_t ranges(const gs_frame& f, const uint32_t* keys, int64_t n_sized, const int32_t* count_dev,
                   hipStream_t st) {
   hipError_t e = fill_i32(f.tile_range, 0, 2 * (int64_t)f.n_tiles, st);
   if (e != hipSuccess || n_sized <= 0) return e;

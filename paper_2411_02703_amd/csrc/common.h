@@ -133,13 +133,17 @@ size_t scan_scratch_ints(int64_t n);
 hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t s);
 hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t s);
-hipError_t instance_total(const gs_frame& f, hipStream_t s);
+// Binning up to the instance total: visible records sorted by depth, their instance counts and first emission
+// indices, counters[0] = instances (overflow flagged).
+hipError_t bin_records(const gs_frame& f, hipStream_t s);
 hipError_t emit(const gs_frame& f, int64_t n_sized, hipStream_t s);
 size_t sort_scratch_ints(int64_t n);
+hipError_t sort_pairs32(uint32_t* k0, int32_t* v0, uint32_t* k1, int32_t* v1, int64_t n_sized,
+                        const int32_t* count_dev, int64_t cap, int key_bits, int32_t* scratch, hipStream_t s);
 hipError_t sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int64_t n_sized,
                       const int32_t* count_dev, int64_t cap, int key_bits, int32_t* scratch, hipStream_t s);
 hipError_t inst_finish(const gs_frame& f, int64_t n_sized, const int32_t* count_dev, hipStream_t s);
-hipError_t ranges(const gs_frame& f, const uint64_t* keys, int64_t n_sized, const int32_t* count_dev, hipStream_t s);
+hipError_t ranges(const gs_frame& f, const uint32_t* keys, int64_t n_sized, const int32_t* count_dev, hipStream_t s);
 hipError_t tile_schedule(const gs_frame& f, hipStream_t s);
 hipError_t work_items(const gs_frame& f, hipStream_t s);
 hipError_t render_fwd(const gs_frame& f, const gs_opts& o, const gs_images& out, hipStream_t s);
@@ -164,6 +168,11 @@ hipError_t expand(const gs_params& p, const gs_params& m, const gs_params& v, in
                   const float* rgb, int64_t M, const gs_camera& cam, const float* vis, float tau, float near_z,
                   float voxel, int cap, float cell, float init_logit, int64_t* n_added, int32_t* scratch,
                   hipStream_t s);
+// Spatial (Morton) order: out row k = in row perm[k] for params, m, v (scratch: order_scratch_ints(n)).
+size_t order_scratch_ints(int64_t n);
+hipError_t spatial_order(const gs_params& p, const gs_params& m, const gs_params& v, const gs_params& op,
+                         const gs_params& om, const gs_params& ov, int32_t* perm_out, int32_t* scratch,
+                         hipStream_t s);
 // The step counter and bias corrections of one Adam step (skipped when *skip_flags has the overflow bit).
 hipError_t adam_prep(const gs_adam& a, const int32_t* skip_flags, hipStream_t s);
 // Projection backward fused with Adam: params, m, v updated in place; the gradient is written to grads_out

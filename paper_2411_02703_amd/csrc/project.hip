@@ -186,6 +186,7 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ means
                                                  const gs_camera* __restrict__ cams, int V, DevOpts op,
                                                  float4* __restrict__ rec, short4* __restrict__ rect,
                                                  uint64_t* __restrict__ vis_mask,
+                                                 uint32_t* __restrict__ zbits, int32_t* __restrict__ n_rec,
                                                  int32_t* __restrict__ n_inst, int32_t* __restrict__ flags) {
   constexpr int K = (DEG + 1) * (DEG + 1);
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,7 +210,7 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ means
     finite &= isfinite(f[i]);
   }
   uint64_t mask = 0;
-  int cnt = 0;
+  int cnt = 0, inst = 0;
   if (!finite) {
     atomicOr(flags, GS_FLAG_NONFINITE);
   } else {
@@ -255,13 +256,16 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ means
                                      __int_as_float((px0 & 0xffff) | (px1 << 16)),
                                      __int_as_float((py0 & 0xffff) | (py1 << 16)));
         rect[r] = make_short4((short)tx0, (short)tx1, (short)ty0, (short)ty1);
+        zbits[r] = __float_as_uint(tz);
         mask |= 1ull << v;
-        cnt += (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+        ++cnt;
+        inst += (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
       }
     }
   }
   vis_mask[g] = mask;
-  n_inst[g] = cnt;
+  n_rec[g] = cnt;
+  n_inst[g] = inst;
 }
 
 // Records with more tiles than this have their instance partials summed by the whole wave.
@@ -295,7 +299,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
                                                      float* __restrict__ sh, int64_t n,
                                                      const gs_camera* __restrict__ cams, int V, DevOpts op,
                                                      const float4* __restrict__ ipart,
-                                                     const int32_t* __restrict__ inst_off, const short4* __restrict__ rect,
+                                                     const int32_t* __restrict__ rec_inst, const short4* __restrict__ rect,
                                                      const int32_t* __restrict__ count_dev, int64_t capacity,
                                                      const uint64_t* __restrict__ vis_mask, float* __restrict__ g_means,
                                                      float* __restrict__ g_scales, float* __restrict__ g_quats,
@@ -326,24 +330,24 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
 #pragma unroll
   for (int i = 0; i < K * 3; ++i) gf[i] = 0.f;
 
-  // this Gaussian's instances, in emission order: the wave's instances start at the offset of its first
-  // Gaussian and run view by view, Gaussian by Gaussian inside a view, each record's tiles together.  The
-  // lanes take the views together; a record with more than kSolo tiles is summed by the whole wave.
+  // this Gaussian's instances: each visible record's instances are one contiguous run of emission indices
+  // starting at rec_inst of the record.  The lanes take the views together; a record with more than kSolo tiles
+  // is summed by the whole wave.  A run outside the stored instances (an overflowed frame, whose gradient is
+  // undefined) is not read.
   const int64_t n_stored = min((int64_t)count_dev[0], capacity);
-  const int64_t g0 = g - lane;
-  int64_t base = g0 < n ? inst_off[g0] : 0;
   for (int v = 0; v < V; ++v) {
     const bool vis = (mask >> v) & 1ull;
     if (__ballot(vis) == 0) continue;
     const gs_camera& c = cams[v];
     const int64_t r = (int64_t)v * n + g;
     int cnt = 0;
+    int64_t i = 0;
     if (vis) {
       const short4 rc = rect[r];
       cnt = (rc.y - rc.x + 1) * (rc.w - rc.z + 1);
+      i = rec_inst[r];
+      if (i < 0 || i >= n_stored) cnt = 0;
     }
-    int tot;
-    const int64_t i = base + gsk::wave_excl_scan(cnt, tot);
     // the record's gradient: the sum of its instances' partials over the tiles it covers (a contiguous run,
     // read four instances at a time so that their loads are in flight together)
     float4 q0 = make_float4(0.f, 0.f, 0.f, 0.f), q1 = q0, q2 = q0;
@@ -392,7 +396,6 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
         q2 = make_float4(sm[8], sm[9], 0.f, 0.f);
       }
     }
-    base += tot;
     if (!vis) continue;
     const float dmx = q0.x, dmy = q0.y, da = q0.z, db = q0.w;
     const float dc = q1.x, d_o = q1.y, dr = q1.z, dg = q1.w;
@@ -592,19 +595,19 @@ hipError_t project(const gs_params& p, const gs_frame& f, const gs_opts& o, hipS
   switch (p.sh_degree) {
     case 0:
       k_project<0><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams,
-                                               f.n_views, op, rec, rect, f.vis_mask, f.n_inst, flags);
+                                               f.n_views, op, rec, rect, f.vis_mask, f.zbits, f.n_rec, f.n_inst, flags);
       break;
     case 1:
       k_project<1><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams,
-                                               f.n_views, op, rec, rect, f.vis_mask, f.n_inst, flags);
+                                               f.n_views, op, rec, rect, f.vis_mask, f.zbits, f.n_rec, f.n_inst, flags);
       break;
     case 2:
       k_project<2><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams,
-                                               f.n_views, op, rec, rect, f.vis_mask, f.n_inst, flags);
+                                               f.n_views, op, rec, rect, f.vis_mask, f.zbits, f.n_rec, f.n_inst, flags);
       break;
     default:
       k_project<3><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n, f.cams,
-                                               f.n_views, op, rec, rect, f.vis_mask, f.n_inst, flags);
+                                               f.n_views, op, rec, rect, f.vis_mask, f.zbits, f.n_rec, f.n_inst, flags);
       break;
   }
   return hipGetLastError();
@@ -625,7 +628,7 @@ static hipError_t project_bwd_launch(const gs_params& p, const gs_frame& f, cons
   float* gsh = gr ? gr->sh : nullptr;
 #define GS_PB(D)                                                                                              \
   k_project_bwd<D, ADAM><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n,     \
-                                                     f.cams, f.n_views, op, ip, f.inst_off, rect, f.counters,    \
+                                                     f.cams, f.n_views, op, ip, f.rec_inst, rect, f.counters,    \
                                                      f.capacity, f.vis_mask, gm, gl, gq, go, gsh, ad)
   switch (p.sh_degree) {
     case 0: GS_PB(0); break;

@@ -115,6 +115,22 @@ class GaussianModel:
         self.vs = B.params_struct(self.v, self.sh_degree)
         return k
 
+    def reorder_spatially(self) -> np.ndarray:
+        """Store the Gaussians (parameters and moments) in Morton order of their means (gs_spatial_order), a layout
+        for locality: a wave of threads then holds neighbouring Gaussians.  Returns the permutation (new row k was
+        old row perm[k]).  Frames and steps built before must be rebuilt."""
+        out = [{k: torch.empty_like(t) for k, t in d.items()} for d in (self.p, self.m, self.v)]
+        structs = [B.params_struct(d, self.sh_degree) for d in out]
+        perm = torch.empty(self.n, dtype=torch.int32, device=self.p["means"].device)
+        B.gs_spatial_order(self.ps, self.ms, self.vs, structs[0], structs[1], structs[2], perm)
+        self.p, self.m, self.v = out
+        self.g = {key: torch.zeros_like(t) for key, t in self.p.items()}
+        self.ps = B.params_struct(self.p, self.sh_degree)
+        self.gs = B.params_struct(self.g, self.sh_degree)
+        self.ms = B.params_struct(self.m, self.sh_degree)
+        self.vs = B.params_struct(self.v, self.sh_degree)
+        return perm.cpu().numpy()
+
     def set_sparse_adam(self, on: bool = True) -> None:
         """Visible-only Adam in the fused backward (gs_render_bwd_adam): Gaussians seen by no view of the step keep
         their parameters and moments."""

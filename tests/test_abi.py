@@ -90,17 +90,19 @@ def test_frame_layout_on_host(lib):
     lib.gs_plan_cameras(arr, 2, ctypes.byref(o))
     n, cap = 1000, 5000
     nbytes = lib.gs_frame_bytes(n, arr, 2, ctypes.byref(o), cap)
-    assert nbytes >= 2 * n * (48 + 8) + cap * (2 * 12 + 48 + 4)
+    assert nbytes >= 2 * n * (48 + 8 + 4 + 4) + cap * (2 * 8 + 48 + 4)
     f = B.gs_frame()
     base = 1 << 20  # carving is pure host arithmetic: any 256-aligned address works
     assert lib.gs_frame_init(ctypes.byref(f), base, nbytes, n, arr, base, 2, ctypes.byref(o), cap) == 0
-    ptrs = sorted([f.rec, f.rect, f.ipart, f.inst_rec, f.vis_mask, f.n_inst, f.inst_off, f.keys[0],
-                   f.keys[1], f.vals[0],
+    ptrs = sorted([f.rec, f.rect, f.ipart, f.inst_rec, f.vis_mask, f.n_inst, f.n_rec, f.rec_first, f.zbits, f.rec_inst,
+                   f.rkeys[0], f.rkeys[1], f.rvals[0], f.rvals[1], f.keys[0], f.keys[1], f.vals[0],
                    f.vals[1], f.tile_range, f.counters, f.seg_count, f.seg_first, f.items, f.seg, f.split, f.loss,
                    f.scratch])
+    assert len(set(ptrs)) == len(ptrs)
+    assert f.rec_cap == min(2 * n, cap)
     assert all(p % 256 == 0 for p in ptrs) and ptrs[0] == base and ptrs[-1] < base + nbytes
     total_tiles = sum(c.tiles_x * c.tiles_y for c in arr)
-    assert f.n_tiles == total_tiles and f.key_bits == 32 + max(1, int(np.ceil(np.log2(total_tiles))))
+    assert f.n_tiles == total_tiles and f.key_bits == max(1, int(np.ceil(np.log2(total_tiles))))
     # depth segments of the fused backward: default length 512, capacities bound every split
     assert f.seg_len == 512 and f.seg_cap == 2 * cap // 512 + 2 and f.long_cap == cap // 512 + 1
     assert f.item_cap == total_tiles + f.seg_cap

@@ -204,7 +204,7 @@ def test_binning_matches_oracle(gpu_lib, seed, n, W, H, mu):
     fr, V, n = out["frame"], len(sc.cams), sc.n
     I = out["n_inst"]
     keys, vals = B.sorted_pairs(fr, I)
-    keys = keys.cpu().numpy().view(np.uint64)
+    keys = keys.cpu().numpy().view(np.uint32)
     vals = vals.cpu().numpy()
     rng_ = B.frame_tensor(fr, "tile_range", 2 * fr.f.n_tiles, torch.int32).view(-1, 2).cpu().numpy()
     ref = oracle.project(32, sc.params(), 1, sc.cams)
@@ -226,10 +226,10 @@ def test_binning_matches_oracle(gpu_lib, seed, n, W, H, mu):
             assert gk == rk_, f"tile {t}"
             n_diff += 1
         if rng_[t, 1] > rng_[t, 0]:
-            assert np.all((keys[rng_[t, 0]:rng_[t, 1]] >> np.uint64(32)) == t)
+            assert np.all(keys[rng_[t, 0]:rng_[t, 1]] == t)
     log("tiles differing only in marginal records:", n_diff, "marginal records:", len(marginal))
     if not marginal:
-        assert np.array_equal(vals, rv) and np.array_equal(keys, rk)
+        assert np.array_equal(vals, rv) and np.array_equal(keys, (rk >> np.uint64(32)).astype(np.uint32))
 
 
 def test_full_size_batch_binning_is_bit_exact_from_gpu_records(gpu_lib):
@@ -244,10 +244,10 @@ def test_full_size_batch_binning_is_bit_exact_from_gpu_records(gpu_lib):
     B.gs_project(model.ps, fr)
     assert B.gs_bin_tiles(fr, sync_count=False) is None
     I, flags = B.gs_read_counters(fr)
-    log("instances", I, "flags", flags, "key bits", fr.f.key_bits, "passes", fr.f.sort_passes)
+    log("instances", I, "flags", flags, "tile bits", fr.f.key_bits, "passes", fr.f.sort_passes)
     assert flags == 0 and 10_000_000 < I <= fr.capacity
     keys, vals = B.sorted_pairs(fr, I)
-    keys = keys.cpu().numpy().view(np.uint64)
+    keys = keys.cpu().numpy().view(np.uint32)
     vals = vals.cpu().numpy()
     nt = fr.f.n_tiles
     rng_ = B.frame_tensor(fr, "tile_range", 2 * nt, torch.int32).view(-1, 2).cpu().numpy()
@@ -256,7 +256,9 @@ def test_full_size_batch_binning_is_bit_exact_from_gpu_records(gpu_lib):
     del rec
     rk, rv, lo, hi = oracle.bin_records(rect, zbits, vis.astype(np.int32), sc.n, sc.cams)
     assert len(rk) == I
-    assert np.array_equal(keys, rk)
+    # the GPU's sort key is the tile id alone (the depth order comes from the record sort before it): the tile of
+    # every sorted instance and the record id in every position equal the oracle's (tile, depth bits) sort
+    assert np.array_equal(keys, (rk >> np.uint64(32)).astype(np.uint32))
     assert np.array_equal(vals.astype(np.int64), rv)
     empty = lo == hi
     assert np.array_equal(rng_[~empty, 0], lo[~empty]) and np.array_equal(rng_[~empty, 1], hi[~empty])
@@ -1039,6 +1041,39 @@ def test_map_expansion_matches_oracle(gpu_lib, seed, n_map, n_pts, cap, cell, is
     for d in (model.m, model.v):
         for t in d.values():
             assert not t[n0:].any()
+
+
+def test_spatial_order_matches_oracle_and_keeps_the_gradients(gpu_lib):
+    """gs_spatial_order: the Morton permutation equals the oracle's (bit for bit), rows of parameters and moments
+    move with it, and the loss and gradients of the reordered model are the permuted ones (to the rounding of
+    the LDS sums, whose order differs)."""
+    sc = scenes.random_scene(3100, 4000, 96, 72, sh_degree=2, views=3, log_scale_mu=-2.3, depth_fraction=0.3)
+    model = GaussianModel(sc.params(), 2)
+    rng = np.random.default_rng(3101)
+    for t in model.m.values():
+        t.copy_(torch.as_tensor(rng.standard_normal(tuple(t.shape)).astype(np.float32)))
+    before = {k: t.cpu().numpy().copy() for k, t in model.p.items()}
+    m_before = {k: t.cpu().numpy().copy() for k, t in model.m.items()}
+    ref = BatchedStep(GaussianModel(sc.params(), 2), sc.cams, sc.tgt_rgb, sc.tgt_depth, keep_grads=True)
+    ref.run_eager()
+    g_ref = {k: v.cpu().numpy() for k, v in ref.model.g.items()}
+    perm = model.reorder_spatially()
+    assert np.array_equal(perm, oracle.spatial_order(before["means"]))
+    for k in before:
+        assert np.array_equal(model.p[k].cpu().numpy(), before[k][perm]), k
+        assert np.array_equal(model.m[k].cpu().numpy(), m_before[k][perm]), k
+    for t in model.m.values():
+        t.zero_()
+    st = BatchedStep(model, sc.cams, sc.tgt_rgb, sc.tgt_depth, keep_grads=True)
+    st.run_eager()
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(st.loss(), ref.loss(), rtol=1e-5)
+    scale = oracle.gradient_scale(sc.params(), 2, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
+    for k in g_ref:
+        a = model.g[k].cpu().numpy().astype(np.float64)
+        b = g_ref[k][perm].astype(np.float64)
+        rnd = ROUND_C * U32 * scale[k][perm].reshape(a.shape)
+        assert np.all(np.abs(a - b) <= 1e-5 * np.abs(b) + 2 * rnd), k
 
 
 # ----------------------------------------------------------------------------- training policies (Sec. III-D, III-E)

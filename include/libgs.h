@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GS_VERSION 2
+#define GS_VERSION 3
 #define GS_MAX_VIEWS 64
 
 typedef enum {
@@ -142,27 +142,26 @@ typedef struct gs_frame {
   float* rec;           /* [n_views*n][12]: {mu_x, mu_y, z, o}, {conic a, b, c, red},
                            {green, blue, px0 | px1 << 16, py0 | py1 << 16} (pixel rectangle as int16 pairs) */
   int16_t* rect;        /* [n_views*n][4]: tile rectangle tx0, tx1, ty0, ty1 (valid when visible) */
-  float* ipart;         /* [capacity][12]: per tile instance, in emission order (records in ascending depth, ties
-                           by record index; each record's tiles row by row, one contiguous run per record starting
-                           at rec_inst of the record), the compositing backward's partial
+  float* ipart;         /* [capacity][12]: per tile instance, at its partial slot (Gaussian by Gaussian from
+                           inst_first[g], views ascending, each record's tiles row by row from rec_slot of the
+                           record), the compositing backward's partial
                            dL/d{mu_x, mu_y, a, b, c, o, red, green, blue, z} of its record summed over the
                            pixels of its tile (or depth segment); 2 words of padding.  Every backward call
-                           writes every instance once (plain stores, no atomics) */
-  int32_t* inst_rec;    /* [capacity]: record of each instance in emission order */
+                           writes every stored instance once (plain stores, no atomics) */
+  int32_t* inst_first;  /* [n]: exclusive scan of n_inst: the first partial slot of Gaussian g */
   uint64_t* vis_mask;   /* [n]: bit v set if Gaussian g is visible in view v */
   int32_t* n_inst;      /* [n]: tile instances of Gaussian g over all views */
   int32_t* n_rec;       /* [n]: visible records (views) of Gaussian g */
   int32_t* rec_first;   /* [n]: exclusive scan of n_rec: where g's records start in the record list */
   uint32_t* zbits;      /* [n_views*n]: IEEE bits of the camera depth of each visible record */
-  int32_t* rec_inst;    /* [n_views*n]: first emission index of each visible record */
+  int32_t* rec_slot;    /* [n_views*n]: first partial slot of each visible record */
   int64_t rec_cap;      /* capacity of the record list: min(n_views * n, capacity) */
   uint32_t* rkeys[2];   /* [rec_cap] record list: depth bits (sorted into rkeys[0]) */
   int32_t* rvals[2];    /* [rec_cap] record list: record ids (sorted into rvals[0]); rvals[1] then holds each
                            sorted record's first emission index */
   uint32_t* keys[2];    /* [capacity] instance keys: global tile ids (sorted into keys[sort_passes & 1]) */
-  int32_t* vals[2];     /* [capacity] emission indices while sorting; after gs_bin_tiles vals[sort_passes & 1]
-                           holds the record id of each sorted instance and the other buffer its emission
-                           index */
+  int32_t* vals[2];     /* [capacity] record id of each instance (sorted into vals[sort_passes & 1]; the other
+                           buffer is sort scratch) */
   int32_t* tile_range;  /* [n_tiles][2]: [begin, end) of each tile's instances in the sorted list */
   int32_t* tile_order;  /* [n_tiles]: tiles by descending list length (the compositing schedule) */
   int32_t* counters;    /* [256]: [0] instance count, [1] flags, [2..2+n_views) valid depth pixels per view,
@@ -269,7 +268,7 @@ int gs_render_bwd(const gs_params* params, const gs_frame* frame, const gs_opts*
  * dL/d{mean_I, conic, opacity, colour, depth} of its record over its tile's pixels, written to
  * frame->ipart (every instance, no accumulation across calls); in loss mode it also writes frame->loss.
  * gs_project_bwd: projection backward only (eqs. Sigma and muI): one thread per Gaussian sums the
- * partials of its instances view by view (a contiguous run per record in emission order) and adds the parameter
+ * partials of its instances view by view (one contiguous run of slots per Gaussian) and adds the parameter
  * gradients to grads (+=); no atomics. */
 int gs_composite_bwd(const gs_frame* frame, const gs_opts* opts, const gs_images* fwd, const gs_loss* loss,
                      void* stream);

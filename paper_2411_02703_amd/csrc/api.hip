@@ -39,7 +39,7 @@ bool tiles_supported(int tw, int th) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t rec, rect, ipart, instrec, mask, ninst, nrec, instoff, zbits, recinst, rk[2], rv[2], k0, k1, v0, v1, range, order,
+  size_t rec, rect, ipart, instfirst, mask, ninst, nrec, instoff, zbits, recslot, rk[2], rv[2], k0, k1, v0, v1, range, order,
       counters, loss, scratch, total;
   int64_t rec_cap;
   size_t segcount, segfirst, items, seg, split;
@@ -106,13 +106,13 @@ Layout make_layout(int64_t n, int V, int n_tiles, int64_t cap, const gs_opts* op
   L.rec = take(R * 48);
   L.rect = take(R * 8);
   L.ipart = take((size_t)cap * 48);
-  L.instrec = take((size_t)cap * 4);
+  L.instfirst = take((size_t)n * 4);
   L.mask = take((size_t)n * 8);
   L.ninst = take((size_t)n * 4);
   L.nrec = take((size_t)n * 4);
   L.instoff = take((size_t)n * 4);
   L.zbits = take(R * 4);
-  L.recinst = take(R * 4);
+  L.recslot = take(R * 4);
   L.rec_cap = (int64_t)R < cap ? (int64_t)R : cap;
   for (int k = 0; k < 2; ++k) {
     L.rk[k] = take((size_t)L.rec_cap * 4);
@@ -292,13 +292,13 @@ int gs_frame_init(gs_frame* f, void* block, size_t bytes, int64_t n, const gs_ca
   f->rec = reinterpret_cast<float*>(b + L.rec);
   f->rect = reinterpret_cast<int16_t*>(b + L.rect);
   f->ipart = reinterpret_cast<float*>(b + L.ipart);
-  f->inst_rec = reinterpret_cast<int32_t*>(b + L.instrec);
+  f->inst_first = reinterpret_cast<int32_t*>(b + L.instfirst);
   f->vis_mask = reinterpret_cast<uint64_t*>(b + L.mask);
   f->n_inst = reinterpret_cast<int32_t*>(b + L.ninst);
   f->n_rec = reinterpret_cast<int32_t*>(b + L.nrec);
   f->rec_first = reinterpret_cast<int32_t*>(b + L.instoff);
   f->zbits = reinterpret_cast<uint32_t*>(b + L.zbits);
-  f->rec_inst = reinterpret_cast<int32_t*>(b + L.recinst);
+  f->rec_slot = reinterpret_cast<int32_t*>(b + L.recslot);
   f->rec_cap = L.rec_cap;
   for (int k = 0; k < 2; ++k) {
     f->rkeys[k] = reinterpret_cast<uint32_t*>(b + L.rk[k]);
@@ -352,7 +352,6 @@ int gs_bin_tiles(const gs_frame* f, const gs_opts* o, int32_t sync_count, int64_
   GS_HIP(gs_launch::sort_pairs32(f->keys[0], f->vals[0], f->keys[1], f->vals[1], n_sized, count_dev, f->capacity,
                                  f->key_bits, f->scratch, st),
          "gs_bin_tiles: sort by tile");
-  GS_HIP(gs_launch::inst_finish(*f, n_sized, count_dev, st), "gs_bin_tiles: sorted ids");
   GS_HIP(gs_launch::ranges(*f, f->keys[f->sort_passes & 1], n_sized, count_dev, st), "gs_bin_tiles: ranges");
   GS_HIP(gs_launch::tile_schedule(*f, st), "gs_bin_tiles: schedule");
   GS_HIP(gs_launch::work_items(*f, st), "gs_bin_tiles: work items");

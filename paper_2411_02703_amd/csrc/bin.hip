@@ -6,9 +6,12 @@
 //      emission index), and the instances are sorted by tile (2 passes at up to 65,536 tiles).
 // A stable sort by tile of a depth-ordered sequence is the (tile, depth, record) order; ties in depth keep
 // ascending Gaussian index inside a view (the records of one view are listed in Gaussian order), and records
-// of different views never share a tile.  Each record's instances stay one contiguous run of emission indices
-// (its first index is kept per record), which is where the compositing backward stores their partials and the
-// projection backward sums them.
+// of different views never share a tile.  The sorted value of an instance is its record id.
+//
+// The compositing backward stores each instance's partial derivatives at a slot of its own, laid out Gaussian by
+// Gaussian (the exclusive scan of the per-Gaussian instance counts), views ascending inside a Gaussian, a
+// record's tiles row by row: each record's first slot is written here, in Gaussian order, so that the projection
+// backward reads one contiguous run per Gaussian.
 #include "common.h"
 
 namespace {
@@ -39,10 +42,17 @@ __device__ __forceinline__ int block_scan_256(int x, int* sh_wave, int* total) {
   return base + incl - x;
 }
 
-// Each block scans kScanTile consecutive items (exclusive) and writes its total.
+// Each block scans kScanTile consecutive items (exclusive) and writes its total.  The items scanned are the
+// first dev_count(dc, n): blocks past them only write a zero total.
 __global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int32_t* __restrict__ in, int32_t* __restrict__ out,
-                                                          int64_t n, int32_t* __restrict__ sums) {
+                                                          int64_t n_sized, int32_t* __restrict__ sums,
+                                                          gs_launch::DevCount dc) {
   __shared__ int sh_wave[4];
+  const int64_t n = gs_launch::dev_count(dc, n_sized);
+  if ((int64_t)blockIdx.x * kScanTile >= n) {
+    if (threadIdx.x == 0) sums[blockIdx.x] = 0;
+    return;
+  }
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   int v[kScanItems];
   int acc = 0;
@@ -63,10 +73,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int32_t* __res
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t* __restrict__ out, int64_t n,
-                                                         const int32_t* __restrict__ sums) {
-  const int add = sums[blockIdx.x];
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t* __restrict__ out, int64_t n_sized,
+                                                         const int32_t* __restrict__ sums, gs_launch::DevCount dc) {
+  const int64_t n = gs_launch::dev_count(dc, n_sized);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (base >= n) return;
+  const int add = sums[blockIdx.x];
   for (int i = threadIdx.x; i < kScanTile; i += kScanThreads) {
     const int64_t idx = base + i;
     if (idx < n) out[idx] += add;
@@ -91,31 +103,33 @@ __device__ __forceinline__ int64_t sort_count(const int32_t* count_dev, int64_t 
 template <class KeyT>
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const KeyT* __restrict__ keys,
                                                            const int32_t* __restrict__ count_dev, int64_t n_sized,
-                                                           int64_t cap, int shift, int32_t* __restrict__ hist,
-                                                           int nblocks) {
+                                                           int64_t cap, int shift, int32_t* __restrict__ hist) {
   __shared__ int h[256];
+  const int64_t n = sort_count(count_dev, n_sized, cap);
+  // digit-major histogram over the blocks that hold keys: hist[d * nb + b]
+  const int nb = (int)((n + kSortTile - 1) / kSortTile);
+  if ((int)blockIdx.x >= nb) return;
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t n = sort_count(count_dev, n_sized, cap);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   for (int i = 0; i < kSortItems; ++i) {
     const int64_t idx = base + i * kSortThreads + threadIdx.x;
     if (idx < n) atomicAdd(&h[(int)((keys[idx] >> shift) & 255u)], 1);
   }
   __syncthreads();
-  hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+  hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
 // Stable scatter of one 8-bit digit.  Each wave ranks its 512 keys (8 rounds of 64) with ballot-based
 // digit matching, the block orders them in LDS (digit-major, stable), then writes runs to their global
-// offsets from the scanned digit-major histogram.
+// offsets from the scanned digit-major histogram (hist_scan[d * nb + b] over the nb blocks that hold keys).
 template <class KeyT>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const KeyT* __restrict__ kin,
                                                               const int32_t* __restrict__ vin,
                                                               KeyT* __restrict__ kout, int32_t* __restrict__ vout,
                                                               const int32_t* __restrict__ count_dev, int64_t n_sized,
                                                               int64_t cap, int shift,
-                                                              const int32_t* __restrict__ hist_scan, int nblocks) {
+                                                              const int32_t* __restrict__ hist_scan) {
   __shared__ KeyT sk[kSortTile];
   __shared__ int32_t sv[kSortTile];
   __shared__ int32_t wcnt[4][256];
@@ -164,7 +178,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const KeyT* __res
     wcnt[1][tid] = ds + c0;
     wcnt[2][tid] = ds + c0 + c1;
     wcnt[3][tid] = ds + c0 + c1 + c2;
-    gofs[tid] = hist_scan[tid * nblocks + blockIdx.x];
+    gofs[tid] = hist_scan[tid * (int)((n + kSortTile - 1) / kSortTile) + blockIdx.x];
   }
   __syncthreads();
 #pragma unroll
@@ -200,14 +214,22 @@ __global__ void k_record_total(const int32_t* __restrict__ n_rec, const int32_t*
   counters[kRecCount] = first[n - 1] + n_rec[n - 1];
 }
 
+__device__ __forceinline__ int rect_area(const short4 rc) { return (rc.y - rc.x + 1) * (rc.w - rc.z + 1); }
+
+// ... and each visible record's first partial slot: inst_first[g] plus the instances of g's records in the views
+// before it.
 __global__ __launch_bounds__(256) void k_record_list(const uint64_t* __restrict__ vis_mask,
                                                     const int32_t* __restrict__ first,
+                                                    const int32_t* __restrict__ inst_first,
+                                                    const short4* __restrict__ rect,
                                                     const uint32_t* __restrict__ zbits, int V, int64_t n, int64_t rcap,
-                                                    uint32_t* __restrict__ rkeys, int32_t* __restrict__ rvals) {
+                                                    uint32_t* __restrict__ rkeys, int32_t* __restrict__ rvals,
+                                                    int32_t* __restrict__ rec_slot) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   uint64_t m = vis_mask[g];
   int64_t c = first[g];
+  int32_t slot = inst_first[g];
   while (m) {
     const int v = __builtin_ctzll(m);
     m &= m - 1;
@@ -217,10 +239,10 @@ __global__ __launch_bounds__(256) void k_record_list(const uint64_t* __restrict_
       rvals[c] = (int32_t)r;
     }
     ++c;
+    rec_slot[r] = slot;
+    slot += rect_area(rect[r]);
   }
 }
-
-__device__ __forceinline__ int rect_area(const short4 rc) { return (rc.y - rc.x + 1) * (rc.w - rc.z + 1); }
 
 // Instance count of each depth-sorted record (its tile rectangle's area).
 __global__ void k_record_counts(const int32_t* __restrict__ rvals, const short4* __restrict__ rect,
@@ -263,14 +285,12 @@ __device__ __forceinline__ int64_t read_lane64(int64_t x, int l) {
 }
 
 // One thread per depth-sorted record: its run of instances (tiles row by row) starts at eo[j]; key = global tile
-// id, value = emission index; inst_rec keeps the record of each emission index and rec_inst the first emission
-// index of each record.  Records with more than kSolo tiles are written by the whole wave, a tile per lane.
+// id, value = record id.  Records with more than kSolo tiles are written by the whole wave, a tile per lane.
 __global__ __launch_bounds__(256) void k_emit(const int32_t* __restrict__ rvals, const int32_t* __restrict__ eo,
                                              const short4* __restrict__ rect, const gs_camera* __restrict__ cams,
                                              int V, int64_t n, const int32_t* __restrict__ counters, int64_t rcap,
                                              int64_t capacity, uint32_t* __restrict__ keys,
-                                             int32_t* __restrict__ vals, int32_t* __restrict__ inst_rec,
-                                             int32_t* __restrict__ rec_inst) {
+                                             int32_t* __restrict__ vals) {
   const int64_t R = sort_count(counters + kRecCount, rcap, rcap);
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
@@ -285,7 +305,6 @@ __global__ __launch_bounds__(256) void k_emit(const int32_t* __restrict__ rvals,
     const int v = (int)(r / n);
     toff = cams[v].tile_offset;
     tx_n = cams[v].tiles_x;
-    rec_inst[r] = (int32_t)o;
   }
   const int w = rc.y - rc.x + 1, cnt = here ? w * (rc.w - rc.z + 1) : 0;
   if (here && cnt <= kSolo) {
@@ -294,8 +313,7 @@ __global__ __launch_bounds__(256) void k_emit(const int32_t* __restrict__ rvals,
       for (int tx = rc.x; tx <= rc.y; ++tx) {
         if (q < capacity) {
           keys[q] = (uint32_t)(toff + ty * tx_n + tx);
-          vals[q] = (int32_t)q;
-          inst_rec[q] = (int32_t)r;
+          vals[q] = (int32_t)r;
         }
         ++q;
       }
@@ -313,25 +331,10 @@ __global__ __launch_bounds__(256) void k_emit(const int32_t* __restrict__ rvals,
       if (q < capacity) {
         const int ty = y0 + k / wL, tx = x0 + k % wL;
         keys[q] = (uint32_t)(toL + ty * txL + tx);
-        vals[q] = (int32_t)q;
-        inst_rec[q] = (int32_t)rL;
+        vals[q] = (int32_t)rL;
       }
     }
   }
-}
-
-// After the sort: the sorted buffer takes the record of each sorted instance (the compositing reads it) and
-// the other buffer keeps its emission index (the compositing backward stores the instance's partials there,
-// so that each Gaussian's partials form one contiguous run).
-__global__ __launch_bounds__(256) void k_inst_finish(int32_t* __restrict__ vals, int32_t* __restrict__ emi,
-                                                    const int32_t* __restrict__ inst_rec,
-                                                    const int32_t* __restrict__ count_dev, int64_t n_sized,
-                                                    int64_t cap) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= sort_count(count_dev, n_sized, cap)) return;
-  const int32_t i = vals[p];
-  vals[p] = inst_rec[i];
-  emi[p] = i;
 }
 
 __global__ void k_ranges(const uint32_t* __restrict__ keys, const int32_t* __restrict__ count_dev, int64_t n_sized,
@@ -434,17 +437,17 @@ size_t scan_scratch_ints(int64_t n) {
   return total + 64;
 }
 
-hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t st) {
+hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t st, DevCount dc) {
   if (n <= 0) return hipSuccess;
   const int64_t nb = cdiv(n, kScanTile);
   int32_t* sums = scratch;
-  k_scan_tile<<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, n, sums);
+  k_scan_tile<<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, n, sums, dc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (nb > 1) {
-    e = scan_exclusive(sums, sums, nb, scratch + align64(nb), st);
+    e = scan_exclusive(sums, sums, nb, scratch + align64(nb), st, DevCount{});
     if (e != hipSuccess) return e;
-    k_scan_add<<<(unsigned)nb, kScanThreads, 0, st>>>(out, n, sums);
+    k_scan_add<<<(unsigned)nb, kScanThreads, 0, st>>>(out, n, sums, dc);
     return hipGetLastError();
   }
   return hipSuccess;
@@ -480,13 +483,14 @@ static hipError_t sort_impl(KeyT* k0, int32_t* v0, KeyT* k1, int32_t* v1, int64_
   for (int p = 0; p < passes; ++p) {
     const int shift = 8 * p;
     const int src = p & 1, dst = src ^ 1;
-    k_sort_hist<KeyT><<<(unsigned)nb, kSortThreads, 0, st>>>(kb[src], count_dev, n_sized, cap, shift, hist, (int)nb);
+    k_sort_hist<KeyT><<<(unsigned)nb, kSortThreads, 0, st>>>(kb[src], count_dev, n_sized, cap, shift, hist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = scan_exclusive(hist, hist, 256 * nb, scan_scr, st);
+    // the histogram holds 256 * cdiv(count, kSortTile) entries
+    e = scan_exclusive(hist, hist, 256 * nb, scan_scr, st, DevCount{count_dev, cap, kSortTile, 256});
     if (e != hipSuccess) return e;
     k_sort_scatter<KeyT><<<(unsigned)nb, kSortThreads, 0, st>>>(kb[src], vb[src], kb[dst], vb[dst], count_dev,
-                                                                n_sized, cap, shift, hist, (int)nb);
+                                                                n_sized, cap, shift, hist);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -503,9 +507,9 @@ hipError_t sort_pairs32(uint32_t* k0, int32_t* v0, uint32_t* k1, int32_t* v1, in
   return sort_impl<uint32_t>(k0, v0, k1, v1, n_sized, count_dev, cap, key_bits, scratch, st);
 }
 
-// Binning up to the instance total: the record list sorted by depth (in rkeys[0] / rvals[0]), each sorted
-// record's instance count (in rkeys[1], as int32) and its first emission index (in rvals[1]), the instance total
-// and the overflow flag.
+// Binning up to the instance total: the records' first partial slots, the record list sorted by depth (in
+// rkeys[0] / rvals[0]), each sorted record's instance count (in rkeys[1], as int32) and its first emission index
+// (in rvals[1]), the instance total and the overflow flag.
 hipError_t bin_records(const gs_frame& f, hipStream_t st) {
   const int64_t rcap = f.rec_cap;
   hipError_t e = fill_i32(f.counters + kInstSum, 0, 1, st);
@@ -515,10 +519,12 @@ hipError_t bin_records(const gs_frame& f, hipStream_t st) {
   k_sum_counts<<<(unsigned)nb, 256, 0, st>>>(f.n_inst, f.n, f.counters);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = scan_exclusive(f.n_rec, f.rec_first, f.n, f.scratch, st)) != hipSuccess) return e;
+  if ((e = scan_exclusive(f.n_inst, f.inst_first, f.n, f.scratch, st)) != hipSuccess) return e;
   k_record_total<<<1, 1, 0, st>>>(f.n_rec, f.rec_first, f.n, f.counters);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_record_list<<<(unsigned)cdiv(f.n, 256), 256, 0, st>>>(f.vis_mask, f.rec_first, f.zbits, f.n_views, f.n, rcap,
-                                                          f.rkeys[0], f.rvals[0]);
+  k_record_list<<<(unsigned)cdiv(f.n, 256), 256, 0, st>>>(f.vis_mask, f.rec_first, f.inst_first,
+                                                          reinterpret_cast<const short4*>(f.rect), f.zbits, f.n_views,
+                                                          f.n, rcap, f.rkeys[0], f.rvals[0], f.rec_slot);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = sort_pairs32(f.rkeys[0], f.rvals[0], f.rkeys[1], f.rvals[1], rcap, f.counters + kRecCount, rcap, 32,
                         f.scratch, st)) != hipSuccess)
@@ -527,7 +533,9 @@ hipError_t bin_records(const gs_frame& f, hipStream_t st) {
   k_record_counts<<<(unsigned)cdiv(rcap, 256), 256, 0, st>>>(f.rvals[0], reinterpret_cast<const short4*>(f.rect),
                                                              f.counters, rcap, cnt);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = scan_exclusive(cnt, f.rvals[1], rcap, f.scratch, st)) != hipSuccess) return e;
+  if ((e = scan_exclusive(cnt, f.rvals[1], rcap, f.scratch, st, DevCount{f.counters + kRecCount, rcap, 1, 1})) !=
+      hipSuccess)
+    return e;
   k_instance_total<<<1, 1, 0, st>>>(f.capacity, f.counters);
   return hipGetLastError();
 }
@@ -535,8 +543,7 @@ hipError_t bin_records(const gs_frame& f, hipStream_t st) {
 hipError_t emit(const gs_frame& f, int64_t /*n_sized*/, hipStream_t st) {
   k_emit<<<(unsigned)cdiv(f.rec_cap, 256), 256, 0, st>>>(f.rvals[0], f.rvals[1],
                                                          reinterpret_cast<const short4*>(f.rect), f.cams, f.n_views,
-                                                         f.n, f.counters, f.rec_cap, f.capacity, f.keys[0], f.vals[0],
-                                                         f.inst_rec, f.rec_inst);
+                                                         f.n, f.counters, f.rec_cap, f.capacity, f.keys[0], f.vals[0]);
   return hipGetLastError();
 }
 
@@ -565,14 +572,6 @@ hipError_t work_items(const gs_frame& f, hipStream_t st) {
   if ((e = scan_exclusive(f.seg_count, f.seg_first, f.n_tiles, f.scratch, st)) != hipSuccess) return e;
   k_seg_emit<<<nb, 256, 0, st>>>(f.tile_order, f.n_tiles, f.seg_count, f.seg_first, reinterpret_cast<int4*>(f.items),
                                  f.counters);
-  return hipGetLastError();
-}
-
-hipError_t inst_finish(const gs_frame& f, int64_t n_sized, const int32_t* count_dev, hipStream_t st) {
-  if (n_sized <= 0) return hipSuccess;
-  const int s = f.sort_passes & 1;
-  k_inst_finish<<<(unsigned)cdiv(n_sized, 256), 256, 0, st>>>(f.vals[s], f.vals[s ^ 1], f.inst_rec, count_dev,
-                                                               n_sized, f.capacity);
   return hipGetLastError();
 }
 

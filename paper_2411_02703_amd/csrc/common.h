@@ -130,11 +130,26 @@ hipError_t project(const gs_params& p, const gs_frame& f, const gs_opts& o, hipS
 hipError_t project_bwd(const gs_params& p, const gs_frame& f, const gs_opts& o, const gs_params& g,
                        hipStream_t s);
 size_t scan_scratch_ints(int64_t n);
-hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t s);
+// An element count read on the device: min(n_sized, mul * ceil(min(max(*p, 0), cap) / div)); p == NULL: n_sized.
+struct DevCount {
+  const int32_t* p = nullptr;
+  int64_t cap = 0;
+  int div = 1, mul = 1;
+};
+__device__ __forceinline__ int64_t dev_count(const DevCount& c, int64_t n_sized) {
+  if (!c.p) return n_sized;
+  int64_t k = c.p[0];
+  k = k < 0 ? 0 : (k > c.cap ? c.cap : k);
+  k = (k + c.div - 1) / c.div * c.mul;
+  return k < n_sized ? k : n_sized;
+}
+// Exclusive scan of in[0, n) into out (in place allowed); with a device count only its first dev_count items.
+hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t s,
+                          DevCount dc = DevCount{});
 hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t s);
-// Binning up to the instance total: visible records sorted by depth, their instance counts and first emission
-// indices, counters[0] = instances (overflow flagged).
+// Binning up to the instance total: the records' first partial slots, visible records sorted by depth, their
+// instance counts and first emission indices, counters[0] = instances (overflow flagged).
 hipError_t bin_records(const gs_frame& f, hipStream_t s);
 hipError_t emit(const gs_frame& f, int64_t n_sized, hipStream_t s);
 size_t sort_scratch_ints(int64_t n);
@@ -142,7 +157,6 @@ hipError_t sort_pairs32(uint32_t* k0, int32_t* v0, uint32_t* k1, int32_t* v1, in
                         const int32_t* count_dev, int64_t cap, int key_bits, int32_t* scratch, hipStream_t s);
 hipError_t sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int64_t n_sized,
                       const int32_t* count_dev, int64_t cap, int key_bits, int32_t* scratch, hipStream_t s);
-hipError_t inst_finish(const gs_frame& f, int64_t n_sized, const int32_t* count_dev, hipStream_t s);
 hipError_t ranges(const gs_frame& f, const uint32_t* keys, int64_t n_sized, const int32_t* count_dev, hipStream_t s);
 hipError_t tile_schedule(const gs_frame& f, hipStream_t s);
 hipError_t work_items(const gs_frame& f, hipStream_t s);

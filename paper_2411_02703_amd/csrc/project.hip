@@ -299,42 +299,60 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
                                                      float* __restrict__ sh, int64_t n,
                                                      const gs_camera* __restrict__ cams, int V, DevOpts op,
                                                      const float4* __restrict__ ipart,
-                                                     const int32_t* __restrict__ rec_inst, const short4* __restrict__ rect,
+                                                     const int32_t* __restrict__ inst_first, const short4* __restrict__ rect,
                                                      const int32_t* __restrict__ count_dev, int64_t capacity,
                                                      const uint64_t* __restrict__ vis_mask, float* __restrict__ g_means,
                                                      float* __restrict__ g_scales, float* __restrict__ g_quats,
                                                      float* __restrict__ g_opac, float* __restrict__ g_sh,
                                                      AdamArgs ad) {
   constexpr int K = (DEG + 1) * (DEG + 1);
+  constexpr int F = K * 3;   // SH floats per Gaussian
+  constexpr int FP = F + 1;  // LDS row stride (odd, so a lane per row hits distinct banks)
+  // The SH gradient of a lane's Gaussian is summed in its LDS row (FP floats; with ADAM the last one flags a
+  // Gaussian that takes no step) rather than in registers, which halves the kernel's register footprint; with
+  // ADAM the wave then steps its 64 rows in coalesced runs of parameters and moments instead of one 4F-byte
+  // row per lane.
+  __shared__ float sbuf[4 * 64 * FP];
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
+  const int64_t g0 = g - lane;  // first Gaussian of this wave
+  const int nw = (int)max<int64_t>(0, min<int64_t>(64, n - g0));  // Gaussians of this wave
+  float* wb = sbuf + (threadIdx.x >> 6) * 64 * FP;
+  float* gf = wb + lane * FP;  // this lane's row: dL/d SH coefficients
   // every lane stays to the end of the view loop (the wave sums large records together)
   const uint64_t mask = g < n ? vis_mask[g] : 0ull;
   // lanes without a visible record read Gaussian 0 and discard it, unless they take an Adam step of their own
   const int64_t gg = (ADAM ? g < n : mask != 0) ? g : 0;
-  float mu[3], ls[3], qq[4], f[K * 3];
-  for (int i = 0; i < 3; ++i) {
-    mu[i] = means[gg * 3 + i];
-    ls[i] = log_scales[gg * 3 + i];
-  }
-  for (int i = 0; i < 4; ++i) qq[i] = quats[gg * 4 + i];
+  float mu[3], ls[3], qq[4], f[F];
+  for (int i = 0; i < 3; ++i) mu[i] = means[gg * 3 + i];
 #pragma unroll
-  for (int i = 0; i < K * 3; ++i) f[i] = sh[gg * (K * 3) + i];
-  Shape s;
-  shape_of(ls, qq, opac[gg], s);
+  for (int i = 0; i < F; ++i) f[i] = sh[gg * F + i];
+  // only the covariance is needed in the view loop; scales, rotation and the rest of the shape are read and
+  // formed again after it
+  auto load_shape = [&]() {
+    for (int i = 0; i < 3; ++i) ls[i] = log_scales[gg * 3 + i];
+    for (int i = 0; i < 4; ++i) qq[i] = quats[gg * 4 + i];
+  };
+  float Sig[6];
+  {
+    load_shape();
+    Shape s;
+    shape_of(ls, qq, opac[gg], s);
+    for (int i = 0; i < 6; ++i) Sig[i] = s.Sig[i];
+  }
 
   float gmu[3] = {0.f, 0.f, 0.f};
   float gs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // symmetric dL/dSigma: 00 01 02 11 12 22
   float go = 0.f;
-  float gf[K * 3];
 #pragma unroll
-  for (int i = 0; i < K * 3; ++i) gf[i] = 0.f;
+  for (int i = 0; i < F; ++i) gf[i] = 0.f;
 
-  // this Gaussian's instances: each visible record's instances are one contiguous run of emission indices
-  // starting at rec_inst of the record.  The lanes take the views together; a record with more than kSolo tiles
-  // is summed by the whole wave.  A run outside the stored instances (an overflowed frame, whose gradient is
-  // undefined) is not read.
+  // this Gaussian's instances: one contiguous run of partial slots from inst_first[g], view by view (each
+  // visible record's tiles in turn).  The lanes take the views together; a record with more than kSolo tiles
+  // is summed by the whole wave.  Slots outside the stored instances (an overflowed frame, whose gradient is
+  // undefined) are not read.
   const int64_t n_stored = min((int64_t)count_dev[0], capacity);
+  int64_t run = mask != 0 ? inst_first[g] : 0;
   for (int v = 0; v < V; ++v) {
     const bool vis = (mask >> v) & 1ull;
     if (__ballot(vis) == 0) continue;
@@ -345,7 +363,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
     if (vis) {
       const short4 rc = rect[r];
       cnt = (rc.y - rc.x + 1) * (rc.w - rc.z + 1);
-      i = rec_inst[r];
+      i = run;
+      run += cnt;
       if (i < 0 || i >= n_stored) cnt = 0;
     }
     // the record's gradient: the sum of its instances' partials over the tiles it covers (a contiguous run,
@@ -403,7 +422,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
     float tx, ty, tz;
     camera_point(c, mu[0], mu[1], mu[2], tx, ty, tz);
     Ewa e;
-    ewa(c, s.Sig, tx, ty, tz, op.lowpass, e);
+    ewa(c, Sig, tx, ty, tz, op.lowpass, e);
     const float idet = 1.f / e.det;
     const float a = e.C * idet, b = -e.B * idet, cc = e.A * idet;
     // conic (a, b, c) = inverse of [[A, B], [B, C]]
@@ -459,9 +478,11 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
     }
   }
   if (!ADAM && mask == 0) return;
-  if (ADAM && g >= n) return;
+  load_shape();
   float out_mu[3] = {0.f, 0.f, 0.f}, out_ls[3] = {0.f, 0.f, 0.f}, out_q[4] = {0.f, 0.f, 0.f, 0.f}, out_o = 0.f;
   if (mask != 0) {
+    Shape s;
+    shape_of(ls, qq, opac[gg], s);
     // Sigma = M M^T: dL/dM = 2 Gs M ; M = Rq diag(S)
     const float Gs[9] = {gs[0], gs[1], gs[2], gs[1], gs[3], gs[4], gs[2], gs[4], gs[5]};
     float GM[9];
@@ -497,10 +518,11 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
     for (int i = 0; i < 4; ++i) g_quats[g * 4 + i] += out_q[i];
     g_opac[g] += out_o;
 #pragma unroll
-    for (int i = 0; i < K * 3; ++i) g_sh[g * (K * 3) + i] += gf[i];
+    for (int i = 0; i < F; ++i) g_sh[g * F + i] += gf[i];
     return;
   }
-  if (g_means) {
+  const bool live = g < n;
+  if (g_means && live) {
     for (int i = 0; i < 3; ++i) {
       g_means[g * 3 + i] = out_mu[i];
       g_scales[g * 3 + i] = out_ls[i];
@@ -508,12 +530,30 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
     for (int i = 0; i < 4; ++i) g_quats[g * 4 + i] = out_q[i];
     g_opac[g] = out_o;
 #pragma unroll
-    for (int i = 0; i < K * 3; ++i) g_sh[g * (K * 3) + i] = gf[i];
+    for (int i = 0; i < F; ++i) g_sh[g * F + i] = gf[i];
   }
-  if (ad.bias[2] != 0.f) return;  // skipped step (instance capacity overflowed)
-  if (ad.sparse && mask == 0) return;  // visible-only step
+  if (ad.bias[2] != 0.f) return;  // skipped step (instance capacity overflowed); the same in every thread
+  const bool step = live && !(ad.sparse && mask == 0);  // visible-only step: invisible Gaussians stay
   const float bc1 = ad.bias[0], bc2s = ad.bias[1];
   const float b1 = ad.b1, b2 = ad.b2, eps = ad.eps;
+  {
+    // SH: the wave steps its gradient rows in coalesced runs; the three degree-0 coefficients take lr[4], the
+    // others lr[5]
+    wb[lane * FP + F] = step ? 0.f : 1.f;
+    __syncthreads();
+    const float s4 = ad.lr[4] / bc1, s5 = ad.lr[5] / bc1;
+    for (int e = lane; e < nw * F; e += 64) {
+      const int r = e / F, c = e - r * F;
+      if (wb[r * FP + F] != 0.f) continue;
+      const int64_t idx = g0 * F + e;
+      float pv = sh[idx], mm = ad.m_sh[idx], vv = ad.v_sh[idx];
+      adam_one(pv, mm, vv, wb[r * FP + c], c < 3 ? s4 : s5, b1, b2, eps, bc2s);
+      sh[idx] = pv;
+      ad.m_sh[idx] = mm;
+      ad.v_sh[idx] = vv;
+    }
+  }
+  if (!step) return;
   {
     float o = opac[g];
     const float s3 = ad.lr[3] / bc1;
@@ -549,35 +589,6 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
     reinterpret_cast<float4*>(quats)[g] = make_float4(qq[0], qq[1], qq[2], qq[3]);
     reinterpret_cast<float4*>(ad.m_quats)[g] = mq;
     reinterpret_cast<float4*>(ad.v_quats)[g] = vq;
-  }
-  {
-    // SH: the three degree-0 coefficients take lr[4], the others lr[5]
-    const float s4 = ad.lr[4] / bc1, s5 = ad.lr[5] / bc1;
-    float* msh = ad.m_sh + g * (K * 3);
-    float* vsh = ad.v_sh + g * (K * 3);
-    float* psh = sh + g * (K * 3);
-    if constexpr ((K * 3) % 4 == 0) {
-#pragma unroll
-      for (int c = 0; c < K * 3; c += 4) {
-        float4 m4 = *reinterpret_cast<const float4*>(msh + c), v4 = *reinterpret_cast<const float4*>(vsh + c);
-        adam_one(f[c], m4.x, v4.x, gf[c], c < 3 ? s4 : s5, b1, b2, eps, bc2s);
-        adam_one(f[c + 1], m4.y, v4.y, gf[c + 1], c + 1 < 3 ? s4 : s5, b1, b2, eps, bc2s);
-        adam_one(f[c + 2], m4.z, v4.z, gf[c + 2], c + 2 < 3 ? s4 : s5, b1, b2, eps, bc2s);
-        adam_one(f[c + 3], m4.w, v4.w, gf[c + 3], c + 3 < 3 ? s4 : s5, b1, b2, eps, bc2s);
-        *reinterpret_cast<float4*>(psh + c) = make_float4(f[c], f[c + 1], f[c + 2], f[c + 3]);
-        *reinterpret_cast<float4*>(msh + c) = m4;
-        *reinterpret_cast<float4*>(vsh + c) = v4;
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < K * 3; ++c) {
-        float mm = msh[c], vv = vsh[c];
-        adam_one(f[c], mm, vv, gf[c], c < 3 ? s4 : s5, b1, b2, eps, bc2s);
-        psh[c] = f[c];
-        msh[c] = mm;
-        vsh[c] = vv;
-      }
-    }
   }
 }
 
@@ -628,7 +639,7 @@ static hipError_t project_bwd_launch(const gs_params& p, const gs_frame& f, cons
   float* gsh = gr ? gr->sh : nullptr;
 #define GS_PB(D)                                                                                              \
   k_project_bwd<D, ADAM><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n,     \
-                                                     f.cams, f.n_views, op, ip, f.rec_inst, rect, f.counters,    \
+                                                     f.cams, f.n_views, op, ip, f.inst_first, rect, f.counters,    \
                                                      f.capacity, f.vis_mask, gm, gl, gq, go, gsh, ad)
   switch (p.sh_degree) {
     case 0: GS_PB(0); break;

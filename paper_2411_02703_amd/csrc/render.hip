@@ -49,7 +49,7 @@ struct Geo {
 template <class G>
 struct Stage {
   float4 A[G::BATCH], B[G::BATCH], C[G::BATCH];
-  int32_t r[G::BATCH];
+  int32_t slot[G::BATCH];       // backward sweeps: first partial slot of each staged record
   uint32_t bm[G::MC][G::NB];    // per block: staged records whose rectangle meets it
   int alive[G::NW];             // per wave: a pixel is still live
 };
@@ -127,18 +127,22 @@ __device__ __forceinline__ void unpack_rect(const float4& C, int& x0, int& x1, i
   y1 = (int)((unsigned)b >> 16);
 }
 
-// Records of the tile list in flight, per thread: the round held in registers (ids r, data A, B, C) and the
-// ids of the round after it (rn, valid where vn).  Loads are unconditional (an absent record reads record
-// 0, which is never used), so nothing waits on them until the round is written to LDS.
+// Records of the tile list in flight, per thread: the round held in registers (ids r, data A, B, C and, for a
+// backward sweep, the record's first partial slot sl) and the ids of the round after it (rn, -1 past the end).
+// Loads are unconditional (an absent record reads record 0, which is never used), so nothing waits on them
+// until the round is written to LDS.
 template <class G, int DEPTH>
-__device__ __forceinline__ void fetch_records(const float4* __restrict__ rec, const int (&r)[DEPTH], float4 (&A)[DEPTH],
-                                              float4 (&B)[DEPTH], float4 (&C)[DEPTH]) {
+__device__ __forceinline__ void fetch_records(const float4* __restrict__ rec, const int32_t* __restrict__ rec_slot,
+                                              const int (&r)[DEPTH], float4 (&A)[DEPTH], float4 (&B)[DEPTH],
+                                              float4 (&C)[DEPTH], int (&sl)[DEPTH]) {
 #pragma unroll
   for (int k = 0; k < DEPTH; ++k) {
-    const float4* p = rec + 3 * (int64_t)max(r[k], 0);
+    const int64_t ri = max(r[k], 0);
+    const float4* p = rec + 3 * ri;
     A[k] = p[0];
     B[k] = p[1];
     C[k] = p[2];
+    if (rec_slot) sl[k] = rec_slot[ri];
   }
 }
 
@@ -154,19 +158,20 @@ __device__ __forceinline__ void fetch_ids(const int32_t* __restrict__ vals, int 
 // Write the round held in registers into LDS, then start fetching the round after it (its ids were fetched
 // one round earlier) and the ids of the round after that.
 template <class G, int DEPTH>
-__device__ __forceinline__ void stage_round(Stage<G>& s, const float4* __restrict__ rec, const int32_t* __restrict__ vals,
+__device__ __forceinline__ void stage_round(Stage<G>& s, const float4* __restrict__ rec,
+                                            const int32_t* __restrict__ rec_slot, const int32_t* __restrict__ vals,
                                             int b0, int end, int (&r)[DEPTH], int (&rn)[DEPTH], float4 (&A)[DEPTH],
-                                            float4 (&B)[DEPTH], float4 (&C)[DEPTH]) {
+                                            float4 (&B)[DEPTH], float4 (&C)[DEPTH], int (&sl)[DEPTH]) {
 #pragma unroll
   for (int k = 0; k < DEPTH; ++k) {
-    const int slot = k * G::NT + (int)threadIdx.x;
-    s.A[slot] = A[k];
-    s.B[slot] = B[k];
-    s.C[slot] = C[k];
-    s.r[slot] = r[k];
+    const int j = k * G::NT + (int)threadIdx.x;
+    s.A[j] = A[k];
+    s.B[j] = B[k];
+    s.C[j] = C[k];
+    if (rec_slot) s.slot[j] = sl[k];
     r[k] = rn[k];
   }
-  fetch_records<G, DEPTH>(rec, r, A, B, C);
+  fetch_records<G, DEPTH>(rec, rec_slot, r, A, B, C, sl);
   fetch_ids<G, DEPTH>(vals, b0 + 2 * G::BATCH, end, rn);
 }
 
@@ -306,22 +311,23 @@ __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, 
 // All rounds of one tile list: stage (with the next round in flight), hand out, walk.  at_round(b0, go) runs
 // in every thread after each round barrier, before the round's LDS is rewritten: b0 is the first record of
 // the round about to be staged, go whether it will be (false once the list or every pixel has ended).
+// rec_slot: the records' first partial slots, staged with them (backward sweeps), or NULL.
 template <class G, int DEPTH, bool SYNC, bool ENDS, class AtRound, class Step, class Post>
-__device__ __forceinline__ void sweep(Stage<G>& s, const float4* __restrict__ rec, const int32_t* __restrict__ vals,
-                                      int2 rg, const TileCtx& t, const DevOpts& op, bool& live, AtRound at_round,
-                                      Step step, Post post) {
-  int fr[DEPTH], frn[DEPTH];
+__device__ __forceinline__ void sweep(Stage<G>& s, const float4* __restrict__ rec, const int32_t* __restrict__ rec_slot,
+                                      const int32_t* __restrict__ vals, int2 rg, const TileCtx& t, const DevOpts& op,
+                                      bool& live, AtRound at_round, Step step, Post post) {
+  int fr[DEPTH], frn[DEPTH], fs[DEPTH];
   float4 fA[DEPTH], fB[DEPTH], fC[DEPTH];
   fetch_ids<G, DEPTH>(vals, rg.x, rg.y, fr);
   fetch_ids<G, DEPTH>(vals, rg.x + G::BATCH, rg.y, frn);
-  fetch_records<G, DEPTH>(rec, fr, fA, fB, fC);
+  fetch_records<G, DEPTH>(rec, rec_slot, fr, fA, fB, fC, fs);
   for (int b0 = rg.x;; b0 += G::BATCH) {
     const bool go = round_barrier<G>(s, t, live) && b0 < rg.y;
     at_round(b0, go);
     if (!go) break;
     const int nb = min(G::BATCH, rg.y - b0);
     clear_masks<G>(s);
-    stage_round<G, DEPTH>(s, rec, vals, b0, rg.y, fr, frn, fA, fB, fC);
+    stage_round<G, DEPTH>(s, rec, rec_slot, vals, b0, rg.y, fr, frn, fA, fB, fC, fs);
     __syncthreads();
     scatter<G, DEPTH>(s, t, op, nb);
     __syncthreads();
@@ -358,7 +364,7 @@ __device__ __forceinline__ void forward_walk(Stage<G>& s, const float4* __restri
     T = hit ? Tn : T;
     return hit;
   };
-  sweep<G, DEPTH, false, STOP>(s, rec, vals, rg, t, op, live, [](int, bool) {}, step,
+  sweep<G, DEPTH, false, STOP>(s, rec, nullptr, vals, rg, t, op, live, [](int, bool) {}, step,
                                [](int, bool, const float*) {});
 }
 
@@ -417,8 +423,9 @@ struct BwdArgs {
   const int32_t* n_valid;  // per view
   float lambda_d;
   float lambda_ssim;  // loss mode: the L1 colour term takes 1 - lambda_ssim; g_rgb (if given) is added
-  float* ipart;        // [instance][12], in emission order
-  const int32_t* emi;  // emission index of each sorted instance
+  float* ipart;              // [slot][12]: instance partials, each Gaussian's instances one run
+  const int32_t* rec_slot;   // first slot of each record; a record's tiles follow row by row
+  int64_t capacity;          // slots stored (a slot at or past it belongs to an overflowed frame)
   float* loss;
 };
 
@@ -502,17 +509,27 @@ __global__ void k_loss_total(float* __restrict__ loss) {
   }
 }
 
+// Partial slot of the instance of a record (pixel rectangle in C) in the tile at pixel origin (tx0, ty0): the
+// record's first slot plus the tile's index in the record's tile rectangle, row by row (the emission order).
+template <class G>
+__device__ __forceinline__ int64_t inst_slot(int first, const float4& C, const TileCtx& t) {
+  constexpr int TWp = 8 * G::SX, THp = 8 * G::SY;
+  int x0, x1, y0, y1;
+  unpack_rect(C, x0, x1, y0, y1);
+  const int rx0 = x0 / TWp, rx1 = x1 / TWp, ry0 = y0 / THp;
+  return (int64_t)first + (t.ty0 / THp - ry0) * (rx1 - rx0 + 1) + (t.tx0 / TWp - rx0);
+}
+
 // Store the LDS sums of this thread's staged records of the round that started at list position b0 (nb
-// records, still staged in s) as the partials of those instances (at their emission indices), and clear
-// them.  The sums are, over the record's contributing pixels (d = mean - pixel centre, dq = dL/dalpha alpha):
+// records, still staged in s) as the partials of those instances (at their slots), and clear them.  The sums are, over the record's contributing pixels (d = mean - pixel centre, dq = dL/dalpha alpha):
 //   dq dx, dq dy, dq dx^2, dq dx dy, dq dy^2, dL/dalpha G, w g_r, w g_g, w g_b, w g_d;
 // with the conic (a, b, c) of the record, power = -(a dx^2 + c dy^2)/2 - b dx dy gives
 //   dL/dmean = -(a S_x + b S_y, b S_x + c S_y),  dL/d(a, b, c) = -(S_xx / 2, S_xy, S_yy / 2).
 // Plain stores: every instance has exactly one writer (its tile or depth segment), so nothing is accumulated
 // in HBM.
 template <class G, int DEPTH>
-__device__ __forceinline__ void flush_grads(const Stage<G>& s, float (*gacc)[G::BATCH], float* __restrict__ ipart,
-                                            const int32_t* __restrict__ emi, int b0, int nb) {
+__device__ __forceinline__ void flush_grads(const Stage<G>& s, float (*gacc)[G::BATCH], const TileCtx& t,
+                                            float* __restrict__ ipart, int64_t capacity, int nb) {
 #pragma unroll
   for (int k = 0; k < DEPTH; ++k) {
     const int j = k * G::NT + (int)threadIdx.x;
@@ -533,10 +550,13 @@ __device__ __forceinline__ void flush_grads(const Stage<G>& s, float (*gacc)[G::
       v[3] = -v[3];
       v[4] = -0.5f * v[4];
     }
-    float4* dst = reinterpret_cast<float4*>(ipart) + 3 * (int64_t)emi[b0 + j];
-    dst[0] = make_float4(v[0], v[1], v[2], v[3]);
-    dst[1] = make_float4(v[4], v[5], v[6], v[7]);
-    dst[2] = make_float4(v[8], v[9], 0.f, 0.f);
+    const int64_t q = inst_slot<G>(s.slot[j], s.C[j], t);
+    if (q < capacity) {
+      float4* dst = reinterpret_cast<float4*>(ipart) + 3 * q;
+      dst[0] = make_float4(v[0], v[1], v[2], v[3]);
+      dst[1] = make_float4(v[4], v[5], v[6], v[7]);
+      dst[2] = make_float4(v[8], v[9], 0.f, 0.f);
+    }
     if (any) {
 #pragma unroll
       for (int q = 0; q < 10; ++q) gacc[q][j] = 0.f;
@@ -546,11 +566,15 @@ __device__ __forceinline__ void flush_grads(const Stage<G>& s, float (*gacc)[G::
 
 // Zero partials for the instances [b0, end) that the walk never staged (every pixel ended before them).
 template <class G>
-__device__ __forceinline__ void zero_grads(float* __restrict__ ipart, const int32_t* __restrict__ emi, int b0,
-                                           int end) {
+__device__ __forceinline__ void zero_grads(const float4* __restrict__ rec, const int32_t* __restrict__ vals,
+                                           const TileCtx& t, float* __restrict__ ipart,
+                                           const int32_t* __restrict__ rec_slot, int64_t capacity, int b0, int end) {
   const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
   for (int p = b0 + (int)threadIdx.x; p < end; p += G::NT) {
-    float4* dst = reinterpret_cast<float4*>(ipart) + 3 * (int64_t)emi[p];
+    const int64_t r = vals[p];
+    const int64_t q = inst_slot<G>(rec_slot[r], rec[3 * r + 2], t);
+    if (q >= capacity) continue;
+    float4* dst = reinterpret_cast<float4*>(ipart) + 3 * q;
     dst[0] = z;
     dst[1] = z;
     dst[2] = z;
@@ -565,8 +589,7 @@ template <class G, int DEPTH>
 __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATCH], const float4* __restrict__ rec,
                                               const int32_t* __restrict__ vals, int2 rg, const TileCtx& t,
                                               const DevOpts& op, bool live, float T, float Pp, float gr, float gg,
-                                              float gb, float gd, float gv, float S, float* __restrict__ ipart,
-                                              const int32_t* __restrict__ emi) {
+                                              float gb, float gd, float gv, float S, const BwdArgs& a) {
   const float fx = (float)t.px + 0.5f, fy = (float)t.py + 0.5f;
 #pragma unroll
   for (int k = 0; k < DEPTH; ++k)
@@ -671,13 +694,11 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
       }
     }
   };
-  sweep<G, DEPTH, true, true>(s, rec, vals, rg, t, op, live,
+  sweep<G, DEPTH, true, true>(s, rec, a.rec_slot, vals, rg, t, op, live,
                         [&](int b0, bool go) {
-                          if (b0 != rg.x) {
-                            const int p0 = b0 - G::BATCH;
-                            flush_grads<G, DEPTH>(s, gacc, ipart, emi, p0, min(G::BATCH, rg.y - p0));
-                          }
-                          if (!go) zero_grads<G>(ipart, emi, b0, rg.y);
+                          if (b0 != rg.x)
+                            flush_grads<G, DEPTH>(s, gacc, t, a.ipart, a.capacity, min(G::BATCH, rg.y - (b0 - G::BATCH)));
+                          if (!go) zero_grads<G>(rec, vals, t, a.ipart, a.rec_slot, a.capacity, b0, rg.y);
                         },
                         step, post);
 }
@@ -709,7 +730,7 @@ __device__ __forceinline__ void tile_backward(Stage<G>& s, float (*gacc)[G::BATC
   pixel_upstream<LOSS>(t, a, Cf, Gf, Bf, Df, gr, gg, gb, gd, gv, loss_acc);
   const float S = gr * Cf + gg * Gf + gb * Bf + gd * Df + gv * Vf;
   if (LOSS) add_loss<G>(t, a, loss_acc);
-  backward_walk<G, DEPTH>(s, gacc, rec, vals, rg, t, op, t.inside, 1.f, 0.f, gr, gg, gb, gd, gv, S, a.ipart, a.emi);
+  backward_walk<G, DEPTH>(s, gacc, rec, vals, rg, t, op, t.inside, 1.f, 0.f, gr, gg, gb, gd, gv, S, a);
 }
 
 template <int TW, int TH, int DEPTH, int BW, bool HAVE_FWD, bool LOSS>
@@ -1021,8 +1042,7 @@ __global__ __launch_bounds__(TW * TH) void k_seg_bwd(const float4* __restrict__ 
   const float Ts = sp[0], Ps = sp[1 * G::NT];
   backward_walk<G, DEPTH>(s, gacc, rec, vals, segment_range<G>(range[it.x], it.y, g.len), t, op,
                           t.inside && Ts >= op.t_min, Ts, Ps, xp[6 * G::NT], xp[7 * G::NT], xp[8 * G::NT],
-                          xp[9 * G::NT], xp[10 * G::NT], xp[11 * G::NT], a.ipart,
-                          a.emi);
+                          xp[9 * G::NT], xp[10 * G::NT], xp[11 * G::NT], a);
 }
 
 // Work counts of the forward: pairs evaluated (pixel inside the record's pixel rectangle, up to the
@@ -1093,8 +1113,18 @@ __global__ __launch_bounds__(256) void k_count_valid(const float* __restrict__ t
   const gs_camera& c = cams[v];
   const int64_t P = (int64_t)c.width * c.height;
   int cnt = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x)
-    cnt += tgt_depth[c.pixel_offset + i] > 0.f;
+  // eight independent loads in flight per thread and pass
+  const int64_t step = (int64_t)gridDim.x * blockDim.x * 8;
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x * 8 + threadIdx.x; b < P; b += step) {
+    float d[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int64_t i = b + k * (int64_t)blockDim.x;
+      d[k] = i < P ? tgt_depth[c.pixel_offset + i] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) cnt += d[k] > 0.f;
+  }
   for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d);
   if ((threadIdx.x & 63) == 0) atomicAdd(&sh, cnt);
   __syncthreads();
@@ -1269,7 +1299,8 @@ hipError_t render_bwd(const gs_frame& f, const gs_opts& o, const gs_images* fwd,
   a.lambda_d = l.lambda_d;
   a.lambda_ssim = l.lambda_ssim;
   a.ipart = f.ipart;
-  a.emi = f.vals[(f.sort_passes & 1) ^ 1];
+  a.rec_slot = f.rec_slot;
+  a.capacity = f.capacity;
   a.loss = f.loss;
   const bool loss = l.tgt_rgb != nullptr;
   GS_TILE_DISPATCH(launch_bwd, f, op, fwd != nullptr, loss, a, st);

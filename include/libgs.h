@@ -156,7 +156,8 @@ typedef struct gs_frame {
   uint32_t* zbits;      /* [n_views*n]: IEEE bits of the camera depth of each visible record */
   int32_t* rec_slot;    /* [n_views*n]: first partial slot of each visible record */
   int64_t rec_cap;      /* capacity of the record list: min(n_views * n, capacity) */
-  uint32_t* rkeys[2];   /* [rec_cap] record list: depth bits (sorted into rkeys[0]) */
+  uint32_t* rkeys[2];   /* [rec_cap] record list: depth bits while sorting; then each sorted record's tile
+                           rectangle, tx0 | tx1 << 16 in rkeys[0] and ty0 | ty1 << 16 in rkeys[1] */
   int32_t* rvals[2];    /* [rec_cap] record list: record ids (sorted into rvals[0]); rvals[1] then holds each
                            sorted record's first emission index */
   uint32_t* keys[2];    /* [capacity] instance keys: global tile ids (sorted into keys[sort_passes & 1]) */

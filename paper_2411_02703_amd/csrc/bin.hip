@@ -226,13 +226,15 @@ __global__ __launch_bounds__(256) void k_record_list(const uint64_t* __restrict_
                                                     uint32_t* __restrict__ rkeys, int32_t* __restrict__ rvals,
                                                     int32_t* __restrict__ rec_slot) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  uint64_t m = vis_mask[g];
-  int64_t c = first[g];
-  int32_t slot = inst_first[g];
-  while (m) {
-    const int v = __builtin_ctzll(m);
-    m &= m - 1;
+  const bool here = g < n;
+  const uint64_t m = here ? vis_mask[g] : 0ull;
+  int64_t c = here ? first[g] : 0;
+  int32_t slot = here ? inst_first[g] : 0;
+  // the wave takes the views together, so that the per-record reads and writes of one view are coalesced
+  for (int v = 0; v < V; ++v) {
+    const bool vis = (m >> v) & 1ull;
+    if (__ballot(vis) == 0) continue;
+    if (!vis) continue;
     const int64_t r = (int64_t)v * n + g;
     if (c < rcap) {
       rkeys[c] = zbits[r];
@@ -244,12 +246,17 @@ __global__ __launch_bounds__(256) void k_record_list(const uint64_t* __restrict_
   }
 }
 
-// Instance count of each depth-sorted record (its tile rectangle's area).
+// Instance count of each depth-sorted record (its tile rectangle's area), and the rectangle itself in sorted
+// order (tx0 | tx1 << 16 in rx[j], ty0 | ty1 << 16 in ry[j]) so that the emission reads it in coalesced runs.
 __global__ void k_record_counts(const int32_t* __restrict__ rvals, const short4* __restrict__ rect,
-                                const int32_t* __restrict__ counters, int64_t rcap, int32_t* __restrict__ cnt) {
+                                const int32_t* __restrict__ counters, int64_t rcap, int32_t* __restrict__ cnt,
+                                uint32_t* __restrict__ rx, uint32_t* __restrict__ ry) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= sort_count(counters + kRecCount, rcap, rcap)) return;
-  cnt[j] = rect_area(rect[rvals[j]]);
+  const short4 rc = rect[rvals[j]];
+  cnt[j] = rect_area(rc);
+  rx[j] = (uint32_t)(uint16_t)rc.x | ((uint32_t)(uint16_t)rc.y << 16);
+  ry[j] = (uint32_t)(uint16_t)rc.z | ((uint32_t)(uint16_t)rc.w << 16);
 }
 
 // The instance total summed from the per-Gaussian counts (one atomic per workgroup into counters[kInstSum]), so
@@ -287,7 +294,8 @@ __device__ __forceinline__ int64_t read_lane64(int64_t x, int l) {
 // One thread per depth-sorted record: its run of instances (tiles row by row) starts at eo[j]; key = global tile
 // id, value = record id.  Records with more than kSolo tiles are written by the whole wave, a tile per lane.
 __global__ __launch_bounds__(256) void k_emit(const int32_t* __restrict__ rvals, const int32_t* __restrict__ eo,
-                                             const short4* __restrict__ rect, const gs_camera* __restrict__ cams,
+                                             const uint32_t* __restrict__ rx, const uint32_t* __restrict__ ry,
+                                             const gs_camera* __restrict__ cams,
                                              int V, int64_t n, const int32_t* __restrict__ counters, int64_t rcap,
                                              int64_t capacity, uint32_t* __restrict__ keys,
                                              int32_t* __restrict__ vals) {
@@ -301,8 +309,9 @@ __global__ __launch_bounds__(256) void k_emit(const int32_t* __restrict__ rvals,
   if (here) {
     r = rvals[j];
     o = eo[j];
-    rc = rect[r];
-    const int v = (int)(r / n);
+    const uint32_t x = rx[j], y = ry[j];
+    rc = make_short4((short)(x & 0xffffu), (short)(x >> 16), (short)(y & 0xffffu), (short)(y >> 16));
+    const int v = (int)((uint32_t)r / (uint32_t)n);  // r < 2^31
     toff = cams[v].tile_offset;
     tx_n = cams[v].tiles_x;
   }
@@ -507,9 +516,9 @@ hipError_t sort_pairs32(uint32_t* k0, int32_t* v0, uint32_t* k1, int32_t* v1, in
   return sort_impl<uint32_t>(k0, v0, k1, v1, n_sized, count_dev, cap, key_bits, scratch, st);
 }
 
-// Binning up to the instance total: the records' first partial slots, the record list sorted by depth (in
-// rkeys[0] / rvals[0]), each sorted record's instance count (in rkeys[1], as int32) and its first emission index
-// (in rvals[1]), the instance total and the overflow flag.
+// Binning up to the instance total: the records' first partial slots, the record list sorted by depth (record ids
+// in rvals[0]), each sorted record's tile rectangle (rkeys[0], rkeys[1]) and first emission index (rvals[1]), the
+// instance total and the overflow flag.
 hipError_t bin_records(const gs_frame& f, hipStream_t st) {
   const int64_t rcap = f.rec_cap;
   hipError_t e = fill_i32(f.counters + kInstSum, 0, 1, st);
@@ -529,21 +538,22 @@ hipError_t bin_records(const gs_frame& f, hipStream_t st) {
   if ((e = sort_pairs32(f.rkeys[0], f.rvals[0], f.rkeys[1], f.rvals[1], rcap, f.counters + kRecCount, rcap, 32,
                         f.scratch, st)) != hipSuccess)
     return e;  // 4 passes: the sorted records are back in rkeys[0] / rvals[0]
-  int32_t* cnt = reinterpret_cast<int32_t*>(f.rkeys[1]);
+  // counts straight into rvals[1], scanned in place into the emission offsets; the sorted rectangles take the
+  // depth keys' buffers, which are no longer needed
   k_record_counts<<<(unsigned)cdiv(rcap, 256), 256, 0, st>>>(f.rvals[0], reinterpret_cast<const short4*>(f.rect),
-                                                             f.counters, rcap, cnt);
+                                                             f.counters, rcap, f.rvals[1], f.rkeys[0], f.rkeys[1]);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = scan_exclusive(cnt, f.rvals[1], rcap, f.scratch, st, DevCount{f.counters + kRecCount, rcap, 1, 1})) !=
-      hipSuccess)
+  if ((e = scan_exclusive(f.rvals[1], f.rvals[1], rcap, f.scratch, st,
+                          DevCount{f.counters + kRecCount, rcap, 1, 1})) != hipSuccess)
     return e;
   k_instance_total<<<1, 1, 0, st>>>(f.capacity, f.counters);
   return hipGetLastError();
 }
 
 hipError_t emit(const gs_frame& f, int64_t /*n_sized*/, hipStream_t st) {
-  k_emit<<<(unsigned)cdiv(f.rec_cap, 256), 256, 0, st>>>(f.rvals[0], f.rvals[1],
-                                                         reinterpret_cast<const short4*>(f.rect), f.cams, f.n_views,
-                                                         f.n, f.counters, f.rec_cap, f.capacity, f.keys[0], f.vals[0]);
+  k_emit<<<(unsigned)cdiv(f.rec_cap, 256), 256, 0, st>>>(f.rvals[0], f.rvals[1], f.rkeys[0], f.rkeys[1], f.cams,
+                                                         f.n_views, f.n, f.counters, f.rec_cap, f.capacity, f.keys[0],
+                                                         f.vals[0]);
   return hipGetLastError();
 }
 

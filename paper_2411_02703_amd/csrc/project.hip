@@ -353,6 +353,11 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
   // undefined) are not read.
   const int64_t n_stored = min((int64_t)count_dev[0], capacity);
   int64_t run = mask != 0 ? inst_first[g] : 0;
+  // the tile rectangle of this lane's next visible view is fetched one visible view ahead, so that the partial
+  // loads of a view do not wait for it
+  uint64_t rest = mask;
+  short4 rc_next = make_short4(0, -1, 0, -1);
+  if (rest) rc_next = rect[(int64_t)__builtin_ctzll(rest) * n + g];
   for (int v = 0; v < V; ++v) {
     const bool vis = (mask >> v) & 1ull;
     if (__ballot(vis) == 0) continue;
@@ -361,7 +366,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
     int cnt = 0;
     int64_t i = 0;
     if (vis) {
-      const short4 rc = rect[r];
+      const short4 rc = rc_next;  // bit v is the lowest bit of rest
+      rest &= rest - 1;
+      if (rest) rc_next = rect[(int64_t)__builtin_ctzll(rest) * n + g];
       cnt = (rc.y - rc.x + 1) * (rc.w - rc.z + 1);
       i = run;
       run += cnt;

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GS_VERSION 3
+#define GS_VERSION 4
 #define GS_MAX_VIEWS 64
 
 typedef enum {
@@ -147,7 +147,9 @@ typedef struct gs_frame {
                            record), the compositing backward's partial
                            dL/d{mu_x, mu_y, a, b, c, o, red, green, blue, z} of its record summed over the
                            pixels of its tile (or depth segment); 2 words of padding.  Every backward call
-                           writes every stored instance once (plain stores, no atomics) */
+                           writes every stored instance once (plain stores, no atomics).  The projection
+                           backward first sums each record of big_rec into its first slot and sets that slot's
+                           last word to 1 */
   int32_t* inst_first;  /* [n]: exclusive scan of n_inst: the first partial slot of Gaussian g */
   uint64_t* vis_mask;   /* [n]: bit v set if Gaussian g is visible in view v */
   int32_t* n_inst;      /* [n]: tile instances of Gaussian g over all views */
@@ -155,6 +157,8 @@ typedef struct gs_frame {
   int32_t* rec_first;   /* [n]: exclusive scan of n_rec: where g's records start in the record list */
   uint32_t* zbits;      /* [n_views*n]: IEEE bits of the camera depth of each visible record */
   int32_t* rec_slot;    /* [n_views*n]: first partial slot of each visible record */
+  int32_t* big_rec;     /* [rec_cap]: the records with more than 32 tile instances (count in counters[198]); the
+                           projection backward first sums each one's partials into its first slot */
   int64_t rec_cap;      /* capacity of the record list: min(n_views * n, capacity) */
   uint32_t* rkeys[2];   /* [rec_cap] record list: depth bits while sorting; then each sorted record's tile
                            rectangle, tx0 | tx1 << 16 in rkeys[0] and ty0 | ty1 << 16 in rkeys[1] */
@@ -168,7 +172,7 @@ typedef struct gs_frame {
   int32_t* counters;    /* [256]: [0] instance count, [1] flags, [2..2+n_views) valid depth pixels per view,
                            [128..192) tile-length bucket counts and offsets, [192] work items,
                            [193] segment slots of split tiles, [194] split tiles, [196] visible records,
-                           [197] instances summed per Gaussian */
+                           [197] instances summed per Gaussian, [198] records with more than 32 instances */
   int32_t* seg_count;   /* [n_tiles]: segments of the tile at each schedule position */
   int32_t* seg_first;   /* [n_tiles]: exclusive scan of seg_count = first work item of that tile */
   int32_t* items;       /* [item_cap][4]: work items of the compositing calls, split tiles first:

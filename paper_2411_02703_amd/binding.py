@@ -49,7 +49,7 @@ class gs_frame(ctypes.Structure):
                 ("tile_w", c_i32), ("tile_h", c_i32), ("seg_len", c_i32), ("seg_cap", c_i32), ("long_cap", c_i32),
                 ("item_cap", c_i32), ("cams", c_vp), ("block", c_vp), ("bytes", ctypes.c_size_t),
                 ("rec", c_vp), ("rect", c_vp), ("ipart", c_vp), ("inst_first", c_vp), ("vis_mask", c_vp),
-                ("n_inst", c_vp), ("n_rec", c_vp), ("rec_first", c_vp), ("zbits", c_vp), ("rec_slot", c_vp), ("rec_cap", c_i64),
+                ("n_inst", c_vp), ("n_rec", c_vp), ("rec_first", c_vp), ("zbits", c_vp), ("rec_slot", c_vp), ("big_rec", c_vp), ("rec_cap", c_i64),
                 ("rkeys", c_vp * 2), ("rvals", c_vp * 2), ("keys", c_vp * 2), ("vals", c_vp * 2), ("tile_range", c_vp),
                 ("tile_order", c_vp), ("counters", c_vp), ("seg_count", c_vp), ("seg_first", c_vp), ("items", c_vp),
                 ("seg", c_vp), ("split", c_vp), ("loss", c_vp), ("scratch", c_vp), ("scratch_ints", ctypes.c_size_t)]

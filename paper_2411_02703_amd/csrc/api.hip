@@ -39,7 +39,7 @@ bool tiles_supported(int tw, int th) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t rec, rect, ipart, instfirst, mask, ninst, nrec, instoff, zbits, recslot, rk[2], rv[2], k0, k1, v0, v1, range, order,
+  size_t rec, rect, ipart, instfirst, mask, ninst, nrec, instoff, zbits, recslot, bigrec, rk[2], rv[2], k0, k1, v0, v1, range, order,
       counters, loss, scratch, total;
   int64_t rec_cap;
   size_t segcount, segfirst, items, seg, split;
@@ -114,6 +114,7 @@ Layout make_layout(int64_t n, int V, int n_tiles, int64_t cap, const gs_opts* op
   L.zbits = take(R * 4);
   L.recslot = take(R * 4);
   L.rec_cap = (int64_t)R < cap ? (int64_t)R : cap;
+  L.bigrec = take((size_t)L.rec_cap * 4);
   for (int k = 0; k < 2; ++k) {
     L.rk[k] = take((size_t)L.rec_cap * 4);
     L.rv[k] = take((size_t)L.rec_cap * 4);
@@ -299,6 +300,7 @@ int gs_frame_init(gs_frame* f, void* block, size_t bytes, int64_t n, const gs_ca
   f->rec_first = reinterpret_cast<int32_t*>(b + L.instoff);
   f->zbits = reinterpret_cast<uint32_t*>(b + L.zbits);
   f->rec_slot = reinterpret_cast<int32_t*>(b + L.recslot);
+  f->big_rec = reinterpret_cast<int32_t*>(b + L.bigrec);
   f->rec_cap = L.rec_cap;
   for (int k = 0; k < 2; ++k) {
     f->rkeys[k] = reinterpret_cast<uint32_t*>(b + L.rk[k]);

@@ -217,14 +217,18 @@ __global__ void k_record_total(const int32_t* __restrict__ n_rec, const int32_t*
 __device__ __forceinline__ int rect_area(const short4 rc) { return (rc.y - rc.x + 1) * (rc.w - rc.z + 1); }
 
 // ... and each visible record's first partial slot: inst_first[g] plus the instances of g's records in the views
-// before it.
+// before it; wide records (more than kWideRecord tiles) are appended to big_rec (count in counters[kBigCount],
+// one atomic per wave; the list order is not fixed, which nothing depends on).
+constexpr int kBigCount = 198;
+
 __global__ __launch_bounds__(256) void k_record_list(const uint64_t* __restrict__ vis_mask,
                                                     const int32_t* __restrict__ first,
                                                     const int32_t* __restrict__ inst_first,
                                                     const short4* __restrict__ rect,
                                                     const uint32_t* __restrict__ zbits, int V, int64_t n, int64_t rcap,
                                                     uint32_t* __restrict__ rkeys, int32_t* __restrict__ rvals,
-                                                    int32_t* __restrict__ rec_slot) {
+                                                    int32_t* __restrict__ rec_slot, int32_t* __restrict__ big_rec,
+                                                    int32_t* __restrict__ counters) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool here = g < n;
   const uint64_t m = here ? vis_mask[g] : 0ull;
@@ -242,7 +246,18 @@ __global__ __launch_bounds__(256) void k_record_list(const uint64_t* __restrict_
     }
     ++c;
     rec_slot[r] = slot;
-    slot += rect_area(rect[r]);
+    const int area = rect_area(rect[r]);
+    slot += area;
+    const bool wide = area > gsk::kWideRecord;
+    const uint64_t wb = __ballot(wide);
+    if (wb) {
+      const int lead = __builtin_ctzll(wb);
+      int base = 0;
+      if (__lane_id() == lead) base = atomicAdd(counters + kBigCount, __popcll(wb));
+      base = __builtin_amdgcn_readlane(base, lead);
+      const int pos = base + __popcll(wb & gsk::lanemask_lt());
+      if (wide && pos < rcap) big_rec[pos] = (int32_t)r;
+    }
   }
 }
 
@@ -282,8 +297,8 @@ __global__ void k_instance_total(int64_t capacity, int32_t* __restrict__ counter
   if (total > capacity) atomicOr(counters + 1, GS_FLAG_INSTANCE_OVERFLOW);
 }
 
-// Records with more tiles than this are emitted (and their partials summed) by a whole wave, a tile per lane.
-constexpr int kSolo = 32;
+// Records with more tiles than this are emitted by a whole wave, a tile per lane.
+constexpr int kSolo = gsk::kWideRecord;
 
 __device__ __forceinline__ int64_t read_lane64(int64_t x, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
@@ -521,7 +536,7 @@ hipError_t sort_pairs32(uint32_t* k0, int32_t* v0, uint32_t* k1, int32_t* v1, in
 // instance total and the overflow flag.
 hipError_t bin_records(const gs_frame& f, hipStream_t st) {
   const int64_t rcap = f.rec_cap;
-  hipError_t e = fill_i32(f.counters + kInstSum, 0, 1, st);
+  hipError_t e = fill_i32(f.counters + kInstSum, 0, 2, st);  // kInstSum, kBigCount
   if (e != hipSuccess) return e;
   int64_t nb = cdiv(f.n, 256);
   if (nb > 1024) nb = 1024;
@@ -533,7 +548,8 @@ hipError_t bin_records(const gs_frame& f, hipStream_t st) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_record_list<<<(unsigned)cdiv(f.n, 256), 256, 0, st>>>(f.vis_mask, f.rec_first, f.inst_first,
                                                           reinterpret_cast<const short4*>(f.rect), f.zbits, f.n_views,
-                                                          f.n, rcap, f.rkeys[0], f.rvals[0], f.rec_slot);
+                                                          f.n, rcap, f.rkeys[0], f.rvals[0], f.rec_slot, f.big_rec,
+                                                          f.counters);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = sort_pairs32(f.rkeys[0], f.rvals[0], f.rkeys[1], f.rvals[1], rcap, f.counters + kRecCount, rcap, 32,
                         f.scratch, st)) != hipSuccess)

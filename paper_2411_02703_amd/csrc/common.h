@@ -102,6 +102,11 @@ __device__ __forceinline__ float read_lane(float x, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
 
+// Records with more tile instances than this are wide: binning emits them a tile per lane of a wave and lists
+// them (frame counters[198], big_rec), and their instance partials are summed by a wave per record before the
+// projection backward, which then reads one pre-summed partial for them.
+constexpr int kWideRecord = 32;
+
 // Hardware float atomic add without return (global_atomic_add_f32).
 __device__ __forceinline__ void atomic_add_f32(float* p, float v) { unsafeAtomicAdd(p, v); }
 

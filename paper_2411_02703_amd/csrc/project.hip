@@ -268,8 +268,46 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ means
   n_inst[g] = inst;
 }
 
-// Records with more tiles than this have their instance partials summed by the whole wave.
-constexpr int kSolo = 32;
+// The partials of each wide record (more than kWideRecord tile instances), summed by a wave per record into the
+// record's first slot; the padding word of that slot is set to 1 to mark the sum, so that a second projection
+// backward of the same compositing output does not sum it again (the compositing writes 0 there).  Waves take
+// the listed records in a grid-stride loop.
+__global__ __launch_bounds__(256) void k_sum_wide(float4* __restrict__ ipart, const int32_t* __restrict__ big_rec,
+                                                  const short4* __restrict__ rect,
+                                                  const int32_t* __restrict__ rec_slot,
+                                                  const int32_t* __restrict__ counters, int64_t rcap,
+                                                  int64_t capacity) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nbig = min((int64_t)counters[198], rcap);
+  const int64_t n_stored = min((int64_t)counters[0], capacity);
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t b = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); b < nbig; b += waves) {
+    const int32_t r = big_rec[b];
+    const short4 rc = rect[r];
+    const int cnt = (rc.y - rc.x + 1) * (rc.w - rc.z + 1);
+    const int64_t i = rec_slot[r];
+    if (i < 0 || i >= n_stored || ipart[3 * i + 2].w != 0.f) continue;  // not stored, or already summed
+    float sm[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) sm[k] = 0.f;
+    for (int k = lane; k < cnt && i + k < n_stored; k += 64) {
+      const float4* pp = ipart + 3 * (i + k);
+      const float4 a0 = pp[0], a1 = pp[1], a2 = pp[2];
+      sm[0] += a0.x; sm[1] += a0.y; sm[2] += a0.z; sm[3] += a0.w;
+      sm[4] += a1.x; sm[5] += a1.y; sm[6] += a1.z; sm[7] += a1.w;
+      sm[8] += a2.x; sm[9] += a2.y;
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) sm[k] = gsk::wave_sum_last(sm[k]);
+    // every lane has read its instances of the record before the sum is written over the first one
+    __builtin_amdgcn_wave_barrier();
+    if (lane == 63) {
+      ipart[3 * i + 0] = make_float4(sm[0], sm[1], sm[2], sm[3]);
+      ipart[3 * i + 1] = make_float4(sm[4], sm[5], sm[6], sm[7]);
+      ipart[3 * i + 2] = make_float4(sm[8], sm[9], 0.f, 1.f);
+    }
+  }
+}
 
 // Adam's part of the fused backward: moments and parameters of one Gaussian, updated in place (the same
 // update as the separate Adam step: bias-corrected moments, eps added to the corrected root).
@@ -348,9 +386,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
   for (int i = 0; i < F; ++i) gf[i] = 0.f;
 
   // this Gaussian's instances: one contiguous run of partial slots from inst_first[g], view by view (each
-  // visible record's tiles in turn).  The lanes take the views together; a record with more than kSolo tiles
-  // is summed by the whole wave.  Slots outside the stored instances (an overflowed frame, whose gradient is
-  // undefined) are not read.
+  // visible record's tiles in turn).  The lanes take the views together; a wide record (more than kWideRecord
+  // tiles) has its partials pre-summed into its first slot (k_sum_wide), so one slot is read for it.  Slots
+  // outside the stored instances (an overflowed frame, whose gradient is undefined) are not read.
   const int64_t n_stored = min((int64_t)count_dev[0], capacity);
   int64_t run = mask != 0 ? inst_first[g] : 0;
   // the tile rectangle of this lane's next visible view is fetched one visible view ahead, so that the partial
@@ -372,6 +410,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
       cnt = (rc.y - rc.x + 1) * (rc.w - rc.z + 1);
       i = run;
       run += cnt;
+      if (cnt > gsk::kWideRecord) cnt = 1;
       if (i < 0 || i >= n_stored) cnt = 0;
     }
     // the record's gradient: the sum of its instances' partials over the tiles it covers (a contiguous run,
@@ -383,7 +422,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
       q1.x += a1.x; q1.y += a1.y; q1.z += a1.z; q1.w += a1.w;
       q2.x += a2.x; q2.y += a2.y;
     };
-    if (vis && cnt <= kSolo) {
+    if (vis) {
       int64_t j = i;
       const int64_t j_stop = min(i + cnt, n_stored);
       for (; j + 4 <= j_stop; j += 4) {
@@ -395,32 +434,6 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
         for (int k = 0; k < 4; ++k) add(b + 3 * k);
       }
       for (; j < j_stop; ++j) add(ipart + 3 * j);
-    }
-    uint64_t big = __ballot(cnt > kSolo);
-    while (big) {
-      const int L = __builtin_ctzll(big);
-      big &= big - 1;
-      const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)i, L);
-      const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)i >> 32), L);
-      const int64_t iL = (int64_t)(((uint64_t)hi << 32) | lo);
-      const int cL = __builtin_amdgcn_readlane(cnt, L);
-      float sm[10];
-#pragma unroll
-      for (int k = 0; k < 10; ++k) sm[k] = 0.f;
-      for (int k = lane; k < cL && iL + k < n_stored; k += 64) {
-        const float4* pp = ipart + 3 * (iL + k);
-        const float4 a0 = pp[0], a1 = pp[1], a2 = pp[2];
-        sm[0] += a0.x; sm[1] += a0.y; sm[2] += a0.z; sm[3] += a0.w;
-        sm[4] += a1.x; sm[5] += a1.y; sm[6] += a1.z; sm[7] += a1.w;
-        sm[8] += a2.x; sm[9] += a2.y;
-      }
-#pragma unroll
-      for (int k = 0; k < 10; ++k) sm[k] = gsk::read_lane(gsk::wave_sum_last(sm[k]), 63);
-      if (lane == L) {
-        q0 = make_float4(sm[0], sm[1], sm[2], sm[3]);
-        q1 = make_float4(sm[4], sm[5], sm[6], sm[7]);
-        q2 = make_float4(sm[8], sm[9], 0.f, 0.f);
-      }
     }
     if (!vis) continue;
     const float dmx = q0.x, dmy = q0.y, da = q0.z, db = q0.w;
@@ -644,6 +657,10 @@ static hipError_t project_bwd_launch(const gs_params& p, const gs_frame& f, cons
   float* gq = gr ? gr->quats : nullptr;
   float* go = gr ? gr->opacity : nullptr;
   float* gsh = gr ? gr->sh : nullptr;
+  k_sum_wide<<<1024, 256, 0, st>>>(reinterpret_cast<float4*>(f.ipart), f.big_rec, rect, f.rec_slot, f.counters,
+                                   f.rec_cap, f.capacity);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
 #define GS_PB(D)                                                                                              \
   k_project_bwd<D, ADAM><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n,     \
                                                      f.cams, f.n_views, op, ip, f.inst_first, rect, f.counters,    \

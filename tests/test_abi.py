@@ -45,7 +45,7 @@ def test_struct_layouts(lib):
     assert ctypes.sizeof(B.gs_opts) == 64
     assert ctypes.sizeof(B.gs_params) == 56
     assert ctypes.sizeof(B.gs_adam) == 64
-    assert lib.gs_version() == 3
+    assert lib.gs_version() == 4
 
 
 def test_default_opts_and_status_strings(lib):
@@ -94,8 +94,8 @@ def test_frame_layout_on_host(lib):
     f = B.gs_frame()
     base = 1 << 20  # carving is pure host arithmetic: any 256-aligned address works
     assert lib.gs_frame_init(ctypes.byref(f), base, nbytes, n, arr, base, 2, ctypes.byref(o), cap) == 0
-    ptrs = sorted([f.rec, f.rect, f.ipart, f.inst_first, f.vis_mask, f.n_inst, f.n_rec, f.rec_first, f.zbits, f.rec_slot,
-                   f.rkeys[0], f.rkeys[1], f.rvals[0], f.rvals[1], f.keys[0], f.keys[1], f.vals[0],
+    ptrs = sorted([f.rec, f.rect, f.ipart, f.inst_first, f.vis_mask, f.n_inst, f.n_rec, f.rec_first, f.zbits,
+                   f.rec_slot, f.big_rec, f.rkeys[0], f.rkeys[1], f.rvals[0], f.rvals[1], f.keys[0], f.keys[1], f.vals[0],
                    f.vals[1], f.tile_range, f.counters, f.seg_count, f.seg_first, f.items, f.seg, f.split, f.loss,
                    f.scratch])
     assert len(set(ptrs)) == len(ptrs)

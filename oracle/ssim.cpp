@@ -76,9 +76,9 @@ void oracle_ssim_window(double* out) {
 double oracle_ssim_plane(const double* x, const double* y, int H, int W, double* map, double* grad) {
   const std::vector<double> w = window();
   const int64_t P = (int64_t)H * W;
-  double total = 0.0;
   std::vector<double> A(P), Bc(P), Cc(P);  // dS/dmu_x, dS/dE_xx, dS/dE_xy per output pixel
-#pragma omp parallel for reduction(+ : total) schedule(static)
+  std::vector<double> row_total(H, 0.0);    // per-row sums, added in row order below (a fixed summation order)
+#pragma omp parallel for schedule(static)
   for (int py = 0; py < H; ++py)
     for (int px = 0; px < W; ++px) {
       const Stats s = stats_at(x, y, H, W, py, px, w);
@@ -89,7 +89,7 @@ double oracle_ssim_plane(const double* x, const double* y, int H, int W, double*
       const double S = a1 * b1 / d;
       const int64_t p = (int64_t)py * W + px;
       if (map) map[p] = S;
-      total += S;
+      row_total[py] += S;
       // S = a1 b1 / (a2 b2) as a function of (mu_x, E_xx, E_xy) with the y sums fixed:
       //   d a1/d mu_x = 2 mu_y, d b1/d mu_x = -2 mu_y, d a2/d mu_x = 2 mu_x, d b2/d mu_x = -2 mu_x,
       //   d b2/d E_xx = 1, d b1/d E_xy = 2
@@ -97,6 +97,8 @@ double oracle_ssim_plane(const double* x, const double* y, int H, int W, double*
       Bc[p] = -S / b2;
       Cc[p] = 2.0 * a1 / d;
     }
+  double total = 0.0;
+  for (int py = 0; py < H; ++py) total += row_total[py];
   if (grad) {
     // d mean / d x(q) = (1/P) sum_p w(q - p) [A(p) + 2 x(q) B(p) + y(q) C(p)] over the p whose window holds q
 #pragma omp parallel for schedule(static)

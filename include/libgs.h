@@ -154,7 +154,8 @@ typedef struct gs_frame {
   uint64_t* vis_mask;   /* [n]: bit v set if Gaussian g is visible in view v */
   int32_t* n_inst;      /* [n]: tile instances of Gaussian g over all views */
   int32_t* n_rec;       /* [n]: visible records (views) of Gaussian g */
-  int32_t* rec_first;   /* [n]: exclusive scan of n_rec: where g's records start in the record list */
+  int32_t* rec_first;   /* [n]: exclusive scan of n_rec; the records of the 64 Gaussians from g (g a multiple of
+                           64) start at rec_first[g] in the record list */
   uint32_t* zbits;      /* [n_views*n]: IEEE bits of the camera depth of each visible record */
   int32_t* rec_slot;    /* [n_views*n]: first partial slot of each visible record */
   int32_t* big_rec;     /* [rec_cap]: the records with more than 32 tile instances (count in counters[198]); the
@@ -244,8 +245,8 @@ int gs_project(const gs_params* params, const gs_frame* frame, const gs_opts* op
 
 /* Tile binning (Section III-B: rasterisation iterates over the Gaussians rather than along camera rays, and
  * eq. Cp composites them in depth order, the product over j < i running over the Gaussians in front).  The
- * visible records are sorted by depth (stable LSD radix sort of their 32-bit depth bits, records listed
- * Gaussian by Gaussian), emitted in that order as runs of tile instances, and the instances sorted by global
+ * visible records are sorted by depth (stable LSD radix sort of their 32-bit depth bits, the records of each view
+ * listed in Gaussian order), emitted in that order as runs of tile instances, and the instances sorted by global
  * tile id (stable): within a tile the order is ascending depth, ties by record index, which makes the sorted
  * order unique; per-tile ranges and the compositing schedule follow.  Errors: GS_ERR_ARG for an uninitialised
  * frame or options that do not match it; more instances than the capacity set GS_FLAG_INSTANCE_OVERFLOW

@@ -1,9 +1,9 @@
 // Tile binning (integer work, bit-exact by construction).  The order inside a tile is ascending depth bits, ties
 // by record index, so the sorted order is unique.  Two stable LSD radix sorts (8-bit digits) reach it:
-//   1. the visible records, listed Gaussian by Gaussian, are sorted by their 32-bit depth bits (4 passes over
-//      the records, not the instances);
+//   1. the visible records, listed wave by wave and view by view (Gaussians ascending inside a view), are sorted
+//      by their 32-bit depth bits (4 passes over the records, not the instances);
 //   2. the records are emitted in that order, each as its run of tile instances (key = global tile id, value =
-//      emission index), and the instances are sorted by tile (2 passes at up to 65,536 tiles).
+//      record id), and the instances are sorted by tile (2 passes at up to 65,536 tiles).
 // A stable sort by tile of a depth-ordered sequence is the (tile, depth, record) order; ties in depth keep
 // ascending Gaussian index inside a view (the records of one view are listed in Gaussian order), and records
 // of different views never share a tile.  The sorted value of an instance is its record id.
@@ -204,7 +204,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const KeyT* __res
 }
 
 // ------------------------------------------------------------------ the record list and the emission
-// Visible records listed Gaussian by Gaussian (views ascending): key = depth bits, value = record id.  The count
+// Visible records listed wave by wave (64 consecutive Gaussians), view by view inside a wave, Gaussians ascending
+// inside a view: key = depth bits, value = record id.  The count
 // R goes to counters[kRecCount] (entries past the record capacity are not written; R > capacity implies more
 // instances than the instance capacity, which the instance total flags).
 constexpr int kRecCount = 196;
@@ -232,19 +233,26 @@ __global__ __launch_bounds__(256) void k_record_list(const uint64_t* __restrict_
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool here = g < n;
   const uint64_t m = here ? vis_mask[g] : 0ull;
-  int64_t c = here ? first[g] : 0;
+  // The wave's records start where its first Gaussian's do (the scan of the record counts) and are listed view
+  // by view, each view's records in lane (Gaussian) order, so that every read and write of a view is one
+  // coalesced run.  Within a view the list keeps ascending Gaussian index, which is all the depth sort's tie rule
+  // needs (records of different views never share a tile).
+  const int64_t g0 = g - __lane_id();
+  int64_t c = __builtin_amdgcn_readfirstlane((int)(g0 < n ? first[g0] : 0));
   int32_t slot = here ? inst_first[g] : 0;
-  // the wave takes the views together, so that the per-record reads and writes of one view are coalesced
+  const uint64_t lt = gsk::lanemask_lt();
   for (int v = 0; v < V; ++v) {
     const bool vis = (m >> v) & 1ull;
-    if (__ballot(vis) == 0) continue;
+    const uint64_t vb = __ballot(vis);
+    if (vb == 0) continue;
+    const int64_t pos = c + __popcll(vb & lt);
+    c += __popcll(vb);
     if (!vis) continue;
     const int64_t r = (int64_t)v * n + g;
-    if (c < rcap) {
-      rkeys[c] = zbits[r];
-      rvals[c] = (int32_t)r;
+    if (pos < rcap) {
+      rkeys[pos] = zbits[r];
+      rvals[pos] = (int32_t)r;
     }
-    ++c;
     rec_slot[r] = slot;
     const int area = rect_area(rect[r]);
     slot += area;
@@ -255,8 +263,8 @@ __global__ __launch_bounds__(256) void k_record_list(const uint64_t* __restrict_
       int base = 0;
       if (__lane_id() == lead) base = atomicAdd(counters + kBigCount, __popcll(wb));
       base = __builtin_amdgcn_readlane(base, lead);
-      const int pos = base + __popcll(wb & gsk::lanemask_lt());
-      if (wide && pos < rcap) big_rec[pos] = (int32_t)r;
+      const int bpos = base + __popcll(wb & lt);
+      if (wide && bpos < rcap) big_rec[bpos] = (int32_t)r;
     }
   }
 }

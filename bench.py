@@ -66,6 +66,31 @@ def spatial_order(model) -> float:
     return s.elapsed_time(e)
 
 
+def persistent_step_ms(sc, tile, steps, warmup):
+    """The same batched step with the compositing backward's walking kernels launched as persistent grids
+    (resident workgroups taking the work items from an atomic counter) instead of one workgroup per item."""
+    import torch
+
+    from paper_2411_02703_amd import binding as B
+    from paper_2411_02703_amd.step import BatchedStep, GaussianModel
+
+    model = GaussianModel(sc.params(), sc.sh_degree)
+    spatial_order(model)
+    opts = B.default_opts(tile_w=tile[0], tile_h=tile[1], batch_depth=tile[2], block_w=tile[3], seg_len=tile[4],
+                          persistent=1)
+    bat = BatchedStep(model, sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=opts)
+    bat.capture()
+    for _ in range(warmup):
+        bat.run()
+    bat.finish()
+    ms = timed(bat.run, steps, torch.cuda.current_stream())
+    bat.finish()
+    del bat, model
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return ms
+
+
 def measure(sc, steps, warmup, plain_steps, do_plain, tile=None, peak=False):
     """Autotune (unless tile is given), then time the batched step and optionally the plain sequence; with
     peak, also the peak device memory of each (torch allocations, which hold every library buffer)."""
@@ -274,6 +299,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="skip timing the persistent-grid variant of the compositing launches")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-cfg3", action="store_true")
     ap.add_argument("--no-cfg5", action="store_true",
@@ -313,6 +340,10 @@ def main():
     stg = stage_times(r4, args.steps)
     for k, v in stg["stages"].items():
         log(f"  stage {k}: {v['ms']:.3f} ms, roofline {v['roofline_ms']:.3f} ms ({v['frac']:.3f})")
+    pers_ms = None
+    if not args.no_persistent and r4["tile"][4] >= 0:
+        pers_ms = persistent_step_ms(sc4, r4["tile"], args.steps, args.warmup)
+        log(f"  persistent compositing launches: {pers_ms:.3f} ms/step (work-item grids {r4['ms']:.3f})")
     if args.copy_calib > 0:
         src = torch.ones(args.copy_calib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -343,6 +374,10 @@ def main():
                    "layout": "Gaussians in Morton order of their means (one-time reorder, "
                              f"{r4['order_ms']:.2f} ms, outside the timed steps)"},
     }
+    if pers_ms is not None:
+        out["persistent_launch"] = {"ms_per_step": round(pers_ms, 4), "over_work_item_grids": round(pers_ms / r4["ms"], 3),
+                                    "scheme": "walking kernels as grids of resident workgroups taking work items "
+                                              "from an atomic counter (timed as a departure check; not the default)"}
     if "plain_ms" in r4:
         out["plain"] = {"value": round(1000.0 / r4["plain_ms"], 3), "ms_per_step": round(r4["plain_ms"], 4),
                         "steps": args.plain_steps}

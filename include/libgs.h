@@ -102,7 +102,10 @@ typedef struct gs_opts {
                              joined per pixel (transmittance products, then prefix sums); 0 = default 512,
                              < 0 = never split.  Fixed per frame by gs_frame_init.  Results agree with the
                              unsplit walk up to FP32 rounding of the transmittance product */
-  int32_t reserved[1];
+  int32_t persistent;     /* compositing backward with split lists: 0 = one workgroup per work item (default);
+                             1 = persistent grids (compute units x resident workgroups) whose workgroups take the
+                             work items in schedule order from an atomic counter (frame counters[199..201]).
+                             Results identical; offered to time the two launch schemes against each other */
 } gs_opts;
 
 /* Gaussian parameters, or gradients / Adam moments in the same layout.  Row-major float32:
@@ -173,7 +176,8 @@ typedef struct gs_frame {
   int32_t* counters;    /* [256]: [0] instance count, [1] flags, [2..2+n_views) valid depth pixels per view,
                            [128..192) tile-length bucket counts and offsets, [192] work items,
                            [193] segment slots of split tiles, [194] split tiles, [196] visible records,
-                           [197] instances summed per Gaussian, [198] records with more than 32 instances */
+                           [197] instances summed per Gaussian, [198] records with more than 32 instances,
+                           [199..201] work-item counters of the persistent compositing launches */
   int32_t* seg_count;   /* [n_tiles]: segments of the tile at each schedule position */
   int32_t* seg_first;   /* [n_tiles]: exclusive scan of seg_count = first work item of that tile */
   int32_t* items;       /* [item_cap][4]: work items of the compositing calls, split tiles first:

@@ -35,7 +35,7 @@ class gs_camera(ctypes.Structure):
 class gs_opts(ctypes.Structure):
     _fields_ = [("tile_w", c_i32), ("tile_h", c_i32), ("near_z", c_f), ("guard", c_f), ("lowpass", c_f),
                 ("alpha_min", c_f), ("alpha_max", c_f), ("t_min", c_f), ("bg", c_f * 3), ("waves_per_tile", c_i32),
-                ("block_w", c_i32), ("batch_depth", c_i32), ("seg_len", c_i32), ("reserved", c_i32 * 1)]
+                ("block_w", c_i32), ("batch_depth", c_i32), ("seg_len", c_i32), ("persistent", c_i32)]
 
 
 class gs_params(ctypes.Structure):

@@ -786,26 +786,47 @@ __device__ __forceinline__ void segment_sums(Stage<G>& s, const float4* __restri
   o[5 * G::NT] = Vs;
 }
 
+// The work items of a launch: one per workgroup (item blockIdx.x while it is below count), or with PERSIST a
+// grid sized to what the GPU holds at once, whose workgroups take items in schedule order from the counter
+// *ctr (zeroed before the launch) until count is reached; every workgroup then leaves the loop.
+template <bool PERSIST, class Body>
+__device__ __forceinline__ void for_items(int count, int32_t* ctr, Body body) {
+  if constexpr (!PERSIST) {
+    if ((int)blockIdx.x < count) body((int)blockIdx.x);
+  } else {
+    __shared__ int s_item;
+    while (true) {
+      __syncthreads();  // the previous item's LDS is no longer read
+      if (threadIdx.x == 0) s_item = atomicAdd(ctr, 1);
+      __syncthreads();
+      const int b = s_item;
+      if (b >= count) return;
+      body(b);
+    }
+  }
+}
+
 // Backward over the work items: whole tiles run the forward sweep (or read the forward images), the upstream
 // gradient and the backward walk; segments of split tiles run step 1.
-template <int TW, int TH, int DEPTH, int BW, bool HAVE_FWD, bool LOSS>
+template <int TW, int TH, int DEPTH, int BW, bool HAVE_FWD, bool LOSS, bool PERSIST = false>
 __global__ __launch_bounds__(TW * TH) void k_fused_main(const float4* __restrict__ rec,
                                                         const int32_t* __restrict__ vals,
                                                         const int2* __restrict__ range,
                                                         const gs_camera* __restrict__ cams, int V, DevOpts op,
-                                                        BwdArgs a, SegArgs g) {
+                                                        BwdArgs a, SegArgs g, int32_t* ctr) {
   using G = Geo<TW, TH, DEPTH, BW>;
   __shared__ Stage<G> s;
   __shared__ float gacc[10][G::BATCH];
-  if ((int)blockIdx.x >= g.counters[192]) return;
-  const int4 it = g.items[blockIdx.x];
-  TileCtx t;
-  tile_at<G>(cams, V, it.x, t);
-  const int2 rg = range[it.x];
-  if (it.z < 0)
-    tile_backward<G, DEPTH, HAVE_FWD, LOSS>(s, gacc, rec, vals, rg, t, op, a);
-  else
-    segment_sums<G, DEPTH>(s, rec, vals, rg, it, t, op, g);
+  for_items<PERSIST>(g.counters[192], ctr, [&](int b) {
+    const int4 it = g.items[b];
+    TileCtx t;
+    tile_at<G>(cams, V, it.x, t);
+    const int2 rg = range[it.x];
+    if (it.z < 0)
+      tile_backward<G, DEPTH, HAVE_FWD, LOSS>(s, gacc, rec, vals, rg, t, op, a);
+    else
+      segment_sums<G, DEPTH>(s, rec, vals, rg, it, t, op, g);
+  });
 }
 
 // Forward over the work items: whole tiles are composited and written; segments of split tiles run step 1.
@@ -831,34 +852,35 @@ __global__ __launch_bounds__(TW * TH) void k_fwd_main(const float4* __restrict__
   write_pixel(t, op, T, Cr, Cg, Cb, D, Vs, out_rgb, out_depth, out_vis);
 }
 
-template <int TW, int TH, int DEPTH, int BW>
+template <int TW, int TH, int DEPTH, int BW, bool PERSIST = false>
 __global__ __launch_bounds__(TW * TH) void k_seg_stop(const float4* __restrict__ rec, const int32_t* __restrict__ vals,
                                                       const int2* __restrict__ range,
                                                       const gs_camera* __restrict__ cams, int V, DevOpts op,
-                                                      SegArgs g) {
+                                                      SegArgs g, int32_t* ctr) {
   using G = Geo<TW, TH, DEPTH, BW>;
   __shared__ Stage<G> s;
-  if ((int)blockIdx.x >= g.counters[193]) return;
-  const int4 it = g.items[blockIdx.x];
-  TileCtx t;
-  tile_at<G>(cams, V, it.x, t);
-  const int2 rg = range[it.x];
-  const int n = (rg.y - rg.x + g.len - 1) / g.len;
-  // start transmittances of this segment and the next (k_seg_prefix)
-  const float* sp = g.seg + (size_t)(it.z + it.y) * 6 * G::NT + threadIdx.x;
-  const float Ts = sp[0];
-  const bool last = t.inside && Ts >= op.t_min && (it.y == n - 1 || sp[6 * G::NT] < op.t_min);
-  float T = Ts, Cr = 0.f, Cg = 0.f, Cb = 0.f, D = 0.f, Vs = 0.f;
-  forward_walk<G, DEPTH, true>(s, rec, vals, segment_range<G>(rg, it.y, g.len), t, op, last, T, Cr, Cg, Cb, D, Vs);
-  if (last) {
-    float* o = g.split + (size_t)it.w * 12 * G::NT + threadIdx.x;
-    o[0 * G::NT] = T;
-    o[1 * G::NT] = Cr;
-    o[2 * G::NT] = Cg;
-    o[3 * G::NT] = Cb;
-    o[4 * G::NT] = D;
-    o[5 * G::NT] = Vs;
-  }
+  for_items<PERSIST>(g.counters[193], ctr, [&](int b) {
+    const int4 it = g.items[b];
+    TileCtx t;
+    tile_at<G>(cams, V, it.x, t);
+    const int2 rg = range[it.x];
+    const int n = (rg.y - rg.x + g.len - 1) / g.len;
+    // start transmittances of this segment and the next (k_seg_prefix)
+    const float* sp = g.seg + (size_t)(it.z + it.y) * 6 * G::NT + threadIdx.x;
+    const float Ts = sp[0];
+    const bool last = t.inside && Ts >= op.t_min && (it.y == n - 1 || sp[6 * G::NT] < op.t_min);
+    float T = Ts, Cr = 0.f, Cg = 0.f, Cb = 0.f, D = 0.f, Vs = 0.f;
+    forward_walk<G, DEPTH, true>(s, rec, vals, segment_range<G>(rg, it.y, g.len), t, op, last, T, Cr, Cg, Cb, D, Vs);
+    if (last) {
+      float* o = g.split + (size_t)it.w * 12 * G::NT + threadIdx.x;
+      o[0 * G::NT] = T;
+      o[1 * G::NT] = Cr;
+      o[2 * G::NT] = Cg;
+      o[3 * G::NT] = Cb;
+      o[4 * G::NT] = D;
+      o[5 * G::NT] = Vs;
+    }
+  });
 }
 
 // Segments of a split tile whose loads the combine steps keep in flight together (a tile may have a hundred
@@ -1025,24 +1047,25 @@ __global__ __launch_bounds__(TW * TH) void k_seg_combine(const gs_camera* __rest
   xp[11 * G::NT] = S;
 }
 
-template <int TW, int TH, int DEPTH, int BW>
+template <int TW, int TH, int DEPTH, int BW, bool PERSIST = false>
 __global__ __launch_bounds__(TW * TH) void k_seg_bwd(const float4* __restrict__ rec, const int32_t* __restrict__ vals,
                                                      const int2* __restrict__ range,
                                                      const gs_camera* __restrict__ cams, int V, DevOpts op,
-                                                     BwdArgs a, SegArgs g) {
+                                                     BwdArgs a, SegArgs g, int32_t* ctr) {
   using G = Geo<TW, TH, DEPTH, BW>;
   __shared__ Stage<G> s;
   __shared__ float gacc[10][G::BATCH];
-  if ((int)blockIdx.x >= g.counters[193]) return;
-  const int4 it = g.items[blockIdx.x];
-  TileCtx t;
-  tile_at<G>(cams, V, it.x, t);
-  const float* sp = g.seg + (size_t)(it.z + it.y) * 6 * G::NT + threadIdx.x;
-  const float* xp = g.split + (size_t)it.w * 12 * G::NT + threadIdx.x;
-  const float Ts = sp[0], Ps = sp[1 * G::NT];
-  backward_walk<G, DEPTH>(s, gacc, rec, vals, segment_range<G>(range[it.x], it.y, g.len), t, op,
-                          t.inside && Ts >= op.t_min, Ts, Ps, xp[6 * G::NT], xp[7 * G::NT], xp[8 * G::NT],
-                          xp[9 * G::NT], xp[10 * G::NT], xp[11 * G::NT], a);
+  for_items<PERSIST>(g.counters[193], ctr, [&](int b) {
+    const int4 it = g.items[b];
+    TileCtx t;
+    tile_at<G>(cams, V, it.x, t);
+    const float* sp = g.seg + (size_t)(it.z + it.y) * 6 * G::NT + threadIdx.x;
+    const float* xp = g.split + (size_t)it.w * 12 * G::NT + threadIdx.x;
+    const float Ts = sp[0], Ps = sp[1 * G::NT];
+    backward_walk<G, DEPTH>(s, gacc, rec, vals, segment_range<G>(range[it.x], it.y, g.len), t, op,
+                            t.inside && Ts >= op.t_min, Ts, Ps, xp[6 * G::NT], xp[7 * G::NT], xp[8 * G::NT],
+                            xp[9 * G::NT], xp[10 * G::NT], xp[11 * G::NT], a);
+  });
 }
 
 // Work counts of the forward: pairs evaluated (pixel inside the record's pixel rectangle, up to the
@@ -1144,6 +1167,19 @@ SegArgs seg_args(const gs_frame& f) {
   return g;
 }
 
+// Workgroups of a persistent launch: what the GPU holds at once (compute units x resident workgroups of the
+// kernel per unit), at most cap.
+template <class K>
+int resident_grid(K kernel, int block, int64_t cap) {
+  int dev = 0, cus = 0, occ = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, block, 0) != hipSuccess || occ < 1) occ = 1;
+  const int64_t g = (int64_t)cus * occ;
+  return (int)(g < cap ? g : (cap > 0 ? cap : 1));
+}
+
 template <int TW, int TH, int DEPTH, int BW>
 hipError_t launch_fwd(const gs_frame& f, const DevOpts& op, const gs_images& out, hipStream_t st) {
   const int sorted = f.sort_passes & 1;
@@ -1159,7 +1195,8 @@ hipError_t launch_fwd(const gs_frame& f, const DevOpts& op, const gs_images& out
     if (e != hipSuccess) return e;
     k_seg_prefix<TW, TH, BW><<<f.long_cap, bs, 0, st>>>(g, op);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_seg_stop<TW, TH, DEPTH, BW><<<f.seg_cap, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, op, g);
+    k_seg_stop<TW, TH, DEPTH, BW><<<f.seg_cap, bs, 0, st>>>(rec, f.vals[sorted], rng, f.cams, f.n_views, op, g,
+                                                            nullptr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_seg_fwd_out<TW, TH, BW><<<f.long_cap, bs, 0, st>>>(f.cams, f.n_views, op, g, out.rgb, out.depth, out.vis);
     return hipGetLastError();
@@ -1170,35 +1207,54 @@ hipError_t launch_fwd(const gs_frame& f, const DevOpts& op, const gs_images& out
 }
 
 template <int TW, int TH, int DEPTH, int BW, bool HAVE_FWD, bool LOSS>
-hipError_t launch_split_bwd(const gs_frame& f, const DevOpts& op, const BwdArgs& a, hipStream_t st) {
+hipError_t launch_split_bwd(const gs_frame& f, const DevOpts& op, const BwdArgs& a, bool persist, hipStream_t st) {
   const int sorted = f.sort_passes & 1;
   const auto* rec = reinterpret_cast<const float4*>(f.rec);
   const auto* rng = reinterpret_cast<const int2*>(f.tile_range);
   const int32_t* vals = f.vals[sorted];
   const int bs = TW * TH;
   const SegArgs g = seg_args(f);
-  k_fused_main<TW, TH, DEPTH, BW, HAVE_FWD, LOSS><<<f.item_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  // persistent: the three walking kernels take their items from counters[199..201]
+  int32_t* ctr = f.counters + 199;
+  if (persist) {
+    if ((e = gs_launch::fill_i32(ctr, 0, 3, st)) != hipSuccess) return e;
+    auto* kf = k_fused_main<TW, TH, DEPTH, BW, HAVE_FWD, LOSS, true>;
+    kf<<<resident_grid(kf, bs, f.item_cap), bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g, ctr);
+  } else {
+    k_fused_main<TW, TH, DEPTH, BW, HAVE_FWD, LOSS><<<f.item_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op,
+                                                                                a, g, nullptr);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   k_seg_prefix<TW, TH, BW><<<f.long_cap, bs, 0, st>>>(g, op);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_seg_stop<TW, TH, DEPTH, BW><<<f.seg_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, g);
+  if (persist) {
+    auto* ks = k_seg_stop<TW, TH, DEPTH, BW, true>;
+    ks<<<resident_grid(ks, bs, f.seg_cap), bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, g, ctr + 1);
+  } else {
+    k_seg_stop<TW, TH, DEPTH, BW><<<f.seg_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, g, nullptr);
+  }
   if ((e = hipGetLastError()) != hipSuccess) return e;
   k_seg_combine<TW, TH, BW, HAVE_FWD, LOSS><<<f.long_cap, bs, 0, st>>>(f.cams, f.n_views, op, a, g);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_seg_bwd<TW, TH, DEPTH, BW><<<f.seg_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g);
+  if (persist) {
+    auto* kb = k_seg_bwd<TW, TH, DEPTH, BW, true>;
+    kb<<<resident_grid(kb, bs, f.seg_cap), bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g, ctr + 2);
+  } else {
+    k_seg_bwd<TW, TH, DEPTH, BW><<<f.seg_cap, bs, 0, st>>>(rec, vals, rng, f.cams, f.n_views, op, a, g, nullptr);
+  }
   return hipGetLastError();
 }
 
 template <int TW, int TH, int DEPTH, int BW>
-hipError_t launch_bwd(const gs_frame& f, const DevOpts& op, bool have_fwd, bool loss, const BwdArgs& a,
+hipError_t launch_bwd(const gs_frame& f, const DevOpts& op, bool have_fwd, bool loss, const BwdArgs& a, bool persist,
                       hipStream_t st) {
   if (f.seg_len > 0) {
     // long lists split into depth segments
-    if (have_fwd && loss) return launch_split_bwd<TW, TH, DEPTH, BW, true, true>(f, op, a, st);
-    if (have_fwd) return launch_split_bwd<TW, TH, DEPTH, BW, true, false>(f, op, a, st);
-    if (loss) return launch_split_bwd<TW, TH, DEPTH, BW, false, true>(f, op, a, st);
-    return launch_split_bwd<TW, TH, DEPTH, BW, false, false>(f, op, a, st);
+    if (have_fwd && loss) return launch_split_bwd<TW, TH, DEPTH, BW, true, true>(f, op, a, persist, st);
+    if (have_fwd) return launch_split_bwd<TW, TH, DEPTH, BW, true, false>(f, op, a, persist, st);
+    if (loss) return launch_split_bwd<TW, TH, DEPTH, BW, false, true>(f, op, a, persist, st);
+    return launch_split_bwd<TW, TH, DEPTH, BW, false, false>(f, op, a, persist, st);
   }
   const int sorted = f.sort_passes & 1;
   const auto* rec = reinterpret_cast<const float4*>(f.rec);
@@ -1303,7 +1359,7 @@ hipError_t render_bwd(const gs_frame& f, const gs_opts& o, const gs_images* fwd,
   a.capacity = f.capacity;
   a.loss = f.loss;
   const bool loss = l.tgt_rgb != nullptr;
-  GS_TILE_DISPATCH(launch_bwd, f, op, fwd != nullptr, loss, a, st);
+  GS_TILE_DISPATCH(launch_bwd, f, op, fwd != nullptr, loss, a, o.persistent != 0, st);
 }
 
 }  // namespace gs_launch

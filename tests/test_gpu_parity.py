@@ -395,6 +395,31 @@ def test_batched_graph_step_matches_plain_step(gpu_lib):
         np.testing.assert_allclose(mb.p[k].cpu().numpy()[firm], ma.p[k].cpu().numpy()[firm], rtol=1e-5, atol=1e-7)
 
 
+def test_persistent_launch_matches_work_item_grid(gpu_lib):
+    """The persistent compositing launches (grids of resident workgroups taking the frame's work items from an
+    atomic counter) give the loss and gradients of one workgroup per work item, on a frame whose short depth
+    segments split many tiles."""
+    sc = scenes.random_scene(1500, 6000, 128, 96, sh_degree=1, views=3, log_scale_mu=-2.0, depth_fraction=0.3)
+    scale = oracle.gradient_scale(sc.params(), 1, sc.cams, tgt_rgb=sc.tgt_rgb, tgt_depth=sc.tgt_depth)
+    res = {}
+    for pers in (0, 1):
+        m = GaussianModel(sc.params(), 1)
+        st = BatchedStep(m, sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=B.default_opts(seg_len=64, persistent=pers),
+                         keep_grads=True)
+        st.run_eager()
+        torch.cuda.synchronize()
+        c = B.frame_tensor(st.frame, "counters", 256, torch.int32).cpu().numpy()
+        res[pers] = (st.loss(), {k: m.g[k].cpu().numpy() for k in m.g}, int(c[194]), int(c[193]))
+        log("persistent" if pers else "work-item grid", "loss", res[pers][0], "split tiles", res[pers][2],
+            "segments", res[pers][3])
+    assert res[0][2] > 10 and res[0][2:] == res[1][2:]
+    np.testing.assert_allclose(res[1][0], res[0][0], rtol=1e-6)
+    for k, a in res[0][1].items():
+        b = res[1][1][k]
+        rnd = ROUND_C * U32 * scale[k].reshape(a.shape)
+        assert np.all(np.abs(b.astype(np.float64) - a) <= 1e-5 * np.abs(a) + 2 * rnd), k
+
+
 def test_graph_replays_match_eager(gpu_lib):
     sc = scenes.random_scene(900, 2000, 96, 80, sh_degree=2, views=3, log_scale_mu=-2.3, depth_fraction=0.2)
     me = GaussianModel(sc.params(), 2)

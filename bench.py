@@ -52,6 +52,19 @@ def timed(fn, steps, stream):
     return start.elapsed_time(end) / steps
 
 
+def timed_trials(fn, steps, stream, trials=5):
+    """Time exactly `steps` calls as `trials` runs of consecutive calls (equal runs, the last one takes the
+    remainder), each bracketed by events after a synchronize; returns the median run's ms per call and every
+    run's."""
+    if steps < trials:
+        sizes = [1] * steps
+    else:
+        per = steps // trials
+        sizes = [per] * (trials - 1) + [steps - per * (trials - 1)]
+    runs = [timed(fn, k, stream) for k in sizes]
+    return float(sorted(runs)[len(runs) // 2]), runs
+
+
 def spatial_order(model) -> float:
     """Put the model's Gaussians in Morton order of their means (the library's memory layout for locality; both
     the batched and the plain step use it); returns the milliseconds it took on the device."""
@@ -83,7 +96,7 @@ def persistent_step_ms(sc, tile, steps, warmup):
     for _ in range(warmup):
         bat.run()
     bat.finish()
-    ms = timed(bat.run, steps, torch.cuda.current_stream())
+    ms, _ = timed_trials(bat.run, steps, torch.cuda.current_stream())
     bat.finish()
     del bat, model
     torch.cuda.synchronize()
@@ -123,18 +136,18 @@ def measure(sc, steps, warmup, plain_steps, do_plain, tile=None, peak=False):
         bat.run()
     bat.finish()
     replans = bat.replans
-    ms = timed(bat.run, steps, stream)
+    ms, trials = timed_trials(bat.run, steps, stream)
     bat.finish()
     if bat.replans != replans:
         # the capacity was re-planned inside the timed steps (the map grew): time again at the new capacity
         log(f"  batched: capacity re-planned during timing ({bat.frame.capacity}); timing again")
         replans = bat.replans
-        ms = timed(bat.run, steps, stream)
+        ms, trials = timed_trials(bat.run, steps, stream)
         bat.finish()
         if bat.replans != replans:
             raise RuntimeError("instance capacity re-planned twice during timing")
-    res = dict(ms=ms, n_instances=bat.n_instances(), loss=bat.loss(), frame=bat.frame, model=model, step=bat,
-               tile=tile, order_ms=t_order)
+    res = dict(ms=ms, trials=trials, n_instances=bat.n_instances(), loss=bat.loss(), frame=bat.frame, model=model,
+               step=bat, tile=tile, order_ms=t_order)
     if peak:
         res["peak_gb"] = torch.cuda.max_memory_allocated() / 1e9
     log(f"  batched: {ms:.3f} ms/step ({1000 / ms:.2f} it/s), {res['n_instances']} instances")
@@ -143,8 +156,9 @@ def measure(sc, steps, warmup, plain_steps, do_plain, tile=None, peak=False):
             torch.cuda.synchronize()
             base = torch.cuda.memory_allocated()  # the batched step's buffers, still held
             torch.cuda.reset_peak_memory_stats()
-        pm = GaussianModel(sc.params(), sc.sh_degree)
-        spatial_order(pm)
+        # the plain sequence starts from the map the batched step has reached, so both are timed on the same
+        # state of the map (it changes as it trains); the rows are already in Morton order
+        pm = GaussianModel({k: v.detach().cpu().numpy() for k, v in model.p.items()}, sc.sh_degree)
         plain = PlainStep(pm, sc.cams, sc.tgt_rgb, sc.tgt_depth, opts=opts)
         plain.run()
         pms = timed(plain.run, plain_steps, stream)
@@ -295,8 +309,8 @@ def cpu_baseline(sc, kf_views, threads=None):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200, help="timed steps (five runs of steps/5; the median is reported)")
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--plain-steps", type=int, default=5)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-persistent", action="store_true",
@@ -360,6 +374,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(r4["ms"], 4),
+        "ms_per_step_runs": [round(x, 4) for x in r4["trials"]],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -23,7 +23,7 @@ from . import binding as B
 # -1 = never split).  The first is the default: another candidate is chosen only if it is faster by more than
 # TIE (measurement noise would otherwise flip between near-equal ones from run to run).
 CANDIDATES: List[Tuple[int, int, int, int, int]] = [
-    (16, 16, 1, 4, 512), (16, 16, 1, 4, 1024), (16, 8, 1, 4, 512), (16, 8, 1, 4, 1024), (16, 8, 1, 8, 512),
+    (16, 8, 1, 4, 512), (16, 16, 1, 4, 512), (16, 16, 1, 4, 1024), (16, 8, 1, 4, 1024), (16, 8, 1, 8, 512),
     (16, 8, 2, 4, 512), (8, 8, 1, 4, 512), (32, 8, 1, 4, 512), (16, 16, 1, 8, -1), (16, 16, 1, 2, 512)]
 TIE = 0.02
 
@@ -56,7 +56,7 @@ def _store(d: Dict[str, list]) -> None:
         pass
 
 
-def tune_batched(make_step, n: int, cams: Sequence, sh_degree: int, replays: int = 3,
+def tune_batched(make_step, n: int, cams: Sequence, sh_degree: int, replays: int = 8,
                  candidates: Sequence[Tuple[int, int, int, int, int]] = CANDIDATES, use_cache: bool = True,
                  log=None):
     """make_step(opts) -> a BatchedStep.  Returns (best (tile_w, tile_h, depth, block_w, seg_len),

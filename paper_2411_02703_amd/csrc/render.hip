@@ -204,7 +204,8 @@ __device__ __forceinline__ void clear_masks(Stage<G>& s) {
 // and a block is marked iff one of its rows holds a pixel centre in that interval (the union over the block's
 // rows is taken as one interval, a superset).  k is widened by 1% + 0.01: with det > 1e-3 a c (else the whole
 // rectangle is kept) the FP32 power of the walk is within 0.1% of q, so no pair the walk would accept is
-// pruned and the result does not change.
+// pruned and the result does not change (the hardware square root and logarithm used here err by a few ulp,
+// far inside that widening).
 template <class G, int DEPTH>
 __device__ __forceinline__ void scatter(Stage<G>& s, const TileCtx& t, const DevOpts& op, int nb) {
   constexpr int GX = 8 * G::SX / G::BW, GY = 8 * G::SY / G::BW;  // blocks across and down the tile
@@ -235,7 +236,7 @@ __device__ __forceinline__ void scatter(Stage<G>& s, const TileCtx& t, const Dev
           const float dy = (float)yy + 0.5f - A.y;
           const float disc = ak - det * dy * dy;
           if (disc < 0.f) continue;
-          const float sq = sqrtf(disc);
+          const float sq = __builtin_amdgcn_sqrtf(disc);  // the hardware root (~1 ulp): k is widened far more
           // pixel columns whose centres px + 0.5 lie in [A.x + xl, A.x + xr]
           const float xl = A.x + (-cb * dy - sq) * inv_a - 0.5f, xr = A.x + (-cb * dy + sq) * inv_a - 0.5f;
           lo = min(lo, (int)ceilf(fminf(fmaxf(xl, -1.f), 65536.f)));

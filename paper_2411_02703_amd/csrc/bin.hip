@@ -54,21 +54,48 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int32_t* __res
     return;
   }
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  // a thread's 16 items as four 16-byte loads and stores when they are all in range and the arrays are aligned
+  const bool vec = base + kScanItems <= n &&
+                   ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
   int v[kScanItems];
+  if (vec) {
+    const int4* p = reinterpret_cast<const int4*>(in + base);
+#pragma unroll
+    for (int q = 0; q < kScanItems / 4; ++q) {
+      const int4 x = p[q];
+      v[4 * q] = x.x;
+      v[4 * q + 1] = x.y;
+      v[4 * q + 2] = x.z;
+      v[4 * q + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      const int64_t idx = base + i;
+      v[i] = idx < n ? in[idx] : 0;
+    }
+  }
   int acc = 0;
 #pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    const int64_t idx = base + i;
-    v[i] = idx < n ? in[idx] : 0;
-    acc += v[i];
-  }
+  for (int i = 0; i < kScanItems; ++i) acc += v[i];
   int total;
   int run = block_scan_256(acc, sh_wave, &total);
+  int o[kScanItems];
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
-    const int64_t idx = base + i;
-    if (idx < n) out[idx] = run;
+    o[i] = run;
     run += v[i];
+  }
+  if (vec) {
+    int4* p = reinterpret_cast<int4*>(out + base);
+#pragma unroll
+    for (int q = 0; q < kScanItems / 4; ++q) p[q] = make_int4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      const int64_t idx = base + i;
+      if (idx < n) out[idx] = o[i];
+    }
   }
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }

@@ -561,55 +561,72 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
     // others lr[5]
     wb[lane * FP + F] = step ? 0.f : 1.f;
     __syncthreads();
+    // U elements per lane at a time: all their loads are issued before the first is used, so a lane waits
+    // for memory once per U elements rather than once per element
+    constexpr int U = 8;
     const float s4 = ad.lr[4] / bc1, s5 = ad.lr[5] / bc1;
-    for (int e = lane; e < nw * F; e += 64) {
-      const int r = e / F, c = e - r * F;
-      if (wb[r * FP + F] != 0.f) continue;
-      const int64_t idx = g0 * F + e;
-      float pv = sh[idx], mm = ad.m_sh[idx], vv = ad.v_sh[idx];
-      adam_one(pv, mm, vv, wb[r * FP + c], c < 3 ? s4 : s5, b1, b2, eps, bc2s);
-      sh[idx] = pv;
-      ad.m_sh[idx] = mm;
-      ad.v_sh[idx] = vv;
+    const int total = nw * F;
+    for (int e0 = lane; e0 < total; e0 += 64 * U) {
+      float pv[U], mm[U], vv[U];
+      bool on[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + 64 * u;
+        on[u] = e < total && wb[(e / F) * FP + F] == 0.f;
+        const int64_t idx = g0 * F + (on[u] ? e : 0);
+        pv[u] = sh[idx];
+        mm[u] = ad.m_sh[idx];
+        vv[u] = ad.v_sh[idx];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (!on[u]) continue;
+        const int e = e0 + 64 * u;
+        const int r = e / F, c = e - r * F;
+        const int64_t idx = g0 * F + e;
+        adam_one(pv[u], mm[u], vv[u], wb[r * FP + c], c < 3 ? s4 : s5, b1, b2, eps, bc2s);
+        sh[idx] = pv[u];
+        ad.m_sh[idx] = mm[u];
+        ad.v_sh[idx] = vv[u];
+      }
     }
   }
   if (!step) return;
-  {
-    float o = opac[g];
-    const float s3 = ad.lr[3] / bc1;
-    float mm = ad.m_opac[g], vv = ad.v_opac[g];
-    adam_one(o, mm, vv, out_o, s3, b1, b2, eps, bc2s);
-    opac[g] = o;
-    ad.m_opac[g] = mm;
-    ad.v_opac[g] = vv;
+  // every moment is loaded before the first store (the stores could alias the later loads as far as the
+  // compiler knows), so the lane waits for memory once
+  float o = opac[g], mo = ad.m_opac[g], vo = ad.v_opac[g];
+  float mmu[3], vmu[3], mls[3], vls[3];
+  for (int i = 0; i < 3; ++i) {
+    mmu[i] = ad.m_means[g * 3 + i];
+    vmu[i] = ad.v_means[g * 3 + i];
+    mls[i] = ad.m_scales[g * 3 + i];
+    vls[i] = ad.v_scales[g * 3 + i];
   }
-  {
-    const float s0 = ad.lr[0] / bc1, s1 = ad.lr[1] / bc1;
-    for (int i = 0; i < 3; ++i) {
-      float mm = ad.m_means[g * 3 + i], vv = ad.v_means[g * 3 + i];
-      adam_one(mu[i], mm, vv, out_mu[i], s0, b1, b2, eps, bc2s);
-      means[g * 3 + i] = mu[i];
-      ad.m_means[g * 3 + i] = mm;
-      ad.v_means[g * 3 + i] = vv;
-      mm = ad.m_scales[g * 3 + i];
-      vv = ad.v_scales[g * 3 + i];
-      adam_one(ls[i], mm, vv, out_ls[i], s1, b1, b2, eps, bc2s);
-      log_scales[g * 3 + i] = ls[i];
-      ad.m_scales[g * 3 + i] = mm;
-      ad.v_scales[g * 3 + i] = vv;
-    }
+  float4 mq = reinterpret_cast<const float4*>(ad.m_quats)[g], vq = reinterpret_cast<const float4*>(ad.v_quats)[g];
+  const float s0 = ad.lr[0] / bc1, s1 = ad.lr[1] / bc1, s2 = ad.lr[2] / bc1, s3 = ad.lr[3] / bc1;
+  adam_one(o, mo, vo, out_o, s3, b1, b2, eps, bc2s);
+  for (int i = 0; i < 3; ++i) {
+    adam_one(mu[i], mmu[i], vmu[i], out_mu[i], s0, b1, b2, eps, bc2s);
+    adam_one(ls[i], mls[i], vls[i], out_ls[i], s1, b1, b2, eps, bc2s);
   }
-  {
-    const float s2 = ad.lr[2] / bc1;
-    float4 mq = reinterpret_cast<const float4*>(ad.m_quats)[g], vq = reinterpret_cast<const float4*>(ad.v_quats)[g];
-    adam_one(qq[0], mq.x, vq.x, out_q[0], s2, b1, b2, eps, bc2s);
-    adam_one(qq[1], mq.y, vq.y, out_q[1], s2, b1, b2, eps, bc2s);
-    adam_one(qq[2], mq.z, vq.z, out_q[2], s2, b1, b2, eps, bc2s);
-    adam_one(qq[3], mq.w, vq.w, out_q[3], s2, b1, b2, eps, bc2s);
-    reinterpret_cast<float4*>(quats)[g] = make_float4(qq[0], qq[1], qq[2], qq[3]);
-    reinterpret_cast<float4*>(ad.m_quats)[g] = mq;
-    reinterpret_cast<float4*>(ad.v_quats)[g] = vq;
+  adam_one(qq[0], mq.x, vq.x, out_q[0], s2, b1, b2, eps, bc2s);
+  adam_one(qq[1], mq.y, vq.y, out_q[1], s2, b1, b2, eps, bc2s);
+  adam_one(qq[2], mq.z, vq.z, out_q[2], s2, b1, b2, eps, bc2s);
+  adam_one(qq[3], mq.w, vq.w, out_q[3], s2, b1, b2, eps, bc2s);
+  opac[g] = o;
+  ad.m_opac[g] = mo;
+  ad.v_opac[g] = vo;
+  for (int i = 0; i < 3; ++i) {
+    means[g * 3 + i] = mu[i];
+    ad.m_means[g * 3 + i] = mmu[i];
+    ad.v_means[g * 3 + i] = vmu[i];
+    log_scales[g * 3 + i] = ls[i];
+    ad.m_scales[g * 3 + i] = mls[i];
+    ad.v_scales[g * 3 + i] = vls[i];
   }
+  reinterpret_cast<float4*>(quats)[g] = make_float4(qq[0], qq[1], qq[2], qq[3]);
+  reinterpret_cast<float4*>(ad.m_quats)[g] = mq;
+  reinterpret_cast<float4*>(ad.v_quats)[g] = vq;
 }
 
 }  // namespace

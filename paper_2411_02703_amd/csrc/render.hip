@@ -35,6 +35,7 @@ struct Geo {
   static constexpr int NW = SX * SY;           // waves per tile
   static constexpr int NT = 64 * NW;           // threads = pixels of the tile
   static constexpr int BATCH = NT * DEPTH;     // records staged per round
+  static constexpr int GS = BATCH + 1;         // LDS row stride of the gradient sums (odd: rows in distinct banks)
   static constexpr int MC = BATCH / 32;        // 32-bit mask words per block
   static constexpr int BW = BW_;               // block width (pixels)
   static constexpr int BS = 8 / BW;            // blocks across a sub-tile
@@ -179,7 +180,7 @@ __device__ __forceinline__ void stage_round(Stage<G>& s, const float4* __restric
 // whether any pixel of the tile is live (the same answer in every thread).
 template <class G>
 __device__ __forceinline__ bool round_barrier(Stage<G>& s, const TileCtx& t, bool live) {
-  const bool wl = __ballot(live) != 0;
+  const bool wl = __builtin_amdgcn_ballot_w64(live) != 0;
   if (t.lane == 0) s.alive[t.wave] = wl;
   __syncthreads();
   bool any = false;
@@ -268,39 +269,47 @@ __device__ __forceinline__ float block_sum(float x) {
   return x;
 }
 
+// Index of the lowest set bit of m, 31 if m is 0 (v_ffbl_b32 gives -1 for 0; a plain count of trailing zeros
+// adds a clamp to 32).
+__device__ __forceinline__ int low_bit_or_31(uint32_t m) {
+  int r;
+  asm("v_ffbl_b32 %0, %1" : "=v"(r) : "v"(m));
+  return r & 31;
+}
+
 // Walk one staged round: every block walks the set bits of its mask in order, its lanes in lock-step, and
 // stops once all its pixels have ended.
 //   step(j, active, A, B, C, acc) -> contributed   (per lane, branch-free; active = this lane has a record
 //                                                   and a live pixel; clears live at the stop)
 //   post(j, hit, acc)                              (whole wave, once per step, only if SYNC)
-// A lane whose block has run out of records reads slot c * 32 (a record staged in this round, since some
-// block has a bit in word c) and is inactive.
+// A lane whose block has run out of records reads slot c * 32 + 31 (every slot of the round is staged, absent
+// records as record 0, so its data are finite) and is inactive.
 // ENDS: the step can end pixels (stop rule); without it a block's liveness is only checked per mask word.
 template <class G, bool SYNC, bool ENDS, class Step, class Post>
 __device__ __forceinline__ void walk_round(const Stage<G>& s, const TileCtx& t, bool& live, Step step, Post post) {
   constexpr uint64_t BMASK = G::BL == 64 ? ~0ull : ((1ull << G::BL) - 1);
 #pragma unroll 1
   for (int c = 0; c < G::MC; ++c) {
-    uint32_t m = ((__ballot(live) >> t.blk_lane0) & BMASK) ? s.bm[c][t.blk] : 0u;
-    if (__ballot(m != 0) == 0) continue;
+    uint32_t m = ((__builtin_amdgcn_ballot_w64(live) >> t.blk_lane0) & BMASK) ? s.bm[c][t.blk] : 0u;
+    if (__builtin_amdgcn_ballot_w64(m != 0) == 0) continue;
     // The block's next record is fetched from LDS while the current one is composited; two register sets
     // take turns (the loop is unrolled by two), so nothing is copied between them.
-    int j0 = c * 32 + (m ? __builtin_ctz(m) : 0), j1 = 0;
+    int j0 = c * 32 + low_bit_or_31(m), j1 = 0;
     float4 A0 = s.A[j0], B0 = s.B[j0], C0 = s.C[j0], A1, B1, C1;
     auto one = [&](int j, const float4& A, const float4& B, const float4& C, int& jn, float4& An, float4& Bn,
                    float4& Cn, bool check) {
       const bool active = m != 0 && live;
       m &= m - 1;
-      jn = c * 32 + (m ? __builtin_ctz(m) : 0);
+      jn = c * 32 + low_bit_or_31(m);
       An = s.A[jn];
       Bn = s.B[jn];
       Cn = s.C[jn];
       float acc[10];
       const bool hit = step(j, active, A, B, C, acc);
       if (SYNC) post(j, hit, acc);
-      if (ENDS && check && ((__ballot(live) >> t.blk_lane0) & BMASK) == 0) m = 0;
+      if (ENDS && check && ((__builtin_amdgcn_ballot_w64(live) >> t.blk_lane0) & BMASK) == 0) m = 0;
     };
-    auto more = [&]() { return SYNC ? __ballot(m != 0) != 0 : m != 0; };
+    auto more = [&]() { return SYNC ? __builtin_amdgcn_ballot_w64(m != 0) != 0 : m != 0; };
     while (more()) {
       one(j0, A0, B0, C0, j1, A1, B1, C1, false);
       if (!more()) break;
@@ -528,8 +537,16 @@ __device__ __forceinline__ int64_t inst_slot(int first, const float4& C, const T
 //   dL/dmean = -(a S_x + b S_y, b S_x + c S_y),  dL/d(a, b, c) = -(S_xx / 2, S_xy, S_yy / 2).
 // Plain stores: every instance has exactly one writer (its tile or depth segment), so nothing is accumulated
 // in HBM.
+// LDS row of per-record sum q (0 S_x, 1 S_y, 2 S_xx, 3 S_xy, 4 S_yy, 5 opacity, 6..9 w g_(r,g,b,d)).  The rows
+// are ordered so that the three sums a lane of the block reduce-scatter ends with lie 4 rows apart (rows
+// r, r + 4, r + 8 with r = c0 + 2 c1, see backward_walk): one address serves its three LDS atomics.
+__device__ __forceinline__ constexpr int lds_row(int q) {
+  return q == 0 ? 0 : q == 1 ? 1 : q == 2 ? 4 : q == 3 ? 8 : q == 4 ? 5 : q == 5 ? 9 : q == 6 ? 2 : q == 7 ? 3
+       : q == 8 ? 6 : 7;
+}
+
 template <class G, int DEPTH>
-__device__ __forceinline__ void flush_grads(const Stage<G>& s, float (*gacc)[G::BATCH], const TileCtx& t,
+__device__ __forceinline__ void flush_grads(const Stage<G>& s, float (*gacc)[G::GS], const TileCtx& t,
                                             float* __restrict__ ipart, int64_t capacity, int nb) {
 #pragma unroll
   for (int k = 0; k < DEPTH; ++k) {
@@ -539,7 +556,7 @@ __device__ __forceinline__ void flush_grads(const Stage<G>& s, float (*gacc)[G::
     bool any = false;
 #pragma unroll
     for (int q = 0; q < 10; ++q) {
-      v[q] = gacc[q][j];
+      v[q] = gacc[lds_row(q)][j];
       any |= v[q] != 0.f;
     }
     {
@@ -587,7 +604,7 @@ __device__ __forceinline__ void zero_grads(const float4* __restrict__ rec, const
 // Per-record partial derivatives are summed in LDS and stored as the instances' partials once per round;
 // instances after the walk's end get zero partials.
 template <class G, int DEPTH>
-__device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATCH], const float4* __restrict__ rec,
+__device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::GS], const float4* __restrict__ rec,
                                               const int32_t* __restrict__ vals, int2 rg, const TileCtx& t,
                                               const DevOpts& op, bool live, float T, float Pp, float gr, float gg,
                                               float gb, float gd, float gv, float S, const BwdArgs& a) {
@@ -596,11 +613,11 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
   for (int k = 0; k < DEPTH; ++k)
 #pragma unroll
     for (int q = 0; q < 10; ++q) gacc[q][k * G::NT + threadIdx.x] = 0.f;
-  // The ten per-record sums live in LDS slots 0 S_x, 1 S_y, 2 S_xx, 3 S_xy, 4 S_yy, 5 opacity, 6..9 w g_(r,g,b,d)
-  // (S_* are moments of dq, see flush_grads).  Each lane computes them as a kept half acc[0..4] and a sent
+  // The ten per-record sums are numbered 0 S_x, 1 S_y, 2 S_xx, 3 S_xy, 4 S_yy, 5 opacity, 6..9 w g_(r,g,b,d)
+  // (S_* are moments of dq, see flush_grads; sum q lives in LDS row lds_row(q)).  Each lane computes them as a kept half acc[0..4] and a sent
   // half acc[5..9] for the first exchange of the block reduce-scatter; which half is kept is the lane's share
-  // c0 (c1 for the second exchange): lanes of share 0 keep S_x, S_xx, S_xy, w g_r, w g_b (slots 0, 2, 3, 6,
-  // 8), lanes of share 1 keep S_y, S_yy, opacity, w g_g, w g_d (slots 1, 4, 5, 7, 9).  The colour halves
+  // c0 (c1 for the second exchange): lanes of share 0 keep S_x, S_xx, S_xy, w g_r, w g_b (sums 0, 2, 3, 6,
+  // 8), lanes of share 1 keep S_y, S_yy, opacity, w g_g, w g_d (sums 1, 4, 5, 7, 9).  The colour halves
   // depend on the lane only, so their selection is made once here.  With BW = 4 the shares are c0 = b0^b2,
   // c1 = b1^b2 of the lane's row index (b_k its bits): the quad exchanges (lane^1, lane^2) flip c0 resp. c1,
   // the row mirrors flip all four bits and keep both shares.  With BW = 2 they are the quad bits b0, b1.
@@ -617,7 +634,7 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
     const bool hit = ok && !stop;
     live = live && !stop;
     const float wh = hit ? alpha * T : 0.f;  // w of a contributing pair, else 0
-    const float qv = gr * B.w + gg * C.x + gb * C.y + gd * A.z + gv;
+    const float qv = __builtin_fmaf(gd, A.z, __builtin_fmaf(gb, C.y, __builtin_fmaf(gg, C.x, __builtin_fmaf(gr, B.w, gv))));
     const float Pn = Pp + wh * qv;
     const float dalpha = T * qv - (S - Pn) * __builtin_amdgcn_rcpf(1.f - alpha);
     const bool shape = hit && !cl;  // a clamped alpha passes no gradient to opacity or shape
@@ -646,15 +663,15 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
                                           : (k == 0 ? 0 : k == 1 ? 2 : k == 2 ? 3 : k == 3 ? 6 : 8); };
   auto slot_sent = [&](int k) { return c0 ? (k == 0 ? 0 : k == 1 ? 2 : k == 2 ? 3 : k == 3 ? 6 : 8)
                                           : (k == 0 ? 1 : k == 1 ? 4 : k == 2 ? 5 : k == 3 ? 7 : 9); };
-  // after both exchanges lane (c0, c1) holds the block sums of slots x0, x1 and (c1 = 0 only) x2
-  const int x0_slot = c1 ? (c0 ? 7 : 6) : (c0 ? 1 : 0);
-  const int x1_slot = c1 ? (c0 ? 9 : 8) : (c0 ? 4 : 2);
-  const int x2_slot = c0 ? 5 : 3;
+  // After both exchanges lane (c0, c1) holds the block sums x0, x1 and (c1 = 0 only) x2 of sums
+  // (0, 2, 3) for (0, 0), (1, 4, 5) for (1, 0), (6, 8) for (0, 1) and (7, 9) for (1, 1): LDS rows r, r + 4,
+  // r + 8 with r = c0 + 2 c1.
+  const int x_row = (c0 ? 1 : 0) + (c1 ? 2 : 0);
   // Sum the partials of one step into the records' LDS accumulators (whole wave; one record per block).  The
   // block reduction runs whenever any lane contributed: letting each contributing lane add its own ten
   // partials when few do costs more in LDS atomics than the reduction (measured).
   auto post = [&](int j, bool hit, const float* acc) {
-    const uint64_t hits = __ballot(hit);
+    const uint64_t hits = __builtin_amdgcn_ballot_w64(hit);
     if (hits == 0) return;
     constexpr uint64_t BMASK = G::BL == 64 ? ~0ull : ((1ull << G::BL) - 1);
     const bool block_hit = ((hits >> t.blk_lane0) & BMASK) != 0;
@@ -677,10 +694,23 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
         x1 += gsk::dpp_f<0x140>(x1);
         x2 += gsk::dpp_f<0x140>(x2);
       }
-      if ((G::BW == 2 || lr < 4) && block_hit) {
-        atomicAdd(&gacc[x0_slot][j], x0);
-        atomicAdd(&gacc[x1_slot][j], x1);
-        if (!c1) atomicAdd(&gacc[x2_slot][j], x2);
+      float* dst = &gacc[x_row][j];
+      if (G::BW == 4) {
+        // lanes 0..3 of the blocks with a contributing lane, as a wave mask formed with scalar operations
+        // (lanes 0 and 1 hold the third sum, c1 = 0)
+        uint64_t rows = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (((uint32_t)(hits >> (16 * r)) & 0xffffu) != 0u) rows |= 0xfull << (16 * r);
+        if (__builtin_amdgcn_inverse_ballot_w64(rows)) {
+          atomicAdd(dst, x0);
+          atomicAdd(dst + 4 * G::GS, x1);
+        }
+        if (__builtin_amdgcn_inverse_ballot_w64(rows & 0x0003000300030003ull)) atomicAdd(dst + 8 * G::GS, x2);
+      } else if (block_hit) {
+        atomicAdd(dst, x0);
+        atomicAdd(dst + 4 * G::GS, x1);
+        if (!c1) atomicAdd(dst + 8 * G::GS, x2);
       }
       return;
     }
@@ -690,8 +720,8 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
     if ((t.lane % G::BL) == G::BL - 1 && block_hit) {
 #pragma unroll
       for (int k = 0; k < 5; ++k) {
-        atomicAdd(&gacc[slot_kept(k)][j], sum[k]);
-        atomicAdd(&gacc[slot_sent(k)][j], sum[5 + k]);
+        atomicAdd(&gacc[lds_row(slot_kept(k))][j], sum[k]);
+        atomicAdd(&gacc[lds_row(slot_sent(k))][j], sum[5 + k]);
       }
     }
   };
@@ -706,7 +736,7 @@ __device__ __forceinline__ void backward_walk(Stage<G>& s, float (*gacc)[G::BATC
 
 // Forward sweep (or the forward images), upstream gradient, then the backward walk of one whole tile.
 template <class G, int DEPTH, bool HAVE_FWD, bool LOSS>
-__device__ __forceinline__ void tile_backward(Stage<G>& s, float (*gacc)[G::BATCH], const float4* __restrict__ rec,
+__device__ __forceinline__ void tile_backward(Stage<G>& s, float (*gacc)[G::GS], const float4* __restrict__ rec,
                                               const int32_t* __restrict__ vals, int2 rg, const TileCtx& t,
                                               const DevOpts& op, const BwdArgs& a) {
   float Cf = 0.f, Gf = 0.f, Bf = 0.f, Df = 0.f, Vf = 0.f;
@@ -742,7 +772,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(const float4* __restrict
                                                         const int32_t* __restrict__ order, DevOpts op, BwdArgs a) {
   using G = Geo<TW, TH, DEPTH, BW>;
   __shared__ Stage<G> s;
-  __shared__ float gacc[10][G::BATCH];
+  __shared__ float gacc[10][G::GS];
   TileCtx t;
   int tile;
   if (!tile_setup<G>(cams, V, n_tiles, order, t, tile)) return;
@@ -817,7 +847,7 @@ __global__ __launch_bounds__(TW * TH) void k_fused_main(const float4* __restrict
                                                         BwdArgs a, SegArgs g, int32_t* ctr) {
   using G = Geo<TW, TH, DEPTH, BW>;
   __shared__ Stage<G> s;
-  __shared__ float gacc[10][G::BATCH];
+  __shared__ float gacc[10][G::GS];
   for_items<PERSIST>(g.counters[192], ctr, [&](int b) {
     const int4 it = g.items[b];
     TileCtx t;
@@ -1055,7 +1085,7 @@ __global__ __launch_bounds__(TW * TH) void k_seg_bwd(const float4* __restrict__ 
                                                      BwdArgs a, SegArgs g, int32_t* ctr) {
   using G = Geo<TW, TH, DEPTH, BW>;
   __shared__ Stage<G> s;
-  __shared__ float gacc[10][G::BATCH];
+  __shared__ float gacc[10][G::GS];
   for_items<PERSIST>(g.counters[193], ctr, [&](int b) {
     const int4 it = g.items[b];
     TileCtx t;

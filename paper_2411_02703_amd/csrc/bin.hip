@@ -342,16 +342,24 @@ __device__ __forceinline__ int64_t read_lane64(int64_t x, int l) {
 }
 
 // One thread per depth-sorted record: its run of instances (tiles row by row) starts at eo[j]; key = global tile
-// id, value = record id.  Records with more than kSolo tiles are written by the whole wave, a tile per lane.
+// id, value = record id.  Records with more than kSolo tiles are written by the whole wave, a tile per lane.  The
+// runs of a wave's records are consecutive (eo is their exclusive scan), so the other records are first laid out
+// in a per-wave LDS window of kEmitWin instances and then stored by the wave in coalesced runs, a window at a
+// time; positions of wide records in a window are marked empty and skipped by the copy.
+constexpr int kEmitWin = 512;
+constexpr uint32_t kEmitEmpty = 0xffffffffu;  // no tile id takes this value
+
 __global__ __launch_bounds__(256) void k_emit(const int32_t* __restrict__ rvals, const int32_t* __restrict__ eo,
                                              const uint32_t* __restrict__ rx, const uint32_t* __restrict__ ry,
                                              const gs_camera* __restrict__ cams,
                                              int V, int64_t n, const int32_t* __restrict__ counters, int64_t rcap,
                                              int64_t capacity, uint32_t* __restrict__ keys,
                                              int32_t* __restrict__ vals) {
+  __shared__ uint32_t wkey[4][kEmitWin];
+  __shared__ int32_t wval[4][kEmitWin];
   const int64_t R = sort_count(counters + kRecCount, rcap, rcap);
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const bool here = j < R;
   int64_t r = 0, o = 0;
   short4 rc = make_short4(0, -1, 0, -1);
@@ -366,18 +374,45 @@ __global__ __launch_bounds__(256) void k_emit(const int32_t* __restrict__ rvals,
     tx_n = cams[v].tiles_x;
   }
   const int w = rc.y - rc.x + 1, cnt = here ? w * (rc.w - rc.z + 1) : 0;
-  if (here && cnt <= kSolo) {
-    int64_t q = o;
-    for (int ty = rc.z; ty <= rc.w; ++ty)
-      for (int tx = rc.x; tx <= rc.y; ++tx) {
-        if (q < capacity) {
-          keys[q] = (uint32_t)(toff + ty * tx_n + tx);
-          vals[q] = (int32_t)r;
-        }
-        ++q;
-      }
-  }
+  const uint64_t present = __ballot(here);
+  if (present == 0) return;  // the same in every lane of the wave
   uint64_t big = __ballot(cnt > kSolo);
+  // the wave's instances are [lo, hi): the records of lanes 0 .. last are consecutive in the sorted list
+  const int last = 63 - __builtin_clzll(present);
+  const int64_t lo = read_lane64(o, 0), hi = read_lane64(o + cnt, last);
+  uint32_t* wk = wkey[wv];
+  int32_t* wvv = wval[wv];
+  for (int64_t win = lo; win < hi; win += kEmitWin) {
+    if (big) {
+      for (int i = lane; i < kEmitWin; i += 64) wk[i] = kEmitEmpty;
+    }
+    if (here && cnt <= kSolo) {
+      const int64_t k0 = max(o, win) - o, k1 = min(o + cnt, win + kEmitWin) - o;
+      if (k0 < k1) {
+        int ty = rc.z + (int)k0 / w, tx = rc.x + (int)k0 % w;
+        for (int64_t k = k0; k < k1; ++k) {
+          const int i = (int)(o + k - win);
+          wk[i] = (uint32_t)(toff + ty * tx_n + tx);
+          wvv[i] = (int32_t)r;
+          if (++tx > rc.y) {
+            tx = rc.x;
+            ++ty;
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // the wave's LDS writes land before its reads
+    const int m = (int)min<int64_t>(kEmitWin, hi - win);
+    for (int i = lane; i < m; i += 64) {
+      const uint32_t kk = wk[i];
+      const int64_t q = win + i;
+      if (kk != kEmitEmpty && q < capacity) {
+        keys[q] = kk;
+        vals[q] = wvv[i];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // and its reads before the next window's writes
+  }
   while (big) {
     const int L = __builtin_ctzll(big);
     big &= big - 1;

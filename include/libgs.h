@@ -145,15 +145,17 @@ typedef struct gs_frame {
   float* rec;           /* [n_views*n][12]: {mu_x, mu_y, z, o}, {conic a, b, c, red},
                            {green, blue, px0 | px1 << 16, py0 | py1 << 16} (pixel rectangle as int16 pairs) */
   int16_t* rect;        /* [n_views*n][4]: tile rectangle tx0, tx1, ty0, ty1 (valid when visible) */
-  float* ipart;         /* [capacity][12]: per tile instance, at its partial slot (Gaussian by Gaussian from
-                           inst_first[g], views ascending, each record's tiles row by row from rec_slot of the
-                           record), the compositing backward's partial
+  float* ipart;         /* [capacity][12]: per tile instance, at its partial slot (64 Gaussians at a time from
+                           inst_first of the first of them; within them view by view, Gaussians ascending in a
+                           view; each record's tiles row by row from rec_slot of the record), the compositing
+                           backward's partial
                            dL/d{mu_x, mu_y, a, b, c, o, red, green, blue, z} of its record summed over the
                            pixels of its tile (or depth segment); 2 words of padding.  Every backward call
                            writes every stored instance once (plain stores, no atomics).  The projection
                            backward first sums each record of big_rec into its first slot and sets that slot's
                            last word to 1 */
-  int32_t* inst_first;  /* [n]: exclusive scan of n_inst: the first partial slot of Gaussian g */
+  int32_t* inst_first;  /* [n]: exclusive scan of n_inst; for g a multiple of 64, the first partial slot of the
+                           64 Gaussians from g */
   uint64_t* vis_mask;   /* [n]: bit v set if Gaussian g is visible in view v */
   int32_t* n_inst;      /* [n]: tile instances of Gaussian g over all views */
   int32_t* n_rec;       /* [n]: visible records (views) of Gaussian g */

@@ -244,9 +244,12 @@ __global__ void k_record_total(const int32_t* __restrict__ n_rec, const int32_t*
 
 __device__ __forceinline__ int rect_area(const short4 rc) { return (rc.y - rc.x + 1) * (rc.w - rc.z + 1); }
 
-// ... and each visible record's first partial slot: inst_first[g] plus the instances of g's records in the views
-// before it; wide records (more than kWideRecord tiles) are appended to big_rec (count in counters[kBigCount],
-// one atomic per wave; the list order is not fixed, which nothing depends on).
+// ... and each visible record's first partial slot.  The instances of a wave's 64 Gaussians occupy one run of
+// slots from inst_first[g0] (g0 the wave's first Gaussian), laid out in the record list's order: view by view,
+// Gaussians ascending within a view; so the projection backward, which takes the views together, reads each
+// view's partials of the wave as one contiguous run.  Wide records (more than kWideRecord tiles) are appended
+// to big_rec (count in counters[kBigCount], one atomic per wave; the list order is not fixed, which nothing
+// depends on).
 constexpr int kBigCount = 198;
 
 __global__ __launch_bounds__(256) void k_record_list(const uint64_t* __restrict__ vis_mask,
@@ -266,7 +269,7 @@ __global__ __launch_bounds__(256) void k_record_list(const uint64_t* __restrict_
   // needs (records of different views never share a tile).
   const int64_t g0 = g - __lane_id();
   int64_t c = __builtin_amdgcn_readfirstlane((int)(g0 < n ? first[g0] : 0));
-  int32_t slot = here ? inst_first[g] : 0;
+  int32_t slot_c = __builtin_amdgcn_readfirstlane((int)(g0 < n ? inst_first[g0] : 0));
   const uint64_t lt = gsk::lanemask_lt();
   for (int v = 0; v < V; ++v) {
     const bool vis = (m >> v) & 1ull;
@@ -274,15 +277,18 @@ __global__ __launch_bounds__(256) void k_record_list(const uint64_t* __restrict_
     if (vb == 0) continue;
     const int64_t pos = c + __popcll(vb & lt);
     c += __popcll(vb);
-    if (!vis) continue;
     const int64_t r = (int64_t)v * n + g;
+    const int area = vis ? rect_area(rect[r]) : 0;
+    int view_total;
+    const int before = gsk::wave_excl_scan(area, view_total);
+    const int32_t slot = slot_c + before;
+    slot_c += view_total;
+    if (!vis) continue;
     if (pos < rcap) {
       rkeys[pos] = zbits[r];
       rvals[pos] = (int32_t)r;
     }
     rec_slot[r] = slot;
-    const int area = rect_area(rect[r]);
-    slot += area;
     const bool wide = area > gsk::kWideRecord;
     const uint64_t wb = __ballot(wide);
     if (wb) {

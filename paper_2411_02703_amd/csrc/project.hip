@@ -337,7 +337,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
                                                      float* __restrict__ sh, int64_t n,
                                                      const gs_camera* __restrict__ cams, int V, DevOpts op,
                                                      const float4* __restrict__ ipart,
-                                                     const int32_t* __restrict__ inst_first, const short4* __restrict__ rect,
+                                                     const int32_t* __restrict__ rec_slot, const short4* __restrict__ rect,
                                                      const int32_t* __restrict__ count_dev, int64_t capacity,
                                                      const uint64_t* __restrict__ vis_mask, float* __restrict__ g_means,
                                                      float* __restrict__ g_scales, float* __restrict__ g_quats,
@@ -385,17 +385,22 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
 #pragma unroll
   for (int i = 0; i < F; ++i) gf[i] = 0.f;
 
-  // this Gaussian's instances: one contiguous run of partial slots from inst_first[g], view by view (each
-  // visible record's tiles in turn).  The lanes take the views together; a wide record (more than kWideRecord
-  // tiles) has its partials pre-summed into its first slot (k_sum_wide), so one slot is read for it.  Slots
-  // outside the stored instances (an overflowed frame, whose gradient is undefined) are not read.
+  // each visible record's instances: a contiguous run of partial slots from rec_slot (each record's tiles in
+  // turn; binning lays the wave's records out view by view, so the lanes, which take the views together, read
+  // one contiguous run per view).  A wide record (more than kWideRecord tiles) has its partials pre-summed into
+  // its first slot (k_sum_wide), so one slot is read for it.  Slots outside the stored instances (an
+  // overflowed frame, whose gradient is undefined) are not read.
   const int64_t n_stored = min((int64_t)count_dev[0], capacity);
-  int64_t run = mask != 0 ? inst_first[g] : 0;
-  // the tile rectangle of this lane's next visible view is fetched one visible view ahead, so that the partial
-  // loads of a view do not wait for it
+  // the tile rectangle and first slot of this lane's next visible view are fetched one visible view ahead, so
+  // that the partial loads of a view do not wait for them
   uint64_t rest = mask;
   short4 rc_next = make_short4(0, -1, 0, -1);
-  if (rest) rc_next = rect[(int64_t)__builtin_ctzll(rest) * n + g];
+  int32_t slot_next = 0;
+  if (rest) {
+    const int64_t rn = (int64_t)__builtin_ctzll(rest) * n + g;
+    rc_next = rect[rn];
+    slot_next = rec_slot[rn];
+  }
   for (int v = 0; v < V; ++v) {
     const bool vis = (mask >> v) & 1ull;
     if (__ballot(vis) == 0) continue;
@@ -405,11 +410,14 @@ __global__ __launch_bounds__(256) void k_project_bwd(float* __restrict__ means, 
     int64_t i = 0;
     if (vis) {
       const short4 rc = rc_next;  // bit v is the lowest bit of rest
+      i = slot_next;
       rest &= rest - 1;
-      if (rest) rc_next = rect[(int64_t)__builtin_ctzll(rest) * n + g];
+      if (rest) {
+        const int64_t rn = (int64_t)__builtin_ctzll(rest) * n + g;
+        rc_next = rect[rn];
+        slot_next = rec_slot[rn];
+      }
       cnt = (rc.y - rc.x + 1) * (rc.w - rc.z + 1);
-      i = run;
-      run += cnt;
       if (cnt > gsk::kWideRecord) cnt = 1;
       if (i < 0 || i >= n_stored) cnt = 0;
     }
@@ -680,7 +688,7 @@ static hipError_t project_bwd_launch(const gs_params& p, const gs_frame& f, cons
   if (e != hipSuccess) return e;
 #define GS_PB(D)                                                                                              \
   k_project_bwd<D, ADAM><<<blocks, threads, 0, st>>>(p.means, p.log_scales, p.quats, p.opacity, p.sh, p.n,     \
-                                                     f.cams, f.n_views, op, ip, f.inst_first, rect, f.counters,    \
+                                                     f.cams, f.n_views, op, ip, f.rec_slot, rect, f.counters,    \
                                                      f.capacity, f.vis_mask, gm, gl, gq, go, gsh, ad)
   switch (p.sh_degree) {
     case 0: GS_PB(0); break;

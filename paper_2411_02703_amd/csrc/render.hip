@@ -433,7 +433,7 @@ struct BwdArgs {
   const int32_t* n_valid;  // per view
   float lambda_d;
   float lambda_ssim;  // loss mode: the L1 colour term takes 1 - lambda_ssim; g_rgb (if given) is added
-  float* ipart;              // [slot][12]: instance partials, each Gaussian's instances one run
+  float* ipart;              // [slot][12]: instance partials, each record's instances one run
   const int32_t* rec_slot;   // first slot of each record; a record's tiles follow row by row
   int64_t capacity;          // slots stored (a slot at or past it belongs to an overflowed frame)
   float* loss;

@@ -149,14 +149,16 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const KeyT* __restri
 
 // Stable scatter of one 8-bit digit.  Each wave ranks its 512 keys (8 rounds of 64) with ballot-based
 // digit matching, the block orders them in LDS (digit-major, stable), then writes runs to their global
-// offsets from the scanned digit-major histogram (hist_scan[d * nb + b] over the nb blocks that hold keys).
+// offsets from the scanned digit-major histogram (entry d * nb + b over the nb blocks that hold keys: the
+// tile-local scan hist_scan plus the scanned total of its scan tile, tile_scan).
 template <class KeyT>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const KeyT* __restrict__ kin,
                                                               const int32_t* __restrict__ vin,
                                                               KeyT* __restrict__ kout, int32_t* __restrict__ vout,
                                                               const int32_t* __restrict__ count_dev, int64_t n_sized,
                                                               int64_t cap, int shift,
-                                                              const int32_t* __restrict__ hist_scan) {
+                                                              const int32_t* __restrict__ hist_scan,
+                                                              const int32_t* __restrict__ tile_scan) {
   __shared__ KeyT sk[kSortTile];
   __shared__ int32_t sv[kSortTile];
   __shared__ int32_t wcnt[4][256];
@@ -205,7 +207,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const KeyT* __res
     wcnt[1][tid] = ds + c0;
     wcnt[2][tid] = ds + c0 + c1;
     wcnt[3][tid] = ds + c0 + c1 + c2;
-    gofs[tid] = hist_scan[tid * (int)((n + kSortTile - 1) / kSortTile) + blockIdx.x];
+    const int hi = tid * (int)((n + kSortTile - 1) / kSortTile) + blockIdx.x;
+    gofs[tid] = hist_scan[hi] + tile_scan[hi / kScanTile];
   }
   __syncthreads();
 #pragma unroll
@@ -553,6 +556,19 @@ hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* s
   return hipSuccess;
 }
 
+// The first two phases of scan_exclusive: out holds each kScanTile tile's exclusive scan and scratch[0 ..) the
+// exclusive scan of the tile totals, so the exclusive scan at i is out[i] + scratch[i / kScanTile] (for a
+// consumer that reads each entry once, in place of the pass that would add them).
+static hipError_t scan_exclusive_tiles(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t st,
+                                       DevCount dc) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = cdiv(n, kScanTile);
+  k_scan_tile<<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, n, scratch, dc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return scan_exclusive(scratch, scratch, nb, scratch + align64(nb), st, DevCount{});
+}
+
 hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   k_fill_i32<<<(unsigned)cdiv(n, 256), 256, 0, st>>>(p, v, n);
@@ -586,11 +602,11 @@ static hipError_t sort_impl(KeyT* k0, int32_t* v0, KeyT* k1, int32_t* v1, int64_
     k_sort_hist<KeyT><<<(unsigned)nb, kSortThreads, 0, st>>>(kb[src], count_dev, n_sized, cap, shift, hist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // the histogram holds 256 * cdiv(count, kSortTile) entries
-    e = scan_exclusive(hist, hist, 256 * nb, scan_scr, st, DevCount{count_dev, cap, kSortTile, 256});
+    // the histogram holds 256 * cdiv(count, kSortTile) entries; the scatter adds the scanned tile totals itself
+    e = scan_exclusive_tiles(hist, hist, 256 * nb, scan_scr, st, DevCount{count_dev, cap, kSortTile, 256});
     if (e != hipSuccess) return e;
     k_sort_scatter<KeyT><<<(unsigned)nb, kSortThreads, 0, st>>>(kb[src], vb[src], kb[dst], vb[dst], count_dev,
-                                                                n_sized, cap, shift, hist);
+                                                                n_sized, cap, shift, hist, scan_scr);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -219,6 +219,8 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ means
     if (s.qnorm > 0.f && s.o >= op.alpha_min) {
       // opacity-aware radius factor: outside sqrt(kp * Sigma_I,diag) alpha < exp(-1/2) / 255
       const float kp = 2.f * logf(255.f * s.o) + 1.f;
+      const bool pow2 = (op.tile_w & (op.tile_w - 1)) == 0 && (op.tile_h & (op.tile_h - 1)) == 0;
+      const int lw = __builtin_ctz((unsigned)op.tile_w), lh = __builtin_ctz((unsigned)op.tile_h);
       for (int v = 0; v < V; ++v) {
         const gs_camera& c = cams[v];
         if (c.loss_weight < 0.f) continue;  // an inactive view: nothing is projected into it
@@ -241,7 +243,9 @@ __global__ __launch_bounds__(256) void k_project(const float* __restrict__ means
         hi_y = fminf(fmaxf(hi_y, -1.f), (float)(c.height - 1));
         const int px0 = (int)lo_x, px1 = (int)hi_x, py0 = (int)lo_y, py1 = (int)hi_y;
         if (px0 > px1 || py0 > py1) continue;
-        const int tx0 = px0 / op.tile_w, tx1 = px1 / op.tile_w, ty0 = py0 / op.tile_h, ty1 = py1 / op.tile_h;
+        // (pixel indices are non-negative here: a power-of-two tile size divides by a shift)
+        const int tx0 = pow2 ? px0 >> lw : px0 / op.tile_w, tx1 = pow2 ? px1 >> lw : px1 / op.tile_w;
+        const int ty0 = pow2 ? py0 >> lh : py0 / op.tile_h, ty1 = pow2 ? py1 >> lh : py1 / op.tile_h;
         const float det_inv = 1.f / e.det;
         // colour at the direction from the camera centre
         const float d0 = mu[0] - c.campos[0], d1 = mu[1] - c.campos[1], d2 = mu[2] - c.campos[2];

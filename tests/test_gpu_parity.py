@@ -266,6 +266,38 @@ def test_full_size_batch_binning_is_bit_exact_from_gpu_records(gpu_lib):
     log("full-size binning bit-exact:", I, "instances,", int((~empty).sum()), "non-empty tiles of", nt)
 
 
+def test_partial_slots_lie_view_by_view_within_each_wave_group(gpu_lib):
+    """Partial slot layout (the frame's `ipart` contract): the instances of the 64 Gaussians from g0 (g0 a
+    multiple of 64) occupy one run of slots from inst_first[g0], laid out view by view and, inside a view,
+    Gaussian by Gaussian in ascending order, each record taking its tile rectangle's area; the runs of
+    consecutive groups are adjacent and end at the instance total."""
+    sc = scenes.random_scene(77, 5000, 160, 120, sh_degree=1, views=3, log_scale_mu=-1.6)
+    model = GaussianModel(sc.params(), sc.sh_degree)
+    fr = B.Frame(model.n, sc.cams, B.default_opts(), 2_000_000)
+    B.gs_project(model.ps, fr)
+    assert B.gs_bin_tiles(fr, sync_count=False) is None
+    I, flags = B.gs_read_counters(fr)
+    assert flags == 0 and I > 0
+    n, V = sc.n, len(sc.cams)
+    _, rect, vis = gpu_records(fr, n, V)
+    slot = B.frame_tensor(fr, "rec_slot", V * n, torch.int32).cpu().numpy()
+    first = B.frame_tensor(fr, "inst_first", n, torch.int32).cpu().numpy()
+    area = (rect[:, 1] - rect[:, 0] + 1) * (rect[:, 3] - rect[:, 2] + 1)
+    expect = np.full(V * n, -1, np.int64)
+    pos = 0
+    for g0 in range(0, n, 64):
+        assert first[g0] == pos, g0
+        for v in range(V):
+            for g in range(g0, min(g0 + 64, n)):
+                r = v * n + g
+                if vis[r]:
+                    expect[r] = pos
+                    pos += int(area[r])
+    assert pos == I
+    assert np.array_equal(slot[vis].astype(np.int64), expect[vis])
+    log("slot layout:", int(vis.sum()), "records,", I, "instances")
+
+
 # ----------------------------------------------------------------------------- forward
 @pytest.mark.parametrize("deg,views,W,H", [(0, 1, 128, 96), (3, 3, 100, 77), (2, 2, 33, 17)])
 def test_forward_matches_oracle(gpu_lib, deg, views, W, H):

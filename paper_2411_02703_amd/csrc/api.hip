@@ -379,8 +379,9 @@ int gs_composite_bwd(const gs_frame* f, const gs_opts* o, const gs_images* fwd, 
   if (o->tile_w != f->tile_w || o->tile_h != f->tile_h) return fail(GS_ERR_ARG, "tile size differs from the frame");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (l->tgt_rgb) {
-    GS_HIP(gs_launch::fill_f32(f->loss, 0.f, 1 + gsk::kLossSlots, st), "gs_composite_bwd: clear loss");
-    GS_HIP(gs_launch::count_valid(*f, l->tgt_depth, f->max_view_pixels, st), "gs_composite_bwd: valid depth");
+    // counts the valid target depths per view and clears the loss slots
+    GS_HIP(gs_launch::count_valid(*f, l->tgt_depth, f->max_view_pixels, f->loss, 1 + gsk::kLossSlots, st),
+           "gs_composite_bwd: valid depth");
   }
   GS_HIP(gs_launch::render_bwd(*f, *o, fwd, *l, st), "gs_composite_bwd");
   if (l->tgt_rgb) GS_HIP(gs_launch::loss_total(f->loss, st), "gs_composite_bwd: loss total");

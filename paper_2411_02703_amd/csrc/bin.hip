@@ -116,6 +116,12 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
+// Two int32 ranges set to v in one launch: [p, p + n) and [q, q + m).
+__global__ void k_fill2_i32(int32_t* __restrict__ p, int64_t n, int32_t* __restrict__ q, int64_t m, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+  if (i < m) q[i] = v;
+}
 __global__ void k_fill_f32(float* __restrict__ p, float v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -151,7 +157,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const KeyT* __restri
 // digit matching, the block orders them in LDS (digit-major, stable), then writes runs to their global
 // offsets from the scanned digit-major histogram (entry d * nb + b over the nb blocks that hold keys: the
 // tile-local scan hist_scan plus the scanned total of its scan tile, tile_scan).
-template <class KeyT>
+constexpr int kFoldTiles = 1024;  // histogram scans of at most this many tiles are finished inside the scatter
+
+template <class KeyT, bool FOLD>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const KeyT* __restrict__ kin,
                                                               const int32_t* __restrict__ vin,
                                                               KeyT* __restrict__ kout, int32_t* __restrict__ vout,
@@ -165,11 +173,31 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const KeyT* __res
   __shared__ int32_t dstart[256];
   __shared__ int32_t gofs[256];
   __shared__ int sh_wave[4];
+  __shared__ int32_t tsc[FOLD ? kFoldTiles : 1];
   const int64_t n = sort_count(count_dev, n_sized, cap);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   if (base >= n) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = __lane_id();
   for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
+  if (FOLD) {
+    // tile_scan holds the scan tiles' raw totals: every block forms their exclusive scan itself (at most
+    // kFoldTiles values, four per thread), in place of a separate pass over them
+    const int nbt = (int)((256 * ((n + kSortTile - 1) / kSortTile) + kScanTile - 1) / kScanTile);
+    int t[4], sum = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = 4 * tid + i;
+      t[i] = idx < nbt ? tile_scan[idx] : 0;
+      sum += t[i];
+    }
+    int total;
+    int run = block_scan_256(sum, sh_wave, &total);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      tsc[4 * tid + i] = run;
+      run += t[i];
+    }
+  }
   __syncthreads();
   KeyT key[kSortItems];
   int32_t val[kSortItems];
@@ -208,7 +236,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const KeyT* __res
     wcnt[2][tid] = ds + c0 + c1;
     wcnt[3][tid] = ds + c0 + c1 + c2;
     const int hi = tid * (int)((n + kSortTile - 1) / kSortTile) + blockIdx.x;
-    gofs[tid] = hist_scan[hi] + tile_scan[hi / kScanTile];
+    gofs[tid] = hist_scan[hi] + (FOLD ? tsc[hi / kScanTile] : tile_scan[hi / kScanTile]);
   }
   __syncthreads();
 #pragma unroll
@@ -239,11 +267,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const KeyT* __res
 // R goes to counters[kRecCount] (entries past the record capacity are not written; R > capacity implies more
 // instances than the instance capacity, which the instance total flags).
 constexpr int kRecCount = 196;
-
-__global__ void k_record_total(const int32_t* __restrict__ n_rec, const int32_t* __restrict__ first, int64_t n,
-                               int32_t* __restrict__ counters) {
-  counters[kRecCount] = first[n - 1] + n_rec[n - 1];
-}
+// The instance total summed from the per-Gaussian counts (one atomic per workgroup into counters[kInstSum], by
+// k_sum_counts), so that it is the full count even when the record list itself overflowed.
+constexpr int kInstSum = 197;
 
 __device__ __forceinline__ int rect_area(const short4 rc) { return (rc.y - rc.x + 1) * (rc.w - rc.z + 1); }
 
@@ -256,14 +282,23 @@ __device__ __forceinline__ int rect_area(const short4 rc) { return (rc.y - rc.x 
 constexpr int kBigCount = 198;
 
 __global__ __launch_bounds__(256) void k_record_list(const uint64_t* __restrict__ vis_mask,
+                                                    const int32_t* __restrict__ n_rec,
                                                     const int32_t* __restrict__ first,
                                                     const int32_t* __restrict__ inst_first,
                                                     const short4* __restrict__ rect,
                                                     const uint32_t* __restrict__ zbits, int V, int64_t n, int64_t rcap,
                                                     uint32_t* __restrict__ rkeys, int32_t* __restrict__ rvals,
                                                     int32_t* __restrict__ rec_slot, int32_t* __restrict__ big_rec,
-                                                    int32_t* __restrict__ counters) {
+                                                    int32_t* __restrict__ counters, int64_t capacity) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) {
+    // the record count R, and counters[0] = the instance total (summed by k_sum_counts; the full count) with
+    // the overflow flag if it is above the capacity
+    counters[kRecCount] = first[n - 1] + n_rec[n - 1];
+    const int64_t total = counters[kInstSum];
+    counters[0] = (int32_t)total;
+    if (total > capacity) atomicOr(counters + 1, GS_FLAG_INSTANCE_OVERFLOW);
+  }
   const bool here = g < n;
   const uint64_t m = here ? vis_mask[g] : 0ull;
   // The wave's records start where its first Gaussian's do (the scan of the record counts) and are listed view
@@ -318,10 +353,6 @@ __global__ void k_record_counts(const int32_t* __restrict__ rvals, const short4*
   ry[j] = (uint32_t)(uint16_t)rc.z | ((uint32_t)(uint16_t)rc.w << 16);
 }
 
-// The instance total summed from the per-Gaussian counts (one atomic per workgroup into counters[kInstSum]), so
-// that it is the full count even when the record list itself overflowed.
-constexpr int kInstSum = 197;
-
 __global__ __launch_bounds__(256) void k_sum_counts(const int32_t* __restrict__ n_inst, int64_t n,
                                                    int32_t* __restrict__ counters) {
   __shared__ int part[4];
@@ -332,13 +363,6 @@ __global__ __launch_bounds__(256) void k_sum_counts(const int32_t* __restrict__ 
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) atomicAdd(counters + kInstSum, part[0] + part[1] + part[2] + part[3]);
-}
-
-// counters[0] = instances (the full count); overflow flag if above the capacity.
-__global__ void k_instance_total(int64_t capacity, int32_t* __restrict__ counters) {
-  const int64_t total = counters[kInstSum];
-  counters[0] = (int32_t)total;
-  if (total > capacity) atomicOr(counters + 1, GS_FLAG_INSTANCE_OVERFLOW);
 }
 
 // Records with more tiles than this are emitted by a whole wave, a tile per lane.
@@ -603,10 +627,21 @@ static hipError_t sort_impl(KeyT* k0, int32_t* v0, KeyT* k1, int32_t* v1, int64_
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // the histogram holds 256 * cdiv(count, kSortTile) entries; the scatter adds the scanned tile totals itself
-    e = scan_exclusive_tiles(hist, hist, 256 * nb, scan_scr, st, DevCount{count_dev, cap, kSortTile, 256});
-    if (e != hipSuccess) return e;
-    k_sort_scatter<KeyT><<<(unsigned)nb, kSortThreads, 0, st>>>(kb[src], vb[src], kb[dst], vb[dst], count_dev,
-                                                                n_sized, cap, shift, hist, scan_scr);
+    // (and, for at most kFoldTiles scan tiles, scans those totals itself too)
+    const DevCount dc{count_dev, cap, kSortTile, 256};
+    if (cdiv(256 * nb, kScanTile) <= kFoldTiles) {
+      k_scan_tile<<<(unsigned)cdiv(256 * nb, kScanTile), kScanThreads, 0, st>>>(hist, hist, 256 * nb, scan_scr, dc);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      k_sort_scatter<KeyT, true><<<(unsigned)nb, kSortThreads, 0, st>>>(kb[src], vb[src], kb[dst], vb[dst],
+                                                                        count_dev, n_sized, cap, shift, hist,
+                                                                        scan_scr);
+    } else {
+      e = scan_exclusive_tiles(hist, hist, 256 * nb, scan_scr, st, dc);
+      if (e != hipSuccess) return e;
+      k_sort_scatter<KeyT, false><<<(unsigned)nb, kSortThreads, 0, st>>>(kb[src], vb[src], kb[dst], vb[dst],
+                                                                         count_dev, n_sized, cap, shift, hist,
+                                                                         scan_scr);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -636,12 +671,10 @@ hipError_t bin_records(const gs_frame& f, hipStream_t st) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = scan_exclusive(f.n_rec, f.rec_first, f.n, f.scratch, st)) != hipSuccess) return e;
   if ((e = scan_exclusive(f.n_inst, f.inst_first, f.n, f.scratch, st)) != hipSuccess) return e;
-  k_record_total<<<1, 1, 0, st>>>(f.n_rec, f.rec_first, f.n, f.counters);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_record_list<<<(unsigned)cdiv(f.n, 256), 256, 0, st>>>(f.vis_mask, f.rec_first, f.inst_first,
+  k_record_list<<<(unsigned)cdiv(f.n, 256), 256, 0, st>>>(f.vis_mask, f.n_rec, f.rec_first, f.inst_first,
                                                           reinterpret_cast<const short4*>(f.rect), f.zbits, f.n_views,
                                                           f.n, rcap, f.rkeys[0], f.rvals[0], f.rec_slot, f.big_rec,
-                                                          f.counters);
+                                                          f.counters, f.capacity);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = sort_pairs32(f.rkeys[0], f.rvals[0], f.rkeys[1], f.rvals[1], rcap, f.counters + kRecCount, rcap, 32,
                         f.scratch, st)) != hipSuccess)
@@ -654,8 +687,7 @@ hipError_t bin_records(const gs_frame& f, hipStream_t st) {
   if ((e = scan_exclusive(f.rvals[1], f.rvals[1], rcap, f.scratch, st,
                           DevCount{f.counters + kRecCount, rcap, 1, 1})) != hipSuccess)
     return e;
-  k_instance_total<<<1, 1, 0, st>>>(f.capacity, f.counters);
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t emit(const gs_frame& f, int64_t /*n_sized*/, hipStream_t st) {
@@ -665,11 +697,12 @@ hipError_t emit(const gs_frame& f, int64_t /*n_sized*/, hipStream_t st) {
   return hipGetLastError();
 }
 
+// The longest-first schedule; its 32 bucket counts (counters[128..160)) were cleared by ranges(), which runs
+// just before it.
 hipError_t tile_schedule(const gs_frame& f, hipStream_t st) {
   int32_t* cnt = f.counters + 128;
   int32_t* off = f.counters + 160;
-  hipError_t e = fill_i32(cnt, 0, 32, st);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
   const auto* rng = reinterpret_cast<const int2*>(f.tile_range);
   const unsigned nb = (unsigned)cdiv(f.n_tiles, 256);
   k_sched_hist<<<nb, 256, 0, st>>>(rng, f.n_tiles, f.seg_len, cnt);
@@ -693,9 +726,12 @@ hipError_t work_items(const gs_frame& f, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Tile ranges; the schedule's bucket counts (counters[128..160)) are cleared in the same launch as the ranges.
 hipError_t ranges(const gs_frame& f, const uint32_t* keys, int64_t n_sized, const int32_t* count_dev,
                   hipStream_t st) {
-  hipError_t e = fill_i32(f.tile_range, 0, 2 * (int64_t)f.n_tiles, st);
+  const int64_t nr = 2 * (int64_t)f.n_tiles;
+  k_fill2_i32<<<(unsigned)cdiv(nr > 32 ? nr : 32, 256), 256, 0, st>>>(f.tile_range, nr, f.counters + 128, 32, 0);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess || n_sized <= 0) return e;
   k_ranges<<<(unsigned)cdiv(n_sized, 256), 256, 0, st>>>(keys, count_dev, n_sized, f.capacity,
                                                          reinterpret_cast<int2*>(f.tile_range));

@@ -167,7 +167,8 @@ hipError_t tile_schedule(const gs_frame& f, hipStream_t s);
 hipError_t work_items(const gs_frame& f, hipStream_t s);
 hipError_t render_fwd(const gs_frame& f, const gs_opts& o, const gs_images& out, hipStream_t s);
 hipError_t count_pairs(const gs_frame& f, const gs_opts& o, unsigned long long* counts, hipStream_t s);
-hipError_t count_valid(const gs_frame& f, const float* tgt_depth, int64_t max_pixels, hipStream_t s);
+hipError_t count_valid(const gs_frame& f, const float* tgt_depth, int64_t max_pixels, float* loss, int n_loss,
+                       hipStream_t s);
 // loss[0] = sum of the partial sums loss[1 .. kLossSlots]
 hipError_t loss_total(float* loss, hipStream_t s);
 hipError_t render_bwd(const gs_frame& f, const gs_opts& o, const gs_images* fwd, const gs_loss& l,

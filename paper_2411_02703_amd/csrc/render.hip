@@ -1159,8 +1159,11 @@ __global__ __launch_bounds__(TW * TH) void k_count_pairs(const float4* __restric
 // Valid LiDAR-depth pixels per view: grid-stride per view, one atomic per block.
 __global__ __launch_bounds__(256) void k_count_valid(const float* __restrict__ tgt_depth,
                                                      const gs_camera* __restrict__ cams,
-                                                     int32_t* __restrict__ n_valid) {
+                                                     int32_t* __restrict__ n_valid, float* __restrict__ loss,
+                                                     int n_loss) {
   __shared__ int sh;
+  // the loss slots are cleared here too (the compositing that follows adds into them)
+  if (blockIdx.x == 0 && blockIdx.y == 0 && (int)threadIdx.x < n_loss) loss[threadIdx.x] = 0.f;
   if (threadIdx.x == 0) sh = 0;
   __syncthreads();
   const int v = blockIdx.y;
@@ -1361,13 +1364,14 @@ hipError_t loss_total(float* loss, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t count_valid(const gs_frame& f, const float* tgt_depth, int64_t max_pixels, hipStream_t st) {
+hipError_t count_valid(const gs_frame& f, const float* tgt_depth, int64_t max_pixels, float* loss, int n_loss,
+                       hipStream_t st) {
   hipError_t e = fill_i32(f.counters + 2, 0, f.n_views, st);
   if (e != hipSuccess) return e;
   int64_t bx = (max_pixels + 256 * 32 - 1) / (256 * 32);
   if (bx < 1) bx = 1;
   dim3 grid((unsigned)bx, (unsigned)f.n_views);
-  k_count_valid<<<grid, 256, 0, st>>>(tgt_depth, f.cams, f.counters + 2);
+  k_count_valid<<<grid, 256, 0, st>>>(tgt_depth, f.cams, f.counters + 2, loss, n_loss);
   return hipGetLastError();
 }
 

@@ -351,8 +351,10 @@ int gs_bin_tiles(const gs_frame* f, const gs_opts* o, int32_t sync_count, int64_
     count_dev = nullptr;
   }
   GS_HIP(gs_launch::emit(*f, n_sized, st), "gs_bin_tiles: emit");
+  // the instance sort folds its histogram scans only for small frames (a few M instances): with ~20 M the
+  // scatter's extra scan costs more than the launch it saves (measured)
   GS_HIP(gs_launch::sort_pairs32(f->keys[0], f->vals[0], f->keys[1], f->vals[1], n_sized, count_dev, f->capacity,
-                                 f->key_bits, f->scratch, st),
+                                 f->key_bits, f->scratch, st, 256),
          "gs_bin_tiles: sort by tile");
   GS_HIP(gs_launch::ranges(*f, f->keys[f->sort_passes & 1], n_sized, count_dev, st), "gs_bin_tiles: ranges");
   GS_HIP(gs_launch::tile_schedule(*f, st), "gs_bin_tiles: schedule");

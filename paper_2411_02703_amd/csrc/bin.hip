@@ -157,7 +157,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const KeyT* __restri
 // digit matching, the block orders them in LDS (digit-major, stable), then writes runs to their global
 // offsets from the scanned digit-major histogram (entry d * nb + b over the nb blocks that hold keys: the
 // tile-local scan hist_scan plus the scanned total of its scan tile, tile_scan).
-constexpr int kFoldTiles = 1024;  // histogram scans of at most this many tiles are finished inside the scatter
+// Histogram scans of at most this many tiles can be finished inside the scatter (each block scans the tile
+// totals itself, four per thread); whether they are is the caller's choice (fold_tiles), since with many keys
+// per pass the scatter's extra phase costs more than the separate pass it saves.
+constexpr int kFoldTiles = 4 * kSortThreads;
 
 template <class KeyT, bool FOLD>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const KeyT* __restrict__ kin,
@@ -612,7 +615,7 @@ size_t sort_scratch_ints(int64_t n) {
 
 template <class KeyT>
 static hipError_t sort_impl(KeyT* k0, int32_t* v0, KeyT* k1, int32_t* v1, int64_t n_sized, const int32_t* count_dev,
-                            int64_t cap, int key_bits, int32_t* scratch, hipStream_t st) {
+                            int64_t cap, int key_bits, int32_t* scratch, hipStream_t st, int fold_tiles) {
   if (n_sized <= 0) return hipSuccess;
   const int64_t nb = cdiv(n_sized, kSortTile);
   int32_t* hist = scratch;
@@ -629,7 +632,7 @@ static hipError_t sort_impl(KeyT* k0, int32_t* v0, KeyT* k1, int32_t* v1, int64_
     // the histogram holds 256 * cdiv(count, kSortTile) entries; the scatter adds the scanned tile totals itself
     // (and, for at most kFoldTiles scan tiles, scans those totals itself too)
     const DevCount dc{count_dev, cap, kSortTile, 256};
-    if (cdiv(256 * nb, kScanTile) <= kFoldTiles) {
+    if (cdiv(256 * nb, kScanTile) <= fold_tiles) {
       k_scan_tile<<<(unsigned)cdiv(256 * nb, kScanTile), kScanThreads, 0, st>>>(hist, hist, 256 * nb, scan_scr, dc);
       if ((e = hipGetLastError()) != hipSuccess) return e;
       k_sort_scatter<KeyT, true><<<(unsigned)nb, kSortThreads, 0, st>>>(kb[src], vb[src], kb[dst], vb[dst],
@@ -650,12 +653,14 @@ static hipError_t sort_impl(KeyT* k0, int32_t* v0, KeyT* k1, int32_t* v1, int64_
 
 hipError_t sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int64_t n_sized, const int32_t* count_dev,
                       int64_t cap, int key_bits, int32_t* scratch, hipStream_t st) {
-  return sort_impl<uint64_t>(k0, v0, k1, v1, n_sized, count_dev, cap, key_bits, scratch, st);
+  return sort_impl<uint64_t>(k0, v0, k1, v1, n_sized, count_dev, cap, key_bits, scratch, st, kFoldTiles);
 }
 
 hipError_t sort_pairs32(uint32_t* k0, int32_t* v0, uint32_t* k1, int32_t* v1, int64_t n_sized,
-                        const int32_t* count_dev, int64_t cap, int key_bits, int32_t* scratch, hipStream_t st) {
-  return sort_impl<uint32_t>(k0, v0, k1, v1, n_sized, count_dev, cap, key_bits, scratch, st);
+                        const int32_t* count_dev, int64_t cap, int key_bits, int32_t* scratch, hipStream_t st,
+                        int fold_tiles) {
+  return sort_impl<uint32_t>(k0, v0, k1, v1, n_sized, count_dev, cap, key_bits, scratch, st,
+                             fold_tiles < kFoldTiles ? fold_tiles : kFoldTiles);
 }
 
 // Binning up to the instance total: the records' first partial slots, the record list sorted by depth (record ids
@@ -677,7 +682,7 @@ hipError_t bin_records(const gs_frame& f, hipStream_t st) {
                                                           f.counters, f.capacity);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = sort_pairs32(f.rkeys[0], f.rvals[0], f.rkeys[1], f.rvals[1], rcap, f.counters + kRecCount, rcap, 32,
-                        f.scratch, st)) != hipSuccess)
+                        f.scratch, st, kFoldTiles)) != hipSuccess)
     return e;  // 4 passes: the sorted records are back in rkeys[0] / rvals[0]
   // counts straight into rvals[1], scanned in place into the emission offsets; the sorted rectangles take the
   // depth keys' buffers, which are no longer needed

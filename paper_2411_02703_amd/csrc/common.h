@@ -158,8 +158,11 @@ hipError_t fill_f32(float* p, float v, int64_t n, hipStream_t s);
 hipError_t bin_records(const gs_frame& f, hipStream_t s);
 hipError_t emit(const gs_frame& f, int64_t n_sized, hipStream_t s);
 size_t sort_scratch_ints(int64_t n);
+// fold_tiles: passes whose histogram scan has at most this many 4096-entry tiles (by the capacity) let the
+// scatter scan the tile totals itself (one launch fewer per pass; capped at 1024)
 hipError_t sort_pairs32(uint32_t* k0, int32_t* v0, uint32_t* k1, int32_t* v1, int64_t n_sized,
-                        const int32_t* count_dev, int64_t cap, int key_bits, int32_t* scratch, hipStream_t s);
+                        const int32_t* count_dev, int64_t cap, int key_bits, int32_t* scratch, hipStream_t s,
+                        int fold_tiles);
 hipError_t sort_pairs(uint64_t* k0, int32_t* v0, uint64_t* k1, int32_t* v1, int64_t n_sized,
                       const int32_t* count_dev, int64_t cap, int key_bits, int32_t* scratch, hipStream_t s);
 hipError_t ranges(const gs_frame& f, const uint32_t* keys, int64_t n_sized, const int32_t* count_dev, hipStream_t s);

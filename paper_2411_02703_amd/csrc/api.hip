@@ -134,7 +134,10 @@ Layout make_layout(int64_t n, int V, int n_tiles, int64_t cap, const gs_opts* op
   L.split = take((size_t)L.long_cap * 12 * NT * 4);
   int64_t big = n > n_tiles ? n : n_tiles;
   if (L.rec_cap > big) big = L.rec_cap;
-  const size_t s1 = gs_launch::scan_scratch_ints(big), s2 = gs_launch::sort_scratch_ints(cap);
+  // (the per-Gaussian count scans run as one pair: twice a scan's scratch over n)
+  size_t s1 = gs_launch::scan_scratch_ints(big);
+  if (2 * gs_launch::scan_scratch_ints(n) > s1) s1 = 2 * gs_launch::scan_scratch_ints(n);
+  const size_t s2 = gs_launch::sort_scratch_ints(cap);
   L.scratch_ints = s1 > s2 ? s1 : s2;
   L.scratch = take(L.scratch_ints * 4);
   L.total = o;

@@ -43,10 +43,17 @@ __device__ __forceinline__ int block_scan_256(int x, int* sh_wave, int* total) {
 }
 
 // Each block scans kScanTile consecutive items (exclusive) and writes its total.  The items scanned are the
-// first dev_count(dc, n): blocks past them only write a zero total.
-__global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int32_t* __restrict__ in, int32_t* __restrict__ out,
-                                                          int64_t n_sized, int32_t* __restrict__ sums,
-                                                          gs_launch::DevCount dc) {
+// first dev_count(dc, n): blocks past them only write a zero total.  A launch with gridDim.y = 2 scans a second
+// array of the same length in its second row of blocks (in_b, out_b, sums_b).
+__global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int32_t* in, int32_t* out, int64_t n_sized,
+                                                          int32_t* sums, gs_launch::DevCount dc,
+                                                          const int32_t* in_b = nullptr, int32_t* out_b = nullptr,
+                                                          int32_t* sums_b = nullptr) {
+  if (blockIdx.y) {
+    in = in_b;
+    out = out_b;
+    sums = sums_b;
+  }
   __shared__ int sh_wave[4];
   const int64_t n = gs_launch::dev_count(dc, n_sized);
   if ((int64_t)blockIdx.x * kScanTile >= n) {
@@ -100,8 +107,13 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tile(const int32_t* __res
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t* __restrict__ out, int64_t n_sized,
-                                                         const int32_t* __restrict__ sums, gs_launch::DevCount dc) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(int32_t* out, int64_t n_sized, const int32_t* sums,
+                                                         gs_launch::DevCount dc, int32_t* out_b = nullptr,
+                                                         const int32_t* sums_b = nullptr) {
+  if (blockIdx.y) {
+    out = out_b;
+    sums = sums_b;
+  }
   const int64_t n = gs_launch::dev_count(dc, n_sized);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   if (base >= n) return;
@@ -583,6 +595,23 @@ hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, int32_t* s
   return hipSuccess;
 }
 
+// Two exclusive scans of arrays of the same length in the launches of one (each kernel covers both).  Scratch:
+// 2 * scan_scratch_ints(n).
+static hipError_t scan_exclusive_pair(const int32_t* in0, int32_t* out0, const int32_t* in1, int32_t* out1,
+                                      int64_t n, int32_t* scratch, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int64_t nb = cdiv(n, kScanTile);
+  int32_t* sums0 = scratch;
+  int32_t* sums1 = scratch + align64(nb);
+  k_scan_tile<<<dim3((unsigned)nb, 2), kScanThreads, 0, st>>>(in0, out0, n, sums0, DevCount{}, in1, out1, sums1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nb == 1) return e;
+  if ((e = scan_exclusive_pair(sums0, sums0, sums1, sums1, nb, scratch + 2 * align64(nb), st)) != hipSuccess)
+    return e;
+  k_scan_add<<<dim3((unsigned)nb, 2), kScanThreads, 0, st>>>(out0, n, sums0, DevCount{}, out1, sums1);
+  return hipGetLastError();
+}
+
 // The first two phases of scan_exclusive: out holds each kScanTile tile's exclusive scan and scratch[0 ..) the
 // exclusive scan of the tile totals, so the exclusive scan at i is out[i] + scratch[i / kScanTile] (for a
 // consumer that reads each entry once, in place of the pass that would add them).
@@ -674,8 +703,8 @@ hipError_t bin_records(const gs_frame& f, hipStream_t st) {
   if (nb > 1024) nb = 1024;
   k_sum_counts<<<(unsigned)nb, 256, 0, st>>>(f.n_inst, f.n, f.counters);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = scan_exclusive(f.n_rec, f.rec_first, f.n, f.scratch, st)) != hipSuccess) return e;
-  if ((e = scan_exclusive(f.n_inst, f.inst_first, f.n, f.scratch, st)) != hipSuccess) return e;
+  if ((e = scan_exclusive_pair(f.n_rec, f.rec_first, f.n_inst, f.inst_first, f.n, f.scratch, st)) != hipSuccess)
+    return e;
   k_record_list<<<(unsigned)cdiv(f.n, 256), 256, 0, st>>>(f.vis_mask, f.n_rec, f.rec_first, f.inst_first,
                                                           reinterpret_cast<const short4*>(f.rect), f.zbits, f.n_views,
                                                           f.n, rcap, f.rkeys[0], f.rvals[0], f.rec_slot, f.big_rec,

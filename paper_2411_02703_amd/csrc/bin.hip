@@ -563,6 +563,72 @@ __global__ __launch_bounds__(256) void k_seg_emit(const int32_t* __restrict__ or
   for (int k = 0; k < n; ++k) items[first + k] = make_int4(t, k, n > 1 ? first : -1, p);
 }
 
+// Frames of at most kSchedOneBlock tiles: the schedule and the work items in one workgroup, each phase a loop
+// over the tiles between barriers (bucket histogram; its scan; the scatter into schedule order, which also
+// stores each position's segment count; the scan of the segment counts with the items), in place of the seven
+// launches above, whose fixed cost dominates there.  The results are those of the launches above (the order
+// inside a bucket is again that of the LDS atomics).  Without segments (seg_len <= 0) only the schedule.
+constexpr int kSchedOneBlock = 16384;
+
+__global__ __launch_bounds__(1024) void k_schedule_small(const int2* __restrict__ range, int n_tiles, int seg_len,
+                                                         int32_t* __restrict__ order, int32_t* __restrict__ seg_count,
+                                                         int32_t* __restrict__ seg_first, int4* __restrict__ items,
+                                                         int32_t* __restrict__ counters) {
+  __shared__ int h[32], base[32], wsum[16];
+  const int tid = threadIdx.x;
+  if (tid < 32) h[tid] = 0;
+  __syncthreads();
+  for (int t = tid; t < n_tiles; t += 1024) atomicAdd(&h[len_bucket(range, t, seg_len)], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int b = 0; b < 32; ++b) {
+      base[b] = run;
+      counters[128 + b] = h[b];
+      run += h[b];
+      counters[160 + b] = run;
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < n_tiles; t += 1024) {
+    const int len = range[t].y - range[t].x;
+    const int pos = atomicAdd(&base[seg_len > 0 && len > seg_len ? 0 : __clz((unsigned)len + 1u)], 1);
+    order[pos] = t;
+    if (seg_len > 0) seg_count[pos] = len > seg_len ? (len + seg_len - 1) / seg_len : 1;
+  }
+  if (seg_len <= 0) return;
+  __syncthreads();  // order and seg_count of this workgroup visible to all its threads
+  const int nl = h[0], wave = tid >> 6;
+  int carry = 0;
+  for (int c0 = 0; c0 < n_tiles; c0 += 1024) {
+    const int p = c0 + tid;
+    const int n = p < n_tiles ? seg_count[p] : 0;
+    const int t = p < n_tiles ? order[p] : 0;
+    int wt;
+    const int ex = gsk::wave_excl_scan(n, wt);
+    if (__lane_id() == 0) wsum[wave] = wt;
+    __syncthreads();
+    int before = 0, chunk = 0;
+    for (int w = 0; w < 16; ++w) {
+      before += w < wave ? wsum[w] : 0;
+      chunk += wsum[w];
+    }
+    const int first = carry + before + ex;
+    if (p < n_tiles) {
+      seg_first[p] = first;
+      for (int k = 0; k < n; ++k) items[first + k] = make_int4(t, k, n > 1 ? first : -1, p);
+      if (p == nl - 1) counters[193] = first + n;
+    }
+    carry += chunk;
+    __syncthreads();  // wsum is rewritten by the next chunk
+  }
+  if (tid == 0) {
+    counters[194] = nl;
+    if (nl == 0) counters[193] = 0;
+    counters[192] = carry;
+  }
+}
+
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t align64(int64_t a) { return (a + 63) & ~int64_t(63); }
 
@@ -738,6 +804,11 @@ hipError_t tile_schedule(const gs_frame& f, hipStream_t st) {
   int32_t* off = f.counters + 160;
   hipError_t e = hipSuccess;
   const auto* rng = reinterpret_cast<const int2*>(f.tile_range);
+  if (f.n_tiles <= kSchedOneBlock) {  // with the work items
+    k_schedule_small<<<1, 1024, 0, st>>>(rng, f.n_tiles, f.seg_len, f.tile_order, f.seg_count, f.seg_first,
+                                         reinterpret_cast<int4*>(f.items), f.counters);
+    return hipGetLastError();
+  }
   const unsigned nb = (unsigned)cdiv(f.n_tiles, 256);
   k_sched_hist<<<nb, 256, 0, st>>>(rng, f.n_tiles, f.seg_len, cnt);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -748,7 +819,7 @@ hipError_t tile_schedule(const gs_frame& f, hipStream_t st) {
 }
 
 hipError_t work_items(const gs_frame& f, hipStream_t st) {
-  if (f.seg_len <= 0) return hipSuccess;
+  if (f.seg_len <= 0 || f.n_tiles <= kSchedOneBlock) return hipSuccess;  // small frames: by tile_schedule
   const auto* rng = reinterpret_cast<const int2*>(f.tile_range);
   const unsigned nb = (unsigned)cdiv(f.n_tiles, 256);
   k_seg_count<<<nb, 256, 0, st>>>(rng, f.tile_order, f.n_tiles, f.seg_len, f.seg_count);

@@ -679,6 +679,39 @@ def test_tile_schedule_is_a_longest_first_permutation(gpu_lib):
     assert np.all(np.diff(buckets) <= 0)
 
 
+@pytest.mark.parametrize("W,H,tile", [(150, 110, (16, 16)), (1100, 980, (8, 8))])
+def test_schedule_and_work_items_of_small_and_large_frames(gpu_lib, W, H, tile):
+    """Frames of few tiles plan the schedule and the work items in one workgroup, large ones (here 50,922 tiles)
+    in several launches; both give a longest-first permutation with split tiles first, the segment counts and
+    their exclusive scan, one item per segment and the item, slot and split-tile totals."""
+    seg = 64
+    sc = scenes.random_scene(1610, 6000, W, H, sh_degree=0, views=3, log_scale_mu=-2.2)
+    out = run_gpu(sc, tile=tile, targets=False, seg=seg)
+    fr = out["frame"]
+    nt = fr.f.n_tiles
+    order = B.frame_tensor(fr, "tile_order", nt, torch.int32).cpu().numpy()
+    rng_ = B.frame_tensor(fr, "tile_range", 2 * nt, torch.int32).view(-1, 2).cpu().numpy()
+    first = B.frame_tensor(fr, "seg_first", nt, torch.int32).cpu().numpy()
+    assert np.array_equal(np.sort(order), np.arange(nt))
+    lens = (rng_[:, 1] - rng_[:, 0])[order]
+    nl = int((lens > seg).sum())
+    assert np.all(lens[:nl] > seg) and np.all(lens[nl:] <= seg)
+    assert np.all(np.diff(np.floor(np.log2(lens[nl:] + 1.0))) <= 0)
+    most = _check_segment_plan(out, seg)
+    counts = np.where(lens > seg, -(-lens // seg), 1)
+    assert np.array_equal(first, np.concatenate([[0], np.cumsum(counts)[:-1]]))
+    items, slots, longs = _split_counts(out)
+    assert (items, slots, longs) == (int(counts.sum()), int(counts[:nl].sum()), nl)
+    it = B.frame_tensor(fr, "items", 4 * items, torch.int32).view(-1, 4).cpu().numpy()
+    pos = np.repeat(np.arange(nt), counts)
+    k = np.arange(items) - first[pos]
+    expect = np.stack([order[pos], k, np.where(counts[pos] > 1, first[pos], -1), pos], axis=1)
+    assert np.array_equal(it, expect)
+    log("schedule", (W, H, tile), "tiles", nt, "items", items, "split tiles", nl, "most segments", most)
+    if tile == (8, 8):
+        assert nt > 16384
+
+
 def _subpixel_scene(seed, n=20000, W=64, H=48, views=1, deg=0):
     # many sub-pixel Gaussians per tile: most records meet one 4x4 block
     return scenes.random_scene(seed, n, W, H, sh_degree=deg, views=views, log_scale_mu=-5.0, log_scale_sigma=0.3,

@@ -575,10 +575,31 @@ __global__ __launch_bounds__(1024) void k_schedule_small(const int2* __restrict_
                                                          int32_t* __restrict__ seg_first, int4* __restrict__ items,
                                                          int32_t* __restrict__ counters) {
   __shared__ int h[32], base[32], wsum[16];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = __lane_id(), wave = tid >> 6;
   if (tid < 32) h[tid] = 0;
   __syncthreads();
-  for (int t = tid; t < n_tiles; t += 1024) atomicAdd(&h[len_bucket(range, t, seg_len)], 1);
+  // each thread's list lengths, loaded once (all loads in flight together) and kept for the scatter
+  constexpr int kPer = kSchedOneBlock / 1024;
+  int lens[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    const int t = j * 1024 + tid;
+    lens[j] = t < n_tiles ? range[t].y - range[t].x : -1;
+  }
+  auto bucket = [&](int len) { return len < 0 ? 32 : (seg_len > 0 && len > seg_len ? 0 : __clz((unsigned)len + 1u)); };
+  // the LDS atomics are taken once per distinct bucket of a wave (a wave's tiles fall into a few buckets, and
+  // atomics of many lanes on one address serialise)
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    if (j * 1024 >= n_tiles) break;
+    const int b = bucket(lens[j]);
+    for (uint64_t rest = __builtin_amdgcn_ballot_w64(b < 32); rest;) {
+      const int lb = __builtin_amdgcn_readlane(b, __builtin_ctzll(rest));
+      const uint64_t m = __builtin_amdgcn_ballot_w64(b == lb);
+      if (lane == 0) atomicAdd(&h[lb], __popcll(m));
+      rest &= ~m;
+    }
+  }
   __syncthreads();
   if (tid == 0) {
     int run = 0;
@@ -590,34 +611,58 @@ __global__ __launch_bounds__(1024) void k_schedule_small(const int2* __restrict_
     }
   }
   __syncthreads();
-  for (int t = tid; t < n_tiles; t += 1024) {
-    const int len = range[t].y - range[t].x;
-    const int pos = atomicAdd(&base[seg_len > 0 && len > seg_len ? 0 : __clz((unsigned)len + 1u)], 1);
-    order[pos] = t;
-    if (seg_len > 0) seg_count[pos] = len > seg_len ? (len + seg_len - 1) / seg_len : 1;
+  const uint64_t lt = gsk::lanemask_lt();
+#pragma unroll
+  for (int j = 0; j < kPer; ++j) {
+    if (j * 1024 >= n_tiles) break;
+    const int t = j * 1024 + tid, len = lens[j], b = bucket(len);
+    int pos = 0;
+    for (uint64_t rest = __builtin_amdgcn_ballot_w64(b < 32); rest;) {
+      const int lb = __builtin_amdgcn_readlane(b, __builtin_ctzll(rest));
+      const uint64_t m = __builtin_amdgcn_ballot_w64(b == lb);
+      int at = 0;
+      if (lane == 0) at = atomicAdd(&base[lb], __popcll(m));
+      at = __builtin_amdgcn_readlane(at, 0);
+      if (b == lb) pos = at + __popcll(m & lt);
+      rest &= ~m;
+    }
+    if (b < 32) {
+      order[pos] = t;
+      if (seg_len > 0) seg_count[pos] = len > seg_len ? (len + seg_len - 1) / seg_len : 1;
+    }
   }
   if (seg_len <= 0) return;
   __syncthreads();  // order and seg_count of this workgroup visible to all its threads
-  const int nl = h[0], wave = tid >> 6;
+  const int nl = h[0];
   int carry = 0;
-  for (int c0 = 0; c0 < n_tiles; c0 += 1024) {
-    const int p = c0 + tid;
-    const int n = p < n_tiles ? seg_count[p] : 0;
-    const int t = p < n_tiles ? order[p] : 0;
+  for (int c0 = 0; c0 < n_tiles; c0 += 4096) {  // four consecutive positions per thread
+    const int p0 = c0 + 4 * tid;
+    int cnt[4], til[4], sum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      cnt[j] = p0 + j < n_tiles ? seg_count[p0 + j] : 0;
+      til[j] = p0 + j < n_tiles ? order[p0 + j] : 0;
+      sum += cnt[j];
+    }
     int wt;
-    const int ex = gsk::wave_excl_scan(n, wt);
-    if (__lane_id() == 0) wsum[wave] = wt;
+    const int ex = gsk::wave_excl_scan(sum, wt);
+    if (lane == 0) wsum[wave] = wt;
     __syncthreads();
     int before = 0, chunk = 0;
     for (int w = 0; w < 16; ++w) {
       before += w < wave ? wsum[w] : 0;
       chunk += wsum[w];
     }
-    const int first = carry + before + ex;
-    if (p < n_tiles) {
-      seg_first[p] = first;
-      for (int k = 0; k < n; ++k) items[first + k] = make_int4(t, k, n > 1 ? first : -1, p);
-      if (p == nl - 1) counters[193] = first + n;
+    int first = carry + before + ex;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int p = p0 + j, n = cnt[j];
+      if (p < n_tiles) {
+        seg_first[p] = first;
+        for (int k = 0; k < n; ++k) items[first + k] = make_int4(til[j], k, n > 1 ? first : -1, p);
+        if (p == nl - 1) counters[193] = first + n;
+      }
+      first += n;
     }
     carry += chunk;
     __syncthreads();  // wsum is rewritten by the next chunk

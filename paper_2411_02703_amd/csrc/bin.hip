@@ -282,8 +282,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const KeyT* __res
 // R goes to counters[kRecCount] (entries past the record capacity are not written; R > capacity implies more
 // instances than the instance capacity, which the instance total flags).
 constexpr int kRecCount = 196;
-// The instance total summed from the per-Gaussian counts (one atomic per workgroup into counters[kInstSum], by
-// k_sum_counts), so that it is the full count even when the record list itself overflowed.
+// The instance total: the end of the exclusive scan of the per-Gaussian instance counts (the full count even
+// when the record list itself overflowed), set by the record list's first thread.
 constexpr int kInstSum = 197;
 
 __device__ __forceinline__ int rect_area(const short4 rc) { return (rc.y - rc.x + 1) * (rc.w - rc.z + 1); }
@@ -300,6 +300,7 @@ __global__ __launch_bounds__(256) void k_record_list(const uint64_t* __restrict_
                                                     const int32_t* __restrict__ n_rec,
                                                     const int32_t* __restrict__ first,
                                                     const int32_t* __restrict__ inst_first,
+                                                    const int32_t* __restrict__ n_inst,
                                                     const short4* __restrict__ rect,
                                                     const uint32_t* __restrict__ zbits, int V, int64_t n, int64_t rcap,
                                                     uint32_t* __restrict__ rkeys, int32_t* __restrict__ rvals,
@@ -307,10 +308,11 @@ __global__ __launch_bounds__(256) void k_record_list(const uint64_t* __restrict_
                                                     int32_t* __restrict__ counters, int64_t capacity) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g == 0) {
-    // the record count R, and counters[0] = the instance total (summed by k_sum_counts; the full count) with
-    // the overflow flag if it is above the capacity
+    // the record count R, and counters[0] = the instance total (the end of the per-Gaussian instance scan; the
+    // full count) with the overflow flag if it is above the capacity
     counters[kRecCount] = first[n - 1] + n_rec[n - 1];
-    const int64_t total = counters[kInstSum];
+    const int64_t total = (int64_t)inst_first[n - 1] + n_inst[n - 1];
+    counters[kInstSum] = (int32_t)total;
     counters[0] = (int32_t)total;
     if (total > capacity) atomicOr(counters + 1, GS_FLAG_INSTANCE_OVERFLOW);
   }
@@ -366,18 +368,6 @@ __global__ void k_record_counts(const int32_t* __restrict__ rvals, const short4*
   cnt[j] = rect_area(rc);
   rx[j] = (uint32_t)(uint16_t)rc.x | ((uint32_t)(uint16_t)rc.y << 16);
   ry[j] = (uint32_t)(uint16_t)rc.z | ((uint32_t)(uint16_t)rc.w << 16);
-}
-
-__global__ __launch_bounds__(256) void k_sum_counts(const int32_t* __restrict__ n_inst, int64_t n,
-                                                   int32_t* __restrict__ counters) {
-  __shared__ int part[4];
-  int s = 0;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x)
-    s += n_inst[g];
-  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(counters + kInstSum, part[0] + part[1] + part[2] + part[3]);
 }
 
 // Records with more tiles than this are emitted by a whole wave, a tile per lane.
@@ -810,13 +800,9 @@ hipError_t bin_records(const gs_frame& f, hipStream_t st) {
   const int64_t rcap = f.rec_cap;
   hipError_t e = fill_i32(f.counters + kInstSum, 0, 2, st);  // kInstSum, kBigCount
   if (e != hipSuccess) return e;
-  int64_t nb = cdiv(f.n, 256);
-  if (nb > 1024) nb = 1024;
-  k_sum_counts<<<(unsigned)nb, 256, 0, st>>>(f.n_inst, f.n, f.counters);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = scan_exclusive_pair(f.n_rec, f.rec_first, f.n_inst, f.inst_first, f.n, f.scratch, st)) != hipSuccess)
     return e;
-  k_record_list<<<(unsigned)cdiv(f.n, 256), 256, 0, st>>>(f.vis_mask, f.n_rec, f.rec_first, f.inst_first,
+  k_record_list<<<(unsigned)cdiv(f.n, 256), 256, 0, st>>>(f.vis_mask, f.n_rec, f.rec_first, f.inst_first, f.n_inst,
                                                           reinterpret_cast<const short4*>(f.rect), f.zbits, f.n_views,
                                                           f.n, rcap, f.rkeys[0], f.rvals[0], f.rec_slot, f.big_rec,
                                                           f.counters, f.capacity);
